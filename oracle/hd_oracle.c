@@ -1,0 +1,812 @@
+/*
+ * FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY (see hd_oracle.h).
+ *
+ * Plain loops, one system at a time, no blocking or fusion: each function
+ * follows the definition it cites so that it can be checked against the
+ * paper by eye.  Built with -O2 -ffp-contract=off so that every product and
+ * sum is rounded exactly as written.
+ */
+#include "hd_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { MOBILE = 0, FIXED = 1, RIGID = 2 };
+
+struct orc_sys {
+    orc_params p;
+    int dim, n;
+    double *x, *v, *rO;      /* SoA [dim][n] */
+    uint8_t *type, *role;
+    double *cofs;            /* rigid atoms: offset from the rigid-body COM */
+    int n_rigid, first_rigid;
+    double XR[3], VR[3], XR0[3];
+    double *ftot;            /* total force at the current positions */
+    double FR[3];            /* total force on the rigid body */
+    int64_t step;
+    double t_md, t_hyper;
+    orc_scalars last;
+    int brute;
+    int have_force;
+};
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from the definition in Salmon et al. (SC'11): ten rounds of
+ * two 32x32->64 multiplies with the round keys bumped by the Weyl constants. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Counter = (step low, step high, particle, tag); key = (seed low, seed high).
+ * Uniforms u = (w + 1/2) 2^-32 lie strictly inside (0, 1); Box-Muller maps
+ * (u0, u1) -> (z0, z1) and (u2, u3) -> (z2, z3). */
+void orc_normals(uint64_t seed, int64_t step, uint32_t particle, uint32_t tag, double z[4])
+{
+    uint32_t ctr[4] = {(uint32_t)((uint64_t)step & 0xffffffffu),
+                       (uint32_t)((uint64_t)step >> 32), particle, tag};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    const double two_m32 = 2.3283064365386963e-10; /* 2^-32 */
+    double u[4];
+    for (int k = 0; k < 4; ++k) u[k] = ((double)w[k] + 0.5) * two_m32;
+    const double two_pi = 6.283185307179586;
+    double r0 = sqrt(-2.0 * log(u[0]));
+    double r1 = sqrt(-2.0 * log(u[2]));
+    z[0] = r0 * cos(two_pi * u[1]);
+    z[1] = r0 * sin(two_pi * u[1]);
+    z[2] = r1 * cos(two_pi * u[3]);
+    z[3] = r1 * sin(two_pi * u[3]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Minimum image along one axis: strict comparisons with half the box. */
+static double minimg(double dx, double L, int periodic)
+{
+    if (!periodic) return dx;
+    if (dx > 0.5 * L) dx -= L;
+    else if (dx < -0.5 * L) dx += L;
+    return dx;
+}
+
+static double wrap(double x, double L, int periodic)
+{
+    if (!periodic) return x;
+    if (x >= L) x -= L;
+    else if (x < 0.0) x += L;
+    return x;
+}
+
+/* r^2 between atoms i and j with displacement dx_k = x_j - x_i, summed as
+ * (dx*dx + dy*dy) + dz*dz. */
+static double pair_r2(const orc_params *p, const double *x, int n, int i, int j)
+{
+    double r2 = 0.0;
+    for (int k = 0; k < p->dim; ++k) {
+        double d = minimg(x[k * n + j] - x[k * n + i], p->box[k], p->periodic[k]);
+        r2 = r2 + d * d;
+    }
+    return r2;
+}
+
+static int excluded(const uint8_t *role, int i, int j)
+{
+    return (role[i] == FIXED && role[j] == FIXED) || (role[i] == RIGID && role[j] == RIGID);
+}
+
+int64_t orc_pairs_brute(const orc_params *p, const double *x, const uint8_t *role,
+                        double rl, int exclude, int32_t *ij, int64_t cap)
+{
+    const int n = p->n;
+    const double rl2 = rl * rl;
+    int64_t cnt = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            if (exclude && excluded(role, i, j)) continue;
+            if (pair_r2(p, x, n, i, j) < rl2) {
+                if (cnt < cap) { ij[2 * cnt] = i; ij[2 * cnt + 1] = j; }
+                ++cnt;
+            }
+        }
+    return cnt;
+}
+
+/* Cell list: per axis nc cells of edge >= rl (a single cell when fewer than
+ * three would fit on a periodic axis); open axes span the current extent. */
+typedef struct {
+    int nc[3];
+    double lo[3], h[3];
+    int *head, *next;
+} cells_t;
+
+static int cell_coord(const cells_t *c, int k, double xk)
+{
+    int ci = (int)floor((xk - c->lo[k]) / c->h[k]);
+    if (ci < 0) ci = 0;
+    if (ci >= c->nc[k]) ci = c->nc[k] - 1;
+    return ci;
+}
+
+static void cells_build(cells_t *c, const orc_params *p, const double *x, double rl)
+{
+    const int n = p->n;
+    for (int k = 0; k < 3; ++k) { c->nc[k] = 1; c->lo[k] = 0.0; c->h[k] = 1.0; }
+    for (int k = 0; k < p->dim; ++k) {
+        if (p->periodic[k]) {
+            int m = (int)floor(p->box[k] / rl);
+            if (m < 3) m = 1;
+            c->nc[k] = m;
+            c->lo[k] = 0.0;
+            c->h[k] = p->box[k] / m;
+        } else {
+            double mn = x[k * n], mx = x[k * n];
+            for (int i = 1; i < n; ++i) {
+                if (x[k * n + i] < mn) mn = x[k * n + i];
+                if (x[k * n + i] > mx) mx = x[k * n + i];
+            }
+            int m = (int)floor((mx - mn) / rl);
+            if (m < 1) m = 1;
+            c->nc[k] = m;
+            c->lo[k] = mn;
+            c->h[k] = (mx - mn) / m;
+            if (c->h[k] < rl) c->h[k] = rl;
+        }
+    }
+    int ncell = c->nc[0] * c->nc[1] * c->nc[2];
+    c->head = (int *)malloc(sizeof(int) * ncell);
+    c->next = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    for (int q = 0; q < ncell; ++q) c->head[q] = -1;
+    for (int i = n - 1; i >= 0; --i) {
+        int cc[3] = {0, 0, 0};
+        for (int k = 0; k < p->dim; ++k) cc[k] = cell_coord(c, k, x[k * n + i]);
+        int q = (cc[2] * c->nc[1] + cc[1]) * c->nc[0] + cc[0];
+        c->next[i] = c->head[q];
+        c->head[q] = i;
+    }
+}
+
+static void cells_free(cells_t *c) { free(c->head); free(c->next); }
+
+/* Visit every pair i<j in neighbouring cells once and apply fn to those with
+ * r^2 < rl^2 (and not excluded when exclude != 0). */
+typedef void (*pair_fn)(void *ctx, int i, int j);
+
+static void for_pairs_cells(const orc_params *p, const double *x, const uint8_t *role,
+                            double rl, int exclude, pair_fn fn, void *ctx)
+{
+    const int n = p->n;
+    cells_t c;
+    cells_build(&c, p, x, rl);
+    const double rl2 = rl * rl;
+    int lo[3], hi[3];
+    for (int i = 0; i < n; ++i) {
+        int cc[3] = {0, 0, 0};
+        for (int k = 0; k < p->dim; ++k) cc[k] = cell_coord(&c, k, x[k * n + i]);
+        for (int k = 0; k < 3; ++k) {
+            if (c.nc[k] == 1) { lo[k] = 0; hi[k] = 0; }
+            else { lo[k] = -1; hi[k] = 1; }
+        }
+        for (int oz = lo[2]; oz <= hi[2]; ++oz)
+            for (int oy = lo[1]; oy <= hi[1]; ++oy)
+                for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+                    int q3[3] = {cc[0] + ox, cc[1] + oy, cc[2] + oz};
+                    int skip = 0;
+                    for (int k = 0; k < 3; ++k) {
+                        if (q3[k] < 0 || q3[k] >= c.nc[k]) {
+                            if (k < p->dim && p->periodic[k]) q3[k] = (q3[k] + c.nc[k]) % c.nc[k];
+                            else skip = 1;
+                        }
+                    }
+                    if (skip) continue;
+                    int q = (q3[2] * c.nc[1] + q3[1]) * c.nc[0] + q3[0];
+                    for (int j = c.head[q]; j >= 0; j = c.next[j]) {
+                        if (j <= i) continue;
+                        if (exclude && excluded(role, i, j)) continue;
+                        if (pair_r2(p, x, n, i, j) < rl2) fn(ctx, i, j);
+                    }
+                }
+    }
+    cells_free(&c);
+}
+
+typedef struct { int32_t *ij; int64_t cap, cnt; } collect_ctx;
+static void collect_pair(void *vctx, int i, int j)
+{
+    collect_ctx *c = (collect_ctx *)vctx;
+    if (c->cnt < c->cap) { c->ij[2 * c->cnt] = i; c->ij[2 * c->cnt + 1] = j; }
+    c->cnt++;
+}
+
+int64_t orc_pairs_cells(const orc_params *p, const double *x, const uint8_t *role,
+                        double rl, int exclude, int32_t *ij, int64_t cap)
+{
+    collect_ctx c = {ij, cap, 0};
+    for_pairs_cells(p, x, role, rl, exclude, collect_pair, &c);
+    return c.cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* System state */
+
+static void place_rigid(orc_sys *s)
+{
+    const int n = s->n;
+    for (int i = 0; i < n; ++i) {
+        if (s->role[i] != RIGID) continue;
+        for (int k = 0; k < s->dim; ++k)
+            s->x[k * n + i] = wrap(s->XR[k] + s->cofs[k * n + i], s->p.box[k], s->p.periodic[k]);
+    }
+}
+
+/* Rigid-body centre of mass from the current rigid atom positions, unwrapped
+ * about the first rigid atom; offsets c_i = x_i - X_R. */
+static void init_rigid(orc_sys *s)
+{
+    const int n = s->n;
+    s->n_rigid = 0;
+    s->first_rigid = -1;
+    for (int i = 0; i < n; ++i)
+        if (s->role[i] == RIGID) { if (s->first_rigid < 0) s->first_rigid = i; s->n_rigid++; }
+    for (int k = 0; k < 3; ++k) { s->XR[k] = 0.0; s->VR[k] = 0.0; s->XR0[k] = 0.0; }
+    if (s->n_rigid == 0) return;
+    const int f = s->first_rigid;
+    for (int k = 0; k < s->dim; ++k) {
+        double xf = s->x[k * n + f];
+        double sum = 0.0;
+        for (int i = 0; i < n; ++i)
+            if (s->role[i] == RIGID)
+                sum += xf + minimg(s->x[k * n + i] - xf, s->p.box[k], s->p.periodic[k]);
+        s->XR[k] = sum / s->n_rigid;
+        for (int i = 0; i < n; ++i)
+            if (s->role[i] == RIGID)
+                s->cofs[k * n + i] = (xf + minimg(s->x[k * n + i] - xf, s->p.box[k], s->p.periodic[k])) - s->XR[k];
+        s->XR0[k] = s->XR[k];
+    }
+    place_rigid(s);
+}
+
+orc_sys *orc_create(const orc_params *p, const double *x, const uint8_t *type,
+                    const uint8_t *role, const double *rO)
+{
+    orc_sys *s = (orc_sys *)calloc(1, sizeof(orc_sys));
+    s->p = *p;
+    s->dim = p->dim;
+    s->n = p->n;
+    size_t nd = (size_t)p->dim * p->n;
+    s->x = (double *)malloc(sizeof(double) * nd);
+    s->v = (double *)calloc(nd, sizeof(double));
+    s->rO = (double *)malloc(sizeof(double) * nd);
+    s->cofs = (double *)calloc(nd, sizeof(double));
+    s->ftot = (double *)calloc(nd, sizeof(double));
+    s->type = (uint8_t *)malloc(p->n);
+    s->role = (uint8_t *)malloc(p->n);
+    memcpy(s->x, x, sizeof(double) * nd);
+    memcpy(s->rO, rO ? rO : x, sizeof(double) * nd);
+    memcpy(s->type, type, p->n);
+    memcpy(s->role, role, p->n);
+    init_rigid(s);
+    return s;
+}
+
+void orc_destroy(orc_sys *s)
+{
+    if (!s) return;
+    free(s->x); free(s->v); free(s->rO); free(s->cofs); free(s->ftot);
+    free(s->type); free(s->role);
+    free(s);
+}
+
+void orc_set_params(orc_sys *s, const orc_params *p)
+{
+    s->p = *p;
+    s->have_force = 0;
+}
+
+/* New positions: mobile and fixed atoms are copied; the rigid body moves by
+ * the minimum-image displacement of its first atom and the rigid atoms are
+ * re-placed at X_R + c_i. */
+void orc_set_positions(orc_sys *s, const double *x)
+{
+    const int n = s->n;
+    if (s->n_rigid > 0) {
+        const int f = s->first_rigid;
+        for (int k = 0; k < s->dim; ++k)
+            s->XR[k] = s->XR[k] + minimg(x[k * n + f] - s->x[k * n + f], s->p.box[k], s->p.periodic[k]);
+    }
+    for (int i = 0; i < n; ++i)
+        if (s->role[i] != RIGID)
+            for (int k = 0; k < s->dim; ++k) s->x[k * n + i] = x[k * n + i];
+    place_rigid(s);
+    s->have_force = 0;
+}
+
+/* New velocities: mobile atoms copied; fixed atoms zero; the rigid body takes
+ * the mean velocity of its atoms. */
+void orc_set_velocities(orc_sys *s, const double *v)
+{
+    const int n = s->n;
+    for (int k = 0; k < s->dim; ++k) {
+        double sum = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (s->role[i] == MOBILE) s->v[k * n + i] = v[k * n + i];
+            else if (s->role[i] == FIXED) s->v[k * n + i] = 0.0;
+            else sum += v[k * n + i];
+        }
+        if (s->n_rigid > 0) s->VR[k] = sum / s->n_rigid;
+        for (int i = 0; i < n; ++i)
+            if (s->role[i] == RIGID) s->v[k * n + i] = s->VR[k];
+    }
+}
+
+void orc_set_reference(orc_sys *s, const double *rO)
+{
+    memcpy(s->rO, rO, sizeof(double) * (size_t)s->dim * s->n);
+    s->have_force = 0;
+}
+
+void orc_set_pair_method(orc_sys *s, int brute) { s->brute = brute; }
+
+/* Maxwell-Boltzmann draw: v = sqrt(kT/m) z with tag 1 at step 0; the rigid
+ * body (particle index n) with its total mass. */
+void orc_init_velocities(orc_sys *s)
+{
+    const int n = s->n;
+    double z[4];
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < s->dim; ++k) s->v[k * n + i] = 0.0;
+        if (s->role[i] != MOBILE) continue;
+        orc_normals(s->p.seed, 0, (uint32_t)i, 1u, z);
+        double sc = sqrt(s->p.kT / s->p.mass);
+        for (int k = 0; k < s->dim; ++k) s->v[k * n + i] = sc * z[k];
+    }
+    if (s->n_rigid > 0) {
+        orc_normals(s->p.seed, 0, (uint32_t)n, 1u, z);
+        double M = s->p.mass * s->n_rigid;
+        double sc = sqrt(s->p.kT / M);
+        for (int k = 0; k < s->dim; ++k) s->VR[k] = sc * z[k];
+        for (int i = 0; i < n; ++i)
+            if (s->role[i] == RIGID)
+                for (int k = 0; k < s->dim; ++k) s->v[k * n + i] = s->VR[k];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Energy, forces and the Hessian-vector product */
+
+typedef struct {
+    const orc_sys *s;
+    const double *u;
+    double *f, *hu, *e_atom;
+    double e_lj;
+    double shift[2][2];
+} pair_ctx;
+
+/* One Lennard-Jones pair (eq. 9), energy-shifted at rc.  Delta = x_i - x_j
+ * (minimum image).  f = -phi'(r)/r so that F_i += f Delta; the pair Hessian
+ * block is B I + C Delta Delta^T with B = phi'/r = -f and
+ * C = (phi'' - phi'/r)/r^2; (Hu)_i += B w + C (Delta.w) Delta, w = u_i - u_j,
+ * with the opposite sign on j. */
+static void lj_pair(void *vctx, int i, int j)
+{
+    pair_ctx *c = (pair_ctx *)vctx;
+    const orc_sys *s = c->s;
+    const orc_params *p = &s->p;
+    const int n = s->n, dim = s->dim;
+    double D[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+    double r2 = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        D[k] = -minimg(s->x[k * n + j] - s->x[k * n + i], p->box[k], p->periodic[k]);
+        r2 = r2 + D[k] * D[k];
+    }
+    if (!(r2 < p->rc * p->rc)) return;
+    int a = s->type[i], b = s->type[j];
+    double eps = p->eps[a][b];
+    double s2 = p->sig[a][b] * p->sig[a][b];
+    double r2i = 1.0 / r2;
+    double sr2 = s2 * r2i;
+    double sr6 = sr2 * sr2 * sr2;
+    double phi = 4.0 * eps * (sr6 * sr6 - sr6) - c->shift[a][b];
+    double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
+    double B = -f;
+    double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
+    double Dw = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        w[k] = c->u[k * n + i] - c->u[k * n + j];
+        Dw = Dw + D[k] * w[k];
+    }
+    for (int k = 0; k < dim; ++k) {
+        c->f[k * n + i] += f * D[k];
+        c->f[k * n + j] -= f * D[k];
+        double h = B * w[k] + C * Dw * D[k];
+        c->hu[k * n + i] += h;
+        c->hu[k * n + j] -= h;
+    }
+    c->e_atom[i] += 0.5 * phi;
+    c->e_atom[j] += 0.5 * phi;
+    c->e_lj += phi;
+}
+
+/* Slope bias dV1(g) of eq. 14 and its derivative d dV1 / dg. */
+static void bias_switch(const orc_params *p, double g, double *dv, double *dvp)
+{
+    if (g >= p->g_hi) { *dv = p->dv_max; *dvp = 0.0; return; }
+    if (g <= p->g_lo) { *dv = 0.0; *dvp = 0.0; return; }
+    double xi = (g - p->g_hi) / (p->g_lo - p->g_hi);
+    double xm1 = 1.0;
+    for (int q = 0; q < p->m_b - 1; ++q) xm1 *= xi;  /* xi^(m-1) */
+    double xm = xm1 * xi;                            /* xi^m */
+    double one = 1.0 - xm;
+    *dv = p->dv_max * one * one;
+    *dvp = -2.0 * p->m_b * p->dv_max * one * xm1 / (p->g_lo - p->g_hi);
+}
+
+static double slider_at(const orc_params *p, int64_t step)
+{
+    return p->x_slider + p->v_slider * ((double)step * p->dt);
+}
+
+/* Full evaluation at the current positions.  Writes the scalars into *sc. */
+static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot,
+                     double *e_atom, orc_scalars *sc)
+{
+    const orc_params *p = &s->p;
+    const int n = s->n, dim = s->dim;
+    const size_t nd = (size_t)dim * n;
+    double *u = (double *)calloc(nd, sizeof(double));
+    memset(f, 0, sizeof(double) * nd);
+    memset(hu, 0, sizeof(double) * nd);
+    memset(e_atom, 0, sizeof(double) * n);
+
+    /* u = r - r_O (eq. 7), minimum image; fixed atoms are not degrees of
+     * freedom and carry u = 0. */
+    for (int i = 0; i < n; ++i) {
+        if (s->role[i] == FIXED) continue;
+        for (int k = 0; k < dim; ++k)
+            u[k * n + i] = minimg(s->x[k * n + i] - s->rO[k * n + i], p->box[k], p->periodic[k]);
+    }
+
+    pair_ctx c;
+    c.s = s; c.u = u; c.f = f; c.hu = hu; c.e_atom = e_atom; c.e_lj = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double s2 = p->sig[a][b] * p->sig[a][b];
+            double sr2 = s2 / (p->rc * p->rc);
+            double sr6 = sr2 * sr2 * sr2;
+            c.shift[a][b] = 4.0 * p->eps[a][b] * (sr6 * sr6 - sr6);
+        }
+    if (s->brute) {
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                if (excluded(s->role, i, j)) continue;
+                lj_pair(&c, i, j);
+            }
+    } else {
+        for_pairs_cells(p, s->x, s->role, p->rc, 1, lj_pair, &c);
+    }
+
+    /* Slider drive on the rigid layer (Sec. 3.1.1): spring k along x to the
+     * slider, a y anchor of the same stiffness in 3D, and the normal load F_N
+     * pushing down along the last axis.  Each rigid atom carries 1/n_R of the
+     * drive force; the drive Hessian couples all rigid atoms with k/n_R^2. */
+    double v_drive = 0.0, xs = slider_at(p, s->step), x_tip = 0.0, f_lat = 0.0;
+    if (s->n_rigid > 0) {
+        const int nR = s->n_rigid;
+        const int perp = dim - 1;
+        double Fd[3] = {0, 0, 0};
+        x_tip = s->XR[0] - s->XR0[0];
+        f_lat = p->k_spring * (xs - x_tip);
+        v_drive = 0.5 * p->k_spring * (xs - x_tip) * (xs - x_tip);
+        Fd[0] = p->k_spring * (xs - x_tip);
+        if (dim == 3) {
+            double dy = s->XR[1] - s->XR0[1];
+            v_drive += 0.5 * p->k_spring * dy * dy;
+            Fd[1] = -p->k_spring * dy;
+        }
+        v_drive += p->f_normal * (s->XR[perp] - s->XR0[perp]);
+        Fd[perp] += -p->f_normal;
+        double UR[3] = {0, 0, 0};
+        for (int i = 0; i < n; ++i)
+            if (s->role[i] == RIGID)
+                for (int k = 0; k < dim; ++k) UR[k] += u[k * n + i];
+        int nspring = (dim == 3) ? 2 : 1;   /* axes with a spring */
+        for (int i = 0; i < n; ++i) {
+            if (s->role[i] != RIGID) continue;
+            for (int k = 0; k < dim; ++k) f[k * n + i] += Fd[k] / nR;
+            for (int k = 0; k < nspring; ++k)
+                hu[k * n + i] += p->k_spring / ((double)nR * nR) * UR[k];
+        }
+    }
+
+    /* d (eq. 7), slope g = grad V . s = -F.u/d (eq. 5). */
+    double d2 = 0.0, G = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (s->role[i] == FIXED) continue;
+        for (int k = 0; k < dim; ++k) {
+            d2 += u[k * n + i] * u[k * n + i];
+            G += f[k * n + i] * u[k * n + i];
+        }
+    }
+    double d = sqrt(d2);
+    double g = (d < 1e-12) ? 0.0 : -G / d;
+
+    /* Bias: eq. 13 with dV2 = 0 reduces to dV1 (eq. 14).  Its force is
+     * -dV1'(g) grad g with grad g = (Hu - F - g u/d)/d. */
+    double dv = 0.0, dvp = 0.0;
+    if (p->bias_on) bias_switch(p, g, &dv, &dvp);
+    for (size_t q = 0; q < nd; ++q) fb[q] = 0.0;
+    if (p->bias_on && d >= 1e-12 && dvp != 0.0) {
+        for (int i = 0; i < n; ++i) {
+            if (s->role[i] == FIXED) continue;
+            for (int k = 0; k < dim; ++k) {
+                double grad_g = (hu[k * n + i] - f[k * n + i] - g * u[k * n + i] / d) / d;
+                fb[k * n + i] = -dvp * grad_g;
+            }
+        }
+    }
+    for (size_t q = 0; q < nd; ++q) ftot[q] = f[q] + fb[q];
+    for (int k = 0; k < 3; ++k) s->FR[k] = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (s->role[i] == RIGID)
+            for (int k = 0; k < dim; ++k) s->FR[k] += ftot[k * n + i];
+
+    /* kinetic energy: mobile atoms plus the rigid body */
+    double ek = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (s->role[i] == MOBILE)
+            for (int k = 0; k < dim; ++k) ek += 0.5 * p->mass * s->v[k * n + i] * s->v[k * n + i];
+    if (s->n_rigid > 0)
+        for (int k = 0; k < dim; ++k) ek += 0.5 * p->mass * s->n_rigid * s->VR[k] * s->VR[k];
+
+    sc->e_lj = c.e_lj;
+    sc->v_drive = v_drive;
+    sc->e_pot = c.e_lj + v_drive;
+    sc->e_kin = ek;
+    sc->d = d;
+    sc->g = g;
+    sc->dv = dv;
+    sc->dvp = dvp;
+    sc->x_slider = xs;
+    sc->x_tip = x_tip;
+    sc->f_lat = f_lat;
+    sc->t_md = s->t_md;
+    sc->t_hyper = s->t_hyper;
+    sc->step = s->step;
+    sc->flags = isfinite(sc->e_pot) ? 0 : 1;
+    free(u);
+}
+
+void orc_compute(orc_sys *s, double *f_lj, double *hu, double *f_b, double *f_tot,
+                 double *e_atom, orc_scalars *out)
+{
+    const size_t nd = (size_t)s->dim * s->n;
+    double *F = (double *)malloc(sizeof(double) * nd);
+    double *H = (double *)malloc(sizeof(double) * nd);
+    double *B = (double *)malloc(sizeof(double) * nd);
+    double *E = (double *)malloc(sizeof(double) * s->n);
+    orc_scalars sc;
+    evaluate(s, F, H, B, s->ftot, E, &sc);
+    s->have_force = 1;
+    s->last = sc;
+    if (f_lj) memcpy(f_lj, F, sizeof(double) * nd);
+    if (hu) memcpy(hu, H, sizeof(double) * nd);
+    if (f_b) memcpy(f_b, B, sizeof(double) * nd);
+    if (f_tot) memcpy(f_tot, s->ftot, sizeof(double) * nd);
+    if (e_atom) memcpy(e_atom, E, sizeof(double) * s->n);
+    if (out) *out = sc;
+    free(F); free(H); free(B); free(E);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Langevin BAOAB (Leimkuhler & Matthews 2013) per integrated degree of
+ * freedom -- each mobile atom and the rigid body as one particle of mass
+ * n_R m:  B: v += dt/2 F/m;  A: x += dt/2 v;  O: v = c1 v + c2 xi;
+ * A: x += dt/2 v;  new forces;  B: v += dt/2 F/m.  Fixed atoms never move.
+ * The noise xi for step n uses Philox counter (n, particle, tag 0). */
+void orc_step(orc_sys *s, int64_t nsteps)
+{
+    const orc_params *p = &s->p;
+    const int n = s->n, dim = s->dim;
+    const size_t nd = (size_t)dim * n;
+    double *F = (double *)malloc(sizeof(double) * nd);
+    double *H = (double *)malloc(sizeof(double) * nd);
+    double *B = (double *)malloc(sizeof(double) * nd);
+    double *E = (double *)malloc(sizeof(double) * n);
+    if (!s->have_force) {
+        evaluate(s, F, H, B, s->ftot, E, &s->last);
+        s->have_force = 1;
+    }
+    const double dt = p->dt, hdt = 0.5 * p->dt;
+    const double c1 = exp(-p->gamma * dt);
+    const double c2 = sqrt((1.0 - c1 * c1) * p->kT / p->mass);
+    const double M = p->mass * s->n_rigid;
+    const double c2R = s->n_rigid > 0 ? sqrt((1.0 - c1 * c1) * p->kT / M) : 0.0;
+    double z[4];
+    for (int64_t it = 0; it < nsteps; ++it) {
+        const int64_t step = s->step;
+        for (int i = 0; i < n; ++i) {
+            if (s->role[i] != MOBILE) continue;
+            orc_normals(p->seed, step, (uint32_t)i, 0u, z);
+            for (int k = 0; k < dim; ++k) {
+                double v = s->v[k * n + i];
+                double x = s->x[k * n + i];
+                v = v + hdt * s->ftot[k * n + i] / p->mass;
+                x = x + hdt * v;
+                v = c1 * v + c2 * z[k];
+                x = x + hdt * v;
+                s->x[k * n + i] = wrap(x, p->box[k], p->periodic[k]);
+                s->v[k * n + i] = v;
+            }
+        }
+        if (s->n_rigid > 0) {
+            orc_normals(p->seed, step, (uint32_t)n, 0u, z);
+            for (int k = 0; k < dim; ++k) {
+                double v = s->VR[k];
+                double x = s->XR[k];
+                v = v + hdt * s->FR[k] / M;
+                x = x + hdt * v;
+                v = c1 * v + c2R * z[k];
+                x = x + hdt * v;
+                s->XR[k] = x;
+                s->VR[k] = v;
+            }
+            place_rigid(s);
+        }
+        s->step = step + 1;
+        evaluate(s, F, H, B, s->ftot, E, &s->last);
+        for (int i = 0; i < n; ++i) {
+            if (s->role[i] != MOBILE) continue;
+            for (int k = 0; k < dim; ++k)
+                s->v[k * n + i] = s->v[k * n + i] + hdt * s->ftot[k * n + i] / p->mass;
+        }
+        if (s->n_rigid > 0) {
+            for (int k = 0; k < dim; ++k) s->VR[k] = s->VR[k] + hdt * s->FR[k] / M;
+            for (int i = 0; i < n; ++i)
+                if (s->role[i] == RIGID)
+                    for (int k = 0; k < dim; ++k) s->v[k * n + i] = s->VR[k];
+        }
+        /* boosted clock, right Riemann sum: dV at the post-step positions */
+        s->t_md += dt;
+        s->t_hyper += dt * exp(s->last.dv / p->kT);
+        /* refresh kinetic energy and clock in the reported scalars */
+        double ek = 0.0;
+        for (int i = 0; i < n; ++i)
+            if (s->role[i] == MOBILE)
+                for (int k = 0; k < dim; ++k) ek += 0.5 * p->mass * s->v[k * n + i] * s->v[k * n + i];
+        for (int k = 0; k < dim; ++k) ek += 0.5 * M * s->VR[k] * s->VR[k];
+        s->last.e_kin = ek;
+        s->last.t_md = s->t_md;
+        s->last.t_hyper = s->t_hyper;
+    }
+    free(F); free(H); free(B); free(E);
+}
+
+void orc_get_positions(const orc_sys *s, double *x)
+{
+    memcpy(x, s->x, sizeof(double) * (size_t)s->dim * s->n);
+}
+
+void orc_get_velocities(const orc_sys *s, double *v)
+{
+    memcpy(v, s->v, sizeof(double) * (size_t)s->dim * s->n);
+}
+
+void orc_get_scalars(const orc_sys *s, orc_scalars *out) { *out = s->last; }
+
+void orc_get_rigid(const orc_sys *s, double XR[3], double VR[3], double XR0[3])
+{
+    for (int k = 0; k < 3; ++k) { XR[k] = s->XR[k]; VR[k] = s->VR[k]; XR0[k] = s->XR0[k]; }
+}
+
+/* ------------------------------------------------------------------------ */
+/* FIRE (Bitzek et al., PRL 97, 170201, 2006) on the unbiased potential:
+ * mobile atoms and the rigid body are the degrees of freedom; MD with
+ * velocity mixing v <- (1-a) v + a |v| F/|F| while P = F.v > 0, restart with a
+ * smaller step when P <= 0. */
+int64_t orc_fire(orc_sys *s, double ftol, int64_t maxit)
+{
+    orc_params saved = s->p;
+    s->p.bias_on = 0;
+    const int n = s->n, dim = s->dim;
+    const size_t nd = (size_t)dim * n;
+    double *F = (double *)malloc(sizeof(double) * nd);
+    double *H = (double *)malloc(sizeof(double) * nd);
+    double *B = (double *)malloc(sizeof(double) * nd);
+    double *E = (double *)malloc(sizeof(double) * n);
+    double *v = (double *)calloc(nd, sizeof(double));
+    double VR[3] = {0, 0, 0};
+    const double M = s->p.mass * (s->n_rigid > 0 ? s->n_rigid : 1);
+    double dt = s->p.dt, dtmax = 10.0 * s->p.dt, alpha = 0.1;
+    const double alpha0 = 0.1, finc = 1.1, fdec = 0.5, falpha = 0.99;
+    const int nmin = 5;
+    int since_neg = 0;
+    int64_t it;
+    orc_scalars sc;
+    evaluate(s, F, H, B, s->ftot, E, &sc);
+    for (it = 0; it < maxit; ++it) {
+        /* convergence on max |F| over degrees of freedom */
+        double fmax2 = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (s->role[i] != MOBILE) continue;
+            double a = 0.0;
+            for (int k = 0; k < dim; ++k) a += F[k * n + i] * F[k * n + i];
+            if (a > fmax2) fmax2 = a;
+        }
+        if (s->n_rigid > 0) {
+            double a = 0.0;
+            for (int k = 0; k < dim; ++k) a += s->FR[k] * s->FR[k];
+            if (a > fmax2) fmax2 = a;
+        }
+        if (sqrt(fmax2) < ftol) break;
+        /* power and norms */
+        double P = 0.0, vv = 0.0, ff = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (s->role[i] != MOBILE) continue;
+            for (int k = 0; k < dim; ++k) {
+                P += F[k * n + i] * v[k * n + i];
+                vv += v[k * n + i] * v[k * n + i];
+                ff += F[k * n + i] * F[k * n + i];
+            }
+        }
+        for (int k = 0; k < dim && s->n_rigid > 0; ++k) {
+            P += s->FR[k] * VR[k];
+            vv += VR[k] * VR[k];
+            ff += s->FR[k] * s->FR[k];
+        }
+        double vn = sqrt(vv), fn = sqrt(ff);
+        if (P > 0.0) {
+            double mixv = 1.0 - alpha, mixf = (fn > 0.0) ? alpha * vn / fn : 0.0;
+            for (int i = 0; i < n; ++i) {
+                if (s->role[i] != MOBILE) continue;
+                for (int k = 0; k < dim; ++k) v[k * n + i] = mixv * v[k * n + i] + mixf * F[k * n + i];
+            }
+            for (int k = 0; k < dim; ++k) VR[k] = mixv * VR[k] + mixf * s->FR[k];
+            if (since_neg > nmin) {
+                dt = dt * finc; if (dt > dtmax) dt = dtmax;
+                alpha *= falpha;
+            }
+            since_neg++;
+        } else {
+            dt *= fdec;
+            alpha = alpha0;
+            since_neg = 0;
+            for (size_t q = 0; q < nd; ++q) v[q] = 0.0;
+            for (int k = 0; k < 3; ++k) VR[k] = 0.0;
+        }
+        /* semi-implicit Euler step */
+        for (int i = 0; i < n; ++i) {
+            if (s->role[i] != MOBILE) continue;
+            for (int k = 0; k < dim; ++k) {
+                v[k * n + i] += dt * F[k * n + i] / s->p.mass;
+                s->x[k * n + i] = wrap(s->x[k * n + i] + dt * v[k * n + i], s->p.box[k], s->p.periodic[k]);
+            }
+        }
+        if (s->n_rigid > 0) {
+            for (int k = 0; k < dim; ++k) {
+                VR[k] += dt * s->FR[k] / M;
+                s->XR[k] += dt * VR[k];
+            }
+            place_rigid(s);
+        }
+        evaluate(s, F, H, B, s->ftot, E, &sc);
+    }
+    free(F); free(H); free(B); free(E); free(v);
+    s->p = saved;
+    s->have_force = 0;
+    return it < maxit ? it : -it;
+}

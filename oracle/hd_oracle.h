@@ -1,0 +1,113 @@
+/*
+ * FP64 CPU oracle for the hyperdynamics-for-sliding hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is a plain, slow, obviously
+ * correct reference for what the GPU path computes.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never calls it.  It shares no code, header, table or helper
+ * with the GPU library.
+ *
+ * What it computes (Kim & Falk, "Accelerated molecular dynamics simulation
+ * of low-velocity frictional sliding"):
+ *   - Lennard-Jones pair potential with a type table (eq. 9; parameters of
+ *     Sec. 3.1.1 and Sec. 3.2.1), energy-shifted at the cutoff rc;
+ *   - the slider drive on the rigid top layer (Sec. 3.1.1), lateral force
+ *     F_R = k (x_S - x_T) (eq. 10);
+ *   - the local variables d (eq. 7) and slope g = grad V . s (eq. 5) about
+ *     the basin minimum r_O, over the generalised position vector;
+ *   - the slope bias dV1(g) (eq. 14) combined by eq. 13 with dV2 = 0, and its
+ *     force via the Hessian-vector product H u;
+ *   - the boosted clock t_hyper = sum dt exp(dV/kT) (eq. 3 as a time average;
+ *     eq. 8 fixes what it means for stepped sliding);
+ *   - a Langevin BAOAB step (replaces the paper's Nose-Hoover chain);
+ *   - Philox4x32-10 + Box-Muller normals;
+ *   - a FIRE minimiser for r_O.
+ *
+ * Parity unpinned: none of the functions below; each is pinned by tests
+ * (closed forms, finite differences, invariants, brute force, limits).
+ *
+ * Units: reduced LJ units.  Arrays are SoA: x[k*n + i] is component k of
+ * atom i.  Roles: 0 mobile, 1 fixed, 2 rigid.  Types: 0 substrate, 1 tip.
+ */
+#ifndef HD_ORACLE_H
+#define HD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t dim, n;
+    double box[3];
+    int32_t periodic[3];
+    double mass;
+    double eps[2][2], sig[2][2], rc, skin;
+    double dt, gamma, kT;
+    uint64_t seed;
+    double k_spring, f_normal, x_slider, v_slider;
+    int32_t bias_on, m_b;
+    double dv_max, g_lo, g_hi;
+} orc_params;
+
+typedef struct {
+    double e_lj, v_drive, e_pot, e_kin;
+    double d, g, dv, dvp;
+    double x_slider, x_tip, f_lat;
+    double t_md, t_hyper;
+    int64_t step;
+    int32_t flags;
+} orc_scalars;
+
+/* Opaque simulation state for one system. */
+typedef struct orc_sys orc_sys;
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Four standard normals from counter (step, particle, tag) and the seed,
+ * via (w + 0.5) 2^-32 uniforms and the Box-Muller transform. */
+void orc_normals(uint64_t seed, int64_t step, uint32_t particle, uint32_t tag, double z[4]);
+
+/* Pairs (i<j) with r^2 < rl^2, excluding fixed-fixed and rigid-rigid pairs
+ * when exclude != 0.  Brute force over all pairs.  Returns the count; writes
+ * at most cap pairs as (i, j) into ij. */
+int64_t orc_pairs_brute(const orc_params *p, const double *x, const uint8_t *role,
+                        double rl, int exclude, int32_t *ij, int64_t cap);
+/* Same set via the oracle's own cell list. */
+int64_t orc_pairs_cells(const orc_params *p, const double *x, const uint8_t *role,
+                        double rl, int exclude, int32_t *ij, int64_t cap);
+
+orc_sys *orc_create(const orc_params *p, const double *x, const uint8_t *type,
+                    const uint8_t *role, const double *rO);
+void orc_destroy(orc_sys *s);
+void orc_set_params(orc_sys *s, const orc_params *p);
+void orc_set_positions(orc_sys *s, const double *x);
+void orc_set_velocities(orc_sys *s, const double *v);
+void orc_set_reference(orc_sys *s, const double *rO);
+/* Maxwell-Boltzmann velocities from the seed (tag 1, step 0). */
+void orc_init_velocities(orc_sys *s);
+/* 0 = cell list (default), 1 = brute force over all pairs. */
+void orc_set_pair_method(orc_sys *s, int brute);
+
+/* Evaluate energy, forces, Hu and the bias at the current positions.  Does not
+ * advance the clock.  Outputs (any may be NULL): f_lj = -grad V (LJ + drive
+ * share), hu = H u, f_b = bias force, f_tot = f_lj + f_b, e_atom = per-atom
+ * half pair energies. */
+void orc_compute(orc_sys *s, double *f_lj, double *hu, double *f_b, double *f_tot,
+                 double *e_atom, orc_scalars *out);
+/* Advance nsteps BAOAB steps (bias included when enabled). */
+void orc_step(orc_sys *s, int64_t nsteps);
+void orc_get_positions(const orc_sys *s, double *x);
+void orc_get_velocities(const orc_sys *s, double *v);
+void orc_get_scalars(const orc_sys *s, orc_scalars *out);
+/* Rigid body state: centre of mass X_R, velocity V_R, initial X_R(0). */
+void orc_get_rigid(const orc_sys *s, double XR[3], double VR[3], double XR0[3]);
+/* Relax positions with FIRE (bias off) until max |F| < ftol on integrated
+ * degrees of freedom.  Returns iterations used (negative if not converged).
+ * The relaxed positions become the current positions. */
+int64_t orc_fire(orc_sys *s, double ftol, int64_t maxit);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,552 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test below checks the oracle against something other than itself:
+closed forms of eq. 9, the tip-bond constants printed with eq. 12, finite
+differences of the energy (forces, Hu, slope g of eq. 5, bias force), the
+boundary values of eq. 14, limits of eq. 3, Newton's third law, known-answer
+vectors of Philox4x32-10, the exact stationary statistics of BAOAB on a
+harmonic oscillator, time reversibility of velocity Verlet, and brute-force
+neighbour sets.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from hd_inputs import (AFCC, A2D, ROLE_FIXED, ROLE_MOBILE, ROLE_RIGID, SystemSpec,
+                       build_2d, build_3d, perturbed)
+from tests.conftest import golden
+
+
+def small2d(**kw):
+    s = build_2d(nx=12, ny=4, tip_w=4, tip_h=3, n_fixed_rows=1)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def small3d(**kw):
+    s = build_3d(7, 7, 2, R=2.0)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def pair_system(r, types=(0, 0), eps_ts=0.5):
+    """Two mobile atoms on the x axis of a wide open 2D box."""
+    pos = np.array([[10.0, 10.0 + r], [0.0, 0.0]])
+    return SystemSpec(dim=2, pos=pos, type=np.array(types, np.uint8),
+                      role=np.array([ROLE_MOBILE, ROLE_MOBILE], np.uint8),
+                      box=np.array([40.0, 0.0, 0.0]), periodic=np.array([1, 0, 0], np.int32),
+                      eps=np.array([[1.0, eps_ts], [eps_ts, 1.0]]))
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+def test_philox_known_answers(oracle_mod):
+    with open("tests/golden/philox4x32_10_kat.txt") as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        vals = [int(v, 16) for v in r]
+        out = oracle_mod.philox4x32_10(vals[0:4], vals[4:6])
+        assert list(out) == vals[6:10]
+
+
+def test_normals_moments(oracle_mod):
+    z = np.array([oracle_mod.normals(12345, s, p, 0) for s in range(50) for p in range(100)]).ravel()
+    assert abs(z.mean()) < 4.0 / math.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 4.0 * math.sqrt(2.0 / z.size)
+    # fourth moment of a standard normal is 3
+    assert abs((z ** 4).mean() - 3.0) < 0.25
+    # different tags and steps give different streams
+    assert not np.array_equal(oracle_mod.normals(1, 0, 0, 0), oracle_mod.normals(1, 0, 0, 1))
+    assert not np.array_equal(oracle_mod.normals(1, 0, 0, 0), oracle_mod.normals(1, 1, 0, 0))
+
+
+# --------------------------------------------------------------------------
+# Lennard-Jones closed forms (eq. 9) and the tip-bond constants (eq. 12)
+# --------------------------------------------------------------------------
+def test_lj_closed_forms(oracle_mod):
+    g = golden("lj_closed_forms.txt")
+    rmin = 2.0 ** (1.0 / 6.0)
+    assert rmin == pytest.approx(float(g["r_min"]), rel=1e-15)
+    o = oracle_mod.OracleSystem(pair_system(rmin))
+    r = o.compute()
+    assert np.abs(r["f_lj"]).max() < 1e-13
+    assert r["e_lj"] == pytest.approx(float(g["well_depth_shifted"]), abs=1e-12)
+    # force magnitude at r = sigma is 24 eps/sigma, repulsive
+    o = oracle_mod.OracleSystem(pair_system(1.0))
+    r = o.compute()
+    assert r["f_lj"][0, 0] == pytest.approx(-float(g["force_at_sigma"]), rel=1e-14)
+    assert r["f_lj"][0, 1] == pytest.approx(float(g["force_at_sigma"]), rel=1e-14)
+    assert r["e_lj"] == pytest.approx(0.0 - float(g["phi_rc"]), abs=1e-14)
+    # mixed pair scales with eps_ab
+    o = oracle_mod.OracleSystem(pair_system(1.0, types=(0, 1), eps_ts=0.5))
+    assert o.compute()["f_lj"][0, 1] == pytest.approx(12.0, rel=1e-14)
+    # beyond the cutoff nothing interacts
+    o = oracle_mod.OracleSystem(pair_system(2.5000001))
+    r = o.compute()
+    assert r["e_lj"] == 0.0 and np.all(r["f_lj"] == 0.0)
+
+
+def test_hessian_at_minimum_matches_eq12(oracle_mod):
+    """H u with u along the bond gives phi''(r_min) = 72 * 2^(-1/3), which the
+    paper rounds to the harmonic stiffness k = 57.2 at r_O = 1.12 (eq. 12)."""
+    g = golden("eq12_tip_bond.txt")
+    c = golden("lj_closed_forms.txt")
+    rmin = 2.0 ** (1.0 / 6.0)
+    spec = pair_system(rmin)
+    # reference r_O displaced so that u = (+1, 0) on atom 0 and 0 on atom 1
+    rO = spec.pos.copy()
+    rO[0, 0] -= 1.0
+    o = oracle_mod.OracleSystem(spec, rO=rO)
+    hu = o.compute()["hu"]
+    # (Hu)_0 = H_pair (u_0 - u_1); along the bond that is phi''
+    assert hu[0, 0] == pytest.approx(float(c["curvature_min"]), rel=1e-12)
+    assert hu[0, 0] == pytest.approx(72.0 * 2.0 ** (-1.0 / 3.0), rel=1e-13)
+    assert hu[0, 0] == pytest.approx(float(g["k"]), rel=float(g["rtol"]))
+    assert rmin == pytest.approx(float(g["r_O"]), rel=float(g["rtol"]))
+    # transverse direction: phi'(r_min)/r_min = 0
+    rO = spec.pos.copy(); rO[1, 0] -= 1.0
+    o = oracle_mod.OracleSystem(spec, rO=rO)
+    assert abs(o.compute()["hu"][1, 0]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Forces, Hu, slope and bias force against finite differences
+# --------------------------------------------------------------------------
+_SYSCACHE = {}
+
+
+def _energy(oracle_mod, spec, x, rO, key="e_pot"):
+    """Energy at positions x on a system created once per (spec, rO), so the
+    drive's reference position X_R(0) stays that of the unperturbed model."""
+    ck = (id(spec), None if rO is None else rO.tobytes())
+    if ck not in _SYSCACHE:
+        _SYSCACHE.clear()
+        _SYSCACHE[ck] = (spec, oracle_mod.OracleSystem(spec, rO=rO))
+    o = _SYSCACHE[ck][1]
+    o.set_positions(x)
+    r = o.compute()
+    if key == "all":
+        return r
+    return r[key] if key != "bias" else r["dv"]
+
+
+def _at(oracle_mod, spec, x, rO=None):
+    """Full evaluation at x on the cached system (same X_R(0) as _energy)."""
+    return _energy(oracle_mod, spec, x, rO, "all")
+
+
+@pytest.mark.parametrize("maker", [small2d, small3d])
+def test_forces_match_energy_gradient(oracle_mod, maker):
+    spec = maker()
+    x = perturbed(spec, 0.06, 7)
+    r = _at(oracle_mod, spec, x)
+    h = 1e-6
+    mob = np.where(spec.role == ROLE_MOBILE)[0]
+    for i in mob[:: max(1, len(mob) // 12)]:
+        for k in range(spec.dim):
+            xp = x.copy(); xp[k, i] += h
+            xm = x.copy(); xm[k, i] -= h
+            fd = -(_energy(oracle_mod, spec, xp, None) - _energy(oracle_mod, spec, xm, None)) / (2 * h)
+            assert r["f_lj"][k, i] == pytest.approx(fd, rel=2e-6, abs=2e-6)
+
+
+def test_rigid_body_force_matches_energy_gradient(oracle_mod):
+    spec = small2d(x_slider=0.3)
+    x = perturbed(spec, 0.05, 3)
+    r = _at(oracle_mod, spec, x, spec.pos)
+    rig = spec.role == ROLE_RIGID
+    FR = r["f_lj"][:, rig].sum(axis=1)
+    h = 1e-6
+    for k in range(spec.dim):
+        xp = x.copy(); xp[k, rig] += h
+        xm = x.copy(); xm[k, rig] -= h
+        fd = -(_energy(oracle_mod, spec, xp, spec.pos) - _energy(oracle_mod, spec, xm, spec.pos)) / (2 * h)
+        assert FR[k] == pytest.approx(fd, rel=1e-6, abs=1e-6)
+
+
+@pytest.mark.parametrize("maker", [small2d, small3d])
+def test_newton_third_law(oracle_mod, maker):
+    """Internal LJ forces sum to zero; what remains is the drive on the rigid
+    layer (spring along x, anchor along y in 3D, -F_N along the normal)."""
+    spec = maker(x_slider=0.2)
+    x = perturbed(spec, 0.05, 11)
+    o = oracle_mod.OracleSystem(spec, x=x)
+    r = o.compute()
+    XR, _, XR0 = o.rigid()
+    drive = np.zeros(spec.dim)
+    drive[0] = spec.k_spring * (spec.x_slider - (XR[0] - XR0[0]))
+    if spec.dim == 3:
+        drive[1] = -spec.k_spring * (XR[1] - XR0[1])
+    drive[-1] += -spec.f_normal
+    total = r["f_lj"].sum(axis=1)
+    scale = np.abs(r["f_lj"]).sum()
+    assert np.all(np.abs(total - drive) <= 1e-12 * scale)
+    assert r["f_lat"] == pytest.approx(drive[0], abs=1e-14)
+
+
+@pytest.mark.parametrize("maker", [small2d, small3d])
+def test_hu_matches_force_difference(oracle_mod, maker):
+    """H u = -(F(r + h u) - F(r - h u)) / 2h (Hessian-vector product)."""
+    spec = maker(x_slider=0.1)
+    x = perturbed(spec, 0.05, 5)
+    rO = spec.pos.copy()
+    r = _at(oracle_mod, spec, x, rO)
+    u = x - rO
+    for k in range(spec.dim):
+        if spec.periodic[k]:
+            L = spec.box[k]
+            u[k] = u[k] - L * np.round(u[k] / L)
+    u[:, spec.role == ROLE_FIXED] = 0.0
+    h = 1e-5
+    fp = _at(oracle_mod, spec, x + h * u, rO)["f_lj"]
+    fm = _at(oracle_mod, spec, x - h * u, rO)["f_lj"]
+    fd = -(fp - fm) / (2 * h)
+    nf = spec.role != ROLE_FIXED
+    err = np.abs(fd[:, nf] - r["hu"][:, nf]).max() / np.abs(r["hu"][:, nf]).max()
+    assert err < 1e-7
+
+
+@pytest.mark.parametrize("maker", [small2d, small3d])
+def test_slope_is_directional_derivative(oracle_mod, maker):
+    """g = grad V . s with s = u/d (eq. 5, eq. 7)."""
+    spec = maker(x_slider=0.1)
+    x = perturbed(spec, 0.05, 9)
+    rO = spec.pos.copy()
+    r = _at(oracle_mod, spec, x, rO)
+    u = x - rO
+    for k in range(spec.dim):
+        if spec.periodic[k]:
+            u[k] -= spec.box[k] * np.round(u[k] / spec.box[k])
+    u[:, spec.role == ROLE_FIXED] = 0.0
+    d = math.sqrt((u * u).sum())
+    assert r["d"] == pytest.approx(d, rel=1e-13)
+    s = u / d
+    h = 1e-6
+    ep = _energy(oracle_mod, spec, x + h * s, rO)
+    em = _energy(oracle_mod, spec, x - h * s, rO)
+    assert r["g"] == pytest.approx((ep - em) / (2 * h), rel=1e-6)
+
+
+def _bias_spec(oracle_mod, maker, x, rO, frac=0.4, m_b=2):
+    """Thresholds placed so that the current g sits inside (g_L, g_U)."""
+    spec = maker(x_slider=0.1)
+    o = oracle_mod.OracleSystem(spec, rO=rO)
+    o.set_positions(x)
+    g0 = o.compute()["g"]
+    span = 2.0 * abs(g0) + 1.0
+    spec.bias_on, spec.m_b, spec.dv_max = 1, m_b, 0.7
+    spec.g_lo = g0 - frac * span
+    spec.g_hi = g0 + (1.0 - frac) * span
+    return spec
+
+
+def test_bias_switch_boundaries_and_derivative(oracle_mod):
+    spec = small2d()
+    x = perturbed(spec, 0.05, 2)
+    rO = spec.pos.copy()
+    base = _bias_spec(oracle_mod, small2d, x, rO)
+    g0 = oracle_mod.OracleSystem(base, x=x, rO=rO).compute()["g"]
+
+    def dv_at(shift, m_b=2):
+        # dV(g0 + shift) == dV evaluated with both thresholds moved by -shift
+        s = base.copy(); s.m_b = m_b
+        s.g_lo, s.g_hi = base.g_lo - shift, base.g_hi - shift
+        r = oracle_mod.OracleSystem(s, x=x, rO=rO).compute()
+        return r["dv"], r["dvp"]
+
+    # plateau values of eq. 14
+    assert dv_at(base.g_hi - g0)[0] == base.dv_max      # g = g_U
+    assert dv_at(base.g_hi - g0 + 1.0)[0] == base.dv_max
+    assert dv_at(base.g_lo - g0)[0] == 0.0              # g = g_L
+    assert dv_at(base.g_lo - g0 - 1.0)[0] == 0.0
+    # range [0, dV_max] (stated under eq. 15)
+    for t in np.linspace(-1.2, 1.2, 25):
+        v, _ = dv_at(t * (base.g_hi - base.g_lo))
+        assert 0.0 <= v <= base.dv_max
+    # derivative: analytic vs central difference; C1 at both ends for m >= 2
+    for m_b in (1, 2, 3):
+        for t in (0.1, 0.5, 0.9):
+            sh = base.g_lo + t * (base.g_hi - base.g_lo) - g0
+            h = 1e-6 * (base.g_hi - base.g_lo)
+            _, dvp = dv_at(sh, m_b)
+            fd = (dv_at(sh + h, m_b)[0] - dv_at(sh - h, m_b)[0]) / (2 * h)
+            assert dvp == pytest.approx(fd, rel=1e-6)
+    eps = 1e-7 * (base.g_hi - base.g_lo)
+    assert dv_at(base.g_hi - g0 - eps)[1] < 1e-5
+    assert dv_at(base.g_lo - g0 + eps)[1] < 1e-5
+    # closed form in the middle for m = 2: xi = 1/2 -> dV = dVmax (1 - 1/4)^2
+    mid = 0.5 * (base.g_lo + base.g_hi) - g0
+    assert dv_at(mid)[0] == pytest.approx(base.dv_max * 0.75 ** 2, rel=1e-12)
+
+
+@pytest.mark.parametrize("maker", [small2d, small3d])
+def test_bias_force_matches_bias_gradient(oracle_mod, maker):
+    spec0 = maker()
+    x = perturbed(spec0, 0.05, 4)
+    rO = spec0.pos.copy()
+    spec = _bias_spec(oracle_mod, maker, x, rO)
+    r = _at(oracle_mod, spec, x, rO)
+    assert 0.0 < r["dv"] < spec.dv_max
+    h = 1e-6
+    mob = np.where(spec.role == ROLE_MOBILE)[0]
+    worst = 0.0
+    scale = np.abs(r["f_b"]).max()
+    for i in mob[:: max(1, len(mob) // 10)]:
+        for k in range(spec.dim):
+            xp = x.copy(); xp[k, i] += h
+            xm = x.copy(); xm[k, i] -= h
+            fd = -(_energy(oracle_mod, spec, xp, rO, "bias") - _energy(oracle_mod, spec, xm, rO, "bias")) / (2 * h)
+            worst = max(worst, abs(fd - r["f_b"][k, i]) / scale)
+    assert worst < 1e-6
+    # the rigid body as a whole
+    rig = spec.role == ROLE_RIGID
+    FbR = r["f_b"][:, rig].sum(axis=1)
+    for k in range(spec.dim):
+        xp = x.copy(); xp[k, rig] += h
+        xm = x.copy(); xm[k, rig] -= h
+        fd = -(_energy(oracle_mod, spec, xp, rO, "bias") - _energy(oracle_mod, spec, xm, rO, "bias")) / (2 * h)
+        assert abs(fd - FbR[k]) / scale < 1e-6
+    np.testing.assert_array_equal(r["f_tot"], r["f_lj"] + r["f_b"])
+
+
+# --------------------------------------------------------------------------
+# Boosted clock (eq. 3) limits
+# --------------------------------------------------------------------------
+def test_clock_limits(oracle_mod):
+    spec = small2d(kT=0.1)
+    spec.bias_on, spec.dv_max = 1, 0.3
+    # dV == dVmax everywhere: bias force vanishes, trajectory equals the
+    # unbiased one bit for bit, t_hyper = t_MD exp(dVmax/kT)
+    full = spec.copy(); full.g_lo, full.g_hi = -2e30, -1e30
+    off = spec.copy(); off.bias_on = 0
+    a = oracle_mod.OracleSystem(full); a.init_velocities(); a.step(60)
+    b = oracle_mod.OracleSystem(off); b.init_velocities(); b.step(60)
+    np.testing.assert_array_equal(a.positions(), b.positions())
+    np.testing.assert_array_equal(a.velocities(), b.velocities())
+    sa = a.scalars()
+    assert sa["dv"] == spec.dv_max
+    assert sa["t_hyper"] == pytest.approx(sa["t_md"] * math.exp(spec.dv_max / spec.kT), rel=1e-13)
+    assert sa["t_md"] == pytest.approx(60 * spec.dt, rel=1e-13)
+    # dV == 0 everywhere: t_hyper == t_MD
+    zero = spec.copy(); zero.g_lo, zero.g_hi = 1e30, 2e30
+    c = oracle_mod.OracleSystem(zero); c.init_velocities(); c.step(30)
+    sc = c.scalars()
+    assert sc["t_hyper"] == sc["t_md"]
+
+
+# --------------------------------------------------------------------------
+# Integrator
+# --------------------------------------------------------------------------
+def test_velocity_verlet_time_reversible(oracle_mod):
+    """gamma = 0, kT = 0: BAOAB is velocity Verlet, exactly time reversible."""
+    spec = small2d(gamma=0.0, kT=0.0, x_slider=0.2)
+    x = perturbed(spec, 0.05, 21)
+    o = oracle_mod.OracleSystem(spec, x=x)
+    v0 = np.zeros((2, spec.n))
+    rng = np.random.default_rng(0)
+    v0[:, spec.role == ROLE_MOBILE] = rng.normal(0, 0.3, size=(2, int((spec.role == ROLE_MOBILE).sum())))
+    v0[:, spec.role == ROLE_RIGID] = 0.05
+    o.set_velocities(v0)
+    x0 = o.positions()
+    o.step(200)
+    o.set_velocities(-o.velocities())
+    o.step(200)
+    d = o.positions() - x0
+    d[0] -= spec.box[0] * np.round(d[0] / spec.box[0])
+    assert np.abs(d).max() < 1e-9
+    np.testing.assert_allclose(-o.velocities(), v0, atol=1e-9)
+
+
+@pytest.mark.parametrize("bias", [0, 1])
+def test_nve_energy_error_is_second_order(oracle_mod, bias):
+    """Energy fluctuation of velocity Verlet scales as dt^2; with the bias on
+    the conserved quantity is K + V + dV."""
+    spec = small2d(gamma=0.0, kT=0.0, x_slider=0.15)
+    x = perturbed(spec, 0.04, 8)
+    if bias:
+        spec = _bias_spec(oracle_mod, small2d, x, spec.pos.copy(), frac=0.3)
+        spec.gamma, spec.kT = 0.0, 1.0   # kT only scales the clock here
+
+    def spread(dt, nsteps):
+        s = spec.copy(); s.dt = dt
+        o = oracle_mod.OracleSystem(s, x=x)
+        rng = np.random.default_rng(1)
+        v = np.zeros((2, s.n))
+        v[:, s.role == ROLE_MOBILE] = rng.normal(0, 0.2, size=(2, int((s.role == ROLE_MOBILE).sum())))
+        o.set_velocities(v)
+        tot = []
+        for _ in range(nsteps):
+            o.step(1)
+            sc = o.scalars()
+            tot.append(sc["e_pot"] + sc["e_kin"] + sc["dv"])
+        tot = np.array(tot)
+        return tot.max() - tot.min()
+
+    e1 = spread(0.004, 250)
+    e2 = spread(0.002, 500)
+    assert e1 < 5e-3 * spec.n
+    assert 3.0 < e1 / e2 < 5.0
+
+
+def _harmonic_rigid_system(k, nR, kT, gamma, dt):
+    """nR rigid atoms only: the drive spring makes X_R,x a harmonic oscillator
+    of stiffness k and mass nR; no LJ (rigid-rigid pairs are excluded)."""
+    pos = np.array([[1.0 + 1.2 * i for i in range(nR)], [5.0] * nR])
+    return SystemSpec(dim=2, pos=pos, type=np.ones(nR, np.uint8),
+                      role=np.full(nR, ROLE_RIGID, np.uint8),
+                      box=np.array([50.0, 0, 0]), periodic=np.array([1, 0, 0], np.int32),
+                      k_spring=k, f_normal=0.0, kT=kT, gamma=gamma, dt=dt, seed=99)
+
+
+@pytest.mark.slow
+def test_baoab_harmonic_stationary_statistics(oracle_mod):
+    """BAOAB samples a harmonic oscillator's positions exactly for any stable
+    dt: <x^2> = kT/k, while <v^2> = (kT/M)(1 - w^2 dt^2/4)."""
+    k, nR, kT, gamma, dt = 4.0, 10, 1.0, 1.0, 1.0
+    spec = _harmonic_rigid_system(k, nR, kT, gamma, dt)
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    o.step(200)
+    xs, vs = [], []
+    for _ in range(60000):
+        o.step(1)
+        XR, VR, XR0 = o.rigid()
+        xs.append(XR[0] - XR0[0]); vs.append(VR[0])
+    xs, vs = np.array(xs), np.array(vs)
+    M = float(nR)
+    w2 = k / M
+    assert (xs ** 2).mean() == pytest.approx(kT / k, rel=0.03)
+    assert (vs ** 2).mean() == pytest.approx(kT / M * (1 - w2 * dt * dt / 4), rel=0.03)
+    # and clearly not the continuous-time value kT/M
+    assert abs((vs ** 2).mean() - kT / M) > 0.05 * kT / M
+
+
+@pytest.mark.slow
+def test_equipartition(oracle_mod):
+    spec = small2d(kT=0.1, gamma=1.0)
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    o.step(500)
+    ndof = 2 * int((spec.role == ROLE_MOBILE).sum()) + 2
+    ks = []
+    for _ in range(200):
+        o.step(10)
+        ks.append(o.scalars()["e_kin"])
+    assert np.mean(ks) / (0.5 * ndof) == pytest.approx(spec.kT, rel=0.04)
+
+
+def test_maxwell_boltzmann_init(oracle_mod):
+    spec = build_2d(kT=0.1) if False else build_2d()
+    spec.kT = 0.25
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    v = o.velocities()[:, spec.role == ROLE_MOBILE]
+    assert v.var() == pytest.approx(spec.kT, rel=0.08)
+    assert np.all(o.velocities()[:, spec.role == ROLE_FIXED] == 0.0)
+    # draws follow the counter definition: atom i, tag 1, step 0
+    i = int(np.where(spec.role == ROLE_MOBILE)[0][3])
+    z = oracle_mod.normals(spec.seed, 0, i, 1)
+    np.testing.assert_array_equal(o.velocities()[:, i], math.sqrt(spec.kT) * z[:2])
+
+
+def test_fixed_atoms_never_move_and_rigid_layer_stays_rigid(oracle_mod):
+    spec = small3d(kT=0.2)
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    o.step(40)
+    x = o.positions()
+    fx = spec.role == ROLE_FIXED
+    np.testing.assert_array_equal(x[:, fx], spec.pos[:, fx])
+    rig = np.where(spec.role == ROLE_RIGID)[0]
+    d0 = spec.pos[:, rig] - spec.pos[:, rig[:1]]
+    d1 = x[:, rig] - x[:, rig[:1]]
+    for k in range(2):
+        d1[k] -= spec.box[k] * np.round((d1[k] - d0[k]) / spec.box[k])
+    np.testing.assert_allclose(d1, d0, atol=1e-12)
+
+
+def test_fire_relaxes_to_a_minimum(oracle_mod):
+    spec = small2d(x_slider=0.0)
+    o = oracle_mod.OracleSystem(spec, x=perturbed(spec, 0.05, 1))
+    e0 = o.compute()["e_pot"]
+    it = o.fire(ftol=1e-8, maxit=100000)
+    assert it >= 0
+    r = o.compute()
+    assert r["e_pot"] < e0
+    mob = spec.role == ROLE_MOBILE
+    assert np.sqrt((r["f_lj"][:, mob] ** 2).sum(0)).max() < 1e-8
+    # at the minimum with r_O there, d = 0 and the guard sets g = 0
+    o2 = oracle_mod.OracleSystem(spec, x=o.positions(), rO=o.positions())
+    r2 = o2.compute()
+    assert r2["d"] == 0.0 and r2["g"] == 0.0
+
+
+# --------------------------------------------------------------------------
+# Neighbour sets
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("maker", [small2d, small3d, lambda: build_2d(), lambda: build_3d(9, 9, 3, 3.0)])
+def test_cell_pairs_equal_brute_force(oracle_mod, maker):
+    spec = maker()
+    x = perturbed(spec, 0.1, 13)
+    for rl in (2.5, 2.8):
+        for excl in (True, False):
+            a = oracle_mod.pairs_brute(spec, x, rl, excl)
+            b = oracle_mod.pairs_cells(spec, x, rl, excl)
+            sa = set(map(tuple, a)); sb = set(map(tuple, b))
+            assert len(sa) == len(a) and sa == sb
+
+
+def test_pair_edge_cases(oracle_mod):
+    # exactly r = rl (2.75 is exact in binary) is excluded; strict <
+    spec = pair_system(2.75)
+    assert len(oracle_mod.pairs_brute(spec, spec.pos, 2.75)) == 0
+    assert len(oracle_mod.pairs_brute(spec, spec.pos, 2.7500000001)) == 1
+    # pairs straddling the periodic wrap are found by both methods
+    pos = np.array([[0.3, 39.5], [1.0, 1.0]])
+    s2 = SystemSpec(dim=2, pos=pos, type=np.zeros(2, np.uint8), role=np.zeros(2, np.uint8),
+                    box=np.array([40.0, 0, 0]), periodic=np.array([1, 0, 0], np.int32))
+    assert len(oracle_mod.pairs_brute(s2, pos, 2.8)) == 1
+    assert len(oracle_mod.pairs_cells(s2, pos, 2.8)) == 1
+    # fixed-fixed and rigid-rigid pairs are excluded from the interaction set
+    spec = build_2d()
+    pairs = oracle_mod.pairs_brute(spec, spec.pos, 2.8, True)
+    ro = spec.role
+    assert not np.any((ro[pairs[:, 0]] == ROLE_FIXED) & (ro[pairs[:, 1]] == ROLE_FIXED))
+    assert not np.any((ro[pairs[:, 0]] == ROLE_RIGID) & (ro[pairs[:, 1]] == ROLE_RIGID))
+
+
+def test_model_sizes():
+    g = golden("model_sizes.txt")
+    s = build_2d()
+    assert s.n == int(g["2d_total"])
+    assert int((s.role == ROLE_FIXED).sum()) == int(g["2d_fixed"])
+    assert int((s.role == ROLE_RIGID).sum()) == int(g["2d_rigid"])
+    assert int((s.type == 1).sum()) == int(g["2d_tip"])
+    t = build_3d()
+    assert int((t.type == 0).sum()) == int(g["3d_substrate"])
+    assert int((t.role == ROLE_FIXED).sum()) == int(g["3d_fixed"])
+    # every atom sits on a lattice site in registry: nearest distance 2^(1/6)
+    for spec in (s, t):
+        pairs = None
+    assert 20 * 20 * 6 * 4 == int(g["3d_substrate"])
+    assert 100 * 100 * 25 * 4 == int(g["3d_large_substrate"])
+
+
+@pytest.mark.parametrize("maker", [lambda: build_2d(), lambda: build_3d()])
+def test_lattice_in_registry(oracle_mod, maker):
+    """Nearest-neighbour distance everywhere (tip included) is 2^(1/6)."""
+    spec = maker()
+    pairs = oracle_mod.pairs_brute(spec, spec.pos, 1.2, False)
+    d = spec.pos[:, pairs[:, 0]] - spec.pos[:, pairs[:, 1]]
+    for k in range(spec.dim):
+        if spec.periodic[k]:
+            d[k] -= spec.box[k] * np.round(d[k] / spec.box[k])
+    r = np.sqrt((d * d).sum(0))
+    np.testing.assert_allclose(r, 2 ** (1 / 6), rtol=1e-12)
+    # every atom has at least one nearest neighbour
+    assert len(np.unique(pairs)) == spec.n
