@@ -1,0 +1,222 @@
+/*
+ * hd.h -- C ABI of libhd.so, the MI355X (gfx950) hot path of hyperdynamics
+ * for driven frictional sliding (Kim & Falk, "Accelerated molecular dynamics
+ * simulation of low-velocity frictional sliding").
+ *
+ * One context holds a batch of independent AFM tip/substrate models, each at
+ * its own slider position (the parallel slider-position scheme of Sec. 2.3:
+ * the transition probabilities at different stepped slider positions are
+ * independent, so the positions can run at the same time).  Every step of
+ * every system runs in HIP kernels on the GPU:
+ *   - Lennard-Jones energy and forces with a type table (eq. 9; parameters of
+ *     Sec. 3.1.1 / Sec. 3.2.1), energy-shifted at rc, over cell-binned Verlet
+ *     neighbour lists with a skin;
+ *   - the slider drive on the rigid top tip layer: spring k to the slider
+ *     along x, anchor of stiffness k along y in 3D, normal load F_N pushing
+ *     down (Sec. 3.1.1, Sec. 3.2.1); lateral force F_R = k (x_S - x_T) (eq. 10);
+ *   - the slope bias: d (eq. 7), g = grad V . s (eq. 5), dV1(g) (eq. 14)
+ *     combined by eq. 13 with the eigenvalue term dV2 set to zero, and the
+ *     bias force -dV1'(g) grad g with grad g = (H u - F - g u/d)/d;
+ *   - the boosted clock t_hyper = sum dt exp(dV/kT) (eq. 3, eq. 8);
+ *   - a Langevin BAOAB step (the paper's Nose-Hoover chain is replaced by a
+ *     Langevin thermostat), with Philox4x32-10 normals.
+ *
+ * Conventions
+ *   - Every call returns hd_status; nothing throws across the ABI.  On
+ *     failure hd_last_error(ctx) gives a message.  After HD_E_HIP the context
+ *     is poisoned and only hd_destroy is valid.
+ *   - Host arrays are owned by the caller and copied during the call.  Per-atom
+ *     arrays are SoA float64 of shape [dim][n_atoms] (component k of atom i at
+ *     k*n_atoms + i).  Device pointers (the *_device calls) must hold the same
+ *     layout and stay valid until the call returns.
+ *   - Device memory is owned by the context (hd_finalize allocates it,
+ *     hd_destroy frees it).  Work is ordered on the context's HIP stream; the
+ *     hd_read_* calls synchronise that stream before returning.
+ *   - Systems are added before hd_finalize; per-system parameters (slider,
+ *     bias, thermostat) may change afterwards.
+ *   - One context per host thread.
+ */
+#ifndef HD_H
+#define HD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HD_OK = 0,
+    HD_E_ARG = -1,       /* invalid argument (null pointer, bad index, bad size) */
+    HD_E_OOM = -2,       /* device or host allocation failed */
+    HD_E_HIP = -3,       /* HIP runtime error; the context is poisoned */
+    HD_E_STATE = -4,     /* call not valid in the current lifecycle state */
+    HD_E_UNSTABLE = -5,  /* every system has been frozen as unstable */
+    HD_E_NOGPU = -6      /* no usable gfx950 device */
+} hd_status;
+
+/* Arithmetic of the pair pass.  Positions, velocities, reductions, the bias
+ * scalars and the clock are float64 in both. */
+typedef enum {
+    HD_FP64 = 0,   /* float64 pair arithmetic */
+    HD_FP32C = 1   /* float32 pair arithmetic with compensated per-atom sums;
+                      displacements and the cutoff decision in float64 */
+} hd_precision;
+
+/* How hd_step schedules the batch.  BATCHED runs every system in one
+ * persistent launch per chunk of steps (one workgroup per system).  GRID runs
+ * a short sequence of kernels per step over all systems, captured in a HIP
+ * graph.  SEQUENTIAL is GRID applied to one system at a time (the plain
+ * single-system path). */
+typedef enum { HD_EXEC_BATCHED = 0, HD_EXEC_GRID = 1, HD_EXEC_SEQUENTIAL = 2 } hd_exec;
+
+/* Per-atom roles and types. */
+enum { HD_ROLE_MOBILE = 0, HD_ROLE_FIXED = 1, HD_ROLE_RIGID = 2 };
+enum { HD_TYPE_SUBSTRATE = 0, HD_TYPE_TIP = 1 };
+
+typedef struct hd_ctx hd_ctx;
+
+/* Geometry of one model.  dim is 2 or 3.  box[k] is the periodic length on
+ * axes with periodic[k] != 0 (it must be at least 2 (rc + skin)); open axes
+ * ignore box[k].  pos is SoA [dim][n_atoms]; type and role have n_atoms
+ * entries.  Atoms with role RIGID move together as one body of mass
+ * n_rigid * mass; atoms with role FIXED never move. */
+typedef struct {
+    int32_t dim;
+    int32_t n_atoms;
+    double box[3];
+    int32_t periodic[3];
+    const double *pos;
+    const uint8_t *type;
+    const uint8_t *role;
+    double mass;
+} hd_system_desc;
+
+/* Lennard-Jones table indexed [type_a][type_b] (eq. 9), energy-shifted at rc;
+ * skin is the Verlet-list margin (lists are rebuilt when an atom has moved
+ * more than skin/2 since the last build). */
+typedef struct { double eps[2][2], sig[2][2], rc, skin; } hd_lj_params;
+
+/* Langevin thermostat: time step, friction, temperature, 64-bit seed of the
+ * Philox stream (key = seed; counter = step, particle, tag). */
+typedef struct { double dt, gamma, kT; uint64_t seed; } hd_thermo_params;
+
+/* Slider drive: spring stiffness k, normal load F_N, slider position x_S and
+ * slider velocity (v_slider = 0: stepped sliding at fixed x_S; otherwise
+ * x_S(step) = x_slider + v_slider * step * dt). */
+typedef struct { double k_spring, f_normal, x_slider, v_slider; } hd_drive_params;
+
+/* Slope bias of eq. 14: dV_max, thresholds g_lo < g_hi, integer exponent
+ * m_b >= 1.  enabled = 0 turns the bias (and its force) off. */
+typedef struct { int32_t enabled, m_b; double dv_max, g_lo, g_hi; } hd_bias_params;
+
+/* Per-system scalars after the last evaluation. */
+typedef struct {
+    double e_pot;     /* LJ energy + drive energy */
+    double e_kin;     /* mobile atoms + rigid body */
+    double dv;        /* bias dV */
+    double dvp;       /* d dV / d g */
+    double g;         /* slope, eq. 5 */
+    double d;         /* distance from r_O, eq. 7 */
+    double t_md;      /* elapsed MD time */
+    double t_hyper;   /* boosted time sum dt exp(dV/kT) */
+    double x_slider;  /* slider position at the last evaluation */
+    double x_tip;     /* tip position X_R,x - X_R,x(0) */
+    double f_lat;     /* lateral force k (x_S - x_T), eq. 10 */
+    int64_t step;     /* steps taken */
+    int32_t flags;    /* HD_FLAG_* bits */
+    int32_t n_rebuilds;
+} hd_scalars;
+
+enum { HD_FLAG_UNSTABLE = 1, HD_FLAG_NBR_OVERFLOW = 2 };
+
+/* Which per-atom force hd_read_forces returns. */
+enum { HD_FORCE_TOTAL = 0, HD_FORCE_LJ = 1, HD_FORCE_BIAS = 2, HD_HU = 3 };
+
+/* Create a context on HIP device `device`.  hip_stream is a hipStream_t to
+ * order work on (for example torch.cuda.current_stream().cuda_stream) or NULL
+ * for a stream owned by the context. */
+hd_status hd_create(hd_precision prec, int device, void *hip_stream, hd_ctx **out);
+
+/* Choose the scheduler before hd_finalize (default HD_EXEC_BATCHED). */
+hd_status hd_set_exec(hd_ctx *ctx, hd_exec exec);
+
+/* Tuning knobs before hd_finalize: threads per workgroup of the batched kernel
+ * (64..1024, multiple of 64; 0 = automatic) and the neighbour-slot capacity
+ * per atom (0 = automatic). */
+hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors);
+
+/* Append one model.  Copies every array.  Returns its index in *sys_id.  The
+ * basin reference r_O defaults to the given positions; velocities start at 0;
+ * the bias starts disabled. */
+hd_status hd_add_system(hd_ctx *ctx, const hd_system_desc *desc, const hd_lj_params *lj,
+                        const hd_thermo_params *thermo, const hd_drive_params *drive,
+                        int32_t *sys_id);
+
+/* Basin minimum r_O (eq. 7), SoA [dim][n]. */
+hd_status hd_set_reference(hd_ctx *ctx, int32_t sys, const double *rO);
+hd_status hd_set_bias(hd_ctx *ctx, int32_t sys, const hd_bias_params *bias);
+/* Stepped slider position x_S (Sec. 2.3). */
+hd_status hd_set_slider(hd_ctx *ctx, int32_t sys, double x_slider);
+hd_status hd_set_thermo(hd_ctx *ctx, int32_t sys, const hd_thermo_params *thermo);
+/* Maxwell-Boltzmann velocities v = sqrt(kT/m) z from the seed (Philox tag 1,
+ * step 0; the rigid body draws with particle index n_atoms and its mass). */
+hd_status hd_init_velocities(hd_ctx *ctx, int32_t sys);
+/* Replace positions: mobile and fixed atoms are copied; the rigid body moves
+ * by the minimum-image displacement of its first atom and its atoms are
+ * re-placed at X_R + c_i. */
+hd_status hd_set_positions(hd_ctx *ctx, int32_t sys, const double *pos);
+/* Replace velocities: mobile atoms copied, fixed atoms zero, the rigid body
+ * takes the mean of its atoms' velocities. */
+hd_status hd_set_velocities(hd_ctx *ctx, int32_t sys, const double *vel);
+
+/* Lay out the batch in device memory, upload it and evaluate forces at the
+ * initial positions. */
+hd_status hd_finalize(hd_ctx *ctx);
+
+/* Advance every system by n_steps BAOAB steps (asynchronous on the context
+ * stream).  Returns HD_E_UNSTABLE only when every system is frozen. */
+hd_status hd_step(hd_ctx *ctx, int64_t n_steps);
+/* Evaluate forces, energy, H u and the bias at the current positions without
+ * stepping or advancing the clock; rebuilds every neighbour list. */
+hd_status hd_compute(hd_ctx *ctx);
+hd_status hd_sync(hd_ctx *ctx);
+
+/* Host read-outs (synchronising).  out holds dim*n_atoms doubles. */
+hd_status hd_read_forces(hd_ctx *ctx, int32_t sys, int32_t which, double *out);
+hd_status hd_read_positions(hd_ctx *ctx, int32_t sys, double *out);
+hd_status hd_read_velocities(hd_ctx *ctx, int32_t sys, double *out);
+hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out);
+/* Device-to-device copy of a system's positions / forces into a caller
+ * buffer of dim*n_atoms doubles (stream-ordered, not synchronising). */
+hd_status hd_copy_positions_device(hd_ctx *ctx, int32_t sys, double *dev_out);
+hd_status hd_copy_forces_device(hd_ctx *ctx, int32_t sys, int32_t which, double *dev_out);
+
+/* Checkpoint of one system: positions, velocities, reference, rigid body,
+ * step, clock and seed.  With buf == NULL, *bytes receives the size needed.
+ * Philox is counter based, so a restored run continues bit-identically. */
+hd_status hd_get_state(hd_ctx *ctx, int32_t sys, void *buf, size_t *bytes);
+hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes);
+
+/* Neighbour pairs (i < j, system-local indices) of the current list, i.e.
+ * pairs with r^2 < (rc + skin)^2 at the last build, without fixed-fixed and
+ * rigid-rigid pairs.  Writes up to cap pairs into ij[2*k], ij[2*k+1] and the
+ * total count into *n_pairs. */
+hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int64_t *n_pairs);
+
+/* Number of systems, and the atom count / dimension of one. */
+hd_status hd_system_info(hd_ctx *ctx, int32_t sys, int32_t *dim, int32_t *n_atoms);
+int32_t hd_num_systems(const hd_ctx *ctx);
+
+/* Per-kernel timing of the last hd_step, measured with HIP events on the
+ * context stream: total milliseconds and launches. */
+hd_status hd_last_step_timing(hd_ctx *ctx, double *ms, int64_t *launches);
+
+const char *hd_last_error(const hd_ctx *ctx);
+void hd_destroy(hd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HD_H */

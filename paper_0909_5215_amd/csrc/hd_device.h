@@ -1,0 +1,361 @@
+// Device-side layout and arithmetic shared by the batched (one workgroup per
+// system) kernel and the grid kernels.  gfx950 only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hdk {
+
+enum : int { ROLE_MOBILE = 0, ROLE_FIXED = 1, ROLE_RIGID = 2 };
+enum : int { FLAG_UNSTABLE = 1, FLAG_NBR_OVERFLOW = 2 };
+enum : int { NRED = 12 };  // E, d2, G, sumF_R[3], sumHu_R[3], sumU_R[3]
+
+// Read-only description of one system (uploaded at finalize / parameter
+// changes).  Per-atom arrays of the batch are concatenated; component k of
+// batch atom a lives at k*ntot + a.
+struct SysDesc {
+  int32_t dim, n;
+  int64_t off;                 // first batch atom of this system
+  int32_t n_rigid, first_rigid;
+  int32_t periodic[3];
+  double box[3], hbox[3];
+  double mass, inv_mass, massR, inv_massR;
+  double eps[4], sig2[4], shift[4];      // [ta*2+tb]
+  float eps_f[4], sig2_f[4], shift_f[4];
+  double rc2, rl2, skin_half2;
+  double dt, hdt, c1, c2, c2R, kT;
+  uint64_t seed;
+  double k_spring, f_normal, x_slider, v_slider;
+  int32_t bias_on, m_b;
+  double dv_max, g_lo, g_hi;
+  // cell grid, fixed for the life of the context
+  int32_t nc[3], ncell;
+  double lo[3], inv_h[3];
+  int64_t cell_off, cstart_off;
+  // neighbour list: entry (j << 1 | type_j) of slot k of atom i at
+  // nbr[nbr_off + k*n + i]
+  int64_t nbr_off;
+  int32_t maxnb, pad0;
+  double XR0[3];
+};
+
+// Mutable per-system state.
+struct SysState {
+  double XR[3], VR[3], FR[3];  // rigid body: centre of mass, velocity, force
+  double t_md, t_hyper;
+  int64_t step;
+  double e_lj, v_drive, e_pot, e_kin, d, g, dv, dvp, x_slider, x_tip, f_lat;
+  int32_t flags, n_rebuilds;
+  int32_t rebuild, pad1;
+};
+
+struct Arrays {
+  int64_t ntot;
+  double *x, *v, *rO, *xb, *cofs, *ftot;  // [3][ntot]
+  double *flj, *hu, *fb;                  // [3][ntot]
+  double *eatom;                          // [ntot]
+  void *u;                                // [3][ntot] float or double
+  uint8_t *tr;                            // type | role << 1
+  int32_t *nbr, *nnb;
+  int32_t *cell_count, *cell_start, *cell_atoms, *cidx;
+  int32_t *sys_of;                        // [ntot] system of each batch atom
+  double *partials;                       // grid kernels: per-tile sums
+  int32_t *tile_done;                     // grid kernels: per-system counters
+  double *XR_next;                        // grid kernels: [S][6] rigid body after drift
+  int32_t *rebuild_flag;                  // grid kernels: [S]
+};
+
+// ---------------------------------------------------------------------------
+// Small helpers
+__device__ __forceinline__ double minimg(double dx, double L, double hL, int periodic) {
+  if (periodic) {
+    if (dx > hL) dx -= L;
+    else if (dx < -hL) dx += L;
+  }
+  return dx;
+}
+
+__device__ __forceinline__ double wrapx(double x, double L, int periodic) {
+  if (periodic) {
+    if (x >= L) x -= L;
+    else if (x < 0.0) x += L;
+  }
+  return x;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+// Standard normals for (step, particle, tag): uniforms (w + 1/2) 2^-32 and
+// Box-Muller on (u0,u1) -> z0,z1 and (u2,u3) -> z2,z3.
+__device__ __forceinline__ void normals4(uint64_t seed, int64_t step, uint32_t particle,
+                                         uint32_t tag, double z[4]) {
+  uint32_t c[4] = {(uint32_t)((uint64_t)step & 0xffffffffu), (uint32_t)((uint64_t)step >> 32),
+                   particle, tag};
+  philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  const double s = 2.3283064365386963e-10;
+  const double u0 = ((double)c[0] + 0.5) * s, u1 = ((double)c[1] + 0.5) * s;
+  const double u2 = ((double)c[2] + 0.5) * s, u3 = ((double)c[3] + 0.5) * s;
+  const double two_pi = 6.283185307179586;
+  const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+  z[0] = r0 * cos(two_pi * u1);
+  z[1] = r0 * sin(two_pi * u1);
+  z[2] = r1 * cos(two_pi * u3);
+  z[3] = r1 * sin(two_pi * u3);
+}
+
+// Slope bias of eq. 14 and its derivative in g.
+__device__ __forceinline__ void bias_switch(const SysDesc &D, double g, double &dv, double &dvp) {
+  if (g >= D.g_hi) { dv = D.dv_max; dvp = 0.0; return; }
+  if (g <= D.g_lo) { dv = 0.0; dvp = 0.0; return; }
+  const double xi = (g - D.g_hi) / (D.g_lo - D.g_hi);
+  double xm1 = 1.0;
+  for (int q = 0; q < D.m_b - 1; ++q) xm1 *= xi;
+  const double xm = xm1 * xi;
+  const double one = 1.0 - xm;
+  dv = D.dv_max * one * one;
+  dvp = -2.0 * D.m_b * D.dv_max * one * xm1 / (D.g_lo - D.g_hi);
+}
+
+// Per-system scalars derived from the reduced sums (LJ part) and the rigid
+// body: drive energy and force, slope, bias.
+struct Scal {
+  double e_lj, v_drive, e_pot, d, g, dv, dvp, xs, x_tip, f_lat;
+  double Fd[3];      // drive force on the rigid body
+  double hud[3];     // drive Hessian term per rigid atom (k/nR^2) sum_R u
+  double sumFb[3];   // bias force summed over rigid atoms
+};
+
+__device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums[NRED],
+                                             const double XR[3], int64_t step, Scal &S) {
+  const int dim = D.dim;
+  S.xs = D.x_slider + D.v_slider * ((double)step * D.dt);
+  S.e_lj = sums[0];
+  S.v_drive = 0.0; S.x_tip = 0.0; S.f_lat = 0.0;
+  double G = sums[2];
+  for (int k = 0; k < 3; ++k) { S.Fd[k] = 0.0; S.hud[k] = 0.0; S.sumFb[k] = 0.0; }
+  if (D.n_rigid > 0) {
+    const int perp = dim - 1;
+    const double nR = (double)D.n_rigid;
+    S.x_tip = XR[0] - D.XR0[0];
+    const double ext = S.xs - S.x_tip;
+    S.f_lat = D.k_spring * ext;
+    S.v_drive = 0.5 * D.k_spring * ext * ext;
+    S.Fd[0] = D.k_spring * ext;
+    if (dim == 3) {
+      const double dy = XR[1] - D.XR0[1];
+      S.v_drive += 0.5 * D.k_spring * dy * dy;
+      S.Fd[1] = -D.k_spring * dy;
+    }
+    S.v_drive += D.f_normal * (XR[perp] - D.XR0[perp]);
+    S.Fd[perp] += -D.f_normal;
+    const int nspring = dim == 3 ? 2 : 1;
+    for (int k = 0; k < nspring; ++k) S.hud[k] = D.k_spring / (nR * nR) * sums[9 + k];
+    // drive share of each rigid atom enters F.u
+    for (int k = 0; k < dim; ++k) G += (S.Fd[k] / nR) * sums[9 + k];
+  }
+  S.e_pot = S.e_lj + S.v_drive;
+  S.d = sqrt(sums[1]);
+  S.g = (S.d < 1e-12) ? 0.0 : -G / S.d;
+  S.dv = 0.0; S.dvp = 0.0;
+  if (D.bias_on) bias_switch(D, S.g, S.dv, S.dvp);
+  if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0 && D.n_rigid > 0) {
+    const double nR = (double)D.n_rigid;
+    for (int k = 0; k < dim; ++k) {
+      const double sumHu = sums[6 + k] + nR * S.hud[k];
+      const double sumF = sums[3 + k] + S.Fd[k];
+      S.sumFb[k] = -S.dvp * ((sumHu - sumF - S.g * sums[9 + k] / S.d) / S.d);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pair pass for one atom over its full neighbour list.
+//
+// FP64: everything in double.  FP32C: the displacement and the cutoff test
+// are float64 (so the interacting set is decided exactly as in float64); the
+// pair arithmetic is float32 and the per-atom sums are compensated (Kahan-
+// Babuska/Neumaier two-term sums), converted to float64 at the end.
+
+struct Comp {  // Neumaier compensated float sum
+  float s, c;
+  __device__ __forceinline__ void init() { s = 0.f; c = 0.f; }
+  __device__ __forceinline__ void add(float x) {
+    const float t = s + x;
+    c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+  }
+  __device__ __forceinline__ double get() const { return (double)s + (double)c; }
+};
+
+template <typename T> struct PairAcc;
+
+template <> struct PairAcc<double> {
+  double F[3], H[3], e;
+  __device__ __forceinline__ void init() {
+    for (int k = 0; k < 3; ++k) { F[k] = 0.0; H[k] = 0.0; }
+    e = 0.0;
+  }
+};
+
+template <> struct PairAcc<float> {
+  Comp F[3], H[3], e;
+  __device__ __forceinline__ void init() {
+    for (int k = 0; k < 3; ++k) { F[k].init(); H[k].init(); }
+    e.init();
+  }
+};
+
+__device__ __forceinline__ float rcp_nr(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int i,
+                                          const double xi[3], const T ui[3], int ti,
+                                          PairAcc<T> &acc) {
+  const int64_t off = D.off, N = A.ntot;
+  const int n = D.n;
+  const T *__restrict__ u = (const T *)A.u;
+  const int32_t *__restrict__ nbr = A.nbr + D.nbr_off;
+  const int nn = A.nnb[off + i];
+  for (int q = 0; q < nn; ++q) {
+    const int ent = nbr[(int64_t)q * n + i];
+    const int j = ent >> 1, tj = ent & 1;
+    const int64_t aj = off + j;
+    // displacement x_i - x_j and r^2 = (dx*dx + dy*dy) + dz*dz, rounded
+    // operation by operation so the cutoff decision is the float64 one
+    double dx[3];
+    double r2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      dx[k] = minimg(xi[k] - A.x[k * N + aj], D.box[k], D.hbox[k], D.periodic[k]);
+      r2 = __dadd_rn(r2, __dmul_rn(dx[k], dx[k]));
+    }
+    if (!(r2 < D.rc2)) continue;
+    const int tt = ti * 2 + tj;
+    if constexpr (sizeof(T) == 8) {
+      const double eps = D.eps[tt];
+      const double r2i = 1.0 / r2;
+      const double sr2 = D.sig2[tt] * r2i;
+      const double sr6 = sr2 * sr2 * sr2;
+      const double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
+      const double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
+      const double e = 4.0 * eps * (sr6 * sr6 - sr6) - D.shift[tt];
+      double w[3], Dw = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        w[k] = ui[k] - u[k * N + aj];
+        Dw += dx[k] * w[k];
+      }
+      const double CDw = C * Dw;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        acc.F[k] += f * dx[k];
+        acc.H[k] += CDw * dx[k] - f * w[k];
+      }
+      acc.e += 0.5 * e;
+    } else {
+      const float eps = D.eps_f[tt];
+      const float r2f = (float)r2;
+      const float r2i = rcp_nr(r2f);
+      const float sr2 = D.sig2_f[tt] * r2i;
+      const float sr6 = sr2 * sr2 * sr2;
+      const float epsr = eps * r2i * sr6;
+      const float f = epsr * (48.0f * sr6 - 24.0f);
+      const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
+      const float e = 4.0f * eps * sr6 * (sr6 - 1.0f) - D.shift_f[tt];
+      float d[3], w[3], Dw = 0.0f;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        d[k] = (float)dx[k];
+        w[k] = ui[k] - u[k * N + aj];
+        Dw = __builtin_fmaf(d[k], w[k], Dw);
+      }
+      const float CDw = C * Dw;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        acc.F[k].add(f * d[k]);
+        acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
+      }
+      acc.e.add(0.5f * e);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup reductions (wavefront 64).  Deterministic: fixed shuffle tree and
+// fixed order over waves.  lds must hold NV * 16 doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    v[k] = x;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[k * 16 + wave] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += lds[k * 16 + w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int block_or(int v, int *lds_int) {
+  if (threadIdx.x == 0) *lds_int = 0;
+  __syncthreads();
+  if (v) atomicOr(lds_int, 1);
+  __syncthreads();
+  const int r = *lds_int;
+  __syncthreads();
+  return r;
+}
+
+// Exclusive prefix sum of one int per thread across the workgroup; returns
+// the exclusive prefix and writes the total.  lds_int holds >= 17 ints.
+__device__ __forceinline__ int block_exscan(int v, int *lds_int, int &total) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds_int[wave] = x;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int w = 0; w < nw; ++w) { const int t = lds_int[w]; lds_int[w] = run; run += t; }
+    lds_int[16] = run;
+  }
+  __syncthreads();
+  const int r = lds_int[wave] + x - v;
+  total = lds_int[16];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace hdk

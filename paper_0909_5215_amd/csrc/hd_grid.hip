@@ -1,0 +1,477 @@
+// Grid scheduler: a step is a short sequence of kernels over tiles of atoms,
+// each tile a contiguous atom range of one system.  Used for the plain
+// single-system path (one system per graph) and for systems too large for one
+// workgroup.  Kernel boundaries are the per-system barriers; per-system sums
+// are reduced by the last tile of each system to finish (release/acquire
+// fences around a per-system counter), in a fixed tile order.
+#include "hd_device.h"
+#include "hd_launch.h"
+
+namespace hdk {
+
+// Scalars of the last evaluation, consumed by the kick kernel.
+struct GridScal {
+  Scal S;
+  double XRn[3], VRn[3];
+};
+
+// Tile of this workgroup.  Workgroups are dealt round-robin to the 8 XCDs;
+// consecutive tiles (spatial neighbours) are given to the same XCD so that
+// their halo data shares one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nt) {
+  const int q = nt >> 3, r = nt & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+template <int DIM>
+__device__ void rigid_advance(const SysDesc &D, const SysState &st, int64_t step, double XRn[3],
+                              double VRn[3]) {
+  double z[4];
+  normals4(D.seed, step, (uint32_t)D.n, 0u, z);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    double v = st.VR[k], x = st.XR[k];
+    v = v + D.hdt * st.FR[k] * D.inv_massR;
+    x = x + D.hdt * v;
+    v = D.c1 * v + D.c2R * z[k];
+    x = x + D.hdt * v;
+    XRn[k] = x;
+    VRn[k] = v;
+  }
+}
+
+// B A O A for every atom of the tile; rigid atoms follow the rigid body, which
+// each of their threads advances identically.  Also refreshes u and raises
+// the system's rebuild flag when an atom has left its skin.
+template <int DIM, typename T>
+__device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A, const Tile &t,
+                           bool compute_only) {
+  const int i = t.first + threadIdx.x;
+  if (threadIdx.x >= t.count) return;
+  const int64_t N = A.ntot, a = D.off + i;
+  const int role = A.tr[a] >> 1;
+  if (role == ROLE_FIXED) return;
+  const int64_t step = st.step;
+  double xn[3] = {0, 0, 0};
+  if (role == ROLE_MOBILE) {
+    if (!compute_only) {
+      double z[4];
+      normals4(D.seed, step, (uint32_t)i, 0u, z);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        double v = A.v[k * N + a], x = A.x[k * N + a];
+        v = v + D.hdt * A.ftot[k * N + a] * D.inv_mass;
+        x = x + D.hdt * v;
+        v = D.c1 * v + D.c2 * z[k];
+        x = x + D.hdt * v;
+        x = wrapx(x, D.box[k], D.periodic[k]);
+        A.x[k * N + a] = x;
+        A.v[k * N + a] = v;
+        xn[k] = x;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) xn[k] = A.x[k * N + a];
+    }
+  } else {
+    double XRn[3], VRn[3];
+    if (!compute_only) {
+      rigid_advance<DIM>(D, st, step, XRn, VRn);
+    } else {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { XRn[k] = st.XR[k]; VRn[k] = st.VR[k]; }
+    }
+    const int s = A.sys_of[a];
+    if (i == D.first_rigid) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { A.XR_next[s * 6 + k] = XRn[k]; A.XR_next[s * 6 + 3 + k] = VRn[k]; }
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      xn[k] = wrapx(XRn[k] + A.cofs[k * N + a], D.box[k], D.periodic[k]);
+      A.x[k * N + a] = xn[k];
+    }
+  }
+  double d2 = 0.0;
+  T *u = (T *)A.u;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    u[k * N + a] = (T)minimg(xn[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+    const double dd = minimg(xn[k] - A.xb[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+    d2 += dd * dd;
+  }
+  if (d2 > D.skin_half2) atomicOr(&A.rebuild_flag[A.sys_of[a]], 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void kg_drift(const SysDesc *__restrict__ descs,
+                                                 const SysState *__restrict__ states, Arrays A,
+                                                 const Tile *__restrict__ tiles, int ntiles,
+                                                 int compute_only) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  const SysDesc &D = descs[t.sys];
+  if (D.dim == 2) drift_tile<2, T>(D, states[t.sys], A, t, compute_only != 0);
+  else drift_tile<3, T>(D, states[t.sys], A, t, compute_only != 0);
+}
+
+// ---- neighbour-list rebuild, only for systems whose flag is raised --------
+__global__ void kg_set_flags(int32_t *flags, const int32_t *sys_ids, int nsys, int value) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nsys) flags[sys_ids[k]] = value;
+}
+
+template <int DIM>
+__device__ int cell_of_g(const SysDesc &D, const double *x, int64_t N, int64_t a) {
+  int c3[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    int ck = (int)floor((x[k * N + a] - D.lo[k]) * D.inv_h[k]);
+    ck = ck < 0 ? 0 : (ck >= D.nc[k] ? D.nc[k] - 1 : ck);
+    c3[k] = ck;
+  }
+  return (c3[2] * D.nc[1] + c3[1]) * D.nc[0] + c3[0];
+}
+
+__global__ __launch_bounds__(1024) void kg_cell_count(const SysDesc *__restrict__ descs, Arrays A,
+                                                      const Tile *__restrict__ tiles, int ntiles) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  if (!A.rebuild_flag[t.sys] || threadIdx.x >= t.count) return;
+  const SysDesc &D = descs[t.sys];
+  const int64_t a = D.off + t.first + threadIdx.x;
+  const int c = D.dim == 2 ? cell_of_g<2>(D, A.x, A.ntot, a) : cell_of_g<3>(D, A.x, A.ntot, a);
+  A.cidx[a] = c;
+  atomicAdd(&A.cell_count[D.cell_off + c], 1);
+}
+
+__global__ __launch_bounds__(1024) void kg_cell_scan(const SysDesc *__restrict__ descs, Arrays A,
+                                                     const int32_t *__restrict__ sys_ids) {
+  const int s = sys_ids[blockIdx.x];
+  if (!A.rebuild_flag[s]) return;
+  __shared__ int lds_int[32];
+  const SysDesc &D = descs[s];
+  const int tid = threadIdx.x, B = blockDim.x, ncell = D.ncell;
+  int32_t *cnt = A.cell_count + D.cell_off;
+  int32_t *cst = A.cell_start + D.cstart_off;
+  const int chunk = (ncell + B - 1) / B;
+  const int c0 = tid * chunk, c1 = min(ncell, c0 + chunk);
+  int local = 0;
+  for (int c = c0; c < c1; ++c) local += __hip_atomic_load(&cnt[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int total = 0;
+  int run = block_exscan(local, lds_int, total);
+  for (int c = c0; c < c1; ++c) {
+    const int k = __hip_atomic_load(&cnt[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cst[c] = run;
+    run += k;
+    __hip_atomic_store(&cnt[c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (tid == 0) cst[ncell] = total;
+}
+
+__global__ __launch_bounds__(1024) void kg_cell_scatter(const SysDesc *__restrict__ descs, Arrays A,
+                                                        const Tile *__restrict__ tiles, int ntiles) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  if (!A.rebuild_flag[t.sys] || threadIdx.x >= t.count) return;
+  const SysDesc &D = descs[t.sys];
+  const int i = t.first + threadIdx.x;
+  const int64_t a = D.off + i;
+  const int c = A.cidx[a];
+  const int slot = atomicAdd(&A.cell_count[D.cell_off + c], 1);
+  A.cell_atoms[D.off + A.cell_start[D.cstart_off + c] + slot] = i;
+}
+
+// One thread per cell: sort the cell's atoms by index, then clear its count.
+__global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ descs, Arrays A,
+                                                    const int32_t *__restrict__ sys_ids, int nsys) {
+  const int s = sys_ids[blockIdx.y];
+  if (!A.rebuild_flag[s]) return;
+  const SysDesc &D = descs[s];
+  int32_t *cat = A.cell_atoms + D.off;
+  const int32_t *cst = A.cell_start + D.cstart_off;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < D.ncell; c += gridDim.x * blockDim.x) {
+    const int b = cst[c], e = cst[c + 1];
+    for (int p = b + 1; p < e; ++p) {
+      const int key = cat[p];
+      int q = p - 1;
+      while (q >= b && cat[q] > key) { cat[q + 1] = cat[q]; --q; }
+      cat[q + 1] = key;
+    }
+    __hip_atomic_store(&A.cell_count[D.cell_off + c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int DIM>
+__device__ int list_atom_g(const SysDesc &D, const Arrays &A, int i) {
+  const int64_t N = A.ntot, off = D.off, ai = off + i;
+  const int n = D.n;
+  double xi[3];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xi[k] = A.x[k * N + ai];
+  const int ri = A.tr[ai] >> 1;
+  int cc[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    int ck = (int)floor((xi[k] - D.lo[k]) * D.inv_h[k]);
+    cc[k] = ck < 0 ? 0 : (ck >= D.nc[k] ? D.nc[k] - 1 : ck);
+  }
+  int lo3[3] = {0, 0, 0}, hi3[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < DIM; ++k)
+    if (D.nc[k] > 1) { lo3[k] = -1; hi3[k] = 1; }
+  const int32_t *cstart = A.cell_start + D.cstart_off;
+  const int32_t *catoms = A.cell_atoms + off;
+  int32_t *list = A.nbr + D.nbr_off;
+  int cnt = 0;
+  for (int oz = lo3[2]; oz <= hi3[2]; ++oz)
+    for (int oy = lo3[1]; oy <= hi3[1]; ++oy)
+      for (int ox = lo3[0]; ox <= hi3[0]; ++ox) {
+        int q3[3] = {cc[0] + ox, cc[1] + oy, cc[2] + oz};
+        bool skip = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (q3[k] < 0 || q3[k] >= D.nc[k]) {
+            if (k < DIM && D.periodic[k]) q3[k] = (q3[k] + D.nc[k]) % D.nc[k];
+            else skip = true;
+          }
+        }
+        if (skip) continue;
+        const int q = (q3[2] * D.nc[1] + q3[1]) * D.nc[0] + q3[0];
+        for (int p = cstart[q]; p < cstart[q + 1]; ++p) {
+          const int j = catoms[p];
+          if (j == i) continue;
+          const int64_t aj = off + j;
+          const int trj = A.tr[aj], rj = trj >> 1;
+          if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
+          double r2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            const double d = minimg(A.x[k * N + aj] - xi[k], D.box[k], D.hbox[k], D.periodic[k]);
+            r2 = __dadd_rn(r2, __dmul_rn(d, d));
+          }
+          if (r2 < D.rl2) {
+            if (cnt < D.maxnb) list[(int64_t)cnt * n + i] = (j << 1) | (trj & 1);
+            ++cnt;
+          }
+        }
+      }
+  return cnt;
+}
+
+__global__ __launch_bounds__(1024) void kg_build_list(const SysDesc *__restrict__ descs,
+                                                      SysState *__restrict__ states, Arrays A,
+                                                      const Tile *__restrict__ tiles, int ntiles) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  if (!A.rebuild_flag[t.sys] || threadIdx.x >= t.count) return;
+  const SysDesc &D = descs[t.sys];
+  const int i = t.first + threadIdx.x;
+  const int64_t a = D.off + i, N = A.ntot;
+  const int c = D.dim == 2 ? list_atom_g<2>(D, A, i) : list_atom_g<3>(D, A, i);
+  A.nnb[a] = c < D.maxnb ? c : D.maxnb;
+  if (c > D.maxnb) atomicOr(&states[t.sys].flags, FLAG_NBR_OVERFLOW);
+  for (int k = 0; k < D.dim; ++k) A.xb[k * N + a] = A.x[k * N + a];
+  if (i == 0) atomicAdd(&states[t.sys].n_rebuilds, 1);
+}
+
+// ---- pair pass with per-tile sums and last-tile reduction ------------------
+template <int DIM, typename T>
+__device__ void pairs_tile(const SysDesc &D, SysState &st, const Arrays &A, const Tile &t,
+                           GridScal *gs, int tile_index, bool compute_only) {
+  __shared__ double red[NRED * 16];
+  __shared__ int last;
+  const int64_t N = A.ntot;
+  double sums[NRED];
+#pragma unroll
+  for (int q = 0; q < NRED; ++q) sums[q] = 0.0;
+  if (threadIdx.x < t.count) {
+    const int i = t.first + threadIdx.x;
+    const int64_t a = D.off + i;
+    const int tr = A.tr[a], role = tr >> 1;
+    double xi[3] = {0, 0, 0}, u64[3] = {0, 0, 0};
+    T ui[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      xi[k] = A.x[k * N + a];
+      if (role != ROLE_FIXED) u64[k] = minimg(xi[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+      ui[k] = (T)u64[k];
+    }
+    PairAcc<T> acc;
+    acc.init();
+    pair_atom<DIM, T>(D, A, i, xi, ui, tr & 1, acc);
+    double F[3], H[3], e;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      if constexpr (sizeof(T) == 8) { F[k] = acc.F[k]; H[k] = acc.H[k]; }
+      else { F[k] = acc.F[k].get(); H[k] = acc.H[k].get(); }
+      A.flj[k * N + a] = F[k];
+      A.hu[k * N + a] = H[k];
+    }
+    if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
+    A.eatom[a] = e;
+    sums[0] = e;
+    if (role != ROLE_FIXED) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { sums[1] += u64[k] * u64[k]; sums[2] += F[k] * u64[k]; }
+    }
+    if (role == ROLE_RIGID) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { sums[3 + k] = F[k]; sums[6 + k] = H[k]; sums[9 + k] = u64[k]; }
+    }
+  }
+  block_sum<NRED>(sums, red);
+  const int s = t.sys;
+  double *part = A.partials + (int64_t)tile_index * NRED;
+  if (threadIdx.x < NRED) part[threadIdx.x] = sums[threadIdx.x];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int prev = atomicAdd(&A.tile_done[s], 1);
+    last = (prev == t.tiles_in_sys - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // last tile of the system: fixed-order reduction over its tiles
+  const int first_tile = tile_index - t.tile_in_sys;
+  double tot[NRED];
+#pragma unroll
+  for (int q = 0; q < NRED; ++q) tot[q] = 0.0;
+  for (int k = threadIdx.x; k < t.tiles_in_sys; k += blockDim.x) {
+    const double *p = A.partials + (int64_t)(first_tile + k) * NRED;
+#pragma unroll
+    for (int q = 0; q < NRED; ++q) tot[q] += __hip_atomic_load(&p[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum<NRED>(tot, red);
+  if (threadIdx.x == 0) {
+    double XRn[3] = {st.XR[0], st.XR[1], st.XR[2]};
+    double VRn[3] = {st.VR[0], st.VR[1], st.VR[2]};
+    if (!compute_only && D.n_rigid > 0) {
+      for (int k = 0; k < DIM; ++k) { XRn[k] = A.XR_next[s * 6 + k]; VRn[k] = A.XR_next[s * 6 + 3 + k]; }
+    }
+    const int64_t estep = compute_only ? st.step : st.step + 1;
+    Scal S;
+    eval_scalars(D, tot, XRn, estep, S);
+    double FR[3] = {0, 0, 0};
+    for (int k = 0; k < DIM; ++k) FR[k] = tot[3 + k] + S.Fd[k] + S.sumFb[k];
+    if (!compute_only) {
+      for (int k = 0; k < DIM; ++k) { st.XR[k] = XRn[k]; st.VR[k] = VRn[k] + D.hdt * FR[k] * D.inv_massR; }
+      st.t_md += D.dt;
+      st.t_hyper += D.dt * exp(S.dv / D.kT);
+      st.step = st.step + 1;
+    }
+    for (int k = 0; k < DIM; ++k) st.FR[k] = FR[k];
+    st.e_lj = S.e_lj; st.v_drive = S.v_drive; st.e_pot = S.e_pot;
+    st.d = S.d; st.g = S.g; st.dv = S.dv; st.dvp = S.dvp;
+    st.x_slider = S.xs; st.x_tip = S.x_tip; st.f_lat = S.f_lat;
+    if (!isfinite(S.e_pot)) st.flags |= FLAG_UNSTABLE;
+    gs[s].S = S;
+    for (int k = 0; k < 3; ++k) { gs[s].VRn[k] = st.VR[k]; gs[s].XRn[k] = st.XR[k]; }
+    A.tile_done[s] = 0;
+    A.rebuild_flag[s] = 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ descs,
+                                                 SysState *__restrict__ states, Arrays A,
+                                                 const Tile *__restrict__ tiles, int ntiles,
+                                                 GridScal *gs, int compute_only) {
+  const int ti = xcd_tile(blockIdx.x, ntiles);
+  const Tile t = tiles[ti];
+  const SysDesc &D = descs[t.sys];
+  if (D.dim == 2) pairs_tile<2, T>(D, states[t.sys], A, t, gs, ti, compute_only != 0);
+  else pairs_tile<3, T>(D, states[t.sys], A, t, gs, ti, compute_only != 0);
+}
+
+// ---- bias force, total force and final B -----------------------------------
+__global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ descs, Arrays A,
+                                                const Tile *__restrict__ tiles, int ntiles,
+                                                const GridScal *__restrict__ gs, int compute_only) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  if (threadIdx.x >= t.count) return;
+  const SysDesc &D = descs[t.sys];
+  const Scal &S = gs[t.sys].S;
+  const int64_t N = A.ntot, a = D.off + t.first + threadIdx.x;
+  const int role = A.tr[a] >> 1;
+  for (int k = 0; k < D.dim; ++k) {
+    double f = A.flj[k * N + a], h = A.hu[k * N + a], fb = 0.0;
+    if (role != ROLE_FIXED) {
+      if (role == ROLE_RIGID) { f += S.Fd[k] / (double)D.n_rigid; h += S.hud[k]; }
+      if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0) {
+        const double uk = minimg(A.x[k * N + a] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+        fb = -S.dvp * ((h - f - S.g * uk / S.d) / S.d);
+      }
+    }
+    const double ft = f + fb;
+    A.flj[k * N + a] = f;
+    A.hu[k * N + a] = h;
+    A.fb[k * N + a] = fb;
+    A.ftot[k * N + a] = ft;
+    if (!compute_only) {
+      if (role == ROLE_MOBILE) A.v[k * N + a] = A.v[k * N + a] + D.hdt * ft * D.inv_mass;
+      else if (role == ROLE_RIGID) A.v[k * N + a] = gs[t.sys].VRn[k];
+    }
+  }
+}
+
+// Kinetic energy per system (mobile atoms + rigid body), one workgroup each.
+__global__ __launch_bounds__(256) void kg_ekin(const SysDesc *__restrict__ descs,
+                                               SysState *__restrict__ states, Arrays A,
+                                               const int32_t *__restrict__ sys_ids) {
+  __shared__ double red[16];
+  const int s = sys_ids[blockIdx.x];
+  const SysDesc &D = descs[s];
+  double ek[1] = {0.0};
+  for (int i = threadIdx.x; i < D.n; i += blockDim.x) {
+    const int64_t a = D.off + i;
+    if ((A.tr[a] >> 1) != ROLE_MOBILE) continue;
+    for (int k = 0; k < D.dim; ++k) { const double v = A.v[k * A.ntot + a]; ek[0] += 0.5 * D.mass * v * v; }
+  }
+  block_sum<1>(ek, red);
+  if (threadIdx.x == 0) {
+    double ekr = 0.0;
+    if (D.n_rigid > 0)
+      for (int k = 0; k < D.dim; ++k) ekr += 0.5 * D.massR * states[s].VR[k] * states[s].VR[k];
+    states[s].e_kin = ek[0] + ekr;
+  }
+}
+
+// ---------------------------------------------------------------------------
+size_t grid_scal_bytes() { return sizeof(GridScal); }
+
+hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
+                     const GridPlan &P, bool compute_only, hipStream_t stream, int *launches) {
+  const int nt = P.ntiles, B = P.block, co = compute_only ? 1 : 0;
+  GridScal *gs = (GridScal *)P.gscal;
+  int nl = 0;
+  if (compute_only) {
+    hipLaunchKernelGGL(kg_set_flags, dim3((P.nsys + 255) / 256), dim3(256), 0, stream,
+                       A.rebuild_flag, P.sys_ids, P.nsys, 1);
+    ++nl;
+  }
+  if (prec == 0)
+    hipLaunchKernelGGL(kg_drift<double>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, co);
+  else
+    hipLaunchKernelGGL(kg_drift<float>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, co);
+  hipLaunchKernelGGL(kg_cell_count, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
+  hipLaunchKernelGGL(kg_cell_scan, dim3(P.nsys), dim3(256), 0, stream, descs, A, P.sys_ids);
+  hipLaunchKernelGGL(kg_cell_scatter, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
+  const int sort_blocks = (P.max_ncell + 255) / 256 < 1024 ? (P.max_ncell + 255) / 256 : 1024;
+  hipLaunchKernelGGL(kg_cell_sort, dim3(sort_blocks > 0 ? sort_blocks : 1, P.nsys), dim3(256), 0, stream,
+                     descs, A, P.sys_ids, P.nsys);
+  hipLaunchKernelGGL(kg_build_list, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt);
+  if (prec == 0)
+    hipLaunchKernelGGL(kg_pairs<double>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, gs, co);
+  else
+    hipLaunchKernelGGL(kg_pairs<float>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, gs, co);
+  hipLaunchKernelGGL(kg_kick, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, co);
+  nl += 8;
+  if (launches) *launches += nl;
+  return hipGetLastError();
+}
+
+hipError_t grid_ekin(const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
+                     hipStream_t stream) {
+  hipLaunchKernelGGL(kg_ekin, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids);
+  return hipGetLastError();
+}
+
+}  // namespace hdk

@@ -1,0 +1,42 @@
+// Host-side launchers of the kernels in hd_kernels.hip / hd_grid.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hd_device.h"
+
+namespace hdk {
+
+// One workgroup of `block` threads per listed system; nsteps BAOAB steps
+// (mode bit 0: evaluate only).  prec 0 = float64, 1 = float32 compensated.
+hipError_t launch_batched(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
+                          const int32_t *sys_list, int nsys, int block, int64_t nsteps, int mode,
+                          hipStream_t stream);
+
+// Tiles of the grid scheduler: each tile is a contiguous atom range of one
+// system (tiles never straddle systems).
+struct Tile {
+  int32_t sys, first, count, tile_in_sys, tiles_in_sys, pad;
+};
+
+struct GridPlan {
+  const Tile *tiles;       // device
+  int ntiles;
+  int block;               // threads per tile (== max atoms per tile)
+  const int32_t *sys_ids;  // device, systems covered
+  int nsys;
+  int max_ncell;           // largest cell count among the covered systems
+  void *gscal;             // device, per-system scalars of the last evaluation
+};
+
+size_t grid_scal_bytes();
+
+// One full step (or an evaluation when compute_only) of the grid scheduler.
+// Enqueues several kernels on `stream`; safe to capture in a HIP graph (no
+// memset or host synchronisation inside).
+hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
+                     const GridPlan &P, bool compute_only, hipStream_t stream, int *launches);
+// Kinetic energy of the covered systems.
+hipError_t grid_ekin(const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
+                     hipStream_t stream);
+
+}  // namespace hdk

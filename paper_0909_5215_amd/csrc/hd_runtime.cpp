@@ -1,0 +1,994 @@
+// Host runtime of libhd.so: contexts, batch layout in device memory, the two
+// schedulers (batched persistent launch; grid kernels captured in HIP graphs),
+// checkpoints and read-outs.  Every function exported here is declared in
+// include/hd.h.  Host arithmetic is limited to laying out inputs (cell grids,
+// rigid-body offsets); every step of the method runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hd.h"
+#include "hd_device.h"
+#include "hd_launch.h"
+
+using hdk::SysDesc;
+using hdk::SysState;
+
+namespace {
+
+constexpr int64_t kChunkSteps = 2000;   // steps per batched launch
+constexpr int kGraphSteps = 50;         // steps per captured grid graph
+
+struct SysHost {
+  int dim = 0, n = 0;
+  double box[3] = {0, 0, 0};
+  int periodic[3] = {0, 0, 0};
+  double mass = 1.0;
+  std::vector<double> pos, rO, cofs;
+  std::vector<uint8_t> type, role;
+  hd_lj_params lj{};
+  hd_thermo_params th{};
+  hd_drive_params dr{};
+  hd_bias_params bias{};
+  int n_rigid = 0, first_rigid = -1;
+  double XR[3] = {0, 0, 0}, XR0[3] = {0, 0, 0};
+  bool init_vel = false;
+  std::vector<double> vel;  // explicit velocities set before finalize
+};
+
+struct Plan {
+  hdk::Tile *d_tiles = nullptr;
+  int32_t *d_sys = nullptr;
+  hdk::GridPlan gp{};
+  hipGraphExec_t exec = nullptr;
+  int graph_steps = 0;
+  int launches_per_graph = 0;
+};
+
+double minimg_h(double dx, double L, int periodic) {
+  if (!periodic) return dx;
+  if (dx > 0.5 * L) dx -= L;
+  else if (dx < -0.5 * L) dx += L;
+  return dx;
+}
+
+double wrap_h(double x, double L, int periodic) {
+  if (!periodic) return x;
+  if (x >= L) x -= L;
+  else if (x < 0.0) x += L;
+  return x;
+}
+
+}  // namespace
+
+struct hd_ctx {
+  hd_precision prec = HD_FP64;
+  int device = 0;
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;
+  hd_exec exec = HD_EXEC_BATCHED;
+  int block_threads = 0, max_nb = 0;
+  std::vector<SysHost> sys;
+  bool finalized = false, poisoned = false, need_eval = false;
+  std::string err;
+  // device memory
+  std::vector<void *> allocs;
+  hdk::Arrays A{};
+  SysDesc *d_desc = nullptr;
+  SysState *d_state = nullptr;
+  int32_t *d_all = nullptr;
+  std::vector<SysDesc> h_desc;
+  int block = 256;
+  int64_t ntot = 0;
+  // grid plans: [0] all systems (GRID), or one per system (SEQUENTIAL)
+  std::vector<Plan> plans;
+  void *d_gscal = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0.0;
+  int64_t last_launches = 0;
+};
+
+namespace {
+
+hd_status fail(hd_ctx *c, hd_status st, const std::string &msg) {
+  if (c) {
+    c->err = msg;
+    if (st == HD_E_HIP) c->poisoned = true;
+  }
+  return st;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, HD_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define CHECK_CTX()                                                                      \
+  do {                                                                                   \
+    if (!ctx) return HD_E_ARG;                                                           \
+    if (ctx->poisoned) return fail(ctx, HD_E_HIP, "context poisoned by an earlier HIP error"); \
+  } while (0)
+
+template <typename T>
+hd_status dalloc(hd_ctx *ctx, T **p, size_t count) {
+  void *q = nullptr;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) return fail(ctx, HD_E_OOM, "hipMalloc failed: " + std::string(hipGetErrorString(e)));
+  e = hipMemsetAsync(q, 0, bytes, ctx->stream);
+  if (e != hipSuccess) return fail(ctx, HD_E_HIP, "hipMemsetAsync failed");
+  ctx->allocs.push_back(q);
+  *p = (T *)q;
+  return HD_OK;
+}
+
+// Rigid body from the current rigid atoms: COM unwrapped about the first rigid
+// atom, offsets c_i = x_i - X_R, atoms re-placed at X_R + c_i.
+void init_rigid(SysHost &s) {
+  const int n = s.n;
+  s.n_rigid = 0;
+  s.first_rigid = -1;
+  for (int i = 0; i < n; ++i)
+    if (s.role[i] == HD_ROLE_RIGID) { if (s.first_rigid < 0) s.first_rigid = i; s.n_rigid++; }
+  s.cofs.assign((size_t)s.dim * n, 0.0);
+  for (int k = 0; k < 3; ++k) { s.XR[k] = 0; s.XR0[k] = 0; }
+  if (s.n_rigid == 0) return;
+  const int f = s.first_rigid;
+  for (int k = 0; k < s.dim; ++k) {
+    const double xf = s.pos[(size_t)k * n + f];
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (s.role[i] == HD_ROLE_RIGID) sum += xf + minimg_h(s.pos[(size_t)k * n + i] - xf, s.box[k], s.periodic[k]);
+    s.XR[k] = sum / s.n_rigid;
+    for (int i = 0; i < n; ++i)
+      if (s.role[i] == HD_ROLE_RIGID)
+        s.cofs[(size_t)k * n + i] = (xf + minimg_h(s.pos[(size_t)k * n + i] - xf, s.box[k], s.periodic[k])) - s.XR[k];
+    s.XR0[k] = s.XR[k];
+  }
+  for (int i = 0; i < n; ++i)
+    if (s.role[i] == HD_ROLE_RIGID)
+      for (int k = 0; k < s.dim; ++k)
+        s.pos[(size_t)k * n + i] = wrap_h(s.XR[k] + s.cofs[(size_t)k * n + i], s.box[k], s.periodic[k]);
+}
+
+void fill_desc(const hd_ctx *ctx, const SysHost &s, SysDesc &D) {
+  D.dim = s.dim;
+  D.n = s.n;
+  D.n_rigid = s.n_rigid;
+  D.first_rigid = s.first_rigid;
+  for (int k = 0; k < 3; ++k) {
+    D.periodic[k] = (k < s.dim) ? s.periodic[k] : 0;
+    D.box[k] = s.box[k];
+    D.hbox[k] = 0.5 * s.box[k];
+    D.XR0[k] = s.XR0[k];
+  }
+  D.mass = s.mass;
+  D.inv_mass = 1.0 / s.mass;
+  D.massR = s.mass * (s.n_rigid > 0 ? s.n_rigid : 1);
+  D.inv_massR = 1.0 / D.massR;
+  const double rc = s.lj.rc;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int t = a * 2 + b;
+      const double eps = s.lj.eps[a][b], s2 = s.lj.sig[a][b] * s.lj.sig[a][b];
+      const double sr2 = s2 / (rc * rc), sr6 = sr2 * sr2 * sr2;
+      D.eps[t] = eps;
+      D.sig2[t] = s2;
+      D.shift[t] = 4.0 * eps * (sr6 * sr6 - sr6);
+      D.eps_f[t] = (float)eps;
+      D.sig2_f[t] = (float)s2;
+      D.shift_f[t] = (float)D.shift[t];
+    }
+  D.rc2 = rc * rc;
+  const double rl = rc + s.lj.skin;
+  D.rl2 = rl * rl;
+  D.skin_half2 = 0.25 * s.lj.skin * s.lj.skin;
+  D.dt = s.th.dt;
+  D.hdt = 0.5 * s.th.dt;
+  D.c1 = std::exp(-s.th.gamma * s.th.dt);
+  D.c2 = std::sqrt((1.0 - D.c1 * D.c1) * s.th.kT / s.mass);
+  D.c2R = std::sqrt((1.0 - D.c1 * D.c1) * s.th.kT / D.massR);
+  D.kT = s.th.kT;
+  D.seed = s.th.seed;
+  D.k_spring = s.dr.k_spring;
+  D.f_normal = s.dr.f_normal;
+  D.x_slider = s.dr.x_slider;
+  D.v_slider = s.dr.v_slider;
+  D.bias_on = s.bias.enabled;
+  D.m_b = s.bias.m_b;
+  D.dv_max = s.bias.dv_max;
+  D.g_lo = s.bias.g_lo;
+  D.g_hi = s.bias.g_hi;
+  (void)ctx;
+}
+
+// Cell grid: cells of edge strictly above rc + skin (so atoms closer than the
+// list radius always land in the same or adjacent cells); a periodic axis with
+// room for fewer than three cells uses one; open axes span the initial extent
+// plus a margin, atoms beyond it are clamped into the edge cells.
+void fill_cells(const SysHost &s, SysDesc &D) {
+  const double rl = (s.lj.rc + s.lj.skin) * (1.0 + 1e-9);
+  for (int k = 0; k < 3; ++k) { D.nc[k] = 1; D.lo[k] = 0.0; D.inv_h[k] = 0.0; }
+  for (int k = 0; k < s.dim; ++k) {
+    if (s.periodic[k]) {
+      int m = (int)std::floor(s.box[k] / rl);
+      if (m < 3) m = 1;
+      D.nc[k] = m;
+      D.lo[k] = 0.0;
+      D.inv_h[k] = m / s.box[k];
+    } else {
+      double mn = s.pos[(size_t)k * s.n], mx = mn;
+      for (int i = 1; i < s.n; ++i) {
+        mn = std::min(mn, s.pos[(size_t)k * s.n + i]);
+        mx = std::max(mx, s.pos[(size_t)k * s.n + i]);
+      }
+      const double margin = 2.0 * rl + 5.0;
+      const double span = (mx - mn) + 2.0 * margin;
+      int m = (int)std::floor(span / rl);
+      if (m < 1) m = 1;
+      D.nc[k] = m;
+      D.lo[k] = mn - margin;
+      D.inv_h[k] = m / span;
+    }
+  }
+  D.ncell = D.nc[0] * D.nc[1] * D.nc[2];
+}
+
+hd_status upload_desc(hd_ctx *ctx, int s) {
+  SysDesc &D = ctx->h_desc[s];
+  fill_desc(ctx, ctx->sys[s], D);
+  HIPCHK(hipMemcpyAsync(ctx->d_desc + s, &D, sizeof(SysDesc), hipMemcpyHostToDevice, ctx->stream));
+  return HD_OK;
+}
+
+hd_status sync_in(hd_ctx *ctx) {
+  // order our stream after the caller's stream
+  if (ctx->user_stream && ctx->user_stream != ctx->stream) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(e, ctx->user_stream));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, e, 0));
+    HIPCHK(hipEventDestroy(e));
+  }
+  return HD_OK;
+}
+
+hd_status sync_out(hd_ctx *ctx) {
+  if (ctx->user_stream && ctx->user_stream != ctx->stream) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(e, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->user_stream, e, 0));
+    HIPCHK(hipEventDestroy(e));
+  }
+  return HD_OK;
+}
+
+hd_status check_sys(hd_ctx *ctx, int32_t s) {
+  if (s < 0 || s >= (int32_t)ctx->sys.size()) return fail(ctx, HD_E_ARG, "system index out of range");
+  return HD_OK;
+}
+
+hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
+  const int B = ctx->block;
+  std::vector<hdk::Tile> tiles;
+  int max_ncell = 1;
+  for (int s : systems) {
+    const int n = ctx->sys[s].n;
+    const int nt = (n + B - 1) / B;
+    for (int t = 0; t < nt; ++t) {
+      hdk::Tile T{};
+      T.sys = s;
+      T.first = t * B;
+      T.count = std::min(B, n - t * B);
+      T.tile_in_sys = t;
+      T.tiles_in_sys = nt;
+      tiles.push_back(T);
+    }
+    max_ncell = std::max(max_ncell, ctx->h_desc[s].ncell);
+  }
+  hd_status st = dalloc(ctx, &P.d_tiles, tiles.size());
+  if (st != HD_OK) return st;
+  st = dalloc(ctx, &P.d_sys, systems.size());
+  if (st != HD_OK) return st;
+  HIPCHK(hipMemcpyAsync(P.d_tiles, tiles.data(), tiles.size() * sizeof(hdk::Tile), hipMemcpyHostToDevice, ctx->stream));
+  std::vector<int32_t> ids(systems.begin(), systems.end());
+  HIPCHK(hipMemcpyAsync(P.d_sys, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  P.gp.tiles = P.d_tiles;
+  P.gp.ntiles = (int)tiles.size();
+  P.gp.block = B;
+  P.gp.sys_ids = P.d_sys;
+  P.gp.nsys = (int)systems.size();
+  P.gp.max_ncell = max_ncell;
+  P.gp.gscal = ctx->d_gscal;
+  return HD_OK;
+}
+
+hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps) {
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  int launches = 0;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < steps && e == hipSuccess; ++i)
+    e = hdk::grid_step(ctx->prec == HD_FP64 ? 0 : 1, ctx->d_desc, ctx->d_state, ctx->A, P.gp, false, cs, &launches);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cs, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    hipStreamDestroy(cs);
+    return fail(ctx, HD_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  HIPCHK(hipGraphInstantiate(&P.exec, g, nullptr, nullptr, 0));
+  HIPCHK(hipGraphDestroy(g));
+  HIPCHK(hipStreamDestroy(cs));
+  P.graph_steps = steps;
+  P.launches_per_graph = launches;
+  return HD_OK;
+}
+
+// Evaluate at the current positions (rebuilding lists) for every system.
+hd_status evaluate_all(hd_ctx *ctx) {
+  const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+  if (ctx->exec == HD_EXEC_BATCHED) {
+    HIPCHK(hdk::launch_batched(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_all, (int)ctx->sys.size(),
+                               ctx->block, 0, 1, ctx->stream));
+  } else {
+    for (auto &P : ctx->plans) {
+      int l = 0;
+      HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, true, ctx->stream, &l));
+      HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, ctx->stream));
+    }
+  }
+  ctx->need_eval = false;
+  return HD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+hd_status hd_create(hd_precision prec, int device, void *hip_stream, hd_ctx **out) {
+  if (!out || (prec != HD_FP64 && prec != HD_FP32C)) return HD_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return HD_E_NOGPU;
+  if (device < 0 || device >= ndev) return HD_E_ARG;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HD_E_NOGPU;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HD_E_NOGPU;
+  hd_ctx *ctx = new (std::nothrow) hd_ctx();
+  if (!ctx) return HD_E_OOM;
+  ctx->prec = prec;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) { delete ctx; return HD_E_HIP; }
+  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return HD_E_HIP; }
+  ctx->user_stream = (hipStream_t)hip_stream;
+  hipEventCreate(&ctx->ev0);
+  hipEventCreate(&ctx->ev1);
+  *out = ctx;
+  return HD_OK;
+}
+
+hd_status hd_set_exec(hd_ctx *ctx, hd_exec exec) {
+  CHECK_CTX();
+  if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_exec after hd_finalize");
+  if (exec != HD_EXEC_BATCHED && exec != HD_EXEC_GRID && exec != HD_EXEC_SEQUENTIAL)
+    return fail(ctx, HD_E_ARG, "unknown scheduler");
+  ctx->exec = exec;
+  return HD_OK;
+}
+
+hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors) {
+  CHECK_CTX();
+  if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_launch after hd_finalize");
+  if (block_threads != 0 && (block_threads < 64 || block_threads > 1024 || block_threads % 64 != 0))
+    return fail(ctx, HD_E_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
+  if (max_neighbors < 0 || max_neighbors > 4096) return fail(ctx, HD_E_ARG, "max_neighbors out of range");
+  ctx->block_threads = block_threads;
+  ctx->max_nb = max_neighbors;
+  return HD_OK;
+}
+
+hd_status hd_add_system(hd_ctx *ctx, const hd_system_desc *desc, const hd_lj_params *lj,
+                        const hd_thermo_params *thermo, const hd_drive_params *drive, int32_t *sys_id) {
+  CHECK_CTX();
+  if (ctx->finalized) return fail(ctx, HD_E_STATE, "systems must be added before hd_finalize");
+  if (!desc || !lj || !thermo || !drive) return fail(ctx, HD_E_ARG, "null parameter block");
+  if (desc->dim != 2 && desc->dim != 3) return fail(ctx, HD_E_ARG, "dim must be 2 or 3");
+  if (desc->n_atoms <= 0 || desc->n_atoms > (1 << 28)) return fail(ctx, HD_E_ARG, "n_atoms out of range");
+  if (!desc->pos || !desc->type || !desc->role) return fail(ctx, HD_E_ARG, "null per-atom array");
+  if (!(desc->mass > 0)) return fail(ctx, HD_E_ARG, "mass must be positive");
+  if (!(lj->rc > 0) || !(lj->skin >= 0)) return fail(ctx, HD_E_ARG, "bad cutoff or skin");
+  const double rl = lj->rc + lj->skin;
+  for (int k = 0; k < desc->dim; ++k)
+    if (desc->periodic[k] && !(desc->box[k] >= 2.0 * rl))
+      return fail(ctx, HD_E_ARG, "periodic box shorter than twice the list radius");
+  if (!(thermo->dt > 0) || thermo->gamma < 0 || thermo->kT < 0) return fail(ctx, HD_E_ARG, "bad thermostat");
+  SysHost s;
+  s.dim = desc->dim;
+  s.n = desc->n_atoms;
+  for (int k = 0; k < 3; ++k) { s.box[k] = desc->box[k]; s.periodic[k] = (k < s.dim) ? desc->periodic[k] : 0; }
+  s.mass = desc->mass;
+  const size_t nd = (size_t)s.dim * s.n;
+  s.pos.assign(desc->pos, desc->pos + nd);
+  s.type.assign(desc->type, desc->type + s.n);
+  s.role.assign(desc->role, desc->role + s.n);
+  for (int i = 0; i < s.n; ++i) {
+    if (s.type[i] > 1) return fail(ctx, HD_E_ARG, "type must be 0 or 1");
+    if (s.role[i] > 2) return fail(ctx, HD_E_ARG, "role must be 0, 1 or 2");
+  }
+  for (int k = 0; k < s.dim; ++k)
+    if (s.periodic[k])
+      for (int i = 0; i < s.n; ++i) {
+        double &x = s.pos[(size_t)k * s.n + i];
+        if (!(x >= 0.0 && x < s.box[k])) x = x - s.box[k] * std::floor(x / s.box[k]);
+        if (x >= s.box[k]) x = 0.0;
+      }
+  s.lj = *lj;
+  s.th = *thermo;
+  s.dr = *drive;
+  s.bias = hd_bias_params{0, 2, 0.0, 0.0, 1.0};
+  init_rigid(s);
+  s.rO = s.pos;
+  ctx->sys.push_back(std::move(s));
+  if (sys_id) *sys_id = (int32_t)ctx->sys.size() - 1;
+  return HD_OK;
+}
+
+hd_status hd_set_bias(hd_ctx *ctx, int32_t sys, const hd_bias_params *bias) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK || !bias) return fail(ctx, HD_E_ARG, "bad system or null bias");
+  if (bias->enabled && (bias->m_b < 1 || !(bias->g_lo < bias->g_hi) || bias->dv_max < 0))
+    return fail(ctx, HD_E_ARG, "bias needs m_b >= 1, g_lo < g_hi, dv_max >= 0");
+  if (bias->enabled && ctx->sys[sys].th.kT > 0 && bias->dv_max / ctx->sys[sys].th.kT > 700.0)
+    return fail(ctx, HD_E_ARG, "dv_max/kT above 700 overflows the boosted clock");
+  ctx->sys[sys].bias = *bias;
+  if (ctx->finalized) { ctx->need_eval = true; return upload_desc(ctx, sys); }
+  return HD_OK;
+}
+
+hd_status hd_set_slider(hd_ctx *ctx, int32_t sys, double x_slider) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK) return HD_E_ARG;
+  ctx->sys[sys].dr.x_slider = x_slider;
+  if (ctx->finalized) { ctx->need_eval = true; return upload_desc(ctx, sys); }
+  return HD_OK;
+}
+
+hd_status hd_set_thermo(hd_ctx *ctx, int32_t sys, const hd_thermo_params *thermo) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK || !thermo) return fail(ctx, HD_E_ARG, "bad system or null thermo");
+  if (!(thermo->dt > 0) || thermo->gamma < 0 || thermo->kT < 0) return fail(ctx, HD_E_ARG, "bad thermostat");
+  ctx->sys[sys].th = *thermo;
+  if (ctx->finalized) { ctx->need_eval = true; return upload_desc(ctx, sys); }
+  return HD_OK;
+}
+
+hd_status hd_set_reference(hd_ctx *ctx, int32_t sys, const double *rO) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK || !rO) return fail(ctx, HD_E_ARG, "bad system or null r_O");
+  SysHost &s = ctx->sys[sys];
+  s.rO.assign(rO, rO + (size_t)s.dim * s.n);
+  if (ctx->finalized) {
+    for (int k = 0; k < s.dim; ++k)
+      HIPCHK(hipMemcpyAsync(ctx->A.rO + k * ctx->ntot + ctx->h_desc[sys].off, s.rO.data() + (size_t)k * s.n,
+                            sizeof(double) * s.n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->need_eval = true;
+  }
+  return HD_OK;
+}
+
+hd_status hd_finalize(hd_ctx *ctx);
+
+static hd_status run_init_velocities(hd_ctx *ctx, int32_t sys);
+
+hd_status hd_init_velocities(hd_ctx *ctx, int32_t sys) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK) return HD_E_ARG;
+  if (!ctx->finalized) {
+    ctx->sys[sys].init_vel = true;
+    ctx->sys[sys].vel.clear();
+    return HD_OK;
+  }
+  return run_init_velocities(ctx, sys);
+}
+
+hd_status hd_sync(hd_ctx *ctx) {
+  CHECK_CTX();
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+}  // extern "C"
+
+namespace hdk {
+hipError_t launch_init_velocities(const SysDesc *descs, SysState *states, const Arrays &A, int sys,
+                                  int n, int block, hipStream_t stream);
+}
+
+static hd_status run_init_velocities(hd_ctx *ctx, int32_t sys) {
+  HIPCHK(hdk::launch_init_velocities(ctx->d_desc, ctx->d_state, ctx->A, sys, ctx->sys[sys].n, 256, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+extern "C" {
+
+hd_status hd_finalize(hd_ctx *ctx) {
+  CHECK_CTX();
+  if (ctx->finalized) return fail(ctx, HD_E_STATE, "already finalized");
+  const int S = (int)ctx->sys.size();
+  if (S == 0) return fail(ctx, HD_E_STATE, "no systems");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, HD_E_HIP, "hipSetDevice");
+  // layout
+  ctx->h_desc.assign(S, SysDesc{});
+  int64_t off = 0, cell_off = 0, cstart_off = 0, nbr_off = 0;
+  int max_dim = 2;
+  for (int s = 0; s < S; ++s) {
+    SysHost &h = ctx->sys[s];
+    SysDesc &D = ctx->h_desc[s];
+    fill_desc(ctx, h, D);
+    fill_cells(h, D);
+    D.off = off;
+    D.cell_off = cell_off;
+    D.cstart_off = cstart_off;
+    D.maxnb = ctx->max_nb > 0 ? ctx->max_nb : (h.dim == 2 ? 32 : 128);
+    D.nbr_off = nbr_off;
+    off += h.n;
+    cell_off += D.ncell;
+    cstart_off += D.ncell + 1;
+    nbr_off += (int64_t)D.maxnb * h.n;
+    max_dim = std::max(max_dim, h.dim);
+  }
+  const int64_t N = off;
+  ctx->ntot = N;
+  hdk::Arrays &A = ctx->A;
+  A.ntot = N;
+  hd_status st;
+#define ALLOC(p, cnt) do { st = dalloc(ctx, &(p), (cnt)); if (st != HD_OK) return st; } while (0)
+  ALLOC(A.x, 3 * N); ALLOC(A.v, 3 * N); ALLOC(A.rO, 3 * N); ALLOC(A.xb, 3 * N); ALLOC(A.cofs, 3 * N);
+  ALLOC(A.ftot, 3 * N); ALLOC(A.flj, 3 * N); ALLOC(A.hu, 3 * N); ALLOC(A.fb, 3 * N);
+  ALLOC(A.eatom, N);
+  if (ctx->prec == HD_FP64) { double *u; ALLOC(u, 3 * N); A.u = u; }
+  else { float *u; ALLOC(u, 3 * N); A.u = u; }
+  ALLOC(A.tr, N); ALLOC(A.nbr, nbr_off); ALLOC(A.nnb, N);
+  ALLOC(A.cell_count, cell_off); ALLOC(A.cell_start, cstart_off); ALLOC(A.cell_atoms, N); ALLOC(A.cidx, N);
+  ALLOC(A.sys_of, N);
+  ALLOC(A.tile_done, S); ALLOC(A.XR_next, 6 * S); ALLOC(A.rebuild_flag, S);
+  ALLOC(ctx->d_desc, S); ALLOC(ctx->d_state, S); ALLOC(ctx->d_all, S);
+  {
+    char *g;
+    ALLOC(g, hdk::grid_scal_bytes() * S);
+    ctx->d_gscal = g;
+  }
+  // block size
+  int maxn = 0;
+  for (auto &h : ctx->sys) maxn = std::max(maxn, h.n);
+  if (ctx->block_threads > 0) ctx->block = ctx->block_threads;
+  else if (ctx->exec == HD_EXEC_BATCHED) ctx->block = maxn <= 256 ? 256 : (maxn <= 512 ? 512 : 1024);
+  else ctx->block = 256;
+  // host staging
+  std::vector<double> x(3 * N, 0.0), rO(3 * N, 0.0), cofs(3 * N, 0.0), v(3 * N, 0.0);
+  std::vector<uint8_t> tr(N);
+  std::vector<int32_t> sys_of(N), all(S);
+  std::vector<SysState> states(S);
+  for (int s = 0; s < S; ++s) {
+    SysHost &h = ctx->sys[s];
+    const SysDesc &D = ctx->h_desc[s];
+    for (int k = 0; k < h.dim; ++k)
+      for (int i = 0; i < h.n; ++i) {
+        x[k * N + D.off + i] = h.pos[(size_t)k * h.n + i];
+        rO[k * N + D.off + i] = h.rO[(size_t)k * h.n + i];
+        cofs[k * N + D.off + i] = h.cofs[(size_t)k * h.n + i];
+        if (!h.vel.empty()) v[k * N + D.off + i] = h.vel[(size_t)k * h.n + i];
+      }
+    for (int i = 0; i < h.n; ++i) {
+      tr[D.off + i] = (uint8_t)(h.type[i] | (h.role[i] << 1));
+      sys_of[D.off + i] = s;
+    }
+    all[s] = s;
+    SysState &T = states[s];
+    std::memset(&T, 0, sizeof(T));
+    for (int k = 0; k < 3; ++k) T.XR[k] = h.XR[k];
+    if (!h.vel.empty() && h.n_rigid > 0) {
+      for (int k = 0; k < h.dim; ++k) {
+        double sum = 0.0;
+        for (int i = 0; i < h.n; ++i)
+          if (h.role[i] == HD_ROLE_RIGID) sum += h.vel[(size_t)k * h.n + i];
+        T.VR[k] = sum / h.n_rigid;
+      }
+    }
+    T.rebuild = 1;
+  }
+  HIPCHK(hipMemcpyAsync(A.x, x.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(A.xb, x.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(A.rO, rO.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(A.cofs, cofs.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(A.v, v.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(A.tr, tr.data(), N, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(A.sys_of, sys_of.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_all, all.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc.data(), S * sizeof(SysDesc), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_state, states.data(), S * sizeof(SysState), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->finalized = true;
+  // schedulers
+  if (ctx->exec == HD_EXEC_GRID) {
+    std::vector<int> sys_all(S);
+    for (int s = 0; s < S; ++s) sys_all[s] = s;
+    ctx->plans.resize(1);
+    if ((st = build_plan(ctx, sys_all, ctx->plans[0])) != HD_OK) return st;
+  } else if (ctx->exec == HD_EXEC_SEQUENTIAL) {
+    ctx->plans.resize(S);
+    for (int s = 0; s < S; ++s)
+      if ((st = build_plan(ctx, std::vector<int>{s}, ctx->plans[s])) != HD_OK) return st;
+  }
+  {
+    int max_tiles = 1;
+    for (auto &P : ctx->plans) max_tiles = std::max(max_tiles, P.gp.ntiles);
+    ALLOC(A.partials, (size_t)max_tiles * hdk::NRED);
+  }
+  if (ctx->exec != HD_EXEC_BATCHED) {
+    // grid path: rebuild flags raised for the first evaluation
+    std::vector<int32_t> ones(S, 1);
+    HIPCHK(hipMemcpyAsync(A.rebuild_flag, ones.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  }
+  for (int s = 0; s < S; ++s)
+    if (ctx->sys[s].init_vel) {
+      if ((st = run_init_velocities(ctx, s)) != HD_OK) return st;
+    }
+  if ((st = evaluate_all(ctx)) != HD_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+#undef ALLOC
+}
+
+hd_status hd_compute(hd_ctx *ctx) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_compute before hd_finalize");
+  hd_status st = sync_in(ctx);
+  if (st != HD_OK) return st;
+  if ((st = evaluate_all(ctx)) != HD_OK) return st;
+  return sync_out(ctx);
+}
+
+hd_status hd_step(hd_ctx *ctx, int64_t n_steps) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_step before hd_finalize");
+  if (n_steps < 0) return fail(ctx, HD_E_ARG, "negative step count");
+  if (n_steps == 0) return HD_OK;
+  hd_status st = sync_in(ctx);
+  if (st != HD_OK) return st;
+  if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
+  const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+  int64_t launches = 0;
+  HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+  if (ctx->exec == HD_EXEC_BATCHED) {
+    int64_t left = n_steps;
+    while (left > 0) {
+      const int64_t k = std::min(left, kChunkSteps);
+      HIPCHK(hdk::launch_batched(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_all, (int)ctx->sys.size(),
+                                 ctx->block, k, 0, ctx->stream));
+      ++launches;
+      left -= k;
+    }
+  } else {
+    for (auto &P : ctx->plans) {
+      int64_t left = n_steps;
+      if (left >= kGraphSteps && !P.exec && (st = capture_plan(ctx, P, kGraphSteps)) != HD_OK) return st;
+      while (left >= kGraphSteps && P.exec) {
+        HIPCHK(hipGraphLaunch(P.exec, ctx->stream));
+        launches += P.launches_per_graph;
+        left -= P.graph_steps;
+      }
+      while (left > 0) {
+        int l = 0;
+        HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, false, ctx->stream, &l));
+        launches += l;
+        --left;
+      }
+      HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, ctx->stream));
+      ++launches;
+    }
+  }
+  HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+  ctx->last_launches = launches;
+  ctx->last_ms = -1.0;
+  return sync_out(ctx);
+}
+
+hd_status hd_last_step_timing(hd_ctx *ctx, double *ms, int64_t *launches) {
+  CHECK_CTX();
+  HIPCHK(hipEventSynchronize(ctx->ev1));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, ctx->ev0, ctx->ev1));
+  if (ms) *ms = t;
+  if (launches) *launches = ctx->last_launches;
+  return HD_OK;
+}
+
+static hd_status copy_field(hd_ctx *ctx, int32_t sys, const double *base, double *out, hipMemcpyKind kind) {
+  const SysHost &s = ctx->sys[sys];
+  const SysDesc &D = ctx->h_desc[sys];
+  for (int k = 0; k < s.dim; ++k)
+    HIPCHK(hipMemcpyAsync(out + (size_t)k * s.n, base + k * ctx->ntot + D.off, sizeof(double) * s.n, kind, ctx->stream));
+  return HD_OK;
+}
+
+hd_status hd_read_forces(hd_ctx *ctx, int32_t sys, int32_t which, double *out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !out) return fail(ctx, HD_E_ARG, "bad system or null output");
+  const double *src = which == HD_FORCE_TOTAL ? ctx->A.ftot : which == HD_FORCE_LJ ? ctx->A.flj
+                    : which == HD_FORCE_BIAS ? ctx->A.fb : which == HD_HU ? ctx->A.hu : nullptr;
+  if (!src) return fail(ctx, HD_E_ARG, "unknown force selector");
+  hd_status st = copy_field(ctx, sys, src, out, hipMemcpyDeviceToHost);
+  if (st != HD_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+hd_status hd_read_positions(hd_ctx *ctx, int32_t sys, double *out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !out) return fail(ctx, HD_E_ARG, "bad system or null output");
+  hd_status st = copy_field(ctx, sys, ctx->A.x, out, hipMemcpyDeviceToHost);
+  if (st != HD_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+hd_status hd_read_velocities(hd_ctx *ctx, int32_t sys, double *out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !out) return fail(ctx, HD_E_ARG, "bad system or null output");
+  hd_status st = copy_field(ctx, sys, ctx->A.v, out, hipMemcpyDeviceToHost);
+  if (st != HD_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+hd_status hd_copy_positions_device(hd_ctx *ctx, int32_t sys, double *dev_out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !dev_out) return fail(ctx, HD_E_ARG, "bad system or null output");
+  return copy_field(ctx, sys, ctx->A.x, dev_out, hipMemcpyDeviceToDevice);
+}
+
+hd_status hd_copy_forces_device(hd_ctx *ctx, int32_t sys, int32_t which, double *dev_out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !dev_out) return fail(ctx, HD_E_ARG, "bad system or null output");
+  const double *src = which == HD_FORCE_TOTAL ? ctx->A.ftot : which == HD_FORCE_LJ ? ctx->A.flj
+                    : which == HD_FORCE_BIAS ? ctx->A.fb : which == HD_HU ? ctx->A.hu : nullptr;
+  if (!src) return fail(ctx, HD_E_ARG, "unknown force selector");
+  return copy_field(ctx, sys, src, dev_out, hipMemcpyDeviceToDevice);
+}
+
+hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !out) return fail(ctx, HD_E_ARG, "bad system or null output");
+  SysState T;
+  HIPCHK(hipMemcpyAsync(&T, ctx->d_state + sys, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  out->e_pot = T.e_pot;
+  out->e_kin = T.e_kin;
+  out->dv = T.dv;
+  out->dvp = T.dvp;
+  out->g = T.g;
+  out->d = T.d;
+  out->t_md = T.t_md;
+  out->t_hyper = T.t_hyper;
+  out->x_slider = T.x_slider;
+  out->x_tip = T.x_tip;
+  out->f_lat = T.f_lat;
+  out->step = T.step;
+  out->flags = T.flags;
+  out->n_rebuilds = T.n_rebuilds;
+  return HD_OK;
+}
+
+// Replace positions of one system: the rigid body follows its first atom.
+hd_status hd_set_positions(hd_ctx *ctx, int32_t sys, const double *pos) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK || !pos) return fail(ctx, HD_E_ARG, "bad system or null positions");
+  SysHost &s = ctx->sys[sys];
+  const int n = s.n;
+  std::vector<double> cur((size_t)s.dim * n);
+  double XR[3] = {s.XR[0], s.XR[1], s.XR[2]};
+  SysState T{};
+  if (ctx->finalized) {
+    hd_status st = copy_field(ctx, sys, ctx->A.x, cur.data(), hipMemcpyDeviceToHost);
+    if (st != HD_OK) return st;
+    HIPCHK(hipMemcpyAsync(&T, ctx->d_state + sys, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 3; ++k) XR[k] = T.XR[k];
+  } else {
+    cur = s.pos;
+  }
+  if (s.n_rigid > 0) {
+    const int f = s.first_rigid;
+    for (int k = 0; k < s.dim; ++k)
+      XR[k] = XR[k] + minimg_h(pos[(size_t)k * n + f] - cur[(size_t)k * n + f], s.box[k], s.periodic[k]);
+  }
+  std::vector<double> nx((size_t)s.dim * n);
+  for (int k = 0; k < s.dim; ++k)
+    for (int i = 0; i < n; ++i) {
+      const size_t q = (size_t)k * n + i;
+      nx[q] = (s.role[i] == HD_ROLE_RIGID) ? wrap_h(XR[k] + s.cofs[q], s.box[k], s.periodic[k]) : pos[q];
+    }
+  if (!ctx->finalized) {
+    s.pos = nx;
+    for (int k = 0; k < 3; ++k) s.XR[k] = XR[k];
+    return HD_OK;
+  }
+  const SysDesc &D = ctx->h_desc[sys];
+  for (int k = 0; k < s.dim; ++k)
+    HIPCHK(hipMemcpyAsync(ctx->A.x + k * ctx->ntot + D.off, nx.data() + (size_t)k * n, sizeof(double) * n,
+                          hipMemcpyHostToDevice, ctx->stream));
+  for (int k = 0; k < 3; ++k) T.XR[k] = XR[k];
+  T.rebuild = 1;
+  HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  if (ctx->exec != HD_EXEC_BATCHED) {
+    int32_t one = 1;
+    HIPCHK(hipMemcpyAsync(ctx->A.rebuild_flag + sys, &one, sizeof(one), hipMemcpyHostToDevice, ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->need_eval = true;
+  return HD_OK;
+}
+
+hd_status hd_set_velocities(hd_ctx *ctx, int32_t sys, const double *vel) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK || !vel) return fail(ctx, HD_E_ARG, "bad system or null velocities");
+  SysHost &s = ctx->sys[sys];
+  const int n = s.n;
+  std::vector<double> nv((size_t)s.dim * n, 0.0);
+  double VR[3] = {0, 0, 0};
+  for (int k = 0; k < s.dim; ++k) {
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const size_t q = (size_t)k * n + i;
+      if (s.role[i] == HD_ROLE_MOBILE) nv[q] = vel[q];
+      else if (s.role[i] == HD_ROLE_RIGID) sum += vel[q];
+    }
+    if (s.n_rigid > 0) VR[k] = sum / s.n_rigid;
+    for (int i = 0; i < n; ++i)
+      if (s.role[i] == HD_ROLE_RIGID) nv[(size_t)k * n + i] = VR[k];
+  }
+  if (!ctx->finalized) {
+    s.vel = nv;
+    s.init_vel = false;
+    return HD_OK;
+  }
+  const SysDesc &D = ctx->h_desc[sys];
+  for (int k = 0; k < s.dim; ++k)
+    HIPCHK(hipMemcpyAsync(ctx->A.v + k * ctx->ntot + D.off, nv.data() + (size_t)k * n, sizeof(double) * n,
+                          hipMemcpyHostToDevice, ctx->stream));
+  SysState T;
+  HIPCHK(hipMemcpyAsync(&T, ctx->d_state + sys, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < 3; ++k) T.VR[k] = VR[k];
+  HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+// Checkpoint layout: header, then x, v, rO, xb, ftot as [dim][n] doubles.
+struct CkptHeader {
+  uint32_t magic, version;
+  int32_t dim, n;
+  SysState state;
+};
+static const uint32_t kMagic = 0x68644350u;  // "hdCP"
+
+hd_status hd_get_state(hd_ctx *ctx, int32_t sys, void *buf, size_t *bytes) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !bytes) return fail(ctx, HD_E_ARG, "bad system or null size");
+  const SysHost &s = ctx->sys[sys];
+  const size_t nd = (size_t)s.dim * s.n;
+  const size_t need = sizeof(CkptHeader) + 5 * nd * sizeof(double);
+  if (!buf) { *bytes = need; return HD_OK; }
+  if (*bytes < need) return fail(ctx, HD_E_ARG, "checkpoint buffer too small");
+  CkptHeader h{};
+  h.magic = kMagic;
+  h.version = 1;
+  h.dim = s.dim;
+  h.n = s.n;
+  HIPCHK(hipMemcpyAsync(&h.state, ctx->d_state + sys, sizeof(SysState), hipMemcpyDeviceToHost, ctx->stream));
+  double *p = (double *)((char *)buf + sizeof(CkptHeader));
+  const double *fields[5] = {ctx->A.x, ctx->A.v, ctx->A.rO, ctx->A.xb, ctx->A.ftot};
+  for (int f = 0; f < 5; ++f) {
+    hd_status st = copy_field(ctx, sys, fields[f], p + f * nd, hipMemcpyDeviceToHost);
+    if (st != HD_OK) return st;
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memcpy(buf, &h, sizeof(h));
+  *bytes = need;
+  return HD_OK;
+}
+
+hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !buf) return fail(ctx, HD_E_ARG, "bad system or null buffer");
+  const SysHost &s = ctx->sys[sys];
+  const size_t nd = (size_t)s.dim * s.n;
+  if (bytes < sizeof(CkptHeader) + 5 * nd * sizeof(double)) return fail(ctx, HD_E_ARG, "checkpoint too short");
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kMagic || h.version != 1 || h.dim != s.dim || h.n != s.n)
+    return fail(ctx, HD_E_ARG, "checkpoint does not match this system");
+  const double *p = (const double *)((const char *)buf + sizeof(CkptHeader));
+  double *fields[5] = {ctx->A.x, ctx->A.v, ctx->A.rO, ctx->A.xb, ctx->A.ftot};
+  const SysDesc &D = ctx->h_desc[sys];
+  for (int f = 0; f < 5; ++f)
+    for (int k = 0; k < s.dim; ++k)
+      HIPCHK(hipMemcpyAsync(fields[f] + k * ctx->ntot + D.off, p + f * nd + (size_t)k * s.n, sizeof(double) * s.n,
+                            hipMemcpyHostToDevice, ctx->stream));
+  SysState T = h.state;
+  T.rebuild = 2;  // rebuild the list from the recorded build positions
+  HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int64_t *n_pairs) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !n_pairs || (cap > 0 && !ij)) return fail(ctx, HD_E_ARG, "bad arguments");
+  const SysHost &s = ctx->sys[sys];
+  const SysDesc &D = ctx->h_desc[sys];
+  std::vector<int32_t> nnb(s.n), list((size_t)D.maxnb * s.n);
+  HIPCHK(hipMemcpyAsync(nnb.data(), ctx->A.nnb + D.off, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(list.data(), ctx->A.nbr + D.nbr_off, sizeof(int32_t) * list.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  int64_t cnt = 0;
+  for (int i = 0; i < s.n; ++i)
+    for (int q = 0; q < nnb[i]; ++q) {
+      const int j = list[(size_t)q * s.n + i] >> 1;
+      if (j <= i) continue;
+      if (cnt < cap) { ij[2 * cnt] = i; ij[2 * cnt + 1] = j; }
+      ++cnt;
+    }
+  *n_pairs = cnt;
+  return HD_OK;
+}
+
+hd_status hd_system_info(hd_ctx *ctx, int32_t sys, int32_t *dim, int32_t *n_atoms) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK) return HD_E_ARG;
+  if (dim) *dim = ctx->sys[sys].dim;
+  if (n_atoms) *n_atoms = ctx->sys[sys].n;
+  return HD_OK;
+}
+
+int32_t hd_num_systems(const hd_ctx *ctx) { return ctx ? (int32_t)ctx->sys.size() : 0; }
+
+const char *hd_last_error(const hd_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void hd_destroy(hd_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  for (auto &P : ctx->plans)
+    if (P.exec) hipGraphExecDestroy(P.exec);
+  for (void *p : ctx->allocs) hipFree(p);
+  if (ctx->ev0) hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) hipEventDestroy(ctx->ev1);
+  if (ctx->stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,317 @@
+"""ctypes binding of libhd.so (include/hd.h), same names as the C ABI.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  The library is loaded from this package directory; if it is
+missing, or no gfx950 device is present, the calls fail loudly (there is no
+CPU fallback).  PyTorch, when used, only supplies a HIP stream and device
+buffers for the *_device copies.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhd.so")
+
+HD_OK, HD_E_ARG, HD_E_OOM, HD_E_HIP, HD_E_STATE, HD_E_UNSTABLE, HD_E_NOGPU = 0, -1, -2, -3, -4, -5, -6
+HD_FP64, HD_FP32C = 0, 1
+HD_EXEC_BATCHED, HD_EXEC_GRID, HD_EXEC_SEQUENTIAL = 0, 1, 2
+HD_FORCE_TOTAL, HD_FORCE_LJ, HD_FORCE_BIAS, HD_HU = 0, 1, 2, 3
+HD_FLAG_UNSTABLE, HD_FLAG_NBR_OVERFLOW = 1, 2
+
+_c = ctypes
+_dp = _c.POINTER(_c.c_double)
+
+
+class hd_system_desc(_c.Structure):
+    _fields_ = [("dim", _c.c_int32), ("n_atoms", _c.c_int32), ("box", _c.c_double * 3),
+                ("periodic", _c.c_int32 * 3), ("pos", _dp), ("type", _c.POINTER(_c.c_uint8)),
+                ("role", _c.POINTER(_c.c_uint8)), ("mass", _c.c_double)]
+
+
+class hd_lj_params(_c.Structure):
+    _fields_ = [("eps", (_c.c_double * 2) * 2), ("sig", (_c.c_double * 2) * 2),
+                ("rc", _c.c_double), ("skin", _c.c_double)]
+
+
+class hd_thermo_params(_c.Structure):
+    _fields_ = [("dt", _c.c_double), ("gamma", _c.c_double), ("kT", _c.c_double), ("seed", _c.c_uint64)]
+
+
+class hd_drive_params(_c.Structure):
+    _fields_ = [("k_spring", _c.c_double), ("f_normal", _c.c_double),
+                ("x_slider", _c.c_double), ("v_slider", _c.c_double)]
+
+
+class hd_bias_params(_c.Structure):
+    _fields_ = [("enabled", _c.c_int32), ("m_b", _c.c_int32), ("dv_max", _c.c_double),
+                ("g_lo", _c.c_double), ("g_hi", _c.c_double)]
+
+
+class hd_scalars(_c.Structure):
+    _fields_ = [("e_pot", _c.c_double), ("e_kin", _c.c_double), ("dv", _c.c_double),
+                ("dvp", _c.c_double), ("g", _c.c_double), ("d", _c.c_double),
+                ("t_md", _c.c_double), ("t_hyper", _c.c_double), ("x_slider", _c.c_double),
+                ("x_tip", _c.c_double), ("f_lat", _c.c_double), ("step", _c.c_int64),
+                ("flags", _c.c_int32), ("n_rebuilds", _c.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# name -> (restype, argtypes)
+_P = _c.c_void_p
+_SIGS = {
+    "hd_create": (_c.c_int, [_c.c_int, _c.c_int, _c.c_void_p, _c.POINTER(_c.c_void_p)]),
+    "hd_set_exec": (_c.c_int, [_P, _c.c_int]),
+    "hd_set_launch": (_c.c_int, [_P, _c.c_int32, _c.c_int32]),
+    "hd_add_system": (_c.c_int, [_P, _c.POINTER(hd_system_desc), _c.POINTER(hd_lj_params),
+                                 _c.POINTER(hd_thermo_params), _c.POINTER(hd_drive_params),
+                                 _c.POINTER(_c.c_int32)]),
+    "hd_set_reference": (_c.c_int, [_P, _c.c_int32, _dp]),
+    "hd_set_bias": (_c.c_int, [_P, _c.c_int32, _c.POINTER(hd_bias_params)]),
+    "hd_set_slider": (_c.c_int, [_P, _c.c_int32, _c.c_double]),
+    "hd_set_thermo": (_c.c_int, [_P, _c.c_int32, _c.POINTER(hd_thermo_params)]),
+    "hd_init_velocities": (_c.c_int, [_P, _c.c_int32]),
+    "hd_set_positions": (_c.c_int, [_P, _c.c_int32, _dp]),
+    "hd_set_velocities": (_c.c_int, [_P, _c.c_int32, _dp]),
+    "hd_finalize": (_c.c_int, [_P]),
+    "hd_step": (_c.c_int, [_P, _c.c_int64]),
+    "hd_compute": (_c.c_int, [_P]),
+    "hd_sync": (_c.c_int, [_P]),
+    "hd_read_forces": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _dp]),
+    "hd_read_positions": (_c.c_int, [_P, _c.c_int32, _dp]),
+    "hd_read_velocities": (_c.c_int, [_P, _c.c_int32, _dp]),
+    "hd_read_scalars": (_c.c_int, [_P, _c.c_int32, _c.POINTER(hd_scalars)]),
+    "hd_copy_positions_device": (_c.c_int, [_P, _c.c_int32, _c.c_void_p]),
+    "hd_copy_forces_device": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_void_p]),
+    "hd_get_state": (_c.c_int, [_P, _c.c_int32, _c.c_void_p, _c.POINTER(_c.c_size_t)]),
+    "hd_set_state": (_c.c_int, [_P, _c.c_int32, _c.c_void_p, _c.c_size_t]),
+    "hd_debug_pairs": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int32), _c.c_int64,
+                                  _c.POINTER(_c.c_int64)]),
+    "hd_system_info": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "hd_num_systems": (_c.c_int32, [_P]),
+    "hd_last_step_timing": (_c.c_int, [_P, _dp, _c.POINTER(_c.c_int64)]),
+    "hd_last_error": (_c.c_char_p, [_P]),
+    "hd_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhd.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> List[str]:
+    return list(_SIGS)
+
+
+class HDError(RuntimeError):
+    pass
+
+
+def _check(ctx, status: int, what: str):
+    if status != HD_OK:
+        msg = load().hd_last_error(ctx).decode() if ctx else ""
+        raise HDError(f"{what} failed with status {status}: {msg}")
+
+
+def _darr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+class Context:
+    """One hd_ctx: a batch of AFM model instances on one GPU."""
+
+    def __init__(self, precision: int = HD_FP32C, device: int = 0, stream=None,
+                 exec_mode: int = HD_EXEC_BATCHED, block_threads: int = 0, max_neighbors: int = 0):
+        L = load()
+        h = ctypes.c_void_p()
+        st = L.hd_create(int(precision), int(device), stream, ctypes.byref(h))
+        if st != HD_OK:
+            raise HDError(f"hd_create failed with status {st} (gfx950 device required)")
+        self._h = h
+        self.precision = precision
+        self.dims: List[int] = []
+        self.sizes: List[int] = []
+        _check(h, L.hd_set_exec(h, int(exec_mode)), "hd_set_exec")
+        _check(h, L.hd_set_launch(h, int(block_threads), int(max_neighbors)), "hd_set_launch")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().hd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- construction -----------------------------------------------------
+    def add_system(self, spec) -> int:
+        """Add one hd_inputs.SystemSpec (geometry + run parameters)."""
+        L = load()
+        pos = np.ascontiguousarray(spec.pos, dtype=np.float64)
+        typ = np.ascontiguousarray(spec.type, dtype=np.uint8)
+        rol = np.ascontiguousarray(spec.role, dtype=np.uint8)
+        d = hd_system_desc()
+        d.dim, d.n_atoms = spec.dim, spec.n
+        for k in range(3):
+            d.box[k] = float(spec.box[k])
+            d.periodic[k] = int(spec.periodic[k])
+        d.pos = _darr(pos)
+        d.type = typ.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        d.role = rol.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        d.mass = spec.mass
+        lj = hd_lj_params()
+        for a in range(2):
+            for b in range(2):
+                lj.eps[a][b] = float(spec.eps[a, b])
+                lj.sig[a][b] = float(spec.sig[a, b])
+        lj.rc, lj.skin = spec.rc, spec.skin
+        th = hd_thermo_params(spec.dt, spec.gamma, spec.kT, int(spec.seed))
+        dr = hd_drive_params(spec.k_spring, spec.f_normal, spec.x_slider, spec.v_slider)
+        sid = ctypes.c_int32()
+        _check(self._h, L.hd_add_system(self._h, ctypes.byref(d), ctypes.byref(lj), ctypes.byref(th),
+                                        ctypes.byref(dr), ctypes.byref(sid)), "hd_add_system")
+        s = sid.value
+        self.dims.append(spec.dim)
+        self.sizes.append(spec.n)
+        if spec.rO is not None:
+            self.set_reference(s, spec.rO)
+        if spec.bias_on:
+            self.set_bias(s, True, spec.m_b, spec.dv_max, spec.g_lo, spec.g_hi)
+        return s
+
+    def set_reference(self, s: int, rO: np.ndarray):
+        a = np.ascontiguousarray(rO, dtype=np.float64)
+        _check(self._h, load().hd_set_reference(self._h, s, _darr(a)), "hd_set_reference")
+
+    def set_bias(self, s: int, enabled: bool, m_b: int, dv_max: float, g_lo: float, g_hi: float):
+        b = hd_bias_params(int(enabled), int(m_b), float(dv_max), float(g_lo), float(g_hi))
+        _check(self._h, load().hd_set_bias(self._h, s, ctypes.byref(b)), "hd_set_bias")
+
+    def set_slider(self, s: int, x: float):
+        _check(self._h, load().hd_set_slider(self._h, s, float(x)), "hd_set_slider")
+
+    def set_thermo(self, s: int, dt: float, gamma: float, kT: float, seed: int):
+        t = hd_thermo_params(dt, gamma, kT, int(seed))
+        _check(self._h, load().hd_set_thermo(self._h, s, ctypes.byref(t)), "hd_set_thermo")
+
+    def init_velocities(self, s: int):
+        _check(self._h, load().hd_init_velocities(self._h, s), "hd_init_velocities")
+
+    def set_positions(self, s: int, x: np.ndarray):
+        a = np.ascontiguousarray(x, dtype=np.float64)
+        _check(self._h, load().hd_set_positions(self._h, s, _darr(a)), "hd_set_positions")
+
+    def set_velocities(self, s: int, v: np.ndarray):
+        a = np.ascontiguousarray(v, dtype=np.float64)
+        _check(self._h, load().hd_set_velocities(self._h, s, _darr(a)), "hd_set_velocities")
+
+    def finalize(self):
+        _check(self._h, load().hd_finalize(self._h), "hd_finalize")
+
+    # -- running ----------------------------------------------------------
+    def step(self, n: int):
+        _check(self._h, load().hd_step(self._h, int(n)), "hd_step")
+
+    def compute(self):
+        _check(self._h, load().hd_compute(self._h), "hd_compute")
+
+    def sync(self):
+        _check(self._h, load().hd_sync(self._h), "hd_sync")
+
+    def last_step_timing(self):
+        ms = ctypes.c_double()
+        nl = ctypes.c_int64()
+        _check(self._h, load().hd_last_step_timing(self._h, ctypes.byref(ms), ctypes.byref(nl)),
+               "hd_last_step_timing")
+        return ms.value, nl.value
+
+    # -- read-outs --------------------------------------------------------
+    def _out(self, s):
+        return np.zeros((self.dims[s], self.sizes[s]), dtype=np.float64)
+
+    def forces(self, s: int, which: int = HD_FORCE_TOTAL) -> np.ndarray:
+        o = self._out(s)
+        _check(self._h, load().hd_read_forces(self._h, s, int(which), _darr(o)), "hd_read_forces")
+        return o
+
+    def positions(self, s: int) -> np.ndarray:
+        o = self._out(s)
+        _check(self._h, load().hd_read_positions(self._h, s, _darr(o)), "hd_read_positions")
+        return o
+
+    def velocities(self, s: int) -> np.ndarray:
+        o = self._out(s)
+        _check(self._h, load().hd_read_velocities(self._h, s, _darr(o)), "hd_read_velocities")
+        return o
+
+    def scalars(self, s: int) -> dict:
+        sc = hd_scalars()
+        _check(self._h, load().hd_read_scalars(self._h, s, ctypes.byref(sc)), "hd_read_scalars")
+        return sc.as_dict()
+
+    def copy_positions_device(self, s: int, dev_ptr: int):
+        _check(self._h, load().hd_copy_positions_device(self._h, s, ctypes.c_void_p(dev_ptr)),
+               "hd_copy_positions_device")
+
+    def copy_forces_device(self, s: int, which: int, dev_ptr: int):
+        _check(self._h, load().hd_copy_forces_device(self._h, s, int(which), ctypes.c_void_p(dev_ptr)),
+               "hd_copy_forces_device")
+
+    def get_state(self, s: int) -> bytes:
+        n = ctypes.c_size_t()
+        L = load()
+        _check(self._h, L.hd_get_state(self._h, s, None, ctypes.byref(n)), "hd_get_state")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self._h, L.hd_get_state(self._h, s, buf, ctypes.byref(n)), "hd_get_state")
+        return buf.raw
+
+    def set_state(self, s: int, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self._h, load().hd_set_state(self._h, s, buf, len(blob)), "hd_set_state")
+
+    def debug_pairs(self, s: int) -> np.ndarray:
+        L = load()
+        n = ctypes.c_int64()
+        _check(self._h, L.hd_debug_pairs(self._h, s, None, 0, ctypes.byref(n)), "hd_debug_pairs")
+        out = np.zeros((max(n.value, 1), 2), dtype=np.int32)
+        _check(self._h, L.hd_debug_pairs(self._h, s, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         n.value, ctypes.byref(n)), "hd_debug_pairs")
+        return out[: n.value]
+
+
+def make_context(specs: Sequence, precision: int = HD_FP32C, exec_mode: int = HD_EXEC_BATCHED,
+                 init_velocities: bool = True, block_threads: int = 0, stream=None,
+                 max_neighbors: int = 0) -> Context:
+    """Context holding every spec, finalized, with Maxwell-Boltzmann velocities."""
+    ctx = Context(precision, 0, stream, exec_mode, block_threads, max_neighbors)
+    for sp in specs:
+        s = ctx.add_system(sp)
+        if init_velocities:
+            ctx.init_velocities(s)
+    ctx.finalize()
+    return ctx

@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances
+* neighbour lists: bit-exact set equality with the oracle's brute force;
+* float64 path: relative L2 error of forces / H u per system <= 1e-11 and
+  scalars to 1e-11 (summation order differs: full lists on the GPU, half
+  pairs in the oracle);
+* float32 path: relative L2 force error <= 1e-5 and |dV - dV_ref| <= 1e-6 dV_max
+  (the stated tolerances of the hot path);
+* short trajectories (identical Philox streams): float64 positions within
+  1e-10, float32 within a bound that follows from the force tolerance.
+"""
+import numpy as np
+import pytest
+
+from hd_inputs import (AFCC, A2D, ROLE_FIXED, ROLE_MOBILE, ROLE_RIGID, build_2d, build_3d,
+                       config_c4, perturbed)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    from paper_0909_5215_amd import hd as _hd
+    _hd.load()
+    return _hd
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def biased(oracle_mod, spec, frac=0.4, dv_max=0.5):
+    """Copy of spec whose slope thresholds bracket the snapshot's g."""
+    g = oracle_mod.OracleSystem(spec).compute()["g"]
+    s = spec.copy()
+    span = 2.0 * abs(g) + 1.0
+    s.bias_on, s.m_b, s.dv_max = 1, 2, dv_max
+    s.g_lo, s.g_hi = g - frac * span, g + (1.0 - frac) * span
+    return s
+
+
+def snapshot_2d(seed=3, x_slider=0.25):
+    """Perturbed 2D model; r_O is the lattice, so u = x - r_O is the jitter."""
+    s = build_2d()
+    s.x_slider = x_slider
+    s.rO = s.pos.copy()
+    s.pos = perturbed(s, 0.05, seed)
+    return s
+
+
+def snapshot_3d(seed=5, nx=20, nz=6, R=8.0, x_slider=0.4):
+    s = build_3d(nx, nx, nz, R)
+    s.x_slider = x_slider
+    s.rO = s.pos.copy()
+    s.pos = perturbed(s, 0.05, seed)
+    return s
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("maker", [snapshot_2d, lambda: snapshot_3d(nx=10, nz=4, R=4.0)])
+@pytest.mark.parametrize("exec_mode", [0, 2])
+def test_neighbour_pairs_bit_exact(hd, oracle_mod, maker, exec_mode):
+    spec = maker()
+    ctx = hd.make_context([spec], precision=hd.HD_FP64, exec_mode=exec_mode, init_velocities=False)
+    got = ctx.debug_pairs(0)
+    ref = oracle_mod.pairs_brute(spec, spec.pos, spec.rc + spec.skin, exclude=True)
+    sg = set(map(tuple, got.tolist()))
+    sr = set(map(tuple, ref.tolist()))
+    assert len(sg) == len(got)
+    assert sg == sr
+
+
+def _compare_eval(hd, oracle_mod, spec, precision, exec_mode=0, ftol=None):
+    ref = oracle_mod.OracleSystem(spec).compute()
+    ctx = hd.make_context([spec], precision=precision, exec_mode=exec_mode, init_velocities=False)
+    sc = ctx.scalars(0)
+    out = {w: ctx.forces(0, w) for w in (hd.HD_FORCE_TOTAL, hd.HD_FORCE_LJ, hd.HD_FORCE_BIAS, hd.HD_HU)}
+    return ref, sc, out
+
+
+@pytest.mark.parametrize("exec_mode", [0, 1, 2])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_evaluation_fp64(hd, oracle_mod, exec_mode, dim):
+    spec = snapshot_2d() if dim == 2 else snapshot_3d(nx=12, nz=4, R=5.0)
+    spec = biased(oracle_mod, spec)
+    ref, sc, out = _compare_eval(hd, oracle_mod, spec, hd.HD_FP64, exec_mode)
+    assert 0.0 < ref["dv"] < spec.dv_max
+    assert rel(out[hd.HD_FORCE_LJ], ref["f_lj"]) < 1e-11
+    assert rel(out[hd.HD_HU], ref["hu"]) < 1e-11
+    assert rel(out[hd.HD_FORCE_BIAS], ref["f_b"]) < 1e-10
+    assert rel(out[hd.HD_FORCE_TOTAL], ref["f_tot"]) < 1e-11
+    for k in ("e_pot", "g", "d"):
+        assert sc[k] == pytest.approx(ref[k], rel=1e-11), k
+    assert abs(sc["dv"] - ref["dv"]) <= 1e-11 * spec.dv_max
+    assert sc["f_lat"] == pytest.approx(ref["f_lat"], rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("exec_mode", [0, 1])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_evaluation_fp32c(hd, oracle_mod, exec_mode, dim):
+    spec = snapshot_2d(seed=7) if dim == 2 else snapshot_3d(seed=9)
+    spec = biased(oracle_mod, spec)
+    ref, sc, out = _compare_eval(hd, oracle_mod, spec, hd.HD_FP32C, exec_mode)
+    assert rel(out[hd.HD_FORCE_TOTAL], ref["f_tot"]) <= 1e-5
+    assert rel(out[hd.HD_FORCE_LJ], ref["f_lj"]) <= 1e-5
+    assert abs(sc["dv"] - ref["dv"]) <= 1e-6 * spec.dv_max
+    assert sc["e_pot"] == pytest.approx(ref["e_pot"], rel=1e-6)
+    assert sc["g"] == pytest.approx(ref["g"], rel=1e-5)
+
+
+def _trajectory(hd, oracle_mod, spec, precision, nsteps, exec_mode=0):
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    o.step(nsteps)
+    ctx = hd.make_context([spec], precision=precision, exec_mode=exec_mode, init_velocities=True)
+    ctx.step(nsteps)
+    return o, ctx
+
+
+@pytest.mark.parametrize("exec_mode", [0, 1])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_short_trajectory_fp64(hd, oracle_mod, exec_mode, dim):
+    spec = snapshot_2d(seed=11) if dim == 2 else snapshot_3d(seed=12, nx=10, nz=4, R=4.0)
+    spec.kT, spec.gamma = 0.1, 1.0
+    spec = biased(oracle_mod, spec)
+    o, ctx = _trajectory(hd, oracle_mod, spec, hd.HD_FP64, 10, exec_mode)
+    dx = ctx.positions(0) - o.positions()
+    for k in range(spec.dim):
+        if spec.periodic[k]:
+            dx[k] -= spec.box[k] * np.round(dx[k] / spec.box[k])
+    assert np.abs(dx).max() < 1e-10
+    assert np.abs(ctx.velocities(0) - o.velocities()).max() < 1e-9
+    sc, so = ctx.scalars(0), o.scalars()
+    assert sc["step"] == so["step"] == 10
+    assert sc["t_hyper"] == pytest.approx(so["t_hyper"], rel=1e-10)
+    assert sc["t_md"] == pytest.approx(so["t_md"], rel=1e-14)
+    assert sc["e_kin"] == pytest.approx(so["e_kin"], rel=1e-9)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_short_trajectory_fp32c(hd, oracle_mod, dim):
+    """Force errors of ~1e-6 relative move positions by ~dt^2 |dF| per step."""
+    spec = snapshot_2d(seed=13) if dim == 2 else snapshot_3d(seed=14, nx=10, nz=4, R=4.0)
+    spec = biased(oracle_mod, spec)
+    o, ctx = _trajectory(hd, oracle_mod, spec, hd.HD_FP32C, 10)
+    dx = ctx.positions(0) - o.positions()
+    for k in range(spec.dim):
+        if spec.periodic[k]:
+            dx[k] -= spec.box[k] * np.round(dx[k] / spec.box[k])
+    assert np.abs(dx).max() < 1e-8
+    sc, so = ctx.scalars(0), o.scalars()
+    assert sc["t_hyper"] == pytest.approx(so["t_hyper"], rel=1e-6)
+
+
+def test_clock_limits_on_gpu(hd, oracle_mod):
+    spec = snapshot_2d(seed=4)
+    spec.bias_on, spec.dv_max, spec.kT = 1, 0.3, 0.1
+    spec.g_lo, spec.g_hi = -2e30, -1e30
+    ctx = hd.make_context([spec], precision=hd.HD_FP64)
+    ctx.step(40)
+    sc = ctx.scalars(0)
+    assert sc["dv"] == spec.dv_max
+    assert sc["t_hyper"] == pytest.approx(sc["t_md"] * np.exp(spec.dv_max / spec.kT), rel=1e-13)
+    assert np.all(ctx.forces(0, hd.HD_FORCE_BIAS) == 0.0)
+
+
+def test_batch_matches_single_and_order(hd, oracle_mod):
+    """Each system of a batch gives the same bits as when run alone, in any order."""
+    specs = []
+    for k in range(4):
+        s = snapshot_2d(seed=20 + k, x_slider=k * A2D / 4)
+        specs.append(biased(oracle_mod, s))
+    big = hd.make_context(specs, precision=hd.HD_FP64, block_threads=512)
+    big.step(25)
+    rev = hd.make_context(specs[::-1], precision=hd.HD_FP64, block_threads=512)
+    rev.step(25)
+    for k in (0, 3):
+        one = hd.make_context([specs[k]], precision=hd.HD_FP64, block_threads=512)
+        one.step(25)
+        np.testing.assert_array_equal(big.positions(k), one.positions(0))
+        np.testing.assert_array_equal(rev.positions(3 - k), one.positions(0))
+        assert big.scalars(k)["t_hyper"] == one.scalars(0)["t_hyper"]
+
+
+def test_mixed_uneven_batch(hd, oracle_mod):
+    """2D and 3D instances of different sizes in one launch, each checked
+    against the oracle (float32 tolerances)."""
+    specs = [s for s in config_c4(12, seed=77, n_max=6000)]
+    specs = [biased(oracle_mod, s) for s in specs[:6]]
+    ctx = hd.make_context(specs, precision=hd.HD_FP32C, init_velocities=False)
+    for k, s in enumerate(specs):
+        ref = oracle_mod.OracleSystem(s).compute()
+        assert rel(ctx.forces(k), ref["f_tot"]) <= 1e-5, k
+        assert abs(ctx.scalars(k)["dv"] - ref["dv"]) <= 1e-6 * s.dv_max
+
+
+def test_fp64_determinism_and_checkpoint(hd, oracle_mod):
+    spec = biased(oracle_mod, snapshot_2d(seed=31))
+    a = hd.make_context([spec], precision=hd.HD_FP64)
+    a.step(30)
+    blob = a.get_state(0)
+    a.step(40)
+    b = hd.make_context([spec], precision=hd.HD_FP64)
+    b.step(70)
+    np.testing.assert_array_equal(a.positions(0), b.positions(0))
+    np.testing.assert_array_equal(a.velocities(0), b.velocities(0))
+    c = hd.make_context([spec], precision=hd.HD_FP64)
+    c.set_state(0, blob)
+    c.step(40)
+    np.testing.assert_array_equal(c.positions(0), a.positions(0))
+    np.testing.assert_array_equal(c.velocities(0), a.velocities(0))
+    assert c.scalars(0)["t_hyper"] == a.scalars(0)["t_hyper"]
+    assert c.scalars(0)["step"] == 70
