@@ -1,0 +1,248 @@
+"""Benchmark: biased LJ atom-steps/s of the batched float32 path on one MI355X,
+beside the plain float64 single-system path and the FP64 CPU oracle.
+
+Workload (default): the 2D AFM model (40x10 substrate + 10x8 tip, 480 atoms)
+at 32 stepped slider positions spread over one lattice period, slope bias on,
+Langevin T = 0.1, gamma = 1, dt = 0.005.  Other workloads: --config C3 | C4 |
+C5a | C5b.  Inputs are synthetic lattices built by hd_inputs (seeded).
+
+Setup (untimed): a damped quench on the GPU gives each system's basin
+reference r_O; an unbiased pre-run samples the slope g, and the bias
+thresholds are its 5% and 50% quantiles (dV_max = 5 kT, m = 2).  The timed
+region is K steps of every system with inputs resident in HBM; neighbour-list
+rebuilds are included.
+
+Output: one JSON line (rank 0, one GPU).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "biased LJ atom-steps/s: batched FP32 vs plain FP64, force rel err ≤1e-5"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--plain-steps", type=int, default=0, help="steps per system of the plain path (0 = auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--quench-steps", type=int, default=3000)
+    ap.add_argument("--prerun-steps", type=int, default=2000)
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from hd_inputs import CONFIGS
+    specs = CONFIGS[name]()
+    desc = {
+        "C1": "2D LJ AFM 40x10+10x8 (480 atoms), 1 system, continuous sliding v=0.01",
+        "C2": "2D LJ AFM 40x10+10x8 (480 atoms) x 32 slider positions, slope bias on",
+        "C3": "3D LJ AFM fcc 20x20x6 + R=8 tip (10742 atoms) x 64 slider positions, slope bias on",
+        "C4": "128 uneven 2D/3D instances (log-uniform 500-50k atoms), slope bias on",
+        "C5a": "3D LJ AFM fcc 100x100x25 + R=20 tip (1017285 atoms), 1 system, slope bias on",
+        "C5b": "3D LJ AFM fcc 18x18x6 + R=5 tip (8072 atoms) x 256 slider positions, slope bias on",
+    }[name]
+    return specs, desc
+
+
+def prepare(hd, specs, quench_steps, prerun_steps, block):
+    """Basin references by a damped quench, bias thresholds from an unbiased
+    pre-run (both on the GPU, untimed).  Returns specs with rO and bias set and
+    a checkpoint per system to start the timed runs from."""
+    q = [s.copy() for s in specs]
+    for s in q:
+        s.bias_on, s.kT, s.gamma, s.v_slider = 0, 0.0, 5.0, 0.0
+    ctx = hd.make_context(q, precision=hd.HD_FP64, init_velocities=False, block_threads=block)
+    ctx.step(quench_steps)
+    for k, s in enumerate(specs):
+        s.rO = ctx.positions(k)
+    ctx.close()
+    pre = [s.copy() for s in specs]
+    for s in pre:
+        s.bias_on = 0
+    ctx = hd.make_context(pre, precision=hd.HD_FP32C, init_velocities=True, block_threads=block)
+    for k, s in enumerate(specs):
+        ctx.set_positions(k, s.rO)       # start from the quenched basin
+    ctx.step(prerun_steps // 2)
+    samples = [[] for _ in specs]
+    nsamp = 100
+    every = max(1, prerun_steps // (2 * nsamp))
+    for _ in range(nsamp):
+        ctx.step(every)
+        for k in range(len(specs)):
+            samples[k].append(ctx.scalars(k)["g"])
+    states = []
+    for k, s in enumerate(specs):
+        g = np.array(samples[k])
+        s.bias_on, s.m_b = 1, 2
+        s.dv_max = 5.0 * s.kT
+        lo, hi = np.quantile(g, 0.05), np.quantile(g, 0.5)
+        if not hi > lo:
+            hi = lo + 1e-3 * (abs(lo) + 1.0)
+        s.g_lo, s.g_hi = float(lo), float(hi)
+        states.append(ctx.get_state(k))
+    ctx.close()
+    return specs, states
+
+
+def make_run_ctx(hd, specs, states, precision, exec_mode, block):
+    ctx = hd.Context(precision, 0, None, exec_mode, block, 0)
+    for s in specs:
+        ctx.add_system(s)
+    ctx.finalize()
+    for k, st in enumerate(states):
+        ctx.set_state(k, st)
+    return ctx
+
+
+def time_steps(torch, ctx, steps):
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms, launches = ctx.last_step_timing()
+    return wall, ev_ms, launches
+
+
+def cpu_baseline(specs, states_x, budget_s):
+    """The FP64 oracle as it stands, timed on the host cores on a bounded
+    sample of the same workload: every system (or as many as there are
+    threads) for a number of steps chosen to fill about budget_s seconds."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as orc
+    orc.build(force=False)
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    nsys = min(len(specs), max(cores, 1))
+    systems = []
+    for k in range(nsys):
+        s = specs[k]
+        o = orc.OracleSystem(s)              # same drive reference as the GPU runs
+        o.set_positions(states_x[k][0])
+        o.set_velocities(states_x[k][1])
+        systems.append(o)
+    # calibrate
+    t0 = time.perf_counter()
+    systems[0].step(5)
+    per_step = max(time.perf_counter() - t0, 1e-6) / 5
+    steps = max(5, int(budget_s / per_step * min(1.0, cores / nsys)))
+    steps = min(steps, 100000)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(lambda o: o.step(steps), systems))
+    wall = time.perf_counter() - t0
+    atoms = sum(specs[k].n for k in range(nsys))
+    return {"value": atoms * steps / wall, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nsys} of {len(specs)} systems x {steps} steps (FP64 oracle, one thread per system)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(independent slider positions would be split across GPUs with no per-step communication)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_0909_5215_amd import hd
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    torch.cuda.init()
+
+    specs, desc = workload(args.config)
+    n_atoms = sum(s.n for s in specs)
+    dim = specs[0].dim
+    log(f"{args.config}: {len(specs)} systems, {n_atoms} atoms")
+    specs, states = prepare(hd, specs, args.quench_steps, args.prerun_steps, args.block)
+    log("prepared (quench + pre-run)")
+
+    # ---- batched float32 path ------------------------------------------------
+    ctx = make_run_ctx(hd, specs, states, hd.HD_FP32C, hd.HD_EXEC_BATCHED, args.block)
+    ctx.step(args.warmup)
+    wall, ev_ms, launches = time_steps(torch, ctx, args.steps)
+    value = n_atoms * args.steps / wall
+    flags = [ctx.scalars(k)["flags"] for k in range(len(specs))]
+    t_hyper = [ctx.scalars(k)["t_hyper"] for k in range(len(specs))]
+    t_md = [ctx.scalars(k)["t_md"] for k in range(len(specs))]
+    log(f"batched fp32: {value:.4g} atom-steps/s, wall {wall:.3f}s, events {ev_ms:.1f} ms over {launches} launches")
+    states_x = [(ctx.positions(k), ctx.velocities(k)) for k in range(len(specs))]
+
+    # roofline of the dominant kernel (the batched persistent kernel): the
+    # algorithmic bytes are the per-atom state read and written once per step
+    # (x and v read+written, r_O read, float64): 5*D*8 bytes per atom-step
+    bytes_per_atom_step = 5 * dim * 8
+    steps_per_launch = args.steps / max(launches, 1)
+    avg_launch_s = (ev_ms / 1e3) / max(launches, 1)
+    achieved = bytes_per_atom_step * n_atoms * steps_per_launch / avg_launch_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+            "kernel": "k_batched<float>", "avg_launch_ms": round(ev_ms / max(launches, 1), 4),
+            "steps_per_launch": steps_per_launch, "bytes_per_atom_step": bytes_per_atom_step}
+
+    # ---- plain float64 single-system path -----------------------------------
+    plain = None
+    if not args.no_plain:
+        pctx = make_run_ctx(hd, specs, states, hd.HD_FP64, hd.HD_EXEC_SEQUENTIAL, args.block)
+        psteps = args.plain_steps or max(100, min(1000, args.steps // 20))
+        pctx.step(50)
+        pwall, pev, pl = time_steps(torch, pctx, psteps)
+        pval = n_atoms * psteps / pwall
+        plain = {"value": pval, "unit": "atom-steps/s", "steps": psteps,
+                 "kind": "plain FP64, one system at a time, per-step kernels replayed from HIP graphs"}
+        log(f"plain fp64: {pval:.4g} atom-steps/s")
+        pctx.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(specs, states_x, args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.4g} atom-steps/s on {cpu['cores']} cores")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {desc}", "systems": len(specs), "atoms": n_atoms,
+                   "dim": dim, "parallelism": "batch of independent slider positions, 1 GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64_plain": plain,
+        "speedup_vs_fp64_plain": (value / plain["value"]) if plain else None,
+        "unstable_systems": int(sum(1 for f in flags if f & 1)),
+        "mean_boost": float(np.mean(np.array(t_hyper) / np.maximum(np.array(t_md), 1e-300))),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -142,10 +142,12 @@ hd_status hd_create(hd_precision prec, int device, void *hip_stream, hd_ctx **ou
 /* Choose the scheduler before hd_finalize (default HD_EXEC_BATCHED). */
 hd_status hd_set_exec(hd_ctx *ctx, hd_exec exec);
 
-/* Tuning knobs before hd_finalize: threads per workgroup of the batched kernel
- * (64..1024, multiple of 64; 0 = automatic) and the neighbour-slot capacity
- * per atom (0 = automatic). */
-hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors);
+/* Tuning knobs before hd_finalize: threads per workgroup of the global-memory
+ * batched kernel and of the grid tiles (64..1024, multiple of 64; 0 =
+ * automatic), the neighbour-slot capacity per atom (0 = automatic: 32 in 2D,
+ * 128 in 3D), and whether systems that fit in one workgroup's LDS run in the
+ * LDS-resident kernel (1 = automatic, the default; 0 = never). */
+hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors, int32_t lds_resident);
 
 /* Append one model.  Copies every array.  Returns its index in *sys_id.  The
  * basin reference r_O defaults to the given positions; velocities start at 0;

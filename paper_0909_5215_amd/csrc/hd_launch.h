@@ -12,6 +12,16 @@ hipError_t launch_batched(int prec, const SysDesc *descs, SysState *states, cons
                           const int32_t *sys_list, int nsys, int block, int64_t nsteps, int mode,
                           hipStream_t stream);
 
+// LDS-resident variant for systems of at most 1024 atoms whose positions,
+// displacements, cell list and neighbour list fit in one workgroup's LDS.
+// block >= the largest listed system; nmax is the LDS row stride (>= every
+// listed n); maxnb2 / maxnb3 are the neighbour capacities of 2D / 3D systems;
+// cellmax >= every listed ncell.
+hipError_t launch_small(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
+                        const int32_t *sys_list, int nsys, int block, int nmax, int maxnb2, int maxnb3,
+                        int cellmax, int64_t nsteps, int mode, hipStream_t stream);
+size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax);
+
 // Tiles of the grid scheduler: each tile is a contiguous atom range of one
 // system (tiles never straddle systems).
 struct Tile {

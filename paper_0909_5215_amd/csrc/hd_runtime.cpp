@@ -74,6 +74,7 @@ struct hd_ctx {
   hipStream_t stream = nullptr;
   hd_exec exec = HD_EXEC_BATCHED;
   int block_threads = 0, max_nb = 0;
+  bool small_disabled = false;
   std::vector<SysHost> sys;
   bool finalized = false, poisoned = false, need_eval = false;
   std::string err;
@@ -83,6 +84,14 @@ struct hd_ctx {
   SysDesc *d_desc = nullptr;
   SysState *d_state = nullptr;
   int32_t *d_all = nullptr;
+  // batched scheduler: systems resident in LDS vs in global memory
+  std::vector<int32_t> small_ids, big_ids;
+  int32_t *d_small = nullptr, *d_big = nullptr;
+  int small_block = 64, small_nmax = 0, small_cellmax = 1;
+  int maxnb2 = 32, maxnb3 = 128;
+  size_t lds_limit = 0;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   std::vector<SysDesc> h_desc;
   int block = 256;
   int64_t ntot = 0;
@@ -334,12 +343,39 @@ hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps) {
   return HD_OK;
 }
 
+// One batched launch of every system: LDS-resident systems on the context
+// stream, the others concurrently on a second stream, joined by events.
+hd_status launch_batched_all(hd_ctx *ctx, int64_t nsteps, int mode, int64_t *launches) {
+  const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+  const bool both = !ctx->small_ids.empty() && !ctx->big_ids.empty();
+  if (both) {
+    HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->stream2, ctx->fork, 0));
+  }
+  if (!ctx->small_ids.empty()) {
+    HIPCHK(hdk::launch_small(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_small, (int)ctx->small_ids.size(),
+                             ctx->small_block, ctx->small_nmax, ctx->maxnb2, ctx->maxnb3, ctx->small_cellmax,
+                             nsteps, mode, ctx->stream));
+    if (launches) ++*launches;
+  }
+  if (!ctx->big_ids.empty()) {
+    HIPCHK(hdk::launch_batched(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_big, (int)ctx->big_ids.size(),
+                               ctx->block, nsteps, mode, both ? ctx->stream2 : ctx->stream));
+    if (launches) ++*launches;
+  }
+  if (both) {
+    HIPCHK(hipEventRecord(ctx->join, ctx->stream2));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->join, 0));
+  }
+  return HD_OK;
+}
+
 // Evaluate at the current positions (rebuilding lists) for every system.
 hd_status evaluate_all(hd_ctx *ctx) {
   const int prec = ctx->prec == HD_FP64 ? 0 : 1;
   if (ctx->exec == HD_EXEC_BATCHED) {
-    HIPCHK(hdk::launch_batched(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_all, (int)ctx->sys.size(),
-                               ctx->block, 0, 1, ctx->stream));
+    hd_status st = launch_batched_all(ctx, 0, 1, nullptr);
+    if (st != HD_OK) return st;
   } else {
     for (auto &P : ctx->plans) {
       int l = 0;
@@ -372,8 +408,14 @@ hd_status hd_create(hd_precision prec, int device, void *hip_stream, hd_ctx **ou
   if (hipSetDevice(device) != hipSuccess) { delete ctx; return HD_E_HIP; }
   if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return HD_E_HIP; }
   ctx->user_stream = (hipStream_t)hip_stream;
+  if (hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking) != hipSuccess) { delete ctx; return HD_E_HIP; }
   hipEventCreate(&ctx->ev0);
   hipEventCreate(&ctx->ev1);
+  hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
+  hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
+  ctx->lds_limit = (size_t)lds;
   *out = ctx;
   return HD_OK;
 }
@@ -387,14 +429,16 @@ hd_status hd_set_exec(hd_ctx *ctx, hd_exec exec) {
   return HD_OK;
 }
 
-hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors) {
+hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors, int32_t lds_resident) {
   CHECK_CTX();
   if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_launch after hd_finalize");
   if (block_threads != 0 && (block_threads < 64 || block_threads > 1024 || block_threads % 64 != 0))
     return fail(ctx, HD_E_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
   if (max_neighbors < 0 || max_neighbors > 4096) return fail(ctx, HD_E_ARG, "max_neighbors out of range");
+  if (lds_resident != 0 && lds_resident != 1) return fail(ctx, HD_E_ARG, "lds_resident must be 0 or 1");
   ctx->block_threads = block_threads;
   ctx->max_nb = max_neighbors;
+  ctx->small_disabled = lds_resident == 0;
   return HD_OK;
 }
 
@@ -571,12 +615,58 @@ hd_status hd_finalize(hd_ctx *ctx) {
     ALLOC(g, hdk::grid_scal_bytes() * S);
     ctx->d_gscal = g;
   }
-  // block size
+  // batched scheduler: systems of <= 1024 atoms whose state fits in LDS run
+  // LDS-resident (one thread per atom), the rest from global memory
+  ctx->maxnb2 = ctx->max_nb > 0 ? ctx->max_nb : 32;
+  ctx->maxnb3 = ctx->max_nb > 0 ? ctx->max_nb : 128;
+  ctx->small_ids.clear();
+  ctx->big_ids.clear();
+  if (ctx->exec == HD_EXEC_BATCHED) {
+    const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+    const size_t budget = ctx->lds_limit > 8192 ? ctx->lds_limit - 8192 : 0;  // static LDS of the kernel
+    std::vector<int> cand;
+    int nmax = 0, cellmax = 1;
+    for (int s = 0; s < S; ++s) {
+      const SysHost &h = ctx->sys[s];
+      const int maxnb = h.dim == 2 ? ctx->maxnb2 : ctx->maxnb3;
+      const bool ok = h.n <= 1024 && maxnb <= 32767 &&
+                      hdk::small_lds_bytes(h.dim, prec, h.n, maxnb, ctx->h_desc[s].ncell) <= budget &&
+                      !ctx->small_disabled;
+      if (ok) cand.push_back(s);
+      else ctx->big_ids.push_back(s);
+    }
+    // admit candidates while the common layout (largest n and cell count) fits
+    std::sort(cand.begin(), cand.end(), [&](int a, int b) { return ctx->sys[a].n < ctx->sys[b].n; });
+    for (int s : cand) {
+      const int n2 = std::max(nmax, ctx->sys[s].n), c2 = std::max(cellmax, ctx->h_desc[s].ncell);
+      const size_t b2 = hdk::small_lds_bytes(2, prec, n2, ctx->maxnb2, c2);
+      const size_t b3 = hdk::small_lds_bytes(3, prec, n2, ctx->maxnb3, c2);
+      bool has3 = ctx->sys[s].dim == 3;
+      for (int q : ctx->small_ids) has3 = has3 || ctx->sys[q].dim == 3;
+      const size_t need = has3 ? std::max(b2, b3) : b2;
+      if (need <= budget) { ctx->small_ids.push_back(s); nmax = n2; cellmax = c2; }
+      else ctx->big_ids.push_back(s);
+    }
+    std::sort(ctx->small_ids.begin(), ctx->small_ids.end());
+    std::sort(ctx->big_ids.begin(), ctx->big_ids.end());
+    ctx->small_nmax = nmax;
+    ctx->small_cellmax = cellmax;
+    ctx->small_block = std::max(64, (nmax + 63) / 64 * 64);
+  }
+  // block size of the global-memory batched kernel / grid tiles
   int maxn = 0;
-  for (auto &h : ctx->sys) maxn = std::max(maxn, h.n);
+  for (int s : ctx->big_ids) maxn = std::max(maxn, ctx->sys[s].n);
   if (ctx->block_threads > 0) ctx->block = ctx->block_threads;
   else if (ctx->exec == HD_EXEC_BATCHED) ctx->block = maxn <= 256 ? 256 : (maxn <= 512 ? 512 : 1024);
   else ctx->block = 256;
+  ALLOC(ctx->d_small, ctx->small_ids.size());
+  ALLOC(ctx->d_big, ctx->big_ids.size());
+  if (!ctx->small_ids.empty())
+    HIPCHK(hipMemcpyAsync(ctx->d_small, ctx->small_ids.data(), ctx->small_ids.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, ctx->stream));
+  if (!ctx->big_ids.empty())
+    HIPCHK(hipMemcpyAsync(ctx->d_big, ctx->big_ids.data(), ctx->big_ids.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, ctx->stream));
   // host staging
   std::vector<double> x(3 * N, 0.0), rO(3 * N, 0.0), cofs(3 * N, 0.0), v(3 * N, 0.0);
   std::vector<uint8_t> tr(N);
@@ -677,9 +767,7 @@ hd_status hd_step(hd_ctx *ctx, int64_t n_steps) {
     int64_t left = n_steps;
     while (left > 0) {
       const int64_t k = std::min(left, kChunkSteps);
-      HIPCHK(hdk::launch_batched(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_all, (int)ctx->sys.size(),
-                                 ctx->block, k, 0, ctx->stream));
-      ++launches;
+      if ((st = launch_batched_all(ctx, k, 0, &launches)) != HD_OK) return st;
       left -= k;
     }
   } else {
@@ -987,6 +1075,9 @@ void hd_destroy(hd_ctx *ctx) {
   for (void *p : ctx->allocs) hipFree(p);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
   if (ctx->ev1) hipEventDestroy(ctx->ev1);
+  if (ctx->stream2) { hipStreamSynchronize(ctx->stream2); hipStreamDestroy(ctx->stream2); }
+  if (ctx->fork) hipEventDestroy(ctx->fork);
+  if (ctx->join) hipEventDestroy(ctx->join);
   if (ctx->stream) hipStreamDestroy(ctx->stream);
   delete ctx;
 }

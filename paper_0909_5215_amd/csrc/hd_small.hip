@@ -1,0 +1,462 @@
+// LDS-resident batched kernel for systems that fit one workgroup: one thread
+// per atom, the atom's own state (x, v, total force, r_O, build position) in
+// registers, and the system's positions, displacements u = r - r_O, cell list
+// and neighbour list in LDS for the whole chunk of steps.  A step touches no
+// global memory: the neighbour gathers of the pair pass are LDS reads, and
+// the per-system reductions and barriers stay inside the workgroup.  State is
+// loaded at the start of a launch and written back at its end.
+//
+// The arithmetic is the same as the global-memory batched kernel (BAOAB,
+// LJ + H u pair terms, slope bias of eq. 13-14, boosted clock of eq. 3).
+#include "hd_device.h"
+#include "hd_launch.h"
+
+namespace hdk {
+
+struct SmallLayout {
+  int nmax, maxnb, cellmax;
+  size_t off_x, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
+};
+
+__host__ __device__ inline SmallLayout small_layout(int dim, int tsize, int nmax, int maxnb, int cellmax) {
+  SmallLayout L;
+  L.nmax = nmax; L.maxnb = maxnb; L.cellmax = cellmax;
+  size_t o = 0;
+  L.off_x = o; o += (size_t)8 * dim * nmax;
+  L.off_u = o; o += (size_t)tsize * dim * nmax; o = (o + 7) & ~(size_t)7;
+  L.off_nbr = o; o += (size_t)2 * maxnb * nmax; o = (o + 7) & ~(size_t)7;
+  L.off_cnt = o; o += (size_t)4 * cellmax;
+  L.off_cst = o; o += (size_t)4 * (cellmax + 1);
+  L.off_cat = o; o += (size_t)4 * nmax; o = (o + 15) & ~(size_t)15;
+  L.bytes = o;
+  return L;
+}
+
+size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax) {
+  return small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax).bytes;
+}
+
+// Rebuild the cell list and every atom's neighbour list in LDS from the LDS
+// positions.  Same cell rule, pair test (r^2 summed axis by axis without
+// contraction, strict < (rc+skin)^2) and exclusions as the global version.
+template <int DIM>
+__device__ int lds_rebuild(const SysDesc &D, const double *__restrict__ xs, uint16_t *__restrict__ nbr,
+                           int *__restrict__ cnt, int *__restrict__ cst, int *__restrict__ cat,
+                           const uint8_t *__restrict__ tr_all, int stride, int *lds_int, int &nn_own,
+                           const double xi[3], int i, int ri) {
+  const int tid = threadIdx.x, B = blockDim.x, n = D.n, ncell = D.ncell;
+  for (int c = tid; c < ncell; c += B) cnt[c] = 0;
+  __syncthreads();
+  int my_cell = 0;
+  if (i < n) {
+    int c3[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      int ck = (int)floor((xi[k] - D.lo[k]) * D.inv_h[k]);
+      c3[k] = ck < 0 ? 0 : (ck >= D.nc[k] ? D.nc[k] - 1 : ck);
+    }
+    my_cell = (c3[2] * D.nc[1] + c3[1]) * D.nc[0] + c3[0];
+    atomicAdd(&cnt[my_cell], 1);
+  }
+  __syncthreads();
+  const int chunk = (ncell + B - 1) / B;
+  const int c0 = tid * chunk, c1 = min(ncell, c0 + chunk);
+  int local = 0;
+  for (int c = c0; c < c1; ++c) local += cnt[c];
+  int total = 0;
+  int run = block_exscan(local, lds_int, total);
+  for (int c = c0; c < c1; ++c) { const int k = cnt[c]; cst[c] = run; run += k; cnt[c] = 0; }
+  if (tid == 0) cst[ncell] = total;
+  __syncthreads();
+  if (i < n) {
+    const int slot = atomicAdd(&cnt[my_cell], 1);
+    cat[cst[my_cell] + slot] = i;
+  }
+  __syncthreads();
+  for (int c = tid; c < ncell; c += B) {
+    const int b = cst[c], e = cst[c + 1];
+    for (int p = b + 1; p < e; ++p) {
+      const int key = cat[p];
+      int q = p - 1;
+      while (q >= b && cat[q] > key) { cat[q + 1] = cat[q]; --q; }
+      cat[q + 1] = key;
+    }
+  }
+  __syncthreads();
+  int ov = 0;
+  if (i < n) {
+    int cc[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      int ck = (int)floor((xi[k] - D.lo[k]) * D.inv_h[k]);
+      cc[k] = ck < 0 ? 0 : (ck >= D.nc[k] ? D.nc[k] - 1 : ck);
+    }
+    int lo3[3] = {0, 0, 0}, hi3[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+      if (D.nc[k] > 1) { lo3[k] = -1; hi3[k] = 1; }
+    int count = 0;
+    for (int oz = lo3[2]; oz <= hi3[2]; ++oz)
+      for (int oy = lo3[1]; oy <= hi3[1]; ++oy)
+        for (int ox = lo3[0]; ox <= hi3[0]; ++ox) {
+          int q3[3] = {cc[0] + ox, cc[1] + oy, cc[2] + oz};
+          bool skip = false;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            if (q3[k] < 0 || q3[k] >= D.nc[k]) {
+              if (k < DIM && D.periodic[k]) q3[k] = (q3[k] + D.nc[k]) % D.nc[k];
+              else skip = true;
+            }
+          }
+          if (skip) continue;
+          const int q = (q3[2] * D.nc[1] + q3[1]) * D.nc[0] + q3[0];
+          for (int p = cst[q]; p < cst[q + 1]; ++p) {
+            const int j = cat[p];
+            if (j == i) continue;
+            const int trj = tr_all[j];
+            const int rj = trj >> 1;
+            if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
+            double r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+              const double d = minimg(xs[k * stride + j] - xi[k], D.box[k], D.hbox[k], D.periodic[k]);
+              r2 = __dadd_rn(r2, __dmul_rn(d, d));
+            }
+            if (r2 < D.rl2) {
+              if (count < D.maxnb) nbr[count * stride + i] = (uint16_t)((j << 1) | (trj & 1));
+              ++count;
+            }
+          }
+        }
+    nn_own = count < D.maxnb ? count : D.maxnb;
+    if (count > D.maxnb) ov = 1;
+  }
+  return block_or(ov, lds_int + 20);
+}
+
+template <int DIM, typename T>
+__device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Arrays &A,
+                          int64_t nsteps, int mode, char *lds, const SmallLayout L) {
+  const int tid = threadIdx.x;
+  const int n = D.n, stride = L.nmax;
+  const int64_t N = A.ntot, off = D.off;
+  double *xs = (double *)(lds + L.off_x);
+  T *us = (T *)(lds + L.off_u);
+  uint16_t *nbr = (uint16_t *)(lds + L.off_nbr);
+  int *cnt = (int *)(lds + L.off_cnt);
+  int *cst = (int *)(lds + L.off_cst);
+  int *cat = (int *)(lds + L.off_cat);
+
+  __shared__ double red[NRED * 16];
+  __shared__ int lds_int[32];
+  __shared__ uint8_t tr_all[1024];
+  __shared__ double sh_XR[3], sh_VR[3], sh_FR[3], sh_clock[2];
+  __shared__ int64_t sh_step;
+  __shared__ int sh_flags, sh_rebuilds;
+
+  const int i = tid;
+  const bool own = i < n;
+  const int64_t a = off + i;
+  int tr = 0, role = ROLE_FIXED;
+  double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, ft[3] = {0, 0, 0}, rO[3] = {0, 0, 0}, xb[3] = {0, 0, 0},
+         cofs[3] = {0, 0, 0};
+  if (own) {
+    tr = A.tr[a];
+    role = tr >> 1;
+    tr_all[i] = (uint8_t)tr;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      x[k] = A.x[k * N + a]; v[k] = A.v[k * N + a]; ft[k] = A.ftot[k * N + a];
+      rO[k] = A.rO[k * N + a]; xb[k] = A.xb[k * N + a]; cofs[k] = A.cofs[k * N + a];
+    }
+  }
+  if (tid == 0) {
+    for (int k = 0; k < 3; ++k) { sh_XR[k] = stg->XR[k]; sh_VR[k] = stg->VR[k]; sh_FR[k] = stg->FR[k]; }
+    sh_clock[0] = stg->t_md; sh_clock[1] = stg->t_hyper;
+    sh_step = stg->step;
+    sh_flags = stg->flags;
+    sh_rebuilds = stg->n_rebuilds;
+  }
+  __syncthreads();
+  if (sh_flags & FLAG_UNSTABLE) return;
+
+  const bool compute_only = (mode & 1) != 0;
+  const int64_t iters = compute_only ? 1 : nsteps;
+  // the list lives in LDS only for this launch: rebuild at the start, from
+  // the recorded build positions unless an evaluation was requested
+  int rebuild_req = (compute_only || stg->rebuild == 1) ? 1 : 2;
+  int nn = 0;
+  Scal S;
+  double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, e_own = 0.0, fbv[3] = {0, 0, 0};
+
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t step = sh_step;
+    int moved = 0;
+    if (!compute_only) {
+      if (own && role == ROLE_MOBILE) {
+        double z[4];
+        normals4(D.seed, step, (uint32_t)i, 0u, z);
+        double d2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          double vv = v[k], xx = x[k];
+          vv = vv + D.hdt * ft[k] * D.inv_mass;
+          xx = xx + D.hdt * vv;
+          vv = D.c1 * vv + D.c2 * z[k];
+          xx = xx + D.hdt * vv;
+          x[k] = wrapx(xx, D.box[k], D.periodic[k]);
+          v[k] = vv;
+          const double dd = minimg(x[k] - xb[k], D.box[k], D.hbox[k], D.periodic[k]);
+          d2 += dd * dd;
+        }
+        if (d2 > D.skin_half2) moved = 1;
+      }
+      if (tid == 0 && D.n_rigid > 0) {
+        double z[4];
+        normals4(D.seed, step, (uint32_t)n, 0u, z);
+        for (int k = 0; k < DIM; ++k) {
+          double vv = sh_VR[k], xx = sh_XR[k];
+          vv = vv + D.hdt * sh_FR[k] * D.inv_massR;
+          xx = xx + D.hdt * vv;
+          vv = D.c1 * vv + D.c2R * z[k];
+          xx = xx + D.hdt * vv;
+          sh_XR[k] = xx;
+          sh_VR[k] = vv;
+        }
+      }
+      __syncthreads();
+    }
+    double u64[3] = {0, 0, 0};
+    if (own) {
+      if (role == ROLE_RIGID) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          x[k] = wrapx(sh_XR[k] + cofs[k], D.box[k], D.periodic[k]);
+          const double dd = minimg(x[k] - xb[k], D.box[k], D.hbox[k], D.periodic[k]);
+          d2 += dd * dd;
+        }
+        if (!compute_only && d2 > D.skin_half2) moved = 1;
+      }
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        if (role != ROLE_FIXED) u64[k] = minimg(x[k] - rO[k], D.box[k], D.hbox[k], D.periodic[k]);
+        xs[k * stride + i] = x[k];
+        us[k * stride + i] = (T)u64[k];
+      }
+    }
+    const int need = block_or(moved, lds_int + 24);
+    if (need || rebuild_req) {
+      // at a launch start the list is rebuilt from the recorded build
+      // positions, which reproduces the list of an uninterrupted run
+      const bool from_xb = !need && rebuild_req == 2;
+      double xsrc[3] = {0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) xsrc[k] = from_xb ? xb[k] : x[k];
+      if (from_xb) {
+        if (own)
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) xs[k * stride + i] = xb[k];
+        __syncthreads();
+      }
+      const int ov = lds_rebuild<DIM>(D, xs, nbr, cnt, cst, cat, tr_all, stride, lds_int, nn, xsrc, i, role);
+      if (own) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xb[k] = xsrc[k];
+      }
+      if (tid == 0) {
+        if (!from_xb) sh_rebuilds++;
+        if (ov) sh_flags |= FLAG_NBR_OVERFLOW;
+      }
+      if (from_xb) {
+        if (own)
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) xs[k * stride + i] = x[k];
+        __syncthreads();
+      }
+      rebuild_req = 0;
+    }
+    // ---- pair pass from LDS ------------------------------------------------
+    double sums[NRED];
+#pragma unroll
+    for (int q = 0; q < NRED; ++q) sums[q] = 0.0;
+    if (own) {
+      PairAcc<T> acc;
+      acc.init();
+      const int ti = tr & 1;
+      T ui[3];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) ui[k] = (T)u64[k];
+      for (int q = 0; q < nn; ++q) {
+        const int ent = nbr[q * stride + i];
+        const int j = ent >> 1, tj = ent & 1;
+        double dx[3];
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          dx[k] = minimg(x[k] - xs[k * stride + j], D.box[k], D.hbox[k], D.periodic[k]);
+          r2 = __dadd_rn(r2, __dmul_rn(dx[k], dx[k]));
+        }
+        if (!(r2 < D.rc2)) continue;
+        const int tt = ti * 2 + tj;
+        if constexpr (sizeof(T) == 8) {
+          const double eps = D.eps[tt];
+          const double r2i = 1.0 / r2;
+          const double sr2 = D.sig2[tt] * r2i;
+          const double sr6 = sr2 * sr2 * sr2;
+          const double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
+          const double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
+          const double e = 4.0 * eps * (sr6 * sr6 - sr6) - D.shift[tt];
+          double w[3], Dw = 0.0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) { w[k] = ui[k] - us[k * stride + j]; Dw += dx[k] * w[k]; }
+          const double CDw = C * Dw;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) { acc.F[k] += f * dx[k]; acc.H[k] += CDw * dx[k] - f * w[k]; }
+          acc.e += 0.5 * e;
+        } else {
+          const float eps = D.eps_f[tt];
+          const float r2i = rcp_nr((float)r2);
+          const float sr2 = D.sig2_f[tt] * r2i;
+          const float sr6 = sr2 * sr2 * sr2;
+          const float epsr = eps * r2i * sr6;
+          const float f = epsr * (48.0f * sr6 - 24.0f);
+          const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
+          const float e = 4.0f * eps * sr6 * (sr6 - 1.0f) - D.shift_f[tt];
+          float d[3], w[3], Dw = 0.0f;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            d[k] = (float)dx[k];
+            w[k] = ui[k] - us[k * stride + j];
+            Dw = __builtin_fmaf(d[k], w[k], Dw);
+          }
+          const float CDw = C * Dw;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            acc.F[k].add(f * d[k]);
+            acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
+          }
+          acc.e.add(0.5f * e);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        if constexpr (sizeof(T) == 8) { F[k] = acc.F[k]; H[k] = acc.H[k]; }
+        else { F[k] = acc.F[k].get(); H[k] = acc.H[k].get(); }
+      }
+      if constexpr (sizeof(T) == 8) e_own = acc.e; else e_own = acc.e.get();
+      sums[0] = e_own;
+      if (role != ROLE_FIXED) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) { sums[1] += u64[k] * u64[k]; sums[2] += F[k] * u64[k]; }
+      }
+      if (role == ROLE_RIGID) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) { sums[3 + k] = F[k]; sums[6 + k] = H[k]; sums[9 + k] = u64[k]; }
+      }
+    }
+    block_sum<NRED>(sums, red);
+    const int64_t estep = compute_only ? step : step + 1;
+    double XRl[3] = {sh_XR[0], sh_XR[1], sh_XR[2]};
+    eval_scalars(D, sums, XRl, estep, S);
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        double f = F[k], h = H[k], fb = 0.0;
+        if (role != ROLE_FIXED) {
+          if (role == ROLE_RIGID) { f += S.Fd[k] / (double)D.n_rigid; h += S.hud[k]; }
+          if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0)
+            fb = -S.dvp * ((h - f - S.g * u64[k] / S.d) / S.d);
+        }
+        F[k] = f;
+        H[k] = h;
+        fbv[k] = fb;
+        ft[k] = f + fb;
+        if (!compute_only && role == ROLE_MOBILE) v[k] = v[k] + D.hdt * ft[k] * D.inv_mass;
+      }
+    }
+    if (tid == 0) {
+      for (int k = 0; k < DIM; ++k) sh_FR[k] = sums[3 + k] + S.Fd[k] + S.sumFb[k];
+      if (!compute_only) {
+        for (int k = 0; k < DIM; ++k) sh_VR[k] = sh_VR[k] + D.hdt * sh_FR[k] * D.inv_massR;
+        sh_clock[0] += D.dt;
+        sh_clock[1] += D.dt * exp(S.dv / D.kT);
+        sh_step = step + 1;
+      }
+      if (!isfinite(S.e_pot)) sh_flags |= FLAG_UNSTABLE;
+    }
+    __syncthreads();
+    if (sh_flags & FLAG_UNSTABLE) break;
+  }
+  // ---- write back ----------------------------------------------------------
+  double ek[1] = {0.0};
+  if (own) {
+    T *u = (T *)A.u;
+    if (role == ROLE_RIGID) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) v[k] = sh_VR[k];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      A.x[k * N + a] = x[k]; A.v[k * N + a] = v[k]; A.ftot[k * N + a] = ft[k];
+      A.xb[k * N + a] = xb[k];
+      A.flj[k * N + a] = F[k]; A.hu[k * N + a] = H[k]; A.fb[k * N + a] = fbv[k];
+      u[k * N + a] = us[k * stride + i];
+    }
+    A.eatom[a] = e_own;
+    A.nnb[a] = nn;
+    if (role == ROLE_MOBILE)
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) ek[0] += 0.5 * D.mass * v[k] * v[k];
+  }
+  block_sum<1>(ek, red);
+  if (tid == 0) {
+    double ekr = 0.0;
+    for (int k = 0; k < DIM; ++k) ekr += 0.5 * D.massR * sh_VR[k] * sh_VR[k];
+    for (int k = 0; k < 3; ++k) { stg->XR[k] = sh_XR[k]; stg->VR[k] = sh_VR[k]; stg->FR[k] = sh_FR[k]; }
+    stg->t_md = sh_clock[0];
+    stg->t_hyper = sh_clock[1];
+    stg->step = sh_step;
+    stg->e_lj = S.e_lj; stg->v_drive = S.v_drive; stg->e_pot = S.e_pot;
+    stg->e_kin = ek[0] + (D.n_rigid > 0 ? ekr : 0.0);
+    stg->d = S.d; stg->g = S.g; stg->dv = S.dv; stg->dvp = S.dvp;
+    stg->x_slider = S.xs; stg->x_tip = S.x_tip; stg->f_lat = S.f_lat;
+    stg->flags = sh_flags;
+    stg->n_rebuilds = sh_rebuilds;
+    stg->rebuild = 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_small(const SysDesc *__restrict__ descs,
+                                                SysState *__restrict__ states, Arrays A,
+                                                const int32_t *__restrict__ sys_list, int64_t nsteps,
+                                                int mode, SmallLayout L2, SmallLayout L3) {
+  extern __shared__ __align__(16) char lds[];
+  const int s = sys_list[blockIdx.x];
+  const SysDesc &D = descs[s];
+  if (D.dim == 2) run_small<2, T>(D, states + s, A, nsteps, mode, lds, L2);
+  else run_small<3, T>(D, states + s, A, nsteps, mode, lds, L3);
+}
+
+hipError_t launch_small(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
+                        const int32_t *sys_list, int nsys, int block, int nmax, int maxnb2, int maxnb3,
+                        int cellmax, int64_t nsteps, int mode, hipStream_t stream) {
+  if (nsys <= 0) return hipSuccess;
+  const int ts = prec == 0 ? 8 : 4;
+  const SmallLayout L2 = small_layout(2, ts, nmax, maxnb2, cellmax);
+  const SmallLayout L3 = small_layout(3, ts, nmax, maxnb3, cellmax);
+  const size_t bytes = L2.bytes > L3.bytes ? L2.bytes : L3.bytes;
+  if (prec == 0) {
+    hipFuncSetAttribute((const void *)k_small<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(k_small<double>, dim3(nsys), dim3(block), bytes, stream, descs, states, A, sys_list,
+                       nsteps, mode, L2, L3);
+  } else {
+    hipFuncSetAttribute((const void *)k_small<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(k_small<float>, dim3(nsys), dim3(block), bytes, stream, descs, states, A, sys_list,
+                       nsteps, mode, L2, L3);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hdk

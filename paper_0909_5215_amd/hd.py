@@ -68,7 +68,7 @@ _P = _c.c_void_p
 _SIGS = {
     "hd_create": (_c.c_int, [_c.c_int, _c.c_int, _c.c_void_p, _c.POINTER(_c.c_void_p)]),
     "hd_set_exec": (_c.c_int, [_P, _c.c_int]),
-    "hd_set_launch": (_c.c_int, [_P, _c.c_int32, _c.c_int32]),
+    "hd_set_launch": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int32]),
     "hd_add_system": (_c.c_int, [_P, _c.POINTER(hd_system_desc), _c.POINTER(hd_lj_params),
                                  _c.POINTER(hd_thermo_params), _c.POINTER(hd_drive_params),
                                  _c.POINTER(_c.c_int32)]),
@@ -140,7 +140,8 @@ class Context:
     """One hd_ctx: a batch of AFM model instances on one GPU."""
 
     def __init__(self, precision: int = HD_FP32C, device: int = 0, stream=None,
-                 exec_mode: int = HD_EXEC_BATCHED, block_threads: int = 0, max_neighbors: int = 0):
+                 exec_mode: int = HD_EXEC_BATCHED, block_threads: int = 0, max_neighbors: int = 0,
+                 lds_resident: bool = True):
         L = load()
         h = ctypes.c_void_p()
         st = L.hd_create(int(precision), int(device), stream, ctypes.byref(h))
@@ -151,7 +152,8 @@ class Context:
         self.dims: List[int] = []
         self.sizes: List[int] = []
         _check(h, L.hd_set_exec(h, int(exec_mode)), "hd_set_exec")
-        _check(h, L.hd_set_launch(h, int(block_threads), int(max_neighbors)), "hd_set_launch")
+        _check(h, L.hd_set_launch(h, int(block_threads), int(max_neighbors), int(bool(lds_resident))),
+               "hd_set_launch")
 
     @property
     def handle(self):
@@ -306,9 +308,9 @@ class Context:
 
 def make_context(specs: Sequence, precision: int = HD_FP32C, exec_mode: int = HD_EXEC_BATCHED,
                  init_velocities: bool = True, block_threads: int = 0, stream=None,
-                 max_neighbors: int = 0) -> Context:
+                 max_neighbors: int = 0, lds_resident: bool = True) -> Context:
     """Context holding every spec, finalized, with Maxwell-Boltzmann velocities."""
-    ctx = Context(precision, 0, stream, exec_mode, block_threads, max_neighbors)
+    ctx = Context(precision, 0, stream, exec_mode, block_threads, max_neighbors, lds_resident)
     for sp in specs:
         s = ctx.add_system(sp)
         if init_velocities:

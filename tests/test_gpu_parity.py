@@ -195,20 +195,51 @@ def test_mixed_uneven_batch(hd, oracle_mod):
         assert abs(ctx.scalars(k)["dv"] - ref["dv"]) <= 1e-6 * s.dv_max
 
 
-def test_fp64_determinism_and_checkpoint(hd, oracle_mod):
+@pytest.mark.parametrize("lds", [True, False])
+def test_fp64_determinism_and_checkpoint(hd, oracle_mod, lds):
+    """Chunked runs equal one long run bit for bit, and a checkpoint restored
+    into a fresh context continues bit-identically."""
     spec = biased(oracle_mod, snapshot_2d(seed=31))
-    a = hd.make_context([spec], precision=hd.HD_FP64)
+    a = hd.make_context([spec], precision=hd.HD_FP64, lds_resident=lds)
     a.step(30)
     blob = a.get_state(0)
     a.step(40)
-    b = hd.make_context([spec], precision=hd.HD_FP64)
+    b = hd.make_context([spec], precision=hd.HD_FP64, lds_resident=lds)
     b.step(70)
     np.testing.assert_array_equal(a.positions(0), b.positions(0))
     np.testing.assert_array_equal(a.velocities(0), b.velocities(0))
-    c = hd.make_context([spec], precision=hd.HD_FP64)
+    c = hd.make_context([spec], precision=hd.HD_FP64, lds_resident=lds)
     c.set_state(0, blob)
     c.step(40)
     np.testing.assert_array_equal(c.positions(0), a.positions(0))
     np.testing.assert_array_equal(c.velocities(0), a.velocities(0))
     assert c.scalars(0)["t_hyper"] == a.scalars(0)["t_hyper"]
     assert c.scalars(0)["step"] == 70
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lds_resident_matches_global_kernel(hd, oracle_mod, precision):
+    """The LDS-resident kernel and the global-memory kernel follow the same
+    trajectory (same arithmetic, different memory); both match the oracle."""
+    specs = [biased(oracle_mod, snapshot_2d(seed=40 + k, x_slider=k * A2D / 3)) for k in range(3)]
+    a = hd.make_context(specs, precision=precision, lds_resident=True)
+    b = hd.make_context(specs, precision=precision, lds_resident=False)
+    for ctx in (a, b):
+        ctx.step(60)
+    for k in range(3):
+        dx = a.positions(k) - b.positions(k)
+        dx[0] -= specs[k].box[0] * np.round(dx[0] / specs[k].box[0])
+        assert np.abs(dx).max() < (1e-11 if precision == 0 else 1e-7)
+        sa, sb = a.scalars(k), b.scalars(k)
+        assert sa["step"] == sb["step"] == 60
+        assert sa["t_hyper"] == pytest.approx(sb["t_hyper"], rel=1e-9 if precision == 0 else 1e-5)
+    # an evaluation through the LDS-resident kernel against the oracle
+    ref = oracle_mod.OracleSystem(specs[1]).compute()
+    c = hd.make_context([specs[1]], precision=precision, lds_resident=True, init_velocities=False)
+    tol = 1e-11 if precision == 0 else 1e-5
+    assert rel(c.forces(0), ref["f_tot"]) <= tol
+    assert rel(c.forces(0, hd.HD_HU), ref["hu"]) <= tol
+    assert abs(c.scalars(0)["dv"] - ref["dv"]) <= (1e-11 if precision == 0 else 1e-6) * specs[1].dv_max
+    pairs = set(map(tuple, c.debug_pairs(0).tolist()))
+    refp = set(map(tuple, oracle_mod.pairs_brute(specs[1], specs[1].pos, 2.8).tolist()))
+    assert pairs == refp
