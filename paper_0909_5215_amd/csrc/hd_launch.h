@@ -19,7 +19,7 @@ hipError_t launch_batched(int prec, const SysDesc *descs, SysState *states, cons
 // cellmax >= every listed ncell.
 hipError_t launch_small(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
                         const int32_t *sys_list, int nsys, int block, int nmax, int maxnb2, int maxnb3,
-                        int cellmax, int64_t nsteps, int mode, hipStream_t stream);
+                        int cellmax, int dims_mask, int64_t nsteps, int mode, hipStream_t stream);
 size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax);
 
 // Tiles of the grid scheduler: each tile is a contiguous atom range of one

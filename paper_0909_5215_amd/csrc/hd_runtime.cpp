@@ -87,7 +87,7 @@ struct hd_ctx {
   // batched scheduler: systems resident in LDS vs in global memory
   std::vector<int32_t> small_ids, big_ids;
   int32_t *d_small = nullptr, *d_big = nullptr;
-  int small_block = 64, small_nmax = 0, small_cellmax = 1;
+  int small_block = 64, small_nmax = 0, small_cellmax = 1, small_dims = 0;
   int maxnb2 = 32, maxnb3 = 128;
   size_t lds_limit = 0;
   hipStream_t stream2 = nullptr;
@@ -355,7 +355,7 @@ hd_status launch_batched_all(hd_ctx *ctx, int64_t nsteps, int mode, int64_t *lau
   if (!ctx->small_ids.empty()) {
     HIPCHK(hdk::launch_small(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_small, (int)ctx->small_ids.size(),
                              ctx->small_block, ctx->small_nmax, ctx->maxnb2, ctx->maxnb3, ctx->small_cellmax,
-                             nsteps, mode, ctx->stream));
+                             ctx->small_dims, nsteps, mode, ctx->stream));
     if (launches) ++*launches;
   }
   if (!ctx->big_ids.empty()) {
@@ -648,6 +648,8 @@ hd_status hd_finalize(hd_ctx *ctx) {
       else ctx->big_ids.push_back(s);
     }
     std::sort(ctx->small_ids.begin(), ctx->small_ids.end());
+    ctx->small_dims = 0;
+    for (int q : ctx->small_ids) ctx->small_dims |= (ctx->sys[q].dim == 2 ? 1 : 2);
     std::sort(ctx->big_ids.begin(), ctx->big_ids.end());
     ctx->small_nmax = nmax;
     ctx->small_cellmax = cellmax;

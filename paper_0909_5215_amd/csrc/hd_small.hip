@@ -441,18 +441,23 @@ __global__ __launch_bounds__(1024) void k_small(const SysDesc *__restrict__ desc
 
 hipError_t launch_small(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
                         const int32_t *sys_list, int nsys, int block, int nmax, int maxnb2, int maxnb3,
-                        int cellmax, int64_t nsteps, int mode, hipStream_t stream) {
+                        int cellmax, int dims_mask, int64_t nsteps, int mode, hipStream_t stream) {
   if (nsys <= 0) return hipSuccess;
   const int ts = prec == 0 ? 8 : 4;
   const SmallLayout L2 = small_layout(2, ts, nmax, maxnb2, cellmax);
   const SmallLayout L3 = small_layout(3, ts, nmax, maxnb3, cellmax);
-  const size_t bytes = L2.bytes > L3.bytes ? L2.bytes : L3.bytes;
+  size_t bytes = 16;
+  if ((dims_mask & 1) && L2.bytes > bytes) bytes = L2.bytes;
+  if ((dims_mask & 2) && L3.bytes > bytes) bytes = L3.bytes;
+  hipError_t e;
   if (prec == 0) {
-    hipFuncSetAttribute((const void *)k_small<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    e = hipFuncSetAttribute((const void *)k_small<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_small<double>, dim3(nsys), dim3(block), bytes, stream, descs, states, A, sys_list,
                        nsteps, mode, L2, L3);
   } else {
-    hipFuncSetAttribute((const void *)k_small<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    e = hipFuncSetAttribute((const void *)k_small<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_small<float>, dim3(nsys), dim3(block), bytes, stream, descs, states, A, sys_list,
                        nsteps, mode, L2, L3);
   }
