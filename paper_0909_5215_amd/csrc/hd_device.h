@@ -136,13 +136,15 @@ struct Scal {
   double sumFb[3];   // bias force summed over rigid atoms
 };
 
+template <int DIM>
 __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums[NRED],
                                              const double XR[3], int64_t step, Scal &S) {
-  const int dim = D.dim;
+  constexpr int dim = DIM;
   S.xs = D.x_slider + D.v_slider * ((double)step * D.dt);
   S.e_lj = sums[0];
   S.v_drive = 0.0; S.x_tip = 0.0; S.f_lat = 0.0;
   double G = sums[2];
+#pragma unroll
   for (int k = 0; k < 3; ++k) { S.Fd[k] = 0.0; S.hud[k] = 0.0; S.sumFb[k] = 0.0; }
   if (D.n_rigid > 0) {
     const int perp = dim - 1;
@@ -159,9 +161,11 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
     }
     S.v_drive += D.f_normal * (XR[perp] - D.XR0[perp]);
     S.Fd[perp] += -D.f_normal;
-    const int nspring = dim == 3 ? 2 : 1;
+    constexpr int nspring = dim == 3 ? 2 : 1;
+#pragma unroll
     for (int k = 0; k < nspring; ++k) S.hud[k] = D.k_spring / (nR * nR) * sums[9 + k];
     // drive share of each rigid atom enters F.u
+#pragma unroll
     for (int k = 0; k < dim; ++k) G += (S.Fd[k] / nR) * sums[9 + k];
   }
   S.e_pot = S.e_lj + S.v_drive;
@@ -171,6 +175,7 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
   if (D.bias_on) bias_switch(D, S.g, S.dv, S.dvp);
   if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0 && D.n_rigid > 0) {
     const double nR = (double)D.n_rigid;
+#pragma unroll
     for (int k = 0; k < dim; ++k) {
       const double sumHu = sums[6 + k] + nR * S.hud[k];
       const double sumF = sums[3 + k] + S.Fd[k];

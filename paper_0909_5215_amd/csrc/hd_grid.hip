@@ -348,7 +348,7 @@ __device__ void pairs_tile(const SysDesc &D, SysState &st, const Arrays &A, cons
     }
     const int64_t estep = compute_only ? st.step : st.step + 1;
     Scal S;
-    eval_scalars(D, tot, XRn, estep, S);
+    eval_scalars<DIM>(D, tot, XRn, estep, S);
     double FR[3] = {0, 0, 0};
     for (int k = 0; k < DIM; ++k) FR[k] = tot[3 + k] + S.Fd[k] + S.sumFb[k];
     if (!compute_only) {

@@ -181,6 +181,7 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
   __shared__ double sh_clock[2];
   __shared__ int64_t sh_step;
   __shared__ int sh_flags, sh_rebuilds;
+  __shared__ Scal sh_out;
 
   if (tid == 0) {
     for (int k = 0; k < 3; ++k) { sh_XR[k] = stg->XR[k]; sh_VR[k] = stg->VR[k]; sh_FR[k] = stg->FR[k]; }
@@ -197,7 +198,6 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
   // list requests: 1 = rebuild from the current positions, 2 = rebuild from
   // the recorded build positions (checkpoint restore); evaluations rebuild
   int rebuild_req = compute_only ? 1 : stg->rebuild;
-  Scal S;
 
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t step = sh_step;
@@ -314,7 +314,8 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
     block_sum<NRED>(sums, red);
     const int64_t estep = compute_only ? step : step + 1;
     double XRl[3] = {sh_XR[0], sh_XR[1], sh_XR[2]};
-    eval_scalars(D, sums, XRl, estep, S);
+    Scal S;
+    eval_scalars<DIM>(D, sums, XRl, estep, S);
     // ---- bias force, total force, final B --------------------------------
     for (int i = tid; i < n; i += B) {
       const int64_t a = off + i;
@@ -349,10 +350,12 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
         sh_step = step + 1;
       }
       if (!isfinite(S.e_pot)) sh_flags |= FLAG_UNSTABLE;
+      sh_out = S;
     }
     __syncthreads();
     if (sh_flags & FLAG_UNSTABLE) break;
   }
+  const Scal &S = sh_out;
   // ---- write back: rigid atom velocities, kinetic energy, scalars ----------
   double ek[1] = {0.0};
   for (int i = tid; i < n; i += B) {
@@ -384,15 +387,15 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_batched(const SysDesc *__restrict__ descs,
-                                                  SysState *__restrict__ states, Arrays A,
-                                                  const int32_t *__restrict__ sys_list,
-                                                  int64_t nsteps, int mode) {
+// MODE 0: nsteps BAOAB steps; MODE 1: one evaluation (own instantiation).
+// One instantiation per dimension and workgroup size.
+template <typename T, int DIM, int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batched(const SysDesc *__restrict__ descs,
+                                                   SysState *__restrict__ states, Arrays A,
+                                                   const int32_t *__restrict__ sys_list,
+                                                   int64_t nsteps) {
   const int s = sys_list[blockIdx.x];
-  const SysDesc &D = descs[s];
-  if (D.dim == 2) run_system<2, T>(D, states + s, A, nsteps, mode);
-  else run_system<3, T>(D, states + s, A, nsteps, mode);
+  run_system<DIM, T>(descs[s], states + s, A, nsteps, MODE);
 }
 
 // Maxwell-Boltzmann velocities v = sqrt(kT/m) z, Philox tag 1 at step 0; the
@@ -429,17 +432,30 @@ hipError_t launch_init_velocities(const SysDesc *descs, SysState *states, const 
   return hipGetLastError();
 }
 
-hipError_t launch_batched(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
+template <typename T, int DIM>
+static hipError_t launch_batched_d(const SysDesc *descs, SysState *states, const Arrays &A,
+                                   const int32_t *sys_list, int nsys, int block, int64_t nsteps, int mode,
+                                   hipStream_t stream) {
+  if (mode)
+    hipLaunchKernelGGL((k_batched<T, DIM, 1, 1024>), dim3(nsys), dim3(1024), 0, stream, descs, states, A, sys_list, nsteps);
+  else if (block <= 256)
+    hipLaunchKernelGGL((k_batched<T, DIM, 0, 256>), dim3(nsys), dim3(256), 0, stream, descs, states, A, sys_list, nsteps);
+  else if (block <= 512)
+    hipLaunchKernelGGL((k_batched<T, DIM, 0, 512>), dim3(nsys), dim3(512), 0, stream, descs, states, A, sys_list, nsteps);
+  else
+    hipLaunchKernelGGL((k_batched<T, DIM, 0, 1024>), dim3(nsys), dim3(1024), 0, stream, descs, states, A, sys_list, nsteps);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
                           const int32_t *sys_list, int nsys, int block, int64_t nsteps, int mode,
                           hipStream_t stream) {
   if (nsys <= 0) return hipSuccess;
   if (prec == 0)
-    hipLaunchKernelGGL(k_batched<double>, dim3(nsys), dim3(block), 0, stream, descs, states, A,
-                       sys_list, nsteps, mode);
-  else
-    hipLaunchKernelGGL(k_batched<float>, dim3(nsys), dim3(block), 0, stream, descs, states, A,
-                       sys_list, nsteps, mode);
-  return hipGetLastError();
+    return dim == 2 ? launch_batched_d<double, 2>(descs, states, A, sys_list, nsys, block, nsteps, mode, stream)
+                    : launch_batched_d<double, 3>(descs, states, A, sys_list, nsys, block, nsteps, mode, stream);
+  return dim == 2 ? launch_batched_d<float, 2>(descs, states, A, sys_list, nsys, block, nsteps, mode, stream)
+                  : launch_batched_d<float, 3>(descs, states, A, sys_list, nsys, block, nsteps, mode, stream);
 }
 
 }  // namespace hdk

@@ -6,20 +6,21 @@
 
 namespace hdk {
 
-// One workgroup of `block` threads per listed system; nsteps BAOAB steps
-// (mode bit 0: evaluate only).  prec 0 = float64, 1 = float32 compensated.
-hipError_t launch_batched(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
+// One workgroup of `block` threads (256, 512 or 1024) per listed system, all
+// of dimension `dim`; nsteps BAOAB steps (mode 1: evaluate only, 1024
+// threads).  prec 0 = float64, 1 = float32 compensated.
+hipError_t launch_batched(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
                           const int32_t *sys_list, int nsys, int block, int64_t nsteps, int mode,
                           hipStream_t stream);
 
 // LDS-resident variant for systems of at most 1024 atoms whose positions,
 // displacements, cell list and neighbour list fit in one workgroup's LDS.
-// block >= the largest listed system; nmax is the LDS row stride (>= every
-// listed n); maxnb2 / maxnb3 are the neighbour capacities of 2D / 3D systems;
-// cellmax >= every listed ncell.
-hipError_t launch_small(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
-                        const int32_t *sys_list, int nsys, int block, int nmax, int maxnb2, int maxnb3,
-                        int cellmax, int dims_mask, int64_t nsteps, int mode, hipStream_t stream);
+// All listed systems have dimension `dim`; nmax (<= 1024) is the LDS row
+// stride and bounds every listed n; maxnb is their neighbour capacity;
+// cellmax bounds every listed ncell.
+hipError_t launch_small(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
+                        const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax,
+                        int64_t nsteps, int mode, hipStream_t stream);
 size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax);
 
 // Tiles of the grid scheduler: each tile is a contiguous atom range of one

@@ -84,10 +84,17 @@ struct hd_ctx {
   SysDesc *d_desc = nullptr;
   SysState *d_state = nullptr;
   int32_t *d_all = nullptr;
-  // batched scheduler: systems resident in LDS vs in global memory
+  // batched scheduler: groups of systems of one dimension, resident in LDS
+  // (small) or in global memory
+  struct Group {
+    int dim = 2;
+    bool small = false;
+    std::vector<int32_t> ids;
+    int32_t *d_ids = nullptr;
+    int nmax = 0, cellmax = 1, maxnb = 32;
+  };
+  std::vector<Group> groups;
   std::vector<int32_t> small_ids, big_ids;
-  int32_t *d_small = nullptr, *d_big = nullptr;
-  int small_block = 64, small_nmax = 0, small_cellmax = 1, small_dims = 0;
   int maxnb2 = 32, maxnb3 = 128;
   size_t lds_limit = 0;
   hipStream_t stream2 = nullptr;
@@ -343,8 +350,9 @@ hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps) {
   return HD_OK;
 }
 
-// One batched launch of every system: LDS-resident systems on the context
-// stream, the others concurrently on a second stream, joined by events.
+// One batched launch of every system: LDS-resident groups on the context
+// stream, global-memory groups concurrently on a second stream, joined by
+// events.
 hd_status launch_batched_all(hd_ctx *ctx, int64_t nsteps, int mode, int64_t *launches) {
   const int prec = ctx->prec == HD_FP64 ? 0 : 1;
   const bool both = !ctx->small_ids.empty() && !ctx->big_ids.empty();
@@ -352,15 +360,15 @@ hd_status launch_batched_all(hd_ctx *ctx, int64_t nsteps, int mode, int64_t *lau
     HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
     HIPCHK(hipStreamWaitEvent(ctx->stream2, ctx->fork, 0));
   }
-  if (!ctx->small_ids.empty()) {
-    HIPCHK(hdk::launch_small(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_small, (int)ctx->small_ids.size(),
-                             ctx->small_block, ctx->small_nmax, ctx->maxnb2, ctx->maxnb3, ctx->small_cellmax,
-                             ctx->small_dims, nsteps, mode, ctx->stream));
-    if (launches) ++*launches;
-  }
-  if (!ctx->big_ids.empty()) {
-    HIPCHK(hdk::launch_batched(prec, ctx->d_desc, ctx->d_state, ctx->A, ctx->d_big, (int)ctx->big_ids.size(),
-                               ctx->block, nsteps, mode, both ? ctx->stream2 : ctx->stream));
+  for (auto &G : ctx->groups) {
+    if (G.ids.empty()) continue;
+    if (G.small) {
+      HIPCHK(hdk::launch_small(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
+                               G.nmax, G.maxnb, G.cellmax, nsteps, mode, ctx->stream));
+    } else {
+      HIPCHK(hdk::launch_batched(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
+                                 ctx->block, nsteps, mode, both ? ctx->stream2 : ctx->stream));
+    }
     if (launches) ++*launches;
   }
   if (both) {
@@ -621,11 +629,11 @@ hd_status hd_finalize(hd_ctx *ctx) {
   ctx->maxnb3 = ctx->max_nb > 0 ? ctx->max_nb : 128;
   ctx->small_ids.clear();
   ctx->big_ids.clear();
+  ctx->groups.clear();
   if (ctx->exec == HD_EXEC_BATCHED) {
     const int prec = ctx->prec == HD_FP64 ? 0 : 1;
     const size_t budget = ctx->lds_limit > 8192 ? ctx->lds_limit - 8192 : 0;  // static LDS of the kernel
     std::vector<int> cand;
-    int nmax = 0, cellmax = 1;
     for (int s = 0; s < S; ++s) {
       const SysHost &h = ctx->sys[s];
       const int maxnb = h.dim == 2 ? ctx->maxnb2 : ctx->maxnb3;
@@ -635,40 +643,48 @@ hd_status hd_finalize(hd_ctx *ctx) {
       if (ok) cand.push_back(s);
       else ctx->big_ids.push_back(s);
     }
-    // admit candidates while the common layout (largest n and cell count) fits
+    // admit candidates (by size) while the group's common layout fits
     std::sort(cand.begin(), cand.end(), [&](int a, int b) { return ctx->sys[a].n < ctx->sys[b].n; });
+    int gn[2] = {0, 0}, gc[2] = {1, 1};
+    std::vector<int32_t> sm[2];
     for (int s : cand) {
-      const int n2 = std::max(nmax, ctx->sys[s].n), c2 = std::max(cellmax, ctx->h_desc[s].ncell);
-      const size_t b2 = hdk::small_lds_bytes(2, prec, n2, ctx->maxnb2, c2);
-      const size_t b3 = hdk::small_lds_bytes(3, prec, n2, ctx->maxnb3, c2);
-      bool has3 = ctx->sys[s].dim == 3;
-      for (int q : ctx->small_ids) has3 = has3 || ctx->sys[q].dim == 3;
-      const size_t need = has3 ? std::max(b2, b3) : b2;
-      if (need <= budget) { ctx->small_ids.push_back(s); nmax = n2; cellmax = c2; }
-      else ctx->big_ids.push_back(s);
+      const int d = ctx->sys[s].dim - 2;
+      const int maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
+      const int n2 = std::max(gn[d], ctx->sys[s].n), c2 = std::max(gc[d], ctx->h_desc[s].ncell);
+      if (hdk::small_lds_bytes(d + 2, prec, n2, maxnb, c2) <= budget) {
+        sm[d].push_back(s); gn[d] = n2; gc[d] = c2;
+      } else {
+        ctx->big_ids.push_back(s);
+      }
     }
-    std::sort(ctx->small_ids.begin(), ctx->small_ids.end());
-    ctx->small_dims = 0;
-    for (int q : ctx->small_ids) ctx->small_dims |= (ctx->sys[q].dim == 2 ? 1 : 2);
+    for (int d = 0; d < 2; ++d) {
+      std::sort(sm[d].begin(), sm[d].end());
+      for (int s : sm[d]) ctx->small_ids.push_back(s);
+      if (sm[d].empty()) continue;
+      hd_ctx::Group G;
+      G.dim = d + 2; G.small = true; G.ids = sm[d]; G.nmax = gn[d]; G.cellmax = gc[d];
+      G.maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
+      ctx->groups.push_back(G);
+    }
     std::sort(ctx->big_ids.begin(), ctx->big_ids.end());
-    ctx->small_nmax = nmax;
-    ctx->small_cellmax = cellmax;
-    ctx->small_block = std::max(64, (nmax + 63) / 64 * 64);
+    for (int d = 0; d < 2; ++d) {
+      hd_ctx::Group G;
+      G.dim = d + 2;
+      for (int s : ctx->big_ids) if (ctx->sys[s].dim == d + 2) G.ids.push_back(s);
+      if (!G.ids.empty()) ctx->groups.push_back(G);
+    }
   }
   // block size of the global-memory batched kernel / grid tiles
   int maxn = 0;
   for (int s : ctx->big_ids) maxn = std::max(maxn, ctx->sys[s].n);
   if (ctx->block_threads > 0) ctx->block = ctx->block_threads;
-  else if (ctx->exec == HD_EXEC_BATCHED) ctx->block = maxn <= 256 ? 256 : (maxn <= 512 ? 512 : 1024);
+  else if (ctx->exec == HD_EXEC_BATCHED) ctx->block = maxn <= 256 ? 256 : 512;
   else ctx->block = 256;
-  ALLOC(ctx->d_small, ctx->small_ids.size());
-  ALLOC(ctx->d_big, ctx->big_ids.size());
-  if (!ctx->small_ids.empty())
-    HIPCHK(hipMemcpyAsync(ctx->d_small, ctx->small_ids.data(), ctx->small_ids.size() * sizeof(int32_t),
-                          hipMemcpyHostToDevice, ctx->stream));
-  if (!ctx->big_ids.empty())
-    HIPCHK(hipMemcpyAsync(ctx->d_big, ctx->big_ids.data(), ctx->big_ids.size() * sizeof(int32_t),
-                          hipMemcpyHostToDevice, ctx->stream));
+  for (auto &G : ctx->groups) {
+    ALLOC(G.d_ids, G.ids.size());
+    HIPCHK(hipMemcpyAsync(G.d_ids, G.ids.data(), G.ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+  }
   // host staging
   std::vector<double> x(3 * N, 0.0), rO(3 * N, 0.0), cofs(3 * N, 0.0), v(3 * N, 0.0);
   std::vector<uint8_t> tr(N);

@@ -153,6 +153,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   __shared__ double sh_XR[3], sh_VR[3], sh_FR[3], sh_clock[2];
   __shared__ int64_t sh_step;
   __shared__ int sh_flags, sh_rebuilds;
+  __shared__ Scal sh_out;
 
   const int i = tid;
   const bool own = i < n;
@@ -186,7 +187,6 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   // the recorded build positions unless an evaluation was requested
   int rebuild_req = (compute_only || stg->rebuild == 1) ? 1 : 2;
   int nn = 0;
-  Scal S;
   double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, e_own = 0.0, fbv[3] = {0, 0, 0};
 
   for (int64_t it = 0; it < iters; ++it) {
@@ -358,7 +358,8 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     block_sum<NRED>(sums, red);
     const int64_t estep = compute_only ? step : step + 1;
     double XRl[3] = {sh_XR[0], sh_XR[1], sh_XR[2]};
-    eval_scalars(D, sums, XRl, estep, S);
+    Scal S;
+    eval_scalars<DIM>(D, sums, XRl, estep, S);
     if (own) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
@@ -384,10 +385,12 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         sh_step = step + 1;
       }
       if (!isfinite(S.e_pot)) sh_flags |= FLAG_UNSTABLE;
+      sh_out = S;
     }
     __syncthreads();
     if (sh_flags & FLAG_UNSTABLE) break;
   }
+  const Scal &S = sh_out;
   // ---- write back ----------------------------------------------------------
   double ek[1] = {0.0};
   if (own) {
@@ -427,41 +430,54 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_small(const SysDesc *__restrict__ descs,
-                                                SysState *__restrict__ states, Arrays A,
-                                                const int32_t *__restrict__ sys_list, int64_t nsteps,
-                                                int mode, SmallLayout L2, SmallLayout L3) {
+// MODE 0: nsteps BAOAB steps; MODE 1: one evaluation at the current
+// positions (separate instantiation so the two never share a profile row).
+// One instantiation per dimension and workgroup size, so that the register
+// budget follows the launch size.
+template <typename T, int DIM, int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_small(const SysDesc *__restrict__ descs,
+                                                 SysState *__restrict__ states, Arrays A,
+                                                 const int32_t *__restrict__ sys_list, int64_t nsteps,
+                                                 SmallLayout L) {
   extern __shared__ __align__(16) char lds[];
   const int s = sys_list[blockIdx.x];
-  const SysDesc &D = descs[s];
-  if (D.dim == 2) run_small<2, T>(D, states + s, A, nsteps, mode, lds, L2);
-  else run_small<3, T>(D, states + s, A, nsteps, mode, lds, L3);
+  run_small<DIM, T>(descs[s], states + s, A, nsteps, MODE, lds, L);
 }
 
-hipError_t launch_small(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
-                        const int32_t *sys_list, int nsys, int block, int nmax, int maxnb2, int maxnb3,
-                        int cellmax, int dims_mask, int64_t nsteps, int mode, hipStream_t stream) {
-  if (nsys <= 0) return hipSuccess;
-  const int ts = prec == 0 ? 8 : 4;
-  const SmallLayout L2 = small_layout(2, ts, nmax, maxnb2, cellmax);
-  const SmallLayout L3 = small_layout(3, ts, nmax, maxnb3, cellmax);
-  size_t bytes = 16;
-  if ((dims_mask & 1) && L2.bytes > bytes) bytes = L2.bytes;
-  if ((dims_mask & 2) && L3.bytes > bytes) bytes = L3.bytes;
-  hipError_t e;
-  if (prec == 0) {
-    e = hipFuncSetAttribute((const void *)k_small<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_small<double>, dim3(nsys), dim3(block), bytes, stream, descs, states, A, sys_list,
-                       nsteps, mode, L2, L3);
-  } else {
-    e = hipFuncSetAttribute((const void *)k_small<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_small<float>, dim3(nsys), dim3(block), bytes, stream, descs, states, A, sys_list,
-                       nsteps, mode, L2, L3);
-  }
+template <typename T, int DIM, int MODE, int BLOCK>
+static hipError_t launch_small_t(const SysDesc *descs, SysState *states, const Arrays &A,
+                                 const int32_t *sys_list, int nsys, size_t bytes, int64_t nsteps,
+                                 SmallLayout L, hipStream_t stream) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_small<T, DIM, MODE, BLOCK>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_small<T, DIM, MODE, BLOCK>), dim3(nsys), dim3(BLOCK), bytes, stream, descs, states, A,
+                     sys_list, nsteps, L);
   return hipGetLastError();
+}
+
+template <typename T, int DIM>
+static hipError_t launch_small_d(const SysDesc *descs, SysState *states, const Arrays &A,
+                                 const int32_t *sys_list, int nsys, int block, size_t bytes, int64_t nsteps,
+                                 int mode, SmallLayout L, hipStream_t stream) {
+  if (mode) return launch_small_t<T, DIM, 1, 1024>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  if (block <= 256) return launch_small_t<T, DIM, 0, 256>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  if (block <= 512) return launch_small_t<T, DIM, 0, 512>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  return launch_small_t<T, DIM, 0, 1024>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+}
+
+hipError_t launch_small(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
+                        const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax,
+                        int64_t nsteps, int mode, hipStream_t stream) {
+  if (nsys <= 0) return hipSuccess;
+  if (nmax > 1024) return hipErrorInvalidValue;
+  const SmallLayout L = small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax);
+  const int block = nmax <= 256 ? 256 : (nmax <= 512 ? 512 : 1024);
+  if (prec == 0)
+    return dim == 2 ? launch_small_d<double, 2>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream)
+                    : launch_small_d<double, 3>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream);
+  return dim == 2 ? launch_small_d<float, 2>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream)
+                  : launch_small_d<float, 3>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream);
 }
 
 }  // namespace hdk
