@@ -227,6 +227,78 @@ __device__ __forceinline__ float rcp_nr(float x) {
   return __builtin_fmaf(r, e, r);
 }
 
+// One neighbour's contribution to F_i, (H u)_i and the half pair energy.
+// dx = x_i - x_j (float64, minimum image), r2 its exactly rounded square
+// norm.  The term is evaluated branch-free; a neighbour that is not `live`
+// (outside rc) contributes exactly zero.
+template <int DIM, typename T>
+__device__ __forceinline__ void pair_term(const SysDesc &D, int tt, bool live, const double dx[3], double r2,
+                                          const T ui[3], const T uj[3], PairAcc<T> &acc) {
+  if constexpr (sizeof(T) == 8) {
+    const double m = live ? 1.0 : 0.0;
+    const double r2i = 1.0 / (live ? r2 : 1.0);
+    const double eps = D.eps[tt] * m;
+    const double sr2 = D.sig2[tt] * r2i;
+    const double sr6 = sr2 * sr2 * sr2;
+    const double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
+    const double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
+    const double e = 4.0 * eps * (sr6 * sr6 - sr6) - D.shift[tt] * m;
+    double w[3], Dw = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      w[k] = ui[k] - uj[k];
+      Dw += dx[k] * w[k];
+    }
+    const double CDw = C * Dw;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      acc.F[k] += f * dx[k];
+      acc.H[k] += CDw * dx[k] - f * w[k];
+    }
+    acc.e += 0.5 * e;
+  } else {
+    const float m = live ? 1.0f : 0.0f;
+    const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
+    const float eps = D.eps_f[tt] * m;
+    const float sr2 = D.sig2_f[tt] * r2i;
+    const float sr6 = sr2 * sr2 * sr2;
+    const float epsr = eps * r2i * sr6;
+    const float f = epsr * (48.0f * sr6 - 24.0f);
+    const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
+    const float e = 4.0f * eps * sr6 * (sr6 - 1.0f) - D.shift_f[tt] * m;
+    float d[3], w[3], Dw = 0.0f;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      d[k] = (float)dx[k];
+      w[k] = ui[k] - uj[k];
+      Dw = __builtin_fmaf(d[k], w[k], Dw);
+    }
+    const float CDw = C * Dw;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      acc.F[k].add(f * d[k]);
+      acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
+    }
+    acc.e.add(0.5f * e);
+  }
+}
+
+// Displacement x_i - x_j (minimum image) and r^2 = (dx*dx + dy*dy) + dz*dz,
+// rounded operation by operation so that the cutoff decision is exactly the
+// float64 one.
+template <int DIM>
+__device__ __forceinline__ double pair_disp(const SysDesc &D, const double xi[3], const double xj[3],
+                                            double dx[3]) {
+  double r2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    dx[k] = minimg(xi[k] - xj[k], D.box[k], D.hbox[k], D.periodic[k]);
+    r2 = __dadd_rn(r2, __dmul_rn(dx[k], dx[k]));
+  }
+  return r2;
+}
+
+// Pair pass of atom i over its full list in global memory.
 template <int DIM, typename T>
 __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int i,
                                           const double xi[3], const T ui[3], int ti,
@@ -234,69 +306,19 @@ __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int
   const int64_t off = D.off, N = A.ntot;
   const int n = D.n;
   const T *__restrict__ u = (const T *)A.u;
+  const double *__restrict__ x = A.x;
   const int32_t *__restrict__ nbr = A.nbr + D.nbr_off;
   const int nn = A.nnb[off + i];
+#pragma unroll 2
   for (int q = 0; q < nn; ++q) {
     const int ent = nbr[(int64_t)q * n + i];
-    const int j = ent >> 1, tj = ent & 1;
-    const int64_t aj = off + j;
-    // displacement x_i - x_j and r^2 = (dx*dx + dy*dy) + dz*dz, rounded
-    // operation by operation so the cutoff decision is the float64 one
-    double dx[3];
-    double r2 = 0.0;
+    const int64_t aj = off + (ent >> 1);
+    double xj[3], dx[3];
+    T uj[3];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      dx[k] = minimg(xi[k] - A.x[k * N + aj], D.box[k], D.hbox[k], D.periodic[k]);
-      r2 = __dadd_rn(r2, __dmul_rn(dx[k], dx[k]));
-    }
-    if (!(r2 < D.rc2)) continue;
-    const int tt = ti * 2 + tj;
-    if constexpr (sizeof(T) == 8) {
-      const double eps = D.eps[tt];
-      const double r2i = 1.0 / r2;
-      const double sr2 = D.sig2[tt] * r2i;
-      const double sr6 = sr2 * sr2 * sr2;
-      const double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
-      const double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
-      const double e = 4.0 * eps * (sr6 * sr6 - sr6) - D.shift[tt];
-      double w[3], Dw = 0.0;
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        w[k] = ui[k] - u[k * N + aj];
-        Dw += dx[k] * w[k];
-      }
-      const double CDw = C * Dw;
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        acc.F[k] += f * dx[k];
-        acc.H[k] += CDw * dx[k] - f * w[k];
-      }
-      acc.e += 0.5 * e;
-    } else {
-      const float eps = D.eps_f[tt];
-      const float r2f = (float)r2;
-      const float r2i = rcp_nr(r2f);
-      const float sr2 = D.sig2_f[tt] * r2i;
-      const float sr6 = sr2 * sr2 * sr2;
-      const float epsr = eps * r2i * sr6;
-      const float f = epsr * (48.0f * sr6 - 24.0f);
-      const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
-      const float e = 4.0f * eps * sr6 * (sr6 - 1.0f) - D.shift_f[tt];
-      float d[3], w[3], Dw = 0.0f;
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        d[k] = (float)dx[k];
-        w[k] = ui[k] - u[k * N + aj];
-        Dw = __builtin_fmaf(d[k], w[k], Dw);
-      }
-      const float CDw = C * Dw;
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        acc.F[k].add(f * d[k]);
-        acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
-      }
-      acc.e.add(0.5f * e);
-    }
+    for (int k = 0; k < DIM; ++k) { xj[k] = x[k * N + aj]; uj[k] = u[k * N + aj]; }
+    const double r2 = pair_disp<DIM>(D, xi, xj, dx);
+    pair_term<DIM, T>(D, ti * 2 + (ent & 1), r2 < D.rc2, dx, r2, ui, uj, acc);
   }
 }
 

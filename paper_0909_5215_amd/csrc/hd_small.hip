@@ -287,57 +287,16 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       T ui[3];
 #pragma unroll
       for (int k = 0; k < DIM; ++k) ui[k] = (T)u64[k];
+#pragma unroll 4
       for (int q = 0; q < nn; ++q) {
         const int ent = nbr[q * stride + i];
-        const int j = ent >> 1, tj = ent & 1;
-        double dx[3];
-        double r2 = 0.0;
+        const int j = ent >> 1;
+        double xj[3], dx[3];
+        T uj[3];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          dx[k] = minimg(x[k] - xs[k * stride + j], D.box[k], D.hbox[k], D.periodic[k]);
-          r2 = __dadd_rn(r2, __dmul_rn(dx[k], dx[k]));
-        }
-        if (!(r2 < D.rc2)) continue;
-        const int tt = ti * 2 + tj;
-        if constexpr (sizeof(T) == 8) {
-          const double eps = D.eps[tt];
-          const double r2i = 1.0 / r2;
-          const double sr2 = D.sig2[tt] * r2i;
-          const double sr6 = sr2 * sr2 * sr2;
-          const double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
-          const double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
-          const double e = 4.0 * eps * (sr6 * sr6 - sr6) - D.shift[tt];
-          double w[3], Dw = 0.0;
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) { w[k] = ui[k] - us[k * stride + j]; Dw += dx[k] * w[k]; }
-          const double CDw = C * Dw;
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) { acc.F[k] += f * dx[k]; acc.H[k] += CDw * dx[k] - f * w[k]; }
-          acc.e += 0.5 * e;
-        } else {
-          const float eps = D.eps_f[tt];
-          const float r2i = rcp_nr((float)r2);
-          const float sr2 = D.sig2_f[tt] * r2i;
-          const float sr6 = sr2 * sr2 * sr2;
-          const float epsr = eps * r2i * sr6;
-          const float f = epsr * (48.0f * sr6 - 24.0f);
-          const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
-          const float e = 4.0f * eps * sr6 * (sr6 - 1.0f) - D.shift_f[tt];
-          float d[3], w[3], Dw = 0.0f;
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) {
-            d[k] = (float)dx[k];
-            w[k] = ui[k] - us[k * stride + j];
-            Dw = __builtin_fmaf(d[k], w[k], Dw);
-          }
-          const float CDw = C * Dw;
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) {
-            acc.F[k].add(f * d[k]);
-            acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
-          }
-          acc.e.add(0.5f * e);
-        }
+        for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = us[k * stride + j]; }
+        const double r2 = pair_disp<DIM>(D, x, xj, dx);
+        pair_term<DIM, T>(D, ti * 2 + (ent & 1), r2 < D.rc2, dx, r2, ui, uj, acc);
       }
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
