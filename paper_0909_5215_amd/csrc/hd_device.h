@@ -8,7 +8,10 @@ namespace hdk {
 
 enum : int { ROLE_MOBILE = 0, ROLE_FIXED = 1, ROLE_RIGID = 2 };
 enum : int { FLAG_UNSTABLE = 1, FLAG_NBR_OVERFLOW = 2 };
-enum : int { NRED = 12 };  // E, d2, G, sumF_R[3], sumHu_R[3], sumU_R[3]
+// Per-system sums: E, d2, G, sumF_R[3], sumHu_R[3], sumU_R[3], and the count
+// of atoms whose LJ force is non-finite or above kForceLimit.
+enum : int { NRED = 13 };
+constexpr double kForceLimit2 = 1e12;  // (1e6 eps/sigma)^2
 
 // Read-only description of one system (uploaded at finalize / parameter
 // changes).  Per-atom arrays of the batch are concatenated; component k of
@@ -134,6 +137,7 @@ struct Scal {
   double Fd[3];      // drive force on the rigid body
   double hud[3];     // drive Hessian term per rigid atom (k/nR^2) sum_R u
   double sumFb[3];   // bias force summed over rigid atoms
+  double bad;        // atoms with a non-finite or runaway force
 };
 
 template <int DIM>
@@ -169,6 +173,7 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
     for (int k = 0; k < dim; ++k) G += (S.Fd[k] / nR) * sums[9 + k];
   }
   S.e_pot = S.e_lj + S.v_drive;
+  S.bad = sums[12];
   S.d = sqrt(sums[1]);
   S.g = (S.d < 1e-12) ? 0.0 : -G / S.d;
   S.dv = 0.0; S.dvp = 0.0;

@@ -307,6 +307,10 @@ __device__ void pairs_tile(const SysDesc &D, SysState &st, const Arrays &A, cons
     if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
     A.eatom[a] = e;
     sums[0] = e;
+    double f2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) f2 += F[k] * F[k];
+    sums[12] = (f2 <= kForceLimit2) ? 0.0 : 1.0;
     if (role != ROLE_FIXED) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) { sums[1] += u64[k] * u64[k]; sums[2] += F[k] * u64[k]; }
@@ -361,7 +365,7 @@ __device__ void pairs_tile(const SysDesc &D, SysState &st, const Arrays &A, cons
     st.e_lj = S.e_lj; st.v_drive = S.v_drive; st.e_pot = S.e_pot;
     st.d = S.d; st.g = S.g; st.dv = S.dv; st.dvp = S.dvp;
     st.x_slider = S.xs; st.x_tip = S.x_tip; st.f_lat = S.f_lat;
-    if (!isfinite(S.e_pot)) st.flags |= FLAG_UNSTABLE;
+    if (!isfinite(S.e_pot) || S.bad > 0.0) st.flags |= FLAG_UNSTABLE;
     gs[s].S = S;
     for (int k = 0; k < 3; ++k) { gs[s].VRn[k] = st.VR[k]; gs[s].XRn[k] = st.XR[k]; }
     A.tile_done[s] = 0;

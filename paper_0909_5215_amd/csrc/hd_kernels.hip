@@ -299,6 +299,12 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
       if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
       A.eatom[a] = e;
       sums[0] += e;
+      {
+        double f2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) f2 += F[k] * F[k];
+        if (!(f2 <= kForceLimit2)) sums[12] += 1.0;
+      }
       if (role != ROLE_FIXED) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -349,7 +355,7 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
         sh_clock[1] += D.dt * exp(S.dv / D.kT);
         sh_step = step + 1;
       }
-      if (!isfinite(S.e_pot)) sh_flags |= FLAG_UNSTABLE;
+      if (!isfinite(S.e_pot) || S.bad > 0.0) sh_flags |= FLAG_UNSTABLE;
       sh_out = S;
     }
     __syncthreads();

@@ -945,6 +945,7 @@ hd_status hd_set_positions(hd_ctx *ctx, int32_t sys, const double *pos) {
                           hipMemcpyHostToDevice, ctx->stream));
   for (int k = 0; k < 3; ++k) T.XR[k] = XR[k];
   T.rebuild = 1;
+  T.flags &= ~HD_FLAG_UNSTABLE;  // new positions: the system runs again
   HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
   if (ctx->exec != HD_EXEC_BATCHED) {
     int32_t one = 1;

@@ -305,6 +305,12 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       }
       if constexpr (sizeof(T) == 8) e_own = acc.e; else e_own = acc.e.get();
       sums[0] = e_own;
+      {
+        double f2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) f2 += F[k] * F[k];
+        sums[12] = (f2 <= kForceLimit2) ? 0.0 : 1.0;
+      }
       if (role != ROLE_FIXED) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) { sums[1] += u64[k] * u64[k]; sums[2] += F[k] * u64[k]; }
@@ -343,7 +349,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         sh_clock[1] += D.dt * exp(S.dv / D.kT);
         sh_step = step + 1;
       }
-      if (!isfinite(S.e_pot)) sh_flags |= FLAG_UNSTABLE;
+      if (!isfinite(S.e_pot) || S.bad > 0.0) sh_flags |= FLAG_UNSTABLE;
       sh_out = S;
     }
     __syncthreads();

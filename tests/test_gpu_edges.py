@@ -1,0 +1,136 @@
+"""Edge cases of the GPU path: tiny and degenerate systems, the size limit of
+the LDS-resident kernel, neighbour-capacity overflow, d = 0, argument errors
+and the per-system instability flag (a system whose energy becomes
+non-finite is frozen while the others continue)."""
+import numpy as np
+import pytest
+
+from hd_inputs import (ROLE_FIXED, ROLE_MOBILE, ROLE_RIGID, SystemSpec, build_2d, perturbed)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    from paper_0909_5215_amd import hd as _hd
+    _hd.load()
+    return _hd
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def custom(pos, role, typ=None, L=30.0):
+    n = pos.shape[1]
+    return SystemSpec(dim=2, pos=np.array(pos, dtype=np.float64), role=np.array(role, np.uint8),
+                      type=np.zeros(n, np.uint8) if typ is None else np.array(typ, np.uint8),
+                      box=np.array([L, 0.0, 0.0]), periodic=np.array([1, 0, 0], np.int32))
+
+
+@pytest.mark.parametrize("lds", [True, False])
+def test_single_atom_and_tiny_systems(hd, oracle_mod, lds):
+    one = custom([[1.0], [2.0]], [ROLE_MOBILE])
+    two = custom([[1.0, 2.2], [2.0, 2.1]], [ROLE_MOBILE, ROLE_MOBILE])
+    nodrive = custom([[1.0, 2.2, 3.3], [2.0, 2.1, 2.0]], [ROLE_MOBILE, ROLE_FIXED, ROLE_MOBILE])
+    specs = [one, two, nodrive]
+    ctx = hd.make_context(specs, precision=hd.HD_FP64, lds_resident=lds)
+    for k, s in enumerate(specs):
+        ref = oracle_mod.OracleSystem(s).compute()
+        np.testing.assert_allclose(ctx.forces(k), ref["f_tot"], rtol=1e-12, atol=1e-12)
+        assert ctx.scalars(k)["e_pot"] == pytest.approx(ref["e_pot"], abs=1e-12)
+    ctx.step(30)
+    for k in range(3):
+        assert ctx.scalars(k)["step"] == 30
+        assert np.all(np.isfinite(ctx.positions(k)))
+    assert ctx.scalars(0)["e_pot"] == 0.0
+
+
+def test_all_fixed_system_never_moves(hd):
+    s = build_2d(nx=12, ny=4, tip_w=4, tip_h=3)
+    s.role[:] = ROLE_FIXED
+    ctx = hd.make_context([s], precision=hd.HD_FP32C)
+    x0 = ctx.positions(0)
+    ctx.step(25)
+    np.testing.assert_array_equal(ctx.positions(0), x0)
+
+
+def _exactly(nsub_x, nsub_y, tip_w, tip_h, extra=0):
+    s = build_2d(nx=nsub_x, ny=nsub_y, tip_w=tip_w, tip_h=tip_h)
+    if extra:
+        xs = np.concatenate([s.pos, np.array([[s.box[0] / 3], [s.pos[1].max() + 6.0]])], axis=1)
+        s = SystemSpec(dim=2, pos=xs, type=np.append(s.type, 0).astype(np.uint8),
+                       role=np.append(s.role, ROLE_MOBILE).astype(np.uint8), box=s.box, periodic=s.periodic,
+                       eps=s.eps)
+    return s
+
+
+@pytest.mark.parametrize("extra", [0, 1])
+def test_lds_kernel_size_limit(hd, oracle_mod, extra):
+    """1024 atoms is the largest LDS-resident system; 1025 goes to the global
+    kernel.  Both agree with the oracle."""
+    s = _exactly(64, 14, 16, 8, extra)
+    assert s.n == 1024 + extra
+    s.rO = s.pos.copy()
+    s.pos = perturbed(s, 0.05, 9)
+    ref = oracle_mod.OracleSystem(s).compute()
+    ctx = hd.make_context([s], precision=hd.HD_FP32C, init_velocities=False)
+    assert rel(ctx.forces(0), ref["f_tot"]) <= 1e-5
+    ctx.step(10)
+    assert ctx.scalars(0)["flags"] == 0
+
+
+@pytest.mark.parametrize("lds", [True, False])
+def test_neighbour_overflow_is_flagged(hd, lds):
+    s = build_2d()
+    ctx = hd.make_context([s], precision=hd.HD_FP32C, max_neighbors=8, lds_resident=lds)
+    assert ctx.scalars(0)["flags"] & hd.HD_FLAG_NBR_OVERFLOW
+    ctx.step(5)
+    assert ctx.scalars(0)["step"] == 5
+
+
+def test_zero_distance_guard(hd, oracle_mod):
+    """At x = r_O the distance d is 0: g is set to 0 and there is no bias force."""
+    s = build_2d()
+    s.bias_on, s.g_lo, s.g_hi, s.dv_max = 1, -1.0, 1.0, 0.3
+    ctx = hd.make_context([s], precision=hd.HD_FP64, init_velocities=False)
+    sc = ctx.scalars(0)
+    ref = oracle_mod.OracleSystem(s).compute()
+    assert sc["d"] == 0.0 and sc["g"] == 0.0
+    assert sc["dv"] == pytest.approx(ref["dv"], abs=1e-15)
+    assert np.all(ctx.forces(0, hd.HD_FORCE_BIAS) == 0.0)
+
+
+def test_argument_errors(hd):
+    s = build_2d()
+    ctx = hd.Context(hd.HD_FP32C)
+    with pytest.raises(hd.HDError):
+        ctx.step(1)                                  # before finalize
+    k = ctx.add_system(s)
+    with pytest.raises(hd.HDError):
+        ctx.set_bias(k, True, 2, 0.5, 1.0, 0.0)      # g_lo >= g_hi
+    with pytest.raises(hd.HDError):
+        ctx.set_bias(k, True, 0, 0.5, 0.0, 1.0)      # m_b < 1
+    ctx.finalize()
+    with pytest.raises(hd.HDError):
+        ctx.scalars(5)                               # bad system index
+    with pytest.raises(hd.HDError):
+        ctx.add_system(s)                            # after finalize
+    bad = build_2d(nx=4, ny=4, tip_w=2, tip_h=2)     # box shorter than 2 (rc + skin)
+    c2 = hd.Context(hd.HD_FP32C)
+    with pytest.raises(hd.HDError):
+        c2.add_system(bad)
+
+
+def test_unstable_system_is_frozen_others_continue(hd):
+    good = build_2d()
+    bad = build_2d()
+    i, j = 150, 151                                  # two mobile substrate atoms
+    bad.pos[0, j] = bad.pos[0, i] + 0.05              # nearly on top of each other
+    bad.pos[1, j] = bad.pos[1, i]
+    ctx = hd.make_context([good, bad], precision=hd.HD_FP64)
+    ctx.step(50)
+    assert ctx.scalars(0)["flags"] == 0
+    assert ctx.scalars(0)["step"] == 50
+    assert ctx.scalars(1)["flags"] & hd.HD_FLAG_UNSTABLE
+    assert ctx.scalars(1)["step"] < 50

@@ -1,0 +1,106 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (batched scheduler, float32 pair arithmetic with compensated
+sums).  The oracle evaluates sampled systems of each batch in full; every
+system's scalars must be finite.
+
+Tolerances as in test_gpu_parity: relative L2 force error <= 1e-5 per system,
+|dV - dV_ref| <= 1e-6 dV_max.
+"""
+import numpy as np
+import pytest
+
+from hd_inputs import config_c2, config_c3, config_c4, config_c5a, config_c5b, perturbed
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    from paper_0909_5215_amd import hd as _hd
+    _hd.load()
+    return _hd
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def snapshot(oracle_mod, spec, seed, need_bias=True):
+    """Jittered lattice snapshot with r_O = lattice and thresholds that
+    bracket the snapshot's slope."""
+    s = spec.copy()
+    s.rO = s.pos.copy()
+    s.pos = perturbed(s, 0.05, seed)
+    if need_bias:
+        g = oracle_mod.OracleSystem(s).compute()["g"]
+        span = 2.0 * abs(g) + 1.0
+        s.bias_on, s.m_b, s.dv_max = 1, 2, 5.0 * s.kT
+        s.g_lo, s.g_hi = g - 0.4 * span, g + 0.6 * span
+    return s
+
+
+def check_batch(hd, oracle_mod, specs, sample):
+    ctx = hd.make_context(specs, precision=hd.HD_FP32C, init_velocities=False)
+    for k in range(len(specs)):
+        sc = ctx.scalars(k)
+        assert np.isfinite(sc["e_pot"]) and sc["flags"] == 0, k
+    for k in sample:
+        ref = oracle_mod.OracleSystem(specs[k]).compute()
+        assert rel(ctx.forces(k), ref["f_tot"]) <= 1e-5, k
+        sc = ctx.scalars(k)
+        assert abs(sc["dv"] - ref["dv"]) <= 1e-6 * specs[k].dv_max, k
+        assert sc["e_pot"] == pytest.approx(ref["e_pot"], rel=1e-6), k
+    return ctx
+
+
+def test_c2_full_batch(hd, oracle_mod):
+    specs = [snapshot(oracle_mod, s, 100 + k) for k, s in enumerate(config_c2())]
+    check_batch(hd, oracle_mod, specs, range(len(specs)))
+
+
+def test_c3_sampled(hd, oracle_mod):
+    base = config_c3()
+    sample = [0, 21, 42, 63]
+    specs = [snapshot(oracle_mod, s, 200 + k, need_bias=(k in sample)) for k, s in enumerate(base)]
+    check_batch(hd, oracle_mod, specs, sample)
+
+
+def test_c5b_sampled(hd, oracle_mod):
+    base = config_c5b()
+    sample = [0, 101, 255]
+    specs = [snapshot(oracle_mod, s, 300 + k, need_bias=(k in sample)) for k, s in enumerate(base)]
+    check_batch(hd, oracle_mod, specs, sample)
+
+
+def test_c4_sampled(hd, oracle_mod):
+    base = config_c4()
+    sizes = np.array([s.n for s in base])
+    sample = sorted({int(sizes.argmin()), int(sizes.argmax()), 7, 77})
+    specs = [snapshot(oracle_mod, s, 400 + k, need_bias=(k in sample)) for k, s in enumerate(base)]
+    check_batch(hd, oracle_mod, specs, sample)
+
+
+@pytest.mark.slow
+def test_c5a_one_million_atoms(hd, oracle_mod):
+    spec = snapshot(oracle_mod, config_c5a()[0], 500)
+    check_batch(hd, oracle_mod, [spec], [0])
+
+
+def test_c3_short_trajectory_sampled(hd, oracle_mod):
+    """20 steps of the full C3 batch; two sampled systems against the oracle's
+    trajectories from the same state and Philox stream."""
+    base = config_c3()
+    sample = [5, 50]
+    specs = [snapshot(oracle_mod, s, 600 + k, need_bias=(k in sample)) for k, s in enumerate(base)]
+    ctx = hd.make_context(specs, precision=hd.HD_FP32C, init_velocities=True)
+    ctx.step(20)
+    for k in sample:
+        o = oracle_mod.OracleSystem(specs[k])
+        o.init_velocities()
+        o.step(20)
+        dx = ctx.positions(k) - o.positions()
+        for d in range(3):
+            if specs[k].periodic[d]:
+                dx[d] -= specs[k].box[d] * np.round(dx[d] / specs[k].box[d])
+        assert np.abs(dx).max() < 1e-8, k
+        assert ctx.scalars(k)["t_hyper"] == pytest.approx(o.scalars()["t_hyper"], rel=1e-6)
