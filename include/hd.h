@@ -178,11 +178,16 @@ hd_status hd_set_velocities(hd_ctx *ctx, int32_t sys, const double *vel);
 hd_status hd_finalize(hd_ctx *ctx);
 
 /* Advance every system by n_steps BAOAB steps (asynchronous on the context
- * stream).  Returns HD_E_UNSTABLE only when every system is frozen. */
+ * stream).  A system whose energy becomes non-finite, or one of whose atoms
+ * feels a force above 1e6 eps/sigma, is frozen (HD_FLAG_UNSTABLE) while the
+ * others continue; hd_set_positions or hd_set_state revive it.  Returns
+ * HD_E_UNSTABLE when the last hd_sync found every system frozen. */
 hd_status hd_step(hd_ctx *ctx, int64_t n_steps);
 /* Evaluate forces, energy, H u and the bias at the current positions without
  * stepping or advancing the clock; rebuilds every neighbour list. */
 hd_status hd_compute(hd_ctx *ctx);
+/* Wait for the context stream; returns HD_E_UNSTABLE if every system is
+ * frozen. */
 hd_status hd_sync(hd_ctx *ctx);
 
 /* Host read-outs (synchronising).  out holds dim*n_atoms doubles. */

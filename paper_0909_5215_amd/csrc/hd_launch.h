@@ -22,6 +22,10 @@ hipError_t launch_small(int prec, int dim, const SysDesc *descs, SysState *state
                         const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax,
                         int64_t nsteps, int mode, hipStream_t stream);
 size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax);
+// Dynamic LDS bytes of one LDS-resident group, and the one-time permission to
+// use that much (call outside graph capture, before the first launch).
+size_t small_group_bytes(int prec, int dim, int nmax, int maxnb, int cellmax);
+hipError_t small_allow_lds(int prec, int dim, size_t bytes);
 
 // Tiles of the grid scheduler: each tile is a contiguous atom range of one
 // system (tiles never straddle systems).

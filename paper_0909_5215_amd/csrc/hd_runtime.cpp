@@ -105,6 +105,9 @@ struct hd_ctx {
   // grid plans: [0] all systems (GRID), or one per system (SEQUENTIAL)
   std::vector<Plan> plans;
   void *d_gscal = nullptr;
+  hipGraphExec_t batched_graph = nullptr;  // one chunk of the batched scheduler
+  int64_t batched_graph_launches = 0;
+  bool all_frozen = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   int64_t last_launches = 0;
@@ -558,6 +561,14 @@ hd_status hd_init_velocities(hd_ctx *ctx, int32_t sys) {
 hd_status hd_sync(hd_ctx *ctx) {
   CHECK_CTX();
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->finalized) {
+    std::vector<SysState> st(ctx->sys.size());
+    HIPCHK(hipMemcpy(st.data(), ctx->d_state, st.size() * sizeof(SysState), hipMemcpyDeviceToHost));
+    bool all = !st.empty();
+    for (auto &t : st) all = all && (t.flags & HD_FLAG_UNSTABLE);
+    ctx->all_frozen = all;
+    if (all) return fail(ctx, HD_E_UNSTABLE, "every system is frozen as unstable");
+  }
   return HD_OK;
 }
 
@@ -684,6 +695,10 @@ hd_status hd_finalize(hd_ctx *ctx) {
     ALLOC(G.d_ids, G.ids.size());
     HIPCHK(hipMemcpyAsync(G.d_ids, G.ids.data(), G.ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           ctx->stream));
+    if (G.small) {
+      const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+      HIPCHK(hdk::small_allow_lds(prec, G.dim, hdk::small_group_bytes(prec, G.dim, G.nmax, G.maxnb, G.cellmax)));
+    }
   }
   // host staging
   std::vector<double> x(3 * N, 0.0), rO(3 * N, 0.0), cofs(3 * N, 0.0), v(3 * N, 0.0);
@@ -775,6 +790,7 @@ hd_status hd_step(hd_ctx *ctx, int64_t n_steps) {
   if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_step before hd_finalize");
   if (n_steps < 0) return fail(ctx, HD_E_ARG, "negative step count");
   if (n_steps == 0) return HD_OK;
+  if (ctx->all_frozen) return fail(ctx, HD_E_UNSTABLE, "every system is frozen as unstable");
   hd_status st = sync_in(ctx);
   if (st != HD_OK) return st;
   if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
@@ -783,11 +799,27 @@ hd_status hd_step(hd_ctx *ctx, int64_t n_steps) {
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
   if (ctx->exec == HD_EXEC_BATCHED) {
     int64_t left = n_steps;
-    while (left > 0) {
-      const int64_t k = std::min(left, kChunkSteps);
-      if ((st = launch_batched_all(ctx, k, 0, &launches)) != HD_OK) return st;
-      left -= k;
+    // full chunks replay a captured graph of one chunk (the persistent
+    // launches of every group, forked over two streams); the rest is direct
+    if (left >= kChunkSteps && !ctx->batched_graph) {
+      hipStream_t cs = ctx->stream;
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      int64_t nl = 0;
+      hd_status cst = launch_batched_all(ctx, kChunkSteps, 0, &nl);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(cs, &g);
+      if (cst != HD_OK) return cst;
+      if (e2 != hipSuccess) return fail(ctx, HD_E_HIP, std::string("batched graph capture: ") + hipGetErrorString(e2));
+      HIPCHK(hipGraphInstantiate(&ctx->batched_graph, g, nullptr, nullptr, 0));
+      HIPCHK(hipGraphDestroy(g));
+      ctx->batched_graph_launches = nl;
     }
+    while (left >= kChunkSteps) {
+      HIPCHK(hipGraphLaunch(ctx->batched_graph, ctx->stream));
+      launches += ctx->batched_graph_launches;
+      left -= kChunkSteps;
+    }
+    if (left > 0 && (st = launch_batched_all(ctx, left, 0, &launches)) != HD_OK) return st;
   } else {
     for (auto &P : ctx->plans) {
       int64_t left = n_steps;
@@ -946,6 +978,7 @@ hd_status hd_set_positions(hd_ctx *ctx, int32_t sys, const double *pos) {
   for (int k = 0; k < 3; ++k) T.XR[k] = XR[k];
   T.rebuild = 1;
   T.flags &= ~HD_FLAG_UNSTABLE;  // new positions: the system runs again
+  ctx->all_frozen = false;
   HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
   if (ctx->exec != HD_EXEC_BATCHED) {
     int32_t one = 1;
@@ -1048,7 +1081,13 @@ hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) 
   SysState T = h.state;
   T.rebuild = 2;  // rebuild the list from the recorded build positions
   HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  if (ctx->exec != HD_EXEC_BATCHED) {
+    // the grid scheduler rebuilds from the restored current positions
+    int32_t one = 1;
+    HIPCHK(hipMemcpyAsync(ctx->A.rebuild_flag + sys, &one, sizeof(one), hipMemcpyHostToDevice, ctx->stream));
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->all_frozen = false;
   return HD_OK;
 }
 
@@ -1091,6 +1130,7 @@ void hd_destroy(hd_ctx *ctx) {
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   for (auto &P : ctx->plans)
     if (P.exec) hipGraphExecDestroy(P.exec);
+  if (ctx->batched_graph) hipGraphExecDestroy(ctx->batched_graph);
   for (void *p : ctx->allocs) hipFree(p);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
   if (ctx->ev1) hipEventDestroy(ctx->ev1);

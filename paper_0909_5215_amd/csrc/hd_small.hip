@@ -413,12 +413,31 @@ template <typename T, int DIM, int MODE, int BLOCK>
 static hipError_t launch_small_t(const SysDesc *descs, SysState *states, const Arrays &A,
                                  const int32_t *sys_list, int nsys, size_t bytes, int64_t nsteps,
                                  SmallLayout L, hipStream_t stream) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_small<T, DIM, MODE, BLOCK>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_small<T, DIM, MODE, BLOCK>), dim3(nsys), dim3(BLOCK), bytes, stream, descs, states, A,
                      sys_list, nsteps, L);
   return hipGetLastError();
+}
+
+template <typename T, int DIM>
+static hipError_t allow_lds_d(int bytes) {
+  const void *fns[4] = {(const void *)k_small<T, DIM, 1, 1024>, (const void *)k_small<T, DIM, 0, 256>,
+                        (const void *)k_small<T, DIM, 0, 512>, (const void *)k_small<T, DIM, 0, 1024>};
+  for (const void *f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Allow `bytes` of dynamic LDS for every LDS-resident kernel of this
+// precision and dimension (done once, outside any graph capture).
+hipError_t small_allow_lds(int prec, int dim, size_t bytes) {
+  if (prec == 0) return dim == 2 ? allow_lds_d<double, 2>((int)bytes) : allow_lds_d<double, 3>((int)bytes);
+  return dim == 2 ? allow_lds_d<float, 2>((int)bytes) : allow_lds_d<float, 3>((int)bytes);
+}
+
+size_t small_group_bytes(int prec, int dim, int nmax, int maxnb, int cellmax) {
+  return small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax).bytes;
 }
 
 template <typename T, int DIM>
