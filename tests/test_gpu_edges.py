@@ -22,6 +22,7 @@ def rel(a, b):
 
 
 def custom(pos, role, typ=None, L=30.0):
+    pos = np.array(pos, dtype=np.float64)
     n = pos.shape[1]
     return SystemSpec(dim=2, pos=np.array(pos, dtype=np.float64), role=np.array(role, np.uint8),
                       type=np.zeros(n, np.uint8) if typ is None else np.array(typ, np.uint8),
