@@ -373,6 +373,10 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     }
     A.eatom[a] = e_own;
     A.nnb[a] = nn;
+    // the list itself lives in LDS; leave a copy in the global list so that
+    // read-outs (hd_debug_pairs) see the list the last step used
+    int32_t *gl = A.nbr + D.nbr_off;
+    for (int q = 0; q < nn; ++q) gl[(int64_t)q * n + i] = (int32_t)nbr[q * stride + i];
     if (role == ROLE_MOBILE)
 #pragma unroll
       for (int k = 0; k < DIM; ++k) ek[0] += 0.5 * D.mass * v[k] * v[k];
