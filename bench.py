@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--quench-steps", type=int, default=3000)
     ap.add_argument("--prerun-steps", type=int, default=2000)
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -170,6 +172,18 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
     torch.cuda.init()
+
+    if args.copy_calib:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters calibrate the traffic of the kernels profiled beside it
+        nbytes = args.copy_calib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read and written per copy, 3 copies")
+        del src, dst
 
     specs, desc = workload(args.config)
     n_atoms = sum(s.n for s in specs)
