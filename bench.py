@@ -81,7 +81,9 @@ def prepare(hd, specs, quench_steps, prerun_steps, block):
     pre = [s.copy() for s in specs]
     for s in pre:
         s.bias_on = 0
-    ctx = hd.make_context(pre, precision=hd.HD_FP32C, init_velocities=True, block_threads=block)
+    # float64 pre-run: the float32 stepping kernel then runs only in the
+    # warm-up and the timed region, so its profile rows are the timed launches
+    ctx = hd.make_context(pre, precision=hd.HD_FP64, init_velocities=True, block_threads=block)
     for k, s in enumerate(specs):
         ctx.set_positions(k, s.rO)       # start from the quenched basin
     ctx.step(prerun_steps // 2)
@@ -195,8 +197,11 @@ def main():
     # ---- batched float32 path ------------------------------------------------
     ctx = make_run_ctx(hd, specs, states, hd.HD_FP32C, hd.HD_EXEC_BATCHED, args.block)
     ctx.step(args.warmup)
+    reb0 = [ctx.scalars(k)["n_rebuilds"] for k in range(len(specs))]
     wall, ev_ms, launches = time_steps(torch, ctx, args.steps)
     value = n_atoms * args.steps / wall
+    reb1 = [ctx.scalars(k)["n_rebuilds"] for k in range(len(specs))]
+    rebuild_rate = float(np.mean(np.array(reb1) - np.array(reb0))) * 1000.0 / args.steps
     flags = [ctx.scalars(k)["flags"] for k in range(len(specs))]
     t_hyper = [ctx.scalars(k)["t_hyper"] for k in range(len(specs))]
     t_md = [ctx.scalars(k)["t_md"] for k in range(len(specs))]
@@ -253,6 +258,7 @@ def main():
         "fp64_plain": plain,
         "speedup_vs_fp64_plain": (value / plain["value"]) if plain else None,
         "unstable_systems": int(sum(1 for f in flags if f & 1)),
+        "list_rebuilds_per_1000_steps": rebuild_rate,
         "mean_boost": float(np.mean(np.array(t_hyper) / np.maximum(np.array(t_md), 1e-300))),
     }
     print(json.dumps(out), flush=True)

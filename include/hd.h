@@ -64,11 +64,12 @@ typedef enum {
                       displacements and the cutoff decision in float64 */
 } hd_precision;
 
-/* How hd_step schedules the batch.  BATCHED runs every system in one
- * persistent launch per chunk of steps (one workgroup per system).  GRID runs
- * a short sequence of kernels per step over all systems, captured in a HIP
- * graph.  SEQUENTIAL is GRID applied to one system at a time (the plain
- * single-system path). */
+/* How hd_step schedules the batch.  BATCHED runs small systems in one
+ * persistent launch per chunk of steps (one workgroup per system, state in
+ * LDS) and large systems on the grid kernels, concurrently (see
+ * hd_set_launch).  GRID runs a short sequence of kernels per step over all
+ * systems, replayed from a HIP graph.  SEQUENTIAL is GRID applied to one
+ * system at a time (the plain single-system path). */
 typedef enum { HD_EXEC_BATCHED = 0, HD_EXEC_GRID = 1, HD_EXEC_SEQUENTIAL = 2 } hd_exec;
 
 /* Per-atom roles and types. */
@@ -142,12 +143,16 @@ hd_status hd_create(hd_precision prec, int device, void *hip_stream, hd_ctx **ou
 /* Choose the scheduler before hd_finalize (default HD_EXEC_BATCHED). */
 hd_status hd_set_exec(hd_ctx *ctx, hd_exec exec);
 
-/* Tuning knobs before hd_finalize: threads per workgroup of the global-memory
- * batched kernel and of the grid tiles (64..1024, multiple of 64; 0 =
+/* Tuning knobs before hd_finalize: threads per workgroup of the grid tiles and
+ * of the one-workgroup global kernel (64..1024, multiple of 64; 0 =
  * automatic), the neighbour-slot capacity per atom (0 = automatic: 32 in 2D,
- * 128 in 3D), and whether systems that fit in one workgroup's LDS run in the
- * LDS-resident kernel (1 = automatic, the default; 0 = never). */
-hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors, int32_t lds_resident);
+ * 128 in 3D), and HD_LAUNCH_* flags.  Under HD_EXEC_BATCHED, systems that fit
+ * one workgroup's LDS (at most 1024 atoms) run in the LDS-resident persistent
+ * kernel when HD_LAUNCH_LDS is set (the default); the others run on the grid
+ * kernels over the whole chip, concurrently, or on the persistent
+ * one-workgroup global kernel when HD_LAUNCH_PERSISTENT_LARGE is set. */
+enum { HD_LAUNCH_LDS = 1, HD_LAUNCH_PERSISTENT_LARGE = 2 };
+hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors, int32_t flags);
 
 /* Append one model.  Copies every array.  Returns its index in *sys_id.  The
  * basin reference r_O defaults to the given positions; velocities start at 0;

@@ -100,7 +100,9 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
     const double dd = minimg(xn[k] - A.xb[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
     d2 += dd * dd;
   }
-  if (d2 > D.skin_half2) atomicOr(&A.rebuild_flag[A.sys_of[a]], 1);
+  // an atom outside its skin forces a rebuild from the current positions
+  // (value 1), superseding a pending rebuild from build positions (value 2)
+  if (d2 > D.skin_half2) atomicExch(&A.rebuild_flag[A.sys_of[a]], 1);
 }
 
 template <typename T>
@@ -135,10 +137,12 @@ __device__ int cell_of_g(const SysDesc &D, const double *x, int64_t N, int64_t a
 __global__ __launch_bounds__(1024) void kg_cell_count(const SysDesc *__restrict__ descs, Arrays A,
                                                       const Tile *__restrict__ tiles, int ntiles) {
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
-  if (!A.rebuild_flag[t.sys] || threadIdx.x >= t.count) return;
+  const int flag = A.rebuild_flag[t.sys];
+  if (!flag || threadIdx.x >= t.count) return;
   const SysDesc &D = descs[t.sys];
   const int64_t a = D.off + t.first + threadIdx.x;
-  const int c = D.dim == 2 ? cell_of_g<2>(D, A.x, A.ntot, a) : cell_of_g<3>(D, A.x, A.ntot, a);
+  const double *xs = flag == 2 ? A.xb : A.x;  // 2: from the recorded build positions
+  const int c = D.dim == 2 ? cell_of_g<2>(D, xs, A.ntot, a) : cell_of_g<3>(D, xs, A.ntot, a);
   A.cidx[a] = c;
   atomicAdd(&A.cell_count[D.cell_off + c], 1);
 }
@@ -200,12 +204,12 @@ __global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ 
 }
 
 template <int DIM>
-__device__ int list_atom_g(const SysDesc &D, const Arrays &A, int i) {
+__device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__restrict__ xs, int i) {
   const int64_t N = A.ntot, off = D.off, ai = off + i;
   const int n = D.n;
   double xi[3];
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = A.x[k * N + ai];
+  for (int k = 0; k < DIM; ++k) xi[k] = xs[k * N + ai];
   const int ri = A.tr[ai] >> 1;
   int cc[3] = {0, 0, 0};
 #pragma unroll
@@ -244,7 +248,7 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int i) {
           double r2 = 0.0;
 #pragma unroll
           for (int k = 0; k < DIM; ++k) {
-            const double d = minimg(A.x[k * N + aj] - xi[k], D.box[k], D.hbox[k], D.periodic[k]);
+            const double d = minimg(xs[k * N + aj] - xi[k], D.box[k], D.hbox[k], D.periodic[k]);
             r2 = __dadd_rn(r2, __dmul_rn(d, d));
           }
           if (r2 < D.rl2) {
@@ -260,15 +264,18 @@ __global__ __launch_bounds__(1024) void kg_build_list(const SysDesc *__restrict_
                                                       SysState *__restrict__ states, Arrays A,
                                                       const Tile *__restrict__ tiles, int ntiles) {
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
-  if (!A.rebuild_flag[t.sys] || threadIdx.x >= t.count) return;
+  const int flag = A.rebuild_flag[t.sys];
+  if (!flag || threadIdx.x >= t.count) return;
   const SysDesc &D = descs[t.sys];
   const int i = t.first + threadIdx.x;
   const int64_t a = D.off + i, N = A.ntot;
-  const int c = D.dim == 2 ? list_atom_g<2>(D, A, i) : list_atom_g<3>(D, A, i);
+  const double *xs = flag == 2 ? A.xb : A.x;
+  const int c = D.dim == 2 ? list_atom_g<2>(D, A, xs, i) : list_atom_g<3>(D, A, xs, i);
   A.nnb[a] = c < D.maxnb ? c : D.maxnb;
   if (c > D.maxnb) atomicOr(&states[t.sys].flags, FLAG_NBR_OVERFLOW);
-  for (int k = 0; k < D.dim; ++k) A.xb[k * N + a] = A.x[k * N + a];
-  if (i == 0) atomicAdd(&states[t.sys].n_rebuilds, 1);
+  if (flag != 2)
+    for (int k = 0; k < D.dim; ++k) A.xb[k * N + a] = A.x[k * N + a];
+  if (i == 0 && flag != 2) atomicAdd(&states[t.sys].n_rebuilds, 1);
 }
 
 // ---- pair pass with per-tile sums and last-tile reduction ------------------

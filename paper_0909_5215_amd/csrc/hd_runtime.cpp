@@ -75,6 +75,7 @@ struct hd_ctx {
   hd_exec exec = HD_EXEC_BATCHED;
   int block_threads = 0, max_nb = 0;
   bool small_disabled = false;
+  bool persistent_big = false;  // large systems on the one-workgroup global kernel
   std::vector<SysHost> sys;
   bool finalized = false, poisoned = false, need_eval = false;
   std::string err;
@@ -353,30 +354,19 @@ hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps) {
   return HD_OK;
 }
 
-// One batched launch of every system: LDS-resident groups on the context
-// stream, global-memory groups concurrently on a second stream, joined by
-// events.
-hd_status launch_batched_all(hd_ctx *ctx, int64_t nsteps, int mode, int64_t *launches) {
+// One persistent launch per group (LDS-resident groups, and large systems
+// when they run on the one-workgroup global kernel), on `stream`.
+hd_status launch_groups(hd_ctx *ctx, int64_t nsteps, int mode, hipStream_t stream, int64_t *launches) {
   const int prec = ctx->prec == HD_FP64 ? 0 : 1;
-  const bool both = !ctx->small_ids.empty() && !ctx->big_ids.empty();
-  if (both) {
-    HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
-    HIPCHK(hipStreamWaitEvent(ctx->stream2, ctx->fork, 0));
-  }
   for (auto &G : ctx->groups) {
     if (G.ids.empty()) continue;
-    if (G.small) {
+    if (G.small)
       HIPCHK(hdk::launch_small(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
-                               G.nmax, G.maxnb, G.cellmax, nsteps, mode, ctx->stream));
-    } else {
+                               G.nmax, G.maxnb, G.cellmax, nsteps, mode, stream));
+    else
       HIPCHK(hdk::launch_batched(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
-                                 ctx->block, nsteps, mode, both ? ctx->stream2 : ctx->stream));
-    }
+                                 ctx->block, nsteps, mode, stream));
     if (launches) ++*launches;
-  }
-  if (both) {
-    HIPCHK(hipEventRecord(ctx->join, ctx->stream2));
-    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->join, 0));
   }
   return HD_OK;
 }
@@ -384,17 +374,66 @@ hd_status launch_batched_all(hd_ctx *ctx, int64_t nsteps, int mode, int64_t *lau
 // Evaluate at the current positions (rebuilding lists) for every system.
 hd_status evaluate_all(hd_ctx *ctx) {
   const int prec = ctx->prec == HD_FP64 ? 0 : 1;
-  if (ctx->exec == HD_EXEC_BATCHED) {
-    hd_status st = launch_batched_all(ctx, 0, 1, nullptr);
-    if (st != HD_OK) return st;
-  } else {
-    for (auto &P : ctx->plans) {
-      int l = 0;
-      HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, true, ctx->stream, &l));
-      HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, ctx->stream));
-    }
+  hd_status st = launch_groups(ctx, 0, 1, ctx->stream, nullptr);
+  if (st != HD_OK) return st;
+  for (auto &P : ctx->plans) {
+    int l = 0;
+    HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, true, ctx->stream, &l));
+    HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, ctx->stream));
   }
   ctx->need_eval = false;
+  return HD_OK;
+}
+
+// Grid plans: graph replays of kGraphSteps steps, the rest direct, then the
+// kinetic energy.
+hd_status run_plans(hd_ctx *ctx, int64_t n_steps, hipStream_t stream, int64_t *launches) {
+  const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+  hd_status st;
+  for (auto &P : ctx->plans) {
+    int64_t left = n_steps;
+    if (left >= kGraphSteps && !P.exec && (st = capture_plan(ctx, P, kGraphSteps)) != HD_OK) return st;
+    while (left >= kGraphSteps && P.exec) {
+      HIPCHK(hipGraphLaunch(P.exec, stream));
+      *launches += P.launches_per_graph;
+      left -= P.graph_steps;
+    }
+    while (left > 0) {
+      int l = 0;
+      HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, false, stream, &l));
+      *launches += l;
+      --left;
+    }
+    HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, stream));
+    ++*launches;
+  }
+  return HD_OK;
+}
+
+// Persistent groups: full chunks replay a captured graph of one chunk, the
+// rest is launched directly.
+hd_status run_groups(hd_ctx *ctx, int64_t n_steps, hipStream_t stream, int64_t *launches) {
+  if (ctx->groups.empty()) return HD_OK;
+  hd_status st;
+  int64_t left = n_steps;
+  if (left >= kChunkSteps && !ctx->batched_graph) {
+    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    int64_t nl = 0;
+    const hd_status cst = launch_groups(ctx, kChunkSteps, 0, stream, &nl);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(stream, &g);
+    if (cst != HD_OK) return cst;
+    if (e2 != hipSuccess) return fail(ctx, HD_E_HIP, std::string("batched graph capture: ") + hipGetErrorString(e2));
+    HIPCHK(hipGraphInstantiate(&ctx->batched_graph, g, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(g));
+    ctx->batched_graph_launches = nl;
+  }
+  while (left >= kChunkSteps) {
+    HIPCHK(hipGraphLaunch(ctx->batched_graph, stream));
+    *launches += ctx->batched_graph_launches;
+    left -= kChunkSteps;
+  }
+  if (left > 0 && (st = launch_groups(ctx, left, 0, stream, launches)) != HD_OK) return st;
   return HD_OK;
 }
 
@@ -440,16 +479,17 @@ hd_status hd_set_exec(hd_ctx *ctx, hd_exec exec) {
   return HD_OK;
 }
 
-hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors, int32_t lds_resident) {
+hd_status hd_set_launch(hd_ctx *ctx, int32_t block_threads, int32_t max_neighbors, int32_t flags) {
   CHECK_CTX();
   if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_launch after hd_finalize");
   if (block_threads != 0 && (block_threads < 64 || block_threads > 1024 || block_threads % 64 != 0))
     return fail(ctx, HD_E_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
   if (max_neighbors < 0 || max_neighbors > 4096) return fail(ctx, HD_E_ARG, "max_neighbors out of range");
-  if (lds_resident != 0 && lds_resident != 1) return fail(ctx, HD_E_ARG, "lds_resident must be 0 or 1");
+  if (flags & ~(HD_LAUNCH_LDS | HD_LAUNCH_PERSISTENT_LARGE)) return fail(ctx, HD_E_ARG, "unknown launch flag");
   ctx->block_threads = block_threads;
   ctx->max_nb = max_neighbors;
-  ctx->small_disabled = lds_resident == 0;
+  ctx->small_disabled = (flags & HD_LAUNCH_LDS) == 0;
+  ctx->persistent_big = (flags & HD_LAUNCH_PERSISTENT_LARGE) != 0;
   return HD_OK;
 }
 
@@ -678,18 +718,20 @@ hd_status hd_finalize(hd_ctx *ctx) {
       ctx->groups.push_back(G);
     }
     std::sort(ctx->big_ids.begin(), ctx->big_ids.end());
-    for (int d = 0; d < 2; ++d) {
-      hd_ctx::Group G;
-      G.dim = d + 2;
-      for (int s : ctx->big_ids) if (ctx->sys[s].dim == d + 2) G.ids.push_back(s);
-      if (!G.ids.empty()) ctx->groups.push_back(G);
+    if (ctx->persistent_big) {
+      for (int d = 0; d < 2; ++d) {
+        hd_ctx::Group G;
+        G.dim = d + 2;
+        for (int s : ctx->big_ids) if (ctx->sys[s].dim == d + 2) G.ids.push_back(s);
+        if (!G.ids.empty()) ctx->groups.push_back(G);
+      }
     }
   }
   // block size of the global-memory batched kernel / grid tiles
   int maxn = 0;
   for (int s : ctx->big_ids) maxn = std::max(maxn, ctx->sys[s].n);
   if (ctx->block_threads > 0) ctx->block = ctx->block_threads;
-  else if (ctx->exec == HD_EXEC_BATCHED) ctx->block = maxn <= 256 ? 256 : 512;
+  else if (ctx->exec == HD_EXEC_BATCHED && ctx->persistent_big) ctx->block = maxn <= 256 ? 256 : 512;
   else ctx->block = 256;
   for (auto &G : ctx->groups) {
     ALLOC(G.d_ids, G.ids.size());
@@ -746,7 +788,11 @@ hd_status hd_finalize(hd_ctx *ctx) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->finalized = true;
   // schedulers
-  if (ctx->exec == HD_EXEC_GRID) {
+  if (ctx->exec == HD_EXEC_BATCHED && !ctx->persistent_big && !ctx->big_ids.empty()) {
+    std::vector<int> big(ctx->big_ids.begin(), ctx->big_ids.end());
+    ctx->plans.resize(1);
+    if ((st = build_plan(ctx, big, ctx->plans[0])) != HD_OK) return st;
+  } else if (ctx->exec == HD_EXEC_GRID) {
     std::vector<int> sys_all(S);
     for (int s = 0; s < S; ++s) sys_all[s] = s;
     ctx->plans.resize(1);
@@ -761,7 +807,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
     for (auto &P : ctx->plans) max_tiles = std::max(max_tiles, P.gp.ntiles);
     ALLOC(A.partials, (size_t)max_tiles * hdk::NRED);
   }
-  if (ctx->exec != HD_EXEC_BATCHED) {
+  if (!ctx->plans.empty()) {
     // grid path: rebuild flags raised for the first evaluation
     std::vector<int32_t> ones(S, 1);
     HIPCHK(hipMemcpyAsync(A.rebuild_flag, ones.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
@@ -794,50 +840,20 @@ hd_status hd_step(hd_ctx *ctx, int64_t n_steps) {
   hd_status st = sync_in(ctx);
   if (st != HD_OK) return st;
   if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
-  const int prec = ctx->prec == HD_FP64 ? 0 : 1;
   int64_t launches = 0;
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
-  if (ctx->exec == HD_EXEC_BATCHED) {
-    int64_t left = n_steps;
-    // full chunks replay a captured graph of one chunk (the persistent
-    // launches of every group, forked over two streams); the rest is direct
-    if (left >= kChunkSteps && !ctx->batched_graph) {
-      hipStream_t cs = ctx->stream;
-      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      int64_t nl = 0;
-      hd_status cst = launch_batched_all(ctx, kChunkSteps, 0, &nl);
-      hipGraph_t g = nullptr;
-      const hipError_t e2 = hipStreamEndCapture(cs, &g);
-      if (cst != HD_OK) return cst;
-      if (e2 != hipSuccess) return fail(ctx, HD_E_HIP, std::string("batched graph capture: ") + hipGetErrorString(e2));
-      HIPCHK(hipGraphInstantiate(&ctx->batched_graph, g, nullptr, nullptr, 0));
-      HIPCHK(hipGraphDestroy(g));
-      ctx->batched_graph_launches = nl;
-    }
-    while (left >= kChunkSteps) {
-      HIPCHK(hipGraphLaunch(ctx->batched_graph, ctx->stream));
-      launches += ctx->batched_graph_launches;
-      left -= kChunkSteps;
-    }
-    if (left > 0 && (st = launch_batched_all(ctx, left, 0, &launches)) != HD_OK) return st;
-  } else {
-    for (auto &P : ctx->plans) {
-      int64_t left = n_steps;
-      if (left >= kGraphSteps && !P.exec && (st = capture_plan(ctx, P, kGraphSteps)) != HD_OK) return st;
-      while (left >= kGraphSteps && P.exec) {
-        HIPCHK(hipGraphLaunch(P.exec, ctx->stream));
-        launches += P.launches_per_graph;
-        left -= P.graph_steps;
-      }
-      while (left > 0) {
-        int l = 0;
-        HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, false, ctx->stream, &l));
-        launches += l;
-        --left;
-      }
-      HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, ctx->stream));
-      ++launches;
-    }
+  // persistent groups on the context stream, grid plans concurrently on the
+  // second stream, joined before the closing event
+  const bool both = !ctx->groups.empty() && !ctx->plans.empty();
+  if (both) {
+    HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->stream2, ctx->fork, 0));
+  }
+  if ((st = run_groups(ctx, n_steps, ctx->stream, &launches)) != HD_OK) return st;
+  if ((st = run_plans(ctx, n_steps, both ? ctx->stream2 : ctx->stream, &launches)) != HD_OK) return st;
+  if (both) {
+    HIPCHK(hipEventRecord(ctx->join, ctx->stream2));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->join, 0));
   }
   HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
   ctx->last_launches = launches;
@@ -980,7 +996,7 @@ hd_status hd_set_positions(hd_ctx *ctx, int32_t sys, const double *pos) {
   T.flags &= ~HD_FLAG_UNSTABLE;  // new positions: the system runs again
   ctx->all_frozen = false;
   HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
-  if (ctx->exec != HD_EXEC_BATCHED) {
+  if (!ctx->plans.empty()) {
     int32_t one = 1;
     HIPCHK(hipMemcpyAsync(ctx->A.rebuild_flag + sys, &one, sizeof(one), hipMemcpyHostToDevice, ctx->stream));
   }
@@ -1081,10 +1097,10 @@ hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) 
   SysState T = h.state;
   T.rebuild = 2;  // rebuild the list from the recorded build positions
   HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
-  if (ctx->exec != HD_EXEC_BATCHED) {
-    // the grid scheduler rebuilds from the restored current positions
-    int32_t one = 1;
-    HIPCHK(hipMemcpyAsync(ctx->A.rebuild_flag + sys, &one, sizeof(one), hipMemcpyHostToDevice, ctx->stream));
+  if (!ctx->plans.empty()) {
+    // the grid scheduler rebuilds its list from the restored build positions
+    int32_t two = 2;
+    HIPCHK(hipMemcpyAsync(ctx->A.rebuild_flag + sys, &two, sizeof(two), hipMemcpyHostToDevice, ctx->stream));
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->all_frozen = false;

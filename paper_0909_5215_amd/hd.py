@@ -22,6 +22,7 @@ HD_FP64, HD_FP32C = 0, 1
 HD_EXEC_BATCHED, HD_EXEC_GRID, HD_EXEC_SEQUENTIAL = 0, 1, 2
 HD_FORCE_TOTAL, HD_FORCE_LJ, HD_FORCE_BIAS, HD_HU = 0, 1, 2, 3
 HD_FLAG_UNSTABLE, HD_FLAG_NBR_OVERFLOW = 1, 2
+HD_LAUNCH_LDS, HD_LAUNCH_PERSISTENT_LARGE = 1, 2
 
 _c = ctypes
 _dp = _c.POINTER(_c.c_double)
@@ -141,7 +142,7 @@ class Context:
 
     def __init__(self, precision: int = HD_FP32C, device: int = 0, stream=None,
                  exec_mode: int = HD_EXEC_BATCHED, block_threads: int = 0, max_neighbors: int = 0,
-                 lds_resident: bool = True):
+                 lds_resident: bool = True, persistent_large: bool = False):
         L = load()
         h = ctypes.c_void_p()
         st = L.hd_create(int(precision), int(device), stream, ctypes.byref(h))
@@ -152,8 +153,8 @@ class Context:
         self.dims: List[int] = []
         self.sizes: List[int] = []
         _check(h, L.hd_set_exec(h, int(exec_mode)), "hd_set_exec")
-        _check(h, L.hd_set_launch(h, int(block_threads), int(max_neighbors), int(bool(lds_resident))),
-               "hd_set_launch")
+        flags = (HD_LAUNCH_LDS if lds_resident else 0) | (HD_LAUNCH_PERSISTENT_LARGE if persistent_large else 0)
+        _check(h, L.hd_set_launch(h, int(block_threads), int(max_neighbors), flags), "hd_set_launch")
 
     @property
     def handle(self):
@@ -308,9 +309,11 @@ class Context:
 
 def make_context(specs: Sequence, precision: int = HD_FP32C, exec_mode: int = HD_EXEC_BATCHED,
                  init_velocities: bool = True, block_threads: int = 0, stream=None,
-                 max_neighbors: int = 0, lds_resident: bool = True) -> Context:
+                 max_neighbors: int = 0, lds_resident: bool = True,
+                 persistent_large: bool = False) -> Context:
     """Context holding every spec, finalized, with Maxwell-Boltzmann velocities."""
-    ctx = Context(precision, 0, stream, exec_mode, block_threads, max_neighbors, lds_resident)
+    ctx = Context(precision, 0, stream, exec_mode, block_threads, max_neighbors, lds_resident,
+                  persistent_large)
     for sp in specs:
         s = ctx.add_system(sp)
         if init_velocities:

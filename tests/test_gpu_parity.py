@@ -243,3 +243,27 @@ def test_lds_resident_matches_global_kernel(hd, oracle_mod, precision):
     pairs = set(map(tuple, c.debug_pairs(0).tolist()))
     refp = set(map(tuple, oracle_mod.pairs_brute(specs[1], specs[1].pos, 2.8).tolist()))
     assert pairs == refp
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_systems_on_both_schedulers(hd, oracle_mod, precision):
+    """Systems above the LDS limit run on the grid kernels by default, or on
+    the persistent one-workgroup kernel on request; both follow the oracle."""
+    specs = [biased(oracle_mod, snapshot_3d(seed=70 + k, nx=10, nz=4, R=4.0, x_slider=0.1 * k)) for k in range(2)]
+    specs.append(biased(oracle_mod, snapshot_2d(seed=72)))       # a small one alongside
+    a = hd.make_context(specs, precision=precision)
+    b = hd.make_context(specs, precision=precision, persistent_large=True)
+    tol = 1e-11 if precision == 0 else 1e-5
+    for k, s in enumerate(specs):
+        ref = oracle_mod.OracleSystem(s).compute()
+        for ctx in (a, b):
+            assert rel(ctx.forces(k), ref["f_tot"]) <= tol, k
+    for ctx in (a, b):
+        ctx.step(60)
+    for k, s in enumerate(specs):
+        dx = a.positions(k) - b.positions(k)
+        for d in range(s.dim):
+            if s.periodic[d]:
+                dx[d] -= s.box[d] * np.round(dx[d] / s.box[d])
+        assert np.abs(dx).max() < (1e-10 if precision == 0 else 1e-6), k
+        assert a.scalars(k)["step"] == b.scalars(k)["step"] == 60
