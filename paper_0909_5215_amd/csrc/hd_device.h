@@ -117,6 +117,26 @@ __device__ __forceinline__ void normals4(uint64_t seed, int64_t step, uint32_t p
   z[3] = r1 * sin(two_pi * u3);
 }
 
+// The first NZ standard normals of (step, particle, tag): the same transform
+// as normals4, evaluating only the components a DIM-dimensional update uses.
+template <int NZ>
+__device__ __forceinline__ void normals_n(uint64_t seed, int64_t step, uint32_t particle, uint32_t tag,
+                                          double z[3]) {
+  uint32_t c[4] = {(uint32_t)((uint64_t)step & 0xffffffffu), (uint32_t)((uint64_t)step >> 32),
+                   particle, tag};
+  philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  const double s = 2.3283064365386963e-10;
+  const double two_pi = 6.283185307179586;
+  const double u0 = ((double)c[0] + 0.5) * s, u1 = ((double)c[1] + 0.5) * s;
+  const double r0 = sqrt(-2.0 * log(u0));
+  z[0] = r0 * cos(two_pi * u1);
+  z[1] = r0 * sin(two_pi * u1);
+  if constexpr (NZ > 2) {
+    const double u2 = ((double)c[2] + 0.5) * s, u3 = ((double)c[3] + 0.5) * s;
+    z[2] = sqrt(-2.0 * log(u2)) * cos(two_pi * u3);
+  }
+}
+
 // Slope bias of eq. 14 and its derivative in g.
 __device__ __forceinline__ void bias_switch(const SysDesc &D, double g, double &dv, double &dvp) {
   if (g >= D.g_hi) { dv = D.dv_max; dvp = 0.0; return; }
@@ -197,15 +217,16 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
 // pair arithmetic is float32 and the per-atom sums are compensated (Kahan-
 // Babuska/Neumaier two-term sums), converted to float64 at the end.
 
-struct Comp {  // Neumaier compensated float sum
+struct Comp {  // Kahan compensated float sum: s - c is the running total
   float s, c;
   __device__ __forceinline__ void init() { s = 0.f; c = 0.f; }
   __device__ __forceinline__ void add(float x) {
-    const float t = s + x;
-    c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
     s = t;
   }
-  __device__ __forceinline__ double get() const { return (double)s + (double)c; }
+  __device__ __forceinline__ double get() const { return (double)s - (double)c; }
 };
 
 template <typename T> struct PairAcc;
@@ -285,6 +306,36 @@ __device__ __forceinline__ void pair_term(const SysDesc &D, int tt, bool live, c
       acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
     }
     acc.e.add(0.5f * e);
+  }
+}
+
+// Float32 pair vectors for a half list: f_ij Delta (force on i), h_ij (the
+// pair's H u contribution to i) and the pair energy; j receives the negatives.
+template <int DIM>
+__device__ __forceinline__ void pair_vals_f(const SysDesc &D, int tt, bool live, const double dx[3], double r2,
+                                            const float ui[3], const float uj[3], float fv[3], float hv[3],
+                                            float &e) {
+  const float m = live ? 1.0f : 0.0f;
+  const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
+  const float eps = D.eps_f[tt] * m;
+  const float sr2 = D.sig2_f[tt] * r2i;
+  const float sr6 = sr2 * sr2 * sr2;
+  const float epsr = eps * r2i * sr6;
+  const float f = epsr * (48.0f * sr6 - 24.0f);
+  const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
+  e = 4.0f * eps * sr6 * (sr6 - 1.0f) - D.shift_f[tt] * m;
+  float d[3], w[3], Dw = 0.0f;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    d[k] = (float)dx[k];
+    w[k] = ui[k] - uj[k];
+    Dw = __builtin_fmaf(d[k], w[k], Dw);
+  }
+  const float CDw = C * Dw;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    fv[k] = f * d[k];
+    hv[k] = __builtin_fmaf(CDw, d[k], -f * w[k]);
   }
 }
 

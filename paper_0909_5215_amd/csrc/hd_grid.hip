@@ -26,8 +26,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nt) {
 template <int DIM>
 __device__ void rigid_advance(const SysDesc &D, const SysState &st, int64_t step, double XRn[3],
                               double VRn[3]) {
-  double z[4];
-  normals4(D.seed, step, (uint32_t)D.n, 0u, z);
+  double z[3];
+  normals_n<DIM>(D.seed, step, (uint32_t)D.n, 0u, z);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     double v = st.VR[k], x = st.XR[k];
@@ -55,8 +55,8 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
   double xn[3] = {0, 0, 0};
   if (role == ROLE_MOBILE) {
     if (!compute_only) {
-      double z[4];
-      normals4(D.seed, step, (uint32_t)i, 0u, z);
+      double z[3];
+      normals_n<DIM>(D.seed, step, (uint32_t)i, 0u, z);
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
         double v = A.v[k * N + a], x = A.x[k * N + a];

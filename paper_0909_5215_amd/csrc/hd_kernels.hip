@@ -207,8 +207,8 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
       for (int i = tid; i < n; i += B) {
         const int64_t a = off + i;
         if ((A.tr[a] >> 1) != ROLE_MOBILE) continue;
-        double z[4];
-        normals4(D.seed, step, (uint32_t)i, 0u, z);
+        double z[3];
+        normals_n<DIM>(D.seed, step, (uint32_t)i, 0u, z);
         double d2 = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -226,8 +226,8 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
         if (d2 > D.skin_half2) moved = 1;
       }
       if (tid == 0 && D.n_rigid > 0) {
-        double z[4];
-        normals4(D.seed, step, (uint32_t)n, 0u, z);
+        double z[3];
+        normals_n<DIM>(D.seed, step, (uint32_t)n, 0u, z);
         for (int k = 0; k < DIM; ++k) {
           double v = sh_VR[k], x = sh_XR[k];
           v = v + D.hdt * sh_FR[k] * D.inv_massR;

@@ -15,14 +15,17 @@ namespace hdk {
 
 struct SmallLayout {
   int nmax, maxnb, cellmax;
-  size_t off_x, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
+  size_t off_x, off_acc, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
 };
 
+// float32 systems use half lists (each pair once); the partner's share of
+// F, H u and the energy is accumulated in float64 in LDS (acc region).
 __host__ __device__ inline SmallLayout small_layout(int dim, int tsize, int nmax, int maxnb, int cellmax) {
   SmallLayout L;
   L.nmax = nmax; L.maxnb = maxnb; L.cellmax = cellmax;
   size_t o = 0;
   L.off_x = o; o += (size_t)8 * dim * nmax;
+  L.off_acc = o; if (tsize == 4) o += (size_t)8 * (2 * dim + 1) * nmax;
   L.off_u = o; o += (size_t)tsize * dim * nmax; o = (o + 7) & ~(size_t)7;
   L.off_nbr = o; o += (size_t)2 * maxnb * nmax; o = (o + 7) & ~(size_t)7;
   L.off_cnt = o; o += (size_t)4 * cellmax;
@@ -39,7 +42,7 @@ size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax) {
 // Rebuild the cell list and every atom's neighbour list in LDS from the LDS
 // positions.  Same cell rule, pair test (r^2 summed axis by axis without
 // contraction, strict < (rc+skin)^2) and exclusions as the global version.
-template <int DIM>
+template <int DIM, bool HALF>
 __device__ int lds_rebuild(const SysDesc &D, const double *__restrict__ xs, uint16_t *__restrict__ nbr,
                            int *__restrict__ cnt, int *__restrict__ cst, int *__restrict__ cat,
                            const uint8_t *__restrict__ tr_all, int stride, int *lds_int, int &nn_own,
@@ -112,7 +115,7 @@ __device__ int lds_rebuild(const SysDesc &D, const double *__restrict__ xs, uint
           const int q = (q3[2] * D.nc[1] + q3[1]) * D.nc[0] + q3[0];
           for (int p = cst[q]; p < cst[q + 1]; ++p) {
             const int j = cat[p];
-            if (j == i) continue;
+            if (HALF ? j <= i : j == i) continue;   // half lists keep j > i
             const int trj = tr_all[j];
             const int rj = trj >> 1;
             if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
@@ -140,7 +143,9 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   const int tid = threadIdx.x;
   const int n = D.n, stride = L.nmax;
   const int64_t N = A.ntot, off = D.off;
+  constexpr bool HALF = sizeof(T) == 4;
   double *xs = (double *)(lds + L.off_x);
+  double *jacc = (double *)(lds + L.off_acc);   // [2*DIM+1][stride]: F, H u, e of the j side
   T *us = (T *)(lds + L.off_u);
   uint16_t *nbr = (uint16_t *)(lds + L.off_nbr);
   int *cnt = (int *)(lds + L.off_cnt);
@@ -194,8 +199,8 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     int moved = 0;
     if (!compute_only) {
       if (own && role == ROLE_MOBILE) {
-        double z[4];
-        normals4(D.seed, step, (uint32_t)i, 0u, z);
+        double z[3];
+        normals_n<DIM>(D.seed, step, (uint32_t)i, 0u, z);
         double d2 = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -212,8 +217,8 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         if (d2 > D.skin_half2) moved = 1;
       }
       if (tid == 0 && D.n_rigid > 0) {
-        double z[4];
-        normals4(D.seed, step, (uint32_t)n, 0u, z);
+        double z[3];
+        normals_n<DIM>(D.seed, step, (uint32_t)n, 0u, z);
         for (int k = 0; k < DIM; ++k) {
           double vv = sh_VR[k], xx = sh_XR[k];
           vv = vv + D.hdt * sh_FR[k] * D.inv_massR;
@@ -244,6 +249,10 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         xs[k * stride + i] = x[k];
         us[k * stride + i] = (T)u64[k];
       }
+      if constexpr (HALF) {
+#pragma unroll
+        for (int k = 0; k < 2 * DIM + 1; ++k) jacc[k * stride + i] = 0.0;
+      }
     }
     const int need = block_or(moved, lds_int + 24);
     if (need || rebuild_req) {
@@ -259,7 +268,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
           for (int k = 0; k < DIM; ++k) xs[k * stride + i] = xb[k];
         __syncthreads();
       }
-      const int ov = lds_rebuild<DIM>(D, xs, nbr, cnt, cst, cat, tr_all, stride, lds_int, nn, xsrc, i, role);
+      const int ov = lds_rebuild<DIM, HALF>(D, xs, nbr, cnt, cst, cat, tr_all, stride, lds_int, nn, xsrc, i, role);
       if (own) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) xb[k] = xsrc[k];
@@ -287,16 +296,45 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       T ui[3];
 #pragma unroll
       for (int k = 0; k < DIM; ++k) ui[k] = (T)u64[k];
+      if constexpr (HALF) {
+        // half list: the pair's vectors go to i (compensated, registers) and,
+        // negated, to j (float64 LDS atomics)
 #pragma unroll 4
-      for (int q = 0; q < nn; ++q) {
-        const int ent = nbr[q * stride + i];
-        const int j = ent >> 1;
-        double xj[3], dx[3];
-        T uj[3];
+        for (int q = 0; q < nn; ++q) {
+          const int ent = nbr[q * stride + i];
+          const int j = ent >> 1;
+          double xj[3], dx[3];
+          float uj[3];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = us[k * stride + j]; }
-        const double r2 = pair_disp<DIM>(D, x, xj, dx);
-        pair_term<DIM, T>(D, ti * 2 + (ent & 1), r2 < D.rc2, dx, r2, ui, uj, acc);
+          for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = (float)us[k * stride + j]; }
+          const double r2 = pair_disp<DIM>(D, x, xj, dx);
+          const bool live = r2 < D.rc2;
+          float fv[3], hv[3], e;
+          pair_vals_f<DIM>(D, ti * 2 + (ent & 1), live, dx, r2, (const float *)ui, uj, fv, hv, e);
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) { acc.F[k].add(fv[k]); acc.H[k].add(hv[k]); }
+          acc.e.add(0.5f * e);
+          if (live) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+              atomicAdd(&jacc[k * stride + j], -(double)fv[k]);
+              atomicAdd(&jacc[(DIM + k) * stride + j], -(double)hv[k]);
+            }
+            atomicAdd(&jacc[2 * DIM * stride + j], 0.5 * (double)e);
+          }
+        }
+      } else {
+#pragma unroll 4
+        for (int q = 0; q < nn; ++q) {
+          const int ent = nbr[q * stride + i];
+          const int j = ent >> 1;
+          double xj[3], dx[3];
+          T uj[3];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = us[k * stride + j]; }
+          const double r2 = pair_disp<DIM>(D, x, xj, dx);
+          pair_term<DIM, T>(D, ti * 2 + (ent & 1), r2 < D.rc2, dx, r2, ui, uj, acc);
+        }
       }
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
@@ -304,6 +342,16 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         else { F[k] = acc.F[k].get(); H[k] = acc.H[k].get(); }
       }
       if constexpr (sizeof(T) == 8) e_own = acc.e; else e_own = acc.e.get();
+    }
+    if constexpr (HALF) {
+      __syncthreads();   // every pair's j-side share has landed
+      if (own) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) { F[k] += jacc[k * stride + i]; H[k] += jacc[(DIM + k) * stride + i]; }
+        e_own += jacc[2 * DIM * stride + i];
+      }
+    }
+    if (own) {
       sums[0] = e_own;
       {
         double f2 = 0.0;
