@@ -21,7 +21,7 @@ struct SysDesc {
   int64_t off;                 // first batch atom of this system
   int32_t n_rigid, first_rigid;
   int32_t periodic[3];
-  double box[3], hbox[3];
+  double box[3], hbox[3], inv_box[3];  // inv_box = 1/box on periodic axes, else 0
   double mass, inv_mass, massR, inv_massR;
   double eps[4], sig2[4], shift[4];      // [ta*2+tb]
   float eps_f[4], sig2_f[4], shift_f[4];
@@ -158,6 +158,7 @@ struct Scal {
   double hud[3];     // drive Hessian term per rigid atom (k/nR^2) sum_R u
   double sumFb[3];   // bias force summed over rigid atoms
   double bad;        // atoms with a non-finite or runaway force
+  double bias_a, bias_b;  // bias force = bias_a (Hu - F - bias_b u): -dV'/d, g/d
 };
 
 template <int DIM>
@@ -198,13 +199,21 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
   S.g = (S.d < 1e-12) ? 0.0 : -G / S.d;
   S.dv = 0.0; S.dvp = 0.0;
   if (D.bias_on) bias_switch(D, S.g, S.dv, S.dvp);
+  if (S.d >= 1e-12) {
+    const double inv_d = 1.0 / S.d;
+    S.bias_a = -S.dvp * inv_d;
+    S.bias_b = S.g * inv_d;
+  } else {
+    S.bias_a = 0.0;
+    S.bias_b = 0.0;
+  }
   if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0 && D.n_rigid > 0) {
     const double nR = (double)D.n_rigid;
 #pragma unroll
     for (int k = 0; k < dim; ++k) {
       const double sumHu = sums[6 + k] + nR * S.hud[k];
       const double sumF = sums[3 + k] + S.Fd[k];
-      S.sumFb[k] = -S.dvp * ((sumHu - sumF - S.g * sums[9 + k] / S.d) / S.d);
+      S.sumFb[k] = S.bias_a * (sumHu - sumF - S.bias_b * sums[9 + k]);
     }
   }
 }
@@ -342,13 +351,19 @@ __device__ __forceinline__ void pair_vals_f(const SysDesc &D, int tt, bool live,
 // Displacement x_i - x_j (minimum image) and r^2 = (dx*dx + dy*dy) + dz*dz,
 // rounded operation by operation so that the cutoff decision is exactly the
 // float64 one.
+//
+// Branch-free minimum image: dx - L rint(dx/L) (inv_box is 0 on open axes).
+// Every pair of a list is closer than rc + skin <= L/2, and for those this
+// equals the strict rule (subtract/add L beyond +-L/2) exactly: the shift is
+// an exact multiple of L and the single rounding matches.
 template <int DIM>
 __device__ __forceinline__ double pair_disp(const SysDesc &D, const double xi[3], const double xj[3],
                                             double dx[3]) {
   double r2 = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    dx[k] = minimg(xi[k] - xj[k], D.box[k], D.hbox[k], D.periodic[k]);
+    const double raw = xi[k] - xj[k];
+    dx[k] = __builtin_fma(-D.box[k], __builtin_rint(raw * D.inv_box[k]), raw);
     r2 = __dadd_rn(r2, __dmul_rn(dx[k], dx[k]));
   }
   return r2;
@@ -392,6 +407,55 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     v[k] = x;
   }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[k * 16 + wave] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += lds[k * 16 + w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Cross-lane move of a double by a DPP control (both 32-bit halves move the
+// same way; lanes without a source read 0).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  int lo = (int)(unsigned)(b & 0xffffffffull), hi = (int)(unsigned)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wavefront with DPP (quad permutes, row shifts,
+// row broadcasts), fixed order; every lane receives the total (read from lane
+// 63).
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v += dpp_mov_f64<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov_f64<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov_f64<0x114>(v);  // row_shr:4
+  v += dpp_mov_f64<0x118>(v);  // row_shr:8
+  v += dpp_mov_f64<0x142>(v);  // row_bcast:15
+  v += dpp_mov_f64<0x143>(v);  // row_bcast:31
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Workgroup sum of NV doubles: DPP within each wavefront, then the wave
+// totals added in wave order.  lds must hold NV * 16 doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum_dpp(double (&v)[NV], double *lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_f64(v[k]);
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) lds[k * 16 + wave] = v[k];

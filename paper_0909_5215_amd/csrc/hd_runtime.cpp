@@ -188,6 +188,7 @@ void fill_desc(const hd_ctx *ctx, const SysHost &s, SysDesc &D) {
     D.periodic[k] = (k < s.dim) ? s.periodic[k] : 0;
     D.box[k] = s.box[k];
     D.hbox[k] = 0.5 * s.box[k];
+    D.inv_box[k] = (k < s.dim && s.periodic[k]) ? 1.0 / s.box[k] : 0.0;
     D.XR0[k] = s.XR0[k];
   }
   D.mass = s.mass;

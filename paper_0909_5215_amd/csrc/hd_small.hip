@@ -15,7 +15,7 @@ namespace hdk {
 
 struct SmallLayout {
   int nmax, maxnb, cellmax;
-  size_t off_x, off_acc, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
+  size_t off_x, off_acc, off_rig, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
 };
 
 // float32 systems use half lists (each pair once); the partner's share of
@@ -26,6 +26,8 @@ __host__ __device__ inline SmallLayout small_layout(int dim, int tsize, int nmax
   size_t o = 0;
   L.off_x = o; o += (size_t)8 * dim * nmax;
   L.off_acc = o; if (tsize == 4) o += (size_t)8 * (2 * dim + 1) * nmax;
+  // rigid-layer atoms' F, H u and u, one slot per rigid atom (rank order)
+  L.off_rig = o; o += (size_t)8 * 3 * dim * nmax;
   L.off_u = o; o += (size_t)tsize * dim * nmax; o = (o + 7) & ~(size_t)7;
   L.off_nbr = o; o += (size_t)2 * maxnb * nmax; o = (o + 7) & ~(size_t)7;
   L.off_cnt = o; o += (size_t)4 * cellmax;
@@ -146,6 +148,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   constexpr bool HALF = sizeof(T) == 4;
   double *xs = (double *)(lds + L.off_x);
   double *jacc = (double *)(lds + L.off_acc);   // [2*DIM+1][stride]: F, H u, e of the j side
+  double *rig = (double *)(lds + L.off_rig);    // [3*DIM][stride]: rigid atoms' F, H u, u
   T *us = (T *)(lds + L.off_u);
   uint16_t *nbr = (uint16_t *)(lds + L.off_nbr);
   int *cnt = (int *)(lds + L.off_cnt);
@@ -185,6 +188,9 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   }
   __syncthreads();
   if (sh_flags & FLAG_UNSTABLE) return;
+  // rank of each rigid atom among the rigid atoms (fixed summation order)
+  int rrank_total = 0;
+  const int rrank = block_exscan((own && role == ROLE_RIGID) ? 1 : 0, lds_int, rrank_total);
 
   const bool compute_only = (mode & 1) != 0;
   const int64_t iters = compute_only ? 1 : nsteps;
@@ -365,10 +371,30 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       }
       if (role == ROLE_RIGID) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) { sums[3 + k] = F[k]; sums[6 + k] = H[k]; sums[9 + k] = u64[k]; }
+        for (int k = 0; k < DIM; ++k) {
+          rig[k * stride + rrank] = F[k];
+          rig[(DIM + k) * stride + rrank] = H[k];
+          rig[(2 * DIM + k) * stride + rrank] = u64[k];
+        }
       }
     }
-    block_sum<NRED>(sums, red);
+    {
+      // E, d^2, G and the runaway count over the workgroup (DPP); the rigid
+      // layer's sums from its slots, in rank order
+      double v4[4] = {sums[0], sums[1], sums[2], sums[12]};
+      block_sum_dpp<4>(v4, red);
+      sums[0] = v4[0]; sums[1] = v4[1]; sums[2] = v4[2]; sums[12] = v4[3];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int r = 0; r < rrank_total; ++r) {
+          a += rig[k * stride + r];
+          b += rig[(DIM + k) * stride + r];
+          c += rig[(2 * DIM + k) * stride + r];
+        }
+        sums[3 + k] = a; sums[6 + k] = b; sums[9 + k] = c;
+      }
+    }
     const int64_t estep = compute_only ? step : step + 1;
     double XRl[3] = {sh_XR[0], sh_XR[1], sh_XR[2]};
     Scal S;
@@ -380,7 +406,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         if (role != ROLE_FIXED) {
           if (role == ROLE_RIGID) { f += S.Fd[k] / (double)D.n_rigid; h += S.hud[k]; }
           if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0)
-            fb = -S.dvp * ((h - f - S.g * u64[k] / S.d) / S.d);
+            fb = S.bias_a * (h - f - S.bias_b * u64[k]);
         }
         F[k] = f;
         H[k] = h;
