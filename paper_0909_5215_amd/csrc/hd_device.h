@@ -129,8 +129,10 @@ __device__ __forceinline__ void normals_n(uint64_t seed, int64_t step, uint32_t 
   const double two_pi = 6.283185307179586;
   const double u0 = ((double)c[0] + 0.5) * s, u1 = ((double)c[1] + 0.5) * s;
   const double r0 = sqrt(-2.0 * log(u0));
-  z[0] = r0 * cos(two_pi * u1);
-  z[1] = r0 * sin(two_pi * u1);
+  double sn, cs;
+  sincos(two_pi * u1, &sn, &cs);
+  z[0] = r0 * cs;
+  z[1] = r0 * sn;
   if constexpr (NZ > 2) {
     const double u2 = ((double)c[2] + 0.5) * s, u3 = ((double)c[3] + 0.5) * s;
     z[2] = sqrt(-2.0 * log(u2)) * cos(two_pi * u3);
@@ -463,11 +465,32 @@ __device__ __forceinline__ void block_sum_dpp(double (&v)[NV], double *lds) {
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
+    double t[16];
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t[w] = lds[k * 16 + w];  // all loads in flight at once
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += lds[k * 16 + w];
+#pragma unroll
+    for (int w = 0; w < 16; ++w) s += (w < nw) ? t[w] : 0.0;
     v[k] = s;
   }
   __syncthreads();
+}
+
+// Workgroup OR of one flag per thread with a single barrier: each wavefront
+// writes its ballot to its own slot (slots alternate between two banks so the
+// next call needs no clearing barrier).  lds_int holds >= 32 ints.
+__device__ __forceinline__ int block_any(int v, int *lds_int, int &parity) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = (blockDim.x + 63) >> 6;
+  const unsigned long long b = __ballot(v != 0);
+  int *slot = lds_int + 16 * parity;
+  if (lane == 0) slot[wave] = b != 0ull ? 1 : 0;
+  __syncthreads();
+  int r = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) r |= (w < nw) ? slot[w] : 0;
+  parity ^= 1;
+  return r;
 }
 
 __device__ __forceinline__ int block_or(int v, int *lds_int) {

@@ -14,20 +14,24 @@
 namespace hdk {
 
 struct SmallLayout {
-  int nmax, maxnb, cellmax;
-  size_t off_x, off_acc, off_rig, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
+  int nmax, maxnb, cellmax, rigmax;
+  size_t off_x, off_acc, off_rig, off_ref, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
 };
 
 // float32 systems use half lists (each pair once); the partner's share of
 // F, H u and the energy is accumulated in float64 in LDS (acc region).
-__host__ __device__ inline SmallLayout small_layout(int dim, int tsize, int nmax, int maxnb, int cellmax) {
+__host__ __device__ inline SmallLayout small_layout(int dim, int tsize, int nmax, int maxnb, int cellmax,
+                                                    int rigmax) {
   SmallLayout L;
-  L.nmax = nmax; L.maxnb = maxnb; L.cellmax = cellmax;
+  L.nmax = nmax; L.maxnb = maxnb; L.cellmax = cellmax; L.rigmax = rigmax > 0 ? rigmax : 1;
   size_t o = 0;
   L.off_x = o; o += (size_t)8 * dim * nmax;
   L.off_acc = o; if (tsize == 4) o += (size_t)8 * (2 * dim + 1) * nmax;
-  // rigid-layer atoms' F, H u and u, one slot per rigid atom (rank order)
-  L.off_rig = o; o += (size_t)8 * 3 * dim * nmax;
+  // rigid-layer atoms' F, H u and u, and their offsets c_i, one slot per
+  // rigid atom (rank order)
+  L.off_rig = o; o += (size_t)8 * 4 * dim * L.rigmax;
+  // per-atom reference r_O and positions at the last build
+  L.off_ref = o; o += (size_t)8 * 2 * dim * nmax;
   L.off_u = o; o += (size_t)tsize * dim * nmax; o = (o + 7) & ~(size_t)7;
   L.off_nbr = o; o += (size_t)2 * maxnb * nmax; o = (o + 7) & ~(size_t)7;
   L.off_cnt = o; o += (size_t)4 * cellmax;
@@ -37,8 +41,8 @@ __host__ __device__ inline SmallLayout small_layout(int dim, int tsize, int nmax
   return L;
 }
 
-size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax) {
-  return small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax).bytes;
+size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax, int rigmax) {
+  return small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax, rigmax).bytes;
 }
 
 // Rebuild the cell list and every atom's neighbour list in LDS from the LDS
@@ -117,7 +121,9 @@ __device__ int lds_rebuild(const SysDesc &D, const double *__restrict__ xs, uint
           const int q = (q3[2] * D.nc[1] + q3[1]) * D.nc[0] + q3[0];
           for (int p = cst[q]; p < cst[q + 1]; ++p) {
             const int j = cat[p];
-            if (HALF ? j <= i : j == i) continue;   // half lists keep j > i
+            // half lists: each pair once, owned by i when (j > i) xor (i + j odd),
+            // which gives every atom about half of its neighbours
+            if (j == i || (HALF && ((j > i) == (((i + j) & 1) != 0)))) continue;
             const int trj = tr_all[j];
             const int rj = trj >> 1;
             if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
@@ -142,33 +148,35 @@ __device__ int lds_rebuild(const SysDesc &D, const double *__restrict__ xs, uint
 template <int DIM, typename T>
 __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Arrays &A,
                           int64_t nsteps, int mode, char *lds, const SmallLayout L) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = D.n, stride = L.nmax;
   const int64_t N = A.ntot, off = D.off;
   constexpr bool HALF = sizeof(T) == 4;
   double *xs = (double *)(lds + L.off_x);
   double *jacc = (double *)(lds + L.off_acc);   // [2*DIM+1][stride]: F, H u, e of the j side
-  double *rig = (double *)(lds + L.off_rig);    // [3*DIM][stride]: rigid atoms' F, H u, u
+  const int rstride = L.rigmax;
+  double *rig = (double *)(lds + L.off_rig);    // [3*DIM][rigmax]: rigid atoms' F, H u, u
+  double *cfs = rig + 3 * DIM * rstride;        // [DIM][rigmax]: rigid offsets c_i
+  double *rOs = (double *)(lds + L.off_ref);    // [DIM][stride] r_O
+  double *xbs = rOs + DIM * stride;             // [DIM][stride] positions at the last build
   T *us = (T *)(lds + L.off_u);
   uint16_t *nbr = (uint16_t *)(lds + L.off_nbr);
   int *cnt = (int *)(lds + L.off_cnt);
   int *cst = (int *)(lds + L.off_cst);
   int *cat = (int *)(lds + L.off_cat);
 
-  __shared__ double red[NRED * 16];
+  __shared__ double red[2][4 * 16];   // cross-wave sums, alternating by step
   __shared__ int lds_int[32];
+  __shared__ int vote[32];
   __shared__ uint8_t tr_all[1024];
-  __shared__ double sh_XR[3], sh_VR[3], sh_FR[3], sh_clock[2];
-  __shared__ int64_t sh_step;
-  __shared__ int sh_flags, sh_rebuilds;
+  __shared__ double sh_zR[2][3];      // rigid-body noise, drawn one step ahead
   __shared__ Scal sh_out;
 
   const int i = tid;
   const bool own = i < n;
   const int64_t a = off + i;
   int tr = 0, role = ROLE_FIXED;
-  double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, ft[3] = {0, 0, 0}, rO[3] = {0, 0, 0}, xb[3] = {0, 0, 0},
-         cofs[3] = {0, 0, 0};
+  double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, ft[3] = {0, 0, 0};
   if (own) {
     tr = A.tr[a];
     role = tr >> 1;
@@ -176,33 +184,46 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       x[k] = A.x[k * N + a]; v[k] = A.v[k * N + a]; ft[k] = A.ftot[k * N + a];
-      rO[k] = A.rO[k * N + a]; xb[k] = A.xb[k * N + a]; cofs[k] = A.cofs[k * N + a];
+      rOs[k * stride + i] = A.rO[k * N + a];
+      xbs[k * stride + i] = A.xb[k * N + a];
     }
   }
-  if (tid == 0) {
-    for (int k = 0; k < 3; ++k) { sh_XR[k] = stg->XR[k]; sh_VR[k] = stg->VR[k]; sh_FR[k] = stg->FR[k]; }
-    sh_clock[0] = stg->t_md; sh_clock[1] = stg->t_hyper;
-    sh_step = stg->step;
-    sh_flags = stg->flags;
-    sh_rebuilds = stg->n_rebuilds;
+  // the rigid body, the step counter and the clock are kept by every thread
+  // (identical arithmetic everywhere, so no broadcast barrier is needed)
+  double XR[3], VR[3], FR[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { XR[k] = stg->XR[k]; VR[k] = stg->VR[k]; FR[k] = stg->FR[k]; }
+  int64_t step = stg->step;
+  double t_md = stg->t_md, t_hyper = stg->t_hyper;
+  int flags = stg->flags, rebuilds = stg->n_rebuilds;
+  const int rebuild_state = stg->rebuild;
+  if (flags & FLAG_UNSTABLE) return;
+  const bool compute_only = (mode & 1) != 0;
+  const bool rigid_body = D.n_rigid > 0;
+  if (!compute_only && rigid_body && tid == 0) {
+    double z[3];
+    normals_n<DIM>(D.seed, step, (uint32_t)n, 0u, z);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) sh_zR[step & 1][k] = z[k];
   }
-  __syncthreads();
-  if (sh_flags & FLAG_UNSTABLE) return;
   // rank of each rigid atom among the rigid atoms (fixed summation order)
   int rrank_total = 0;
   const int rrank = block_exscan((own && role == ROLE_RIGID) ? 1 : 0, lds_int, rrank_total);
+  if (own && role == ROLE_RIGID)
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) cfs[k * rstride + rrank] = A.cofs[k * N + a];
 
-  const bool compute_only = (mode & 1) != 0;
   const int64_t iters = compute_only ? 1 : nsteps;
   // the list lives in LDS only for this launch: rebuild at the start, from
   // the recorded build positions unless an evaluation was requested
-  int rebuild_req = (compute_only || stg->rebuild == 1) ? 1 : 2;
+  int rebuild_req = (compute_only || rebuild_state == 1) ? 1 : 2;
+  int vote_parity = 0;
   int nn = 0;
   double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, e_own = 0.0, fbv[3] = {0, 0, 0};
 
   for (int64_t it = 0; it < iters; ++it) {
-    const int64_t step = sh_step;
     int moved = 0;
+    // ---- B A O A: mobile atoms, and the rigid body in every thread --------
     if (!compute_only) {
       if (own && role == ROLE_MOBILE) {
         double z[3];
@@ -217,41 +238,40 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
           xx = xx + D.hdt * vv;
           x[k] = wrapx(xx, D.box[k], D.periodic[k]);
           v[k] = vv;
-          const double dd = minimg(x[k] - xb[k], D.box[k], D.hbox[k], D.periodic[k]);
+          const double dd = minimg(x[k] - xbs[k * stride + i], D.box[k], D.hbox[k], D.periodic[k]);
           d2 += dd * dd;
         }
         if (d2 > D.skin_half2) moved = 1;
       }
-      if (tid == 0 && D.n_rigid > 0) {
-        double z[3];
-        normals_n<DIM>(D.seed, step, (uint32_t)n, 0u, z);
+      if (rigid_body) {
+#pragma unroll
         for (int k = 0; k < DIM; ++k) {
-          double vv = sh_VR[k], xx = sh_XR[k];
-          vv = vv + D.hdt * sh_FR[k] * D.inv_massR;
+          double vv = VR[k], xx = XR[k];
+          vv = vv + D.hdt * FR[k] * D.inv_massR;
           xx = xx + D.hdt * vv;
-          vv = D.c1 * vv + D.c2R * z[k];
+          vv = D.c1 * vv + D.c2R * sh_zR[step & 1][k];
           xx = xx + D.hdt * vv;
-          sh_XR[k] = xx;
-          sh_VR[k] = vv;
+          XR[k] = xx;
+          VR[k] = vv;
         }
       }
-      __syncthreads();
     }
+    // ---- rigid atoms at X_R + c_i; u = r - r_O (eq. 7); publish to LDS -----
     double u64[3] = {0, 0, 0};
     if (own) {
       if (role == ROLE_RIGID) {
         double d2 = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-          x[k] = wrapx(sh_XR[k] + cofs[k], D.box[k], D.periodic[k]);
-          const double dd = minimg(x[k] - xb[k], D.box[k], D.hbox[k], D.periodic[k]);
+          x[k] = wrapx(XR[k] + cfs[k * rstride + rrank], D.box[k], D.periodic[k]);
+          const double dd = minimg(x[k] - xbs[k * stride + i], D.box[k], D.hbox[k], D.periodic[k]);
           d2 += dd * dd;
         }
         if (!compute_only && d2 > D.skin_half2) moved = 1;
       }
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
-        if (role != ROLE_FIXED) u64[k] = minimg(x[k] - rO[k], D.box[k], D.hbox[k], D.periodic[k]);
+        if (role != ROLE_FIXED) u64[k] = minimg(x[k] - rOs[k * stride + i], D.box[k], D.hbox[k], D.periodic[k]);
         xs[k * stride + i] = x[k];
         us[k * stride + i] = (T)u64[k];
       }
@@ -260,29 +280,28 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         for (int k = 0; k < 2 * DIM + 1; ++k) jacc[k * stride + i] = 0.0;
       }
     }
-    const int need = block_or(moved, lds_int + 24);
+    const int need = block_any(moved, vote, vote_parity);   // barrier A
     if (need || rebuild_req) {
       // at a launch start the list is rebuilt from the recorded build
       // positions, which reproduces the list of an uninterrupted run
       const bool from_xb = !need && rebuild_req == 2;
       double xsrc[3] = {0, 0, 0};
+      if (own)
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) xsrc[k] = from_xb ? xb[k] : x[k];
+        for (int k = 0; k < DIM; ++k) xsrc[k] = from_xb ? xbs[k * stride + i] : x[k];
       if (from_xb) {
         if (own)
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) xs[k * stride + i] = xb[k];
+          for (int k = 0; k < DIM; ++k) xs[k * stride + i] = xsrc[k];
         __syncthreads();
       }
       const int ov = lds_rebuild<DIM, HALF>(D, xs, nbr, cnt, cst, cat, tr_all, stride, lds_int, nn, xsrc, i, role);
       if (own) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) xb[k] = xsrc[k];
+        for (int k = 0; k < DIM; ++k) xbs[k * stride + i] = xsrc[k];
       }
-      if (tid == 0) {
-        if (!from_xb) sh_rebuilds++;
-        if (ov) sh_flags |= FLAG_NBR_OVERFLOW;
-      }
+      if (!from_xb) ++rebuilds;
+      if (ov) flags |= FLAG_NBR_OVERFLOW;
       if (from_xb) {
         if (own)
 #pragma unroll
@@ -292,9 +311,6 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       rebuild_req = 0;
     }
     // ---- pair pass from LDS ------------------------------------------------
-    double sums[NRED];
-#pragma unroll
-    for (int q = 0; q < NRED; ++q) sums[q] = 0.0;
     if (own) {
       PairAcc<T> acc;
       acc.init();
@@ -304,19 +320,26 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       for (int k = 0; k < DIM; ++k) ui[k] = (T)u64[k];
       if constexpr (HALF) {
         // half list: the pair's vectors go to i (compensated, registers) and,
-        // negated, to j (float64 LDS atomics)
-#pragma unroll 4
-        for (int q = 0; q < nn; ++q) {
-          const int ent = nbr[q * stride + i];
-          const int j = ent >> 1;
-          double xj[3], dx[3];
-          float uj[3];
+        // negated, to j (float64 LDS atomics).  The next neighbour's data are
+        // loaded before this pair's atomics are issued, so that LDS latency
+        // overlaps the arithmetic.
+        int ent = nn > 0 ? nbr[i] : 0;
+        double xj[3];
+        float uj[3];
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = (float)us[k * stride + j]; }
+        for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + (ent >> 1)]; uj[k] = (float)us[k * stride + (ent >> 1)]; }
+        for (int q = 0; q < nn; ++q) {
+          const int j = ent >> 1, tj = ent & 1;
+          double dx[3];
           const double r2 = pair_disp<DIM>(D, x, xj, dx);
           const bool live = r2 < D.rc2;
           float fv[3], hv[3], e;
-          pair_vals_f<DIM>(D, ti * 2 + (ent & 1), live, dx, r2, (const float *)ui, uj, fv, hv, e);
+          pair_vals_f<DIM>(D, ti * 2 + tj, live, dx, r2, (const float *)ui, uj, fv, hv, e);
+          if (q + 1 < nn) {
+            ent = nbr[(q + 1) * stride + i];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + (ent >> 1)]; uj[k] = (float)us[k * stride + (ent >> 1)]; }
+          }
 #pragma unroll
           for (int k = 0; k < DIM; ++k) { acc.F[k].add(fv[k]); acc.H[k].add(hv[k]); }
           acc.e.add(0.5f * e);
@@ -349,56 +372,82 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       }
       if constexpr (sizeof(T) == 8) e_own = acc.e; else e_own = acc.e.get();
     }
+    // the rigid body's noise for the next step, drawn while others finish
+    if (!compute_only && rigid_body && tid == 0) {
+      double z[3];
+      normals_n<DIM>(D.seed, step + 1, (uint32_t)n, 0u, z);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) sh_zR[(step + 1) & 1][k] = z[k];
+    }
     if constexpr (HALF) {
-      __syncthreads();   // every pair's j-side share has landed
+      __syncthreads();   // barrier B: every pair's j-side share has landed
       if (own) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) { F[k] += jacc[k * stride + i]; H[k] += jacc[(DIM + k) * stride + i]; }
         e_own += jacc[2 * DIM * stride + i];
       }
     }
+    double v4[4] = {0.0, 0.0, 0.0, 0.0};
     if (own) {
-      sums[0] = e_own;
-      {
-        double f2 = 0.0;
+      v4[0] = e_own;
+      double f2 = 0.0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) f2 += F[k] * F[k];
-        sums[12] = (f2 <= kForceLimit2) ? 0.0 : 1.0;
-      }
+      for (int k = 0; k < DIM; ++k) f2 += F[k] * F[k];
+      v4[3] = (f2 <= kForceLimit2) ? 0.0 : 1.0;
       if (role != ROLE_FIXED) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) { sums[1] += u64[k] * u64[k]; sums[2] += F[k] * u64[k]; }
+        for (int k = 0; k < DIM; ++k) { v4[1] += u64[k] * u64[k]; v4[2] += F[k] * u64[k]; }
       }
       if (role == ROLE_RIGID) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-          rig[k * stride + rrank] = F[k];
-          rig[(DIM + k) * stride + rrank] = H[k];
-          rig[(2 * DIM + k) * stride + rrank] = u64[k];
+          rig[k * rstride + rrank] = F[k];
+          rig[(DIM + k) * rstride + rrank] = H[k];
+          rig[(2 * DIM + k) * rstride + rrank] = u64[k];
         }
       }
     }
+    // ---- per-system sums: E, d^2, G, runaway count (DPP + fixed wave order;
+    // barrier C), rigid-layer sums from their slots in rank order ------------
     {
-      // E, d^2, G and the runaway count over the workgroup (DPP); the rigid
-      // layer's sums from its slots, in rank order
-      double v4[4] = {sums[0], sums[1], sums[2], sums[12]};
-      block_sum_dpp<4>(v4, red);
-      sums[0] = v4[0]; sums[1] = v4[1]; sums[2] = v4[2]; sums[12] = v4[3];
+      double *rb = red[step & 1];
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        double a = 0.0, b = 0.0, c = 0.0;
-        for (int r = 0; r < rrank_total; ++r) {
-          a += rig[k * stride + r];
-          b += rig[(DIM + k) * stride + r];
-          c += rig[(2 * DIM + k) * stride + r];
-        }
-        sums[3 + k] = a; sums[6 + k] = b; sums[9 + k] = c;
+      for (int k = 0; k < 4; ++k) v4[k] = wave_sum_f64(v4[k]);
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rb[k * 16 + wave] = v4[k];
       }
+      __syncthreads();
+      const int nw = (blockDim.x + 63) >> 6;
+      double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int w = 0; w < nw; ++w) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc4[k] += rb[k * 16 + w];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v4[k] = acc4[k];
+    }
+    double sums[NRED];
+    sums[0] = v4[0]; sums[1] = v4[1]; sums[2] = v4[2]; sums[12] = v4[3];
+    {
+      double rs[3 * DIM];
+#pragma unroll
+      for (int q = 0; q < 3 * DIM; ++q) rs[q] = 0.0;
+      for (int base = 0; base < rrank_total; base += 64) {
+        const bool in = base + lane < rrank_total;
+#pragma unroll
+        for (int q = 0; q < 3 * DIM; ++q)
+          rs[q] += wave_sum_f64(in ? rig[q * rstride + base + lane] : 0.0);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) { sums[3 + k] = 0.0; sums[6 + k] = 0.0; sums[9 + k] = 0.0; }
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { sums[3 + k] = rs[k]; sums[6 + k] = rs[DIM + k]; sums[9 + k] = rs[2 * DIM + k]; }
     }
     const int64_t estep = compute_only ? step : step + 1;
-    double XRl[3] = {sh_XR[0], sh_XR[1], sh_XR[2]};
     Scal S;
-    eval_scalars<DIM>(D, sums, XRl, estep, S);
+    eval_scalars<DIM>(D, sums, XR, estep, S);
+    // ---- bias force, total force, final B ------------------------------------
     if (own) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
@@ -415,33 +464,33 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         if (!compute_only && role == ROLE_MOBILE) v[k] = v[k] + D.hdt * ft[k] * D.inv_mass;
       }
     }
-    if (tid == 0) {
-      for (int k = 0; k < DIM; ++k) sh_FR[k] = sums[3 + k] + S.Fd[k] + S.sumFb[k];
-      if (!compute_only) {
-        for (int k = 0; k < DIM; ++k) sh_VR[k] = sh_VR[k] + D.hdt * sh_FR[k] * D.inv_massR;
-        sh_clock[0] += D.dt;
-        sh_clock[1] += D.dt * exp(S.dv / D.kT);
-        sh_step = step + 1;
-      }
-      if (!isfinite(S.e_pot) || S.bad > 0.0) sh_flags |= FLAG_UNSTABLE;
-      sh_out = S;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) FR[k] = sums[3 + k] + S.Fd[k] + S.sumFb[k];
+    if (!compute_only) {
+      if (rigid_body)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) VR[k] = VR[k] + D.hdt * FR[k] * D.inv_massR;
+      t_md += D.dt;
+      if (wave == 0) t_hyper += D.dt * exp(S.dv / D.kT);
+      step = step + 1;
     }
-    __syncthreads();
-    if (sh_flags & FLAG_UNSTABLE) break;
+    const bool bad = !isfinite(S.e_pot) || S.bad > 0.0;
+    if (bad) flags |= FLAG_UNSTABLE;
+    if ((it == iters - 1 || bad) && tid == 0) sh_out = S;
+    if (bad) break;
   }
-  const Scal &S = sh_out;
   // ---- write back ----------------------------------------------------------
   double ek[1] = {0.0};
   if (own) {
     T *u = (T *)A.u;
     if (role == ROLE_RIGID) {
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) v[k] = sh_VR[k];
+      for (int k = 0; k < DIM; ++k) v[k] = VR[k];
     }
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       A.x[k * N + a] = x[k]; A.v[k * N + a] = v[k]; A.ftot[k * N + a] = ft[k];
-      A.xb[k * N + a] = xb[k];
+      A.xb[k * N + a] = xbs[k * stride + i];
       A.flj[k * N + a] = F[k]; A.hu[k * N + a] = H[k]; A.fb[k * N + a] = fbv[k];
       u[k * N + a] = us[k * stride + i];
     }
@@ -455,20 +504,22 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 #pragma unroll
       for (int k = 0; k < DIM; ++k) ek[0] += 0.5 * D.mass * v[k] * v[k];
   }
-  block_sum<1>(ek, red);
+  __syncthreads();
+  block_sum<1>(ek, red[0]);
   if (tid == 0) {
+    const Scal &S = sh_out;
     double ekr = 0.0;
-    for (int k = 0; k < DIM; ++k) ekr += 0.5 * D.massR * sh_VR[k] * sh_VR[k];
-    for (int k = 0; k < 3; ++k) { stg->XR[k] = sh_XR[k]; stg->VR[k] = sh_VR[k]; stg->FR[k] = sh_FR[k]; }
-    stg->t_md = sh_clock[0];
-    stg->t_hyper = sh_clock[1];
-    stg->step = sh_step;
+    for (int k = 0; k < DIM; ++k) ekr += 0.5 * D.massR * VR[k] * VR[k];
+    for (int k = 0; k < 3; ++k) { stg->XR[k] = XR[k]; stg->VR[k] = VR[k]; stg->FR[k] = FR[k]; }
+    stg->t_md = t_md;
+    stg->t_hyper = t_hyper;
+    stg->step = step;
     stg->e_lj = S.e_lj; stg->v_drive = S.v_drive; stg->e_pot = S.e_pot;
     stg->e_kin = ek[0] + (D.n_rigid > 0 ? ekr : 0.0);
     stg->d = S.d; stg->g = S.g; stg->dv = S.dv; stg->dvp = S.dvp;
     stg->x_slider = S.xs; stg->x_tip = S.x_tip; stg->f_lat = S.f_lat;
-    stg->flags = sh_flags;
-    stg->n_rebuilds = sh_rebuilds;
+    stg->flags = flags;
+    stg->n_rebuilds = rebuilds;
     stg->rebuild = 0;
   }
 }
@@ -514,8 +565,8 @@ hipError_t small_allow_lds(int prec, int dim, size_t bytes) {
   return dim == 2 ? allow_lds_d<float, 2>((int)bytes) : allow_lds_d<float, 3>((int)bytes);
 }
 
-size_t small_group_bytes(int prec, int dim, int nmax, int maxnb, int cellmax) {
-  return small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax).bytes;
+size_t small_group_bytes(int prec, int dim, int nmax, int maxnb, int cellmax, int rigmax) {
+  return small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax, rigmax).bytes;
 }
 
 template <typename T, int DIM>
@@ -529,11 +580,11 @@ static hipError_t launch_small_d(const SysDesc *descs, SysState *states, const A
 }
 
 hipError_t launch_small(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
-                        const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax,
+                        const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax, int rigmax,
                         int64_t nsteps, int mode, hipStream_t stream) {
   if (nsys <= 0) return hipSuccess;
   if (nmax > 1024) return hipErrorInvalidValue;
-  const SmallLayout L = small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax);
+  const SmallLayout L = small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax, rigmax);
   const int block = nmax <= 256 ? 256 : (nmax <= 512 ? 512 : 1024);
   if (prec == 0)
     return dim == 2 ? launch_small_d<double, 2>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream)
