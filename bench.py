@@ -28,6 +28,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "biased LJ atom-steps/s: batched FP32 vs plain FP64, force rel err ≤1e-5"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_0909_5215_amd", "csrc")
+
+# HBM bytes per launch of the stepping kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of this benchmark, each
+# scaled by what the counter reads for a plain 256 MiB device copy run in the
+# same process (FETCH_SIZE reads 131093 KiB for 262144 KiB moved: factor 2.0;
+# WRITE_SIZE reads 262144 KiB: factor 1.0).  Keyed by workload and kernel, and
+# tied to a hash of the kernel's sources: once they change, the figure no
+# longer describes the kernel and the traffic is reported as null.
+HBM_COUNTERS = {
+    ("C2", "k_small<float, 2, 0, 512>"): {
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "36bdf10fc626c456",
+        "fetch_kib": 867.8, "fetch_scale": 2.0, "write_kib": 2449.1, "write_scale": 1.0,
+    },
+}
 
 
 def parse():
@@ -106,6 +121,27 @@ def prepare(hd, specs, quench_steps, prerun_steps, block):
         states.append(ctx.get_state(k))
     ctx.close()
     return specs, states
+
+
+def src_hash(files):
+    import hashlib
+    m = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def stepping_kernel(specs, block):
+    """Name of the kernel that carries the float32 steps: the LDS-resident
+    kernel when every system fits one workgroup; otherwise the grid kernels,
+    timed together as one step."""
+    nmax = max(s.n for s in specs)
+    dim = specs[0].dim
+    if nmax <= 1024 and all(s.dim == dim for s in specs):
+        b = block if block else (256 if nmax <= 256 else (512 if nmax <= 512 else 1024))
+        return f"k_small<float, {dim}, 0, {b}>"
+    return "grid step (kg_* kernels, timed as a whole)"
 
 
 def make_run_ctx(hd, specs, states, precision, exec_mode, block):
@@ -208,17 +244,25 @@ def main():
     log(f"batched fp32: {value:.4g} atom-steps/s, wall {wall:.3f}s, events {ev_ms:.1f} ms over {launches} launches")
     states_x = [(ctx.positions(k), ctx.velocities(k)) for k in range(len(specs))]
 
-    # roofline of the dominant kernel (the batched persistent kernel): the
+    # roofline of the dominant kernel (timed with HIP events on the stream it
+    # runs on, averaged over its launches in the timed region): the
     # algorithmic bytes are the per-atom state read and written once per step
     # (x and v read+written, r_O read, float64): 5*D*8 bytes per atom-step
     bytes_per_atom_step = 5 * dim * 8
     steps_per_launch = args.steps / max(launches, 1)
     avg_launch_s = (ev_ms / 1e3) / max(launches, 1)
     achieved = bytes_per_atom_step * n_atoms * steps_per_launch / avg_launch_s / 1e9
+    kname = stepping_kernel(specs, args.block)
+    traffic, traffic_bytes = None, None
+    rec = HBM_COUNTERS.get((args.config, kname))
+    if rec and src_hash(rec["src"]) == rec["sha"]:
+        traffic_bytes = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+        traffic = round(traffic_bytes / avg_launch_s / 1e9, 4)
     roof = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
-            "kernel": "k_batched<float>", "avg_launch_ms": round(ev_ms / max(launches, 1), 4),
-            "steps_per_launch": steps_per_launch, "bytes_per_atom_step": bytes_per_atom_step}
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
+            "kernel": kname, "avg_launch_ms": round(ev_ms / max(launches, 1), 4),
+            "steps_per_launch": steps_per_launch, "bytes_per_atom_step": bytes_per_atom_step,
+            "traffic_bytes_per_launch": traffic_bytes}
 
     # ---- plain float64 single-system path -----------------------------------
     plain = None

@@ -1120,14 +1120,19 @@ hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int
   HIPCHK(hipMemcpyAsync(nnb.data(), ctx->A.nnb + D.off, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipMemcpyAsync(list.data(), ctx->A.nbr + D.nbr_off, sizeof(int32_t) * list.size(), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  int64_t cnt = 0;
+  // full lists hold each pair under both atoms, half lists under one of them
+  // (either one): collect (min, max) and drop duplicates
+  std::vector<std::pair<int32_t, int32_t>> pr;
   for (int i = 0; i < s.n; ++i)
     for (int q = 0; q < nnb[i]; ++q) {
       const int j = list[(size_t)q * s.n + i] >> 1;
-      if (j <= i) continue;
-      if (cnt < cap) { ij[2 * cnt] = i; ij[2 * cnt + 1] = j; }
-      ++cnt;
+      if (j == i) continue;
+      pr.emplace_back(std::min(i, j), std::max(i, j));
     }
+  std::sort(pr.begin(), pr.end());
+  pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+  const int64_t cnt = (int64_t)pr.size();
+  for (int64_t k = 0; k < cnt && k < cap; ++k) { ij[2 * k] = pr[k].first; ij[2 * k + 1] = pr[k].second; }
   *n_pairs = cnt;
   return HD_OK;
 }
