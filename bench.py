@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--quench-steps", type=int, default=3000)
     ap.add_argument("--prerun-steps", type=int, default=2000)
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -132,15 +133,18 @@ def src_hash(files):
     return m.hexdigest()[:16]
 
 
-def stepping_kernel(specs, block):
-    """Name of the kernel that carries the float32 steps: the LDS-resident
-    kernel when every system fits one workgroup; otherwise the grid kernels,
-    timed together as one step."""
+def stepping_kernel(specs, sched):
+    """Name of the kernel that carries the float32 steps under the chosen
+    launch shape: the LDS-resident kernel when every system runs in it, the
+    one-workgroup global kernel, or the grid kernels timed together as one
+    step."""
     nmax = max(s.n for s in specs)
     dim = specs[0].dim
-    if nmax <= 1024 and all(s.dim == dim for s in specs):
-        b = block if block else (256 if nmax <= 256 else (512 if nmax <= 512 else 1024))
-        return f"k_small<float, {dim}, 0, {b}>"
+    same_dim = all(s.dim == dim for s in specs)
+    if sched["lds_resident"] and nmax <= 1024 and same_dim:
+        return f"k_small<float, {dim}, 0, {sched['small_block']}>"
+    if sched["persistent_large"] and same_dim:
+        return f"k_batched<float, {dim}, 0, {sched['large_block']}>"
     return "grid step (kg_* kernels, timed as a whole)"
 
 
@@ -232,6 +236,12 @@ def main():
 
     # ---- batched float32 path ------------------------------------------------
     ctx = make_run_ctx(hd, specs, states, hd.HD_FP32C, hd.HD_EXEC_BATCHED, args.block)
+    trials = []
+    if not args.no_autotune:
+        # launch shape from the autotuner (untimed; the state is left as it was)
+        _, trials = ctx.autotune(min_ms=20.0, max_steps=8192)
+    sched = ctx.schedule()
+    log(f"schedule: {sched} ({len(trials)} shapes timed)")
     ctx.step(args.warmup)
     reb0 = [ctx.scalars(k)["n_rebuilds"] for k in range(len(specs))]
     wall, ev_ms, launches = time_steps(torch, ctx, args.steps)
@@ -252,7 +262,7 @@ def main():
     steps_per_launch = args.steps / max(launches, 1)
     avg_launch_s = (ev_ms / 1e3) / max(launches, 1)
     achieved = bytes_per_atom_step * n_atoms * steps_per_launch / avg_launch_s / 1e9
-    kname = stepping_kernel(specs, args.block)
+    kname = stepping_kernel(specs, sched)
     traffic, traffic_bytes = None, None
     rec = HBM_COUNTERS.get((args.config, kname))
     if rec and src_hash(rec["src"]) == rec["sha"]:
@@ -298,6 +308,8 @@ def main():
         "config": {"workload": f"{args.config}: {desc}", "systems": len(specs), "atoms": n_atoms,
                    "dim": dim, "parallelism": "batch of independent slider positions, 1 GPU"},
         "roofline": roof,
+        "schedule": {k: sched[k] for k in ("lds_resident", "small_block", "persistent_large", "large_block")},
+        "autotune_trials": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in t.items()} for t in trials],
         "cpu_baseline": cpu,
         "fp64_plain": plain,
         "speedup_vs_fp64_plain": (value / plain["value"]) if plain else None,

@@ -221,6 +221,48 @@ hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int
 hd_status hd_system_info(hd_ctx *ctx, int32_t sys, int32_t *dim, int32_t *n_atoms);
 int32_t hd_num_systems(const hd_ctx *ctx);
 
+/* Launch shape of the schedule (after hd_finalize).  lds_resident: systems
+ * that fit one workgroup run in the LDS-resident persistent kernel;
+ * small_block: its workgroup size (256, 512 or 1024, one thread per atom,
+ * raised to cover the largest system); persistent_large: the remaining
+ * systems run on the one-workgroup global kernel (1) or on the grid kernels
+ * (0); large_block: threads per grid tile or per workgroup of that kernel;
+ * ms_per_step: the time hd_autotune measured for this shape (0 otherwise). */
+typedef struct {
+    int32_t lds_resident;
+    int32_t small_block;
+    int32_t persistent_large;
+    int32_t large_block;
+    double ms_per_step;
+} hd_schedule;
+
+/* Current launch shape. */
+hd_status hd_get_schedule(hd_ctx *ctx, hd_schedule *out);
+
+/* Switch to a launch shape (after hd_finalize; for instance one that
+ * hd_autotune chose earlier for the same kind of batch).  The state of every
+ * system is kept; neighbour lists are rebuilt from their recorded build
+ * positions, so the run continues bit for bit as a run that used this shape
+ * from the start would.  HD_E_ARG for block sizes outside the ranges above,
+ * HD_E_STATE under HD_EXEC_SEQUENTIAL. */
+hd_status hd_set_schedule(hd_ctx *ctx, const hd_schedule *shape);
+
+/* Autotuner (after hd_finalize, HD_EXEC_BATCHED or HD_EXEC_GRID): times every
+ * candidate launch shape on the context's own batch and keeps the fastest.
+ * Each candidate is rebuilt, warmed up, and timed with HIP events over runs
+ * of 8, 32, 128, ... steps until one lasts at least min_ms milliseconds or
+ * reaches max_steps steps (a candidate more than three times slower than the
+ * best so far is dropped after its first run).  Every system's state is
+ * checkpointed before and restored after each trial, so the tuning leaves
+ * every system's state (positions, velocities, step, clocks) exactly where
+ * it was, and the run continues as one that used the chosen shape from the
+ * start.  The trials are written to trials[0..cap) (may be
+ * NULL) and their count to *n_trials; the chosen shape is then current.
+ * Returns HD_E_UNSTABLE if a trial froze every system (the state is restored
+ * and the previous shape kept). */
+hd_status hd_autotune(hd_ctx *ctx, double min_ms, int64_t max_steps, hd_schedule *trials, int32_t cap,
+                      int32_t *n_trials);
+
 /* Per-kernel timing of the last hd_step, measured with HIP events on the
  * context stream: total milliseconds and launches. */
 hd_status hd_last_step_timing(hd_ctx *ctx, double *ms, int64_t *launches);

@@ -142,6 +142,8 @@ __device__ void wg_rebuild(const SysDesc &D, const Arrays &A, const double *__re
     cat[cst[c] + slot] = i;
   }
   __syncthreads();
+  // sort each cell by index, then clear its count: counts are zero outside a
+  // rebuild, which the grid kernels' counting sort relies on
   for (int c = tid; c < ncell; c += B) {
     const int b = cst[c], e = cst[c + 1];
     for (int p = b + 1; p < e; ++p) {
@@ -150,6 +152,7 @@ __device__ void wg_rebuild(const SysDesc &D, const Arrays &A, const double *__re
       while (q >= b && cat[q] > key) { cat[q + 1] = cat[q]; --q; }
       cat[q + 1] = key;
     }
+    __hip_atomic_store(&cnt[c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   int ov = 0;

@@ -20,7 +20,7 @@ hipError_t launch_batched(int prec, int dim, const SysDesc *descs, SysState *sta
 // cellmax bounds every listed ncell; rigmax bounds every listed n_rigid.
 hipError_t launch_small(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
                         const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax, int rigmax,
-                        int64_t nsteps, int mode, hipStream_t stream);
+                        int block, int64_t nsteps, int mode, hipStream_t stream);
 size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax, int rigmax);
 // Dynamic LDS bytes of one LDS-resident group, and the one-time permission to
 // use that much (call outside graph capture, before the first launch).

@@ -74,6 +74,7 @@ struct hd_ctx {
   hipStream_t stream = nullptr;
   hd_exec exec = HD_EXEC_BATCHED;
   int block_threads = 0, max_nb = 0;
+  int small_block = 0;           // LDS-resident workgroup size floor (0: smallest that fits)
   bool small_disabled = false;
   bool persistent_big = false;  // large systems on the one-workgroup global kernel
   std::vector<SysHost> sys;
@@ -81,6 +82,7 @@ struct hd_ctx {
   std::string err;
   // device memory
   std::vector<void *> allocs;
+  std::vector<void *> sched_allocs;  // schedule-owned (groups, plans, partials)
   hdk::Arrays A{};
   SysDesc *d_desc = nullptr;
   SysState *d_state = nullptr;
@@ -93,6 +95,7 @@ struct hd_ctx {
     std::vector<int32_t> ids;
     int32_t *d_ids = nullptr;
     int nmax = 0, cellmax = 1, maxnb = 32, rigmax = 1;
+    int block = 0;   // threads per workgroup
   };
   std::vector<Group> groups;
   std::vector<int32_t> small_ids, big_ids;
@@ -112,6 +115,7 @@ struct hd_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   int64_t last_launches = 0;
+  double tuned_ms = 0.0;
 };
 
 namespace {
@@ -138,14 +142,14 @@ hd_status fail(hd_ctx *c, hd_status st, const std::string &msg) {
   } while (0)
 
 template <typename T>
-hd_status dalloc(hd_ctx *ctx, T **p, size_t count) {
+hd_status dalloc(hd_ctx *ctx, T **p, size_t count, bool sched = false) {
   void *q = nullptr;
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess) return fail(ctx, HD_E_OOM, "hipMalloc failed: " + std::string(hipGetErrorString(e)));
   e = hipMemsetAsync(q, 0, bytes, ctx->stream);
   if (e != hipSuccess) return fail(ctx, HD_E_HIP, "hipMemsetAsync failed");
-  ctx->allocs.push_back(q);
+  (sched ? ctx->sched_allocs : ctx->allocs).push_back(q);
   *p = (T *)q;
   return HD_OK;
 }
@@ -316,9 +320,9 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
     }
     max_ncell = std::max(max_ncell, ctx->h_desc[s].ncell);
   }
-  hd_status st = dalloc(ctx, &P.d_tiles, tiles.size());
+  hd_status st = dalloc(ctx, &P.d_tiles, tiles.size(), true);
   if (st != HD_OK) return st;
-  st = dalloc(ctx, &P.d_sys, systems.size());
+  st = dalloc(ctx, &P.d_sys, systems.size(), true);
   if (st != HD_OK) return st;
   HIPCHK(hipMemcpyAsync(P.d_tiles, tiles.data(), tiles.size() * sizeof(hdk::Tile), hipMemcpyHostToDevice, ctx->stream));
   std::vector<int32_t> ids(systems.begin(), systems.end());
@@ -363,7 +367,7 @@ hd_status launch_groups(hd_ctx *ctx, int64_t nsteps, int mode, hipStream_t strea
     if (G.ids.empty()) continue;
     if (G.small)
       HIPCHK(hdk::launch_small(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
-                               G.nmax, G.maxnb, G.cellmax, G.rigmax, nsteps, mode, stream));
+                               G.nmax, G.maxnb, G.cellmax, G.rigmax, G.block, nsteps, mode, stream));
     else
       HIPCHK(hdk::launch_batched(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
                                  ctx->block, nsteps, mode, stream));
@@ -438,6 +442,139 @@ hd_status run_groups(hd_ctx *ctx, int64_t n_steps, hipStream_t stream, int64_t *
   return HD_OK;
 }
 
+
+// Workgroup size of the LDS-resident kernel for a group whose largest system
+// has nmax atoms: one thread per atom, at least the tuned floor.
+int small_block_for(const hd_ctx *ctx, int nmax) {
+  int b = nmax <= 256 ? 256 : (nmax <= 512 ? 512 : 1024);
+  while (b < ctx->small_block && b < 1024) b *= 2;
+  return b;
+}
+
+// Drop the schedule (graphs, groups, plans and their device buffers).
+void clear_schedule(hd_ctx *ctx) {
+  hipStreamSynchronize(ctx->stream);
+  hipStreamSynchronize(ctx->stream2);
+  for (auto &P : ctx->plans)
+    if (P.exec) hipGraphExecDestroy(P.exec);
+  ctx->plans.clear();
+  if (ctx->batched_graph) hipGraphExecDestroy(ctx->batched_graph);
+  ctx->batched_graph = nullptr;
+  for (void *q : ctx->sched_allocs) hipFree(q);
+  ctx->sched_allocs.clear();
+  ctx->groups.clear();
+  ctx->small_ids.clear();
+  ctx->big_ids.clear();
+  ctx->A.partials = nullptr;
+}
+
+// Assign systems to the LDS-resident groups, the one-workgroup kernel or the
+// grid plans, following the scheduler and launch knobs of the context.
+hd_status build_schedule(hd_ctx *ctx) {
+  const int S = (int)ctx->sys.size();
+  hdk::Arrays &A = ctx->A;
+  hd_status st;
+#define ALLOC(p, cnt) do { st = dalloc(ctx, &(p), (cnt), true); if (st != HD_OK) return st; } while (0)
+  // batched scheduler: systems of <= 1024 atoms whose state fits in LDS run
+  // LDS-resident (one thread per atom), the rest from global memory
+  ctx->small_ids.clear();
+  ctx->big_ids.clear();
+  ctx->groups.clear();
+  if (ctx->exec == HD_EXEC_BATCHED) {
+    const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+    const size_t budget = ctx->lds_limit > 8192 ? ctx->lds_limit - 8192 : 0;  // static LDS of the kernel
+    std::vector<int> cand;
+    for (int s = 0; s < S; ++s) {
+      const SysHost &h = ctx->sys[s];
+      const int maxnb = h.dim == 2 ? ctx->maxnb2 : ctx->maxnb3;
+      const bool ok = h.n <= 1024 && maxnb <= 32767 &&
+                      hdk::small_lds_bytes(h.dim, prec, h.n, maxnb, ctx->h_desc[s].ncell, h.n_rigid) <= budget &&
+                      !ctx->small_disabled;
+      if (ok) cand.push_back(s);
+      else ctx->big_ids.push_back(s);
+    }
+    // admit candidates (by size) while the group's common layout fits
+    std::sort(cand.begin(), cand.end(), [&](int a, int b) { return ctx->sys[a].n < ctx->sys[b].n; });
+    int gn[2] = {0, 0}, gc[2] = {1, 1}, gr[2] = {1, 1};
+    std::vector<int32_t> sm[2];
+    for (int s : cand) {
+      const int d = ctx->sys[s].dim - 2;
+      const int maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
+      const int n2 = std::max(gn[d], ctx->sys[s].n), c2 = std::max(gc[d], ctx->h_desc[s].ncell);
+      const int r2 = std::max(gr[d], ctx->sys[s].n_rigid);
+      if (hdk::small_lds_bytes(d + 2, prec, n2, maxnb, c2, r2) <= budget) {
+        sm[d].push_back(s); gn[d] = n2; gc[d] = c2; gr[d] = r2;
+      } else {
+        ctx->big_ids.push_back(s);
+      }
+    }
+    for (int d = 0; d < 2; ++d) {
+      std::sort(sm[d].begin(), sm[d].end());
+      for (int s : sm[d]) ctx->small_ids.push_back(s);
+      if (sm[d].empty()) continue;
+      hd_ctx::Group G;
+      G.dim = d + 2; G.small = true; G.ids = sm[d]; G.nmax = gn[d]; G.cellmax = gc[d]; G.rigmax = gr[d];
+      G.maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
+      ctx->groups.push_back(G);
+    }
+    std::sort(ctx->big_ids.begin(), ctx->big_ids.end());
+    if (ctx->persistent_big) {
+      for (int d = 0; d < 2; ++d) {
+        hd_ctx::Group G;
+        G.dim = d + 2;
+        for (int s : ctx->big_ids) if (ctx->sys[s].dim == d + 2) G.ids.push_back(s);
+        if (!G.ids.empty()) ctx->groups.push_back(G);
+      }
+    }
+  }
+  // block size of the global-memory batched kernel / grid tiles
+  int maxn = 0;
+  for (int s : ctx->big_ids) maxn = std::max(maxn, ctx->sys[s].n);
+  if (ctx->block_threads > 0) ctx->block = ctx->block_threads;
+  else if (ctx->exec == HD_EXEC_BATCHED && ctx->persistent_big) ctx->block = maxn <= 256 ? 256 : 512;
+  else ctx->block = 256;
+  for (auto &G : ctx->groups) {
+    ALLOC(G.d_ids, G.ids.size());
+    G.block = G.small ? small_block_for(ctx, G.nmax) : ctx->block;
+    HIPCHK(hipMemcpyAsync(G.d_ids, G.ids.data(), G.ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    if (G.small) {
+      const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+      HIPCHK(hdk::small_allow_lds(prec, G.dim,
+                                  hdk::small_group_bytes(prec, G.dim, G.nmax, G.maxnb, G.cellmax, G.rigmax)));
+    }
+  }
+  // grid plans
+  if (ctx->exec == HD_EXEC_BATCHED && !ctx->persistent_big && !ctx->big_ids.empty()) {
+    std::vector<int> big(ctx->big_ids.begin(), ctx->big_ids.end());
+    ctx->plans.resize(1);
+    if ((st = build_plan(ctx, big, ctx->plans[0])) != HD_OK) return st;
+  } else if (ctx->exec == HD_EXEC_GRID) {
+    std::vector<int> sys_all(S);
+    for (int s = 0; s < S; ++s) sys_all[s] = s;
+    ctx->plans.resize(1);
+    if ((st = build_plan(ctx, sys_all, ctx->plans[0])) != HD_OK) return st;
+  } else if (ctx->exec == HD_EXEC_SEQUENTIAL) {
+    ctx->plans.resize(S);
+    for (int s = 0; s < S; ++s)
+      if ((st = build_plan(ctx, std::vector<int>{s}, ctx->plans[s])) != HD_OK) return st;
+  }
+  {
+    int max_tiles = 1;
+    for (auto &P : ctx->plans) max_tiles = std::max(max_tiles, P.gp.ntiles);
+    ALLOC(A.partials, (size_t)max_tiles * hdk::NRED);
+  }
+  if (!ctx->plans.empty()) {
+    // grid path: the first step rebuilds every list from the recorded build
+    // positions (equal to the positions at hd_finalize), so that a schedule
+    // change in the middle of a run keeps the list an uninterrupted run has
+    std::vector<int32_t> twos(S, 2);
+    HIPCHK(hipMemcpyAsync(A.rebuild_flag, twos.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+#undef ALLOC
+}
 }  // namespace
 
 // ===========================================================================
@@ -675,76 +812,8 @@ hd_status hd_finalize(hd_ctx *ctx) {
     ALLOC(g, hdk::grid_scal_bytes() * S);
     ctx->d_gscal = g;
   }
-  // batched scheduler: systems of <= 1024 atoms whose state fits in LDS run
-  // LDS-resident (one thread per atom), the rest from global memory
   ctx->maxnb2 = ctx->max_nb > 0 ? ctx->max_nb : 32;
   ctx->maxnb3 = ctx->max_nb > 0 ? ctx->max_nb : 128;
-  ctx->small_ids.clear();
-  ctx->big_ids.clear();
-  ctx->groups.clear();
-  if (ctx->exec == HD_EXEC_BATCHED) {
-    const int prec = ctx->prec == HD_FP64 ? 0 : 1;
-    const size_t budget = ctx->lds_limit > 8192 ? ctx->lds_limit - 8192 : 0;  // static LDS of the kernel
-    std::vector<int> cand;
-    for (int s = 0; s < S; ++s) {
-      const SysHost &h = ctx->sys[s];
-      const int maxnb = h.dim == 2 ? ctx->maxnb2 : ctx->maxnb3;
-      const bool ok = h.n <= 1024 && maxnb <= 32767 &&
-                      hdk::small_lds_bytes(h.dim, prec, h.n, maxnb, ctx->h_desc[s].ncell, h.n_rigid) <= budget &&
-                      !ctx->small_disabled;
-      if (ok) cand.push_back(s);
-      else ctx->big_ids.push_back(s);
-    }
-    // admit candidates (by size) while the group's common layout fits
-    std::sort(cand.begin(), cand.end(), [&](int a, int b) { return ctx->sys[a].n < ctx->sys[b].n; });
-    int gn[2] = {0, 0}, gc[2] = {1, 1}, gr[2] = {1, 1};
-    std::vector<int32_t> sm[2];
-    for (int s : cand) {
-      const int d = ctx->sys[s].dim - 2;
-      const int maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
-      const int n2 = std::max(gn[d], ctx->sys[s].n), c2 = std::max(gc[d], ctx->h_desc[s].ncell);
-      const int r2 = std::max(gr[d], ctx->sys[s].n_rigid);
-      if (hdk::small_lds_bytes(d + 2, prec, n2, maxnb, c2, r2) <= budget) {
-        sm[d].push_back(s); gn[d] = n2; gc[d] = c2; gr[d] = r2;
-      } else {
-        ctx->big_ids.push_back(s);
-      }
-    }
-    for (int d = 0; d < 2; ++d) {
-      std::sort(sm[d].begin(), sm[d].end());
-      for (int s : sm[d]) ctx->small_ids.push_back(s);
-      if (sm[d].empty()) continue;
-      hd_ctx::Group G;
-      G.dim = d + 2; G.small = true; G.ids = sm[d]; G.nmax = gn[d]; G.cellmax = gc[d]; G.rigmax = gr[d];
-      G.maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
-      ctx->groups.push_back(G);
-    }
-    std::sort(ctx->big_ids.begin(), ctx->big_ids.end());
-    if (ctx->persistent_big) {
-      for (int d = 0; d < 2; ++d) {
-        hd_ctx::Group G;
-        G.dim = d + 2;
-        for (int s : ctx->big_ids) if (ctx->sys[s].dim == d + 2) G.ids.push_back(s);
-        if (!G.ids.empty()) ctx->groups.push_back(G);
-      }
-    }
-  }
-  // block size of the global-memory batched kernel / grid tiles
-  int maxn = 0;
-  for (int s : ctx->big_ids) maxn = std::max(maxn, ctx->sys[s].n);
-  if (ctx->block_threads > 0) ctx->block = ctx->block_threads;
-  else if (ctx->exec == HD_EXEC_BATCHED && ctx->persistent_big) ctx->block = maxn <= 256 ? 256 : 512;
-  else ctx->block = 256;
-  for (auto &G : ctx->groups) {
-    ALLOC(G.d_ids, G.ids.size());
-    HIPCHK(hipMemcpyAsync(G.d_ids, G.ids.data(), G.ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                          ctx->stream));
-    if (G.small) {
-      const int prec = ctx->prec == HD_FP64 ? 0 : 1;
-      HIPCHK(hdk::small_allow_lds(prec, G.dim,
-                                  hdk::small_group_bytes(prec, G.dim, G.nmax, G.maxnb, G.cellmax, G.rigmax)));
-    }
-  }
   // host staging
   std::vector<double> x(3 * N, 0.0), rO(3 * N, 0.0), cofs(3 * N, 0.0), v(3 * N, 0.0);
   std::vector<uint8_t> tr(N);
@@ -790,31 +859,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
   HIPCHK(hipMemcpyAsync(ctx->d_state, states.data(), S * sizeof(SysState), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->finalized = true;
-  // schedulers
-  if (ctx->exec == HD_EXEC_BATCHED && !ctx->persistent_big && !ctx->big_ids.empty()) {
-    std::vector<int> big(ctx->big_ids.begin(), ctx->big_ids.end());
-    ctx->plans.resize(1);
-    if ((st = build_plan(ctx, big, ctx->plans[0])) != HD_OK) return st;
-  } else if (ctx->exec == HD_EXEC_GRID) {
-    std::vector<int> sys_all(S);
-    for (int s = 0; s < S; ++s) sys_all[s] = s;
-    ctx->plans.resize(1);
-    if ((st = build_plan(ctx, sys_all, ctx->plans[0])) != HD_OK) return st;
-  } else if (ctx->exec == HD_EXEC_SEQUENTIAL) {
-    ctx->plans.resize(S);
-    for (int s = 0; s < S; ++s)
-      if ((st = build_plan(ctx, std::vector<int>{s}, ctx->plans[s])) != HD_OK) return st;
-  }
-  {
-    int max_tiles = 1;
-    for (auto &P : ctx->plans) max_tiles = std::max(max_tiles, P.gp.ntiles);
-    ALLOC(A.partials, (size_t)max_tiles * hdk::NRED);
-  }
-  if (!ctx->plans.empty()) {
-    // grid path: rebuild flags raised for the first evaluation
-    std::vector<int32_t> ones(S, 1);
-    HIPCHK(hipMemcpyAsync(A.rebuild_flag, ones.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-  }
+  if ((st = build_schedule(ctx)) != HD_OK) return st;
   for (int s = 0; s < S; ++s)
     if (ctx->sys[s].init_vel) {
       if ((st = run_init_velocities(ctx, s)) != HD_OK) return st;
@@ -862,6 +907,147 @@ hd_status hd_step(hd_ctx *ctx, int64_t n_steps) {
   ctx->last_launches = launches;
   ctx->last_ms = -1.0;
   return sync_out(ctx);
+}
+
+hd_status hd_get_schedule(hd_ctx *ctx, hd_schedule *out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (!out) return fail(ctx, HD_E_ARG, "null output");
+  out->lds_resident = ctx->small_disabled ? 0 : 1;
+  out->small_block = 0;
+  for (const auto &G : ctx->groups)
+    if (G.small) out->small_block = std::max(out->small_block, G.block);
+  out->persistent_large = ctx->persistent_big ? 1 : 0;
+  out->large_block = ctx->block;
+  out->ms_per_step = ctx->tuned_ms;
+  return HD_OK;
+}
+
+namespace {
+
+hd_status apply_schedule(hd_ctx *ctx, const hd_schedule &c) {
+  clear_schedule(ctx);
+  ctx->small_disabled = c.lds_resident == 0;
+  ctx->small_block = c.small_block;
+  ctx->persistent_big = c.persistent_large != 0;
+  ctx->block_threads = c.large_block;
+  hd_status st = build_schedule(ctx);
+  if (st != HD_OK) return st;
+  // a system may now run on another kernel, whose list format differs (half
+  // or full lists): every kernel rebuilds from the recorded build positions
+  std::vector<SysState> T(ctx->sys.size());
+  HIPCHK(hipMemcpyAsync(T.data(), ctx->d_state, T.size() * sizeof(SysState), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (auto &t : T) t.rebuild = 2;
+  HIPCHK(hipMemcpyAsync(ctx->d_state, T.data(), T.size() * sizeof(SysState), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+hd_status restore_all(hd_ctx *ctx, const std::vector<std::vector<char>> &ck) {
+  for (size_t s = 0; s < ck.size(); ++s) {
+    const hd_status st = hd_set_state(ctx, (int32_t)s, ck[s].data(), ck[s].size());
+    if (st != HD_OK) return st;
+  }
+  return HD_OK;
+}
+
+}  // namespace
+
+hd_status hd_set_schedule(hd_ctx *ctx, const hd_schedule *shape) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_schedule before hd_finalize");
+  if (!shape) return fail(ctx, HD_E_ARG, "null schedule");
+  if (ctx->exec == HD_EXEC_SEQUENTIAL) return fail(ctx, HD_E_STATE, "the sequential scheduler has no launch shapes");
+  const int sb = shape->small_block, lb = shape->large_block;
+  if ((sb != 0 && sb != 256 && sb != 512 && sb != 1024) || lb < 64 || lb > 1024 || lb % 64 != 0)
+    return fail(ctx, HD_E_ARG, "small_block must be 0, 256, 512 or 1024; large_block a multiple of 64 in [64, 1024]");
+  hd_status st;
+  if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
+  if ((st = apply_schedule(ctx, *shape)) != HD_OK) return st;
+  ctx->tuned_ms = shape->ms_per_step;
+  return HD_OK;
+}
+
+hd_status hd_autotune(hd_ctx *ctx, double min_ms, int64_t max_steps, hd_schedule *trials, int32_t cap,
+                      int32_t *n_trials) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_autotune before hd_finalize");
+  if (ctx->exec == HD_EXEC_SEQUENTIAL) return fail(ctx, HD_E_STATE, "the sequential scheduler has no launch shapes to tune");
+  if (!(min_ms > 0) || max_steps < 8 || cap < 0 || (cap > 0 && !trials))
+    return fail(ctx, HD_E_ARG, "hd_autotune needs min_ms > 0, max_steps >= 8, a trial buffer when cap > 0");
+  const int S = (int)ctx->sys.size();
+  hd_status st;
+  if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
+  // checkpoint every system
+  std::vector<std::vector<char>> ck(S);
+  for (int s = 0; s < S; ++s) {
+    size_t b = 0;
+    if ((st = hd_get_state(ctx, s, nullptr, &b)) != HD_OK) return st;
+    ck[s].resize(b);
+    if ((st = hd_get_state(ctx, s, ck[s].data(), &b)) != HD_OK) return st;
+  }
+  hd_schedule prev{};
+  if ((st = hd_get_schedule(ctx, &prev)) != HD_OK) return st;
+  // candidates: LDS-resident or not for the systems that fit, its workgroup
+  // size, and the shape of the rest (grid tile size, or one workgroup per
+  // system on the global kernel)
+  bool any_fit = false, any_large = false;
+  int nmax_fit = 0;
+  for (int s = 0; s < S; ++s) {
+    if (ctx->sys[s].n <= 1024) { any_fit = true; nmax_fit = std::max(nmax_fit, ctx->sys[s].n); }
+    else any_large = true;
+  }
+  std::vector<hd_schedule> cand;
+  const int large_grid[3] = {128, 256, 512}, large_pers[3] = {256, 512, 1024};
+  auto add_large = [&](hd_schedule c, bool need) {
+    if (!need) { c.persistent_large = 0; c.large_block = 256; cand.push_back(c); return; }
+    for (int b : large_grid) { c.persistent_large = 0; c.large_block = b; cand.push_back(c); }
+    if (ctx->exec == HD_EXEC_BATCHED)
+      for (int b : large_pers) { c.persistent_large = 1; c.large_block = b; cand.push_back(c); }
+  };
+  if (ctx->exec == HD_EXEC_BATCHED && any_fit) {
+    for (int b : {256, 512, 1024}) {
+      if (b < nmax_fit && b != 1024) continue;
+      add_large(hd_schedule{1, b, 0, 256, 0.0}, any_large);
+    }
+  }
+  add_large(hd_schedule{0, 0, 0, 256, 0.0}, true);
+  // measure
+  std::vector<hd_schedule> done;
+  double best_ms = 0.0;
+  int best = -1;
+  for (const hd_schedule &c0 : cand) {
+    hd_schedule c = c0;
+    if ((st = apply_schedule(ctx, c)) != HD_OK) return st;
+    if ((st = restore_all(ctx, ck)) != HD_OK) return st;
+    if ((st = hd_step(ctx, 4)) != HD_OK) break;         // warm-up: code objects, first rebuild
+    double ms_step = 0.0;
+    for (int64_t k = 8;; k *= 4) {
+      if ((st = hd_step(ctx, std::min(k, max_steps))) != HD_OK) break;
+      double ms = 0.0;
+      if ((st = hd_last_step_timing(ctx, &ms, nullptr)) != HD_OK) return st;
+      ms_step = ms / (double)std::min(k, max_steps);
+      if (ms >= min_ms || k >= max_steps) break;
+      if (best >= 0 && ms_step > 3.0 * best_ms) break;
+    }
+    if (st != HD_OK) break;
+    c.ms_per_step = ms_step;
+    if (best < 0 || ms_step < best_ms) { best = (int)done.size(); best_ms = ms_step; }
+    done.push_back(c);
+  }
+  // keep the fastest shape (or the previous one after a failure) and put
+  // every system back where it was
+  const hd_status trial_st = st;
+  if (trial_st != HD_OK && trial_st != HD_E_UNSTABLE) return trial_st;
+  const hd_schedule keep = (trial_st == HD_OK && best >= 0) ? done[best] : prev;
+  if ((st = apply_schedule(ctx, keep)) != HD_OK) return st;
+  if ((st = restore_all(ctx, ck)) != HD_OK) return st;
+  ctx->tuned_ms = trial_st == HD_OK ? keep.ms_per_step : 0.0;
+  if (n_trials) *n_trials = (int32_t)done.size();
+  for (int32_t q = 0; q < cap && q < (int32_t)done.size(); ++q) trials[q] = done[q];
+  if (trial_st != HD_OK) return fail(ctx, trial_st, "a trial froze every system; previous launch shape kept");
+  return HD_OK;
 }
 
 hd_status hd_last_step_timing(hd_ctx *ctx, double *ms, int64_t *launches) {
@@ -1155,6 +1341,7 @@ void hd_destroy(hd_ctx *ctx) {
   for (auto &P : ctx->plans)
     if (P.exec) hipGraphExecDestroy(P.exec);
   if (ctx->batched_graph) hipGraphExecDestroy(ctx->batched_graph);
+  for (void *p : ctx->sched_allocs) hipFree(p);
   for (void *p : ctx->allocs) hipFree(p);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
   if (ctx->ev1) hipEventDestroy(ctx->ev1);

@@ -581,11 +581,11 @@ static hipError_t launch_small_d(const SysDesc *descs, SysState *states, const A
 
 hipError_t launch_small(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
                         const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax, int rigmax,
-                        int64_t nsteps, int mode, hipStream_t stream) {
+                        int block, int64_t nsteps, int mode, hipStream_t stream) {
   if (nsys <= 0) return hipSuccess;
-  if (nmax > 1024) return hipErrorInvalidValue;
+  // one thread per atom: the workgroup must cover the largest system
+  if (nmax > 1024 || block < nmax || (block != 256 && block != 512 && block != 1024)) return hipErrorInvalidValue;
   const SmallLayout L = small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax, rigmax);
-  const int block = nmax <= 256 ? 256 : (nmax <= 512 ? 512 : 1024);
   if (prec == 0)
     return dim == 2 ? launch_small_d<double, 2>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream)
                     : launch_small_d<double, 3>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream);

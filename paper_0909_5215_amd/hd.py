@@ -64,6 +64,15 @@ class hd_scalars(_c.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class hd_schedule(_c.Structure):
+    _fields_ = [("lds_resident", _c.c_int32), ("small_block", _c.c_int32),
+                ("persistent_large", _c.c_int32), ("large_block", _c.c_int32),
+                ("ms_per_step", _c.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # name -> (restype, argtypes)
 _P = _c.c_void_p
 _SIGS = {
@@ -97,6 +106,10 @@ _SIGS = {
     "hd_system_info": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "hd_num_systems": (_c.c_int32, [_P]),
     "hd_last_step_timing": (_c.c_int, [_P, _dp, _c.POINTER(_c.c_int64)]),
+    "hd_get_schedule": (_c.c_int, [_P, _c.POINTER(hd_schedule)]),
+    "hd_set_schedule": (_c.c_int, [_P, _c.POINTER(hd_schedule)]),
+    "hd_autotune": (_c.c_int, [_P, _c.c_double, _c.c_int64, _c.POINTER(hd_schedule), _c.c_int32,
+                               _c.POINTER(_c.c_int32)]),
     "hd_last_error": (_c.c_char_p, [_P]),
     "hd_destroy": (None, [_P]),
 }
@@ -252,6 +265,25 @@ class Context:
         _check(self._h, load().hd_last_step_timing(self._h, ctypes.byref(ms), ctypes.byref(nl)),
                "hd_last_step_timing")
         return ms.value, nl.value
+
+    def schedule(self) -> dict:
+        out = hd_schedule()
+        _check(self._h, load().hd_get_schedule(self._h, ctypes.byref(out)), "hd_get_schedule")
+        return out.as_dict()
+
+    def set_schedule(self, shape: dict):
+        sh = hd_schedule(**{k: shape[k] for k, _ in hd_schedule._fields_ if k in shape})
+        _check(self._h, load().hd_set_schedule(self._h, ctypes.byref(sh)), "hd_set_schedule")
+
+    def autotune(self, min_ms: float = 20.0, max_steps: int = 8192):
+        """Time every launch shape on this batch, keep the fastest (the
+        trajectory is left where it was).  Returns (chosen, trials)."""
+        cap = 32
+        buf = (hd_schedule * cap)()
+        n = ctypes.c_int32()
+        _check(self._h, load().hd_autotune(self._h, float(min_ms), int(max_steps), buf, cap, ctypes.byref(n)),
+               "hd_autotune")
+        return self.schedule(), [buf[k].as_dict() for k in range(min(n.value, cap))]
 
     # -- read-outs --------------------------------------------------------
     def _out(self, s):
