@@ -227,12 +227,16 @@ int32_t hd_num_systems(const hd_ctx *ctx);
  * raised to cover the largest system); persistent_large: the remaining
  * systems run on the one-workgroup global kernel (1) or on the grid kernels
  * (0); large_block: threads per grid tile or per workgroup of that kernel;
+ * small_half_lists: under HD_FP32C the LDS-resident pair pass visits each
+ * pair once and adds the partner's share with float64 LDS atomics (1), or
+ * visits it from both atoms (0); always 0 under HD_FP64;
  * ms_per_step: the time hd_autotune measured for this shape (0 otherwise). */
 typedef struct {
     int32_t lds_resident;
     int32_t small_block;
     int32_t persistent_large;
     int32_t large_block;
+    int32_t small_half_lists;
     double ms_per_step;
 } hd_schedule;
 

@@ -75,6 +75,7 @@ struct hd_ctx {
   hd_exec exec = HD_EXEC_BATCHED;
   int block_threads = 0, max_nb = 0;
   int small_block = 0;           // LDS-resident workgroup size floor (0: smallest that fits)
+  bool small_half = true;        // float32 LDS-resident pair pass on half lists
   bool small_disabled = false;
   bool persistent_big = false;  // large systems on the one-workgroup global kernel
   std::vector<SysHost> sys;
@@ -359,6 +360,11 @@ hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps) {
   return HD_OK;
 }
 
+// Pair-pass variant of the LDS-resident kernel: float64 (full lists), float32
+// with half lists and float64 LDS accumulation of the partner's share, or
+// float32 with full lists.
+int small_kind(const hd_ctx *ctx) { return ctx->prec == HD_FP64 ? 0 : (ctx->small_half ? 1 : 2); }
+
 // One persistent launch per group (LDS-resident groups, and large systems
 // when they run on the one-workgroup global kernel), on `stream`.
 hd_status launch_groups(hd_ctx *ctx, int64_t nsteps, int mode, hipStream_t stream, int64_t *launches) {
@@ -366,7 +372,7 @@ hd_status launch_groups(hd_ctx *ctx, int64_t nsteps, int mode, hipStream_t strea
   for (auto &G : ctx->groups) {
     if (G.ids.empty()) continue;
     if (G.small)
-      HIPCHK(hdk::launch_small(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
+      HIPCHK(hdk::launch_small(small_kind(ctx), G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
                                G.nmax, G.maxnb, G.cellmax, G.rigmax, G.block, nsteps, mode, stream));
     else
       HIPCHK(hdk::launch_batched(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
@@ -453,14 +459,14 @@ int small_block_for(const hd_ctx *ctx, int nmax) {
 
 // Drop the schedule (graphs, groups, plans and their device buffers).
 void clear_schedule(hd_ctx *ctx) {
-  hipStreamSynchronize(ctx->stream);
-  hipStreamSynchronize(ctx->stream2);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream2);
   for (auto &P : ctx->plans)
-    if (P.exec) hipGraphExecDestroy(P.exec);
+    if (P.exec) (void)hipGraphExecDestroy(P.exec);
   ctx->plans.clear();
-  if (ctx->batched_graph) hipGraphExecDestroy(ctx->batched_graph);
+  if (ctx->batched_graph) (void)hipGraphExecDestroy(ctx->batched_graph);
   ctx->batched_graph = nullptr;
-  for (void *q : ctx->sched_allocs) hipFree(q);
+  for (void *q : ctx->sched_allocs) (void)hipFree(q);
   ctx->sched_allocs.clear();
   ctx->groups.clear();
   ctx->small_ids.clear();
@@ -481,7 +487,7 @@ hd_status build_schedule(hd_ctx *ctx) {
   ctx->big_ids.clear();
   ctx->groups.clear();
   if (ctx->exec == HD_EXEC_BATCHED) {
-    const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+    const int prec = small_kind(ctx);
     const size_t budget = ctx->lds_limit > 8192 ? ctx->lds_limit - 8192 : 0;  // static LDS of the kernel
     std::vector<int> cand;
     for (int s = 0; s < S; ++s) {
@@ -539,7 +545,7 @@ hd_status build_schedule(hd_ctx *ctx) {
     HIPCHK(hipMemcpyAsync(G.d_ids, G.ids.data(), G.ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           ctx->stream));
     if (G.small) {
-      const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+      const int prec = small_kind(ctx);
       HIPCHK(hdk::small_allow_lds(prec, G.dim,
                                   hdk::small_group_bytes(prec, G.dim, G.nmax, G.maxnb, G.cellmax, G.rigmax)));
     }
@@ -919,6 +925,7 @@ hd_status hd_get_schedule(hd_ctx *ctx, hd_schedule *out) {
     if (G.small) out->small_block = std::max(out->small_block, G.block);
   out->persistent_large = ctx->persistent_big ? 1 : 0;
   out->large_block = ctx->block;
+  out->small_half_lists = (ctx->prec != HD_FP64 && ctx->small_half) ? 1 : 0;
   out->ms_per_step = ctx->tuned_ms;
   return HD_OK;
 }
@@ -931,6 +938,7 @@ hd_status apply_schedule(hd_ctx *ctx, const hd_schedule &c) {
   ctx->small_block = c.small_block;
   ctx->persistent_big = c.persistent_large != 0;
   ctx->block_threads = c.large_block;
+  ctx->small_half = c.small_half_lists != 0;
   hd_status st = build_schedule(ctx);
   if (st != HD_OK) return st;
   // a system may now run on another kernel, whose list format differs (half
@@ -1007,12 +1015,13 @@ hd_status hd_autotune(hd_ctx *ctx, double min_ms, int64_t max_steps, hd_schedule
       for (int b : large_pers) { c.persistent_large = 1; c.large_block = b; cand.push_back(c); }
   };
   if (ctx->exec == HD_EXEC_BATCHED && any_fit) {
-    for (int b : {256, 512, 1024}) {
-      if (b < nmax_fit && b != 1024) continue;
-      add_large(hd_schedule{1, b, 0, 256, 0.0}, any_large);
-    }
+    for (int half = (ctx->prec == HD_FP64 ? 0 : 1); half >= 0; --half)
+      for (int b : {256, 512, 1024}) {
+        if (b < nmax_fit && b != 1024) continue;
+        add_large(hd_schedule{1, b, 0, 256, half, 0.0}, any_large);
+      }
   }
-  add_large(hd_schedule{0, 0, 0, 256, 0.0}, true);
+  add_large(hd_schedule{0, 0, 0, 256, 0, 0.0}, true);
   // measure
   std::vector<hd_schedule> done;
   double best_ms = 0.0;

@@ -18,15 +18,17 @@ struct SmallLayout {
   size_t off_x, off_acc, off_rig, off_ref, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
 };
 
-// float32 systems use half lists (each pair once); the partner's share of
-// F, H u and the energy is accumulated in float64 in LDS (acc region).
-__host__ __device__ inline SmallLayout small_layout(int dim, int tsize, int nmax, int maxnb, int cellmax,
+// Pair-pass variants ("kind"): 0 float64 with full lists; 1 float32 with half
+// lists (each pair once; the partner's share of F, H u and the energy is
+// accumulated in float64 in LDS, the acc region); 2 float32 with full lists.
+__host__ __device__ inline SmallLayout small_layout(int dim, int kind, int nmax, int maxnb, int cellmax,
                                                     int rigmax) {
+  const int tsize = kind == 0 ? 8 : 4;
   SmallLayout L;
   L.nmax = nmax; L.maxnb = maxnb; L.cellmax = cellmax; L.rigmax = rigmax > 0 ? rigmax : 1;
   size_t o = 0;
   L.off_x = o; o += (size_t)8 * dim * nmax;
-  L.off_acc = o; if (tsize == 4) o += (size_t)8 * (2 * dim + 1) * nmax;
+  L.off_acc = o; if (kind == 1) o += (size_t)8 * (2 * dim + 1) * nmax;
   // rigid-layer atoms' F, H u and u, and their offsets c_i, one slot per
   // rigid atom (rank order)
   L.off_rig = o; o += (size_t)8 * 4 * dim * L.rigmax;
@@ -41,8 +43,8 @@ __host__ __device__ inline SmallLayout small_layout(int dim, int tsize, int nmax
   return L;
 }
 
-size_t small_lds_bytes(int dim, int prec, int nmax, int maxnb, int cellmax, int rigmax) {
-  return small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax, rigmax).bytes;
+size_t small_lds_bytes(int dim, int kind, int nmax, int maxnb, int cellmax, int rigmax) {
+  return small_layout(dim, kind, nmax, maxnb, cellmax, rigmax).bytes;
 }
 
 // Rebuild the cell list and every atom's neighbour list in LDS from the LDS
@@ -145,13 +147,13 @@ __device__ int lds_rebuild(const SysDesc &D, const double *__restrict__ xs, uint
   return block_or(ov, lds_int + 20);
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, bool HALF>
 __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Arrays &A,
                           int64_t nsteps, int mode, char *lds, const SmallLayout L) {
+  static_assert(!HALF || sizeof(T) == 4, "half lists are a float32 variant");
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = D.n, stride = L.nmax;
   const int64_t N = A.ntot, off = D.off;
-  constexpr bool HALF = sizeof(T) == 4;
   double *xs = (double *)(lds + L.off_x);
   double *jacc = (double *)(lds + L.off_acc);   // [2*DIM+1][stride]: F, H u, e of the j side
   const int rstride = L.rigmax;
@@ -528,29 +530,29 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 // positions (separate instantiation so the two never share a profile row).
 // One instantiation per dimension and workgroup size, so that the register
 // budget follows the launch size.
-template <typename T, int DIM, int MODE, int BLOCK>
+template <typename T, int DIM, int MODE, int BLOCK, bool HALF>
 __global__ __launch_bounds__(BLOCK) void k_small(const SysDesc *__restrict__ descs,
                                                  SysState *__restrict__ states, Arrays A,
                                                  const int32_t *__restrict__ sys_list, int64_t nsteps,
                                                  SmallLayout L) {
   extern __shared__ __align__(16) char lds[];
   const int s = sys_list[blockIdx.x];
-  run_small<DIM, T>(descs[s], states + s, A, nsteps, MODE, lds, L);
+  run_small<DIM, T, HALF>(descs[s], states + s, A, nsteps, MODE, lds, L);
 }
 
-template <typename T, int DIM, int MODE, int BLOCK>
+template <typename T, int DIM, int MODE, int BLOCK, bool HALF>
 static hipError_t launch_small_t(const SysDesc *descs, SysState *states, const Arrays &A,
                                  const int32_t *sys_list, int nsys, size_t bytes, int64_t nsteps,
                                  SmallLayout L, hipStream_t stream) {
-  hipLaunchKernelGGL((k_small<T, DIM, MODE, BLOCK>), dim3(nsys), dim3(BLOCK), bytes, stream, descs, states, A,
-                     sys_list, nsteps, L);
+  hipLaunchKernelGGL((k_small<T, DIM, MODE, BLOCK, HALF>), dim3(nsys), dim3(BLOCK), bytes, stream, descs, states,
+                     A, sys_list, nsteps, L);
   return hipGetLastError();
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool HALF>
 static hipError_t allow_lds_d(int bytes) {
-  const void *fns[4] = {(const void *)k_small<T, DIM, 1, 1024>, (const void *)k_small<T, DIM, 0, 256>,
-                        (const void *)k_small<T, DIM, 0, 512>, (const void *)k_small<T, DIM, 0, 1024>};
+  const void *fns[4] = {(const void *)k_small<T, DIM, 1, 1024, HALF>, (const void *)k_small<T, DIM, 0, 256, HALF>,
+                        (const void *)k_small<T, DIM, 0, 512, HALF>, (const void *)k_small<T, DIM, 0, 1024, HALF>};
   for (const void *f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -558,39 +560,48 @@ static hipError_t allow_lds_d(int bytes) {
   return hipSuccess;
 }
 
-// Allow `bytes` of dynamic LDS for every LDS-resident kernel of this
-// precision and dimension (done once, outside any graph capture).
-hipError_t small_allow_lds(int prec, int dim, size_t bytes) {
-  if (prec == 0) return dim == 2 ? allow_lds_d<double, 2>((int)bytes) : allow_lds_d<double, 3>((int)bytes);
-  return dim == 2 ? allow_lds_d<float, 2>((int)bytes) : allow_lds_d<float, 3>((int)bytes);
+// Allow `bytes` of dynamic LDS for every LDS-resident kernel of this variant
+// and dimension (done once per schedule, outside any graph capture).
+hipError_t small_allow_lds(int kind, int dim, size_t bytes) {
+  if (kind == 0) return dim == 2 ? allow_lds_d<double, 2, false>((int)bytes) : allow_lds_d<double, 3, false>((int)bytes);
+  if (kind == 1) return dim == 2 ? allow_lds_d<float, 2, true>((int)bytes) : allow_lds_d<float, 3, true>((int)bytes);
+  return dim == 2 ? allow_lds_d<float, 2, false>((int)bytes) : allow_lds_d<float, 3, false>((int)bytes);
 }
 
-size_t small_group_bytes(int prec, int dim, int nmax, int maxnb, int cellmax, int rigmax) {
-  return small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax, rigmax).bytes;
+size_t small_group_bytes(int kind, int dim, int nmax, int maxnb, int cellmax, int rigmax) {
+  return small_layout(dim, kind, nmax, maxnb, cellmax, rigmax).bytes;
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool HALF>
 static hipError_t launch_small_d(const SysDesc *descs, SysState *states, const Arrays &A,
                                  const int32_t *sys_list, int nsys, int block, size_t bytes, int64_t nsteps,
                                  int mode, SmallLayout L, hipStream_t stream) {
-  if (mode) return launch_small_t<T, DIM, 1, 1024>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
-  if (block <= 256) return launch_small_t<T, DIM, 0, 256>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
-  if (block <= 512) return launch_small_t<T, DIM, 0, 512>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
-  return launch_small_t<T, DIM, 0, 1024>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  if (mode)
+    return launch_small_t<T, DIM, 1, 1024, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  if (block <= 256)
+    return launch_small_t<T, DIM, 0, 256, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  if (block <= 512)
+    return launch_small_t<T, DIM, 0, 512, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  return launch_small_t<T, DIM, 0, 1024, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
 }
 
-hipError_t launch_small(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
+hipError_t launch_small(int kind, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
                         const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax, int rigmax,
                         int block, int64_t nsteps, int mode, hipStream_t stream) {
   if (nsys <= 0) return hipSuccess;
   // one thread per atom: the workgroup must cover the largest system
   if (nmax > 1024 || block < nmax || (block != 256 && block != 512 && block != 1024)) return hipErrorInvalidValue;
-  const SmallLayout L = small_layout(dim, prec == 0 ? 8 : 4, nmax, maxnb, cellmax, rigmax);
-  if (prec == 0)
-    return dim == 2 ? launch_small_d<double, 2>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream)
-                    : launch_small_d<double, 3>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream);
-  return dim == 2 ? launch_small_d<float, 2>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream)
-                  : launch_small_d<float, 3>(descs, states, A, sys_list, nsys, block, L.bytes, nsteps, mode, L, stream);
+  if (kind < 0 || kind > 2 || (dim != 2 && dim != 3)) return hipErrorInvalidValue;
+  const SmallLayout L = small_layout(dim, kind, nmax, maxnb, cellmax, rigmax);
+  const size_t b = L.bytes;
+  if (kind == 0)
+    return dim == 2 ? launch_small_d<double, 2, false>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream)
+                    : launch_small_d<double, 3, false>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream);
+  if (kind == 1)
+    return dim == 2 ? launch_small_d<float, 2, true>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream)
+                    : launch_small_d<float, 3, true>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream);
+  return dim == 2 ? launch_small_d<float, 2, false>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream)
+                  : launch_small_d<float, 3, false>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream);
 }
 
 }  // namespace hdk

@@ -67,7 +67,7 @@ class hd_scalars(_c.Structure):
 class hd_schedule(_c.Structure):
     _fields_ = [("lds_resident", _c.c_int32), ("small_block", _c.c_int32),
                 ("persistent_large", _c.c_int32), ("large_block", _c.c_int32),
-                ("ms_per_step", _c.c_double)]
+                ("small_half_lists", _c.c_int32), ("ms_per_step", _c.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -41,12 +41,13 @@ def test_autotune_keeps_state_and_picks_fastest(hd, oracle_mod, precision):
     ctx.step(30)
     before = [state(ctx, k) for k in range(len(specs))]
     chosen, trials = ctx.autotune(min_ms=2.0, max_steps=256)
-    # LDS on (block 512 or 1024) x 6 large shapes, LDS off x 6 large shapes
-    assert len(trials) == 18
+    # LDS on (block 512 or 1024; float32 also with or without half lists)
+    # x 6 shapes for the large system, then LDS off x 6
+    assert len(trials) == (18 if precision == 0 else 30)
     assert all(t["ms_per_step"] > 0 for t in trials)
     best = min(trials, key=lambda t: t["ms_per_step"])
     assert chosen["ms_per_step"] == best["ms_per_step"]
-    for key in ("lds_resident", "persistent_large", "large_block"):
+    for key in ("lds_resident", "persistent_large", "large_block", "small_half_lists"):
         assert chosen[key] == best[key]
     for k in range(len(specs)):
         after = state(ctx, k)
@@ -73,8 +74,9 @@ def test_tuned_run_equals_switched_run(hd, oracle_mod):
 
 
 @pytest.mark.parametrize("shape", [
-    {"lds_resident": 1, "small_block": 1024, "persistent_large": 0, "large_block": 128},
-    {"lds_resident": 1, "small_block": 512, "persistent_large": 1, "large_block": 1024},
+    {"lds_resident": 1, "small_block": 1024, "persistent_large": 0, "large_block": 128, "small_half_lists": 1},
+    {"lds_resident": 1, "small_block": 512, "persistent_large": 1, "large_block": 1024, "small_half_lists": 0},
+    {"lds_resident": 1, "small_block": 512, "persistent_large": 0, "large_block": 256, "small_half_lists": 1},
     {"lds_resident": 0, "small_block": 0, "persistent_large": 0, "large_block": 512},
     {"lds_resident": 0, "small_block": 0, "persistent_large": 1, "large_block": 256},
 ])
@@ -85,6 +87,7 @@ def test_every_shape_follows_the_oracle(hd, oracle_mod, shape):
     ctx.compute()
     got = ctx.schedule()
     assert got["lds_resident"] == shape["lds_resident"] and got["large_block"] == shape["large_block"]
+    assert got["small_half_lists"] == shape.get("small_half_lists", 0)
     for k, s in enumerate(specs):
         ref = oracle_mod.OracleSystem(s).compute()
         assert rel(ctx.forces(k), ref["f_tot"]) <= 1e-5, k
@@ -108,7 +111,10 @@ def test_schedule_argument_errors(hd, oracle_mod):
 
 
 SHAPES = {
-    "lds+grid": {"lds_resident": 1, "small_block": 512, "persistent_large": 0, "large_block": 256},
+    "lds+grid": {"lds_resident": 1, "small_block": 512, "persistent_large": 0, "large_block": 256,
+                 "small_half_lists": 1},
+    "lds-full": {"lds_resident": 1, "small_block": 512, "persistent_large": 0, "large_block": 256,
+                 "small_half_lists": 0},
     "grid": {"lds_resident": 0, "small_block": 0, "persistent_large": 0, "large_block": 128},
     "persistent": {"lds_resident": 0, "small_block": 0, "persistent_large": 1, "large_block": 512},
 }
@@ -118,6 +124,7 @@ SHAPES = {
     ("persistent", "grid", 0),       # one-workgroup rebuild, then the grid's counting sort
     ("lds+grid", "persistent", 1),   # half lists in LDS, then full lists in global memory
     ("grid", "lds+grid", 1),
+    ("lds+grid", "lds-full", 1),     # half lists, then full lists, both in LDS
 ])
 def test_switch_equals_restore_into_fresh_context(hd, oracle_mod, first, second, precision):
     """Switching shape mid-run gives the same trajectory as checkpointing and
