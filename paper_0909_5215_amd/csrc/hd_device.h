@@ -31,6 +31,9 @@ struct SysDesc {
   double k_spring, f_normal, x_slider, v_slider;
   int32_t bias_on, m_b;
   double dv_max, g_lo, g_hi;
+  // reciprocals used by the per-step scalars: 1/kT, 1/(g_L - g_U), 1/n_R,
+  // k/n_R^2
+  double inv_kT, inv_glh, inv_nR, k_nR2;
   // cell grid, fixed for the life of the context
   int32_t nc[3], ncell;
   double lo[3], inv_h[3];
@@ -139,17 +142,64 @@ __device__ __forceinline__ void normals_n(uint64_t seed, int64_t step, uint32_t 
   }
 }
 
+// Float32 form of the same transform for the float32 pair-arithmetic mode:
+// the same Philox words, the logarithm and the angle evaluated in float32.
+// -2 ln u is taken from whichever of u and 1 - u is below one half, both
+// formed from the integer word so that the small one is nearly exact; the
+// angle 2 pi u is split into its quadrant (top two bits of the word) and a
+// fraction of a quarter turn.  Relative error about 1e-7.
+__device__ __forceinline__ float m2ln_u32(uint32_t c) {
+  const float s = 2.3283064365386963e-10f;  // 2^-32
+  if (c < 0x80000000u) return -2.0f * logf(((float)c + 0.5f) * s);
+  return -2.0f * log1pf(-(((float)(0xffffffffu - c) + 0.5f) * s));
+}
+
+__device__ __forceinline__ void sincos_turn_u32(uint32_t c, float &sn, float &cs) {
+  const float th = ((float)(c & 0x3fffffffu) + 0.5f) * (1.5707963267948966f * 9.313225746154785e-10f);
+  float s0, c0;
+  sincosf(th, &s0, &c0);
+  const uint32_t q = c >> 30;
+  sn = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
+  cs = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
+}
+
+template <int NZ>
+__device__ __forceinline__ void normals_nf(uint64_t seed, int64_t step, uint32_t particle, uint32_t tag,
+                                           double z[3]) {
+  uint32_t c[4] = {(uint32_t)((uint64_t)step & 0xffffffffu), (uint32_t)((uint64_t)step >> 32),
+                   particle, tag};
+  philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  const float r0 = sqrtf(m2ln_u32(c[0]));
+  float sn, cs;
+  sincos_turn_u32(c[1], sn, cs);
+  z[0] = (double)(r0 * cs);
+  z[1] = (double)(r0 * sn);
+  if constexpr (NZ > 2) {
+    float s3, c3;
+    sincos_turn_u32(c[3], s3, c3);
+    z[2] = (double)(sqrtf(m2ln_u32(c[2])) * c3);
+  }
+}
+
+// Langevin normals of a kernel computing pairs in T: float64 transform for
+// float64, float32 transform for float32.
+template <int NZ, typename T>
+__device__ __forceinline__ void noise(uint64_t seed, int64_t step, uint32_t particle, double z[3]) {
+  if constexpr (sizeof(T) == 4) normals_nf<NZ>(seed, step, particle, 0u, z);
+  else normals_n<NZ>(seed, step, particle, 0u, z);
+}
+
 // Slope bias of eq. 14 and its derivative in g.
 __device__ __forceinline__ void bias_switch(const SysDesc &D, double g, double &dv, double &dvp) {
   if (g >= D.g_hi) { dv = D.dv_max; dvp = 0.0; return; }
   if (g <= D.g_lo) { dv = 0.0; dvp = 0.0; return; }
-  const double xi = (g - D.g_hi) / (D.g_lo - D.g_hi);
+  const double xi = (g - D.g_hi) * D.inv_glh;
   double xm1 = 1.0;
   for (int q = 0; q < D.m_b - 1; ++q) xm1 *= xi;
   const double xm = xm1 * xi;
   const double one = 1.0 - xm;
   dv = D.dv_max * one * one;
-  dvp = -2.0 * D.m_b * D.dv_max * one * xm1 / (D.g_lo - D.g_hi);
+  dvp = -2.0 * D.m_b * D.dv_max * one * xm1 * D.inv_glh;
 }
 
 // Per-system scalars derived from the reduced sums (LJ part) and the rigid
@@ -175,7 +225,6 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
   for (int k = 0; k < 3; ++k) { S.Fd[k] = 0.0; S.hud[k] = 0.0; S.sumFb[k] = 0.0; }
   if (D.n_rigid > 0) {
     const int perp = dim - 1;
-    const double nR = (double)D.n_rigid;
     S.x_tip = XR[0] - D.XR0[0];
     const double ext = S.xs - S.x_tip;
     S.f_lat = D.k_spring * ext;
@@ -190,26 +239,31 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
     S.Fd[perp] += -D.f_normal;
     constexpr int nspring = dim == 3 ? 2 : 1;
 #pragma unroll
-    for (int k = 0; k < nspring; ++k) S.hud[k] = D.k_spring / (nR * nR) * sums[9 + k];
+    for (int k = 0; k < nspring; ++k) S.hud[k] = D.k_nR2 * sums[9 + k];
     // drive share of each rigid atom enters F.u
 #pragma unroll
-    for (int k = 0; k < dim; ++k) G += (S.Fd[k] / nR) * sums[9 + k];
+    for (int k = 0; k < dim; ++k) G += (S.Fd[k] * D.inv_nR) * sums[9 + k];
   }
   S.e_pot = S.e_lj + S.v_drive;
   S.bad = sums[12];
-  S.d = sqrt(sums[1]);
-  S.g = (S.d < 1e-12) ? 0.0 : -G / S.d;
+  // d = |u| and 1/d from one reciprocal square root refined by two Newton
+  // steps (relative error ~1e-16)
+  const double d2 = sums[1];
+  double inv_d = 0.0;
+  if (d2 > 0.0) {
+    double y = __builtin_amdgcn_rsq(d2);
+    y = y * __builtin_fma(-0.5 * d2 * y, y, 1.5);
+    y = y * __builtin_fma(-0.5 * d2 * y, y, 1.5);
+    inv_d = y;
+  }
+  S.d = d2 * inv_d;
+  const bool has_d = S.d >= 1e-12;
+  S.g = has_d ? -G * inv_d : 0.0;
   S.dv = 0.0; S.dvp = 0.0;
   if (D.bias_on) bias_switch(D, S.g, S.dv, S.dvp);
-  if (S.d >= 1e-12) {
-    const double inv_d = 1.0 / S.d;
-    S.bias_a = -S.dvp * inv_d;
-    S.bias_b = S.g * inv_d;
-  } else {
-    S.bias_a = 0.0;
-    S.bias_b = 0.0;
-  }
-  if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0 && D.n_rigid > 0) {
+  S.bias_a = has_d ? -S.dvp * inv_d : 0.0;
+  S.bias_b = has_d ? S.g * inv_d : 0.0;
+  if (D.bias_on && has_d && S.dvp != 0.0 && D.n_rigid > 0) {
     const double nR = (double)D.n_rigid;
 #pragma unroll
     for (int k = 0; k < dim; ++k) {
@@ -225,8 +279,8 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
 //
 // FP64: everything in double.  FP32C: the displacement and the cutoff test
 // are float64 (so the interacting set is decided exactly as in float64); the
-// pair arithmetic is float32 and the per-atom sums are compensated (Kahan-
-// Babuska/Neumaier two-term sums), converted to float64 at the end.
+// pair arithmetic is float32 and the per-atom sums are compensated (Kahan
+// two-term sums), converted to float64 at the end.
 
 struct Comp {  // Kahan compensated float sum: s - c is the running total
   float s, c;
@@ -264,22 +318,45 @@ __device__ __forceinline__ float rcp_nr(float x) {
   return __builtin_fmaf(r, e, r);
 }
 
+// The LJ parameters of atom i's type against both neighbour types (eq. 9 with
+// the pair's epsilon and sigma, energy-shifted at rc), held in registers for
+// the whole neighbour loop: the neighbour's type then selects between two
+// registers instead of indexing a table in memory per pair.
+template <typename T>
+struct LJRow {
+  T eps[2], sig2[2], shift[2];
+  __device__ __forceinline__ void load(const SysDesc &D, int ti) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if constexpr (sizeof(T) == 8) {
+        eps[b] = ti ? D.eps[2 + b] : D.eps[b];
+        sig2[b] = ti ? D.sig2[2 + b] : D.sig2[b];
+        shift[b] = ti ? D.shift[2 + b] : D.shift[b];
+      } else {
+        eps[b] = ti ? D.eps_f[2 + b] : D.eps_f[b];
+        sig2[b] = ti ? D.sig2_f[2 + b] : D.sig2_f[b];
+        shift[b] = ti ? D.shift_f[2 + b] : D.shift_f[b];
+      }
+    }
+  }
+};
+
 // One neighbour's contribution to F_i, (H u)_i and the half pair energy.
 // dx = x_i - x_j (float64, minimum image), r2 its exactly rounded square
 // norm.  The term is evaluated branch-free; a neighbour that is not `live`
 // (outside rc) contributes exactly zero.
 template <int DIM, typename T>
-__device__ __forceinline__ void pair_term(const SysDesc &D, int tt, bool live, const double dx[3], double r2,
+__device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, const double dx[3], double r2,
                                           const T ui[3], const T uj[3], PairAcc<T> &acc) {
   if constexpr (sizeof(T) == 8) {
     const double m = live ? 1.0 : 0.0;
     const double r2i = 1.0 / (live ? r2 : 1.0);
-    const double eps = D.eps[tt] * m;
-    const double sr2 = D.sig2[tt] * r2i;
+    const double eps = (tj ? R.eps[1] : R.eps[0]) * m;
+    const double sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
     const double sr6 = sr2 * sr2 * sr2;
     const double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
     const double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
-    const double e = 4.0 * eps * (sr6 * sr6 - sr6) - D.shift[tt] * m;
+    const double e = 4.0 * eps * (sr6 * sr6 - sr6) - (tj ? R.shift[1] : R.shift[0]) * m;
     double w[3], Dw = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -296,13 +373,13 @@ __device__ __forceinline__ void pair_term(const SysDesc &D, int tt, bool live, c
   } else {
     const float m = live ? 1.0f : 0.0f;
     const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
-    const float eps = D.eps_f[tt] * m;
-    const float sr2 = D.sig2_f[tt] * r2i;
+    const float eps = (tj ? R.eps[1] : R.eps[0]) * m;
+    const float sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
     const float sr6 = sr2 * sr2 * sr2;
     const float epsr = eps * r2i * sr6;
     const float f = epsr * (48.0f * sr6 - 24.0f);
     const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
-    const float e = 4.0f * eps * sr6 * (sr6 - 1.0f) - D.shift_f[tt] * m;
+    const float e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
     float d[3], w[3], Dw = 0.0f;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -323,18 +400,18 @@ __device__ __forceinline__ void pair_term(const SysDesc &D, int tt, bool live, c
 // Float32 pair vectors for a half list: f_ij Delta (force on i), h_ij (the
 // pair's H u contribution to i) and the pair energy; j receives the negatives.
 template <int DIM>
-__device__ __forceinline__ void pair_vals_f(const SysDesc &D, int tt, bool live, const double dx[3], double r2,
+__device__ __forceinline__ void pair_vals_f(const LJRow<float> &R, int tj, bool live, const double dx[3], double r2,
                                             const float ui[3], const float uj[3], float fv[3], float hv[3],
                                             float &e) {
   const float m = live ? 1.0f : 0.0f;
   const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
-  const float eps = D.eps_f[tt] * m;
-  const float sr2 = D.sig2_f[tt] * r2i;
+  const float eps = (tj ? R.eps[1] : R.eps[0]) * m;
+  const float sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
   const float sr6 = sr2 * sr2 * sr2;
   const float epsr = eps * r2i * sr6;
   const float f = epsr * (48.0f * sr6 - 24.0f);
   const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
-  e = 4.0f * eps * sr6 * (sr6 - 1.0f) - D.shift_f[tt] * m;
+  e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
   float d[3], w[3], Dw = 0.0f;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -382,6 +459,8 @@ __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int
   const double *__restrict__ x = A.x;
   const int32_t *__restrict__ nbr = A.nbr + D.nbr_off;
   const int nn = A.nnb[off + i];
+  LJRow<T> R;
+  R.load(D, ti);
 #pragma unroll 2
   for (int q = 0; q < nn; ++q) {
     const int ent = nbr[(int64_t)q * n + i];
@@ -391,7 +470,7 @@ __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { xj[k] = x[k * N + aj]; uj[k] = u[k * N + aj]; }
     const double r2 = pair_disp<DIM>(D, xi, xj, dx);
-    pair_term<DIM, T>(D, ti * 2 + (ent & 1), r2 < D.rc2, dx, r2, ui, uj, acc);
+    pair_term<DIM, T>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
   }
 }
 
@@ -437,6 +516,14 @@ __device__ __forceinline__ double dpp_mov_f64(double v) {
 // Sum over the 64 lanes of a wavefront with DPP (quad permutes, row shifts,
 // row broadcasts), fixed order; every lane receives the total (read from lane
 // 63).
+// Value of v in lane l, returned to every lane (uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v) {
   v += dpp_mov_f64<0xb1>(v);   // quad_perm [1,0,3,2]
   v += dpp_mov_f64<0x4e>(v);   // quad_perm [2,3,0,1]

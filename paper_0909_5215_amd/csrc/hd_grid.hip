@@ -23,11 +23,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nt) {
   return x * q + min(x, r) + (b >> 3);
 }
 
-template <int DIM>
+template <int DIM, typename T>
 __device__ void rigid_advance(const SysDesc &D, const SysState &st, int64_t step, double XRn[3],
                               double VRn[3]) {
   double z[3];
-  normals_n<DIM>(D.seed, step, (uint32_t)D.n, 0u, z);
+  noise<DIM, T>(D.seed, step, (uint32_t)D.n, z);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     double v = st.VR[k], x = st.XR[k];
@@ -56,7 +56,7 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
   if (role == ROLE_MOBILE) {
     if (!compute_only) {
       double z[3];
-      normals_n<DIM>(D.seed, step, (uint32_t)i, 0u, z);
+      noise<DIM, T>(D.seed, step, (uint32_t)i, z);
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
         double v = A.v[k * N + a], x = A.x[k * N + a];
@@ -76,7 +76,7 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
   } else {
     double XRn[3], VRn[3];
     if (!compute_only) {
-      rigid_advance<DIM>(D, st, step, XRn, VRn);
+      rigid_advance<DIM, T>(D, st, step, XRn, VRn);
     } else {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) { XRn[k] = st.XR[k]; VRn[k] = st.VR[k]; }
@@ -365,7 +365,7 @@ __device__ void pairs_tile(const SysDesc &D, SysState &st, const Arrays &A, cons
     if (!compute_only) {
       for (int k = 0; k < DIM; ++k) { st.XR[k] = XRn[k]; st.VR[k] = VRn[k] + D.hdt * FR[k] * D.inv_massR; }
       st.t_md += D.dt;
-      st.t_hyper += D.dt * exp(S.dv / D.kT);
+      st.t_hyper += D.dt * exp(S.dv * D.inv_kT);
       st.step = st.step + 1;
     }
     for (int k = 0; k < DIM; ++k) st.FR[k] = FR[k];

@@ -211,7 +211,7 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
         const int64_t a = off + i;
         if ((A.tr[a] >> 1) != ROLE_MOBILE) continue;
         double z[3];
-        normals_n<DIM>(D.seed, step, (uint32_t)i, 0u, z);
+        noise<DIM, T>(D.seed, step, (uint32_t)i, z);
         double d2 = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -230,7 +230,7 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
       }
       if (tid == 0 && D.n_rigid > 0) {
         double z[3];
-        normals_n<DIM>(D.seed, step, (uint32_t)n, 0u, z);
+        noise<DIM, T>(D.seed, step, (uint32_t)n, z);
         for (int k = 0; k < DIM; ++k) {
           double v = sh_VR[k], x = sh_XR[k];
           v = v + D.hdt * sh_FR[k] * D.inv_massR;
@@ -355,7 +355,7 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
       if (!compute_only) {
         for (int k = 0; k < DIM; ++k) sh_VR[k] = sh_VR[k] + D.hdt * sh_FR[k] * D.inv_massR;
         sh_clock[0] += D.dt;
-        sh_clock[1] += D.dt * exp(S.dv / D.kT);
+        sh_clock[1] += D.dt * exp(S.dv * D.inv_kT);
         sh_step = step + 1;
       }
       if (!isfinite(S.e_pot) || S.bad > 0.0) sh_flags |= FLAG_UNSTABLE;

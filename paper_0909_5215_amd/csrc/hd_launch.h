@@ -17,14 +17,14 @@ hipError_t launch_batched(int prec, int dim, const SysDesc *descs, SysState *sta
 // displacements, cell list and neighbour list fit in one workgroup's LDS.
 // All listed systems have dimension `dim`; nmax (<= 1024) is the LDS row
 // stride and bounds every listed n; maxnb is their neighbour capacity;
-// cellmax bounds every listed ncell; rigmax bounds every listed n_rigid.
+// cellmax bounds every listed ncell.
 hipError_t launch_small(int kind, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
-                        const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax, int rigmax,
+                        const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax,
                         int block, int64_t nsteps, int mode, hipStream_t stream);
-size_t small_lds_bytes(int dim, int kind, int nmax, int maxnb, int cellmax, int rigmax);
+size_t small_lds_bytes(int dim, int kind, int nmax, int maxnb, int cellmax);
 // Dynamic LDS bytes of one LDS-resident group, and the one-time permission to
 // use that much (call outside graph capture, before the first launch).
-size_t small_group_bytes(int kind, int dim, int nmax, int maxnb, int cellmax, int rigmax);
+size_t small_group_bytes(int kind, int dim, int nmax, int maxnb, int cellmax);
 hipError_t small_allow_lds(int kind, int dim, size_t bytes);
 
 // Tiles of the grid scheduler: each tile is a contiguous atom range of one

@@ -95,7 +95,7 @@ struct hd_ctx {
     bool small = false;
     std::vector<int32_t> ids;
     int32_t *d_ids = nullptr;
-    int nmax = 0, cellmax = 1, maxnb = 32, rigmax = 1;
+    int nmax = 0, cellmax = 1, maxnb = 32;
     int block = 0;   // threads per workgroup
   };
   std::vector<Group> groups;
@@ -233,6 +233,10 @@ void fill_desc(const hd_ctx *ctx, const SysHost &s, SysDesc &D) {
   D.dv_max = s.bias.dv_max;
   D.g_lo = s.bias.g_lo;
   D.g_hi = s.bias.g_hi;
+  D.inv_kT = 1.0 / s.th.kT;
+  D.inv_glh = (s.bias.g_lo != s.bias.g_hi) ? 1.0 / (s.bias.g_lo - s.bias.g_hi) : 0.0;
+  D.inv_nR = s.n_rigid > 0 ? 1.0 / s.n_rigid : 0.0;
+  D.k_nR2 = s.n_rigid > 0 ? s.dr.k_spring / ((double)s.n_rigid * s.n_rigid) : 0.0;
   (void)ctx;
 }
 
@@ -373,7 +377,7 @@ hd_status launch_groups(hd_ctx *ctx, int64_t nsteps, int mode, hipStream_t strea
     if (G.ids.empty()) continue;
     if (G.small)
       HIPCHK(hdk::launch_small(small_kind(ctx), G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
-                               G.nmax, G.maxnb, G.cellmax, G.rigmax, G.block, nsteps, mode, stream));
+                               G.nmax, G.maxnb, G.cellmax, G.block, nsteps, mode, stream));
     else
       HIPCHK(hdk::launch_batched(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
                                  ctx->block, nsteps, mode, stream));
@@ -494,22 +498,21 @@ hd_status build_schedule(hd_ctx *ctx) {
       const SysHost &h = ctx->sys[s];
       const int maxnb = h.dim == 2 ? ctx->maxnb2 : ctx->maxnb3;
       const bool ok = h.n <= 1024 && maxnb <= 32767 &&
-                      hdk::small_lds_bytes(h.dim, prec, h.n, maxnb, ctx->h_desc[s].ncell, h.n_rigid) <= budget &&
+                      hdk::small_lds_bytes(h.dim, prec, h.n, maxnb, ctx->h_desc[s].ncell) <= budget &&
                       !ctx->small_disabled;
       if (ok) cand.push_back(s);
       else ctx->big_ids.push_back(s);
     }
     // admit candidates (by size) while the group's common layout fits
     std::sort(cand.begin(), cand.end(), [&](int a, int b) { return ctx->sys[a].n < ctx->sys[b].n; });
-    int gn[2] = {0, 0}, gc[2] = {1, 1}, gr[2] = {1, 1};
+    int gn[2] = {0, 0}, gc[2] = {1, 1};
     std::vector<int32_t> sm[2];
     for (int s : cand) {
       const int d = ctx->sys[s].dim - 2;
       const int maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
       const int n2 = std::max(gn[d], ctx->sys[s].n), c2 = std::max(gc[d], ctx->h_desc[s].ncell);
-      const int r2 = std::max(gr[d], ctx->sys[s].n_rigid);
-      if (hdk::small_lds_bytes(d + 2, prec, n2, maxnb, c2, r2) <= budget) {
-        sm[d].push_back(s); gn[d] = n2; gc[d] = c2; gr[d] = r2;
+      if (hdk::small_lds_bytes(d + 2, prec, n2, maxnb, c2) <= budget) {
+        sm[d].push_back(s); gn[d] = n2; gc[d] = c2;
       } else {
         ctx->big_ids.push_back(s);
       }
@@ -519,7 +522,7 @@ hd_status build_schedule(hd_ctx *ctx) {
       for (int s : sm[d]) ctx->small_ids.push_back(s);
       if (sm[d].empty()) continue;
       hd_ctx::Group G;
-      G.dim = d + 2; G.small = true; G.ids = sm[d]; G.nmax = gn[d]; G.cellmax = gc[d]; G.rigmax = gr[d];
+      G.dim = d + 2; G.small = true; G.ids = sm[d]; G.nmax = gn[d]; G.cellmax = gc[d];
       G.maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
       ctx->groups.push_back(G);
     }
@@ -547,7 +550,7 @@ hd_status build_schedule(hd_ctx *ctx) {
     if (G.small) {
       const int prec = small_kind(ctx);
       HIPCHK(hdk::small_allow_lds(prec, G.dim,
-                                  hdk::small_group_bytes(prec, G.dim, G.nmax, G.maxnb, G.cellmax, G.rigmax)));
+                                  hdk::small_group_bytes(prec, G.dim, G.nmax, G.maxnb, G.cellmax)));
     }
   }
   // grid plans

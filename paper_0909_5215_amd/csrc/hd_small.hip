@@ -14,24 +14,20 @@
 namespace hdk {
 
 struct SmallLayout {
-  int nmax, maxnb, cellmax, rigmax;
-  size_t off_x, off_acc, off_rig, off_ref, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
+  int nmax, maxnb, cellmax;
+  size_t off_x, off_acc, off_ref, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
 };
 
 // Pair-pass variants ("kind"): 0 float64 with full lists; 1 float32 with half
 // lists (each pair once; the partner's share of F, H u and the energy is
 // accumulated in float64 in LDS, the acc region); 2 float32 with full lists.
-__host__ __device__ inline SmallLayout small_layout(int dim, int kind, int nmax, int maxnb, int cellmax,
-                                                    int rigmax) {
+__host__ __device__ inline SmallLayout small_layout(int dim, int kind, int nmax, int maxnb, int cellmax) {
   const int tsize = kind == 0 ? 8 : 4;
   SmallLayout L;
-  L.nmax = nmax; L.maxnb = maxnb; L.cellmax = cellmax; L.rigmax = rigmax > 0 ? rigmax : 1;
+  L.nmax = nmax; L.maxnb = maxnb; L.cellmax = cellmax;
   size_t o = 0;
   L.off_x = o; o += (size_t)8 * dim * nmax;
   L.off_acc = o; if (kind == 1) o += (size_t)8 * (2 * dim + 1) * nmax;
-  // rigid-layer atoms' F, H u and u, and their offsets c_i, one slot per
-  // rigid atom (rank order)
-  L.off_rig = o; o += (size_t)8 * 4 * dim * L.rigmax;
   // per-atom reference r_O and positions at the last build
   L.off_ref = o; o += (size_t)8 * 2 * dim * nmax;
   L.off_u = o; o += (size_t)tsize * dim * nmax; o = (o + 7) & ~(size_t)7;
@@ -43,8 +39,8 @@ __host__ __device__ inline SmallLayout small_layout(int dim, int kind, int nmax,
   return L;
 }
 
-size_t small_lds_bytes(int dim, int kind, int nmax, int maxnb, int cellmax, int rigmax) {
-  return small_layout(dim, kind, nmax, maxnb, cellmax, rigmax).bytes;
+size_t small_lds_bytes(int dim, int kind, int nmax, int maxnb, int cellmax) {
+  return small_layout(dim, kind, nmax, maxnb, cellmax).bytes;
 }
 
 // Rebuild the cell list and every atom's neighbour list in LDS from the LDS
@@ -147,6 +143,16 @@ __device__ int lds_rebuild(const SysDesc &D, const double *__restrict__ xs, uint
   return block_or(ov, lds_int + 20);
 }
 
+// The scalars of a step that every thread needs for its bias force and
+// final half-kick (written by wave 0, read by all after a barrier).
+struct Bcast {
+  double Fd_n[3];   // drive force per rigid atom
+  double hud[3];    // drive Hessian term per rigid atom
+  double FR[3];     // total force on the rigid body
+  double bias_a, bias_b;
+  int bias_live, bad;
+};
+
 template <int DIM, typename T, bool HALF>
 __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Arrays &A,
                           int64_t nsteps, int mode, char *lds, const SmallLayout L) {
@@ -156,9 +162,6 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   const int64_t N = A.ntot, off = D.off;
   double *xs = (double *)(lds + L.off_x);
   double *jacc = (double *)(lds + L.off_acc);   // [2*DIM+1][stride]: F, H u, e of the j side
-  const int rstride = L.rigmax;
-  double *rig = (double *)(lds + L.off_rig);    // [3*DIM][rigmax]: rigid atoms' F, H u, u
-  double *cfs = rig + 3 * DIM * rstride;        // [DIM][rigmax]: rigid offsets c_i
   double *rOs = (double *)(lds + L.off_ref);    // [DIM][stride] r_O
   double *xbs = rOs + DIM * stride;             // [DIM][stride] positions at the last build
   T *us = (T *)(lds + L.off_u);
@@ -167,7 +170,9 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   int *cst = (int *)(lds + L.off_cst);
   int *cat = (int *)(lds + L.off_cat);
 
-  __shared__ double red[2][4 * 16];   // cross-wave sums, alternating by step
+  constexpr int NV = 4 + 3 * DIM;      // per-system sums of a step
+  __shared__ double red[2][NV * 16];  // wave partials, alternating by step
+  __shared__ Bcast bc[2];             // the step's scalars for every thread
   __shared__ int lds_int[32];
   __shared__ int vote[32];
   __shared__ uint8_t tr_all[1024];
@@ -178,7 +183,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   const bool own = i < n;
   const int64_t a = off + i;
   int tr = 0, role = ROLE_FIXED;
-  double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, ft[3] = {0, 0, 0};
+  double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, ft[3] = {0, 0, 0}, cof[3] = {0, 0, 0};
   if (own) {
     tr = A.tr[a];
     role = tr >> 1;
@@ -186,6 +191,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       x[k] = A.x[k * N + a]; v[k] = A.v[k * N + a]; ft[k] = A.ftot[k * N + a];
+      cof[k] = A.cofs[k * N + a];
       rOs[k * stride + i] = A.rO[k * N + a];
       xbs[k * stride + i] = A.xb[k * N + a];
     }
@@ -202,18 +208,13 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   if (flags & FLAG_UNSTABLE) return;
   const bool compute_only = (mode & 1) != 0;
   const bool rigid_body = D.n_rigid > 0;
+  const bool wave_rigid = __ballot(own && role == ROLE_RIGID) != 0;   // uniform per wavefront
   if (!compute_only && rigid_body && tid == 0) {
     double z[3];
-    normals_n<DIM>(D.seed, step, (uint32_t)n, 0u, z);
+    noise<DIM, T>(D.seed, step, (uint32_t)n, z);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) sh_zR[step & 1][k] = z[k];
   }
-  // rank of each rigid atom among the rigid atoms (fixed summation order)
-  int rrank_total = 0;
-  const int rrank = block_exscan((own && role == ROLE_RIGID) ? 1 : 0, lds_int, rrank_total);
-  if (own && role == ROLE_RIGID)
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) cfs[k * rstride + rrank] = A.cofs[k * N + a];
 
   const int64_t iters = compute_only ? 1 : nsteps;
   // the list lives in LDS only for this launch: rebuild at the start, from
@@ -222,14 +223,18 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   int vote_parity = 0;
   int nn = 0;
   double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, e_own = 0.0, fbv[3] = {0, 0, 0};
+  // this atom's normals for the coming step, when already drawn
+  double zn[3] = {0, 0, 0};
+  bool have_zn = false;
 
   for (int64_t it = 0; it < iters; ++it) {
     int moved = 0;
     // ---- B A O A: mobile atoms, and the rigid body in every thread --------
     if (!compute_only) {
       if (own && role == ROLE_MOBILE) {
-        double z[3];
-        normals_n<DIM>(D.seed, step, (uint32_t)i, 0u, z);
+        double z[3] = {zn[0], zn[1], zn[2]};
+        if (!have_zn) noise<DIM, T>(D.seed, step, (uint32_t)i, z);
+        have_zn = false;
         double d2 = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -265,7 +270,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         double d2 = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-          x[k] = wrapx(XR[k] + cfs[k * rstride + rrank], D.box[k], D.periodic[k]);
+          x[k] = wrapx(XR[k] + cof[k], D.box[k], D.periodic[k]);
           const double dd = minimg(x[k] - xbs[k * stride + i], D.box[k], D.hbox[k], D.periodic[k]);
           d2 += dd * dd;
         }
@@ -317,6 +322,8 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       PairAcc<T> acc;
       acc.init();
       const int ti = tr & 1;
+      LJRow<T> R;
+      R.load(D, ti);
       T ui[3];
 #pragma unroll
       for (int k = 0; k < DIM; ++k) ui[k] = (T)u64[k];
@@ -336,7 +343,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
           const double r2 = pair_disp<DIM>(D, x, xj, dx);
           const bool live = r2 < D.rc2;
           float fv[3], hv[3], e;
-          pair_vals_f<DIM>(D, ti * 2 + tj, live, dx, r2, (const float *)ui, uj, fv, hv, e);
+          pair_vals_f<DIM>(R, tj, live, dx, r2, (const float *)ui, uj, fv, hv, e);
           if (q + 1 < nn) {
             ent = nbr[(q + 1) * stride + i];
 #pragma unroll
@@ -364,7 +371,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 #pragma unroll
           for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = us[k * stride + j]; }
           const double r2 = pair_disp<DIM>(D, x, xj, dx);
-          pair_term<DIM, T>(D, ti * 2 + (ent & 1), r2 < D.rc2, dx, r2, ui, uj, acc);
+          pair_term<DIM, T>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
         }
       }
 #pragma unroll
@@ -377,7 +384,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     // the rigid body's noise for the next step, drawn while others finish
     if (!compute_only && rigid_body && tid == 0) {
       double z[3];
-      normals_n<DIM>(D.seed, step + 1, (uint32_t)n, 0u, z);
+      noise<DIM, T>(D.seed, step + 1, (uint32_t)n, z);
 #pragma unroll
       for (int k = 0; k < DIM; ++k) sh_zR[(step + 1) & 1][k] = z[k];
     }
@@ -389,94 +396,116 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         e_own += jacc[2 * DIM * stride + i];
       }
     }
-    double v4[4] = {0.0, 0.0, 0.0, 0.0};
+    // ---- per-system sums (eq. 5, 7 and the rigid layer): DPP within each
+    // wavefront, partials to LDS (barrier C); wave 0 adds them in wave order,
+    // evaluates the scalars (eq. 13-14 and the drive) and broadcasts them
+    // (barrier D) ---------------------------------------------------------
+    double vals[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) vals[q] = 0.0;
     if (own) {
-      v4[0] = e_own;
+      vals[0] = e_own;
       double f2 = 0.0;
 #pragma unroll
       for (int k = 0; k < DIM; ++k) f2 += F[k] * F[k];
-      v4[3] = (f2 <= kForceLimit2) ? 0.0 : 1.0;
+      vals[3] = (f2 <= kForceLimit2) ? 0.0 : 1.0;
       if (role != ROLE_FIXED) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) { v4[1] += u64[k] * u64[k]; v4[2] += F[k] * u64[k]; }
+        for (int k = 0; k < DIM; ++k) { vals[1] += u64[k] * u64[k]; vals[2] += F[k] * u64[k]; }
       }
       if (role == ROLE_RIGID) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          rig[k * rstride + rrank] = F[k];
-          rig[(DIM + k) * rstride + rrank] = H[k];
-          rig[(2 * DIM + k) * rstride + rrank] = u64[k];
-        }
+        for (int k = 0; k < DIM; ++k) { vals[4 + k] = F[k]; vals[4 + DIM + k] = H[k]; vals[4 + 2 * DIM + k] = u64[k]; }
       }
     }
-    // ---- per-system sums: E, d^2, G, runaway count (DPP + fixed wave order;
-    // barrier C), rigid-layer sums from their slots in rank order ------------
-    {
-      double *rb = red[step & 1];
+    double *rb = red[step & 1];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v4[k] = wave_sum_f64(v4[k]);
-      if (lane == 0) {
+    for (int q = 0; q < 4; ++q) vals[q] = wave_sum_f64(vals[q]);
+    // rigid-layer sums only in the wavefronts that hold rigid atoms (the
+    // others contribute exact zeros)
+    if (wave_rigid) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) rb[k * 16 + wave] = v4[k];
-      }
-      __syncthreads();
-      const int nw = (blockDim.x + 63) >> 6;
-      double acc4[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int w = 0; w < nw; ++w) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc4[k] += rb[k * 16 + w];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) v4[k] = acc4[k];
+      for (int q = 4; q < NV; ++q) vals[q] = wave_sum_f64(vals[q]);
     }
-    double sums[NRED];
-    sums[0] = v4[0]; sums[1] = v4[1]; sums[2] = v4[2]; sums[12] = v4[3];
-    {
-      double rs[3 * DIM];
+    if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < 3 * DIM; ++q) rs[q] = 0.0;
-      for (int base = 0; base < rrank_total; base += 64) {
-        const bool in = base + lane < rrank_total;
-#pragma unroll
-        for (int q = 0; q < 3 * DIM; ++q)
-          rs[q] += wave_sum_f64(in ? rig[q * rstride + base + lane] : 0.0);
-      }
-#pragma unroll
-      for (int k = 0; k < 3; ++k) { sums[3 + k] = 0.0; sums[6 + k] = 0.0; sums[9 + k] = 0.0; }
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) { sums[3 + k] = rs[k]; sums[6 + k] = rs[DIM + k]; sums[9 + k] = rs[2 * DIM + k]; }
+      for (int q = 0; q < NV; ++q) rb[q * 16 + wave] = vals[q];
+    }
+    __syncthreads();   // barrier C
+    // while wave 0 evaluates the scalars, the other wavefronts draw their
+    // atoms' normals for the next step (they depend on the counter only)
+    if (wave != 0 && !compute_only && own && role == ROLE_MOBILE && it + 1 < iters) {
+      noise<DIM, T>(D.seed, step + 1, (uint32_t)i, zn);
+      have_zn = true;
     }
     const int64_t estep = compute_only ? step : step + 1;
+    Bcast &B = bc[step & 1];
     Scal S;
-    eval_scalars<DIM>(D, sums, XR, estep, S);
-    // ---- bias force, total force, final B ------------------------------------
-    if (own) {
+    if (wave == 0) {
+      // lane q adds sum q over the waves in wave order
+      const int nw = (blockDim.x + 63) >> 6;
+      double t = 0.0;
+      if (lane < NV)
+        for (int w = 0; w < nw; ++w) t += rb[lane * 16 + w];
+      double sums[NRED];
+#pragma unroll
+      for (int q = 0; q < NRED; ++q) sums[q] = 0.0;
+      sums[0] = readlane_f64(t, 0);
+      sums[1] = readlane_f64(t, 1);
+      sums[2] = readlane_f64(t, 2);
+      sums[12] = readlane_f64(t, 3);
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
-        double f = F[k], h = H[k], fb = 0.0;
-        if (role != ROLE_FIXED) {
-          if (role == ROLE_RIGID) { f += S.Fd[k] / (double)D.n_rigid; h += S.hud[k]; }
-          if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0)
-            fb = S.bias_a * (h - f - S.bias_b * u64[k]);
+        sums[3 + k] = readlane_f64(t, 4 + k);
+        sums[6 + k] = readlane_f64(t, 4 + DIM + k);
+        sums[9 + k] = readlane_f64(t, 4 + 2 * DIM + k);
+      }
+      eval_scalars<DIM>(D, sums, XR, estep, S);
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          B.Fd_n[k] = S.Fd[k] / (double)(D.n_rigid > 0 ? D.n_rigid : 1);
+          B.hud[k] = S.hud[k];
+          B.FR[k] = sums[3 + k] + S.Fd[k] + S.sumFb[k];
         }
+        B.bias_a = S.bias_a;
+        B.bias_b = S.bias_b;
+        B.bias_live = (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0) ? 1 : 0;
+        B.bad = (!isfinite(S.e_pot) || S.bad > 0.0) ? 1 : 0;
+      }
+    }
+    __syncthreads();   // barrier D
+    // the boosted clock (eq. 3) is wave 0's alone, off the others' path
+    if (wave == 0 && !compute_only) t_hyper += D.dt * exp(S.dv * D.inv_kT);
+    // ---- bias force, total force, final B ------------------------------------
+    // one batch of LDS reads, then branch-free arithmetic
+    const Bcast Bl = B;
+    {
+      const bool rigid = own && role == ROLE_RIGID;
+      const bool biased = own && role != ROLE_FIXED && Bl.bias_live;
+      const bool kick = !compute_only && own && role == ROLE_MOBILE;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const double f = F[k] + (rigid ? Bl.Fd_n[k] : 0.0);
+        const double h = H[k] + (rigid ? Bl.hud[k] : 0.0);
+        const double fb = biased ? Bl.bias_a * (h - f - Bl.bias_b * u64[k]) : 0.0;
         F[k] = f;
         H[k] = h;
         fbv[k] = fb;
         ft[k] = f + fb;
-        if (!compute_only && role == ROLE_MOBILE) v[k] = v[k] + D.hdt * ft[k] * D.inv_mass;
+        v[k] = kick ? v[k] + D.hdt * ft[k] * D.inv_mass : v[k];
       }
     }
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) FR[k] = sums[3 + k] + S.Fd[k] + S.sumFb[k];
+    for (int k = 0; k < DIM; ++k) FR[k] = Bl.FR[k];
     if (!compute_only) {
       if (rigid_body)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) VR[k] = VR[k] + D.hdt * FR[k] * D.inv_massR;
       t_md += D.dt;
-      if (wave == 0) t_hyper += D.dt * exp(S.dv / D.kT);
       step = step + 1;
     }
-    const bool bad = !isfinite(S.e_pot) || S.bad > 0.0;
+    const bool bad = Bl.bad != 0;
     if (bad) flags |= FLAG_UNSTABLE;
     if ((it == iters - 1 || bad) && tid == 0) sh_out = S;
     if (bad) break;
@@ -568,8 +597,8 @@ hipError_t small_allow_lds(int kind, int dim, size_t bytes) {
   return dim == 2 ? allow_lds_d<float, 2, false>((int)bytes) : allow_lds_d<float, 3, false>((int)bytes);
 }
 
-size_t small_group_bytes(int kind, int dim, int nmax, int maxnb, int cellmax, int rigmax) {
-  return small_layout(dim, kind, nmax, maxnb, cellmax, rigmax).bytes;
+size_t small_group_bytes(int kind, int dim, int nmax, int maxnb, int cellmax) {
+  return small_layout(dim, kind, nmax, maxnb, cellmax).bytes;
 }
 
 template <typename T, int DIM, bool HALF>
@@ -586,13 +615,13 @@ static hipError_t launch_small_d(const SysDesc *descs, SysState *states, const A
 }
 
 hipError_t launch_small(int kind, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
-                        const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax, int rigmax,
+                        const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax,
                         int block, int64_t nsteps, int mode, hipStream_t stream) {
   if (nsys <= 0) return hipSuccess;
   // one thread per atom: the workgroup must cover the largest system
   if (nmax > 1024 || block < nmax || (block != 256 && block != 512 && block != 1024)) return hipErrorInvalidValue;
   if (kind < 0 || kind > 2 || (dim != 2 && dim != 3)) return hipErrorInvalidValue;
-  const SmallLayout L = small_layout(dim, kind, nmax, maxnb, cellmax, rigmax);
+  const SmallLayout L = small_layout(dim, kind, nmax, maxnb, cellmax);
   const size_t b = L.bytes;
   if (kind == 0)
     return dim == 2 ? launch_small_d<double, 2, false>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream)
