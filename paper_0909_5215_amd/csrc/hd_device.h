@@ -66,10 +66,20 @@ struct Arrays {
   int32_t *cell_count, *cell_start, *cell_atoms, *cidx;
   int32_t *sys_of;                        // [ntot] system of each batch atom
   double *partials;                       // grid kernels: per-tile sums
-  int32_t *tile_done;                     // grid kernels: per-system counters
   double *XR_next;                        // grid kernels: [S][6] rigid body after drift
   int32_t *rebuild_flag;                  // grid kernels: [S]
+  // grid kernels: atoms are visited in cell-sorted order.  pos[a] is the
+  // sorted position of atom a within its system (cell_atoms is the inverse);
+  // rec holds one 64-byte pair record per sorted position, refreshed by
+  // every drift: x (float64, doubles 0-2), u (float64, doubles 3-5) and
+  // type | role << 1 (double 7).  Neighbour lists hold sorted positions, so a
+  // neighbour's data is one aligned record, and the atoms of a wavefront
+  // share cells and read nearby records.
+  int32_t *pos;                           // [ntot]
+  double *rec;                            // [ntot][8]
 };
+
+constexpr int kRecDoubles = 8;
 
 // ---------------------------------------------------------------------------
 // Small helpers
@@ -431,6 +441,14 @@ __device__ __forceinline__ void pair_vals_f(const LJRow<float> &R, int tj, bool 
 // rounded operation by operation so that the cutoff decision is exactly the
 // float64 one.
 //
+// r2 + d*d rounded twice, as the float64 rule has it: no fused multiply-add
+// (the pragma keeps the compiler from contracting the pair).
+__device__ __forceinline__ double add_sq_exact(double r2, double d) {
+#pragma clang fp contract(off)
+  const double p = d * d;
+  return r2 + p;
+}
+
 // Branch-free minimum image: dx - L rint(dx/L) (inv_box is 0 on open axes).
 // Every pair of a list is closer than rc + skin <= L/2, and for those this
 // equals the strict rule (subtract/add L beyond +-L/2) exactly: the shift is
@@ -443,7 +461,7 @@ __device__ __forceinline__ double pair_disp(const SysDesc &D, const double xi[3]
   for (int k = 0; k < DIM; ++k) {
     const double raw = xi[k] - xj[k];
     dx[k] = __builtin_fma(-D.box[k], __builtin_rint(raw * D.inv_box[k]), raw);
-    r2 = __dadd_rn(r2, __dmul_rn(dx[k], dx[k]));
+    r2 = add_sq_exact(r2, dx[k]);
   }
   return r2;
 }
@@ -469,6 +487,35 @@ __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int
     T uj[3];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { xj[k] = x[k * N + aj]; uj[k] = u[k * N + aj]; }
+    const double r2 = pair_disp<DIM>(D, xi, xj, dx);
+    pair_term<DIM, T>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
+  }
+}
+
+// Pair pass of the atom at sorted position p over its full list (entries
+// hold sorted positions), neighbours read from the packed records; same
+// arithmetic as pair_atom.
+template <int DIM, typename T>
+__device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
+                                              const double xi[3], const T ui[3], int ti,
+                                              PairAcc<T> &acc) {
+  const int64_t off = D.off;
+  const int n = D.n;
+  const double *__restrict__ rec = A.rec + off * kRecDoubles;
+  const int32_t *__restrict__ nbr = A.nbr + D.nbr_off;
+  const int nn = A.nnb[off + p];
+  LJRow<T> R;
+  R.load(D, ti);
+#pragma unroll 2
+  for (int q = 0; q < nn; ++q) {
+    // the list is read once per step: a streaming load, so that it does not
+    // evict the records the neighbouring atoms share
+    const int ent = __builtin_nontemporal_load(nbr + (int64_t)q * n + p);
+    const double *r = rec + (int64_t)(ent >> 1) * kRecDoubles;
+    double xj[3], dx[3];
+    T uj[3];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; }
     const double r2 = pair_disp<DIM>(D, xi, xj, dx);
     pair_term<DIM, T>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
   }

@@ -49,8 +49,15 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
   const int i = t.first + threadIdx.x;
   if (threadIdx.x >= t.count) return;
   const int64_t N = A.ntot, a = D.off + i;
-  const int role = A.tr[a] >> 1;
-  if (role == ROLE_FIXED) return;
+  const int tr = A.tr[a], role = tr >> 1;
+  double *rec = A.rec + (D.off + A.pos[a]) * kRecDoubles;
+  if (role == ROLE_FIXED) {
+    // fixed atoms: position as is, u = 0
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { rec[k] = A.x[k * N + a]; rec[3 + k] = 0.0; }
+    rec[7] = (double)tr;
+    return;
+  }
   const int64_t step = st.step;
   double xn[3] = {0, 0, 0};
   if (role == ROLE_MOBILE) {
@@ -96,10 +103,14 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
   T *u = (T *)A.u;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    u[k * N + a] = (T)minimg(xn[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+    const double uk = minimg(xn[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+    u[k * N + a] = (T)uk;
+    rec[k] = xn[k];
+    rec[3 + k] = uk;
     const double dd = minimg(xn[k] - A.xb[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
     d2 += dd * dd;
   }
+  rec[7] = (double)tr;
   // an atom outside its skin forces a rebuild from the current positions
   // (value 1), superseding a pending rebuild from build positions (value 2)
   if (d2 > D.skin_half2) atomicExch(&A.rebuild_flag[A.sys_of[a]], 1);
@@ -203,8 +214,12 @@ __global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ 
   }
 }
 
+// List of the atom at sorted position p (atom i): candidates cell by cell in
+// stencil order, within a cell in index order (the cells are sorted); each
+// entry holds the neighbour's sorted position and type.  Positions from xs
+// (the current or the recorded build positions).
 template <int DIM>
-__device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__restrict__ xs, int i) {
+__device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__restrict__ xs, int p, int i) {
   const int64_t N = A.ntot, off = D.off, ai = off + i;
   const int n = D.n;
   double xi[3];
@@ -239,20 +254,19 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__re
         }
         if (skip) continue;
         const int q = (q3[2] * D.nc[1] + q3[1]) * D.nc[0] + q3[0];
-        for (int p = cstart[q]; p < cstart[q + 1]; ++p) {
-          const int j = catoms[p];
-          if (j == i) continue;
-          const int64_t aj = off + j;
+        for (int pp = cstart[q]; pp < cstart[q + 1]; ++pp) {
+          if (pp == p) continue;
+          const int64_t aj = off + catoms[pp];
           const int trj = A.tr[aj], rj = trj >> 1;
           if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
-          double r2 = 0.0;
+          double xj[3], dx[3];
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) {
-            const double d = minimg(xs[k * N + aj] - xi[k], D.box[k], D.hbox[k], D.periodic[k]);
-            r2 = __dadd_rn(r2, __dmul_rn(d, d));
-          }
+          for (int k = 0; k < DIM; ++k) xj[k] = xs[k * N + aj];
+          // r^2 exactly as the float64 rule: minimum image, then the sum of
+          // squares axis by axis without contraction
+          const double r2 = pair_disp<DIM>(D, xi, xj, dx);
           if (r2 < D.rl2) {
-            if (cnt < D.maxnb) list[(int64_t)cnt * n + i] = (j << 1) | (trj & 1);
+            if (cnt < D.maxnb) list[(int64_t)cnt * n + p] = (pp << 1) | (trj & 1);
             ++cnt;
           }
         }
@@ -267,42 +281,55 @@ __global__ __launch_bounds__(1024) void kg_build_list(const SysDesc *__restrict_
   const int flag = A.rebuild_flag[t.sys];
   if (!flag || threadIdx.x >= t.count) return;
   const SysDesc &D = descs[t.sys];
-  const int i = t.first + threadIdx.x;
-  const int64_t a = D.off + i, N = A.ntot;
+  // one thread per sorted position: the atoms of a wavefront share cells
+  const int p = t.first + threadIdx.x;
+  const int64_t off = D.off, N = A.ntot;
+  const int i = A.cell_atoms[off + p];
+  const int64_t a = off + i;
   const double *xs = flag == 2 ? A.xb : A.x;
-  const int c = D.dim == 2 ? list_atom_g<2>(D, A, xs, i) : list_atom_g<3>(D, A, xs, i);
-  A.nnb[a] = c < D.maxnb ? c : D.maxnb;
+  const int c = D.dim == 2 ? list_atom_g<2>(D, A, xs, p, i) : list_atom_g<3>(D, A, xs, p, i);
+  A.nnb[off + p] = c < D.maxnb ? c : D.maxnb;
   if (c > D.maxnb) atomicOr(&states[t.sys].flags, FLAG_NBR_OVERFLOW);
+  // the atom's record moves to its new sorted position (current x and u)
+  A.pos[a] = p;
+  double *rec = A.rec + (off + p) * kRecDoubles;
+  const int tr = A.tr[a];
+  for (int k = 0; k < D.dim; ++k) {
+    const double xk = A.x[k * N + a];
+    rec[k] = xk;
+    rec[3 + k] = (tr >> 1) == ROLE_FIXED ? 0.0 : minimg(xk - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+  }
+  rec[7] = (double)tr;
   if (flag != 2)
     for (int k = 0; k < D.dim; ++k) A.xb[k * N + a] = A.x[k * N + a];
-  if (i == 0 && flag != 2) atomicAdd(&states[t.sys].n_rebuilds, 1);
+  if (p == 0 && flag != 2) atomicAdd(&states[t.sys].n_rebuilds, 1);
 }
 
 // ---- pair pass with per-tile sums and last-tile reduction ------------------
 template <int DIM, typename T>
-__device__ void pairs_tile(const SysDesc &D, SysState &st, const Arrays &A, const Tile &t,
-                           GridScal *gs, int tile_index, bool compute_only) {
+__device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int tile_index) {
   __shared__ double red[NRED * 16];
-  __shared__ int last;
   const int64_t N = A.ntot;
   double sums[NRED];
 #pragma unroll
   for (int q = 0; q < NRED; ++q) sums[q] = 0.0;
   if (threadIdx.x < t.count) {
-    const int i = t.first + threadIdx.x;
-    const int64_t a = D.off + i;
-    const int tr = A.tr[a], role = tr >> 1;
+    // one thread per sorted position; results go to the atom's own index
+    const int p = t.first + threadIdx.x;
+    const int64_t a = D.off + A.cell_atoms[D.off + p];
+    const double *r = A.rec + (D.off + p) * kRecDoubles;
+    const int tr = (int)r[7], role = tr >> 1;
     double xi[3] = {0, 0, 0}, u64[3] = {0, 0, 0};
     T ui[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      xi[k] = A.x[k * N + a];
-      if (role != ROLE_FIXED) u64[k] = minimg(xi[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+      xi[k] = r[k];
+      u64[k] = r[3 + k];
       ui[k] = (T)u64[k];
     }
     PairAcc<T> acc;
     acc.init();
-    pair_atom<DIM, T>(D, A, i, xi, ui, tr & 1, acc);
+    pair_atom_rec<DIM, T>(D, A, p, xi, ui, tr & 1, acc);
     double F[3], H[3], e;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -328,27 +355,26 @@ __device__ void pairs_tile(const SysDesc &D, SysState &st, const Arrays &A, cons
     }
   }
   block_sum<NRED>(sums, red);
-  const int s = t.sys;
   double *part = A.partials + (int64_t)tile_index * NRED;
   if (threadIdx.x < NRED) part[threadIdx.x] = sums[threadIdx.x];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int prev = atomicAdd(&A.tile_done[s], 1);
-    last = (prev == t.tiles_in_sys - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // last tile of the system: fixed-order reduction over its tiles
-  const int first_tile = tile_index - t.tile_in_sys;
+}
+
+// Per-system sums of the tile partials in tile order (one workgroup per
+// system), then the scalars (eq. 5, 7, 13-14, the drive), the rigid body's
+// final half-kick and the boosted clock (eq. 3).  A separate launch: the
+// kernel boundary makes every tile's partials visible without device-wide
+// fences inside the pair kernel.
+template <int DIM>
+__device__ void reduce_system(const SysDesc &D, SysState &st, const Arrays &A, int s, int first_tile,
+                              int ntiles_s, GridScal *gs, bool compute_only) {
+  __shared__ double red[NRED * 16];
   double tot[NRED];
 #pragma unroll
   for (int q = 0; q < NRED; ++q) tot[q] = 0.0;
-  for (int k = threadIdx.x; k < t.tiles_in_sys; k += blockDim.x) {
+  for (int k = threadIdx.x; k < ntiles_s; k += blockDim.x) {
     const double *p = A.partials + (int64_t)(first_tile + k) * NRED;
 #pragma unroll
-    for (int q = 0; q < NRED; ++q) tot[q] += __hip_atomic_load(&p[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int q = 0; q < NRED; ++q) tot[q] += p[q];
   }
   block_sum<NRED>(tot, red);
   if (threadIdx.x == 0) {
@@ -375,21 +401,32 @@ __device__ void pairs_tile(const SysDesc &D, SysState &st, const Arrays &A, cons
     if (!isfinite(S.e_pot) || S.bad > 0.0) st.flags |= FLAG_UNSTABLE;
     gs[s].S = S;
     for (int k = 0; k < 3; ++k) { gs[s].VRn[k] = st.VR[k]; gs[s].XRn[k] = st.XR[k]; }
-    A.tile_done[s] = 0;
     A.rebuild_flag[s] = 0;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ descs,
+__global__ __launch_bounds__(256) void kg_reduce(const SysDesc *__restrict__ descs,
                                                  SysState *__restrict__ states, Arrays A,
-                                                 const Tile *__restrict__ tiles, int ntiles,
-                                                 GridScal *gs, int compute_only) {
+                                                 const int32_t *__restrict__ sys_ids,
+                                                 const int32_t *__restrict__ sys_tile0,
+                                                 const Tile *__restrict__ tiles, GridScal *gs,
+                                                 int compute_only) {
+  const int s = sys_ids[blockIdx.x];
+  const int first = sys_tile0[blockIdx.x];
+  const int nts = tiles[first].tiles_in_sys;
+  const SysDesc &D = descs[s];
+  if (D.dim == 2) reduce_system<2>(D, states[s], A, s, first, nts, gs, compute_only != 0);
+  else reduce_system<3>(D, states[s], A, s, first, nts, gs, compute_only != 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ descs, Arrays A,
+                                                 const Tile *__restrict__ tiles, int ntiles) {
   const int ti = xcd_tile(blockIdx.x, ntiles);
   const Tile t = tiles[ti];
   const SysDesc &D = descs[t.sys];
-  if (D.dim == 2) pairs_tile<2, T>(D, states[t.sys], A, t, gs, ti, compute_only != 0);
-  else pairs_tile<3, T>(D, states[t.sys], A, t, gs, ti, compute_only != 0);
+  if (D.dim == 2) pairs_tile<2, T>(D, A, t, ti);
+  else pairs_tile<3, T>(D, A, t, ti);
 }
 
 // ---- bias force, total force and final B -----------------------------------
@@ -470,11 +507,13 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
                      descs, A, P.sys_ids, P.nsys);
   hipLaunchKernelGGL(kg_build_list, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt);
   if (prec == 0)
-    hipLaunchKernelGGL(kg_pairs<double>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, gs, co);
+    hipLaunchKernelGGL(kg_pairs<double>, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
   else
-    hipLaunchKernelGGL(kg_pairs<float>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, gs, co);
+    hipLaunchKernelGGL(kg_pairs<float>, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
+  hipLaunchKernelGGL(kg_reduce, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids, P.sys_tile0,
+                     P.tiles, gs, co);
   hipLaunchKernelGGL(kg_kick, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, co);
-  nl += 8;
+  nl += 9;
   if (launches) *launches += nl;
   return hipGetLastError();
 }

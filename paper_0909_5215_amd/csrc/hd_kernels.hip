@@ -87,7 +87,7 @@ __device__ int build_list_atom(const SysDesc &D, const Arrays &A, const double *
 #pragma unroll
           for (int k = 0; k < DIM; ++k) {
             const double d = minimg(xs[k * N + aj] - xi[k], D.box[k], D.hbox[k], D.periodic[k]);
-            r2 = __dadd_rn(r2, __dmul_rn(d, d));
+            r2 = add_sq_exact(r2, d);
           }
           if (r2 < D.rl2) {
             if (cnt < D.maxnb) list[(int64_t)cnt * n + i] = (j << 1) | (trj & 1);

@@ -38,6 +38,7 @@ struct GridPlan {
   int ntiles;
   int block;               // threads per tile (== max atoms per tile)
   const int32_t *sys_ids;  // device, systems covered
+  const int32_t *sys_tile0;  // device, first tile of each covered system
   int nsys;
   int max_ncell;           // largest cell count among the covered systems
   void *gscal;             // device, per-system scalars of the last evaluation

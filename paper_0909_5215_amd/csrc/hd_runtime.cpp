@@ -43,8 +43,10 @@ struct SysHost {
 };
 
 struct Plan {
+  std::vector<int> ids;  // systems of the plan
   hdk::Tile *d_tiles = nullptr;
   int32_t *d_sys = nullptr;
+  int32_t *d_tile0 = nullptr;
   hdk::GridPlan gp{};
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
@@ -113,6 +115,10 @@ struct hd_ctx {
   hipGraphExec_t batched_graph = nullptr;  // one chunk of the batched scheduler
   int64_t batched_graph_launches = 0;
   bool all_frozen = false;
+  // per system: its neighbour list was last written by the grid kernels
+  // (rows and entries are cell-sorted positions) rather than by a
+  // one-workgroup kernel (atom indices)
+  std::vector<uint8_t> sorted_lists;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   int64_t last_launches = 0;
@@ -310,10 +316,12 @@ hd_status check_sys(hd_ctx *ctx, int32_t s) {
 hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
   const int B = ctx->block;
   std::vector<hdk::Tile> tiles;
+  std::vector<int32_t> tile0;
   int max_ncell = 1;
   for (int s : systems) {
     const int n = ctx->sys[s].n;
     const int nt = (n + B - 1) / B;
+    tile0.push_back((int32_t)tiles.size());
     for (int t = 0; t < nt; ++t) {
       hdk::Tile T{};
       T.sys = s;
@@ -329,13 +337,20 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
   if (st != HD_OK) return st;
   st = dalloc(ctx, &P.d_sys, systems.size(), true);
   if (st != HD_OK) return st;
+  st = dalloc(ctx, &P.d_tile0, systems.size(), true);
+  if (st != HD_OK) return st;
   HIPCHK(hipMemcpyAsync(P.d_tiles, tiles.data(), tiles.size() * sizeof(hdk::Tile), hipMemcpyHostToDevice, ctx->stream));
   std::vector<int32_t> ids(systems.begin(), systems.end());
   HIPCHK(hipMemcpyAsync(P.d_sys, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(P.d_tile0, tile0.data(), tile0.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  P.ids = systems;
   P.gp.tiles = P.d_tiles;
   P.gp.ntiles = (int)tiles.size();
   P.gp.block = B;
   P.gp.sys_ids = P.d_sys;
+  P.gp.sys_tile0 = P.d_tile0;
   P.gp.nsys = (int)systems.size();
   P.gp.max_ncell = max_ncell;
   P.gp.gscal = ctx->d_gscal;
@@ -375,6 +390,7 @@ hd_status launch_groups(hd_ctx *ctx, int64_t nsteps, int mode, hipStream_t strea
   const int prec = ctx->prec == HD_FP64 ? 0 : 1;
   for (auto &G : ctx->groups) {
     if (G.ids.empty()) continue;
+    for (int s : G.ids) ctx->sorted_lists[s] = 0;
     if (G.small)
       HIPCHK(hdk::launch_small(small_kind(ctx), G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
                                G.nmax, G.maxnb, G.cellmax, G.block, nsteps, mode, stream));
@@ -393,6 +409,7 @@ hd_status evaluate_all(hd_ctx *ctx) {
   if (st != HD_OK) return st;
   for (auto &P : ctx->plans) {
     int l = 0;
+    for (int s : P.ids) ctx->sorted_lists[s] = 1;
     HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, true, ctx->stream, &l));
     HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, ctx->stream));
   }
@@ -407,6 +424,7 @@ hd_status run_plans(hd_ctx *ctx, int64_t n_steps, hipStream_t stream, int64_t *l
   hd_status st;
   for (auto &P : ctx->plans) {
     int64_t left = n_steps;
+    for (int s : P.ids) ctx->sorted_lists[s] = 1;
     if (left >= kGraphSteps && !P.exec && (st = capture_plan(ctx, P, kGraphSteps)) != HD_OK) return st;
     while (left >= kGraphSteps && P.exec) {
       HIPCHK(hipGraphLaunch(P.exec, stream));
@@ -809,12 +827,14 @@ hd_status hd_finalize(hd_ctx *ctx) {
   ALLOC(A.x, 3 * N); ALLOC(A.v, 3 * N); ALLOC(A.rO, 3 * N); ALLOC(A.xb, 3 * N); ALLOC(A.cofs, 3 * N);
   ALLOC(A.ftot, 3 * N); ALLOC(A.flj, 3 * N); ALLOC(A.hu, 3 * N); ALLOC(A.fb, 3 * N);
   ALLOC(A.eatom, N);
+  ALLOC(A.rec, (size_t)N * hdk::kRecDoubles);
+  ALLOC(A.pos, N);
   if (ctx->prec == HD_FP64) { double *u; ALLOC(u, 3 * N); A.u = u; }
   else { float *u; ALLOC(u, 3 * N); A.u = u; }
   ALLOC(A.tr, N); ALLOC(A.nbr, nbr_off); ALLOC(A.nnb, N);
   ALLOC(A.cell_count, cell_off); ALLOC(A.cell_start, cstart_off); ALLOC(A.cell_atoms, N); ALLOC(A.cidx, N);
   ALLOC(A.sys_of, N);
-  ALLOC(A.tile_done, S); ALLOC(A.XR_next, 6 * S); ALLOC(A.rebuild_flag, S);
+  ALLOC(A.XR_next, 6 * S); ALLOC(A.rebuild_flag, S);
   ALLOC(ctx->d_desc, S); ALLOC(ctx->d_state, S); ALLOC(ctx->d_all, S);
   {
     char *g;
@@ -826,7 +846,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
   // host staging
   std::vector<double> x(3 * N, 0.0), rO(3 * N, 0.0), cofs(3 * N, 0.0), v(3 * N, 0.0);
   std::vector<uint8_t> tr(N);
-  std::vector<int32_t> sys_of(N), all(S);
+  std::vector<int32_t> sys_of(N), all(S), pos0(N);
   std::vector<SysState> states(S);
   for (int s = 0; s < S; ++s) {
     SysHost &h = ctx->sys[s];
@@ -841,6 +861,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
     for (int i = 0; i < h.n; ++i) {
       tr[D.off + i] = (uint8_t)(h.type[i] | (h.role[i] << 1));
       sys_of[D.off + i] = s;
+      pos0[D.off + i] = i;
     }
     all[s] = s;
     SysState &T = states[s];
@@ -863,6 +884,8 @@ hd_status hd_finalize(hd_ctx *ctx) {
   HIPCHK(hipMemcpyAsync(A.v, v.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(A.tr, tr.data(), N, hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(A.sys_of, sys_of.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(A.pos, pos0.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  ctx->sorted_lists.assign(S, 0);
   HIPCHK(hipMemcpyAsync(ctx->d_all, all.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc.data(), S * sizeof(SysDesc), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->d_state, states.data(), S * sizeof(SysState), hipMemcpyHostToDevice, ctx->stream));
@@ -1314,16 +1337,20 @@ hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int
   if (check_sys(ctx, sys) != HD_OK || !n_pairs || (cap > 0 && !ij)) return fail(ctx, HD_E_ARG, "bad arguments");
   const SysHost &s = ctx->sys[sys];
   const SysDesc &D = ctx->h_desc[sys];
-  std::vector<int32_t> nnb(s.n), list((size_t)D.maxnb * s.n);
+  std::vector<int32_t> nnb(s.n), list((size_t)D.maxnb * s.n), cat(s.n);
   HIPCHK(hipMemcpyAsync(nnb.data(), ctx->A.nnb + D.off, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipMemcpyAsync(list.data(), ctx->A.nbr + D.nbr_off, sizeof(int32_t) * list.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(cat.data(), ctx->A.cell_atoms + D.off, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  // grid lists are indexed by cell-sorted position (cat maps it to the atom)
+  const bool sorted = ctx->sorted_lists[sys] != 0;
   // full lists hold each pair under both atoms, half lists under one of them
   // (either one): collect (min, max) and drop duplicates
   std::vector<std::pair<int32_t, int32_t>> pr;
-  for (int i = 0; i < s.n; ++i)
-    for (int q = 0; q < nnb[i]; ++q) {
-      const int j = list[(size_t)q * s.n + i] >> 1;
+  for (int r = 0; r < s.n; ++r)
+    for (int q = 0; q < nnb[r]; ++q) {
+      const int e = list[(size_t)q * s.n + r] >> 1;
+      const int i = sorted ? cat[r] : r, j = sorted ? cat[e] : e;
       if (j == i) continue;
       pr.emplace_back(std::min(i, j), std::max(i, j));
     }

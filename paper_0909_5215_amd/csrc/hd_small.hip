@@ -129,7 +129,7 @@ __device__ int lds_rebuild(const SysDesc &D, const double *__restrict__ xs, uint
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
               const double d = minimg(xs[k * stride + j] - xi[k], D.box[k], D.hbox[k], D.periodic[k]);
-              r2 = __dadd_rn(r2, __dmul_rn(d, d));
+              r2 = add_sq_exact(r2, d);
             }
             if (r2 < D.rl2) {
               if (count < D.maxnb) nbr[count * stride + i] = (uint16_t)((j << 1) | (trj & 1));
