@@ -506,7 +506,7 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
   const int nn = A.nnb[off + p];
   LJRow<T> R;
   R.load(D, ti);
-#pragma unroll 2
+#pragma unroll 4
   for (int q = 0; q < nn; ++q) {
     // the list is read once per step: a streaming load, so that it does not
     // evict the records the neighbouring atoms share

@@ -194,30 +194,49 @@ __global__ __launch_bounds__(1024) void kg_cell_scatter(const SysDesc *__restric
   A.cell_atoms[D.off + A.cell_start[D.cstart_off + c] + slot] = i;
 }
 
-// One thread per cell: sort the cell's atoms by index, then clear its count.
+// Sort each cell's atoms by index (so that lists are built in a fixed order)
+// and clear its count.  One wavefront per cell: the cell's atoms are staged
+// in LDS and each lane places its own atoms at their rank (the number of
+// smaller indices in the cell).  Cells of more than kSortMax atoms, which
+// only clamping at an open boundary can produce, are sorted by insertion.
+constexpr int kSortMax = 256;
 __global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ descs, Arrays A,
                                                     const int32_t *__restrict__ sys_ids, int nsys) {
+  __shared__ int keys[4][kSortMax];
   const int s = sys_ids[blockIdx.y];
   if (!A.rebuild_flag[s]) return;
   const SysDesc &D = descs[s];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int32_t *cat = A.cell_atoms + D.off;
   const int32_t *cst = A.cell_start + D.cstart_off;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < D.ncell; c += gridDim.x * blockDim.x) {
-    const int b = cst[c], e = cst[c + 1];
-    for (int p = b + 1; p < e; ++p) {
-      const int key = cat[p];
-      int q = p - 1;
-      while (q >= b && cat[q] > key) { cat[q + 1] = cat[q]; --q; }
-      cat[q + 1] = key;
+  for (int c0 = blockIdx.x * 4; c0 < D.ncell; c0 += gridDim.x * 4) {
+    const int c = c0 + wave;
+    const bool have = c < D.ncell;
+    const int b = have ? cst[c] : 0, m = have ? cst[c + 1] - b : 0;
+    const bool staged = m > 1 && m <= kSortMax;
+    if (staged)
+      for (int k = lane; k < m; k += 64) keys[wave][k] = cat[b + k];
+    __syncthreads();
+    if (staged) {
+      for (int k = lane; k < m; k += 64) {
+        const int key = keys[wave][k];
+        int r = 0;
+        for (int j = 0; j < m; ++j) r += keys[wave][j] < key ? 1 : 0;
+        cat[b + r] = key;
+      }
+    } else if (m > kSortMax && lane == 0) {
+      for (int p = b + 1; p < b + m; ++p) {
+        const int key = cat[p];
+        int q = p - 1;
+        while (q >= b && cat[q] > key) { cat[q + 1] = cat[q]; --q; }
+        cat[q + 1] = key;
+      }
     }
-    __hip_atomic_store(&A.cell_count[D.cell_off + c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (have && lane == 0) __hip_atomic_store(&A.cell_count[D.cell_off + c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
   }
 }
 
-// List of the atom at sorted position p (atom i): candidates cell by cell in
-// stencil order, within a cell in index order (the cells are sorted); each
-// entry holds the neighbour's sorted position and type.  Positions from xs
-// (the current or the recorded build positions).
 template <int DIM>
 __device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__restrict__ xs, int p, int i) {
   const int64_t N = A.ntot, off = D.off, ai = off + i;
@@ -254,20 +273,34 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__re
         }
         if (skip) continue;
         const int q = (q3[2] * D.nc[1] + q3[1]) * D.nc[0] + q3[0];
-        for (int pp = cstart[q]; pp < cstart[q + 1]; ++pp) {
-          if (pp == p) continue;
-          const int64_t aj = off + catoms[pp];
-          const int trj = A.tr[aj], rj = trj >> 1;
-          if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
-          double xj[3], dx[3];
+        const int pb = cstart[q], pe = cstart[q + 1];
+        // candidates four at a time: all their loads are issued before any
+        // is tested, so memory latency overlaps across them
+        for (int p0 = pb; p0 < pe; p0 += 4) {
+          int trj[4];
+          double xj[4][3];
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) xj[k] = xs[k * N + aj];
-          // r^2 exactly as the float64 rule: minimum image, then the sum of
-          // squares axis by axis without contraction
-          const double r2 = pair_disp<DIM>(D, xi, xj, dx);
-          if (r2 < D.rl2) {
-            if (cnt < D.maxnb) list[(int64_t)cnt * n + p] = (pp << 1) | (trj & 1);
-            ++cnt;
+          for (int u = 0; u < 4; ++u) {
+            const int pp = p0 + u < pe ? p0 + u : p0;
+            const int64_t aj = off + catoms[pp];
+            trj[u] = A.tr[aj];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) xj[u][k] = xs[k * N + aj];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int pp = p0 + u;
+            if (pp >= pe || pp == p) continue;
+            const int rj = trj[u] >> 1;
+            if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
+            // r^2 exactly as the float64 rule: minimum image, then the sum of
+            // squares axis by axis without contraction
+            double dx[3];
+            const double r2 = pair_disp<DIM>(D, xi, xj[u], dx);
+            if (r2 < D.rl2) {
+              if (cnt < D.maxnb) list[(int64_t)cnt * n + p] = (pp << 1) | (trj[u] & 1);
+              ++cnt;
+            }
           }
         }
       }
@@ -277,7 +310,9 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__re
 __global__ __launch_bounds__(1024) void kg_build_list(const SysDesc *__restrict__ descs,
                                                       SysState *__restrict__ states, Arrays A,
                                                       const Tile *__restrict__ tiles, int ntiles) {
-  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  // consecutive tiles go to different XCDs: the few systems that rebuild in
+  // a step spread over the whole chip
+  const Tile t = tiles[blockIdx.x];
   const int flag = A.rebuild_flag[t.sys];
   if (!flag || threadIdx.x >= t.count) return;
   const SysDesc &D = descs[t.sys];
@@ -502,7 +537,7 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
   hipLaunchKernelGGL(kg_cell_count, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
   hipLaunchKernelGGL(kg_cell_scan, dim3(P.nsys), dim3(256), 0, stream, descs, A, P.sys_ids);
   hipLaunchKernelGGL(kg_cell_scatter, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
-  const int sort_blocks = (P.max_ncell + 255) / 256 < 1024 ? (P.max_ncell + 255) / 256 : 1024;
+  const int sort_blocks = (P.max_ncell + 3) / 4 < 1024 ? (P.max_ncell + 3) / 4 : 1024;
   hipLaunchKernelGGL(kg_cell_sort, dim3(sort_blocks > 0 ? sort_blocks : 1, P.nsys), dim3(256), 0, stream,
                      descs, A, P.sys_ids, P.nsys);
   hipLaunchKernelGGL(kg_build_list, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt);
