@@ -333,7 +333,7 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
       for (int k = 0; k < DIM; ++k) {
         double f = A.flj[k * N + a], h = A.hu[k * N + a], fb = 0.0;
         if (role != ROLE_FIXED) {
-          if (role == ROLE_RIGID) { f += S.Fd[k] / (double)D.n_rigid; h += S.hud[k]; }
+          if (role == ROLE_RIGID) { f += S.Fd[k] * D.inv_nR; h += S.hud[k]; }
           if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0) {
             const double uk = minimg(A.x[k * N + a] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
             fb = S.bias_a * (h - f - S.bias_b * uk);

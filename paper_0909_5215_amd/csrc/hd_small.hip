@@ -464,7 +464,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          B.Fd_n[k] = S.Fd[k] / (double)(D.n_rigid > 0 ? D.n_rigid : 1);
+          B.Fd_n[k] = S.Fd[k] * D.inv_nR;
           B.hud[k] = S.hud[k];
           B.FR[k] = sums[3 + k] + S.Fd[k] + S.sumFb[k];
         }
