@@ -71,6 +71,31 @@ def test_neighbour_pairs_bit_exact(hd, oracle_mod, maker, exec_mode):
     assert sg == sr
 
 
+def _build_positions(blob, dim, n):
+    """Recorded build positions from a checkpoint: header, then x, v, r_O,
+    x_build, F (each dim x n float64)."""
+    nd = dim * n
+    body = np.frombuffer(blob[len(blob) - 5 * nd * 8:], dtype=np.float64)
+    return body[3 * nd:4 * nd].reshape(dim, n).copy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("path", ["lds", "grid", "grid3d"])
+def test_lists_after_rebuilds_bit_exact(hd, oracle_mod, path, precision):
+    """After many steps (several list rebuilds, the grid's in cell-sorted
+    order), the current lists are exactly the oracle's pair set at the
+    recorded build positions."""
+    spec = snapshot_3d(seed=91, nx=10, nz=4, R=4.0) if path == "grid3d" else snapshot_2d(seed=90)
+    exec_mode = hd.HD_EXEC_BATCHED if path == "lds" else hd.HD_EXEC_GRID
+    ctx = hd.make_context([spec], precision=precision, exec_mode=exec_mode)
+    ctx.step(300)
+    assert ctx.scalars(0)["n_rebuilds"] >= 3
+    xb = _build_positions(ctx.get_state(0), spec.dim, spec.n)
+    got = set(map(tuple, ctx.debug_pairs(0).tolist()))
+    ref = set(map(tuple, oracle_mod.pairs_brute(spec, xb, spec.rc + spec.skin, exclude=True).tolist()))
+    assert got == ref
+
+
 def _compare_eval(hd, oracle_mod, spec, precision, exec_mode=0, ftol=None):
     ref = oracle_mod.OracleSystem(spec).compute()
     ctx = hd.make_context([spec], precision=precision, exec_mode=exec_mode, init_velocities=False)
