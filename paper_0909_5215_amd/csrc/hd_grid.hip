@@ -307,37 +307,153 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__re
   return cnt;
 }
 
-__global__ __launch_bounds__(1024) void kg_build_list(const SysDesc *__restrict__ descs,
-                                                      SysState *__restrict__ states, Arrays A,
-                                                      const Tile *__restrict__ tiles, int ntiles) {
-  // consecutive tiles go to different XCDs: the few systems that rebuild in
-  // a step spread over the whole chip
-  const Tile t = tiles[blockIdx.x];
-  const int flag = A.rebuild_flag[t.sys];
-  if (!flag || threadIdx.x >= t.count) return;
-  const SysDesc &D = descs[t.sys];
-  // one thread per sorted position: the atoms of a wavefront share cells
-  const int p = t.first + threadIdx.x;
+// List build with one lane per stencil row: the 3^(DIM-1) rows (dy, dz) of
+// an atom's cell stencil are scanned by separate lanes into LDS sub-lists,
+// which are then concatenated in row order.  The result is the list
+// list_atom_g builds (same entries, same order) with 3 or 9 times the
+// parallelism, which a system whose skin expired needs to hide memory
+// latency.  A row with more than kRowCap entries sends its atom to
+// list_atom_g.  Blocks of kBuildThreads threads, kBuildParts blocks per tile.
+constexpr int kBuildThreads = 256;
+constexpr int kRowCap = 48;
+
+template <int DIM>
+__device__ int scan_row(const SysDesc &D, const Arrays &A, const double *__restrict__ xs, int p,
+                        const double xi[3], int ri, const int cc[3], int oy, int oz, int32_t *sub) {
+  const int64_t N = A.ntot, off = D.off;
+  const int32_t *cstart = A.cell_start + D.cstart_off;
+  const int32_t *catoms = A.cell_atoms + off;
+  int lo0 = 0, hi0 = 0;
+  if (D.nc[0] > 1) { lo0 = -1; hi0 = 1; }
+  int cnt = 0;
+  for (int ox = lo0; ox <= hi0; ++ox) {
+    int q3[3] = {cc[0] + ox, cc[1] + oy, cc[2] + oz};
+    bool skip = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (q3[k] < 0 || q3[k] >= D.nc[k]) {
+        if (k < DIM && D.periodic[k]) q3[k] = (q3[k] + D.nc[k]) % D.nc[k];
+        else skip = true;
+      }
+    }
+    if (skip) continue;
+    const int q = (q3[2] * D.nc[1] + q3[1]) * D.nc[0] + q3[0];
+    const int pb = cstart[q], pe = cstart[q + 1];
+    for (int p0 = pb; p0 < pe; p0 += 4) {
+      int trj[4];
+      double xj[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int pp = p0 + u < pe ? p0 + u : p0;
+        const int64_t aj = off + catoms[pp];
+        trj[u] = A.tr[aj];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xj[u][k] = xs[k * N + aj];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int pp = p0 + u;
+        if (pp >= pe || pp == p) continue;
+        const int rj = trj[u] >> 1;
+        if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
+        double dx[3];
+        const double r2 = pair_disp<DIM>(D, xi, xj[u], dx);
+        if (r2 < D.rl2) {
+          if (cnt < kRowCap) sub[cnt * kBuildThreads] = (pp << 1) | (trj[u] & 1);
+          ++cnt;
+        }
+      }
+    }
+  }
+  return cnt;
+}
+
+template <int DIM>
+__device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, const Tile &t, int part, int flag,
+                           int32_t *sub_all, int *counts) {
+  constexpr int S = DIM == 3 ? 9 : 3;        // stencil rows per atom
+  constexpr int APB = kBuildThreads / S;     // atoms per block
+  const int tid = threadIdx.x, la = tid / S, r = tid % S;
+  const int lp = part * APB + la;            // atom within the tile
+  const bool active = la < APB && lp < t.count;
   const int64_t off = D.off, N = A.ntot;
-  const int i = A.cell_atoms[off + p];
-  const int64_t a = off + i;
+  const int p = t.first + lp;
   const double *xs = flag == 2 ? A.xb : A.x;
-  const int c = D.dim == 2 ? list_atom_g<2>(D, A, xs, p, i) : list_atom_g<3>(D, A, xs, p, i);
-  A.nnb[off + p] = c < D.maxnb ? c : D.maxnb;
-  if (c > D.maxnb) atomicOr(&states[t.sys].flags, FLAG_NBR_OVERFLOW);
+  int i = 0, ri = 0;
+  double xi[3] = {0, 0, 0};
+  int cc[3] = {0, 0, 0};
+  int cnt = 0;
+  if (active) {
+    i = A.cell_atoms[off + p];
+    const int64_t ai = off + i;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) xi[k] = xs[k * N + ai];
+    ri = A.tr[ai] >> 1;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const int ck = (int)floor((xi[k] - D.lo[k]) * D.inv_h[k]);
+      cc[k] = ck < 0 ? 0 : (ck >= D.nc[k] ? D.nc[k] - 1 : ck);
+    }
+    const int oy = DIM == 3 ? r % 3 - 1 : r - 1, oz = DIM == 3 ? r / 3 - 1 : 0;
+    const bool in_y = D.nc[1] > 1 || oy == 0, in_z = DIM < 3 || D.nc[2] > 1 || oz == 0;
+    if (in_y && in_z) cnt = scan_row<DIM>(D, A, xs, p, xi, ri, cc, oy, oz, sub_all + tid);
+  }
+  counts[tid] = cnt;
+  __syncthreads();
+  if (!active) return;
+  int before = 0, total = 0;
+  bool over = false;
+  for (int q = 0; q < S; ++q) {
+    const int c = counts[la * S + q];
+    if (q < r) before += c;
+    total += c;
+    over = over || c > kRowCap;
+  }
+  int32_t *list = A.nbr + D.nbr_off;
+  const int n = D.n;
+  if (!over) {
+    for (int k = 0; k < cnt && before + k < D.maxnb; ++k)
+      list[(int64_t)(before + k) * n + p] = sub_all[k * kBuildThreads + tid];
+  }
+  if (r != 0) return;
+  if (over) total = list_atom_g<DIM>(D, A, xs, p, i);   // a crowded row: the one-lane build
+  const int64_t a = off + i;
+  A.nnb[off + p] = total < D.maxnb ? total : D.maxnb;
+  if (total > D.maxnb) atomicOr(&st.flags, FLAG_NBR_OVERFLOW);
   // the atom's record moves to its new sorted position (current x and u)
   A.pos[a] = p;
   double *rec = A.rec + (off + p) * kRecDoubles;
   const int tr = A.tr[a];
-  for (int k = 0; k < D.dim; ++k) {
+  for (int k = 0; k < DIM; ++k) {
     const double xk = A.x[k * N + a];
     rec[k] = xk;
     rec[3 + k] = (tr >> 1) == ROLE_FIXED ? 0.0 : minimg(xk - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
   }
   rec[7] = (double)tr;
   if (flag != 2)
-    for (int k = 0; k < D.dim; ++k) A.xb[k * N + a] = A.x[k * N + a];
-  if (p == 0 && flag != 2) atomicAdd(&states[t.sys].n_rebuilds, 1);
+    for (int k = 0; k < DIM; ++k) A.xb[k * N + a] = A.x[k * N + a];
+  if (p == 0 && flag != 2) atomicAdd(&st.n_rebuilds, 1);
+}
+
+// blockIdx.x = part * ntiles + tile: consecutive blocks go to different XCDs,
+// so the few systems that rebuild in a step spread over the whole chip.
+__global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__restrict__ descs,
+                                                               SysState *__restrict__ states, Arrays A,
+                                                               const Tile *__restrict__ tiles, int ntiles) {
+  __shared__ int32_t sub[kRowCap * kBuildThreads];
+  __shared__ int counts[kBuildThreads];
+  const int tile = blockIdx.x % ntiles, part = blockIdx.x / ntiles;
+  const Tile t = tiles[tile];
+  const int flag = A.rebuild_flag[t.sys];
+  if (!flag) return;
+  const SysDesc &D = descs[t.sys];
+  if (D.dim == 2) {
+    if (part * (kBuildThreads / 3) >= t.count) return;
+    build_rows<2>(D, states[t.sys], A, t, part, flag, sub, counts);
+  } else {
+    if (part * (kBuildThreads / 9) >= t.count) return;
+    build_rows<3>(D, states[t.sys], A, t, part, flag, sub, counts);
+  }
 }
 
 // ---- pair pass with per-tile sums and last-tile reduction ------------------
@@ -540,7 +656,10 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
   const int sort_blocks = (P.max_ncell + 3) / 4 < 1024 ? (P.max_ncell + 3) / 4 : 1024;
   hipLaunchKernelGGL(kg_cell_sort, dim3(sort_blocks > 0 ? sort_blocks : 1, P.nsys), dim3(256), 0, stream,
                      descs, A, P.sys_ids, P.nsys);
-  hipLaunchKernelGGL(kg_build_list, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt);
+  // enough blocks per tile for 3D systems (kBuildThreads / 9 atoms each)
+  const int parts = (B + kBuildThreads / 9 - 1) / (kBuildThreads / 9);
+  hipLaunchKernelGGL(kg_build_list, dim3(nt * parts), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles,
+                     nt);
   if (prec == 0)
     hipLaunchKernelGGL(kg_pairs<double>, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
   else
