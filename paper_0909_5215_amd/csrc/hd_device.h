@@ -563,6 +563,46 @@ __device__ __forceinline__ double dpp_mov_f64(double v) {
 // Sum over the 64 lanes of a wavefront with DPP (quad permutes, row shifts,
 // row broadcasts), fixed order; every lane receives the total (read from lane
 // 63).
+// Wavefront totals of NP values at once (NP a power of two, at most 64):
+// a reduce-scatter butterfly.  At stage s each lane keeps one half of its
+// current values (lower or upper half by lane bit s) and adds the partner's
+// (lane ^ 2^s) copy of that half, so the work shrinks by half per stage
+// instead of staying NP; after log2(NP) stages the remaining stages add one
+// value.  On return every lane holds the total
+// of value index wave_scatter_index<NP>(lane).  Fixed order: deterministic.
+template <int NP>
+__device__ __forceinline__ double wave_sums_scatter(double (&v)[NP], int lane) {
+  static_assert((NP & (NP - 1)) == 0 && NP <= 64, "NP must be a power of two");
+  constexpr int LOG = NP >= 64 ? 6 : NP >= 32 ? 5 : NP >= 16 ? 4 : NP >= 8 ? 3 : NP >= 4 ? 2 : NP >= 2 ? 1 : 0;
+#pragma unroll
+  for (int s = 0; s < LOG; ++s) {
+    const int half = NP >> (s + 1);
+    const bool upper = (lane >> s) & 1;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      // the partner's share of the half this lane keeps arrives in
+      // (lower lanes keep j, upper lanes keep j + half)
+      const double from_lo = __shfl_xor(v[j], 1 << s, 64);
+      const double from_hi = __shfl_xor(v[j + half], 1 << s, 64);
+      const double sum_lo = v[j] + from_lo, sum_hi = v[j + half] + from_hi;
+      v[j] = upper ? sum_hi : sum_lo;
+    }
+  }
+  double t = v[0];
+#pragma unroll
+  for (int s = LOG; s < 6; ++s) t += __shfl_xor(t, 1 << s, 64);
+  return t;
+}
+
+// The value index whose total lane holds after wave_sums_scatter<NP>.
+template <int NP>
+__device__ __forceinline__ int wave_scatter_index(int lane) {
+  int q = 0;
+#pragma unroll
+  for (int s = 0; (NP >> (s + 1)) >= 1; ++s) q += ((lane >> s) & 1) * (NP >> (s + 1));
+  return q;
+}
+
 // Value of v in lane l, returned to every lane (uniform).
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const unsigned long long b = __double_as_longlong(v);

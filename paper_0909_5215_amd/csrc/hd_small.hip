@@ -153,9 +153,10 @@ struct Bcast {
   int bias_live, bad;
 };
 
-template <int DIM, typename T, bool HALF>
+template <int DIM, typename T, bool HALF, int BLOCK>
 __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Arrays &A,
                           int64_t nsteps, int mode, char *lds, const SmallLayout L) {
+  constexpr int NW = BLOCK / 64;       // wavefronts per workgroup
   static_assert(!HALF || sizeof(T) == 4, "half lists are a float32 variant");
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = D.n, stride = L.nmax;
@@ -419,17 +420,20 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       }
     }
     double *rb = red[step & 1];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) vals[q] = wave_sum_f64(vals[q]);
-    // rigid-layer sums only in the wavefronts that hold rigid atoms (the
-    // others contribute exact zeros)
     if (wave_rigid) {
+      // all NV sums, padded to 16 values
+      double w16[16];
 #pragma unroll
-      for (int q = 4; q < NV; ++q) vals[q] = wave_sum_f64(vals[q]);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < NV; ++q) rb[q * 16 + wave] = vals[q];
+      for (int q = 0; q < 16; ++q) w16[q] = q < NV ? vals[q] : 0.0;
+      const double tot = wave_sums_scatter<16>(w16, lane);
+      const int q = wave_scatter_index<16>(lane);
+      if (lane < 16 && q < NV) rb[q * 16 + wave] = tot;
+    } else {
+      // the rigid-layer sums are exact zeros in wavefronts without rigid atoms
+      double w4[4] = {vals[0], vals[1], vals[2], vals[3]};
+      const double tot = wave_sums_scatter<4>(w4, lane);
+      if (lane < 4) rb[wave_scatter_index<4>(lane) * 16 + wave] = tot;
+      else if (lane < NV) rb[lane * 16 + wave] = 0.0;
     }
     __syncthreads();   // barrier C
     // while wave 0 evaluates the scalars, the other wavefronts draw their
@@ -442,11 +446,16 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     Bcast &B = bc[step & 1];
     Scal S;
     if (wave == 0) {
-      // lane q adds sum q over the waves in wave order
-      const int nw = (blockDim.x + 63) >> 6;
+      // lane q adds sum q over the waves in wave order (all loads in flight
+      // at once)
       double t = 0.0;
-      if (lane < NV)
-        for (int w = 0; w < nw; ++w) t += rb[lane * 16 + w];
+      if (lane < NV) {
+        double pw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) pw[w] = rb[lane * 16 + w];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += pw[w];
+      }
       double sums[NRED];
 #pragma unroll
       for (int q = 0; q < NRED; ++q) sums[q] = 0.0;
@@ -566,7 +575,7 @@ __global__ __launch_bounds__(BLOCK) void k_small(const SysDesc *__restrict__ des
                                                  SmallLayout L) {
   extern __shared__ __align__(16) char lds[];
   const int s = sys_list[blockIdx.x];
-  run_small<DIM, T, HALF>(descs[s], states + s, A, nsteps, MODE, lds, L);
+  run_small<DIM, T, HALF, BLOCK>(descs[s], states + s, A, nsteps, MODE, lds, L);
 }
 
 template <typename T, int DIM, int MODE, int BLOCK, bool HALF>

@@ -135,3 +135,18 @@ def test_unstable_system_is_frozen_others_continue(hd):
     assert ctx.scalars(0)["step"] == 50
     assert ctx.scalars(1)["flags"] & hd.HD_FLAG_UNSTABLE
     assert ctx.scalars(1)["step"] < 50
+
+
+def test_crowded_stencil_rows_fall_back_to_one_lane_build(hd, oracle_mod):
+    """A slab compressed twofold along z puts more neighbours in one stencil
+    row than the row-parallel build holds; those atoms take the one-lane
+    build, and the lists still equal the brute-force set."""
+    from hd_inputs import build_3d
+    s = build_3d(10, 10, 4, 4.0)
+    z0 = s.pos[2].min()
+    s.pos[2] = z0 + 0.5 * (s.pos[2] - z0)
+    ctx = hd.make_context([s], precision=hd.HD_FP64, init_velocities=False, max_neighbors=512)
+    got = set(map(tuple, ctx.debug_pairs(0).tolist()))
+    ref = set(map(tuple, oracle_mod.pairs_brute(s, s.pos, s.rc + s.skin, exclude=True).tolist()))
+    assert max(np.bincount(np.array(sorted(ref)).ravel())) > 48
+    assert got == ref
