@@ -498,7 +498,7 @@ __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int
 template <int DIM, typename T>
 __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
                                               const double xi[3], const T ui[3], int ti,
-                                              PairAcc<T> &acc) {
+                                              PairAcc<T> &acc, int q0 = 0, int qstep = 1) {
   const int64_t off = D.off;
   const int n = D.n;
   const double *__restrict__ rec = A.rec + off * kRecDoubles;
@@ -507,7 +507,7 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
   LJRow<T> R;
   R.load(D, ti);
 #pragma unroll 4
-  for (int q = 0; q < nn; ++q) {
+  for (int q = q0; q < nn; q += qstep) {
     // the list is read once per step: a streaming load, so that it does not
     // evict the records the neighbouring atoms share
     const int ent = __builtin_nontemporal_load(nbr + (int64_t)q * n + p);

@@ -457,39 +457,54 @@ __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__
 }
 
 // ---- pair pass with per-tile sums and last-tile reduction ------------------
-template <int DIM, typename T>
+// LPA adjacent lanes per atom: lane s of an atom takes list entries s,
+// s + LPA, ...; the lanes' sums are then combined by shuffles (a + b on both
+// lanes, the same bits).  More wavefronts per tile hide more gather latency.
+template <int DIM, typename T, int LPA>
 __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int tile_index) {
   __shared__ double red[NRED * 16];
   const int64_t N = A.ntot;
   double sums[NRED];
 #pragma unroll
   for (int q = 0; q < NRED; ++q) sums[q] = 0.0;
-  if (threadIdx.x < t.count) {
-    // one thread per sorted position; results go to the atom's own index
-    const int p = t.first + threadIdx.x;
+  const int la = threadIdx.x / LPA, sub = threadIdx.x % LPA;
+  const bool valid = la < t.count;
+  // one atom per sorted position; results go to the atom's own index
+  const int p = t.first + (valid ? la : 0);
+  const double *r = A.rec + (D.off + p) * kRecDoubles;
+  const int tr = (int)r[7], role = tr >> 1;
+  double xi[3] = {0, 0, 0}, u64[3] = {0, 0, 0};
+  T ui[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    xi[k] = r[k];
+    u64[k] = r[3 + k];
+    ui[k] = (T)u64[k];
+  }
+  PairAcc<T> acc;
+  acc.init();
+  if (valid) pair_atom_rec<DIM, T>(D, A, p, xi, ui, tr & 1, acc, sub, LPA);
+  double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, e;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    if constexpr (sizeof(T) == 8) { F[k] = acc.F[k]; H[k] = acc.H[k]; }
+    else { F[k] = acc.F[k].get(); H[k] = acc.H[k].get(); }
+  }
+  if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
+  // every lane takes part in the shuffles (no divergence around them)
+#pragma unroll
+  for (int d = 1; d < LPA; d <<= 1) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { F[k] += __shfl_xor(F[k], d, 64); H[k] += __shfl_xor(H[k], d, 64); }
+    e += __shfl_xor(e, d, 64);
+  }
+  if (valid && sub == 0) {
     const int64_t a = D.off + A.cell_atoms[D.off + p];
-    const double *r = A.rec + (D.off + p) * kRecDoubles;
-    const int tr = (int)r[7], role = tr >> 1;
-    double xi[3] = {0, 0, 0}, u64[3] = {0, 0, 0};
-    T ui[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      xi[k] = r[k];
-      u64[k] = r[3 + k];
-      ui[k] = (T)u64[k];
-    }
-    PairAcc<T> acc;
-    acc.init();
-    pair_atom_rec<DIM, T>(D, A, p, xi, ui, tr & 1, acc);
-    double F[3], H[3], e;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      if constexpr (sizeof(T) == 8) { F[k] = acc.F[k]; H[k] = acc.H[k]; }
-      else { F[k] = acc.F[k].get(); H[k] = acc.H[k].get(); }
       A.flj[k * N + a] = F[k];
       A.hu[k * N + a] = H[k];
     }
-    if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
     A.eatom[a] = e;
     sums[0] = e;
     double f2 = 0.0;
@@ -570,14 +585,14 @@ __global__ __launch_bounds__(256) void kg_reduce(const SysDesc *__restrict__ des
   else reduce_system<3>(D, states[s], A, s, first, nts, gs, compute_only != 0);
 }
 
-template <typename T>
+template <typename T, int LPA>
 __global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ descs, Arrays A,
                                                  const Tile *__restrict__ tiles, int ntiles) {
   const int ti = xcd_tile(blockIdx.x, ntiles);
   const Tile t = tiles[ti];
   const SysDesc &D = descs[t.sys];
-  if (D.dim == 2) pairs_tile<2, T>(D, A, t, ti);
-  else pairs_tile<3, T>(D, A, t, ti);
+  if (D.dim == 2) pairs_tile<2, T, LPA>(D, A, t, ti);
+  else pairs_tile<3, T, LPA>(D, A, t, ti);
 }
 
 // ---- bias force, total force and final B -----------------------------------
@@ -660,10 +675,23 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
   const int parts = (B + kBuildThreads / 9 - 1) / (kBuildThreads / 9);
   hipLaunchKernelGGL(kg_build_list, dim3(nt * parts), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles,
                      nt);
-  if (prec == 0)
-    hipLaunchKernelGGL(kg_pairs<double>, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
-  else
-    hipLaunchKernelGGL(kg_pairs<float>, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
+  // four or two lanes per atom where the workgroup allows it
+  if (B <= 256) {
+    if (prec == 0)
+      hipLaunchKernelGGL((kg_pairs<double, 4>), dim3(nt), dim3(4 * B), 0, stream, descs, A, P.tiles, nt);
+    else
+      hipLaunchKernelGGL((kg_pairs<float, 4>), dim3(nt), dim3(4 * B), 0, stream, descs, A, P.tiles, nt);
+  } else if (B <= 512) {
+    if (prec == 0)
+      hipLaunchKernelGGL((kg_pairs<double, 2>), dim3(nt), dim3(2 * B), 0, stream, descs, A, P.tiles, nt);
+    else
+      hipLaunchKernelGGL((kg_pairs<float, 2>), dim3(nt), dim3(2 * B), 0, stream, descs, A, P.tiles, nt);
+  } else {
+    if (prec == 0)
+      hipLaunchKernelGGL((kg_pairs<double, 1>), dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
+    else
+      hipLaunchKernelGGL((kg_pairs<float, 1>), dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
+  }
   hipLaunchKernelGGL(kg_reduce, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids, P.sys_tile0,
                      P.tiles, gs, co);
   hipLaunchKernelGGL(kg_kick, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, co);
