@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "biased LJ atom-steps/s: batched FP32 vs plain FP64, force rel err ≤1e-5"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFS = 157.3
 CSRC = os.path.join(ROOT, "paper_0909_5215_amd", "csrc")
 
 # HBM bytes per launch of the stepping kernel, from two rocprofv3 --pmc runs
@@ -122,6 +123,35 @@ def prepare(hd, specs, quench_steps, prerun_steps, block):
         states.append(ctx.get_state(k))
     ctx.close()
     return specs, states
+
+
+def interacting_pairs(specs, positions, max_systems=4):
+    """Interacting unordered pairs per atom (r < rc, neither fixed-fixed nor
+    rigid-rigid) and algorithmic float32 pair flops per atom-step, counted
+    with a k-d tree on up to max_systems systems spread over the batch."""
+    from scipy.spatial import cKDTree
+    idx = sorted({int(round(k * (len(specs) - 1) / max(max_systems - 1, 1))) for k in range(max_systems)})
+    pairs = flops = atoms = 0
+    for k in idx:
+        s, x = specs[k], np.asarray(positions[k])
+        pts = x.T.copy()
+        box = []
+        for d in range(s.dim):
+            if s.periodic[d]:
+                pts[:, d] = np.mod(pts[:, d], s.box[d])
+                box.append(s.box[d])
+            else:
+                lo = pts[:, d].min()
+                pts[:, d] -= lo
+                box.append(2.0 * (pts[:, d].max() + 2.0 * s.rc) + 1.0)   # open axis: no image within reach
+        ij = cKDTree(pts, boxsize=np.array(box)).query_pairs(s.rc * (1.0 - 1e-12), output_type="ndarray")
+        ri, rj = s.role[ij[:, 0]], s.role[ij[:, 1]]
+        keep = ~(((ri == 1) & (rj == 1)) | ((ri == 2) & (rj == 2)))
+        npair = int(keep.sum())
+        pairs += npair
+        flops += npair * (44 if s.dim == 2 else 57)
+        atoms += s.n
+    return pairs / atoms, flops / atoms
 
 
 def src_hash(files):
@@ -259,10 +289,11 @@ def main():
     # runs on, averaged over its launches in the timed region): the
     # algorithmic bytes are the per-atom state read and written once per step
     # (x and v read+written, r_O read, float64): 5*D*8 bytes per atom-step
-    bytes_per_atom_step = 5 * dim * 8
+    alg_bytes_per_step = sum(5 * s.dim * 8 * s.n for s in specs)
+    bytes_per_atom_step = alg_bytes_per_step / n_atoms
     steps_per_launch = args.steps / max(launches, 1)
     avg_launch_s = (ev_ms / 1e3) / max(launches, 1)
-    achieved = bytes_per_atom_step * n_atoms * steps_per_launch / avg_launch_s / 1e9
+    achieved = alg_bytes_per_step * steps_per_launch / avg_launch_s / 1e9
     kname = stepping_kernel(specs, sched)
     traffic, traffic_bytes = None, None
     rec = HBM_COUNTERS.get((args.config, kname))
@@ -272,8 +303,16 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
             "kernel": kname, "avg_launch_ms": round(ev_ms / max(launches, 1), 4),
-            "steps_per_launch": steps_per_launch, "bytes_per_atom_step": bytes_per_atom_step,
+            "steps_per_launch": steps_per_launch, "bytes_per_atom_step": round(bytes_per_atom_step, 3),
             "traffic_bytes_per_launch": traffic_bytes}
+
+    # the arithmetic side: algorithmic float32 flops of the pair pass (44 per
+    # interacting unordered pair in 2D, 57 in 3D), pairs counted on the host
+    # at the end of the timed run, against the float32 vector peak
+    ppa, fpa = interacting_pairs(specs, [x for x, _ in states_x])
+    valu = {"bound": "alu", "achieved": round(fpa * value / 1e12, 4), "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(fpa * value / 1e12 / FP32_PEAK_TFS, 6), "pairs_per_atom": round(ppa, 3),
+            "flops_per_atom_step": round(fpa, 2)}
 
     # ---- plain float64 single-system path -----------------------------------
     plain = None
@@ -287,6 +326,21 @@ def main():
                  "kind": "plain FP64, one system at a time, per-step kernels replayed from HIP graphs"}
         log(f"plain fp64: {pval:.4g} atom-steps/s")
         pctx.close()
+
+    # ---- the same batched path in float64 ------------------------------------
+    fp64b = None
+    if not args.no_plain:
+        bctx = make_run_ctx(hd, specs, states, hd.HD_FP64, hd.HD_EXEC_BATCHED, args.block)
+        if not args.no_autotune:
+            bctx.autotune(min_ms=20.0, max_steps=8192)
+        bsteps = max(1000, args.steps // 10)
+        bctx.step(min(args.warmup, bsteps))
+        bwall, _, _ = time_steps(torch, bctx, bsteps)
+        fp64b = {"value": n_atoms * bsteps / bwall, "unit": "atom-steps/s", "steps": bsteps,
+                 "ms_per_step": bwall * 1e3 / bsteps, "schedule": {k: v for k, v in bctx.schedule().items()
+                                                                   if k != "ms_per_step"}}
+        log(f"batched fp64: {fp64b['value']:.4g} atom-steps/s")
+        bctx.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -309,10 +363,12 @@ def main():
         "config": {"workload": f"{args.config}: {desc}", "systems": len(specs), "atoms": n_atoms,
                    "dim": dim, "parallelism": "batch of independent slider positions, 1 GPU"},
         "roofline": roof,
+        "roofline_valu": valu,
         "schedule": {k: sched[k] for k in ("lds_resident", "small_block", "persistent_large", "large_block")},
         "autotune_trials": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in t.items()} for t in trials],
         "cpu_baseline": cpu,
         "fp64_plain": plain,
+        "fp64_batched": fp64b,
         "speedup_vs_fp64_plain": (value / plain["value"]) if plain else None,
         "unstable_systems": int(sum(1 for f in flags if f & 1)),
         "list_rebuilds_per_1000_steps": rebuild_rate,
