@@ -1,5 +1,5 @@
-// Device-side layout and arithmetic shared by the batched (one workgroup per
-// system) kernel and the grid kernels.  gfx950 only.
+// Device-side layout and arithmetic shared by the LDS-resident, the
+// one-workgroup and the grid kernels.  gfx950 only.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

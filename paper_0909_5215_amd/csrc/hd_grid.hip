@@ -1,9 +1,10 @@
-// Grid scheduler: a step is a short sequence of kernels over tiles of atoms,
-// each tile a contiguous atom range of one system.  Used for the plain
-// single-system path (one system per graph) and for systems too large for one
-// workgroup.  Kernel boundaries are the per-system barriers; per-system sums
-// are reduced by the last tile of each system to finish (release/acquire
-// fences around a per-system counter), in a fixed tile order.
+// Grid scheduler: a step is a short sequence of kernels over tiles, each tile
+// a contiguous range of one system's atoms (atom order for drift and kick,
+// cell-sorted order for the list build and the pair pass).  Used for the
+// plain single-system path (one system per graph) and for systems too large
+// for one workgroup.  Kernel boundaries are the per-system barriers; the pair
+// pass leaves per-tile partial sums that a separate launch reduces per system
+// in a fixed tile order.
 #include "hd_device.h"
 #include "hd_launch.h"
 
@@ -313,7 +314,8 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__re
 // list_atom_g builds (same entries, same order) with 3 or 9 times the
 // parallelism, which a system whose skin expired needs to hide memory
 // latency.  A row with more than kRowCap entries sends its atom to
-// list_atom_g.  Blocks of kBuildThreads threads, kBuildParts blocks per tile.
+// list_atom_g.  Blocks of kBuildThreads threads, enough of them per tile for
+// kBuildThreads / 9 atoms each.
 constexpr int kBuildThreads = 256;
 constexpr int kRowCap = 48;
 
@@ -456,7 +458,7 @@ __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__
   }
 }
 
-// ---- pair pass with per-tile sums and last-tile reduction ------------------
+// ---- pair pass with per-tile partial sums ---------------------------------
 // LPA adjacent lanes per atom: lane s of an atom takes list entries s,
 // s + LPA, ...; the lanes' sums are then combined by shuffles (a + b on both
 // lanes, the same bits).  More wavefronts per tile hide more gather latency.

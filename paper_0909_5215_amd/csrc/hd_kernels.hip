@@ -1,12 +1,13 @@
-// HIP kernels of the hyperdynamics-for-sliding hot path (gfx950).
+// One-workgroup global-memory kernel of the hyperdynamics-for-sliding hot
+// path (gfx950), and the Maxwell-Boltzmann velocity initialisation.
 //
-// Two schedulers share the per-atom arithmetic of hd_device.h:
-//   * k_batched: one workgroup owns one system for a whole chunk of steps
-//     (persistent); all synchronisation is workgroup barriers, so independent
-//     slider positions never wait on each other (the parallel slider-position
-//     scheme of Sec. 2.3 maps onto the batch dimension of the GPU);
-//   * the grid kernels (kg_*): a few launches per step over tiles of atoms,
-//     used for a single large system and for the plain single-system path.
+// k_batched: one workgroup owns one system for a whole chunk of steps
+// (persistent), state and lists in global memory; all synchronisation is
+// workgroup barriers, so independent slider positions never wait on each
+// other (the parallel slider-position scheme of Sec. 2.3 maps onto the batch
+// dimension of the GPU).  It is one of the launch shapes of the autotuner;
+// the LDS-resident kernel (hd_small.hip) and the grid kernels (hd_grid.hip)
+// share the per-atom arithmetic of hd_device.h with it.
 //
 // A step is Langevin BAOAB: B-A-O-A on the integrated degrees of freedom
 // (mobile atoms, the rigid top layer as one body), neighbour-list refresh when

@@ -1,13 +1,15 @@
 // LDS-resident batched kernel for systems that fit one workgroup: one thread
-// per atom, the atom's own state (x, v, total force, r_O, build position) in
-// registers, and the system's positions, displacements u = r - r_O, cell list
-// and neighbour list in LDS for the whole chunk of steps.  A step touches no
-// global memory: the neighbour gathers of the pair pass are LDS reads, and
-// the per-system reductions and barriers stay inside the workgroup.  State is
-// loaded at the start of a launch and written back at its end.
+// per atom, the atom's own x, v and total force in registers, and the
+// system's positions, displacements u = r - r_O, references r_O, build
+// positions, cell list and neighbour list in LDS for the whole chunk of
+// steps.  A step touches no global memory: the neighbour gathers of the pair
+// pass are LDS reads, and the per-system reductions and barriers stay inside
+// the workgroup.  State is loaded at the start of a launch and written back
+// at its end.
 //
-// The arithmetic is the same as the global-memory batched kernel (BAOAB,
-// LJ + H u pair terms, slope bias of eq. 13-14, boosted clock of eq. 3).
+// The method is the one of the grid and one-workgroup kernels (BAOAB, LJ +
+// H u pair terms, slope bias of eq. 13-14, boosted clock of eq. 3); the
+// per-system sums are taken in a different fixed order.
 #include "hd_device.h"
 #include "hd_launch.h"
 
@@ -216,6 +218,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 #pragma unroll
     for (int k = 0; k < DIM; ++k) sh_zR[step & 1][k] = z[k];
   }
+  __syncthreads();   // the first step's rigid-body noise and the atom table are in LDS
 
   const int64_t iters = compute_only ? 1 : nsteps;
   // the list lives in LDS only for this launch: rebuild at the start, from
