@@ -61,7 +61,9 @@ typedef enum {
 typedef enum {
     HD_FP64 = 0,   /* float64 pair arithmetic */
     HD_FP32C = 1   /* float32 pair arithmetic with compensated per-atom sums;
-                      displacements and the cutoff decision in float64 */
+                      displacements and the cutoff decision in float64; the
+                      Langevin normals formed in float32 from the same Philox
+                      words (relative error ~1e-7) */
 } hd_precision;
 
 /* How hd_step schedules the batch.  BATCHED runs small systems in one

@@ -1,6 +1,7 @@
-// Host runtime of libhd.so: contexts, batch layout in device memory, the two
-// schedulers (batched persistent launch; grid kernels captured in HIP graphs),
-// checkpoints and read-outs.  Every function exported here is declared in
+// Host runtime of libhd.so: contexts, batch layout in device memory, the
+// schedulers (persistent launches of the LDS-resident or one-workgroup
+// kernels replayed as graphs of 2000-step chunks; grid kernels captured in
+// graphs of 50 steps), the autotuner, checkpoints and read-outs.  Every function exported here is declared in
 // include/hd.h.  Host arithmetic is limited to laying out inputs (cell grids,
 // rigid-body offsets); every step of the method runs in the kernels.
 #include <hip/hip_runtime.h>
