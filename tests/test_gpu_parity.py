@@ -292,3 +292,58 @@ def test_large_systems_on_both_schedulers(hd, oracle_mod, precision):
                 dx[d] -= s.box[d] * np.round(dx[d] / s.box[d])
         assert np.abs(dx).max() < (1e-10 if precision == 0 else 1e-6), k
         assert a.scalars(k)["step"] == b.scalars(k)["step"] == 60
+
+
+@pytest.mark.parametrize("exec_mode", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_continuous_sliding_trajectory(hd, oracle_mod, exec_mode, precision):
+    """The plain-MD workload (one position, slider moving at v = 0.01, bias
+    off) over 200 steps: the drive's slider position and lateral force follow
+    the oracle (reading: x_S(step) = x_S + v_S step dt)."""
+    from hd_inputs import config_c1
+    spec = config_c1()[0]
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    o.step(200)
+    ctx = hd.make_context([spec], precision=precision, exec_mode=exec_mode, init_velocities=True)
+    ctx.step(200)
+    sc, so = ctx.scalars(0), o.scalars()
+    assert sc["x_slider"] == pytest.approx(so["x_slider"], rel=1e-14, abs=1e-14)
+    assert sc["x_slider"] == pytest.approx(spec.x_slider + 200 * spec.dt * spec.v_slider, rel=1e-12)
+    tol = 1e-9 if precision == 0 else 1e-4
+    assert sc["f_lat"] == pytest.approx(so["f_lat"], rel=tol, abs=tol)
+    assert sc["x_tip"] == pytest.approx(so["x_tip"], rel=tol, abs=tol)
+    assert sc["t_hyper"] == sc["t_md"]       # no bias: the clocks agree
+
+
+@pytest.mark.parametrize("exec_mode", [0, 1])
+def test_parameter_changes_after_finalize(hd, oracle_mod, exec_mode):
+    """Slider position, bias and thermostat changed after hd_finalize take
+    effect at the next evaluation, as in an oracle built with the new values."""
+    spec = biased(oracle_mod, snapshot_2d(seed=13))
+    ctx = hd.make_context([spec], precision=hd.HD_FP64, exec_mode=exec_mode, init_velocities=False)
+    new = spec.copy()
+    new.x_slider = spec.x_slider + 0.37
+    new.dv_max, new.m_b = 0.8, 3
+    new = biased(oracle_mod, new, frac=0.3, dv_max=0.8)
+    new.m_b = 3
+    new.kT, new.gamma = 0.15, 2.0
+    ctx.set_slider(0, new.x_slider)
+    ctx.set_bias(0, True, new.m_b, new.dv_max, new.g_lo, new.g_hi)
+    ctx.set_thermo(0, new.dt, new.gamma, new.kT, new.seed)
+    ctx.compute()
+    ref = oracle_mod.OracleSystem(new).compute()
+    sc = ctx.scalars(0)
+    assert sc["x_slider"] == pytest.approx(new.x_slider, rel=1e-15)
+    assert sc["f_lat"] == pytest.approx(ref["f_lat"], rel=1e-11, abs=1e-12)
+    assert abs(sc["dv"] - ref["dv"]) <= 1e-11 * new.dv_max
+    assert rel(ctx.forces(0), ref["f_tot"]) <= 1e-11
+    # the thermostat change shows in a short trajectory from the same state
+    # (velocities zero on both sides)
+    o = oracle_mod.OracleSystem(new)
+    o.step(10)
+    ctx.step(10)
+    dx = ctx.positions(0) - o.positions()
+    dx[0] -= new.box[0] * np.round(dx[0] / new.box[0])
+    assert np.abs(dx).max() < 1e-10
+    assert np.abs(ctx.velocities(0) - o.velocities()).max() < 1e-9
