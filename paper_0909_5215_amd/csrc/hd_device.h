@@ -77,6 +77,10 @@ struct Arrays {
   // share cells and read nearby records.
   int32_t *pos;                           // [ntot]
   double *rec;                            // [ntot][8]
+  // list build: the build positions (doubles 0-2) and type | role << 1
+  // (double 3) of each sorted position, written by the cell sort, so a
+  // stencil row's candidates are consecutive 32-byte records
+  double *brec;                           // [ntot][4]
 };
 
 constexpr int kRecDoubles = 8;

@@ -195,11 +195,23 @@ __global__ __launch_bounds__(1024) void kg_cell_scatter(const SysDesc *__restric
   A.cell_atoms[D.off + A.cell_start[D.cstart_off + c] + slot] = i;
 }
 
-// Sort each cell's atoms by index (so that lists are built in a fixed order)
-// and clear its count.  One wavefront per cell: the cell's atoms are staged
-// in LDS and each lane places its own atoms at their rank (the number of
-// smaller indices in the cell).  Cells of more than kSortMax atoms, which
-// only clamping at an open boundary can produce, are sorted by insertion.
+// Build record of sorted position p (atom i): build position and type/role.
+__device__ __forceinline__ void put_brec(const SysDesc &D, const Arrays &A, const double *__restrict__ xs,
+                                         int p, int i) {
+  const int64_t a = D.off + i, N = A.ntot;
+  double *b = A.brec + (D.off + p) * 4;
+  b[0] = xs[a];
+  b[1] = xs[N + a];
+  b[2] = D.dim == 3 ? xs[2 * N + a] : 0.0;
+  b[3] = (double)A.tr[a];
+}
+
+// Sort each cell's atoms by index (so that lists are built in a fixed order),
+// write their build records, and clear the cell's count.  One wavefront per
+// cell: the cell's atoms are staged in LDS and each lane places its own atoms
+// at their rank (the number of smaller indices in the cell).  Cells of more
+// than kSortMax atoms, which only clamping at an open boundary can produce,
+// are sorted by insertion.
 constexpr int kSortMax = 256;
 __global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ descs, Arrays A,
                                                     const int32_t *__restrict__ sys_ids, int nsys) {
@@ -207,6 +219,7 @@ __global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ 
   const int s = sys_ids[blockIdx.y];
   if (!A.rebuild_flag[s]) return;
   const SysDesc &D = descs[s];
+  const double *xs = A.rebuild_flag[s] == 2 ? A.xb : A.x;  // 2: from the recorded build positions
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int32_t *cat = A.cell_atoms + D.off;
   const int32_t *cst = A.cell_start + D.cstart_off;
@@ -224,7 +237,10 @@ __global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ 
         int r = 0;
         for (int j = 0; j < m; ++j) r += keys[wave][j] < key ? 1 : 0;
         cat[b + r] = key;
+        put_brec(D, A, xs, b + r, key);
       }
+    } else if (m == 1 && lane == 0) {
+      put_brec(D, A, xs, b, cat[b]);
     } else if (m > kSortMax && lane == 0) {
       for (int p = b + 1; p < b + m; ++p) {
         const int key = cat[p];
@@ -232,20 +248,26 @@ __global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ 
         while (q >= b && cat[q] > key) { cat[q + 1] = cat[q]; --q; }
         cat[q + 1] = key;
       }
+      for (int p = b; p < b + m; ++p) put_brec(D, A, xs, p, cat[p]);
     }
     if (have && lane == 0) __hip_atomic_store(&A.cell_count[D.cell_off + c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }
 }
 
+// List of the atom at sorted position p, one lane: candidates cell by cell in
+// stencil order, within a cell in index order (the cells are sorted); each
+// entry holds the neighbour's sorted position and type.  Positions are the
+// build records the cell sort wrote.
 template <int DIM>
-__device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__restrict__ xs, int p, int i) {
-  const int64_t N = A.ntot, off = D.off, ai = off + i;
+__device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
+  const int64_t off = D.off;
   const int n = D.n;
+  const double *__restrict__ brec = A.brec + off * 4;
   double xi[3];
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = xs[k * N + ai];
-  const int ri = A.tr[ai] >> 1;
+  for (int k = 0; k < DIM; ++k) xi[k] = brec[(int64_t)p * 4 + k];
+  const int ri = (int)brec[(int64_t)p * 4 + 3] >> 1;
   int cc[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -257,7 +279,6 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__re
   for (int k = 0; k < DIM; ++k)
     if (D.nc[k] > 1) { lo3[k] = -1; hi3[k] = 1; }
   const int32_t *cstart = A.cell_start + D.cstart_off;
-  const int32_t *catoms = A.cell_atoms + off;
   int32_t *list = A.nbr + D.nbr_off;
   int cnt = 0;
   for (int oz = lo3[2]; oz <= hi3[2]; ++oz)
@@ -283,10 +304,10 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, const double *__re
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int pp = p0 + u < pe ? p0 + u : p0;
-            const int64_t aj = off + catoms[pp];
-            trj[u] = A.tr[aj];
+            const double *cr = brec + (int64_t)pp * 4;
+            trj[u] = (int)cr[3];
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) xj[u][k] = xs[k * N + aj];
+            for (int k = 0; k < DIM; ++k) xj[u][k] = cr[k];
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
@@ -320,11 +341,10 @@ constexpr int kBuildThreads = 256;
 constexpr int kRowCap = 48;
 
 template <int DIM>
-__device__ int scan_row(const SysDesc &D, const Arrays &A, const double *__restrict__ xs, int p,
+__device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
                         const double xi[3], int ri, const int cc[3], int oy, int oz, int32_t *sub) {
-  const int64_t N = A.ntot, off = D.off;
   const int32_t *cstart = A.cell_start + D.cstart_off;
-  const int32_t *catoms = A.cell_atoms + off;
+  const double *__restrict__ brec = A.brec + D.off * 4;
   int lo0 = 0, hi0 = 0;
   if (D.nc[0] > 1) { lo0 = -1; hi0 = 1; }
   int cnt = 0;
@@ -347,10 +367,10 @@ __device__ int scan_row(const SysDesc &D, const Arrays &A, const double *__restr
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int pp = p0 + u < pe ? p0 + u : p0;
-        const int64_t aj = off + catoms[pp];
-        trj[u] = A.tr[aj];
+        const double *cr = brec + (int64_t)pp * 4;
+        trj[u] = (int)cr[3];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) xj[u][k] = xs[k * N + aj];
+        for (int k = 0; k < DIM; ++k) xj[u][k] = cr[k];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -380,17 +400,16 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
   const bool active = la < APB && lp < t.count;
   const int64_t off = D.off, N = A.ntot;
   const int p = t.first + lp;
-  const double *xs = flag == 2 ? A.xb : A.x;
   int i = 0, ri = 0;
   double xi[3] = {0, 0, 0};
   int cc[3] = {0, 0, 0};
   int cnt = 0;
   if (active) {
     i = A.cell_atoms[off + p];
-    const int64_t ai = off + i;
+    const double *b = A.brec + (off + p) * 4;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) xi[k] = xs[k * N + ai];
-    ri = A.tr[ai] >> 1;
+    for (int k = 0; k < DIM; ++k) xi[k] = b[k];
+    ri = (int)b[3] >> 1;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const int ck = (int)floor((xi[k] - D.lo[k]) * D.inv_h[k]);
@@ -398,7 +417,7 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
     }
     const int oy = DIM == 3 ? r % 3 - 1 : r - 1, oz = DIM == 3 ? r / 3 - 1 : 0;
     const bool in_y = D.nc[1] > 1 || oy == 0, in_z = DIM < 3 || D.nc[2] > 1 || oz == 0;
-    if (in_y && in_z) cnt = scan_row<DIM>(D, A, xs, p, xi, ri, cc, oy, oz, sub_all + tid);
+    if (in_y && in_z) cnt = scan_row<DIM>(D, A, p, xi, ri, cc, oy, oz, sub_all + tid);
   }
   counts[tid] = cnt;
   __syncthreads();
@@ -418,7 +437,7 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
       list[(int64_t)(before + k) * n + p] = sub_all[k * kBuildThreads + tid];
   }
   if (r != 0) return;
-  if (over) total = list_atom_g<DIM>(D, A, xs, p, i);   // a crowded row: the one-lane build
+  if (over) total = list_atom_g<DIM>(D, A, p);   // a crowded row: the one-lane build
   const int64_t a = off + i;
   A.nnb[off + p] = total < D.maxnb ? total : D.maxnb;
   if (total > D.maxnb) atomicOr(&st.flags, FLAG_NBR_OVERFLOW);

@@ -829,6 +829,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
   ALLOC(A.ftot, 3 * N); ALLOC(A.flj, 3 * N); ALLOC(A.hu, 3 * N); ALLOC(A.fb, 3 * N);
   ALLOC(A.eatom, N);
   ALLOC(A.rec, (size_t)N * hdk::kRecDoubles);
+  ALLOC(A.brec, (size_t)N * 4);
   ALLOC(A.pos, N);
   if (ctx->prec == HD_FP64) { double *u; ALLOC(u, 3 * N); A.u = u; }
   else { float *u; ALLOC(u, 3 * N); A.u = u; }
