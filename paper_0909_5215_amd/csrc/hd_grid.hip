@@ -479,8 +479,9 @@ __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__
 
 // ---- pair pass with per-tile partial sums ---------------------------------
 // LPA adjacent lanes per atom: lane s of an atom takes list entries s,
-// s + LPA, ...; the lanes' sums are then combined by shuffles (a + b on both
-// lanes, the same bits).  More wavefronts per tile hide more gather latency.
+// s + LPA, ...; the lanes' sums are then combined by quad permutes (a + b on
+// both lanes, the same bits).  More wavefronts per tile hide more gather
+// latency.
 template <int DIM, typename T, int LPA>
 __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int tile_index) {
   __shared__ double red[NRED * 16];
@@ -512,13 +513,18 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
     else { F[k] = acc.F[k].get(); H[k] = acc.H[k].get(); }
   }
   if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
-  // every lane takes part in the shuffles (no divergence around them)
+  // every lane takes part in the permutes (no divergence around them)
+  if constexpr (LPA >= 2) {
 #pragma unroll
-  for (int d = 1; d < LPA; d <<= 1) {
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) { F[k] += __shfl_xor(F[k], d, 64); H[k] += __shfl_xor(H[k], d, 64); }
-    e += __shfl_xor(e, d, 64);
+    for (int k = 0; k < DIM; ++k) { F[k] += dpp_mov_f64<0xb1>(F[k]); H[k] += dpp_mov_f64<0xb1>(H[k]); }
+    e += dpp_mov_f64<0xb1>(e);   // lanes 0<->1, 2<->3
   }
+  if constexpr (LPA >= 4) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { F[k] += dpp_mov_f64<0x4e>(F[k]); H[k] += dpp_mov_f64<0x4e>(H[k]); }
+    e += dpp_mov_f64<0x4e>(e);   // lanes 0<->2, 1<->3
+  }
+  static_assert(LPA == 1 || LPA == 2 || LPA == 4, "one, two or four lanes per atom");
   if (valid && sub == 0) {
     const int64_t a = D.off + A.cell_atoms[D.off + p];
 #pragma unroll
@@ -541,9 +547,35 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
       for (int k = 0; k < DIM; ++k) { sums[3 + k] = F[k]; sums[6 + k] = H[k]; sums[9 + k] = u64[k]; }
     }
   }
-  block_sum<NRED>(sums, red);
-  double *part = A.partials + (int64_t)tile_index * NRED;
-  if (threadIdx.x < NRED) part[threadIdx.x] = sums[threadIdx.x];
+  // the tile's sums: a reduce-scatter butterfly within each wavefront (the
+  // rigid-layer sums only in wavefronts holding rigid atoms; elsewhere they
+  // are exact zeros), then the first NRED threads add the wave totals in
+  // wave order
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const bool wave_rigid = __ballot(valid && sub == 0 && role == ROLE_RIGID) != 0;
+  if (wave_rigid) {
+    double w16[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w16[q] = q < NRED ? sums[q] : 0.0;
+    const double tot = wave_sums_scatter<16>(w16, lane);
+    const int q = wave_scatter_index<16>(lane);
+    if (lane < 16 && q < NRED) red[q * 16 + wave] = tot;
+  } else {
+    double w4[4] = {sums[0], sums[1], sums[2], sums[12]};
+    const double tot = wave_sums_scatter<4>(w4, lane);
+    if (lane < 4) {
+      const int q = wave_scatter_index<4>(lane);
+      red[(q == 3 ? 12 : q) * 16 + wave] = tot;
+    } else if (lane < NRED) {
+      red[(lane - 1) * 16 + wave] = 0.0;   // the rigid-layer slots 3..11
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < NRED) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[threadIdx.x * 16 + w];
+    A.partials[(int64_t)tile_index * NRED + threadIdx.x] = s;
+  }
 }
 
 // Per-system sums of the tile partials in tile order (one workgroup per
