@@ -40,8 +40,21 @@ CSRC = os.path.join(ROOT, "paper_0909_5215_amd", "csrc")
 # longer describes the kernel and the traffic is reported as null.
 HBM_COUNTERS = {
     ("C2", "k_small<float, 2, 0, 512, false>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "7542396dbe0e5e28",
-        "fetch_kib": 993.1, "fetch_scale": 2.0, "write_kib": 2896.4, "write_scale": 1.0,
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "e0eb644ec32fd886",
+        "fetch_kib": 984.0, "fetch_scale": 2.0, "write_kib": 2896.3, "write_scale": 1.0,
+    },
+}
+
+# VALU wave-instructions of one launch of the stepping kernel (rocprofv3 --pmc
+# SQ_INSTS_VALU, summed over the XCDs) and the steps that launch ran; tied to
+# the kernel's sources like the HBM figures.  The chip issues at most one
+# wave-instruction per CU per cycle (four SIMDs, 4 cycles per 64-lane
+# instruction): 256 x 2.4 GHz = 614.4 G/s.
+VALU_ISSUE_PEAK_G = 256 * 2.4
+VALU_COUNTERS = {
+    ("C2", "k_small<float, 2, 0, 512, false>"): {
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "e0eb644ec32fd886",
+        "insts_valu": 1020393753.0, "steps": 2000,
     },
 }
 
@@ -300,6 +313,17 @@ def main():
     if rec and src_hash(rec["src"]) == rec["sha"]:
         traffic_bytes = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
         traffic = round(traffic_bytes / avg_launch_s / 1e9, 4)
+    # measured VALU issue of the stepping kernel (counters above), against the
+    # chip and against the CUs the launch occupies (one workgroup per system
+    # for the LDS-resident kernel)
+    issue = None
+    vrec = VALU_COUNTERS.get((args.config, kname))
+    if vrec and src_hash(vrec["src"]) == vrec["sha"]:
+        rate = vrec["insts_valu"] * steps_per_launch / vrec["steps"] / avg_launch_s / 1e9
+        cus = min(256, len(specs)) if kname.startswith("k_small") else 256
+        issue = {"unit": "G wave-instr/s", "achieved": round(rate, 2), "peak": VALU_ISSUE_PEAK_G,
+                 "frac": round(rate / VALU_ISSUE_PEAK_G, 4), "cus_occupied": cus,
+                 "frac_of_occupied_cus": round(rate / (cus * 2.4), 4)}
     roof = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
             "kernel": kname, "avg_launch_ms": round(ev_ms / max(launches, 1), 4),
@@ -364,6 +388,7 @@ def main():
                    "dim": dim, "parallelism": "batch of independent slider positions, 1 GPU"},
         "roofline": roof,
         "roofline_valu": valu,
+        "valu_issue": issue,
         "schedule": {k: sched[k] for k in ("lds_resident", "small_block", "persistent_large", "large_block")},
         "autotune_trials": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in t.items()} for t in trials],
         "cpu_baseline": cpu,
