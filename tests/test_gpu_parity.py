@@ -80,19 +80,27 @@ def _build_positions(blob, dim, n):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("path", ["lds", "grid", "grid3d"])
+@pytest.mark.parametrize("path", ["lds", "grid", "grid3d", "grid3d-wide"])
 def test_lists_after_rebuilds_bit_exact(hd, oracle_mod, path, precision):
     """After many steps (several list rebuilds, the grid's in cell-sorted
     order), the current lists are exactly the oracle's pair set at the
-    recorded build positions."""
-    spec = snapshot_3d(seed=91, nx=10, nz=4, R=4.0) if path == "grid3d" else snapshot_2d(seed=90)
+    recorded build positions.  grid3d-wide is a wider slab (4400 cells,
+    26063 atoms)."""
+    if path == "grid3d":
+        spec = snapshot_3d(seed=91, nx=10, nz=4, R=4.0)
+    elif path == "grid3d-wide":
+        spec = snapshot_3d(seed=92, nx=36, nz=5, R=4.0)
+    else:
+        spec = snapshot_2d(seed=90)
     exec_mode = hd.HD_EXEC_BATCHED if path == "lds" else hd.HD_EXEC_GRID
     ctx = hd.make_context([spec], precision=precision, exec_mode=exec_mode)
     ctx.step(300)
     assert ctx.scalars(0)["n_rebuilds"] >= 3
     xb = _build_positions(ctx.get_state(0), spec.dim, spec.n)
     got = set(map(tuple, ctx.debug_pairs(0).tolist()))
-    ref = set(map(tuple, oracle_mod.pairs_brute(spec, xb, spec.rc + spec.skin, exclude=True).tolist()))
+    # the oracle's cell-list pair set (pinned to brute force on the CPU)
+    pairs = oracle_mod.pairs_cells if spec.n > 5000 else oracle_mod.pairs_brute
+    ref = set(map(tuple, pairs(spec, xb, spec.rc + spec.skin, exclude=True).tolist()))
     assert got == ref
 
 
