@@ -269,6 +269,32 @@ hd_status hd_set_schedule(hd_ctx *ctx, const hd_schedule *shape);
 hd_status hd_autotune(hd_ctx *ctx, double min_ms, int64_t max_steps, hd_schedule *trials, int32_t cap,
                       int32_t *n_trials);
 
+/* Energy minimisation (the basin minimum r_O of eq. 7, and the quench-and-
+ * compare transition check of the parallel slider-position algorithm, §2.3):
+ * FIRE (Bitzek et al., PRL 97, 170201, 2006; dt_max = 10 dt, alpha_0 = 0.1,
+ * f_inc = 1.1, f_dec = 0.5, f_alpha = 0.99, N_min = 5) on the unbiased
+ * potential (LJ plus the drive at each system's slider position), from each
+ * listed system's current positions, starting at rest.  Mobile atoms and the
+ * rigid body move (semi-implicit Euler, first step dt); fixed atoms stay.
+ * Converged when the largest force on a degree of freedom is below ftol.
+ * Every system's run state (positions, velocities, forces, clock, lists) is
+ * restored afterwards, so stepping continues exactly as without the call.
+ *   systems[0..count): distinct system indices (after hd_finalize);
+ *   mode HD_QUENCH_CHECK: max_disp[k] = the largest atom displacement
+ *     (minimum image) of system k's minimum from its r_O -- a transition
+ *     when above a threshold of the caller's choosing;
+ *   mode HD_QUENCH_SET_REFERENCE: the minimum becomes the system's r_O;
+ *     max_disp[k] = the largest displacement from the starting positions;
+ *   iters[k] = iterations used, or -max_iters when not converged;
+ *   x_min (may be NULL): host buffer of sum_k dim_k * n_k doubles, receiving
+ *     each listed system's minimum ([dim][n], in list order).
+ * HD_E_ARG for bad arguments (max_iters >= 1, ftol > 0), HD_E_STATE for a
+ * system frozen as unstable.  Allocates its own device scratch. */
+#define HD_QUENCH_CHECK 0
+#define HD_QUENCH_SET_REFERENCE 1
+hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
+                    int32_t mode, int64_t *iters, double *max_disp, double *x_min);
+
 /* Per-kernel timing of the last hd_step, measured with HIP events on the
  * context stream: total milliseconds and launches. */
 hd_status hd_last_step_timing(hd_ctx *ctx, double *ms, int64_t *launches);

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhd.so")
-SOURCES = ["hd_runtime.cpp", "hd_kernels.hip", "hd_grid.hip", "hd_small.hip"]
+SOURCES = ["hd_runtime.cpp", "hd_kernels.hip", "hd_grid.hip", "hd_small.hip", "hd_fire.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -27,6 +27,25 @@ size_t small_lds_bytes(int dim, int kind, int nmax, int maxnb, int cellmax);
 size_t small_group_bytes(int kind, int dim, int nmax, int maxnb, int cellmax);
 hipError_t small_allow_lds(int kind, int dim, size_t bytes);
 
+// FIRE minimisation state of one listed system (hd_fire.hip).
+struct FireSys {
+  double dt, alpha;    // current step and mixing weight
+  double mixv, mixf;   // this iteration's velocity mixing: v <- mixv v + mixf F
+  double fmax;         // largest force on a degree of freedom at the last test
+  int64_t iters;       // iterations done (at convergence: the iteration that met it)
+  int32_t since_neg;   // iterations since the power was last non-positive
+  int32_t done;        // converged
+  int32_t reset;       // this iteration zeroes the velocities (P <= 0)
+  int32_t pad;
+};
+
+// One FIRE iteration of the listed systems (count of them, nmax bounds their
+// atom counts) from the forces in A.ftot and the rigid-body force in the
+// state: convergence test on the largest force (< ftol), velocity mixing and
+// semi-implicit Euler step.  Forces must be re-evaluated before the next one.
+hipError_t fire_iteration(const SysDesc *descs, SysState *states, const Arrays &A, const int32_t *sys_list,
+                          int count, int nmax, FireSys *fire, double ftol, int64_t iter, hipStream_t stream);
+
 // Tiles of the grid scheduler: each tile is a contiguous atom range of one
 // system (tiles never straddle systems).
 struct Tile {

@@ -1333,6 +1333,173 @@ hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) 
   return HD_OK;
 }
 
+hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
+                    int32_t mode, int64_t *iters, double *max_disp, double *x_min) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_quench before hd_finalize");
+  if (!systems || count <= 0 || !iters || !max_disp || !(ftol > 0) || max_iters < 1 ||
+      (mode != HD_QUENCH_CHECK && mode != HD_QUENCH_SET_REFERENCE))
+    return fail(ctx, HD_E_ARG, "hd_quench needs systems, count > 0, ftol > 0, max_iters >= 1, a known mode");
+  const int S = (int)ctx->sys.size();
+  std::vector<char> seen(S, 0);
+  int nmax = 0;
+  for (int k = 0; k < count; ++k) {
+    const int s = systems[k];
+    if (s < 0 || s >= S || seen[s]) return fail(ctx, HD_E_ARG, "quench systems must be distinct valid indices");
+    seen[s] = 1;
+    nmax = std::max(nmax, ctx->sys[s].n);
+  }
+  hd_status st = sync_in(ctx);
+  if (st != HD_OK) return st;
+  if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
+  // every system's state is checkpointed (the quench moves the listed ones
+  // and re-evaluates all), and the read-out arrays saved, so the run
+  // continues afterwards exactly as it would have
+  std::vector<std::vector<char>> ck(S);
+  for (int s = 0; s < S; ++s) {
+    size_t b = 0;
+    if ((st = hd_get_state(ctx, s, nullptr, &b)) != HD_OK) return st;
+    ck[s].resize(b);
+    if ((st = hd_get_state(ctx, s, ck[s].data(), &b)) != HD_OK) return st;
+  }
+  for (int k = 0; k < count; ++k) {
+    SysState T;
+    std::memcpy(&T, ck[systems[k]].data() + offsetof(CkptHeader, state), sizeof(T));
+    if (T.flags & hdk::FLAG_UNSTABLE) return fail(ctx, HD_E_STATE, "cannot quench a system frozen as unstable");
+  }
+  const size_t N = (size_t)ctx->ntot;
+  const size_t ubytes = 3 * N * (ctx->prec == HD_FP64 ? sizeof(double) : sizeof(float));
+  struct Saved { void *dev; void *copy; size_t bytes; };
+  std::vector<Saved> saved = {{ctx->A.flj, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.hu, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.fb, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.eatom, nullptr, N * sizeof(double)},
+                              {ctx->A.u, nullptr, ubytes}};
+  int32_t *d_list = nullptr;
+  hdk::FireSys *d_fire = nullptr;
+  auto release = [&]() {
+    for (auto &v : saved)
+      if (v.copy) (void)hipFree(v.copy);
+    if (d_list) (void)hipFree(d_list);
+    if (d_fire) (void)hipFree(d_fire);
+  };
+  auto hip_fail = [&](hipError_t e) {
+    release();
+    return fail(ctx, HD_E_HIP, std::string("hd_quench: ") + hipGetErrorString(e));
+  };
+  hipError_t e = hipSuccess;
+  for (auto &v : saved) {
+    if ((e = hipMalloc(&v.copy, v.bytes)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpyAsync(v.copy, v.dev, v.bytes, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess)
+      return hip_fail(e);
+  }
+  if ((e = hipMalloc(&d_list, sizeof(int32_t) * count)) != hipSuccess) return hip_fail(e);
+  if ((e = hipMalloc(&d_fire, sizeof(hdk::FireSys) * count)) != hipSuccess) return hip_fail(e);
+  std::vector<hdk::FireSys> fs(count);
+  for (int k = 0; k < count; ++k) {
+    fs[k] = hdk::FireSys{};
+    fs[k].dt = ctx->sys[systems[k]].th.dt;
+    fs[k].alpha = 0.1;
+  }
+  if ((e = hipMemcpyAsync(d_list, systems, sizeof(int32_t) * count, hipMemcpyHostToDevice, ctx->stream)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(d_fire, fs.data(), sizeof(hdk::FireSys) * count, hipMemcpyHostToDevice, ctx->stream)) !=
+          hipSuccess)
+    return hip_fail(e);
+  // FIRE starts at rest: the listed systems' velocities and rigid-body
+  // velocity are zeroed (the checkpoint restores them)
+  for (int k = 0; k < count; ++k) {
+    const int s = systems[k];
+    for (int d = 0; d < ctx->sys[s].dim; ++d)
+      if ((e = hipMemsetAsync(ctx->A.v + d * ctx->ntot + ctx->h_desc[s].off, 0, sizeof(double) * ctx->sys[s].n,
+                              ctx->stream)) != hipSuccess)
+        return hip_fail(e);
+    SysState T;
+    std::memcpy(&T, ck[s].data() + offsetof(CkptHeader, state), sizeof(T));
+    for (int d = 0; d < 3; ++d) T.VR[d] = 0.0;
+    if ((e = hipMemcpyAsync(ctx->d_state + s, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+      return hip_fail(e);
+  }
+  // the unbiased potential: the bias is off for the quench
+  std::vector<int32_t> bias_was(S);
+  for (int s = 0; s < S; ++s) {
+    bias_was[s] = ctx->sys[s].bias.enabled;
+    ctx->sys[s].bias.enabled = 0;
+    if ((st = upload_desc(ctx, s)) != HD_OK) { release(); return st; }
+  }
+  // iterations: forces, then the FIRE step; convergence read back every 32
+  st = evaluate_all(ctx);
+  int64_t it = 0;
+  for (; st == HD_OK && it < max_iters; ++it) {
+    if ((e = hdk::fire_iteration(ctx->d_desc, ctx->d_state, ctx->A, d_list, count, nmax, d_fire, ftol, it,
+                                 ctx->stream)) != hipSuccess)
+      break;
+    if ((st = evaluate_all(ctx)) != HD_OK) break;
+    if ((it & 31) == 31) {
+      if ((e = hipMemcpyAsync(fs.data(), d_fire, sizeof(hdk::FireSys) * count, hipMemcpyDeviceToHost,
+                              ctx->stream)) != hipSuccess ||
+          (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        break;
+      bool all = true;
+      for (const auto &f : fs) all = all && f.done;
+      if (all) break;
+    }
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(fs.data(), d_fire, sizeof(hdk::FireSys) * count, hipMemcpyDeviceToHost, ctx->stream);
+  // the minima (rigid atoms sit at the rigid body's final position)
+  size_t tot = 0;
+  for (int k = 0; k < count; ++k) tot += (size_t)ctx->sys[systems[k]].dim * ctx->sys[systems[k]].n;
+  std::vector<double> xm(tot);
+  if (e == hipSuccess && st == HD_OK) {
+    size_t o = 0;
+    for (int k = 0; k < count && st == HD_OK; ++k) {
+      st = copy_field(ctx, systems[k], ctx->A.x, xm.data() + o, hipMemcpyDeviceToHost);
+      o += (size_t)ctx->sys[systems[k]].dim * ctx->sys[systems[k]].n;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  // restore the bias, the saved arrays and every system's state
+  for (int s = 0; s < S; ++s) {
+    ctx->sys[s].bias.enabled = bias_was[s];
+    const hd_status su = upload_desc(ctx, s);
+    if (st == HD_OK) st = su;
+  }
+  for (auto &v : saved)
+    if (e == hipSuccess) e = hipMemcpyAsync(v.dev, v.copy, v.bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  release();
+  if (e != hipSuccess) return fail(ctx, HD_E_HIP, std::string("hd_quench: ") + hipGetErrorString(e));
+  if (st != HD_OK) return st;
+  if ((st = restore_all(ctx, ck)) != HD_OK) return st;
+  // results: iterations, the largest displacement from r_O (check) or from
+  // the starting positions (set reference), the minima
+  size_t o = 0;
+  for (int k = 0; k < count; ++k) {
+    const int s = systems[k];
+    const SysHost &h = ctx->sys[s];
+    const size_t nd = (size_t)h.dim * h.n;
+    const double *ref = (const double *)(ck[s].data() + sizeof(CkptHeader)) + (mode == HD_QUENCH_CHECK ? 2 : 0) * nd;
+    double worst = 0.0;
+    for (int i = 0; i < h.n; ++i) {
+      double d2 = 0.0;
+      for (int d = 0; d < h.dim; ++d) {
+        double dx = xm[o + (size_t)d * h.n + i] - ref[(size_t)d * h.n + i];
+        if (h.periodic[d]) dx = minimg_h(dx, h.box[d], 1);
+        d2 += dx * dx;
+      }
+      worst = std::max(worst, std::sqrt(d2));
+    }
+    iters[k] = fs[k].done ? fs[k].iters : -max_iters;
+    max_disp[k] = worst;
+    if (x_min) std::memcpy(x_min + o, xm.data() + o, sizeof(double) * nd);
+    if (mode == HD_QUENCH_SET_REFERENCE && (st = hd_set_reference(ctx, s, xm.data() + o)) != HD_OK) return st;
+    o += nd;
+  }
+  return sync_out(ctx);
+}
+
 hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int64_t *n_pairs) {
   CHECK_CTX();
   if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");

@@ -23,6 +23,7 @@ HD_EXEC_BATCHED, HD_EXEC_GRID, HD_EXEC_SEQUENTIAL = 0, 1, 2
 HD_FORCE_TOTAL, HD_FORCE_LJ, HD_FORCE_BIAS, HD_HU = 0, 1, 2, 3
 HD_FLAG_UNSTABLE, HD_FLAG_NBR_OVERFLOW = 1, 2
 HD_LAUNCH_LDS, HD_LAUNCH_PERSISTENT_LARGE = 1, 2
+HD_QUENCH_CHECK, HD_QUENCH_SET_REFERENCE = 0, 1
 
 _c = ctypes
 _dp = _c.POINTER(_c.c_double)
@@ -110,6 +111,8 @@ _SIGS = {
     "hd_set_schedule": (_c.c_int, [_P, _c.POINTER(hd_schedule)]),
     "hd_autotune": (_c.c_int, [_P, _c.c_double, _c.c_int64, _c.POINTER(hd_schedule), _c.c_int32,
                                _c.POINTER(_c.c_int32)]),
+    "hd_quench": (_c.c_int, [_P, _c.POINTER(_c.c_int32), _c.c_int32, _c.c_double, _c.c_int64, _c.c_int32,
+                             _c.POINTER(_c.c_int64), _dp, _dp]),
     "hd_last_error": (_c.c_char_p, [_P]),
     "hd_destroy": (None, [_P]),
 }
@@ -284,6 +287,31 @@ class Context:
         _check(self._h, load().hd_autotune(self._h, float(min_ms), int(max_steps), buf, cap, ctypes.byref(n)),
                "hd_autotune")
         return self.schedule(), [buf[k].as_dict() for k in range(min(n.value, cap))]
+
+    def quench(self, systems, ftol: float = 1e-10, max_iters: int = 100000, set_reference: bool = False):
+        """FIRE minimisation of the listed systems from their current
+        positions (hd_quench); the run state is left as it was.  Returns
+        (iters, max_disp, minima): per system the iterations used (negative:
+        not converged), the largest displacement from r_O (or, with
+        set_reference, from the start; the minimum then becomes r_O), and the
+        minimum positions [dim][n]."""
+        systems = [int(k) for k in systems]
+        n = len(systems)
+        ids = (ctypes.c_int32 * n)(*systems)
+        iters = (ctypes.c_int64 * n)()
+        disp = np.zeros(n, dtype=np.float64)
+        valid = [k for k in systems if 0 <= k < len(self.dims)]   # the library rejects the rest
+        tot = sum(self.dims[k] * self.sizes[k] for k in valid)
+        xm = np.zeros(tot, dtype=np.float64)
+        mode = HD_QUENCH_SET_REFERENCE if set_reference else HD_QUENCH_CHECK
+        _check(self._h, load().hd_quench(self._h, ids, n, float(ftol), int(max_iters), mode, iters, _darr(disp),
+                                         _darr(xm)), "hd_quench")
+        minima, o = [], 0
+        for k in systems:
+            m = self.dims[k] * self.sizes[k]
+            minima.append(xm[o:o + m].reshape(self.dims[k], self.sizes[k]).copy())
+            o += m
+        return [int(v) for v in iters], disp, minima
 
     # -- read-outs --------------------------------------------------------
     def _out(self, s):

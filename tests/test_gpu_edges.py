@@ -150,3 +150,29 @@ def test_crowded_stencil_rows_fall_back_to_one_lane_build(hd, oracle_mod):
     ref = set(map(tuple, oracle_mod.pairs_brute(s, s.pos, s.rc + s.skin, exclude=True).tolist()))
     assert max(np.bincount(np.array(sorted(ref)).ravel())) > 48
     assert got == ref
+
+
+@pytest.mark.parametrize("path", ["lds", "grid"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_narrow_periodic_box_takes_general_minimum_image(hd, oracle_mod, path, dim):
+    """A periodic box narrower than three list radii has one cell on that
+    axis: every pair shares it, with either image, and the list build takes
+    the general minimum image there.  Forces and, after rebuilds, the lists
+    match the oracle."""
+    from hd_inputs import build_3d
+    from tests.test_gpu_parity import _build_positions
+    s = build_2d(nx=6, ny=6, tip_w=3, tip_h=3) if dim == 2 else build_3d(5, 5, 3, 1.0)
+    assert s.box[0] < 3 * (s.rc + s.skin)
+    s.rO = s.pos.copy()
+    s.pos = perturbed(s, 0.05, 70 + dim)
+    exec_mode = hd.HD_EXEC_BATCHED if path == "lds" else hd.HD_EXEC_GRID
+    ctx = hd.make_context([s], precision=hd.HD_FP64, exec_mode=exec_mode, init_velocities=False)
+    ref = oracle_mod.OracleSystem(s).compute()
+    assert rel(ctx.forces(0), ref["f_tot"]) < 1e-11
+    ctx.init_velocities(0)
+    ctx.step(300)
+    assert ctx.scalars(0)["flags"] == 0 and ctx.scalars(0)["n_rebuilds"] >= 1
+    xb = _build_positions(ctx.get_state(0), s.dim, s.n)
+    got = set(map(tuple, ctx.debug_pairs(0).tolist()))
+    want = set(map(tuple, oracle_mod.pairs_brute(s, xb, s.rc + s.skin, exclude=True).tolist()))
+    assert got == want
