@@ -705,11 +705,12 @@ __global__ __launch_bounds__(256) void kg_ekin(const SysDesc *__restrict__ descs
 size_t grid_scal_bytes() { return sizeof(GridScal); }
 
 hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
-                     const GridPlan &P, bool compute_only, hipStream_t stream, int *launches) {
+                     const GridPlan &P, bool compute_only, hipStream_t stream, int *launches,
+                     bool force_rebuild) {
   const int nt = P.ntiles, B = P.block, co = compute_only ? 1 : 0;
   GridScal *gs = (GridScal *)P.gscal;
   int nl = 0;
-  if (compute_only) {
+  if (compute_only && force_rebuild) {
     hipLaunchKernelGGL(kg_set_flags, dim3((P.nsys + 255) / 256), dim3(256), 0, stream,
                        A.rebuild_flag, P.sys_ids, P.nsys, 1);
     ++nl;

@@ -67,9 +67,12 @@ size_t grid_scal_bytes();
 
 // One full step (or an evaluation when compute_only) of the grid scheduler.
 // Enqueues several kernels on `stream`; safe to capture in a HIP graph (no
-// memset or host synchronisation inside).
+// memset or host synchronisation inside).  An evaluation rebuilds every list
+// from the current positions unless force_rebuild is false; then, as in a
+// step, only lists whose atoms left half the skin are rebuilt.
 hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
-                     const GridPlan &P, bool compute_only, hipStream_t stream, int *launches);
+                     const GridPlan &P, bool compute_only, hipStream_t stream, int *launches,
+                     bool force_rebuild = true);
 // Kinetic energy of the covered systems.
 hipError_t grid_ekin(const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
                      hipStream_t stream);

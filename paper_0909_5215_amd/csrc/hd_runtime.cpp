@@ -403,15 +403,18 @@ hd_status launch_groups(hd_ctx *ctx, int64_t nsteps, int mode, hipStream_t strea
   return HD_OK;
 }
 
-// Evaluate at the current positions (rebuilding lists) for every system.
-hd_status evaluate_all(hd_ctx *ctx) {
+// Evaluate at the current positions for every system.  Lists are rebuilt
+// from the current positions, or (force_rebuild false, grid systems) only
+// where an atom left half the skin: the LDS-resident kernel builds its lists
+// at every launch either way.
+hd_status evaluate_all(hd_ctx *ctx, bool force_rebuild = true) {
   const int prec = ctx->prec == HD_FP64 ? 0 : 1;
   hd_status st = launch_groups(ctx, 0, 1, ctx->stream, nullptr);
   if (st != HD_OK) return st;
   for (auto &P : ctx->plans) {
     int l = 0;
     for (int s : P.ids) ctx->sorted_lists[s] = 1;
-    HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, true, ctx->stream, &l));
+    HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, true, ctx->stream, &l, force_rebuild));
     HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, ctx->stream));
   }
   ctx->need_eval = false;
@@ -1428,14 +1431,15 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
     ctx->sys[s].bias.enabled = 0;
     if ((st = upload_desc(ctx, s)) != HD_OK) { release(); return st; }
   }
-  // iterations: forces, then the FIRE step; convergence read back every 32
-  st = evaluate_all(ctx);
+  // iterations: forces, then the FIRE step; convergence read back every 32.
+  // Grid lists are rebuilt only when atoms leave half the skin.
+  st = evaluate_all(ctx, false);
   int64_t it = 0;
   for (; st == HD_OK && it < max_iters; ++it) {
     if ((e = hdk::fire_iteration(ctx->d_desc, ctx->d_state, ctx->A, d_list, count, nmax, d_fire, ftol, it,
                                  ctx->stream)) != hipSuccess)
       break;
-    if ((st = evaluate_all(ctx)) != HD_OK) break;
+    if ((st = evaluate_all(ctx, false)) != HD_OK) break;
     if ((it & 31) == 31) {
       if ((e = hipMemcpyAsync(fs.data(), d_fire, sizeof(hdk::FireSys) * count, hipMemcpyDeviceToHost,
                               ctx->stream)) != hipSuccess ||
