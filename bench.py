@@ -106,8 +106,10 @@ def prepare(hd, specs, quench_steps, prerun_steps, block):
     ctx = hd.make_context(q, precision=hd.HD_FP64, init_velocities=False, block_threads=block)
     t0 = time.perf_counter()
     iters, _, minima = ctx.quench(range(len(q)), ftol=1e-6, max_iters=quench_steps)
-    log(f"FIRE quench: {sum(1 for i in iters if i >= 0)} of {len(iters)} systems below 1e-6, "
-        f"at most {max(abs(i) for i in iters)} iterations, {time.perf_counter() - t0:.2f} s")
+    quench = {"kind": "FIRE on the GPU (hd_quench), float64, all systems at once", "ftol": 1e-6,
+              "seconds": round(time.perf_counter() - t0, 3), "converged": sum(1 for i in iters if i >= 0),
+              "systems": len(iters), "max_iterations": max(abs(i) for i in iters)}
+    log(f"FIRE quench: {quench}")
     for k, s in enumerate(specs):
         s.rO = minima[k]
     ctx.close()
@@ -138,7 +140,7 @@ def prepare(hd, specs, quench_steps, prerun_steps, block):
         s.g_lo, s.g_hi = float(lo), float(hi)
         states.append(ctx.get_state(k))
     ctx.close()
-    return specs, states
+    return specs, states, quench
 
 
 def interacting_pairs(specs, positions, max_systems=4):
@@ -278,7 +280,7 @@ def main():
     n_atoms = sum(s.n for s in specs)
     dim = specs[0].dim
     log(f"{args.config}: {len(specs)} systems, {n_atoms} atoms")
-    specs, states = prepare(hd, specs, args.quench_steps, args.prerun_steps, args.block)
+    specs, states, quench = prepare(hd, specs, args.quench_steps, args.prerun_steps, args.block)
     log("prepared (quench + pre-run)")
 
     # ---- batched float32 path ------------------------------------------------
@@ -401,6 +403,7 @@ def main():
         "unstable_systems": int(sum(1 for f in flags if f & 1)),
         "list_rebuilds_per_1000_steps": rebuild_rate,
         "mean_boost": float(np.mean(np.array(t_hyper) / np.maximum(np.array(t_md), 1e-300))),
+        "r_O_quench": quench,
     }
     print(json.dumps(out), flush=True)
 
