@@ -288,6 +288,9 @@ class Context:
                "hd_autotune")
         return self.schedule(), [buf[k].as_dict() for k in range(min(n.value, cap))]
 
+    def num_systems(self) -> int:
+        return int(load().hd_num_systems(self._h))
+
     def quench(self, systems, ftol: float = 1e-10, max_iters: int = 100000, set_reference: bool = False):
         """FIRE minimisation of the listed systems from their current
         positions (hd_quench); the run state is left as it was.  Returns
