@@ -1,7 +1,7 @@
 """The parallel slider-position algorithm of §2.3 (stepped sliding with S
 slider positions simulated at once), driven from the host over the C ABI.
 
-A round simulates S consecutive slider positions x0 + (base + j) dx,
+A cycle simulates S consecutive slider positions x0 + (base + j) dx,
 j = 0 .. S-1, one system each, all started from the same configuration (the
 frontier).  Each system is first relaxed to its basin minimum at its own
 slider position (GPU FIRE), which becomes its r_O -- the reference the bias
@@ -11,8 +11,8 @@ at chunk boundaries.  At every check, and when a system reaches dtau, its
 minimum is compared with r_O: a largest atom displacement above `threshold`
 is a transition, which ends that position's run.
 
-When the round ends, the latest position k* that saw a transition seeds the
-next round: its state after the transition is copied into every system and
+When the cycle ends, the latest position k* that saw a transition seeds the
+next cycle: its state after the transition is copied into every system and
 the positions become base + k*, ..., base + k* + S - 1; results of the
 positions after k* are discarded.  Without a transition the last position
 seeds base + S, ...  (the dice argument of §2.3: transitions at different
@@ -26,7 +26,7 @@ from typing import List, Optional
 
 
 @dataclass
-class Round:
+class Cycle:
     base: int                 # slider index of position 0
     transitions: List[bool]   # per position: a transition before its interval ended
     steps: List[int]          # MD steps each position ran until it finished
@@ -34,12 +34,12 @@ class Round:
     f_lat: List[float]        # lateral force on the tip when it finished
     max_disp: List[float]     # largest displacement from r_O at the last check
     k_star: int               # latest transitioning position, or -1
-    next_base: int            # slider index of the next round's position 0
+    next_base: int            # slider index of the next cycle's position 0
 
 
 class ParallelSliding:
-    """Rounds of the parallel slider-position algorithm over the systems of a
-    finalized context (system j = position j of a round)."""
+    """Cycles of the parallel slider-position algorithm over the systems of a
+    finalized context (system j = position j of a cycle)."""
 
     def __init__(self, ctx, x0: float, dx: float, dtau: float, threshold: float = 0.5,
                  ftol: float = 1e-6, max_quench: int = 20000, chunk: int = 100, check_every: int = 10,
@@ -60,7 +60,7 @@ class ParallelSliding:
         return self.x0 + index * self.dx
 
     def start(self, base: int, seed_state: Optional[bytes] = None):
-        """Place a round: copy seed_state (if given) into every system, move
+        """Place a cycle: copy seed_state (if given) into every system, move
         system j's slider to position base + j, relax each system to its basin
         minimum there and make it r_O."""
         ctx = self.ctx
@@ -74,7 +74,7 @@ class ParallelSliding:
         self._t0 = [s["t_hyper"] for s in sc]
         self._step0 = [s["step"] for s in sc]
 
-    def run_round(self) -> Round:
+    def run_cycle(self) -> Cycle:
         """Biased MD of every position until each has a transition or has
         advanced its boosted clock by dtau."""
         ctx, S = self.ctx, self.S
@@ -106,8 +106,8 @@ class ParallelSliding:
         seed = k_star if k_star >= 0 else S - 1
         self.seed_state = states[seed]
         next_base = self.base + (k_star if k_star >= 0 else S)
-        return Round(self.base, trans, steps, hyper, flat, disp, k_star, next_base)
+        return Cycle(self.base, trans, steps, hyper, flat, disp, k_star, next_base)
 
-    def advance(self, r: Round):
-        """Start the round that r's outcome seeds."""
+    def advance(self, r: Cycle):
+        """Start the cycle that r's outcome seeds."""
         self.start(r.next_base, self.seed_state)

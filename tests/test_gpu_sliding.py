@@ -1,6 +1,6 @@
 """The parallel slider-position algorithm (paper_0909_5215_amd.sliding) over
-the GPU path: rounds of S positions, the transition check, and the
-redistribution that seeds the next round from the latest transitioning
+the GPU path: cycles of S positions, the transition check, and the
+redistribution that seeds the next cycle from the latest transitioning
 position (or from the last position when none had a transition)."""
 import numpy as np
 import pytest
@@ -27,7 +27,7 @@ def batch(S, seed0=500):
     return specs
 
 
-def test_round_without_transition_advances_by_S(hd):
+def test_cycle_without_transition_advances_by_S(hd):
     from paper_0909_5215_amd.sliding import ParallelSliding
     S = 3
     ctx = hd.make_context(batch(S), precision=hd.HD_FP64)
@@ -35,7 +35,7 @@ def test_round_without_transition_advances_by_S(hd):
     ps.start(0)
     for j in range(S):
         assert ctx.scalars(j)["x_slider"] == pytest.approx(0.01 * j)
-    r = ps.run_round()
+    r = ps.run_cycle()
     assert r.k_star == -1 and not any(r.transitions)
     assert r.next_base == S
     assert all(h >= 1.0 for h in r.hyper_time) and all(st > 0 for st in r.steps)
@@ -49,7 +49,7 @@ def test_round_without_transition_advances_by_S(hd):
         assert ctx.scalars(j)["x_slider"] == pytest.approx(0.01 * (S + j))
 
 
-def test_latest_transition_seeds_the_next_round(hd):
+def test_latest_transition_seeds_the_next_cycle(hd):
     from paper_0909_5215_amd.sliding import ParallelSliding
     S = 4
     ctx = hd.make_context(batch(S, 600), precision=hd.HD_FP64)
@@ -64,7 +64,7 @@ def test_latest_transition_seeds_the_next_round(hd):
         rO = ctx.positions(j).copy()
         rO[0, tip] = (rO[0, tip] + a) % spec.box[0]
         ctx.set_reference(j, rO)
-    r = ps.run_round()
+    r = ps.run_cycle()
     assert r.transitions[1] and r.transitions[2]
     assert not r.transitions[0] and not r.transitions[3]
     assert r.k_star == 2 and r.next_base == 2
@@ -73,7 +73,7 @@ def test_latest_transition_seeds_the_next_round(hd):
     for j in range(S):
         np.testing.assert_array_equal(ctx.positions(j), x2)
         assert ctx.scalars(j)["x_slider"] == pytest.approx(0.01 * (2 + j))
-    # the new round's references are the minima at the new slider positions:
+    # the new cycle's references are the minima at the new slider positions:
     # no transition reads from them
     _, d, _ = ctx.quench(range(S), ftol=1e-6)
     assert float(np.max(d)) < 1e-4

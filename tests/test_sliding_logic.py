@@ -1,6 +1,6 @@
 """Bookkeeping of the parallel slider-position algorithm on the CPU, against
 a scripted stand-in for the GPU context: which positions finish when, the
-latest transitioning position k*, the next round's base and its seed state."""
+latest transitioning position k*, the next cycle's base and its seed state."""
 import pytest
 
 from paper_0909_5215_amd.sliding import ParallelSliding
@@ -50,7 +50,7 @@ def run(rates, jump_at, **kw):
     ctx = FakeContext(rates, jump_at)
     ps = ParallelSliding(ctx, x0=1.0, dx=0.5, dtau=10.0, chunk=10, check_every=3, **kw)
     ps.start(4)
-    return ctx, ps, ps.run_round()
+    return ctx, ps, ps.run_cycle()
 
 
 def test_positions_finish_at_their_own_boosted_interval():
