@@ -295,6 +295,23 @@ hd_status hd_autotune(hd_ctx *ctx, double min_ms, int64_t max_steps, hd_schedule
 hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
                     int32_t mode, int64_t *iters, double *max_disp, double *x_min);
 
+/* Lowest eigenvalue of the Hessian of the unbiased potential over system
+ * sys's degrees of freedom (its mobile atoms' coordinates and the rigid
+ * body's), the variable of the eigenvalue bias (§2.2, eq. 15), at the
+ * current positions: Lanczos with full reorthogonalisation from a random
+ * start (seed), each Hessian-vector product one evaluation of the pair pass's
+ * H u with r_O moved so that u is the Lanczos vector; the rigid body's row
+ * collects its atoms' rows (and the drive's Hessian).  Stops when the
+ * smallest Ritz value changes by less than tol (relative, at least absolute
+ * tol) or after max_iter products (at most the number of degrees of
+ * freedom).  *eps = that Ritz value; *iters = products used (negative: not
+ * converged); mode (may be NULL): host [dim][n] doubles receiving its Ritz
+ * vector (unit norm over the degrees of freedom; fixed atoms 0, rigid atoms
+ * the body's component).  The run state is restored afterwards.  Float32
+ * contexts give H u in float32 (eigenvalue to ~1e-6). */
+hd_status hd_min_mode(hd_ctx *ctx, int32_t sys, int32_t max_iter, double tol, uint64_t seed, double *eps,
+                      int32_t *iters, double *mode);
+
 /* Per-kernel timing of the last hd_step, measured with HIP events on the
  * context stream: total milliseconds and launches. */
 hd_status hd_last_step_timing(hd_ctx *ctx, double *ms, int64_t *launches);

@@ -240,3 +240,62 @@ class OracleSystem:
 
     def fire(self, ftol=1e-10, maxit=200000) -> int:
         return int(lib().orc_fire(self._h, float(ftol), int(maxit)))
+
+
+# --------------------------------------------------------------------------
+# The eigenvalue bias variable (§2.2; eq. 15 uses it): the lowest eigenvalue
+# of the Hessian of the unbiased potential over the degrees of freedom.
+# --------------------------------------------------------------------------
+ROLE_MOBILE_, ROLE_RIGID_ = 0, 2
+
+
+def dof_layout(spec):
+    """Degrees of freedom of a model: each mobile atom's coordinates (atom by
+    atom, dim each), then the rigid body's (dim), when it has rigid atoms."""
+    mob = np.flatnonzero(spec.role == ROLE_MOBILE_)
+    rig = np.flatnonzero(spec.role == ROLE_RIGID_)
+    return mob, rig, spec.dim * len(mob) + (spec.dim if len(rig) else 0)
+
+
+def dof_to_atoms(spec, q):
+    """Atom displacements [dim][n] of a degree-of-freedom vector: fixed atoms
+    stay, every rigid atom moves with the rigid body."""
+    mob, rig, m = dof_layout(spec)
+    w = np.zeros((spec.dim, spec.n))
+    w[:, mob] = np.asarray(q[:spec.dim * len(mob)]).reshape(len(mob), spec.dim).T
+    if len(rig):
+        w[:, rig] = np.asarray(q[spec.dim * len(mob):]).reshape(spec.dim, 1)
+    return w
+
+
+def reduced_hessian(spec, x=None) -> np.ndarray:
+    """Hessian of the unbiased potential (pairs and drive) over the degrees of
+    freedom at positions x, assembled column by column from the oracle's
+    Hessian-vector product: column q is H applied to the unit displacement of
+    degree of freedom q (u = x - r_O with r_O moved by it), the rigid body's
+    row collecting its atoms' rows.  Slow (one evaluation per degree of
+    freedom): small models only."""
+    x = np.asarray(spec.pos if x is None else x, dtype=np.float64)
+    mob, rig, m = dof_layout(spec)
+    o = OracleSystem(spec, x=x)
+    o.set_params(bias_on=0)
+    H = np.zeros((m, m))
+    for c in range(m):
+        e = np.zeros(m)
+        e[c] = 1.0
+        o.set_reference(x - dof_to_atoms(spec, e))
+        hu = o.compute()["hu"]
+        col = list(hu[:, mob].T.reshape(-1))
+        if len(rig):
+            col += list(hu[:, rig].sum(axis=1))
+        H[:, c] = col
+    return H
+
+
+def lowest_hessian_eigenvalue(spec, x=None):
+    """The eigenvalue bias variable: the smallest eigenvalue of
+    reduced_hessian (library symmetric eigensolver) and its unit eigenvector
+    over the degrees of freedom."""
+    H = reduced_hessian(spec, x)
+    vals, vecs = np.linalg.eigh(0.5 * (H + H.T))
+    return float(vals[0]), vecs[:, 0]

@@ -1504,6 +1504,214 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
   return sync_out(ctx);
 }
 
+namespace {
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a[0..k) and off-diagonal b[0..k-1) (Sturm sequence of its LDL^T
+// factors).
+int sturm_below(const std::vector<double> &a, const std::vector<double> &b, int k, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < k; ++i) {
+    const double off = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+    d = a[i] - x - (i > 0 ? off / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Smallest eigenvalue of that matrix, by bisection between Gershgorin bounds.
+double tridiag_min_eig(const std::vector<double> &a, const std::vector<double> &b, int k) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(lo) + std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(a, b, k, mid) >= 1) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Eigenvector of that matrix for the eigenvalue theta: inverse iteration
+// with a slightly shifted tridiagonal solve.
+std::vector<double> tridiag_vec(const std::vector<double> &a, const std::vector<double> &b, int k, double theta) {
+  std::vector<double> y(k, 1.0), c(k), d(k), z(k);
+  const double shift = theta - 1e-10 * std::max(1.0, std::fabs(theta));
+  for (int rep = 0; rep < 3; ++rep) {
+    // Thomas algorithm on (T - shift I) z = y
+    for (int i = 0; i < k; ++i) d[i] = a[i] - shift;
+    c = y;
+    for (int i = 1; i < k; ++i) {
+      const double m = b[i - 1] / d[i - 1];
+      d[i] -= m * b[i - 1];
+      c[i] -= m * c[i - 1];
+    }
+    z[k - 1] = c[k - 1] / d[k - 1];
+    for (int i = k - 2; i >= 0; --i) z[i] = (c[i] - b[i] * z[i + 1]) / d[i];
+    double nz = 0.0;
+    for (double v : z) nz += v * v;
+    nz = std::sqrt(nz);
+    for (int i = 0; i < k; ++i) y[i] = z[i] / nz;
+  }
+  return y;
+}
+
+}  // namespace
+
+hd_status hd_min_mode(hd_ctx *ctx, int32_t sys, int32_t max_iter, double tol, uint64_t seed, double *eps,
+                      int32_t *iters, double *mode) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_min_mode before hd_finalize");
+  if (check_sys(ctx, sys) != HD_OK || !eps || !iters || max_iter < 1 || !(tol > 0))
+    return fail(ctx, HD_E_ARG, "hd_min_mode needs a valid system, eps and iters outputs, max_iter >= 1, tol > 0");
+  const SysHost &h = ctx->sys[sys];
+  const int dim = h.dim, n = h.n;
+  std::vector<int> mob;
+  for (int i = 0; i < n; ++i)
+    if (h.role[i] == HD_ROLE_MOBILE) mob.push_back(i);
+  const bool rigid = h.n_rigid > 0;
+  const int m = dim * (int)mob.size() + (rigid ? dim : 0);   // degrees of freedom
+  if (m == 0) return fail(ctx, HD_E_ARG, "the system has no degrees of freedom");
+  hd_status st = sync_in(ctx);
+  if (st != HD_OK) return st;
+  if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
+  const int S = (int)ctx->sys.size();
+  std::vector<std::vector<char>> ck(S);
+  for (int s = 0; s < S; ++s) {
+    size_t b = 0;
+    if ((st = hd_get_state(ctx, s, nullptr, &b)) != HD_OK) return st;
+    ck[s].resize(b);
+    if ((st = hd_get_state(ctx, s, ck[s].data(), &b)) != HD_OK) return st;
+  }
+  const size_t N = (size_t)ctx->ntot;
+  const size_t ubytes = 3 * N * (ctx->prec == HD_FP64 ? sizeof(double) : sizeof(float));
+  struct Saved { void *dev; void *copy; size_t bytes; };
+  std::vector<Saved> saved = {{ctx->A.flj, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.hu, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.fb, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.eatom, nullptr, N * sizeof(double)},
+                              {ctx->A.u, nullptr, ubytes}};
+  auto release = [&]() {
+    for (auto &v : saved)
+      if (v.copy) (void)hipFree(v.copy);
+  };
+  hipError_t e = hipSuccess;
+  for (auto &v : saved) {
+    if ((e = hipMalloc(&v.copy, v.bytes)) != hipSuccess ||
+        (e = hipMemcpyAsync(v.copy, v.dev, v.bytes, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess) {
+      release();
+      return fail(ctx, HD_E_HIP, std::string("hd_min_mode: ") + hipGetErrorString(e));
+    }
+  }
+  const size_t nd = (size_t)dim * n;
+  const double *x = (const double *)(ck[sys].data() + sizeof(CkptHeader));   // positions
+  std::vector<double> rO_tmp(nd), hu(nd), w_atoms(nd);
+  // reduced Hessian times q: the displacement q of the degrees of freedom
+  // (each rigid atom takes the rigid body's) becomes u = x - r_O by moving
+  // r_O, one evaluation gives H u per atom, projected back (the rigid body
+  // collects its atoms' rows, which include the drive's Hessian)
+  auto matvec = [&](const std::vector<double> &q, std::vector<double> &out) -> hd_status {
+    std::fill(w_atoms.begin(), w_atoms.end(), 0.0);
+    for (size_t t = 0; t < mob.size(); ++t)
+      for (int d = 0; d < dim; ++d) w_atoms[(size_t)d * n + mob[t]] = q[t * dim + d];
+    if (rigid)
+      for (int i = 0; i < n; ++i)
+        if (h.role[i] == HD_ROLE_RIGID)
+          for (int d = 0; d < dim; ++d) w_atoms[(size_t)d * n + i] = q[mob.size() * dim + d];
+    for (size_t k = 0; k < nd; ++k) rO_tmp[k] = x[k] - w_atoms[k];
+    for (int d = 0; d < dim; ++d)
+      HIPCHK(hipMemcpyAsync(ctx->A.rO + d * ctx->ntot + ctx->h_desc[sys].off, rO_tmp.data() + (size_t)d * n,
+                            sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    hd_status r = evaluate_all(ctx);
+    if (r != HD_OK) return r;
+    if ((r = copy_field(ctx, sys, ctx->A.hu, hu.data(), hipMemcpyDeviceToHost)) != HD_OK) return r;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    out.assign(m, 0.0);
+    for (size_t t = 0; t < mob.size(); ++t)
+      for (int d = 0; d < dim; ++d) out[t * dim + d] = hu[(size_t)d * n + mob[t]];
+    if (rigid)
+      for (int i = 0; i < n; ++i)
+        if (h.role[i] == HD_ROLE_RIGID)
+          for (int d = 0; d < dim; ++d) out[mob.size() * dim + d] += hu[(size_t)d * n + i];
+    return HD_OK;
+  };
+  // Lanczos with full reorthogonalisation from a seeded random start
+  const int kmax = std::min(max_iter, m);
+  std::vector<std::vector<double>> Q;
+  std::vector<double> alpha, beta, q(m), wv;
+  uint64_t rs = seed * 0x9E3779B97F4A7C15ull + 1;
+  double nq = 0.0;
+  for (int i = 0; i < m; ++i) {
+    rs ^= rs << 13; rs ^= rs >> 7; rs ^= rs << 17;   // xorshift64
+    q[i] = (double)(rs >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    nq += q[i] * q[i];
+  }
+  for (double &v : q) v /= std::sqrt(nq);
+  double theta = 0.0, prev = 0.0;
+  int used = 0;
+  bool converged = false;
+  for (int j = 0; j < kmax && st == HD_OK; ++j) {
+    Q.push_back(q);
+    if ((st = matvec(q, wv)) != HD_OK) break;
+    double a = 0.0;
+    for (int i = 0; i < m; ++i) a += q[i] * wv[i];
+    alpha.push_back(a);
+    for (int rep = 0; rep < 2; ++rep)
+      for (const auto &v : Q) {
+        double c = 0.0;
+        for (int i = 0; i < m; ++i) c += v[i] * wv[i];
+        for (int i = 0; i < m; ++i) wv[i] -= c * v[i];
+      }
+    double bnorm = 0.0;
+    for (double v : wv) bnorm += v * v;
+    bnorm = std::sqrt(bnorm);
+    used = j + 1;
+    theta = tridiag_min_eig(alpha, beta, used);
+    // converged, or the Krylov space is invariant (H q within the span)
+    if ((j > 0 && std::fabs(theta - prev) <= tol * std::max(1.0, std::fabs(theta))) ||
+        bnorm <= 1e-12 * std::max(std::fabs(a), std::fabs(theta))) {
+      converged = true;
+      break;
+    }
+    prev = theta;
+    beta.push_back(bnorm);
+    for (int i = 0; i < m; ++i) q[i] = wv[i] / bnorm;
+  }
+  // restore the run state
+  for (auto &v : saved)
+    if (e == hipSuccess) e = hipMemcpyAsync(v.dev, v.copy, v.bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  release();
+  if (e != hipSuccess) return fail(ctx, HD_E_HIP, std::string("hd_min_mode: ") + hipGetErrorString(e));
+  if (st != HD_OK) return st;
+  if ((st = restore_all(ctx, ck)) != HD_OK) return st;
+  *eps = theta;
+  *iters = converged ? used : -used;
+  if (mode) {
+    // the Ritz vector, unit norm over the degrees of freedom, as atom
+    // displacements [dim][n] (fixed atoms 0, rigid atoms the body's)
+    const std::vector<double> y = tridiag_vec(alpha, beta, used, theta);
+    std::vector<double> v(m, 0.0);
+    for (int j = 0; j < used; ++j)
+      for (int i = 0; i < m; ++i) v[i] += y[j] * Q[j][i];
+    double nv = 0.0;
+    for (double c : v) nv += c * c;
+    nv = std::sqrt(nv);
+    std::fill(mode, mode + nd, 0.0);
+    for (size_t t = 0; t < mob.size(); ++t)
+      for (int d = 0; d < dim; ++d) mode[(size_t)d * n + mob[t]] = v[t * dim + d] / nv;
+    if (rigid)
+      for (int i = 0; i < n; ++i)
+        if (h.role[i] == HD_ROLE_RIGID)
+          for (int d = 0; d < dim; ++d) mode[(size_t)d * n + i] = v[mob.size() * dim + d] / nv;
+  }
+  return sync_out(ctx);
+}
+
 hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int64_t *n_pairs) {
   CHECK_CTX();
   if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");

@@ -113,6 +113,8 @@ _SIGS = {
                                _c.POINTER(_c.c_int32)]),
     "hd_quench": (_c.c_int, [_P, _c.POINTER(_c.c_int32), _c.c_int32, _c.c_double, _c.c_int64, _c.c_int32,
                              _c.POINTER(_c.c_int64), _dp, _dp]),
+    "hd_min_mode": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_uint64, _dp,
+                               _c.POINTER(_c.c_int32), _dp]),
     "hd_last_error": (_c.c_char_p, [_P]),
     "hd_destroy": (None, [_P]),
 }
@@ -315,6 +317,16 @@ class Context:
             minima.append(xm[o:o + m].reshape(self.dims[k], self.sizes[k]).copy())
             o += m
         return [int(v) for v in iters], disp, minima
+
+    def min_mode(self, s: int, max_iter: int = 300, tol: float = 1e-10, seed: int = 1):
+        """Lowest Hessian eigenvalue over system s's degrees of freedom and its
+        mode (hd_min_mode).  Returns (eps, iters, mode [dim][n])."""
+        eps = ctypes.c_double()
+        it = ctypes.c_int32()
+        m = self._out(s) if 0 <= s < len(self.dims) else np.zeros(1)
+        _check(self._h, load().hd_min_mode(self._h, int(s), int(max_iter), float(tol), int(seed), ctypes.byref(eps),
+                                           ctypes.byref(it), _darr(m)), "hd_min_mode")
+        return eps.value, it.value, m
 
     # -- read-outs --------------------------------------------------------
     def _out(self, s):

@@ -550,3 +550,52 @@ def test_lattice_in_registry(oracle_mod, maker):
     np.testing.assert_allclose(r, 2 ** (1 / 6), rtol=1e-12)
     # every atom has at least one nearest neighbour
     assert len(np.unique(pairs)) == spec.n
+
+
+# --------------------------------------------------------------------------
+# The eigenvalue bias variable: reduced Hessian and its lowest eigenvalue
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("maker", [small2d, small3d], ids=["2d", "3d"])
+def test_reduced_hessian_is_the_energy_curvature(oracle_mod, maker):
+    """q^T H q equals the second difference of the energy along the
+    degree-of-freedom displacement q (mobile atoms and the rigid body), and
+    H is symmetric: a wrong rigid-body row, a missing drive term or a sign
+    slip fails this."""
+    spec = maker(x_slider=0.3)
+    x = perturbed(spec, 0.04, 3)
+    H = oracle_mod.reduced_hessian(spec, x)
+    assert np.abs(H - H.T).max() <= 1e-9 * np.abs(H).max()
+    rng = np.random.default_rng(5)
+    o = oracle_mod.OracleSystem(spec, x=x)
+    o.set_params(bias_on=0)
+    e0 = o.compute()["e_pot"]
+    h = 1e-4
+    for _ in range(3):
+        q = rng.normal(size=H.shape[0])
+        q /= np.linalg.norm(q)
+        w = oracle_mod.dof_to_atoms(spec, q)
+        ep = []
+        for sgn in (1.0, -1.0):
+            o2 = oracle_mod.OracleSystem(spec, x=x)
+            o2.set_params(bias_on=0)
+            o2.set_positions(x + sgn * h * w)
+            ep.append(o2.compute()["e_pot"])
+        fd = (ep[0] - 2.0 * e0 + ep[1]) / h ** 2
+        assert fd == pytest.approx(q @ H @ q, rel=2e-4, abs=1e-4)
+
+
+def test_lowest_eigenvalue_positive_at_a_minimum(oracle_mod):
+    """At a FIRE minimum every curvature is positive, and the lowest
+    eigenvalue bounds every Rayleigh quotient from below."""
+    spec = small2d()
+    o = oracle_mod.OracleSystem(spec, x=perturbed(spec, 0.05, 7))
+    assert o.fire(ftol=1e-9, maxit=200000) >= 0
+    x = o.positions()
+    eps, v = oracle_mod.lowest_hessian_eigenvalue(spec, x)
+    assert eps > 0.0
+    H = oracle_mod.reduced_hessian(spec, x)
+    assert v @ H @ v == pytest.approx(eps, rel=1e-10)
+    rng = np.random.default_rng(9)
+    for _ in range(5):
+        q = rng.normal(size=H.shape[0])
+        assert q @ H @ q / (q @ q) >= eps - 1e-12
