@@ -69,6 +69,13 @@ class SystemSpec:
     dv_max: float = 0.5
     g_lo: float = 0.0
     g_hi: float = 1.0
+    # harmonic tip bonds (eq. 12): tip-tip pairs closer than r_bond_cut are
+    # springs of stiffness k_bond and rest length r_bond, farther tip-tip
+    # pairs do not interact; off by default (tip-tip pairs are then LJ)
+    tip_bonds: int = 0
+    k_bond: float = 72.0 * 2.0 ** (-1.0 / 3.0)
+    r_bond: float = 2.0 ** (1.0 / 6.0)
+    r_bond_cut: float = 1.36
     # basin reference r_O (defaults to the lattice positions)
     rO: Optional[np.ndarray] = None
     label: str = ""
@@ -224,6 +231,69 @@ def build_3d(nx: int = 20, ny: int = 20, nz: int = 6, R: float = 8.0,
                       role=np.concatenate([roles, troles]),
                       box=np.array([Lx, Ly, 0.0]), periodic=np.array([1, 1, 0], np.int32),
                       eps=eps, label=f"3d_{nx}x{ny}x{nz}_R{R:g}")
+
+
+def _cone_sites(layers: int, r_apex: float, tan_half: float):
+    """Half-lattice coordinates of an fcc cone along [001] with flat ends:
+    layer t (t = 0 at the apex) holds the in-layer sites within
+    r_apex + t h tan_half of the axis, which passes through a site."""
+    h = AFCC / 2.0
+    out = []
+    for t in range(layers):
+        r = r_apex + t * h * tan_half
+        m = int(r / h) + 2
+        for py in range(-m, m + 1):
+            for px in range(-m, m + 1):
+                if (px + py + t) & 1:
+                    continue
+                if (px * px + py * py) * h * h <= r * r + _TOL:
+                    out.append((px, py, t))
+    return out
+
+
+def build_3d_cone(nx: int = 15, ny: int = 15, nz: int = 2, layers: int = 6, r_apex: float = 1.9,
+                  tan_half: float = 0.78, eps_st: float = 0.2) -> SystemSpec:
+    """The paper's 3D model (§3.2.1): an fcc substrate of nx x ny x nz cubic
+    cells (1800 atoms by default; periodic in x, y, bottom layer fixed) and a
+    conical fcc tip with flat ends in registry above it, its apex layer of 9
+    atoms one layer spacing above the substrate, 183 atoms in 6 layers by
+    default, top layer rigid; tip-tip interactions are the harmonic bonds of
+    eq. 12, the slider spring k = 10."""
+    h = AFCC / 2.0
+    basis = ((0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1))
+    px, py, pz = [], [], []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                for b in basis:
+                    px.append(2 * i + b[0]); py.append(2 * j + b[1]); pz.append(2 * k + b[2])
+    px = np.array(px); py = np.array(py); pz = np.array(pz)
+    n_sub = px.size
+    roles = np.where(pz == 0, ROLE_FIXED, ROLE_MOBILE).astype(np.uint8)
+    Lx, Ly = nx * AFCC, ny * AFCC
+    rel = _cone_sites(layers, r_apex, tan_half)
+    top_r = r_apex + (layers - 1) * h * tan_half
+    if 2 * top_r + 2 * 2.8 > min(Lx, Ly):
+        raise ValueError("tip wider than the periodic box")
+    cz = 2 * nz                              # apex layer: one spacing above the top layer 2nz-1
+    cx, cy = nx, ny
+    if (cx + cy + cz) & 1:
+        cx += 1
+    tpx = np.array([cx + p[0] for p in rel])
+    tpy = np.array([cy + p[1] for p in rel])
+    tpz = np.array([cz + p[2] for p in rel])
+    troles = np.where(tpz == cz + layers - 1, ROLE_RIGID, ROLE_MOBILE).astype(np.uint8)
+    px = np.concatenate([px, tpx]); py = np.concatenate([py, tpy]); pz = np.concatenate([pz, tpz])
+    pos = np.stack([px * h, py * h, pz * h]).astype(np.float64)
+    pos[0] = np.mod(pos[0], Lx)
+    pos[1] = np.mod(pos[1], Ly)
+    eps = np.array([[1.0, eps_st], [eps_st, 1.0]])
+    return SystemSpec(dim=3, pos=pos,
+                      type=np.concatenate([np.zeros(n_sub, np.uint8), np.ones(len(rel), np.uint8)]),
+                      role=np.concatenate([roles, troles]),
+                      box=np.array([Lx, Ly, 0.0]), periodic=np.array([1, 1, 0], np.int32),
+                      eps=eps, k_spring=10.0, tip_bonds=1,
+                      label=f"3d_cone_{nx}x{ny}x{nz}_{len(rel)}")
 
 
 # ----------------------------------------------------------------------------

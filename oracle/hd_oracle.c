@@ -397,7 +397,8 @@ typedef struct {
     double shift[2][2];
 } pair_ctx;
 
-/* One Lennard-Jones pair (eq. 9), energy-shifted at rc.  Delta = x_i - x_j
+/* One Lennard-Jones pair (eq. 9), energy-shifted at rc, or a harmonic tip
+ * bond (eq. 12) between tip atoms when the model has them.  Delta = x_i - x_j
  * (minimum image).  f = -phi'(r)/r so that F_i += f Delta; the pair Hessian
  * block is B I + C Delta Delta^T with B = phi'/r = -f and
  * C = (phi'' - phi'/r)/r^2; (Hu)_i += B w + C (Delta.w) Delta, w = u_i - u_j,
@@ -414,17 +415,29 @@ static void lj_pair(void *vctx, int i, int j)
         D[k] = -minimg(s->x[k * n + j] - s->x[k * n + i], p->box[k], p->periodic[k]);
         r2 = r2 + D[k] * D[k];
     }
-    if (!(r2 < p->rc * p->rc)) return;
     int a = s->type[i], b = s->type[j];
-    double eps = p->eps[a][b];
-    double s2 = p->sig[a][b] * p->sig[a][b];
-    double r2i = 1.0 / r2;
-    double sr2 = s2 * r2i;
-    double sr6 = sr2 * sr2 * sr2;
-    double phi = 4.0 * eps * (sr6 * sr6 - sr6) - c->shift[a][b];
-    double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
+    double phi, f, C;
+    if (p->tip_bonds && a == 1 && b == 1) {
+        /* harmonic tip bond (eq. 12): phi = k (r - r0)^2 / 2, so
+         * f = -phi'/r = -k (r - r0)/r and C = (phi'' - phi'/r)/r^2
+         * = k r0 / r^3 */
+        if (!(r2 < p->r_bond_cut * p->r_bond_cut)) return;
+        double r = sqrt(r2), dr = r - p->r_bond;
+        phi = 0.5 * p->k_bond * dr * dr;
+        f = -p->k_bond * dr / r;
+        C = p->k_bond * p->r_bond / (r * r2);
+    } else {
+        if (!(r2 < p->rc * p->rc)) return;
+        double eps = p->eps[a][b];
+        double s2 = p->sig[a][b] * p->sig[a][b];
+        double r2i = 1.0 / r2;
+        double sr2 = s2 * r2i;
+        double sr6 = sr2 * sr2 * sr2;
+        phi = 4.0 * eps * (sr6 * sr6 - sr6) - c->shift[a][b];
+        f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
+        C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
+    }
     double B = -f;
-    double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
     double Dw = 0.0;
     for (int k = 0; k < dim; ++k) {
         w[k] = c->u[k * n + i] - c->u[k * n + j];

@@ -48,6 +48,11 @@ typedef struct {
     double k_spring, f_normal, x_slider, v_slider;
     int32_t bias_on, m_b;
     double dv_max, g_lo, g_hi;
+    /* harmonic tip bonds (eq. 12): when tip_bonds, a tip-tip pair closer
+     * than r_bond_cut is a spring 1/2 k_bond (r - r_bond)^2 and farther
+     * tip-tip pairs do not interact */
+    int32_t tip_bonds, pad_tb;
+    double k_bond, r_bond, r_bond_cut;
 } orc_params;
 
 typedef struct {

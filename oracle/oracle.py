@@ -39,6 +39,8 @@ class OrcParams(ctypes.Structure):
         ("x_slider", ctypes.c_double), ("v_slider", ctypes.c_double),
         ("bias_on", ctypes.c_int32), ("m_b", ctypes.c_int32),
         ("dv_max", ctypes.c_double), ("g_lo", ctypes.c_double), ("g_hi", ctypes.c_double),
+        ("tip_bonds", ctypes.c_int32), ("pad_tb", ctypes.c_int32),
+        ("k_bond", ctypes.c_double), ("r_bond", ctypes.c_double), ("r_bond_cut", ctypes.c_double),
     ]
 
 
@@ -123,6 +125,10 @@ def params_from_spec(spec, **over) -> OrcParams:
     p.x_slider, p.v_slider = spec.x_slider, spec.v_slider
     p.bias_on, p.m_b = int(spec.bias_on), int(spec.m_b)
     p.dv_max, p.g_lo, p.g_hi = spec.dv_max, spec.g_lo, spec.g_hi
+    p.tip_bonds = int(getattr(spec, "tip_bonds", 0))
+    p.k_bond = float(getattr(spec, "k_bond", 0.0))
+    p.r_bond = float(getattr(spec, "r_bond", 0.0))
+    p.r_bond_cut = float(getattr(spec, "r_bond_cut", 0.0))
     for k, v in over.items():
         setattr(p, k, v)
     return p

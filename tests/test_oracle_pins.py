@@ -13,7 +13,7 @@ import math
 import numpy as np
 import pytest
 
-from hd_inputs import (AFCC, A2D, ROLE_FIXED, ROLE_MOBILE, ROLE_RIGID, SystemSpec,
+from hd_inputs import (AFCC, A2D, ROLE_FIXED, ROLE_MOBILE, ROLE_RIGID, SystemSpec, build_3d_cone,
                        build_2d, build_3d, perturbed)
 from tests.conftest import golden
 
@@ -27,6 +27,14 @@ def small2d(**kw):
 
 def small3d(**kw):
     s = build_3d(7, 7, 2, R=2.0)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def small_cone(**kw):
+    """A small conical tip with harmonic tip bonds (eq. 12) on a thin slab."""
+    s = build_3d_cone(nx=9, ny=9, nz=1, layers=4)
     for k, v in kw.items():
         setattr(s, k, v)
     return s
@@ -140,7 +148,7 @@ def _at(oracle_mod, spec, x, rO=None):
     return _energy(oracle_mod, spec, x, rO, "all")
 
 
-@pytest.mark.parametrize("maker", [small2d, small3d])
+@pytest.mark.parametrize("maker", [small2d, small3d, small_cone])
 def test_forces_match_energy_gradient(oracle_mod, maker):
     spec = maker()
     x = perturbed(spec, 0.06, 7)
@@ -169,7 +177,7 @@ def test_rigid_body_force_matches_energy_gradient(oracle_mod):
         assert FR[k] == pytest.approx(fd, rel=1e-6, abs=1e-6)
 
 
-@pytest.mark.parametrize("maker", [small2d, small3d])
+@pytest.mark.parametrize("maker", [small2d, small3d, small_cone])
 def test_newton_third_law(oracle_mod, maker):
     """Internal LJ forces sum to zero; what remains is the drive on the rigid
     layer (spring along x, anchor along y in 3D, -F_N along the normal)."""
@@ -189,7 +197,7 @@ def test_newton_third_law(oracle_mod, maker):
     assert r["f_lat"] == pytest.approx(drive[0], abs=1e-14)
 
 
-@pytest.mark.parametrize("maker", [small2d, small3d])
+@pytest.mark.parametrize("maker", [small2d, small3d, small_cone])
 def test_hu_matches_force_difference(oracle_mod, maker):
     """H u = -(F(r + h u) - F(r - h u)) / 2h (Hessian-vector product)."""
     spec = maker(x_slider=0.1)
@@ -599,3 +607,48 @@ def test_lowest_eigenvalue_positive_at_a_minimum(oracle_mod):
     for _ in range(5):
         q = rng.normal(size=H.shape[0])
         assert q @ H @ q / (q @ q) >= eps - 1e-12
+
+
+# --------------------------------------------------------------------------
+# Harmonic tip bonds (eq. 12)
+# --------------------------------------------------------------------------
+def test_harmonic_tip_bond_closed_forms(oracle_mod):
+    """Two tip atoms with bonds on: energy k (r - r0)^2 / 2, force -k (r - r0)
+    along the bond (zero at r0), H u = k u along the bond at r0 and
+    (k (r - r0)/r) u across it; beyond the bond cut no interaction at all
+    (not LJ, although within rc); substrate pairs stay LJ."""
+    k, r0 = 72.0 * 2.0 ** (-1.0 / 3.0), 2.0 ** (1.0 / 6.0)
+    for r in (r0, 1.05, 1.3, 1.5):
+        spec = pair_system(r, types=(1, 1))
+        spec.tip_bonds, spec.k_bond, spec.r_bond, spec.r_bond_cut = 1, k, r0, 1.36
+        res = oracle_mod.OracleSystem(spec).compute()
+        if r < 1.36:
+            assert res["e_pot"] == pytest.approx(0.5 * k * (r - r0) ** 2, rel=1e-13, abs=1e-15)
+            # Delta = x_0 - x_1 points along -x: F_0 = -k (r - r0)/r Delta
+            assert res["f_lj"][0, 0] == pytest.approx(k * (r - r0), rel=1e-12, abs=1e-14)
+            assert res["f_lj"][0, 1] == pytest.approx(-k * (r - r0), rel=1e-12, abs=1e-14)
+        else:
+            assert res["e_pot"] == 0.0 and np.all(res["f_lj"] == 0.0)
+    # H u at r0: along the bond k u, across it 0
+    spec = pair_system(r0, types=(1, 1))
+    spec.tip_bonds, spec.k_bond, spec.r_bond, spec.r_bond_cut = 1, k, r0, 1.36
+    for u_dir, want in (((1.0, 0.0), k), ((0.0, 1.0), 0.0)):
+        rO = spec.pos.copy()
+        rO[:, 0] -= 1e-3 * np.array(u_dir)          # u_0 = x - r_O = 1e-3 u_dir
+        res = oracle_mod.OracleSystem(spec, rO=rO).compute()
+        hu = res["hu"][:, 0]
+        assert hu[0 if u_dir[0] else 1] == pytest.approx(want * 1e-3, rel=1e-9, abs=1e-15)
+    # without bonds the same pair is LJ
+    spec = pair_system(1.5, types=(1, 1))
+    assert oracle_mod.OracleSystem(spec).compute()["e_pot"] != 0.0
+
+
+def test_cone_model_is_the_papers():
+    """§3.2.1: 1800 substrate atoms, 183 tip atoms with 9 at the apex in
+    registry with the substrate, spring k = 10, tip bonds on."""
+    s = build_3d_cone()
+    tip = s.type == 1
+    assert (~tip).sum() == 1800 and tip.sum() == 183
+    z = np.round(s.pos[2, tip], 6)
+    assert np.sum(z == z.min()) == 9
+    assert s.k_spring == 10.0 and s.tip_bonds == 1
