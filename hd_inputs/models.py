@@ -402,8 +402,25 @@ def config_c5b(n_sys: int = 256) -> List[SystemSpec]:
     return out
 
 
+def config_p3(n_sys: int = 64) -> List[SystemSpec]:
+    """The paper's 3D model (1800-atom substrate, 183-atom conical tip with
+    harmonic tip bonds, spring k = 10) at n_sys slider positions over one
+    lattice period, T = 0.1, slope bias on."""
+    base = build_3d_cone()
+    out = []
+    for k in range(n_sys):
+        s = base.copy()
+        s.f_normal, s.kT, s.gamma, s.dt = 5.0, 0.1, 1.0, 0.005
+        s.x_slider = k * AFCC / n_sys
+        s.seed = seed_for(1006, k)
+        s.bias_on = 1
+        s.label = f"P3[{k}]"
+        out.append(s)
+    return out
+
+
 CONFIGS = {"C1": config_c1, "C2": config_c2, "C3": config_c3, "C4": config_c4,
-           "C5a": config_c5a, "C5b": config_c5b}
+           "C5a": config_c5a, "C5b": config_c5b, "P3": config_p3}
 
 
 def perturbed(spec: SystemSpec, amp: float, seed: int) -> np.ndarray:

@@ -163,6 +163,17 @@ hd_status hd_add_system(hd_ctx *ctx, const hd_system_desc *desc, const hd_lj_par
                         const hd_thermo_params *thermo, const hd_drive_params *drive,
                         int32_t *sys_id);
 
+/* Harmonic tip bonds (eq. 12) for system sys: with enabled, a pair of tip
+ * atoms (type 1) closer than r_cut is a spring k_bond (r - r_bond)^2 / 2 and
+ * farther tip pairs do not interact (tip-substrate and substrate pairs stay
+ * LJ); without, tip pairs are LJ.  The cut lies between the tip lattice's
+ * first and second neighbour shells (bonds follow the lattice and, stiff,
+ * do not reach it).  HD_E_ARG unless k_bond >= 0, r_bond > 0 and
+ * 0 < r_cut <= rc; HD_E_STATE after hd_finalize.  Off by default.  Such
+ * systems run on the grid kernels (never LDS-resident). */
+hd_status hd_set_tip_bonds(hd_ctx *ctx, int32_t sys, int32_t enabled, double k_bond, double r_bond,
+                           double r_cut);
+
 /* Basin minimum r_O (eq. 7), SoA [dim][n]. */
 hd_status hd_set_reference(hd_ctx *ctx, int32_t sys, const double *rO);
 hd_status hd_set_bias(hd_ctx *ctx, int32_t sys, const hd_bias_params *bias);

@@ -43,6 +43,12 @@ struct SysDesc {
   int64_t nbr_off;
   int32_t maxnb, pad0;
   double XR0[3];
+  // harmonic tip bonds (eq. 12; tip_bonds != 0): tip-tip pairs closer than
+  // the bond cut (squared: rbc2) are springs k_bond (r - r_bond)^2 / 2,
+  // farther tip-tip pairs do not interact
+  int32_t tip_bonds, pad1;
+  double k_bond, r_bond, rbc2;
+  float k_bond_f, r_bond_f, rbc2_f, pad2;
 };
 
 // Mutable per-system state.
@@ -339,7 +345,12 @@ __device__ __forceinline__ float rcp_nr(float x) {
 template <typename T>
 struct LJRow {
   T eps[2], sig2[2], shift[2];
+  bool bond;          // atom i is a tip atom of a model with tip bonds
+  T kb, rb, rbc2;     // its bond constants
   __device__ __forceinline__ void load(const SysDesc &D, int ti) {
+    bond = D.tip_bonds != 0 && ti == 1;
+    if constexpr (sizeof(T) == 8) { kb = D.k_bond; rb = D.r_bond; rbc2 = D.rbc2; }
+    else { kb = D.k_bond_f; rb = D.r_bond_f; rbc2 = D.rbc2_f; }
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       if constexpr (sizeof(T) == 8) {
@@ -355,22 +366,58 @@ struct LJRow {
   }
 };
 
+// The pair's f = -phi'(r)/r (force on i: f dx), C = (phi'' - phi'/r)/r^2
+// (H u contribution: C (dx.w) dx - f w) and energy phi, for a tip-tip pair
+// of a model with tip bonds (eq. 12): a spring within the bond cut, nothing
+// beyond.  Zero when the pair is outside the cut.
+// 1/r from the hardware reciprocal square root, refined by Newton steps
+// (two in float64: relative error ~1e-16; float32's is ~1 ulp as is).
+template <typename T>
+__device__ __forceinline__ T inv_sqrt(T q) {
+  if constexpr (sizeof(T) == 8) {
+    double y = __builtin_amdgcn_rsq(q);
+    y = y * __builtin_fma(-0.5 * q * y, y, 1.5);
+    return y * __builtin_fma(-0.5 * q * y, y, 1.5);
+  } else {
+    return __builtin_amdgcn_rsqf(q);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bond_terms(const LJRow<T> &R, double r2, T &f, T &C, T &e) {
+  const bool in = r2 < (double)R.rbc2;
+  const T m = in ? T(1) : T(0);
+  const T q = in ? (T)r2 : T(1);
+  const T ir = inv_sqrt<T>(q);
+  const T dr = q * ir - R.rb;
+  f = -R.kb * dr * ir * m;
+  C = R.kb * R.rb * (ir * ir * ir) * m;
+  e = T(0.5) * R.kb * dr * dr * m;
+}
+
 // One neighbour's contribution to F_i, (H u)_i and the half pair energy.
 // dx = x_i - x_j (float64, minimum image), r2 its exactly rounded square
 // norm.  The term is evaluated branch-free; a neighbour that is not `live`
-// (outside rc) contributes exactly zero.
-template <int DIM, typename T>
+// (outside rc) contributes exactly zero.  Tip-tip pairs of a model with tip
+// bonds take the bond instead of the LJ terms (compiled in with BONDS only:
+// kernels that never see such a model keep the LJ-only registers).
+template <int DIM, typename T, bool BONDS = false>
 __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, const double dx[3], double r2,
                                           const T ui[3], const T uj[3], PairAcc<T> &acc) {
   if constexpr (sizeof(T) == 8) {
-    const double m = live ? 1.0 : 0.0;
-    const double r2i = 1.0 / (live ? r2 : 1.0);
-    const double eps = (tj ? R.eps[1] : R.eps[0]) * m;
-    const double sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
-    const double sr6 = sr2 * sr2 * sr2;
-    const double f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
-    const double C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
-    const double e = 4.0 * eps * (sr6 * sr6 - sr6) - (tj ? R.shift[1] : R.shift[0]) * m;
+    double f, C, e;
+    if (BONDS && R.bond && tj) {
+      bond_terms<double>(R, r2, f, C, e);
+    } else {
+      const double m = live ? 1.0 : 0.0;
+      const double r2i = 1.0 / (live ? r2 : 1.0);
+      const double eps = (tj ? R.eps[1] : R.eps[0]) * m;
+      const double sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
+      const double sr6 = sr2 * sr2 * sr2;
+      f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
+      C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
+      e = 4.0 * eps * (sr6 * sr6 - sr6) - (tj ? R.shift[1] : R.shift[0]) * m;
+    }
     double w[3], Dw = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -385,15 +432,20 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
     }
     acc.e += 0.5 * e;
   } else {
-    const float m = live ? 1.0f : 0.0f;
-    const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
-    const float eps = (tj ? R.eps[1] : R.eps[0]) * m;
-    const float sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
-    const float sr6 = sr2 * sr2 * sr2;
-    const float epsr = eps * r2i * sr6;
-    const float f = epsr * (48.0f * sr6 - 24.0f);
-    const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
-    const float e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
+    float f, C, e;
+    if (BONDS && R.bond && tj) {
+      bond_terms<float>(R, r2, f, C, e);
+    } else {
+      const float m = live ? 1.0f : 0.0f;
+      const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
+      const float eps = (tj ? R.eps[1] : R.eps[0]) * m;
+      const float sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
+      const float sr6 = sr2 * sr2 * sr2;
+      const float epsr = eps * r2i * sr6;
+      f = epsr * (48.0f * sr6 - 24.0f);
+      C = epsr * r2i * (672.0f * sr6 - 192.0f);
+      e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
+    }
     float d[3], w[3], Dw = 0.0f;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -413,19 +465,24 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
 
 // Float32 pair vectors for a half list: f_ij Delta (force on i), h_ij (the
 // pair's H u contribution to i) and the pair energy; j receives the negatives.
-template <int DIM>
+template <int DIM, bool BONDS = false>
 __device__ __forceinline__ void pair_vals_f(const LJRow<float> &R, int tj, bool live, const double dx[3], double r2,
                                             const float ui[3], const float uj[3], float fv[3], float hv[3],
                                             float &e) {
-  const float m = live ? 1.0f : 0.0f;
-  const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
-  const float eps = (tj ? R.eps[1] : R.eps[0]) * m;
-  const float sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
-  const float sr6 = sr2 * sr2 * sr2;
-  const float epsr = eps * r2i * sr6;
-  const float f = epsr * (48.0f * sr6 - 24.0f);
-  const float C = epsr * r2i * (672.0f * sr6 - 192.0f);
-  e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
+  float f, C;
+  if (BONDS && R.bond && tj) {
+    bond_terms<float>(R, r2, f, C, e);
+  } else {
+    const float m = live ? 1.0f : 0.0f;
+    const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
+    const float eps = (tj ? R.eps[1] : R.eps[0]) * m;
+    const float sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
+    const float sr6 = sr2 * sr2 * sr2;
+    const float epsr = eps * r2i * sr6;
+    f = epsr * (48.0f * sr6 - 24.0f);
+    C = epsr * r2i * (672.0f * sr6 - 192.0f);
+    e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
+  }
   float d[3], w[3], Dw = 0.0f;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -499,7 +556,7 @@ __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int
 // Pair pass of the atom at sorted position p over its full list (entries
 // hold sorted positions), neighbours read from the packed records; same
 // arithmetic as pair_atom.
-template <int DIM, typename T>
+template <int DIM, typename T, bool BONDS = false>
 __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
                                               const double xi[3], const T ui[3], int ti,
                                               PairAcc<T> &acc, int q0 = 0, int qstep = 1) {
@@ -521,7 +578,7 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; }
     const double r2 = pair_disp<DIM>(D, xi, xj, dx);
-    pair_term<DIM, T>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
+    pair_term<DIM, T, BONDS>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
   }
 }
 

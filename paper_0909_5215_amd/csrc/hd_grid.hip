@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__
 // s + LPA, ...; the lanes' sums are then combined by quad permutes (a + b on
 // both lanes, the same bits).  More wavefronts per tile hide more gather
 // latency.
-template <int DIM, typename T, int LPA>
+template <int DIM, typename T, int LPA, bool BONDS>
 __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int tile_index) {
   __shared__ double red[NRED * 16];
   const int64_t N = A.ntot;
@@ -505,7 +505,7 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
   }
   PairAcc<T> acc;
   acc.init();
-  if (valid) pair_atom_rec<DIM, T>(D, A, p, xi, ui, tr & 1, acc, sub, LPA);
+  if (valid) pair_atom_rec<DIM, T, BONDS>(D, A, p, xi, ui, tr & 1, acc, sub, LPA);
   double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, e;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -638,14 +638,16 @@ __global__ __launch_bounds__(256) void kg_reduce(const SysDesc *__restrict__ des
   else reduce_system<3>(D, states[s], A, s, first, nts, gs, compute_only != 0);
 }
 
-template <typename T, int LPA>
+// BONDS: the plan holds a model with harmonic tip bonds (a separate
+// instantiation, so that LJ-only plans keep their register budget).
+template <typename T, int LPA, bool BONDS>
 __global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ descs, Arrays A,
                                                  const Tile *__restrict__ tiles, int ntiles) {
   const int ti = xcd_tile(blockIdx.x, ntiles);
   const Tile t = tiles[ti];
   const SysDesc &D = descs[t.sys];
-  if (D.dim == 2) pairs_tile<2, T, LPA>(D, A, t, ti);
-  else pairs_tile<3, T, LPA>(D, A, t, ti);
+  if (D.dim == 2) pairs_tile<2, T, LPA, BONDS>(D, A, t, ti);
+  else pairs_tile<3, T, LPA, BONDS>(D, A, t, ti);
 }
 
 // ---- bias force, total force and final B -----------------------------------
@@ -730,22 +732,17 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
   hipLaunchKernelGGL(kg_build_list, dim3(nt * parts), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles,
                      nt);
   // four or two lanes per atom where the workgroup allows it
-  if (B <= 256) {
-    if (prec == 0)
-      hipLaunchKernelGGL((kg_pairs<double, 4>), dim3(nt), dim3(4 * B), 0, stream, descs, A, P.tiles, nt);
-    else
-      hipLaunchKernelGGL((kg_pairs<float, 4>), dim3(nt), dim3(4 * B), 0, stream, descs, A, P.tiles, nt);
-  } else if (B <= 512) {
-    if (prec == 0)
-      hipLaunchKernelGGL((kg_pairs<double, 2>), dim3(nt), dim3(2 * B), 0, stream, descs, A, P.tiles, nt);
-    else
-      hipLaunchKernelGGL((kg_pairs<float, 2>), dim3(nt), dim3(2 * B), 0, stream, descs, A, P.tiles, nt);
+  const int lpa = B <= 256 ? 4 : (B <= 512 ? 2 : 1);
+#define HD_PAIRS(TT, L, BB) \
+  hipLaunchKernelGGL((kg_pairs<TT, L, BB>), dim3(nt), dim3(L * B), 0, stream, descs, A, P.tiles, nt)
+#define HD_PAIRS_B(TT, L) do { if (P.any_bonds) HD_PAIRS(TT, L, true); else HD_PAIRS(TT, L, false); } while (0)
+  if (prec == 0) {
+    if (lpa == 4) HD_PAIRS_B(double, 4); else if (lpa == 2) HD_PAIRS_B(double, 2); else HD_PAIRS_B(double, 1);
   } else {
-    if (prec == 0)
-      hipLaunchKernelGGL((kg_pairs<double, 1>), dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
-    else
-      hipLaunchKernelGGL((kg_pairs<float, 1>), dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
+    if (lpa == 4) HD_PAIRS_B(float, 4); else if (lpa == 2) HD_PAIRS_B(float, 2); else HD_PAIRS_B(float, 1);
   }
+#undef HD_PAIRS_B
+#undef HD_PAIRS
   hipLaunchKernelGGL(kg_reduce, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids, P.sys_tile0,
                      P.tiles, gs, co);
   hipLaunchKernelGGL(kg_kick, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, co);

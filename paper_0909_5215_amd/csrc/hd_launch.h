@@ -61,6 +61,7 @@ struct GridPlan {
   int nsys;
   int max_ncell;           // largest cell count among the covered systems
   void *gscal;             // device, per-system scalars of the last evaluation
+  int any_bonds;           // some covered system has harmonic tip bonds
 };
 
 size_t grid_scal_bytes();

@@ -37,6 +37,8 @@ struct SysHost {
   hd_thermo_params th{};
   hd_drive_params dr{};
   hd_bias_params bias{};
+  int tip_bonds = 0;
+  double k_bond = 0.0, r_bond = 0.0, r_bond_cut = 0.0;
   int n_rigid = 0, first_rigid = -1;
   double XR[3] = {0, 0, 0}, XR0[3] = {0, 0, 0};
   bool init_vel = false;
@@ -235,6 +237,13 @@ void fill_desc(const hd_ctx *ctx, const SysHost &s, SysDesc &D) {
   D.f_normal = s.dr.f_normal;
   D.x_slider = s.dr.x_slider;
   D.v_slider = s.dr.v_slider;
+  D.tip_bonds = s.tip_bonds;
+  D.k_bond = s.k_bond;
+  D.r_bond = s.r_bond;
+  D.rbc2 = s.r_bond_cut * s.r_bond_cut;
+  D.k_bond_f = (float)s.k_bond;
+  D.r_bond_f = (float)s.r_bond;
+  D.rbc2_f = (float)D.rbc2;
   D.bias_on = s.bias.enabled;
   D.m_b = s.bias.m_b;
   D.dv_max = s.bias.dv_max;
@@ -333,6 +342,7 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
       tiles.push_back(T);
     }
     max_ncell = std::max(max_ncell, ctx->h_desc[s].ncell);
+    if (ctx->sys[s].tip_bonds) P.gp.any_bonds = 1;
   }
   hd_status st = dalloc(ctx, &P.d_tiles, tiles.size(), true);
   if (st != HD_OK) return st;
@@ -519,7 +529,8 @@ hd_status build_schedule(hd_ctx *ctx) {
     for (int s = 0; s < S; ++s) {
       const SysHost &h = ctx->sys[s];
       const int maxnb = h.dim == 2 ? ctx->maxnb2 : ctx->maxnb3;
-      const bool ok = h.n <= 1024 && maxnb <= 32767 &&
+      // models with tip bonds run on the grid kernels only
+      const bool ok = h.n <= 1024 && maxnb <= 32767 && !h.tip_bonds &&
                       hdk::small_lds_bytes(h.dim, prec, h.n, maxnb, ctx->h_desc[s].ncell) <= budget &&
                       !ctx->small_disabled;
       if (ok) cand.push_back(s);
@@ -553,7 +564,8 @@ hd_status build_schedule(hd_ctx *ctx) {
       for (int d = 0; d < 2; ++d) {
         hd_ctx::Group G;
         G.dim = d + 2;
-        for (int s : ctx->big_ids) if (ctx->sys[s].dim == d + 2) G.ids.push_back(s);
+        for (int s : ctx->big_ids)
+          if (ctx->sys[s].dim == d + 2 && !ctx->sys[s].tip_bonds) G.ids.push_back(s);
         if (!G.ids.empty()) ctx->groups.push_back(G);
       }
     }
@@ -575,11 +587,14 @@ hd_status build_schedule(hd_ctx *ctx) {
                                   hdk::small_group_bytes(prec, G.dim, G.nmax, G.maxnb, G.cellmax)));
     }
   }
-  // grid plans
-  if (ctx->exec == HD_EXEC_BATCHED && !ctx->persistent_big && !ctx->big_ids.empty()) {
-    std::vector<int> big(ctx->big_ids.begin(), ctx->big_ids.end());
+  // grid plans (with the one-workgroup kernel for the large systems, the
+  // models with tip bonds still take the grid)
+  std::vector<int> grid_big;
+  for (int s : ctx->big_ids)
+    if (!ctx->persistent_big || ctx->sys[s].tip_bonds) grid_big.push_back(s);
+  if (ctx->exec == HD_EXEC_BATCHED && !grid_big.empty()) {
     ctx->plans.resize(1);
-    if ((st = build_plan(ctx, big, ctx->plans[0])) != HD_OK) return st;
+    if ((st = build_plan(ctx, grid_big, ctx->plans[0])) != HD_OK) return st;
   } else if (ctx->exec == HD_EXEC_GRID) {
     std::vector<int> sys_all(S);
     for (int s = 0; s < S; ++s) sys_all[s] = s;
@@ -734,6 +749,21 @@ hd_status hd_set_thermo(hd_ctx *ctx, int32_t sys, const hd_thermo_params *thermo
   if (!(thermo->dt > 0) || thermo->gamma < 0 || thermo->kT < 0) return fail(ctx, HD_E_ARG, "bad thermostat");
   ctx->sys[sys].th = *thermo;
   if (ctx->finalized) { ctx->need_eval = true; return upload_desc(ctx, sys); }
+  return HD_OK;
+}
+
+hd_status hd_set_tip_bonds(hd_ctx *ctx, int32_t sys, int32_t enabled, double k_bond, double r_bond,
+                           double r_cut) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK) return fail(ctx, HD_E_ARG, "bad system");
+  SysHost &s = ctx->sys[sys];
+  if (enabled && !(k_bond >= 0.0 && r_bond > 0.0 && r_cut > 0.0 && r_cut <= s.lj.rc))
+    return fail(ctx, HD_E_ARG, "tip bonds need k >= 0, r0 > 0 and 0 < cut <= rc");
+  if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_tip_bonds after hd_finalize");
+  s.tip_bonds = enabled ? 1 : 0;
+  s.k_bond = k_bond;
+  s.r_bond = r_bond;
+  s.r_bond_cut = r_cut;
   return HD_OK;
 }
 

@@ -115,6 +115,7 @@ _SIGS = {
                              _c.POINTER(_c.c_int64), _dp, _dp]),
     "hd_min_mode": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_uint64, _dp,
                                _c.POINTER(_c.c_int32), _dp]),
+    "hd_set_tip_bonds": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double, _c.c_double]),
     "hd_last_error": (_c.c_char_p, [_P]),
     "hd_destroy": (None, [_P]),
 }
@@ -223,7 +224,13 @@ class Context:
             self.set_reference(s, spec.rO)
         if spec.bias_on:
             self.set_bias(s, True, spec.m_b, spec.dv_max, spec.g_lo, spec.g_hi)
+        if getattr(spec, "tip_bonds", 0):
+            self.set_tip_bonds(s, True, spec.k_bond, spec.r_bond, spec.r_bond_cut)
         return s
+
+    def set_tip_bonds(self, s: int, enabled: bool, k_bond: float, r_bond: float, r_cut: float):
+        _check(self._h, load().hd_set_tip_bonds(self._h, s, int(bool(enabled)), float(k_bond), float(r_bond),
+                                                float(r_cut)), "hd_set_tip_bonds")
 
     def set_reference(self, s: int, rO: np.ndarray):
         a = np.ascontiguousarray(rO, dtype=np.float64)
