@@ -69,6 +69,13 @@ class SystemSpec:
     dv_max: float = 0.5
     g_lo: float = 0.0
     g_hi: float = 1.0
+    # bias variables: bias_var1 enters the switch above, bias_var2 (-1: none)
+    # a second switch with b2_lo, b2_hi, combined by eq. 13; 0 slope (eq. 5),
+    # 1 curvature (eq. 6), 2 distance (eq. 7)
+    bias_var1: int = 0
+    bias_var2: int = -1
+    b2_lo: float = 0.0
+    b2_hi: float = 1.0
     # harmonic tip bonds (eq. 12): tip-tip pairs closer than r_bond_cut are
     # springs of stiffness k_bond and rest length r_bond, farther tip-tip
     # pairs do not interact; off by default (tip-tip pairs are then LJ)

@@ -23,6 +23,7 @@ struct orc_sys {
     int n_rigid, first_rigid;
     double XR[3], VR[3], XR0[3];
     double *ftot;            /* total force at the current positions */
+    double *tuu;             /* T[u,u] of the last evaluation */
     double FR[3];            /* total force on the rigid body */
     int64_t step;
     double t_md, t_hyper;
@@ -294,6 +295,7 @@ orc_sys *orc_create(const orc_params *p, const double *x, const uint8_t *type,
     s->rO = (double *)malloc(sizeof(double) * nd);
     s->cofs = (double *)calloc(nd, sizeof(double));
     s->ftot = (double *)calloc(nd, sizeof(double));
+    s->tuu = (double *)calloc(nd, sizeof(double));
     s->type = (uint8_t *)malloc(p->n);
     s->role = (uint8_t *)malloc(p->n);
     memcpy(s->x, x, sizeof(double) * nd);
@@ -307,7 +309,7 @@ orc_sys *orc_create(const orc_params *p, const double *x, const uint8_t *type,
 void orc_destroy(orc_sys *s)
 {
     if (!s) return;
-    free(s->x); free(s->v); free(s->rO); free(s->cofs); free(s->ftot);
+    free(s->x); free(s->v); free(s->rO); free(s->cofs); free(s->ftot); free(s->tuu);
     free(s->type); free(s->role);
     free(s);
 }
@@ -392,7 +394,7 @@ void orc_init_velocities(orc_sys *s)
 typedef struct {
     const orc_sys *s;
     const double *u;
-    double *f, *hu, *e_atom;
+    double *f, *hu, *e_atom, *tuu;
     double e_lj;
     double shift[2][2];
 } pair_ctx;
@@ -402,7 +404,10 @@ typedef struct {
  * (minimum image).  f = -phi'(r)/r so that F_i += f Delta; the pair Hessian
  * block is B I + C Delta Delta^T with B = phi'/r = -f and
  * C = (phi'' - phi'/r)/r^2; (Hu)_i += B w + C (Delta.w) Delta, w = u_i - u_j,
- * with the opposite sign on j. */
+ * with the opposite sign on j.  The pair's share of u.Hu is
+ * B |w|^2 + C (Delta.w)^2; its gradient in x_i at fixed u, with dB/dr = r C
+ * and Dc = (dC/dr)/r, is (C |w|^2 + Dc (Delta.w)^2) Delta + 2 C (Delta.w) w,
+ * the pair's share of T[u,u] (opposite sign on j). */
 static void lj_pair(void *vctx, int i, int j)
 {
     pair_ctx *c = (pair_ctx *)vctx;
@@ -416,7 +421,7 @@ static void lj_pair(void *vctx, int i, int j)
         r2 = r2 + D[k] * D[k];
     }
     int a = s->type[i], b = s->type[j];
-    double phi, f, C;
+    double phi, f, C, Dc;
     if (p->tip_bonds && a == 1 && b == 1) {
         /* harmonic tip bond (eq. 12): phi = k (r - r0)^2 / 2, so
          * f = -phi'/r = -k (r - r0)/r and C = (phi'' - phi'/r)/r^2
@@ -426,6 +431,7 @@ static void lj_pair(void *vctx, int i, int j)
         phi = 0.5 * p->k_bond * dr * dr;
         f = -p->k_bond * dr / r;
         C = p->k_bond * p->r_bond / (r * r2);
+        Dc = -3.0 * p->k_bond * p->r_bond / (r * r2 * r2);
     } else {
         if (!(r2 < p->rc * p->rc)) return;
         double eps = p->eps[a][b];
@@ -436,6 +442,8 @@ static void lj_pair(void *vctx, int i, int j)
         phi = 4.0 * eps * (sr6 * sr6 - sr6) - c->shift[a][b];
         f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
         C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
+        /* C = eps (672 s^12 r^-16 - 192 s^6 r^-10); (dC/dr)/r: */
+        Dc = eps * r2i * r2i * r2i * sr6 * (-10752.0 * sr6 + 1920.0);
     }
     double B = -f;
     double Dw = 0.0;
@@ -443,30 +451,41 @@ static void lj_pair(void *vctx, int i, int j)
         w[k] = c->u[k * n + i] - c->u[k * n + j];
         Dw = Dw + D[k] * w[k];
     }
+    double w2 = 0.0;
+    for (int k = 0; k < dim; ++k) w2 = w2 + w[k] * w[k];
     for (int k = 0; k < dim; ++k) {
         c->f[k * n + i] += f * D[k];
         c->f[k * n + j] -= f * D[k];
         double h = B * w[k] + C * Dw * D[k];
         c->hu[k * n + i] += h;
         c->hu[k * n + j] -= h;
+        double t = (C * w2 + Dc * Dw * Dw) * D[k] + 2.0 * C * Dw * w[k];
+        c->tuu[k * n + i] += t;
+        c->tuu[k * n + j] -= t;
     }
     c->e_atom[i] += 0.5 * phi;
     c->e_atom[j] += 0.5 * phi;
     c->e_lj += phi;
 }
 
-/* Slope bias dV1(g) of eq. 14 and its derivative d dV1 / dg. */
-static void bias_switch(const orc_params *p, double g, double *dv, double *dvp)
+/* The switch of eq. 14 (eq. 15 has the same form) of a bias variable v with
+ * critical values lo ("lower") and hi ("upper"), and its derivative d dV/dv:
+ * dV_max at or beyond hi, zero at or beyond lo, dV_max (1 - xi^m)^2 with
+ * xi = (v - hi)/(lo - hi) between them.  With lo < hi (slope, curvature) the
+ * bias is full for large values; with lo > hi (the distance, which grows
+ * towards the dividing surface) for small ones. */
+static void bias_switch(const orc_params *p, double v, double lo, double hi, double *dv, double *dvp)
 {
-    if (g >= p->g_hi) { *dv = p->dv_max; *dvp = 0.0; return; }
-    if (g <= p->g_lo) { *dv = 0.0; *dvp = 0.0; return; }
-    double xi = (g - p->g_hi) / (p->g_lo - p->g_hi);
+    const int up = lo < hi;
+    if (up ? v >= hi : v <= hi) { *dv = p->dv_max; *dvp = 0.0; return; }
+    if (up ? v <= lo : v >= lo) { *dv = 0.0; *dvp = 0.0; return; }
+    double xi = (v - hi) / (lo - hi);
     double xm1 = 1.0;
     for (int q = 0; q < p->m_b - 1; ++q) xm1 *= xi;  /* xi^(m-1) */
     double xm = xm1 * xi;                            /* xi^m */
     double one = 1.0 - xm;
     *dv = p->dv_max * one * one;
-    *dvp = -2.0 * p->m_b * p->dv_max * one * xm1 / (p->g_lo - p->g_hi);
+    *dvp = -2.0 * p->m_b * p->dv_max * one * xm1 / (lo - hi);
 }
 
 static double slider_at(const orc_params *p, int64_t step)
@@ -495,7 +514,8 @@ static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot
     }
 
     pair_ctx c;
-    c.s = s; c.u = u; c.f = f; c.hu = hu; c.e_atom = e_atom; c.e_lj = 0.0;
+    memset(s->tuu, 0, sizeof(double) * nd);
+    c.s = s; c.u = u; c.f = f; c.hu = hu; c.e_atom = e_atom; c.tuu = s->tuu; c.e_lj = 0.0;
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
             double s2 = p->sig[a][b] * p->sig[a][b];
@@ -546,29 +566,51 @@ static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot
         }
     }
 
-    /* d (eq. 7), slope g = grad V . s = -F.u/d (eq. 5). */
-    double d2 = 0.0, G = 0.0;
+    /* d (eq. 7), slope g = grad V . s = -F.u/d (eq. 5), curvature
+     * kappa = s.H s = u.Hu/d^2 (eq. 6). */
+    double d2 = 0.0, G = 0.0, uHu = 0.0;
     for (int i = 0; i < n; ++i) {
         if (s->role[i] == FIXED) continue;
         for (int k = 0; k < dim; ++k) {
             d2 += u[k * n + i] * u[k * n + i];
             G += f[k * n + i] * u[k * n + i];
+            uHu += u[k * n + i] * hu[k * n + i];
         }
     }
     double d = sqrt(d2);
-    double g = (d < 1e-12) ? 0.0 : -G / d;
+    const int has_d = d >= 1e-12;
+    double g = has_d ? -G / d : 0.0;
+    double kappa = has_d ? uHu / d2 : 0.0;
 
-    /* Bias: eq. 13 with dV2 = 0 reduces to dV1 (eq. 14).  Its force is
-     * -dV1'(g) grad g with grad g = (Hu - F - g u/d)/d. */
-    double dv = 0.0, dvp = 0.0;
-    if (p->bias_on) bias_switch(p, g, &dv, &dvp);
+    /* Bias (eq. 13): dV = dV1(v1) + dV2(v2) - dV1 dV2 / dV_max, each dVi the
+     * switch of eq. 14 in its variable (no second variable: dV2 = 0, and
+     * eq. 13 reduces to dV1).  Its force is -grad dV, by the chain rule
+     * -(1 - dV2/dV_max) dV1' grad v1 - (1 - dV1/dV_max) dV2' grad v2. */
+    const double val[3] = {g, kappa, d};
+    double dv1 = 0.0, dvp1 = 0.0, dv2 = 0.0, dvp2 = 0.0;
+    const int v1 = p->bias_var1, v2 = p->bias_var2;
+    if (p->bias_on) {
+        bias_switch(p, val[v1], p->g_lo, p->g_hi, &dv1, &dvp1);
+        if (v2 >= 0) bias_switch(p, val[v2], p->b2_lo, p->b2_hi, &dv2, &dvp2);
+    }
+    double dv = dv1 + dv2 - dv1 * dv2 / p->dv_max;
+    double w1 = dvp1 * (1.0 - dv2 / p->dv_max);   /* d dV / d v1 */
+    double w2 = dvp2 * (1.0 - dv1 / p->dv_max);   /* d dV / d v2 */
+    if (v2 < 0) { dv = dv1; w1 = dvp1; w2 = 0.0; }
+    double dvp = w1;
     for (size_t q = 0; q < nd; ++q) fb[q] = 0.0;
-    if (p->bias_on && d >= 1e-12 && dvp != 0.0) {
+    if (p->bias_on && has_d && (w1 != 0.0 || w2 != 0.0)) {
         for (int i = 0; i < n; ++i) {
             if (s->role[i] == FIXED) continue;
             for (int k = 0; k < dim; ++k) {
-                double grad_g = (hu[k * n + i] - f[k * n + i] - g * u[k * n + i] / d) / d;
-                fb[k * n + i] = -dvp * grad_g;
+                const size_t q = (size_t)k * n + i;
+                double grad[3];
+                grad[0] = (hu[q] - f[q] - g * u[q] / d) / d;
+                grad[1] = (2.0 * hu[q] + s->tuu[q]) / d2 - 2.0 * kappa * u[q] / d2;
+                grad[2] = u[q] / d;
+                double gr = w1 * grad[v1];
+                if (v2 >= 0) gr += w2 * grad[v2];
+                fb[q] = -gr;
             }
         }
     }
@@ -594,6 +636,9 @@ static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot
     sc->g = g;
     sc->dv = dv;
     sc->dvp = dvp;
+    sc->kappa = kappa;
+    sc->dv1 = dv1;
+    sc->dv2 = dv2;
     sc->x_slider = xs;
     sc->x_tip = x_tip;
     sc->f_lat = f_lat;
@@ -822,4 +867,9 @@ int64_t orc_fire(orc_sys *s, double ftol, int64_t maxit)
     s->p = saved;
     s->have_force = 0;
     return it < maxit ? it : -it;
+}
+
+void orc_get_tuu(const orc_sys *s, double *t)
+{
+    memcpy(t, s->tuu, sizeof(double) * (size_t)s->dim * s->n);
 }

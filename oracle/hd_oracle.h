@@ -13,10 +13,15 @@
  *     Sec. 3.1.1 and Sec. 3.2.1), energy-shifted at the cutoff rc;
  *   - the slider drive on the rigid top layer (Sec. 3.1.1), lateral force
  *     F_R = k (x_S - x_T) (eq. 10);
- *   - the local variables d (eq. 7) and slope g = grad V . s (eq. 5) about
- *     the basin minimum r_O, over the generalised position vector;
- *   - the slope bias dV1(g) (eq. 14) combined by eq. 13 with dV2 = 0, and its
- *     force via the Hessian-vector product H u;
+ *   - everything about the basin minimum r_O, over the generalised position
+ *     vector;
+ *   - the local variables d (eq. 7), slope g = grad V . s (eq. 5) and
+ *     curvature kappa = d2V/ds2 = u.Hu/d^2 (eq. 6), any one or two of them
+ *     as bias variables: each through the switch of eq. 14 (eq. 15's form),
+ *     two combined by eq. 13; the bias force from the chain rule, with
+ *     grad g = (Hu - F - g u/d)/d, grad kappa = (2 Hu + T[u,u])/d^2
+ *     - 2 kappa u/d^2 (T[u,u]: third derivatives of V contracted twice with
+ *     u) and grad d = u/d;
  *   - the boosted clock t_hyper = sum dt exp(dV/kT) (eq. 3 as a time average;
  *     eq. 8 fixes what it means for stepped sliding);
  *   - a Langevin BAOAB step (replaces the paper's Nose-Hoover chain);
@@ -53,6 +58,13 @@ typedef struct {
      * tip-tip pairs do not interact */
     int32_t tip_bonds, pad_tb;
     double k_bond, r_bond, r_bond_cut;
+    /* bias variables: bias_var1 enters dV1 (thresholds g_lo, g_hi) and
+     * bias_var2 (-1 = none) dV2 (thresholds b2_lo, b2_hi), combined by
+     * eq. 13.  0 = slope (eq. 5), 1 = curvature (eq. 6), 2 = distance
+     * (eq. 7).  A switch is full on the g_hi side and zero on the g_lo
+     * side, whichever of the two is larger. */
+    int32_t bias_var1, bias_var2;
+    double b2_lo, b2_hi;
 } orc_params;
 
 typedef struct {
@@ -61,7 +73,9 @@ typedef struct {
     double x_slider, x_tip, f_lat;
     double t_md, t_hyper;
     int64_t step;
-    int32_t flags;
+    int32_t flags, pad_f;
+    double kappa;         /* curvature along s (eq. 6); 0 when d ~ 0 */
+    double dv1, dv2;      /* the two switches of eq. 13 */
 } orc_scalars;
 
 /* Opaque simulation state for one system. */
@@ -100,6 +114,8 @@ void orc_set_pair_method(orc_sys *s, int brute);
  * half pair energies. */
 void orc_compute(orc_sys *s, double *f_lj, double *hu, double *f_b, double *f_tot,
                  double *e_atom, orc_scalars *out);
+/* T[u,u] of the last evaluation: the gradient of u.H(r)u at fixed u. */
+void orc_get_tuu(const orc_sys *s, double *t);
 /* Advance nsteps BAOAB steps (bias included when enabled). */
 void orc_step(orc_sys *s, int64_t nsteps);
 void orc_get_positions(const orc_sys *s, double *x);

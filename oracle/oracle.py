@@ -41,6 +41,8 @@ class OrcParams(ctypes.Structure):
         ("dv_max", ctypes.c_double), ("g_lo", ctypes.c_double), ("g_hi", ctypes.c_double),
         ("tip_bonds", ctypes.c_int32), ("pad_tb", ctypes.c_int32),
         ("k_bond", ctypes.c_double), ("r_bond", ctypes.c_double), ("r_bond_cut", ctypes.c_double),
+        ("bias_var1", ctypes.c_int32), ("bias_var2", ctypes.c_int32),
+        ("b2_lo", ctypes.c_double), ("b2_hi", ctypes.c_double),
     ]
 
 
@@ -52,7 +54,8 @@ class OrcScalars(ctypes.Structure):
         ("dv", ctypes.c_double), ("dvp", ctypes.c_double),
         ("x_slider", ctypes.c_double), ("x_tip", ctypes.c_double), ("f_lat", ctypes.c_double),
         ("t_md", ctypes.c_double), ("t_hyper", ctypes.c_double),
-        ("step", ctypes.c_int64), ("flags", ctypes.c_int32),
+        ("step", ctypes.c_int64), ("flags", ctypes.c_int32), ("pad_f", ctypes.c_int32),
+        ("kappa", ctypes.c_double), ("dv1", ctypes.c_double), ("dv2", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -93,6 +96,7 @@ def lib():
         L.orc_get_velocities.argtypes = [vp, dp]
         L.orc_get_scalars.argtypes = [vp, P(OrcScalars)]
         L.orc_get_rigid.argtypes = [vp, dp, dp, dp]
+        L.orc_get_tuu.argtypes = [vp, dp]
         L.orc_fire.argtypes = [vp, ctypes.c_double, ctypes.c_int64]
         L.orc_fire.restype = ctypes.c_int64
         _lib = L
@@ -129,6 +133,10 @@ def params_from_spec(spec, **over) -> OrcParams:
     p.k_bond = float(getattr(spec, "k_bond", 0.0))
     p.r_bond = float(getattr(spec, "r_bond", 0.0))
     p.r_bond_cut = float(getattr(spec, "r_bond_cut", 0.0))
+    p.bias_var1 = int(getattr(spec, "bias_var1", 0))
+    p.bias_var2 = int(getattr(spec, "bias_var2", -1))
+    p.b2_lo = float(getattr(spec, "b2_lo", 0.0))
+    p.b2_hi = float(getattr(spec, "b2_hi", 1.0))
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -219,7 +227,9 @@ class OracleSystem:
         e = np.zeros(self.n)
         sc = OrcScalars()
         lib().orc_compute(self._h, _dp(f), _dp(hu), _dp(fb), _dp(ft), _dp(e), ctypes.byref(sc))
-        return {"f_lj": f, "hu": hu, "f_b": fb, "f_tot": ft, "e_atom": e, **sc.as_dict()}
+        t = np.zeros(nd)
+        lib().orc_get_tuu(self._h, _dp(t))
+        return {"f_lj": f, "hu": hu, "f_b": fb, "f_tot": ft, "e_atom": e, "tuu": t, **sc.as_dict()}
 
     def step(self, nsteps: int):
         lib().orc_step(self._h, int(nsteps))

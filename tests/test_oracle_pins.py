@@ -652,3 +652,183 @@ def test_cone_model_is_the_papers():
     z = np.round(s.pos[2, tip], 6)
     assert np.sum(z == z.min()) == 9
     assert s.k_spring == 10.0 and s.tip_bonds == 1
+
+
+# --------------------------------------------------------------------------
+# Curvature (eq. 6) and distance (eq. 7) as bias variables; eq. 13
+# --------------------------------------------------------------------------
+def _lj_derivs(r):
+    """phi', phi'', phi''' of 4 (r^-12 - r^-6) (eq. 9, eps = sigma = 1)."""
+    return (4.0 * (-12.0 * r ** -13 + 6.0 * r ** -7),
+            4.0 * (156.0 * r ** -14 - 42.0 * r ** -8),
+            4.0 * (-2184.0 * r ** -15 + 336.0 * r ** -9))
+
+
+@pytest.mark.parametrize("bond", [False, True])
+def test_curvature_and_third_derivative_closed_forms(oracle_mod, bond):
+    """One pair, u = a e on atom 0 only (d = a): along the bond
+    kappa = phi''(r) and T[u,u]_0 = a^2 phi'''(r) Delta/r; across it
+    kappa = phi'(r)/r and T[u,u]_0 = a^2 (phi'' - phi'/r) Delta / r^2.
+    For a harmonic tip bond (eq. 12) phi'' = k and phi''' = 0."""
+    a = 1e-3
+    k, r0 = 72.0 * 2.0 ** (-1.0 / 3.0), 2.0 ** (1.0 / 6.0)
+    for r in (1.05, 1.12, 1.3):
+        spec = pair_system(r, types=(1, 1) if bond else (0, 0))
+        if bond:
+            spec.tip_bonds, spec.k_bond, spec.r_bond, spec.r_bond_cut = 1, k, r0, 1.36
+            d1, d2, d3 = k * (r - r0), k, 0.0
+        else:
+            d1, d2, d3 = _lj_derivs(r)
+        Dx = -r                                  # Delta = x_0 - x_1 along x
+        for along in (True, False):
+            rO = spec.pos.copy()
+            rO[0 if along else 1, 0] -= a
+            res = oracle_mod.OracleSystem(spec, rO=rO).compute()
+            assert res["d"] == pytest.approx(a, rel=1e-12)
+            if along:
+                assert res["kappa"] == pytest.approx(d2, rel=1e-9)
+                assert res["tuu"][0, 0] == pytest.approx(a * a * d3 * Dx / r, rel=1e-9, abs=1e-15)
+            else:
+                assert res["kappa"] == pytest.approx(d1 / r, rel=1e-9, abs=1e-12)
+                assert res["tuu"][0, 0] == pytest.approx(a * a * (d2 - d1 / r) * Dx / r ** 2, rel=1e-9)
+            np.testing.assert_allclose(res["tuu"][:, 1], -res["tuu"][:, 0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("maker", [small2d, small3d, small_cone])
+def test_curvature_is_the_second_directional_derivative(oracle_mod, maker):
+    """kappa = d2V/ds2 (eq. 6): along the ray r + h s the direction s stays
+    u/d, so kappa is the derivative of the slope g (eq. 5) there, and the
+    second difference of V."""
+    spec = maker(x_slider=0.1)
+    x = perturbed(spec, 0.05, 21)
+    rO = spec.pos.copy()
+    r = _at(oracle_mod, spec, x, rO)
+    u = x - rO
+    for k in range(spec.dim):
+        if spec.periodic[k]:
+            u[k] -= spec.box[k] * np.round(u[k] / spec.box[k])
+    u[:, spec.role == ROLE_FIXED] = 0.0
+    s = u / math.sqrt((u * u).sum())
+    h = 1e-6
+    gp = _at(oracle_mod, spec, x + h * s, rO)["g"]
+    gm = _at(oracle_mod, spec, x - h * s, rO)["g"]
+    assert r["kappa"] == pytest.approx((gp - gm) / (2 * h), rel=1e-6)
+    # a step small enough that no pair crosses a cutoff inside it (the force
+    # jumps there; in the cone model a pair crosses one within 1e-4)
+    h = 2e-5
+    e0 = _energy(oracle_mod, spec, x, rO)
+    ep = _energy(oracle_mod, spec, x + h * s, rO)
+    em = _energy(oracle_mod, spec, x - h * s, rO)
+    # (a loose check: the rounding of E, ~1e-11 over a few thousand pair
+    # terms, is divided by h^2)
+    assert r["kappa"] == pytest.approx((ep - 2 * e0 + em) / h ** 2, rel=1e-3)
+
+
+@pytest.mark.parametrize("maker", [small2d, small3d, small_cone])
+def test_third_derivative_matches_hessian_difference(oracle_mod, maker):
+    """T[u,u] = grad of u.H(r) u at fixed u: moving one atom and its r_O
+    together keeps u and changes only H."""
+    spec = maker(x_slider=0.1)
+    x = perturbed(spec, 0.05, 23)
+    rO = spec.pos.copy()
+    ref = oracle_mod.OracleSystem(spec, x=x, rO=rO).compute()
+    nf = spec.role != ROLE_FIXED
+
+    def uhu(xx, rr):
+        o = oracle_mod.OracleSystem(spec, x=xx, rO=rr)
+        res = o.compute()
+        return res["kappa"] * res["d"] ** 2
+
+    h = 1e-5
+    mob = np.where(spec.role == ROLE_MOBILE)[0]
+    scale = np.abs(ref["tuu"][:, nf]).max()
+    for i in mob[:: max(1, len(mob) // 8)]:
+        for k in range(spec.dim):
+            e = np.zeros_like(x); e[k, i] = h
+            fd = (uhu(x + e, rO + e) - uhu(x - e, rO - e)) / (2 * h)
+            assert abs(fd - ref["tuu"][k, i]) <= 1e-6 * scale
+
+
+def _var_spec(oracle_mod, maker, x, rO, v1, v2, frac1=0.4, frac2=0.6):
+    """Bias on variables v1 (and v2), thresholds placed so that each variable
+    sits inside its switch; the distance switch runs the other way (lo > hi)."""
+    spec = maker(x_slider=0.1)
+    res = oracle_mod.OracleSystem(spec, x=x, rO=rO).compute()
+    val = {0: res["g"], 1: res["kappa"], 2: res["d"]}
+
+    def thresholds(v, frac):
+        span = 2.0 * abs(val[v]) + 1.0
+        lo, hi = val[v] - frac * span, val[v] + (1.0 - frac) * span
+        return (hi, lo) if v == 2 else (lo, hi)
+
+    spec.bias_on, spec.m_b, spec.dv_max = 1, 2, 0.7
+    spec.bias_var1, spec.bias_var2 = v1, v2
+    spec.g_lo, spec.g_hi = thresholds(v1, frac1)
+    if v2 >= 0:
+        spec.b2_lo, spec.b2_hi = thresholds(v2, frac2)
+    return spec
+
+
+VAR_PAIRS = [(1, -1), (2, -1), (0, 1), (0, 2), (1, 2), (2, 0)]
+
+
+@pytest.mark.parametrize("maker", [small2d, small3d, small_cone], ids=["2d", "3d", "cone"])
+@pytest.mark.parametrize("v1,v2", VAR_PAIRS)
+def test_bias_force_matches_gradient_for_every_variable(oracle_mod, maker, v1, v2):
+    spec0 = maker()
+    x = perturbed(spec0, 0.05, 4)
+    rO = spec0.pos.copy()
+    spec = _var_spec(oracle_mod, maker, x, rO, v1, v2)
+    r = _at(oracle_mod, spec, x, rO)
+    assert 0.0 < r["dv"] < spec.dv_max
+    h = 1e-6
+    scale = np.abs(r["f_b"]).max()
+    assert scale > 0.0
+    mob = np.where(spec.role == ROLE_MOBILE)[0]
+    for i in mob[:: max(1, len(mob) // 8)]:
+        for k in range(spec.dim):
+            xp = x.copy(); xp[k, i] += h
+            xm = x.copy(); xm[k, i] -= h
+            fd = -(_energy(oracle_mod, spec, xp, rO, "bias") - _energy(oracle_mod, spec, xm, rO, "bias")) / (2 * h)
+            assert abs(fd - r["f_b"][k, i]) / scale < 1e-6
+    rig = spec.role == ROLE_RIGID
+    FbR = r["f_b"][:, rig].sum(axis=1)
+    for k in range(spec.dim):
+        xp = x.copy(); xp[k, rig] += h
+        xm = x.copy(); xm[k, rig] -= h
+        fd = -(_energy(oracle_mod, spec, xp, rO, "bias") - _energy(oracle_mod, spec, xm, rO, "bias")) / (2 * h)
+        assert abs(fd - FbR[k]) / scale < 1e-6
+
+
+def test_eq13_plateaus_and_symmetry(oracle_mod):
+    """Eq. 13: dV2 = dV_max gives dV = dV_max with no force whatever dV1 is;
+    dV2 = 0 gives exactly the one-variable bias; the two variables may be
+    swapped; dV stays in [0, dV_max]."""
+    spec0 = small3d()
+    x = perturbed(spec0, 0.05, 8)
+    rO = spec0.pos.copy()
+    one = _var_spec(oracle_mod, small3d, x, rO, 0, -1)
+    r1 = oracle_mod.OracleSystem(one, x=x, rO=rO).compute()
+    assert 0.0 < r1["dv"] < one.dv_max
+    d = r1["d"]
+    for full in (True, False):
+        s = one.copy()
+        s.bias_var2 = 2
+        # distance switch: full for d <= b2_hi, zero for d >= b2_lo
+        s.b2_hi, s.b2_lo = (2 * d + 1, 3 * d + 2) if full else (0.1 * d, 0.5 * d)
+        r = oracle_mod.OracleSystem(s, x=x, rO=rO).compute()
+        if full:
+            assert r["dv2"] == s.dv_max and r["dv"] == s.dv_max
+            assert np.all(r["f_b"] == 0.0)
+        else:
+            assert r["dv2"] == 0.0 and r["dv"] == r1["dv"]
+            np.testing.assert_array_equal(r["f_b"], r1["f_b"])
+    a = _var_spec(oracle_mod, small3d, x, rO, 0, 1)
+    b = a.copy()
+    b.bias_var1, b.bias_var2 = 1, 0
+    b.g_lo, b.g_hi, b.b2_lo, b.b2_hi = a.b2_lo, a.b2_hi, a.g_lo, a.g_hi
+    ra = oracle_mod.OracleSystem(a, x=x, rO=rO).compute()
+    rb = oracle_mod.OracleSystem(b, x=x, rO=rO).compute()
+    assert ra["dv"] == rb["dv"] and 0.0 < ra["dv"] < a.dv_max
+    np.testing.assert_array_equal(ra["f_b"], rb["f_b"])
+    assert ra["dv"] == pytest.approx(ra["dv1"] + ra["dv2"] - ra["dv1"] * ra["dv2"] / a.dv_max, rel=1e-15)
