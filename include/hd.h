@@ -110,8 +110,10 @@ typedef struct { double dt, gamma, kT; uint64_t seed; } hd_thermo_params;
  * x_S(step) = x_slider + v_slider * step * dt). */
 typedef struct { double k_spring, f_normal, x_slider, v_slider; } hd_drive_params;
 
-/* Slope bias of eq. 14: dV_max, thresholds g_lo < g_hi, integer exponent
- * m_b >= 1.  enabled = 0 turns the bias (and its force) off. */
+/* Bias of eq. 14: dV_max, thresholds g_lo < g_hi, integer exponent m_b >= 1.
+ * The switch acts on the slope g unless hd_set_bias_variables picks another
+ * variable (for the distance, g_lo > g_hi).  enabled = 0 turns the bias (and
+ * its force) off. */
 typedef struct { int32_t enabled, m_b; double dv_max, g_lo, g_hi; } hd_bias_params;
 
 /* Per-system scalars after the last evaluation. */
@@ -130,12 +132,21 @@ typedef struct {
     int64_t step;     /* steps taken */
     int32_t flags;    /* HD_FLAG_* bits */
     int32_t n_rebuilds;
+    double kappa;     /* curvature u.Hu/d^2 along s, eq. 6 (systems biased on
+                         it; 0 otherwise) */
+    double dv1, dv2;  /* the two switches combined by eq. 13 (dv2 = 0 with
+                         one variable) */
 } hd_scalars;
 
 enum { HD_FLAG_UNSTABLE = 1, HD_FLAG_NBR_OVERFLOW = 2 };
 
 /* Which per-atom force hd_read_forces returns. */
-enum { HD_FORCE_TOTAL = 0, HD_FORCE_LJ = 1, HD_FORCE_BIAS = 2, HD_HU = 3 };
+/* HD_TUU: T[u,u], the gradient of u.H(r)u at fixed u (third derivatives of
+ * V contracted twice with u), kept for systems biased on the curvature. */
+enum { HD_FORCE_TOTAL = 0, HD_FORCE_LJ = 1, HD_FORCE_BIAS = 2, HD_HU = 3, HD_TUU = 4 };
+
+/* Bias variables (eq. 5-7). */
+enum { HD_BIAS_SLOPE = 0, HD_BIAS_CURVATURE = 1, HD_BIAS_DISTANCE = 2 };
 
 /* Create a context on HIP device `device`.  hip_stream is a hipStream_t to
  * order work on (for example torch.cuda.current_stream().cuda_stream) or NULL
@@ -173,6 +184,24 @@ hd_status hd_add_system(hd_ctx *ctx, const hd_system_desc *desc, const hd_lj_par
  * systems run on the grid kernels (never LDS-resident). */
 hd_status hd_set_tip_bonds(hd_ctx *ctx, int32_t sys, int32_t enabled, double k_bond, double r_bond,
                            double r_cut);
+
+/* Bias variables of system `sys` (Sec. 2.2): var1 is the variable the switch
+ * of hd_bias_params acts on, var2 (-1: none) a second one with its own
+ * critical values lo2, hi2 (same dV_max and m_b), the two combined by
+ * eq. 13: dV = dV1 + dV2 - dV1 dV2 / dV_max.  Variables: HD_BIAS_SLOPE
+ * g = grad V . s (eq. 5), HD_BIAS_CURVATURE kappa = d2V/ds2 = u.Hu/d^2
+ * (eq. 6), HD_BIAS_DISTANCE d = |r - r_O| (eq. 7).  A switch is dV_max at or
+ * beyond its upper value and zero at or beyond its lower one; for the slope
+ * and the curvature lower < upper, for the distance lower > upper (the bias
+ * is full near r_O and vanishes as d grows).  The bias force is -grad dV by
+ * the chain rule, with grad g = (Hu - F - g u/d)/d,
+ * grad kappa = (2 Hu + T[u,u])/d^2 - 2 kappa u/d^2 and grad d = u/d.
+ * Default: the slope alone.  Before hd_finalize only (HD_E_STATE after);
+ * HD_E_ARG for an unknown variable, var2 == var1, critical values in the
+ * wrong order (also those already set by hd_set_bias) or, with two
+ * variables, dv_max = 0.  Systems with any other choice than the slope
+ * alone run on the grid kernels (never LDS-resident). */
+hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t var2, double lo2, double hi2);
 
 /* Basin minimum r_O (eq. 7), SoA [dim][n]. */
 hd_status hd_set_reference(hd_ctx *ctx, int32_t sys, const double *rO);

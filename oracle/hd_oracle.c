@@ -593,10 +593,12 @@ static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot
         bias_switch(p, val[v1], p->g_lo, p->g_hi, &dv1, &dvp1);
         if (v2 >= 0) bias_switch(p, val[v2], p->b2_lo, p->b2_hi, &dv2, &dvp2);
     }
-    double dv = dv1 + dv2 - dv1 * dv2 / p->dv_max;
-    double w1 = dvp1 * (1.0 - dv2 / p->dv_max);   /* d dV / d v1 */
-    double w2 = dvp2 * (1.0 - dv1 / p->dv_max);   /* d dV / d v2 */
-    if (v2 < 0) { dv = dv1; w1 = dvp1; w2 = 0.0; }
+    double dv = dv1, w1 = dvp1, w2 = 0.0;
+    if (p->bias_on && v2 >= 0) {
+        dv = dv1 + dv2 - dv1 * dv2 / p->dv_max;
+        w1 = dvp1 * (1.0 - dv2 / p->dv_max);   /* d dV / d v1 */
+        w2 = dvp2 * (1.0 - dv1 / p->dv_max);   /* d dV / d v2 */
+    }
     double dvp = w1;
     for (size_t q = 0; q < nd; ++q) fb[q] = 0.0;
     if (p->bias_on && has_d && (w1 != 0.0 || w2 != 0.0)) {

@@ -9,8 +9,13 @@ namespace hdk {
 enum : int { ROLE_MOBILE = 0, ROLE_FIXED = 1, ROLE_RIGID = 2 };
 enum : int { FLAG_UNSTABLE = 1, FLAG_NBR_OVERFLOW = 2 };
 // Per-system sums: E, d2, G, sumF_R[3], sumHu_R[3], sumU_R[3], and the count
-// of atoms whose LJ force is non-finite or above kForceLimit.
-enum : int { NRED = 13 };
+// of atoms whose LJ force is non-finite or above kForceLimit.  The grid
+// kernels' tile partials add u.Hu and sumT_R[3] (the third-derivative vector
+// T[u,u] over the rigid layer) for systems biased on the curvature.
+enum : int { NRED = 13, NPART = 17 };
+// Bias variables (eq. 5-7) and the extra pair-pass terms a plan compiles in.
+enum : int { BVAR_SLOPE = 0, BVAR_CURV = 1, BVAR_DIST = 2 };
+enum : int { EXT_BONDS = 1, EXT_CURV = 2 };
 constexpr double kForceLimit2 = 1e12;  // (1e6 eps/sigma)^2
 
 // Read-only description of one system (uploaded at finalize / parameter
@@ -49,6 +54,12 @@ struct SysDesc {
   int32_t tip_bonds, pad1;
   double k_bond, r_bond, rbc2;
   float k_bond_f, r_bond_f, rbc2_f, pad2;
+  // bias variables: bias_var1 drives the switch with g_lo/g_hi, bias_var2
+  // (-1: none) a second one with b2_lo/b2_hi, combined by eq. 13.  gen_bias:
+  // anything but the slope alone (grid kernels only); curv: the curvature is
+  // one of them (the pair pass then accumulates T[u,u])
+  int32_t bias_var1, bias_var2, gen_bias, curv;
+  double b2_lo, b2_hi, inv_glh2;
 };
 
 // Mutable per-system state.
@@ -59,6 +70,7 @@ struct SysState {
   double e_lj, v_drive, e_pot, e_kin, d, g, dv, dvp, x_slider, x_tip, f_lat;
   int32_t flags, n_rebuilds;
   int32_t rebuild, pad1;
+  double kappa, dv1, dv2;
 };
 
 struct Arrays {
@@ -87,6 +99,7 @@ struct Arrays {
   // (double 3) of each sorted position, written by the cell sort, so a
   // stencil row's candidates are consecutive 32-byte records
   double *brec;                           // [ntot][4]
+  double *tuu;                            // [3][ntot] T[u,u] (curvature bias)
 };
 
 constexpr int kRecDoubles = 8;
@@ -209,17 +222,23 @@ __device__ __forceinline__ void noise(uint64_t seed, int64_t step, uint32_t part
   else normals_n<NZ>(seed, step, particle, 0u, z);
 }
 
-// Slope bias of eq. 14 and its derivative in g.
-__device__ __forceinline__ void bias_switch(const SysDesc &D, double g, double &dv, double &dvp) {
-  if (g >= D.g_hi) { dv = D.dv_max; dvp = 0.0; return; }
-  if (g <= D.g_lo) { dv = 0.0; dvp = 0.0; return; }
-  const double xi = (g - D.g_hi) * D.inv_glh;
+// The switch of eq. 14 (eq. 15 has the same form) of a bias variable v with
+// critical values lo and hi (inv = 1/(lo - hi)) and its derivative in v:
+// dV_max at or beyond hi, zero at or beyond lo, dV_max (1 - xi^m)^2 with
+// xi = (v - hi)/(lo - hi) between.  With lo < hi (slope, curvature) the bias
+// is full for large values, with lo > hi (distance) for small ones.
+__device__ __forceinline__ void bias_switch(const SysDesc &D, double v, double lo, double hi, double inv,
+                                            double &dv, double &dvp) {
+  const bool up = lo < hi;
+  if (up ? v >= hi : v <= hi) { dv = D.dv_max; dvp = 0.0; return; }
+  if (up ? v <= lo : v >= lo) { dv = 0.0; dvp = 0.0; return; }
+  const double xi = (v - hi) * inv;
   double xm1 = 1.0;
   for (int q = 0; q < D.m_b - 1; ++q) xm1 *= xi;
   const double xm = xm1 * xi;
   const double one = 1.0 - xm;
   dv = D.dv_max * one * one;
-  dvp = -2.0 * D.m_b * D.dv_max * one * xm1 * D.inv_glh;
+  dvp = -2.0 * D.m_b * D.dv_max * one * xm1 * inv;
 }
 
 // Per-system scalars derived from the reduced sums (LJ part) and the rigid
@@ -231,10 +250,14 @@ struct Scal {
   double sumFb[3];   // bias force summed over rigid atoms
   double bad;        // atoms with a non-finite or runaway force
   double bias_a, bias_b;  // bias force = bias_a (Hu - F - bias_b u): -dV'/d, g/d
+  // general bias (eq. 13 over any of slope, curvature, distance): the bias
+  // force is cH Hu + cF F + cU u + cT T[u,u] where live
+  double kappa, dv1, dv2, cH, cF, cU, cT;
+  int live;
 };
 
-template <int DIM>
-__device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums[NRED],
+template <int DIM, bool GEN = false>
+__device__ __forceinline__ void eval_scalars(const SysDesc &D, const double *sums,
                                              const double XR[3], int64_t step, Scal &S) {
   constexpr int dim = DIM;
   S.xs = D.x_slider + D.v_slider * ((double)step * D.dt);
@@ -279,8 +302,65 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double sums
   S.d = d2 * inv_d;
   const bool has_d = S.d >= 1e-12;
   S.g = has_d ? -G * inv_d : 0.0;
+  S.kappa = 0.0; S.dv2 = 0.0;
+  S.cH = S.cF = S.cU = S.cT = 0.0;
+  S.live = 0;
+  if constexpr (GEN) {
+    if (D.gen_bias) {
+      // curvature kappa = u.Hu/d^2 (eq. 6), the drive's Hessian included
+      double uHu = sums[13];
+      if (D.n_rigid > 0) {
+        constexpr int nspring = dim == 3 ? 2 : 1;
+#pragma unroll
+        for (int k = 0; k < nspring; ++k) uHu += S.hud[k] * sums[9 + k];
+      }
+      const double inv_d2 = inv_d * inv_d;
+      S.kappa = has_d ? uHu * inv_d2 : 0.0;
+      double dv1 = 0.0, p1 = 0.0, dv2 = 0.0, p2 = 0.0;
+      const int v1 = D.bias_var1, v2 = D.bias_var2;
+      auto value = [&](int v) { return v == BVAR_SLOPE ? S.g : (v == BVAR_CURV ? S.kappa : S.d); };
+      if (D.bias_on) {
+        bias_switch(D, value(v1), D.g_lo, D.g_hi, D.inv_glh, dv1, p1);
+        if (v2 >= 0) bias_switch(D, value(v2), D.b2_lo, D.b2_hi, D.inv_glh2, dv2, p2);
+      }
+      // eq. 13 and the partial derivatives of dV in the two variables
+      double w1 = p1, w2 = 0.0;
+      S.dv = dv1;
+      if (D.bias_on && v2 >= 0) {
+        S.dv = dv1 + dv2 - dv1 * dv2 / D.dv_max;
+        w1 = p1 * (1.0 - dv2 / D.dv_max);
+        w2 = p2 * (1.0 - dv1 / D.dv_max);
+      }
+      S.dv1 = dv1; S.dv2 = dv2; S.dvp = w1;
+      S.live = (D.bias_on && has_d && (w1 != 0.0 || w2 != 0.0)) ? 1 : 0;
+      // -dV'(v) grad v for each variable, grad g = (Hu - F - g u/d)/d,
+      // grad kappa = (2 Hu + T)/d^2 - 2 kappa u/d^2, grad d = u/d
+      double cH = 0.0, cF = 0.0, cU = 0.0, cT = 0.0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int v = q == 0 ? v1 : v2;
+        const double w = q == 0 ? w1 : w2;
+        if (v == BVAR_SLOPE) { cH -= w * inv_d; cF += w * inv_d; cU += w * S.g * inv_d2; }
+        else if (v == BVAR_CURV) { cH -= 2.0 * w * inv_d2; cT -= w * inv_d2; cU += 2.0 * w * S.kappa * inv_d2; }
+        else if (v == BVAR_DIST) { cU -= w * inv_d; }
+      }
+      if (S.live) { S.cH = cH; S.cF = cF; S.cU = cU; S.cT = cT; }
+      S.bias_a = 0.0; S.bias_b = 0.0;
+      if (S.live && D.n_rigid > 0) {
+        const double nR = (double)D.n_rigid;
+#pragma unroll
+        for (int k = 0; k < dim; ++k) {
+          const double sumHu = sums[6 + k] + nR * S.hud[k];
+          const double sumF = sums[3 + k] + S.Fd[k];
+          S.sumFb[k] = S.cH * sumHu + S.cF * sumF + S.cU * sums[9 + k] + S.cT * sums[14 + k];
+        }
+      }
+      return;
+    }
+  }
   S.dv = 0.0; S.dvp = 0.0;
-  if (D.bias_on) bias_switch(D, S.g, S.dv, S.dvp);
+  if (D.bias_on) bias_switch(D, S.g, D.g_lo, D.g_hi, D.inv_glh, S.dv, S.dvp);
+  S.dv1 = S.dv;
   S.bias_a = has_d ? -S.dvp * inv_d : 0.0;
   S.bias_b = has_d ? S.g * inv_d : 0.0;
   if (D.bias_on && has_d && S.dvp != 0.0 && D.n_rigid > 0) {
@@ -316,18 +396,19 @@ struct Comp {  // Kahan compensated float sum: s - c is the running total
 
 template <typename T> struct PairAcc;
 
+// F, H u, the half pair energy and (curvature bias only) T[u,u]
 template <> struct PairAcc<double> {
-  double F[3], H[3], e;
+  double F[3], H[3], X[3], e;
   __device__ __forceinline__ void init() {
-    for (int k = 0; k < 3; ++k) { F[k] = 0.0; H[k] = 0.0; }
+    for (int k = 0; k < 3; ++k) { F[k] = 0.0; H[k] = 0.0; X[k] = 0.0; }
     e = 0.0;
   }
 };
 
 template <> struct PairAcc<float> {
-  Comp F[3], H[3], e;
+  Comp F[3], H[3], X[3], e;
   __device__ __forceinline__ void init() {
-    for (int k = 0; k < 3; ++k) { F[k].init(); H[k].init(); }
+    for (int k = 0; k < 3; ++k) { F[k].init(); H[k].init(); X[k].init(); }
     e.init();
   }
 };
@@ -383,8 +464,9 @@ __device__ __forceinline__ T inv_sqrt(T q) {
   }
 }
 
+// With the curvature bias also Dc = (dC/dr)/r = -3 k r0 / r^5.
 template <typename T>
-__device__ __forceinline__ void bond_terms(const LJRow<T> &R, double r2, T &f, T &C, T &e) {
+__device__ __forceinline__ void bond_terms(const LJRow<T> &R, double r2, T &f, T &C, T &e, T &Dc) {
   const bool in = r2 < (double)R.rbc2;
   const T m = in ? T(1) : T(0);
   const T q = in ? (T)r2 : T(1);
@@ -393,21 +475,25 @@ __device__ __forceinline__ void bond_terms(const LJRow<T> &R, double r2, T &f, T
   f = -R.kb * dr * ir * m;
   C = R.kb * R.rb * (ir * ir * ir) * m;
   e = T(0.5) * R.kb * dr * dr * m;
+  Dc = T(-3) * C * ir * ir;
 }
 
 // One neighbour's contribution to F_i, (H u)_i and the half pair energy.
 // dx = x_i - x_j (float64, minimum image), r2 its exactly rounded square
 // norm.  The term is evaluated branch-free; a neighbour that is not `live`
 // (outside rc) contributes exactly zero.  Tip-tip pairs of a model with tip
-// bonds take the bond instead of the LJ terms (compiled in with BONDS only:
-// kernels that never see such a model keep the LJ-only registers).
-template <int DIM, typename T, bool BONDS = false>
+// bonds take the bond instead of the LJ terms (compiled in with EXT_BONDS
+// only: kernels that never see such a model keep the LJ-only registers).
+// With EXT_CURV also the pair's share of T[u,u], the gradient of u.H(r)u at
+// fixed u: (C |w|^2 + Dc (dx.w)^2) dx + 2 C (dx.w) w with Dc = (dC/dr)/r.
+template <int DIM, typename T, int EXT = 0>
 __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, const double dx[3], double r2,
                                           const T ui[3], const T uj[3], PairAcc<T> &acc) {
+  constexpr bool BONDS = (EXT & EXT_BONDS) != 0, CURV = (EXT & EXT_CURV) != 0;
   if constexpr (sizeof(T) == 8) {
-    double f, C, e;
+    double f, C, e, Dc = 0.0;
     if (BONDS && R.bond && tj) {
-      bond_terms<double>(R, r2, f, C, e);
+      bond_terms<double>(R, r2, f, C, e, Dc);
     } else {
       const double m = live ? 1.0 : 0.0;
       const double r2i = 1.0 / (live ? r2 : 1.0);
@@ -417,6 +503,7 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
       C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
       e = 4.0 * eps * (sr6 * sr6 - sr6) - (tj ? R.shift[1] : R.shift[0]) * m;
+      if constexpr (CURV) Dc = eps * r2i * r2i * r2i * sr6 * (-10752.0 * sr6 + 1920.0);
     }
     double w[3], Dw = 0.0;
 #pragma unroll
@@ -431,10 +518,18 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       acc.H[k] += CDw * dx[k] - f * w[k];
     }
     acc.e += 0.5 * e;
+    if constexpr (CURV) {
+      double w2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) w2 += w[k] * w[k];
+      const double a = C * w2 + Dc * Dw * Dw, b = 2.0 * CDw;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) acc.X[k] += a * dx[k] + b * w[k];
+    }
   } else {
-    float f, C, e;
+    float f, C, e, Dc = 0.0f;
     if (BONDS && R.bond && tj) {
-      bond_terms<float>(R, r2, f, C, e);
+      bond_terms<float>(R, r2, f, C, e, Dc);
     } else {
       const float m = live ? 1.0f : 0.0f;
       const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
@@ -445,6 +540,7 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       f = epsr * (48.0f * sr6 - 24.0f);
       C = epsr * r2i * (672.0f * sr6 - 192.0f);
       e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
+      if constexpr (CURV) Dc = epsr * r2i * r2i * (-10752.0f * sr6 + 1920.0f);
     }
     float d[3], w[3], Dw = 0.0f;
 #pragma unroll
@@ -460,6 +556,14 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
     }
     acc.e.add(0.5f * e);
+    if constexpr (CURV) {
+      float w2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) w2 = __builtin_fmaf(w[k], w[k], w2);
+      const float a = __builtin_fmaf(Dc * Dw, Dw, C * w2), b = 2.0f * CDw;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) acc.X[k].add(__builtin_fmaf(a, d[k], b * w[k]));
+    }
   }
 }
 
@@ -471,7 +575,8 @@ __device__ __forceinline__ void pair_vals_f(const LJRow<float> &R, int tj, bool 
                                             float &e) {
   float f, C;
   if (BONDS && R.bond && tj) {
-    bond_terms<float>(R, r2, f, C, e);
+    float Dc;
+    bond_terms<float>(R, r2, f, C, e, Dc);
   } else {
     const float m = live ? 1.0f : 0.0f;
     const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
@@ -556,7 +661,7 @@ __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int
 // Pair pass of the atom at sorted position p over its full list (entries
 // hold sorted positions), neighbours read from the packed records; same
 // arithmetic as pair_atom.
-template <int DIM, typename T, bool BONDS = false>
+template <int DIM, typename T, int EXT = 0>
 __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
                                               const double xi[3], const T ui[3], int ti,
                                               PairAcc<T> &acc, int q0 = 0, int qstep = 1) {
@@ -578,7 +683,7 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; }
     const double r2 = pair_disp<DIM>(D, xi, xj, dx);
-    pair_term<DIM, T, BONDS>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
+    pair_term<DIM, T, EXT>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
   }
 }
 

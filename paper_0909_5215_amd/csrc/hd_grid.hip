@@ -482,9 +482,10 @@ __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__
 // s + LPA, ...; the lanes' sums are then combined by quad permutes (a + b on
 // both lanes, the same bits).  More wavefronts per tile hide more gather
 // latency.
-template <int DIM, typename T, int LPA, bool BONDS>
+template <int DIM, typename T, int LPA, int EXT>
 __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int tile_index) {
-  __shared__ double red[NRED * 16];
+  constexpr bool CURV = (EXT & EXT_CURV) != 0;
+  __shared__ double red[NPART * 16];
   const int64_t N = A.ntot;
   double sums[NRED];
 #pragma unroll
@@ -505,12 +506,15 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
   }
   PairAcc<T> acc;
   acc.init();
-  if (valid) pair_atom_rec<DIM, T, BONDS>(D, A, p, xi, ui, tr & 1, acc, sub, LPA);
-  double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, e;
+  if (valid) pair_atom_rec<DIM, T, EXT>(D, A, p, xi, ui, tr & 1, acc, sub, LPA);
+  double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, X[3] = {0, 0, 0}, e;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     if constexpr (sizeof(T) == 8) { F[k] = acc.F[k]; H[k] = acc.H[k]; }
     else { F[k] = acc.F[k].get(); H[k] = acc.H[k].get(); }
+    if constexpr (CURV) {
+      if constexpr (sizeof(T) == 8) X[k] = acc.X[k]; else X[k] = acc.X[k].get();
+    }
   }
   if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
   // every lane takes part in the permutes (no divergence around them)
@@ -518,12 +522,21 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { F[k] += dpp_mov_f64<0xb1>(F[k]); H[k] += dpp_mov_f64<0xb1>(H[k]); }
     e += dpp_mov_f64<0xb1>(e);   // lanes 0<->1, 2<->3
+    if constexpr (CURV) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) X[k] += dpp_mov_f64<0xb1>(X[k]);
+    }
   }
   if constexpr (LPA >= 4) {
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { F[k] += dpp_mov_f64<0x4e>(F[k]); H[k] += dpp_mov_f64<0x4e>(H[k]); }
     e += dpp_mov_f64<0x4e>(e);   // lanes 0<->2, 1<->3
+    if constexpr (CURV) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) X[k] += dpp_mov_f64<0x4e>(X[k]);
+    }
   }
+  double ext[4] = {0.0, 0.0, 0.0, 0.0};   // u.Hu, sum over the rigid layer of T
   static_assert(LPA == 1 || LPA == 2 || LPA == 4, "one, two or four lanes per atom");
   if (valid && sub == 0) {
     const int64_t a = D.off + A.cell_atoms[D.off + p];
@@ -545,6 +558,18 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
     if (role == ROLE_RIGID) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) { sums[3 + k] = F[k]; sums[6 + k] = H[k]; sums[9 + k] = u64[k]; }
+    }
+    if constexpr (CURV) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) A.tuu[k * N + a] = X[k];
+      if (role != ROLE_FIXED) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ext[0] += u64[k] * H[k];
+      }
+      if (role == ROLE_RIGID) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ext[1 + k] = X[k];
+      }
     }
   }
   // the tile's sums: a reduce-scatter butterfly within each wavefront (the
@@ -570,11 +595,16 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
       red[(lane - 1) * 16 + wave] = 0.0;   // the rigid-layer slots 3..11
     }
   }
+  if constexpr (CURV) {
+    const double tot = wave_sums_scatter<4>(ext, lane);
+    if (lane < 4) red[(NRED + wave_scatter_index<4>(lane)) * 16 + wave] = tot;
+  }
   __syncthreads();
-  if (threadIdx.x < NRED) {
+  if (threadIdx.x < NPART) {
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[threadIdx.x * 16 + w];
-    A.partials[(int64_t)tile_index * NRED + threadIdx.x] = s;
+    if (CURV || threadIdx.x < NRED)
+      for (int w = 0; w < nw; ++w) s += red[threadIdx.x * 16 + w];
+    A.partials[(int64_t)tile_index * NPART + threadIdx.x] = s;
   }
 }
 
@@ -586,16 +616,16 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
 template <int DIM>
 __device__ void reduce_system(const SysDesc &D, SysState &st, const Arrays &A, int s, int first_tile,
                               int ntiles_s, GridScal *gs, bool compute_only) {
-  __shared__ double red[NRED * 16];
-  double tot[NRED];
+  __shared__ double red[NPART * 16];
+  double tot[NPART];
 #pragma unroll
-  for (int q = 0; q < NRED; ++q) tot[q] = 0.0;
+  for (int q = 0; q < NPART; ++q) tot[q] = 0.0;
   for (int k = threadIdx.x; k < ntiles_s; k += blockDim.x) {
-    const double *p = A.partials + (int64_t)(first_tile + k) * NRED;
+    const double *p = A.partials + (int64_t)(first_tile + k) * NPART;
 #pragma unroll
-    for (int q = 0; q < NRED; ++q) tot[q] += p[q];
+    for (int q = 0; q < NPART; ++q) tot[q] += p[q];
   }
-  block_sum<NRED>(tot, red);
+  block_sum<NPART>(tot, red);
   if (threadIdx.x == 0) {
     double XRn[3] = {st.XR[0], st.XR[1], st.XR[2]};
     double VRn[3] = {st.VR[0], st.VR[1], st.VR[2]};
@@ -604,7 +634,7 @@ __device__ void reduce_system(const SysDesc &D, SysState &st, const Arrays &A, i
     }
     const int64_t estep = compute_only ? st.step : st.step + 1;
     Scal S;
-    eval_scalars<DIM>(D, tot, XRn, estep, S);
+    eval_scalars<DIM, true>(D, tot, XRn, estep, S);
     double FR[3] = {0, 0, 0};
     for (int k = 0; k < DIM; ++k) FR[k] = tot[3 + k] + S.Fd[k] + S.sumFb[k];
     if (!compute_only) {
@@ -616,6 +646,7 @@ __device__ void reduce_system(const SysDesc &D, SysState &st, const Arrays &A, i
     for (int k = 0; k < DIM; ++k) st.FR[k] = FR[k];
     st.e_lj = S.e_lj; st.v_drive = S.v_drive; st.e_pot = S.e_pot;
     st.d = S.d; st.g = S.g; st.dv = S.dv; st.dvp = S.dvp;
+    st.kappa = S.kappa; st.dv1 = S.dv1; st.dv2 = S.dv2;
     st.x_slider = S.xs; st.x_tip = S.x_tip; st.f_lat = S.f_lat;
     if (!isfinite(S.e_pot) || S.bad > 0.0) st.flags |= FLAG_UNSTABLE;
     gs[s].S = S;
@@ -638,16 +669,18 @@ __global__ __launch_bounds__(256) void kg_reduce(const SysDesc *__restrict__ des
   else reduce_system<3>(D, states[s], A, s, first, nts, gs, compute_only != 0);
 }
 
-// BONDS: the plan holds a model with harmonic tip bonds (a separate
-// instantiation, so that LJ-only plans keep their register budget).
-template <typename T, int LPA, bool BONDS>
+// EXT: the extra pair terms the plan's systems need -- EXT_BONDS for models
+// with harmonic tip bonds, EXT_CURV for a curvature bias (T[u,u]) -- each
+// combination a separate instantiation, so that LJ-only plans keep their
+// register budget.
+template <typename T, int LPA, int EXT>
 __global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ descs, Arrays A,
                                                  const Tile *__restrict__ tiles, int ntiles) {
   const int ti = xcd_tile(blockIdx.x, ntiles);
   const Tile t = tiles[ti];
   const SysDesc &D = descs[t.sys];
-  if (D.dim == 2) pairs_tile<2, T, LPA, BONDS>(D, A, t, ti);
-  else pairs_tile<3, T, LPA, BONDS>(D, A, t, ti);
+  if (D.dim == 2) pairs_tile<2, T, LPA, EXT>(D, A, t, ti);
+  else pairs_tile<3, T, LPA, EXT>(D, A, t, ti);
 }
 
 // ---- bias force, total force and final B -----------------------------------
@@ -664,7 +697,13 @@ __global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ desc
     double f = A.flj[k * N + a], h = A.hu[k * N + a], fb = 0.0;
     if (role != ROLE_FIXED) {
       if (role == ROLE_RIGID) { f += S.Fd[k] * D.inv_nR; h += S.hud[k]; }
-      if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0) {
+      if (D.gen_bias) {
+        if (S.live) {
+          const double uk = minimg(A.x[k * N + a] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+          fb = S.cH * h + S.cF * f + S.cU * uk;
+          if (D.curv) fb += S.cT * A.tuu[k * N + a];
+        }
+      } else if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0) {
         const double uk = minimg(A.x[k * N + a] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
         fb = S.bias_a * (h - f - S.bias_b * uk);
       }
@@ -735,7 +774,11 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
   const int lpa = B <= 256 ? 4 : (B <= 512 ? 2 : 1);
 #define HD_PAIRS(TT, L, BB) \
   hipLaunchKernelGGL((kg_pairs<TT, L, BB>), dim3(nt), dim3(L * B), 0, stream, descs, A, P.tiles, nt)
-#define HD_PAIRS_B(TT, L) do { if (P.any_bonds) HD_PAIRS(TT, L, true); else HD_PAIRS(TT, L, false); } while (0)
+#define HD_PAIRS_B(TT, L)                                                                        \
+  do {                                                                                           \
+    if (P.any_curv) { if (P.any_bonds) HD_PAIRS(TT, L, 3); else HD_PAIRS(TT, L, 2); }            \
+    else { if (P.any_bonds) HD_PAIRS(TT, L, 1); else HD_PAIRS(TT, L, 0); }                       \
+  } while (0)
   if (prec == 0) {
     if (lpa == 4) HD_PAIRS_B(double, 4); else if (lpa == 2) HD_PAIRS_B(double, 2); else HD_PAIRS_B(double, 1);
   } else {

@@ -62,6 +62,7 @@ struct GridPlan {
   int max_ncell;           // largest cell count among the covered systems
   void *gscal;             // device, per-system scalars of the last evaluation
   int any_bonds;           // some covered system has harmonic tip bonds
+  int any_curv;            // some covered system is biased on the curvature
 };
 
 size_t grid_scal_bytes();

@@ -39,11 +39,21 @@ struct SysHost {
   hd_bias_params bias{};
   int tip_bonds = 0;
   double k_bond = 0.0, r_bond = 0.0, r_bond_cut = 0.0;
+  // bias variables (hd_set_bias_variables): var1 drives the switch of
+  // hd_bias_params, var2 (-1: none) a second one, combined by eq. 13
+  int bias_var1 = HD_BIAS_SLOPE, bias_var2 = -1;
+  double b2_lo = 0.0, b2_hi = 1.0;
   int n_rigid = 0, first_rigid = -1;
   double XR[3] = {0, 0, 0}, XR0[3] = {0, 0, 0};
   bool init_vel = false;
   std::vector<double> vel;  // explicit velocities set before finalize
 };
+
+// Systems the LDS-resident and one-workgroup kernels do not cover: models
+// with tip bonds and biases beyond the slope alone.
+static bool grid_only(const SysHost &h) {
+  return h.tip_bonds || h.bias_var1 != HD_BIAS_SLOPE || h.bias_var2 >= 0;
+}
 
 struct Plan {
   std::vector<int> ids;  // systems of the plan
@@ -251,6 +261,13 @@ void fill_desc(const hd_ctx *ctx, const SysHost &s, SysDesc &D) {
   D.g_hi = s.bias.g_hi;
   D.inv_kT = 1.0 / s.th.kT;
   D.inv_glh = (s.bias.g_lo != s.bias.g_hi) ? 1.0 / (s.bias.g_lo - s.bias.g_hi) : 0.0;
+  D.bias_var1 = s.bias_var1;
+  D.bias_var2 = s.bias_var2;
+  D.gen_bias = (s.bias_var1 != HD_BIAS_SLOPE || s.bias_var2 >= 0) ? 1 : 0;
+  D.curv = (s.bias_var1 == HD_BIAS_CURVATURE || s.bias_var2 == HD_BIAS_CURVATURE) ? 1 : 0;
+  D.b2_lo = s.b2_lo;
+  D.b2_hi = s.b2_hi;
+  D.inv_glh2 = (s.b2_lo != s.b2_hi) ? 1.0 / (s.b2_lo - s.b2_hi) : 0.0;
   D.inv_nR = s.n_rigid > 0 ? 1.0 / s.n_rigid : 0.0;
   D.k_nR2 = s.n_rigid > 0 ? s.dr.k_spring / ((double)s.n_rigid * s.n_rigid) : 0.0;
   (void)ctx;
@@ -343,6 +360,7 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
     }
     max_ncell = std::max(max_ncell, ctx->h_desc[s].ncell);
     if (ctx->sys[s].tip_bonds) P.gp.any_bonds = 1;
+    if (ctx->h_desc[s].curv) P.gp.any_curv = 1;
   }
   hd_status st = dalloc(ctx, &P.d_tiles, tiles.size(), true);
   if (st != HD_OK) return st;
@@ -529,8 +547,9 @@ hd_status build_schedule(hd_ctx *ctx) {
     for (int s = 0; s < S; ++s) {
       const SysHost &h = ctx->sys[s];
       const int maxnb = h.dim == 2 ? ctx->maxnb2 : ctx->maxnb3;
-      // models with tip bonds run on the grid kernels only
-      const bool ok = h.n <= 1024 && maxnb <= 32767 && !h.tip_bonds &&
+      // models with tip bonds or a bias beyond the slope alone run on the
+      // grid kernels only
+      const bool ok = h.n <= 1024 && maxnb <= 32767 && !grid_only(h) &&
                       hdk::small_lds_bytes(h.dim, prec, h.n, maxnb, ctx->h_desc[s].ncell) <= budget &&
                       !ctx->small_disabled;
       if (ok) cand.push_back(s);
@@ -565,7 +584,7 @@ hd_status build_schedule(hd_ctx *ctx) {
         hd_ctx::Group G;
         G.dim = d + 2;
         for (int s : ctx->big_ids)
-          if (ctx->sys[s].dim == d + 2 && !ctx->sys[s].tip_bonds) G.ids.push_back(s);
+          if (ctx->sys[s].dim == d + 2 && !grid_only(ctx->sys[s])) G.ids.push_back(s);
         if (!G.ids.empty()) ctx->groups.push_back(G);
       }
     }
@@ -588,10 +607,10 @@ hd_status build_schedule(hd_ctx *ctx) {
     }
   }
   // grid plans (with the one-workgroup kernel for the large systems, the
-  // models with tip bonds still take the grid)
+  // models with tip bonds or a general bias still take the grid)
   std::vector<int> grid_big;
   for (int s : ctx->big_ids)
-    if (!ctx->persistent_big || ctx->sys[s].tip_bonds) grid_big.push_back(s);
+    if (!ctx->persistent_big || grid_only(ctx->sys[s])) grid_big.push_back(s);
   if (ctx->exec == HD_EXEC_BATCHED && !grid_big.empty()) {
     ctx->plans.resize(1);
     if ((st = build_plan(ctx, grid_big, ctx->plans[0])) != HD_OK) return st;
@@ -608,7 +627,7 @@ hd_status build_schedule(hd_ctx *ctx) {
   {
     int max_tiles = 1;
     for (auto &P : ctx->plans) max_tiles = std::max(max_tiles, P.gp.ntiles);
-    ALLOC(A.partials, (size_t)max_tiles * hdk::NRED);
+    ALLOC(A.partials, (size_t)max_tiles * hdk::NPART);
   }
   if (!ctx->plans.empty()) {
     // grid path: the first step rebuilds every list from the recorded build
@@ -723,11 +742,21 @@ hd_status hd_add_system(hd_ctx *ctx, const hd_system_desc *desc, const hd_lj_par
   return HD_OK;
 }
 
+// Critical values of a switch: "lower" below "upper" for the slope and the
+// curvature, above it for the distance (which grows towards the dividing
+// surface).
+static bool thresholds_ok(int var, double lo, double hi) {
+  return var == HD_BIAS_DISTANCE ? lo > hi : lo < hi;
+}
+
 hd_status hd_set_bias(hd_ctx *ctx, int32_t sys, const hd_bias_params *bias) {
   CHECK_CTX();
   if (check_sys(ctx, sys) != HD_OK || !bias) return fail(ctx, HD_E_ARG, "bad system or null bias");
-  if (bias->enabled && (bias->m_b < 1 || !(bias->g_lo < bias->g_hi) || bias->dv_max < 0))
-    return fail(ctx, HD_E_ARG, "bias needs m_b >= 1, g_lo < g_hi, dv_max >= 0");
+  const SysHost &h = ctx->sys[sys];
+  if (bias->enabled && (bias->m_b < 1 || !thresholds_ok(h.bias_var1, bias->g_lo, bias->g_hi) || bias->dv_max < 0))
+    return fail(ctx, HD_E_ARG, "bias needs m_b >= 1, g_lo < g_hi (g_lo > g_hi for the distance), dv_max >= 0");
+  if (bias->enabled && h.bias_var2 >= 0 && !(bias->dv_max > 0))
+    return fail(ctx, HD_E_ARG, "two bias variables need dv_max > 0 (eq. 13 divides by it)");
   if (bias->enabled && ctx->sys[sys].th.kT > 0 && bias->dv_max / ctx->sys[sys].th.kT > 700.0)
     return fail(ctx, HD_E_ARG, "dv_max/kT above 700 overflows the boosted clock");
   ctx->sys[sys].bias = *bias;
@@ -764,6 +793,26 @@ hd_status hd_set_tip_bonds(hd_ctx *ctx, int32_t sys, int32_t enabled, double k_b
   s.k_bond = k_bond;
   s.r_bond = r_bond;
   s.r_bond_cut = r_cut;
+  return HD_OK;
+}
+
+hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t var2, double lo2, double hi2) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK) return fail(ctx, HD_E_ARG, "bad system");
+  SysHost &s = ctx->sys[sys];
+  if (var1 < HD_BIAS_SLOPE || var1 > HD_BIAS_DISTANCE || var2 < -1 || var2 > HD_BIAS_DISTANCE || var2 == var1)
+    return fail(ctx, HD_E_ARG, "bias variables: var1 in {slope, curvature, distance}, var2 another one or -1");
+  if (var2 >= 0 && !thresholds_ok(var2, lo2, hi2))
+    return fail(ctx, HD_E_ARG, "second switch needs lo2 < hi2 (lo2 > hi2 for the distance)");
+  if (s.bias.enabled && !thresholds_ok(var1, s.bias.g_lo, s.bias.g_hi))
+    return fail(ctx, HD_E_ARG, "the bias thresholds do not suit the first variable");
+  if (s.bias.enabled && var2 >= 0 && !(s.bias.dv_max > 0))
+    return fail(ctx, HD_E_ARG, "two bias variables need dv_max > 0 (eq. 13 divides by it)");
+  if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_bias_variables after hd_finalize");
+  s.bias_var1 = var1;
+  s.bias_var2 = var2;
+  s.b2_lo = var2 >= 0 ? lo2 : 0.0;
+  s.b2_hi = var2 >= 0 ? hi2 : 1.0;
   return HD_OK;
 }
 
@@ -863,6 +912,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
   ALLOC(A.eatom, N);
   ALLOC(A.rec, (size_t)N * hdk::kRecDoubles);
   ALLOC(A.brec, (size_t)N * 4);
+  ALLOC(A.tuu, 3 * N);
   ALLOC(A.pos, N);
   if (ctx->prec == HD_FP64) { double *u; ALLOC(u, 3 * N); A.u = u; }
   else { float *u; ALLOC(u, 3 * N); A.u = u; }
@@ -1143,7 +1193,8 @@ hd_status hd_read_forces(hd_ctx *ctx, int32_t sys, int32_t which, double *out) {
   if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
   if (check_sys(ctx, sys) != HD_OK || !out) return fail(ctx, HD_E_ARG, "bad system or null output");
   const double *src = which == HD_FORCE_TOTAL ? ctx->A.ftot : which == HD_FORCE_LJ ? ctx->A.flj
-                    : which == HD_FORCE_BIAS ? ctx->A.fb : which == HD_HU ? ctx->A.hu : nullptr;
+                    : which == HD_FORCE_BIAS ? ctx->A.fb : which == HD_HU ? ctx->A.hu
+                    : which == HD_TUU ? ctx->A.tuu : nullptr;
   if (!src) return fail(ctx, HD_E_ARG, "unknown force selector");
   hd_status st = copy_field(ctx, sys, src, out, hipMemcpyDeviceToHost);
   if (st != HD_OK) return st;
@@ -1183,7 +1234,8 @@ hd_status hd_copy_forces_device(hd_ctx *ctx, int32_t sys, int32_t which, double 
   if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
   if (check_sys(ctx, sys) != HD_OK || !dev_out) return fail(ctx, HD_E_ARG, "bad system or null output");
   const double *src = which == HD_FORCE_TOTAL ? ctx->A.ftot : which == HD_FORCE_LJ ? ctx->A.flj
-                    : which == HD_FORCE_BIAS ? ctx->A.fb : which == HD_HU ? ctx->A.hu : nullptr;
+                    : which == HD_FORCE_BIAS ? ctx->A.fb : which == HD_HU ? ctx->A.hu
+                    : which == HD_TUU ? ctx->A.tuu : nullptr;
   if (!src) return fail(ctx, HD_E_ARG, "unknown force selector");
   return copy_field(ctx, sys, src, dev_out, hipMemcpyDeviceToDevice);
 }
@@ -1209,6 +1261,9 @@ hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
   out->step = T.step;
   out->flags = T.flags;
   out->n_rebuilds = T.n_rebuilds;
+  out->kappa = T.kappa;
+  out->dv1 = T.dv1;
+  out->dv2 = T.dv2;
   return HD_OK;
 }
 

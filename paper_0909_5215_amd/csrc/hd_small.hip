@@ -560,6 +560,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     stg->e_lj = S.e_lj; stg->v_drive = S.v_drive; stg->e_pot = S.e_pot;
     stg->e_kin = ek[0] + (D.n_rigid > 0 ? ekr : 0.0);
     stg->d = S.d; stg->g = S.g; stg->dv = S.dv; stg->dvp = S.dvp;
+    stg->kappa = 0.0; stg->dv1 = S.dv; stg->dv2 = 0.0;
     stg->x_slider = S.xs; stg->x_tip = S.x_tip; stg->f_lat = S.f_lat;
     stg->flags = flags;
     stg->n_rebuilds = rebuilds;

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libhd.so")
 HD_OK, HD_E_ARG, HD_E_OOM, HD_E_HIP, HD_E_STATE, HD_E_UNSTABLE, HD_E_NOGPU = 0, -1, -2, -3, -4, -5, -6
 HD_FP64, HD_FP32C = 0, 1
 HD_EXEC_BATCHED, HD_EXEC_GRID, HD_EXEC_SEQUENTIAL = 0, 1, 2
-HD_FORCE_TOTAL, HD_FORCE_LJ, HD_FORCE_BIAS, HD_HU = 0, 1, 2, 3
+HD_FORCE_TOTAL, HD_FORCE_LJ, HD_FORCE_BIAS, HD_HU, HD_TUU = 0, 1, 2, 3, 4
+HD_BIAS_SLOPE, HD_BIAS_CURVATURE, HD_BIAS_DISTANCE = 0, 1, 2
 HD_FLAG_UNSTABLE, HD_FLAG_NBR_OVERFLOW = 1, 2
 HD_LAUNCH_LDS, HD_LAUNCH_PERSISTENT_LARGE = 1, 2
 HD_QUENCH_CHECK, HD_QUENCH_SET_REFERENCE = 0, 1
@@ -59,7 +60,8 @@ class hd_scalars(_c.Structure):
                 ("dvp", _c.c_double), ("g", _c.c_double), ("d", _c.c_double),
                 ("t_md", _c.c_double), ("t_hyper", _c.c_double), ("x_slider", _c.c_double),
                 ("x_tip", _c.c_double), ("f_lat", _c.c_double), ("step", _c.c_int64),
-                ("flags", _c.c_int32), ("n_rebuilds", _c.c_int32)]
+                ("flags", _c.c_int32), ("n_rebuilds", _c.c_int32),
+                ("kappa", _c.c_double), ("dv1", _c.c_double), ("dv2", _c.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -116,6 +118,7 @@ _SIGS = {
     "hd_min_mode": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_uint64, _dp,
                                _c.POINTER(_c.c_int32), _dp]),
     "hd_set_tip_bonds": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double, _c.c_double]),
+    "hd_set_bias_variables": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double]),
     "hd_last_error": (_c.c_char_p, [_P]),
     "hd_destroy": (None, [_P]),
 }
@@ -222,6 +225,9 @@ class Context:
         self.sizes.append(spec.n)
         if spec.rO is not None:
             self.set_reference(s, spec.rO)
+        v1, v2 = int(getattr(spec, "bias_var1", 0)), int(getattr(spec, "bias_var2", -1))
+        if v1 != HD_BIAS_SLOPE or v2 >= 0:
+            self.set_bias_variables(s, v1, v2, getattr(spec, "b2_lo", 0.0), getattr(spec, "b2_hi", 1.0))
         if spec.bias_on:
             self.set_bias(s, True, spec.m_b, spec.dv_max, spec.g_lo, spec.g_hi)
         if getattr(spec, "tip_bonds", 0):
@@ -231,6 +237,10 @@ class Context:
     def set_tip_bonds(self, s: int, enabled: bool, k_bond: float, r_bond: float, r_cut: float):
         _check(self._h, load().hd_set_tip_bonds(self._h, s, int(bool(enabled)), float(k_bond), float(r_bond),
                                                 float(r_cut)), "hd_set_tip_bonds")
+
+    def set_bias_variables(self, s: int, var1: int, var2: int = -1, lo2: float = 0.0, hi2: float = 1.0):
+        _check(self._h, load().hd_set_bias_variables(self._h, s, int(var1), int(var2), float(lo2), float(hi2)),
+               "hd_set_bias_variables")
 
     def set_reference(self, s: int, rO: np.ndarray):
         a = np.ascontiguousarray(rO, dtype=np.float64)
