@@ -4,11 +4,15 @@ beside the plain float64 single-system path and the FP64 CPU oracle.
 Workload (default): the 2D AFM model (40x10 substrate + 10x8 tip, 480 atoms)
 at 32 stepped slider positions spread over one lattice period, slope bias on,
 Langevin T = 0.1, gamma = 1, dt = 0.005.  Other workloads: --config C3 | C4 |
-C5a | C5b.  Inputs are synthetic lattices built by hd_inputs (seeded).
+C5a | C5b | P3.  Inputs are synthetic lattices built by hd_inputs (seeded).
+--bias picks the bias variables: the slope alone (default) or the slope, the
+curvature and the distance alone or two of them combined by eq. 13.
 
 Setup (untimed): a FIRE quench on the GPU (hd_quench) gives each system's
-basin reference r_O; an unbiased pre-run samples the slope g, and the bias
-thresholds are its 5% and 50% quantiles (dV_max = 5 kT, m = 2).  The timed
+basin reference r_O; an unbiased pre-run samples the bias variables, and the
+thresholds of the slope and the curvature are their 5% and 50% quantiles, of
+the distance its 95% and 50% quantiles (full bias up to the median distance,
+none beyond the 95% one); dV_max = 5 kT, m = 2.  The timed
 region is K steps of every system with inputs resident in HBM; neighbour-list
 rebuilds are included.
 
@@ -65,6 +69,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--config", default="C2")
+    ap.add_argument("--bias", default="slope", choices=sorted(BIAS_CHOICES),
+                    help="bias variables (eq. 13 combines two)")
     ap.add_argument("--plain-steps", type=int, default=0, help="steps per system of the plain path (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -96,6 +102,25 @@ def workload(name):
               "x 64 slider positions, slope bias on",
     }[name]
     return specs, desc
+
+
+# bias variables: 0 slope (eq. 5), 1 curvature (eq. 6), 2 distance (eq. 7)
+BIAS_CHOICES = {"slope": (0, -1), "curvature": (1, -1), "distance": (2, -1),
+                "slope+curvature": (0, 1), "slope+distance": (0, 2), "curvature+distance": (1, 2)}
+
+
+def thresholds(var, samples):
+    """Critical values (lower, upper) of a switch from unbiased samples."""
+    a = np.asarray(samples)
+    if var == 2:
+        lo, hi = np.quantile(a, 0.95), np.quantile(a, 0.5)
+        if not lo > hi:
+            lo = hi + 1e-3 * (abs(hi) + 1.0)
+    else:
+        lo, hi = np.quantile(a, 0.05), np.quantile(a, 0.5)
+        if not hi > lo:
+            hi = lo + 1e-3 * (abs(lo) + 1.0)
+    return float(lo), float(hi)
 
 
 def prepare(hd, specs, quench_steps, prerun_steps, block):
@@ -130,16 +155,16 @@ def prepare(hd, specs, quench_steps, prerun_steps, block):
     for _ in range(nsamp):
         ctx.step(every)
         for k in range(len(specs)):
-            samples[k].append(ctx.scalars(k)["g"])
+            sc = ctx.scalars(k)
+            samples[k].append((sc["g"], sc["kappa"], sc["d"]))
     states = []
     for k, s in enumerate(specs):
-        g = np.array(samples[k])
+        v = np.array(samples[k])
         s.bias_on, s.m_b = 1, 2
         s.dv_max = 5.0 * s.kT
-        lo, hi = np.quantile(g, 0.05), np.quantile(g, 0.5)
-        if not hi > lo:
-            hi = lo + 1e-3 * (abs(lo) + 1.0)
-        s.g_lo, s.g_hi = float(lo), float(hi)
+        s.g_lo, s.g_hi = thresholds(s.bias_var1, v[:, s.bias_var1])
+        if s.bias_var2 >= 0:
+            s.b2_lo, s.b2_hi = thresholds(s.bias_var2, v[:, s.bias_var2])
         states.append(ctx.get_state(k))
     ctx.close()
     return specs, states, quench
@@ -279,6 +304,10 @@ def main():
         del src, dst
 
     specs, desc = workload(args.config)
+    v1, v2 = BIAS_CHOICES[args.bias]
+    for s in specs:
+        s.bias_var1, s.bias_var2 = v1, v2
+    ckey = args.config if args.bias == "slope" else f"{args.config}/{args.bias}"
     n_atoms = sum(s.n for s in specs)
     dim = specs[0].dim
     log(f"{args.config}: {len(specs)} systems, {n_atoms} atoms")
@@ -316,7 +345,7 @@ def main():
     achieved = alg_bytes_per_step * steps_per_launch / avg_launch_s / 1e9
     kname = stepping_kernel(specs, sched)
     traffic, traffic_bytes = None, None
-    rec = HBM_COUNTERS.get((args.config, kname))
+    rec = HBM_COUNTERS.get((ckey, kname))
     if rec and src_hash(rec["src"]) == rec["sha"]:
         traffic_bytes = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
         traffic = round(traffic_bytes / avg_launch_s / 1e9, 4)
@@ -324,7 +353,7 @@ def main():
     # chip and against the CUs the launch occupies (one workgroup per system
     # for the LDS-resident kernel)
     issue = None
-    vrec = VALU_COUNTERS.get((args.config, kname))
+    vrec = VALU_COUNTERS.get((ckey, kname))
     if vrec and src_hash(vrec["src"]) == vrec["sha"]:
         rate = vrec["insts_valu"] * steps_per_launch / vrec["steps"] / avg_launch_s / 1e9
         cus = min(256, len(specs)) if kname.startswith("k_small") else 256
@@ -391,7 +420,7 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {desc}", "systems": len(specs), "atoms": n_atoms,
+        "config": {"workload": f"{args.config}: {desc}", "bias": args.bias, "systems": len(specs), "atoms": n_atoms,
                    "dim": dim, "parallelism": "batch of independent slider positions, 1 GPU"},
         "roofline": roof,
         "roofline_valu": valu,

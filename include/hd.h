@@ -197,10 +197,11 @@ hd_status hd_set_tip_bonds(hd_ctx *ctx, int32_t sys, int32_t enabled, double k_b
  * the chain rule, with grad g = (Hu - F - g u/d)/d,
  * grad kappa = (2 Hu + T[u,u])/d^2 - 2 kappa u/d^2 and grad d = u/d.
  * Default: the slope alone.  Before hd_finalize only (HD_E_STATE after);
- * HD_E_ARG for an unknown variable, var2 == var1, critical values in the
- * wrong order (also those already set by hd_set_bias) or, with two
- * variables, dv_max = 0.  Systems with any other choice than the slope
- * alone run on the grid kernels (never LDS-resident). */
+ * HD_E_ARG for an unknown variable or var2 == var1, and, while the bias is
+ * enabled, for critical values in the wrong order (also those set by
+ * hd_set_bias, which checks the same against the current variables) or,
+ * with two variables, dv_max = 0.  Systems with any other choice than the
+ * slope alone run on the grid kernels (never LDS-resident). */
 hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t var2, double lo2, double hi2);
 
 /* Basin minimum r_O (eq. 7), SoA [dim][n]. */

@@ -749,14 +749,26 @@ static bool thresholds_ok(int var, double lo, double hi) {
   return var == HD_BIAS_DISTANCE ? lo > hi : lo < hi;
 }
 
+// An enabled bias with variables var1 (and var2): m_b >= 1, dv_max >= 0
+// (> 0 with two variables: eq. 13 divides by it), both switches' critical
+// values in their variable's order.  A disabled bias is not checked.
+static const char *bias_problem(const hd_bias_params &b, int var1, int var2, double lo2, double hi2) {
+  if (!b.enabled) return nullptr;
+  if (b.m_b < 1 || b.dv_max < 0) return "bias needs m_b >= 1 and dv_max >= 0";
+  if (!thresholds_ok(var1, b.g_lo, b.g_hi))
+    return "bias needs g_lo < g_hi (g_lo > g_hi when the first variable is the distance)";
+  if (var2 >= 0 && !thresholds_ok(var2, lo2, hi2))
+    return "second switch needs lo2 < hi2 (lo2 > hi2 for the distance)";
+  if (var2 >= 0 && !(b.dv_max > 0)) return "two bias variables need dv_max > 0 (eq. 13 divides by it)";
+  return nullptr;
+}
+
 hd_status hd_set_bias(hd_ctx *ctx, int32_t sys, const hd_bias_params *bias) {
   CHECK_CTX();
   if (check_sys(ctx, sys) != HD_OK || !bias) return fail(ctx, HD_E_ARG, "bad system or null bias");
   const SysHost &h = ctx->sys[sys];
-  if (bias->enabled && (bias->m_b < 1 || !thresholds_ok(h.bias_var1, bias->g_lo, bias->g_hi) || bias->dv_max < 0))
-    return fail(ctx, HD_E_ARG, "bias needs m_b >= 1, g_lo < g_hi (g_lo > g_hi for the distance), dv_max >= 0");
-  if (bias->enabled && h.bias_var2 >= 0 && !(bias->dv_max > 0))
-    return fail(ctx, HD_E_ARG, "two bias variables need dv_max > 0 (eq. 13 divides by it)");
+  if (const char *why = bias_problem(*bias, h.bias_var1, h.bias_var2, h.b2_lo, h.b2_hi))
+    return fail(ctx, HD_E_ARG, why);
   if (bias->enabled && ctx->sys[sys].th.kT > 0 && bias->dv_max / ctx->sys[sys].th.kT > 700.0)
     return fail(ctx, HD_E_ARG, "dv_max/kT above 700 overflows the boosted clock");
   ctx->sys[sys].bias = *bias;
@@ -802,12 +814,7 @@ hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t 
   SysHost &s = ctx->sys[sys];
   if (var1 < HD_BIAS_SLOPE || var1 > HD_BIAS_DISTANCE || var2 < -1 || var2 > HD_BIAS_DISTANCE || var2 == var1)
     return fail(ctx, HD_E_ARG, "bias variables: var1 in {slope, curvature, distance}, var2 another one or -1");
-  if (var2 >= 0 && !thresholds_ok(var2, lo2, hi2))
-    return fail(ctx, HD_E_ARG, "second switch needs lo2 < hi2 (lo2 > hi2 for the distance)");
-  if (s.bias.enabled && !thresholds_ok(var1, s.bias.g_lo, s.bias.g_hi))
-    return fail(ctx, HD_E_ARG, "the bias thresholds do not suit the first variable");
-  if (s.bias.enabled && var2 >= 0 && !(s.bias.dv_max > 0))
-    return fail(ctx, HD_E_ARG, "two bias variables need dv_max > 0 (eq. 13 divides by it)");
+  if (const char *why = bias_problem(s.bias, var1, var2, lo2, hi2)) return fail(ctx, HD_E_ARG, why);
   if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_bias_variables after hd_finalize");
   s.bias_var1 = var1;
   s.bias_var2 = var2;

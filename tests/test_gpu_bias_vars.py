@@ -137,8 +137,14 @@ def test_bias_variable_arguments(hd):
     for bad in ((3, -1), (-1, -1), (0, 0), (1, 3)):
         with pytest.raises(hd.HDError):
             ctx.set_bias_variables(k, *bad)
+    ctx.set_bias_variables(k, 0, 2, 1.0, 2.0)            # bias off: not checked ...
+    with pytest.raises(hd.HDError):
+        ctx.set_bias(k, True, 2, 0.5, 0.0, 1.0)          # ... until it is enabled
+    ctx.set_bias_variables(k, 0, 2, 2.0, 1.0)
+    ctx.set_bias(k, True, 2, 0.5, 0.0, 1.0)
     with pytest.raises(hd.HDError):
         ctx.set_bias_variables(k, 0, 2, 1.0, 2.0)        # distance needs lo2 > hi2
+    ctx.set_bias(k, False, 2, 0.5, 0.0, 1.0)
     ctx.set_bias_variables(k, 2)
     with pytest.raises(hd.HDError):
         ctx.set_bias(k, True, 2, 0.5, 0.0, 1.0)          # distance needs g_lo > g_hi
