@@ -98,8 +98,10 @@ def workload(name):
         "C4": "128 uneven 2D/3D instances (log-uniform 500-50k atoms), slope bias on",
         "C5a": "3D LJ AFM fcc 100x100x25 + R=20 tip (1017285 atoms), 1 system, slope bias on",
         "C5b": "3D LJ AFM fcc 18x18x6 + R=5 tip (8072 atoms) x 256 slider positions, slope bias on",
+        "P2": "the paper's 2D model: triangular 80 + tip 33 (113 atoms), k = 5, T = 0.01 "
+              "x 256 slider positions dx_S = 0.01, slope bias on",
         "P3": "the paper's 3D model: fcc 1800 + conical tip 183 with harmonic tip bonds (1983 atoms) "
-              "x 64 slider positions, slope bias on",
+              "x 64 slider positions dx_S = 0.01, slope bias on",
     }[name]
     return specs, desc
 

@@ -119,7 +119,10 @@ def build_2d(nx: int = 40, ny: int = 10, tip: str = "block", tip_w: int = 10,
     tip='block': tip_w x tip_h block continuing the lattice, centred; its top
     row is rigid.  tip='halfdisk': lattice sites inside a half disk of radius
     R whose flat top row is rigid and whose lowest row sits one lattice row
-    above the substrate.
+    above the substrate.  tip='trapezoid': tip_h rows continuing the lattice,
+    tip_w atoms in the lowest row and one more in each row above, all rows
+    centred on one vertical line (the 2D counterpart of a cone with flat
+    ends); its top row is rigid.
     """
     xs, ys, types, roles = [], [], [], []
     for row in range(ny):
@@ -135,6 +138,21 @@ def build_2d(nx: int = 40, ny: int = 10, tip: str = "block", tip_w: int = 10,
             row = ny + r
             for i in range(tip_w):
                 x, y = _tri_site(i0 + i, row)
+                xs.append(x); ys.append(y)
+                types.append(TYPE_TIP)
+                roles.append(ROLE_RIGID if r == tip_h - 1 else ROLE_MOBILE)
+    elif tip == "trapezoid":
+        # rows of width w = tip_w + r share the centre c (in units of A2D):
+        # c = i0 + (w - 1)/2 + (row & 1)/2 for the first site i0 of each row,
+        # an integer for every row since w and the row parity change together
+        row0 = ny
+        c2 = 2 * (nx // 2 - tip_w // 2) + (tip_w - 1) + (row0 & 1)    # 2c
+        for r in range(tip_h):
+            row, w = ny + r, tip_w + r
+            twice_i0 = c2 - (w - 1) - (row & 1)
+            assert twice_i0 % 2 == 0
+            for j in range(w):
+                x, y = _tri_site(twice_i0 // 2 + j, row)
                 xs.append(x); ys.append(y)
                 types.append(TYPE_TIP)
                 roles.append(ROLE_RIGID if r == tip_h - 1 else ROLE_MOBILE)
@@ -174,6 +192,17 @@ def build_2d(nx: int = 40, ny: int = 10, tip: str = "block", tip_w: int = 10,
                       role=np.array(roles, np.uint8),
                       box=np.array([L, 0.0, 0.0]), periodic=np.array([1, 0, 0], np.int32),
                       eps=eps, label=f"2d_{nx}x{ny}_{tip}")
+
+
+def build_2d_paper() -> SystemSpec:
+    """The paper's 2D model (§3.1.1): 80 substrate atoms (20 x 4 rows, bottom
+    row fixed, periodic in x) and a 33-atom tip in registry (rows of 3, 4,
+    ..., 8 atoms from the contact row up, top row rigid), spring k = 5,
+    normal load F_N = 5, eps_ts = 0.5."""
+    s = build_2d(nx=20, ny=4, tip="trapezoid", tip_w=3, tip_h=6, n_fixed_rows=1)
+    s.k_spring, s.f_normal = 5.0, 5.0
+    s.label = "2d_paper_80+33"
+    return s
 
 
 # ----------------------------------------------------------------------------
@@ -409,16 +438,35 @@ def config_c5b(n_sys: int = 256) -> List[SystemSpec]:
     return out
 
 
+DX_SLIDER = 0.01   # the paper's slider step (§3.1.1)
+
+
+def config_p2(n_sys: int = 256) -> List[SystemSpec]:
+    """The paper's 2D model (113 atoms, spring k = 5) at n_sys consecutive
+    slider positions k dx_S, dx_S = 0.01, T = 0.01, slope bias on."""
+    base = build_2d_paper()
+    out = []
+    for k in range(n_sys):
+        s = base.copy()
+        s.kT, s.gamma, s.dt = 0.01, 1.0, 0.005
+        s.x_slider = k * DX_SLIDER
+        s.seed = seed_for(1007, k)
+        s.bias_on = 1
+        s.label = f"P2[{k}]"
+        out.append(s)
+    return out
+
+
 def config_p3(n_sys: int = 64) -> List[SystemSpec]:
     """The paper's 3D model (1800-atom substrate, 183-atom conical tip with
-    harmonic tip bonds, spring k = 10) at n_sys slider positions over one
-    lattice period, T = 0.1, slope bias on."""
+    harmonic tip bonds, spring k = 10) at n_sys consecutive slider positions
+    k dx_S, dx_S = 0.01, T = 0.1, slope bias on."""
     base = build_3d_cone()
     out = []
     for k in range(n_sys):
         s = base.copy()
         s.f_normal, s.kT, s.gamma, s.dt = 5.0, 0.1, 1.0, 0.005
-        s.x_slider = k * AFCC / n_sys
+        s.x_slider = k * DX_SLIDER
         s.seed = seed_for(1006, k)
         s.bias_on = 1
         s.label = f"P3[{k}]"
@@ -427,7 +475,7 @@ def config_p3(n_sys: int = 64) -> List[SystemSpec]:
 
 
 CONFIGS = {"C1": config_c1, "C2": config_c2, "C3": config_c3, "C4": config_c4,
-           "C5a": config_c5a, "C5b": config_c5b, "P3": config_p3}
+           "C5a": config_c5a, "C5b": config_c5b, "P2": config_p2, "P3": config_p3}
 
 
 def perturbed(spec: SystemSpec, amp: float, seed: int) -> np.ndarray:

@@ -832,3 +832,27 @@ def test_eq13_plateaus_and_symmetry(oracle_mod):
     assert ra["dv"] == rb["dv"] and 0.0 < ra["dv"] < a.dv_max
     np.testing.assert_array_equal(ra["f_b"], rb["f_b"])
     assert ra["dv"] == pytest.approx(ra["dv1"] + ra["dv2"] - ra["dv1"] * ra["dv2"] / a.dv_max, rel=1e-15)
+
+
+def test_2d_paper_model():
+    """§3.1.1: 80 substrate atoms with the bottom layer fixed, 33 tip atoms in
+    registry (every tip site is a site of the substrate's lattice continued
+    upwards), top tip row rigid, spring k = 5, F_N = 5, eps_ts = 0.5."""
+    from hd_inputs import build_2d_paper
+    s = build_2d_paper()
+    tip = s.type == 1
+    assert (~tip).sum() == 80 and tip.sum() == 33
+    assert (s.role == ROLE_FIXED).sum() == 20 and np.all(s.type[s.role == ROLE_FIXED] == 0)
+    a = 2.0 ** (1.0 / 6.0)
+    pitch = a * math.sqrt(3.0) / 2.0
+    rows = np.round(s.pos[1] / pitch).astype(int)
+    np.testing.assert_allclose(s.pos[1], rows * pitch, atol=1e-12)
+    # lattice sites: x = (i + (row mod 2)/2) a
+    frac = s.pos[0] / a - 0.5 * (rows & 1)
+    np.testing.assert_allclose(frac, np.round(frac), atol=1e-9)
+    trow = rows[tip]
+    widths = [int((trow == r).sum()) for r in range(trow.min(), trow.max() + 1)]
+    assert widths == [3, 4, 5, 6, 7, 8]
+    assert trow.min() == rows[~tip].max() + 1                # the contact row sits on the substrate
+    assert np.all(s.role[tip & (rows == trow.max())] == ROLE_RIGID)
+    assert s.k_spring == 5.0 and s.f_normal == 5.0 and s.eps[0, 1] == 0.5
