@@ -53,11 +53,15 @@ class SystemSpec:
     sig: np.ndarray = dataclasses.field(default_factory=lambda: np.ones((2, 2)))
     rc: float = 2.5
     skin: float = 0.3
-    # Langevin thermostat
+    # thermostat: 0 Langevin (gamma), 1 Nose-Hoover chain of nhc_len
+    # thermostats with relaxation time nhc_tau
     dt: float = 0.005
     gamma: float = 1.0
     kT: float = 0.1
     seed: int = 1
+    thermostat: int = 0
+    nhc_len: int = 3
+    nhc_tau: float = 0.5
     # slider drive on the rigid layer
     k_spring: float = 1.0
     f_normal: float = 5.0

@@ -24,6 +24,7 @@ struct orc_sys {
     double XR[3], VR[3], XR0[3];
     double *ftot;            /* total force at the current positions */
     double *tuu;             /* T[u,u] of the last evaluation */
+    double xi[4], eta[4];    /* Nose-Hoover chain velocities and positions */
     double FR[3];            /* total force on the rigid body */
     int64_t step;
     double t_md, t_hyper;
@@ -31,6 +32,8 @@ struct orc_sys {
     int brute;
     int have_force;
 };
+
+static double nhc_energy(const orc_sys *s);
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, from the definition in Salmon et al. (SC'11): ten rounds of
@@ -641,6 +644,7 @@ static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot
     sc->kappa = kappa;
     sc->dv1 = dv1;
     sc->dv2 = dv2;
+    sc->e_nhc = nhc_energy(s);
     sc->x_slider = xs;
     sc->x_tip = x_tip;
     sc->f_lat = f_lat;
@@ -678,6 +682,141 @@ void orc_compute(orc_sys *s, double *f_lj, double *hu, double *f_b, double *f_to
  * n_R m:  B: v += dt/2 F/m;  A: x += dt/2 v;  O: v = c1 v + c2 xi;
  * A: x += dt/2 v;  new forces;  B: v += dt/2 F/m.  Fixed atoms never move.
  * The noise xi for step n uses Philox counter (n, particle, tag 0). */
+/* ------------------------------------------------------------------------ */
+/* Nose-Hoover chain (Martyna, Klein, Tuckerman 1992) */
+
+static int nhc_dof(const orc_sys *s)
+{
+    int nm = 0;
+    for (int i = 0; i < s->n; ++i) nm += s->role[i] == MOBILE;
+    return s->dim * (nm + (s->n_rigid > 0 ? 1 : 0));
+}
+
+/* Twice the kinetic energy of the integrated degrees of freedom. */
+static double twice_kinetic(const orc_sys *s)
+{
+    const int n = s->n, dim = s->dim;
+    double k2 = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (s->role[i] == MOBILE)
+            for (int k = 0; k < dim; ++k) k2 += s->p.mass * s->v[k * n + i] * s->v[k * n + i];
+    if (s->n_rigid > 0)
+        for (int k = 0; k < dim; ++k) k2 += s->p.mass * s->n_rigid * s->VR[k] * s->VR[k];
+    return k2;
+}
+
+/* The force on chain thermostat j (0-based) given twice the kinetic
+ * energy k2 of the particles. */
+static double nhc_G(const orc_sys *s, int j, double k2, const double Q[4])
+{
+    const double kT = s->p.kT;
+    if (j == 0) return (k2 - nhc_dof(s) * kT) / Q[0];
+    return (Q[j - 1] * s->xi[j - 1] * s->xi[j - 1] - kT) / Q[j];
+}
+
+/* Propagate the chain over a time h (half a step): the thermostat
+ * velocities from the chain's end inwards over h/2, the particle velocities
+ * scaled by exp(-xi_1 h) and the thermostat positions advanced by h, then the
+ * thermostat velocities outwards over h/2; each inner update is wrapped in
+ * exp(-xi_{j+1} h/4) factors.  Returns the velocity scale factor. */
+static double nhc_propagate(orc_sys *s, double h)
+{
+    const int M = s->p.nhc_len;
+    const double kT = s->p.kT, t2 = s->p.nhc_tau * s->p.nhc_tau;
+    double Q[4];
+    Q[0] = nhc_dof(s) * kT * t2;
+    for (int j = 1; j < 4; ++j) Q[j] = kT * t2;
+    double k2 = twice_kinetic(s);
+    s->xi[M - 1] += 0.5 * h * nhc_G(s, M - 1, k2, Q);
+    for (int j = M - 2; j >= 0; --j) {
+        const double e = exp(-0.25 * h * s->xi[j + 1]);
+        s->xi[j] *= e;
+        s->xi[j] += 0.5 * h * nhc_G(s, j, k2, Q);
+        s->xi[j] *= e;
+    }
+    const double scale = exp(-h * s->xi[0]);
+    k2 *= scale * scale;
+    for (int j = 0; j < M; ++j) s->eta[j] += h * s->xi[j];
+    for (int j = 0; j < M - 1; ++j) {
+        const double e = exp(-0.25 * h * s->xi[j + 1]);
+        s->xi[j] *= e;
+        s->xi[j] += 0.5 * h * nhc_G(s, j, k2, Q);
+        s->xi[j] *= e;
+    }
+    s->xi[M - 1] += 0.5 * h * nhc_G(s, M - 1, k2, Q);
+    return scale;
+}
+
+static void scale_velocities(orc_sys *s, double c)
+{
+    const int n = s->n, dim = s->dim;
+    for (int i = 0; i < n; ++i)
+        if (s->role[i] != FIXED)
+            for (int k = 0; k < dim; ++k) s->v[k * n + i] *= c;
+    for (int k = 0; k < dim; ++k) s->VR[k] *= c;
+}
+
+static double nhc_energy(const orc_sys *s)
+{
+    if (s->p.thermostat != 1) return 0.0;
+    const double kT = s->p.kT, t2 = s->p.nhc_tau * s->p.nhc_tau;
+    double e = nhc_dof(s) * kT * s->eta[0];
+    for (int j = 0; j < s->p.nhc_len; ++j) {
+        const double Q = (j == 0 ? nhc_dof(s) * kT : kT) * t2;
+        e += 0.5 * Q * s->xi[j] * s->xi[j];
+        if (j > 0) e += kT * s->eta[j];
+    }
+    return e;
+}
+
+void orc_get_nhc(const orc_sys *s, double xi[4], double eta[4])
+{
+    for (int j = 0; j < 4; ++j) { xi[j] = s->xi[j]; eta[j] = s->eta[j]; }
+}
+
+void orc_set_nhc(orc_sys *s, const double xi[4], const double eta[4])
+{
+    for (int j = 0; j < 4; ++j) { s->xi[j] = xi[j]; s->eta[j] = eta[j]; }
+}
+
+/* One step of velocity Verlet inside the chain's half steps:
+ * chain(dt/2); v += dt/2 F/m; x += dt v; forces; v += dt/2 F/m; chain(dt/2). */
+static void nhc_vv_step(orc_sys *s, double *F, double *H, double *B, double *E)
+{
+    const orc_params *p = &s->p;
+    const int n = s->n, dim = s->dim;
+    const double dt = p->dt, hdt = 0.5 * p->dt;
+    const double M = p->mass * s->n_rigid;
+    scale_velocities(s, nhc_propagate(s, hdt));
+    for (int i = 0; i < n; ++i) {
+        if (s->role[i] != MOBILE) continue;
+        for (int k = 0; k < dim; ++k) {
+            double v = s->v[k * n + i] + hdt * s->ftot[k * n + i] / p->mass;
+            s->v[k * n + i] = v;
+            s->x[k * n + i] = wrap(s->x[k * n + i] + dt * v, p->box[k], p->periodic[k]);
+        }
+    }
+    if (s->n_rigid > 0) {
+        for (int k = 0; k < dim; ++k) {
+            s->VR[k] = s->VR[k] + hdt * s->FR[k] / M;
+            s->XR[k] = s->XR[k] + dt * s->VR[k];
+        }
+        place_rigid(s);
+    }
+    s->step = s->step + 1;
+    evaluate(s, F, H, B, s->ftot, E, &s->last);
+    for (int i = 0; i < n; ++i) {
+        if (s->role[i] != MOBILE) continue;
+        for (int k = 0; k < dim; ++k) s->v[k * n + i] = s->v[k * n + i] + hdt * s->ftot[k * n + i] / p->mass;
+    }
+    if (s->n_rigid > 0)
+        for (int k = 0; k < dim; ++k) s->VR[k] = s->VR[k] + hdt * s->FR[k] / M;
+    scale_velocities(s, nhc_propagate(s, hdt));
+    for (int i = 0; i < n; ++i)
+        if (s->role[i] == RIGID)
+            for (int k = 0; k < dim; ++k) s->v[k * n + i] = s->VR[k];
+}
+
 void orc_step(orc_sys *s, int64_t nsteps)
 {
     const orc_params *p = &s->p;
@@ -699,6 +838,10 @@ void orc_step(orc_sys *s, int64_t nsteps)
     double z[4];
     for (int64_t it = 0; it < nsteps; ++it) {
         const int64_t step = s->step;
+        if (p->thermostat == 1) {
+            nhc_vv_step(s, F, H, B, E);
+            goto clock;
+        }
         for (int i = 0; i < n; ++i) {
             if (s->role[i] != MOBILE) continue;
             orc_normals(p->seed, step, (uint32_t)i, 0u, z);
@@ -740,6 +883,7 @@ void orc_step(orc_sys *s, int64_t nsteps)
                 if (s->role[i] == RIGID)
                     for (int k = 0; k < dim; ++k) s->v[k * n + i] = s->VR[k];
         }
+    clock:
         /* boosted clock, right Riemann sum: dV at the post-step positions */
         s->t_md += dt;
         s->t_hyper += dt * exp(s->last.dv / p->kT);
@@ -750,6 +894,7 @@ void orc_step(orc_sys *s, int64_t nsteps)
                 for (int k = 0; k < dim; ++k) ek += 0.5 * p->mass * s->v[k * n + i] * s->v[k * n + i];
         for (int k = 0; k < dim; ++k) ek += 0.5 * M * s->VR[k] * s->VR[k];
         s->last.e_kin = ek;
+        s->last.e_nhc = nhc_energy(s);
         s->last.t_md = s->t_md;
         s->last.t_hyper = s->t_hyper;
     }

@@ -24,7 +24,10 @@
  *     u) and grad d = u/d;
  *   - the boosted clock t_hyper = sum dt exp(dV/kT) (eq. 3 as a time average;
  *     eq. 8 fixes what it means for stepped sliding);
- *   - a Langevin BAOAB step (replaces the paper's Nose-Hoover chain);
+ *   - a Langevin BAOAB step, or the paper's Nose-Hoover chain thermostat
+ *     (Sec. 3.1.1) with velocity Verlet, the chain integrated by the
+ *     Trotter splitting of Martyna, Tuckerman, Tobias and Klein (Mol. Phys.
+ *     87, 1117, 1996);
  *   - Philox4x32-10 + Box-Muller normals;
  *   - a FIRE minimiser for r_O.
  *
@@ -65,6 +68,12 @@ typedef struct {
      * side, whichever of the two is larger. */
     int32_t bias_var1, bias_var2;
     double b2_lo, b2_hi;
+    /* thermostat: 0 Langevin (BAOAB, gamma), 1 Nose-Hoover chain of nhc_len
+     * (1..4) thermostats with relaxation time nhc_tau: masses
+     * Q_1 = N_f kT tau^2, Q_j = kT tau^2, N_f = dim (n_mobile + 1 if the
+     * model has a rigid layer) */
+    int32_t thermostat, nhc_len;
+    double nhc_tau;
 } orc_params;
 
 typedef struct {
@@ -76,6 +85,9 @@ typedef struct {
     int32_t flags, pad_f;
     double kappa;         /* curvature along s (eq. 6); 0 when d ~ 0 */
     double dv1, dv2;      /* the two switches of eq. 13 */
+    /* Nose-Hoover chain energy sum_j Q_j xi_j^2 / 2 + N_f kT eta_1
+     * + kT sum_{j>1} eta_j: with e_kin + e_pot + dv it is conserved */
+    double e_nhc;
 } orc_scalars;
 
 /* Opaque simulation state for one system. */
@@ -114,6 +126,10 @@ void orc_set_pair_method(orc_sys *s, int brute);
  * half pair energies. */
 void orc_compute(orc_sys *s, double *f_lj, double *hu, double *f_b, double *f_tot,
                  double *e_atom, orc_scalars *out);
+/* Nose-Hoover chain state: thermostat velocities xi and positions eta (4
+ * each; entries beyond nhc_len unused). */
+void orc_get_nhc(const orc_sys *s, double xi[4], double eta[4]);
+void orc_set_nhc(orc_sys *s, const double xi[4], const double eta[4]);
 /* T[u,u] of the last evaluation: the gradient of u.H(r)u at fixed u. */
 void orc_get_tuu(const orc_sys *s, double *t);
 /* Advance nsteps BAOAB steps (bias included when enabled). */

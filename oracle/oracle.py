@@ -43,6 +43,7 @@ class OrcParams(ctypes.Structure):
         ("k_bond", ctypes.c_double), ("r_bond", ctypes.c_double), ("r_bond_cut", ctypes.c_double),
         ("bias_var1", ctypes.c_int32), ("bias_var2", ctypes.c_int32),
         ("b2_lo", ctypes.c_double), ("b2_hi", ctypes.c_double),
+        ("thermostat", ctypes.c_int32), ("nhc_len", ctypes.c_int32), ("nhc_tau", ctypes.c_double),
     ]
 
 
@@ -56,6 +57,7 @@ class OrcScalars(ctypes.Structure):
         ("t_md", ctypes.c_double), ("t_hyper", ctypes.c_double),
         ("step", ctypes.c_int64), ("flags", ctypes.c_int32), ("pad_f", ctypes.c_int32),
         ("kappa", ctypes.c_double), ("dv1", ctypes.c_double), ("dv2", ctypes.c_double),
+        ("e_nhc", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -97,6 +99,8 @@ def lib():
         L.orc_get_scalars.argtypes = [vp, P(OrcScalars)]
         L.orc_get_rigid.argtypes = [vp, dp, dp, dp]
         L.orc_get_tuu.argtypes = [vp, dp]
+        L.orc_get_nhc.argtypes = [vp, dp, dp]
+        L.orc_set_nhc.argtypes = [vp, dp, dp]
         L.orc_fire.argtypes = [vp, ctypes.c_double, ctypes.c_int64]
         L.orc_fire.restype = ctypes.c_int64
         _lib = L
@@ -137,6 +141,9 @@ def params_from_spec(spec, **over) -> OrcParams:
     p.bias_var2 = int(getattr(spec, "bias_var2", -1))
     p.b2_lo = float(getattr(spec, "b2_lo", 0.0))
     p.b2_hi = float(getattr(spec, "b2_hi", 1.0))
+    p.thermostat = int(getattr(spec, "thermostat", 0))
+    p.nhc_len = int(getattr(spec, "nhc_len", 3))
+    p.nhc_tau = float(getattr(spec, "nhc_tau", 0.5))
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -253,6 +260,16 @@ class OracleSystem:
         a, b, c = np.zeros(3), np.zeros(3), np.zeros(3)
         lib().orc_get_rigid(self._h, _dp(a), _dp(b), _dp(c))
         return a, b, c
+
+    def nhc(self):
+        xi, eta = np.zeros(4), np.zeros(4)
+        lib().orc_get_nhc(self._h, _dp(xi), _dp(eta))
+        return xi, eta
+
+    def set_nhc(self, xi, eta):
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        lib().orc_set_nhc(self._h, _dp(xi), _dp(eta))
 
     def fire(self, ftol=1e-10, maxit=200000) -> int:
         return int(lib().orc_fire(self._h, float(ftol), int(maxit)))

@@ -856,3 +856,96 @@ def test_2d_paper_model():
     assert trow.min() == rows[~tip].max() + 1                # the contact row sits on the substrate
     assert np.all(s.role[tip & (rows == trow.max())] == ROLE_RIGID)
     assert s.k_spring == 5.0 and s.f_normal == 5.0 and s.eps[0, 1] == 0.5
+
+
+# --------------------------------------------------------------------------
+# Nose-Hoover chain thermostat (Sec. 3.1.1; Martyna, Klein, Tuckerman 1992)
+# --------------------------------------------------------------------------
+def _nhc(spec, tau=0.5, M=3):
+    spec.thermostat, spec.nhc_len, spec.nhc_tau = 1, M, tau
+    return spec
+
+
+@pytest.mark.parametrize("M", [1, 3])
+def test_nhc_time_reversible(oracle_mod, M):
+    """The chain integrator is a symmetric splitting: reversing the particle
+    and thermostat velocities retraces the trajectory."""
+    spec = _nhc(small2d(kT=0.1, x_slider=0.2), M=M)
+    x = perturbed(spec, 0.05, 21)
+    o = oracle_mod.OracleSystem(spec, x=x)
+    o.init_velocities()
+    o.step(20)                               # the thermostats pick up speed
+    x0, v0 = o.positions(), o.velocities()
+    xi0, eta0 = o.nhc()
+    assert np.abs(xi0[:M]).min() > 0.0
+    o.step(150)
+    o.set_velocities(-o.velocities())
+    xi, eta = o.nhc()
+    o.set_nhc(-xi, eta)
+    o.step(150)
+    d = o.positions() - x0
+    d[0] -= spec.box[0] * np.round(d[0] / spec.box[0])
+    assert np.abs(d).max() < 1e-9
+    np.testing.assert_allclose(-o.velocities(), v0, atol=1e-9)
+    xi1, eta1 = o.nhc()
+    np.testing.assert_allclose(-xi1, xi0, atol=1e-9)
+    np.testing.assert_allclose(eta1, eta0, atol=1e-9)
+
+
+@pytest.mark.parametrize("bias", [0, 1])
+def test_nhc_extended_energy_error_is_second_order(oracle_mod, bias):
+    """K + V (+ dV) + the chain's energy is the conserved quantity of the
+    Nose-Hoover chain; velocity Verlet keeps it to O(dt^2)."""
+    base = small2d(kT=0.1, x_slider=0.15)
+    x = perturbed(base, 0.04, 8)
+    spec = _bias_spec(oracle_mod, small2d, x, base.pos.copy(), frac=0.3) if bias else base
+    spec.kT = 0.1
+    _nhc(spec)
+
+    def spread(dt, nsteps):
+        s = spec.copy(); s.dt = dt
+        o = oracle_mod.OracleSystem(s, x=x)
+        o.init_velocities()
+        tot = []
+        for _ in range(nsteps):
+            o.step(1)
+            sc = o.scalars()
+            tot.append(sc["e_pot"] + sc["e_kin"] + sc["dv"] + sc["e_nhc"])
+        tot = np.array(tot)
+        return tot.max() - tot.min(), o.nhc()[0]
+
+    e1, xi = spread(0.004, 250)
+    e2, _ = spread(0.002, 500)
+    assert np.abs(xi).max() > 1e-3            # the chain did work
+    assert 3.0 < e1 / e2 < 5.0
+
+
+@pytest.mark.slow
+def test_nhc_equipartition(oracle_mod):
+    """The chain holds the kinetic temperature at kT: <K> = N_f kT / 2 with
+    N_f the integrated degrees of freedom (mobile atoms and the rigid body)."""
+    spec = _nhc(small2d(kT=0.1))
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    o.step(1000)
+    ndof = 2 * int((spec.role == ROLE_MOBILE).sum()) + 2
+    ks = []
+    for _ in range(400):
+        o.step(10)
+        ks.append(o.scalars()["e_kin"])
+    assert np.mean(ks) / (0.5 * ndof) == pytest.approx(spec.kT, rel=0.04)
+
+
+def test_nhc_single_thermostat_fixes_the_mean_kinetic_energy(oracle_mod):
+    """With one thermostat, Q dxi/dt = 2K - N_f kT: over a long bounded run
+    its time average vanishes, so <2K> = N_f kT whatever the dynamics.  The
+    rigid body alone (a harmonic oscillator along x, free along y) has
+    N_f = 2."""
+    spec = _nhc(_harmonic_rigid_system(4.0, 10, 1.0, 0.0, 0.05), tau=0.5, M=1)
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    k2 = []
+    for _ in range(40000):
+        o.step(1)
+        k2.append(2.0 * o.scalars()["e_kin"])
+    assert np.mean(k2[5000:]) == pytest.approx(2 * spec.kT, rel=0.05)
