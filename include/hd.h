@@ -136,6 +136,8 @@ typedef struct {
                          it; 0 otherwise) */
     double dv1, dv2;  /* the two switches combined by eq. 13 (dv2 = 0 with
                          one variable) */
+    double e_nhc;     /* Nose-Hoover chain energy (0 under Langevin): with
+                         e_pot + e_kin + dv it is conserved */
 } hd_scalars;
 
 enum { HD_FLAG_UNSTABLE = 1, HD_FLAG_NBR_OVERFLOW = 2 };
@@ -203,6 +205,18 @@ hd_status hd_set_tip_bonds(hd_ctx *ctx, int32_t sys, int32_t enabled, double k_b
  * with two variables, dv_max = 0.  Systems with any other choice than the
  * slope alone run on the grid kernels (never LDS-resident). */
 hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t var2, double lo2, double hi2);
+
+/* Thermostat of system `sys`: chain_len = 0 keeps Langevin BAOAB (the
+ * default, friction gamma of hd_thermo_params); 1..4 selects the paper's
+ * Nose-Hoover chain (Sec. 3.1.1) of that many thermostats with relaxation
+ * time tau: masses Q_1 = N_f kT tau^2 and Q_j = kT tau^2, N_f the mobile
+ * atoms' coordinates plus the rigid body's.  A step is the chain over dt/2,
+ * velocity Verlet (half kick, full drift, forces, half kick), the chain over
+ * dt/2, with the Trotter splitting of Martyna, Tuckerman, Tobias and Klein
+ * (1996); gamma is then unused.  The chain starts at rest.  Before
+ * hd_finalize only (HD_E_STATE after); HD_E_ARG for chain_len outside 0..4,
+ * tau <= 0 or kT <= 0.  Such systems run on the grid kernels. */
+hd_status hd_set_nose_hoover(hd_ctx *ctx, int32_t sys, int32_t chain_len, double tau);
 
 /* Basin minimum r_O (eq. 7), SoA [dim][n]. */
 hd_status hd_set_reference(hd_ctx *ctx, int32_t sys, const double *rO);

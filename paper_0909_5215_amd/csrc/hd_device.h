@@ -60,6 +60,11 @@ struct SysDesc {
   // one of them (the pair pass then accumulates T[u,u])
   int32_t bias_var1, bias_var2, gen_bias, curv;
   double b2_lo, b2_hi, inv_glh2;
+  // thermostat: 0 Langevin (BAOAB), 1 Nose-Hoover chain of nhc_len
+  // thermostats, masses nhc_Q1 = N_f kT tau^2 and nhc_Q = kT tau^2, with
+  // nhc_NfkT = N_f kT (grid kernels only)
+  int32_t thermostat, nhc_len;
+  double nhc_Q1, nhc_Q, nhc_NfkT;
 };
 
 // Mutable per-system state.
@@ -71,6 +76,8 @@ struct SysState {
   int32_t flags, n_rebuilds;
   int32_t rebuild, pad1;
   double kappa, dv1, dv2;
+  double xi[4], eta[4];        // Nose-Hoover chain velocities and positions
+  double e_nhc;                // the chain's energy (conserved with K + V + dV)
 };
 
 struct Arrays {

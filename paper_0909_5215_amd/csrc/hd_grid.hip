@@ -27,6 +27,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nt) {
 template <int DIM, typename T>
 __device__ void rigid_advance(const SysDesc &D, const SysState &st, int64_t step, double XRn[3],
                               double VRn[3]) {
+  if (D.thermostat == 1) {   // Nose-Hoover chain: B and a full A
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double v = st.VR[k] + D.hdt * st.FR[k] * D.inv_massR;
+      XRn[k] = st.XR[k] + D.dt * v;
+      VRn[k] = v;
+    }
+    return;
+  }
   double z[3];
   noise<DIM, T>(D.seed, step, (uint32_t)D.n, z);
 #pragma unroll
@@ -41,8 +50,9 @@ __device__ void rigid_advance(const SysDesc &D, const SysState &st, int64_t step
   }
 }
 
-// B A O A for every atom of the tile; rigid atoms follow the rigid body, which
-// each of their threads advances identically.  Also refreshes u and raises
+// B A O A for every atom of the tile (B and a full A under the Nose-Hoover
+// chain, whose velocity scalings are separate launches); rigid atoms follow
+// the rigid body, which each of their threads advances identically.  Also refreshes u and raises
 // the system's rebuild flag when an atom has left its skin.
 template <int DIM, typename T>
 __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A, const Tile &t,
@@ -62,7 +72,16 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
   const int64_t step = st.step;
   double xn[3] = {0, 0, 0};
   if (role == ROLE_MOBILE) {
-    if (!compute_only) {
+    if (!compute_only && D.thermostat == 1) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const double v = A.v[k * N + a] + D.hdt * A.ftot[k * N + a] * D.inv_mass;
+        const double x = wrapx(A.x[k * N + a] + D.dt * v, D.box[k], D.periodic[k]);
+        A.x[k * N + a] = x;
+        A.v[k * N + a] = v;
+        xn[k] = x;
+      }
+    } else if (!compute_only) {
       double z[3];
       noise<DIM, T>(D.seed, step, (uint32_t)i, z);
 #pragma unroll
@@ -720,6 +739,77 @@ __global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ desc
   }
 }
 
+// Nose-Hoover chain (Martyna, Klein, Tuckerman 1992) over half a step h, one
+// workgroup per system, before the drift and after the kick: 2K of the
+// mobile atoms and the rigid body, then the thermostat velocities from the
+// chain's end inwards over h/2, the particle velocities scaled by
+// exp(-xi_1 h) and the thermostat positions advanced by h, the thermostat
+// velocities outwards over h/2 (each inner update inside exp(-xi_{j+1} h/4)
+// factors; Trotter splitting of Martyna, Tuckerman, Tobias, Klein 1996).
+__device__ __forceinline__ double nhc_force(const SysDesc &D, const SysState &st, int j, double k2) {
+  if (j == 0) return (k2 - D.nhc_NfkT) / D.nhc_Q1;
+  const double Qp = j == 1 ? D.nhc_Q1 : D.nhc_Q;
+  return (Qp * st.xi[j - 1] * st.xi[j - 1] - D.kT) / D.nhc_Q;
+}
+
+__global__ __launch_bounds__(256) void kg_nhc_half(const SysDesc *__restrict__ descs,
+                                                   SysState *__restrict__ states, Arrays A,
+                                                   const int32_t *__restrict__ sys_ids) {
+  __shared__ double red[16];
+  __shared__ double scale_sh;
+  const int s = sys_ids[blockIdx.x];
+  const SysDesc &D = descs[s];
+  if (D.thermostat != 1) return;
+  SysState &st = states[s];
+  const int64_t N = A.ntot;
+  double k2[1] = {0.0};
+  for (int i = threadIdx.x; i < D.n; i += blockDim.x) {
+    const int64_t a = D.off + i;
+    if ((A.tr[a] >> 1) != ROLE_MOBILE) continue;
+    for (int k = 0; k < D.dim; ++k) { const double v = A.v[k * N + a]; k2[0] += D.mass * v * v; }
+  }
+  block_sum<1>(k2, red);
+  if (threadIdx.x == 0) {
+    double K2 = k2[0];
+    if (D.n_rigid > 0)
+      for (int k = 0; k < D.dim; ++k) K2 += D.massR * st.VR[k] * st.VR[k];
+    const int M = D.nhc_len;
+    const double h = D.hdt;
+    st.xi[M - 1] += 0.5 * h * nhc_force(D, st, M - 1, K2);
+    for (int j = M - 2; j >= 0; --j) {
+      const double e = exp(-0.25 * h * st.xi[j + 1]);
+      st.xi[j] *= e;
+      st.xi[j] += 0.5 * h * nhc_force(D, st, j, K2);
+      st.xi[j] *= e;
+    }
+    const double c = exp(-h * st.xi[0]);
+    K2 *= c * c;
+    for (int j = 0; j < M; ++j) st.eta[j] += h * st.xi[j];
+    for (int j = 0; j < M - 1; ++j) {
+      const double e = exp(-0.25 * h * st.xi[j + 1]);
+      st.xi[j] *= e;
+      st.xi[j] += 0.5 * h * nhc_force(D, st, j, K2);
+      st.xi[j] *= e;
+    }
+    st.xi[M - 1] += 0.5 * h * nhc_force(D, st, M - 1, K2);
+    for (int k = 0; k < D.dim; ++k) st.VR[k] *= c;
+    double en = D.nhc_NfkT * st.eta[0];
+    for (int j = 0; j < M; ++j) {
+      en += 0.5 * (j == 0 ? D.nhc_Q1 : D.nhc_Q) * st.xi[j] * st.xi[j];
+      if (j > 0) en += D.kT * st.eta[j];
+    }
+    st.e_nhc = en;
+    scale_sh = c;
+  }
+  __syncthreads();
+  const double c = scale_sh;
+  for (int i = threadIdx.x; i < D.n; i += blockDim.x) {
+    const int64_t a = D.off + i;
+    if ((A.tr[a] >> 1) == ROLE_FIXED) continue;
+    for (int k = 0; k < D.dim; ++k) A.v[k * N + a] *= c;
+  }
+}
+
 // Kinetic energy per system (mobile atoms + rigid body), one workgroup each.
 __global__ __launch_bounds__(256) void kg_ekin(const SysDesc *__restrict__ descs,
                                                SysState *__restrict__ states, Arrays A,
@@ -751,6 +841,10 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
   const int nt = P.ntiles, B = P.block, co = compute_only ? 1 : 0;
   GridScal *gs = (GridScal *)P.gscal;
   int nl = 0;
+  if (!compute_only && P.any_nhc) {
+    hipLaunchKernelGGL(kg_nhc_half, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids);
+    ++nl;
+  }
   if (compute_only && force_rebuild) {
     hipLaunchKernelGGL(kg_set_flags, dim3((P.nsys + 255) / 256), dim3(256), 0, stream,
                        A.rebuild_flag, P.sys_ids, P.nsys, 1);
@@ -790,6 +884,10 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
                      P.tiles, gs, co);
   hipLaunchKernelGGL(kg_kick, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, co);
   nl += 9;
+  if (!compute_only && P.any_nhc) {
+    hipLaunchKernelGGL(kg_nhc_half, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids);
+    ++nl;
+  }
   if (launches) *launches += nl;
   return hipGetLastError();
 }

@@ -63,6 +63,7 @@ struct GridPlan {
   void *gscal;             // device, per-system scalars of the last evaluation
   int any_bonds;           // some covered system has harmonic tip bonds
   int any_curv;            // some covered system is biased on the curvature
+  int any_nhc;             // some covered system has the Nose-Hoover chain
 };
 
 size_t grid_scal_bytes();

@@ -43,6 +43,10 @@ struct SysHost {
   // hd_bias_params, var2 (-1: none) a second one, combined by eq. 13
   int bias_var1 = HD_BIAS_SLOPE, bias_var2 = -1;
   double b2_lo = 0.0, b2_hi = 1.0;
+  // thermostat (hd_set_nose_hoover): 0 Langevin, else a Nose-Hoover chain
+  // of nhc_len thermostats with relaxation time nhc_tau
+  int nhc_len = 0;
+  double nhc_tau = 0.5;
   int n_rigid = 0, first_rigid = -1;
   double XR[3] = {0, 0, 0}, XR0[3] = {0, 0, 0};
   bool init_vel = false;
@@ -50,9 +54,9 @@ struct SysHost {
 };
 
 // Systems the LDS-resident and one-workgroup kernels do not cover: models
-// with tip bonds and biases beyond the slope alone.
+// with tip bonds, biases beyond the slope alone, the Nose-Hoover chain.
 static bool grid_only(const SysHost &h) {
-  return h.tip_bonds || h.bias_var1 != HD_BIAS_SLOPE || h.bias_var2 >= 0;
+  return h.tip_bonds || h.bias_var1 != HD_BIAS_SLOPE || h.bias_var2 >= 0 || h.nhc_len > 0;
 }
 
 struct Plan {
@@ -268,6 +272,18 @@ void fill_desc(const hd_ctx *ctx, const SysHost &s, SysDesc &D) {
   D.b2_lo = s.b2_lo;
   D.b2_hi = s.b2_hi;
   D.inv_glh2 = (s.b2_lo != s.b2_hi) ? 1.0 / (s.b2_lo - s.b2_hi) : 0.0;
+  D.thermostat = s.nhc_len > 0 ? 1 : 0;
+  D.nhc_len = s.nhc_len;
+  {
+    // N_f: the mobile atoms' coordinates and the rigid body's
+    int nm = 0;
+    for (int i = 0; i < s.n; ++i) nm += s.role[i] == hdk::ROLE_MOBILE;
+    const int nf = s.dim * (nm + (s.n_rigid > 0 ? 1 : 0));
+    const double t2 = s.nhc_tau * s.nhc_tau;
+    D.nhc_NfkT = nf * s.th.kT;
+    D.nhc_Q1 = D.nhc_NfkT * t2;
+    D.nhc_Q = s.th.kT * t2;
+  }
   D.inv_nR = s.n_rigid > 0 ? 1.0 / s.n_rigid : 0.0;
   D.k_nR2 = s.n_rigid > 0 ? s.dr.k_spring / ((double)s.n_rigid * s.n_rigid) : 0.0;
   (void)ctx;
@@ -361,6 +377,7 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
     max_ncell = std::max(max_ncell, ctx->h_desc[s].ncell);
     if (ctx->sys[s].tip_bonds) P.gp.any_bonds = 1;
     if (ctx->h_desc[s].curv) P.gp.any_curv = 1;
+    if (ctx->h_desc[s].thermostat == 1) P.gp.any_nhc = 1;
   }
   hd_status st = dalloc(ctx, &P.d_tiles, tiles.size(), true);
   if (st != HD_OK) return st;
@@ -788,6 +805,8 @@ hd_status hd_set_thermo(hd_ctx *ctx, int32_t sys, const hd_thermo_params *thermo
   CHECK_CTX();
   if (check_sys(ctx, sys) != HD_OK || !thermo) return fail(ctx, HD_E_ARG, "bad system or null thermo");
   if (!(thermo->dt > 0) || thermo->gamma < 0 || thermo->kT < 0) return fail(ctx, HD_E_ARG, "bad thermostat");
+  if (ctx->sys[sys].nhc_len > 0 && !(thermo->kT > 0))
+    return fail(ctx, HD_E_ARG, "the Nose-Hoover chain needs kT > 0");
   ctx->sys[sys].th = *thermo;
   if (ctx->finalized) { ctx->need_eval = true; return upload_desc(ctx, sys); }
   return HD_OK;
@@ -820,6 +839,19 @@ hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t 
   s.bias_var2 = var2;
   s.b2_lo = var2 >= 0 ? lo2 : 0.0;
   s.b2_hi = var2 >= 0 ? hi2 : 1.0;
+  return HD_OK;
+}
+
+hd_status hd_set_nose_hoover(hd_ctx *ctx, int32_t sys, int32_t chain_len, double tau) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK) return fail(ctx, HD_E_ARG, "bad system");
+  SysHost &s = ctx->sys[sys];
+  if (chain_len < 0 || chain_len > 4) return fail(ctx, HD_E_ARG, "chain length 0 (Langevin) to 4");
+  if (chain_len > 0 && !(tau > 0 && s.th.kT > 0))
+    return fail(ctx, HD_E_ARG, "the Nose-Hoover chain needs tau > 0 and kT > 0");
+  if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_nose_hoover after hd_finalize");
+  s.nhc_len = chain_len;
+  s.nhc_tau = chain_len > 0 ? tau : 0.5;
   return HD_OK;
 }
 
@@ -1271,6 +1303,7 @@ hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
   out->kappa = T.kappa;
   out->dv1 = T.dv1;
   out->dv2 = T.dv2;
+  out->e_nhc = T.e_nhc;
   return HD_OK;
 }
 

@@ -61,7 +61,8 @@ class hd_scalars(_c.Structure):
                 ("t_md", _c.c_double), ("t_hyper", _c.c_double), ("x_slider", _c.c_double),
                 ("x_tip", _c.c_double), ("f_lat", _c.c_double), ("step", _c.c_int64),
                 ("flags", _c.c_int32), ("n_rebuilds", _c.c_int32),
-                ("kappa", _c.c_double), ("dv1", _c.c_double), ("dv2", _c.c_double)]
+                ("kappa", _c.c_double), ("dv1", _c.c_double), ("dv2", _c.c_double),
+                ("e_nhc", _c.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -119,6 +120,7 @@ _SIGS = {
                                _c.POINTER(_c.c_int32), _dp]),
     "hd_set_tip_bonds": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double, _c.c_double]),
     "hd_set_bias_variables": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double]),
+    "hd_set_nose_hoover": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double]),
     "hd_last_error": (_c.c_char_p, [_P]),
     "hd_destroy": (None, [_P]),
 }
@@ -230,6 +232,8 @@ class Context:
             self.set_bias_variables(s, v1, v2, getattr(spec, "b2_lo", 0.0), getattr(spec, "b2_hi", 1.0))
         if spec.bias_on:
             self.set_bias(s, True, spec.m_b, spec.dv_max, spec.g_lo, spec.g_hi)
+        if int(getattr(spec, "thermostat", 0)) == 1:
+            self.set_nose_hoover(s, int(getattr(spec, "nhc_len", 3)), float(getattr(spec, "nhc_tau", 0.5)))
         if getattr(spec, "tip_bonds", 0):
             self.set_tip_bonds(s, True, spec.k_bond, spec.r_bond, spec.r_bond_cut)
         return s
@@ -237,6 +241,9 @@ class Context:
     def set_tip_bonds(self, s: int, enabled: bool, k_bond: float, r_bond: float, r_cut: float):
         _check(self._h, load().hd_set_tip_bonds(self._h, s, int(bool(enabled)), float(k_bond), float(r_bond),
                                                 float(r_cut)), "hd_set_tip_bonds")
+
+    def set_nose_hoover(self, s: int, chain_len: int, tau: float = 0.5):
+        _check(self._h, load().hd_set_nose_hoover(self._h, s, int(chain_len), float(tau)), "hd_set_nose_hoover")
 
     def set_bias_variables(self, s: int, var1: int, var2: int = -1, lo2: float = 0.0, hi2: float = 1.0):
         _check(self._h, load().hd_set_bias_variables(self._h, s, int(var1), int(var2), float(lo2), float(hi2)),
