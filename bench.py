@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--bias", default="slope", choices=sorted(BIAS_CHOICES),
                     help="bias variables (eq. 13 combines two)")
+    ap.add_argument("--thermostat", default="langevin", choices=["langevin", "nhc"],
+                    help="Langevin BAOAB or the Nose-Hoover chain (3 thermostats, tau = 0.5)")
     ap.add_argument("--plain-steps", type=int, default=0, help="steps per system of the plain path (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -309,7 +311,11 @@ def main():
     v1, v2 = BIAS_CHOICES[args.bias]
     for s in specs:
         s.bias_var1, s.bias_var2 = v1, v2
+        if args.thermostat == "nhc":
+            s.thermostat, s.nhc_len, s.nhc_tau = 1, 3, 0.5
     ckey = args.config if args.bias == "slope" else f"{args.config}/{args.bias}"
+    if args.thermostat != "langevin":
+        ckey += f"/{args.thermostat}"
     n_atoms = sum(s.n for s in specs)
     dim = specs[0].dim
     log(f"{args.config}: {len(specs)} systems, {n_atoms} atoms")
@@ -422,7 +428,8 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {desc}", "bias": args.bias, "systems": len(specs), "atoms": n_atoms,
+        "config": {"workload": f"{args.config}: {desc}", "bias": args.bias, "thermostat": args.thermostat,
+                   "systems": len(specs), "atoms": n_atoms,
                    "dim": dim, "parallelism": "batch of independent slider positions, 1 GPU"},
         "roofline": roof,
         "roofline_valu": valu,
