@@ -332,3 +332,28 @@ def lowest_hessian_eigenvalue(spec, x=None):
     H = reduced_hessian(spec, x)
     vals, vecs = np.linalg.eigh(0.5 * (H + H.T))
     return float(vals[0]), vecs[:, 0]
+
+
+def dof_project(spec, a):
+    """An atom vector [dim][n] projected onto the degrees of freedom (the
+    transpose of dof_to_atoms): mobile atoms' entries, then the sum over the
+    rigid atoms."""
+    mob, rig, m = dof_layout(spec)
+    out = list(np.asarray(a)[:, mob].T.reshape(-1))
+    if len(rig):
+        out += list(np.asarray(a)[:, rig].sum(axis=1))
+    return np.array(out)
+
+
+def eigenvalue_gradient(spec, x=None):
+    """Gradient of the lowest eigenvalue eps over the degrees of freedom
+    (its derivative for the eigenvalue bias of eq. 13 and eq. 15): for a
+    simple eigenvalue with unit eigenvector q, d eps = q^T dH q, i.e. the
+    third derivatives of V contracted twice with the atom displacement
+    w = P q -- the oracle's T[u,u] at u = w -- projected back by P^T.
+    Returns (eps, q, gradient)."""
+    x = np.asarray(spec.pos if x is None else x, dtype=np.float64)
+    eps, q = lowest_hessian_eigenvalue(spec, x)
+    o = OracleSystem(spec, x=x, rO=x - dof_to_atoms(spec, q))
+    o.set_params(bias_on=0)
+    return eps, q, dof_project(spec, o.compute()["tuu"])

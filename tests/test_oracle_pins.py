@@ -949,3 +949,24 @@ def test_nhc_single_thermostat_fixes_the_mean_kinetic_energy(oracle_mod):
         o.step(1)
         k2.append(2.0 * o.scalars()["e_kin"])
     assert np.mean(k2[5000:]) == pytest.approx(2 * spec.kT, rel=0.05)
+
+
+@pytest.mark.parametrize("maker", [small2d, small_cone], ids=["2d", "cone"])
+def test_eigenvalue_gradient_matches_eigenvalue_differences(oracle_mod, maker):
+    """d eps / d y for a degree of freedom y against central differences of
+    the library eigenvalue of the reduced Hessian (mobile atoms and the
+    rigid body)."""
+    spec = maker(x_slider=0.1)
+    spec.pos = perturbed(spec, 0.04, 31)
+    eps, q, grad = oracle_mod.eigenvalue_gradient(spec)
+    mob, rig, m = oracle_mod.dof_layout(spec)
+    h = 1e-5
+    scale = np.abs(grad).max()
+    picks = list(range(0, spec.dim * len(mob), max(1, spec.dim * len(mob) // 6))) + [m - 2, m - 1]
+    for c in picks:
+        e = np.zeros(m)
+        e[c] = h
+        dx = oracle_mod.dof_to_atoms(spec, e)
+        ep = oracle_mod.lowest_hessian_eigenvalue(spec, spec.pos + dx)[0]
+        em = oracle_mod.lowest_hessian_eigenvalue(spec, spec.pos - dx)[0]
+        assert abs((ep - em) / (2 * h) - grad[c]) <= 1e-5 * scale, c
