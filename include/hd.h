@@ -367,6 +367,21 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
 hd_status hd_min_mode(hd_ctx *ctx, int32_t sys, int32_t max_iter, double tol, uint64_t seed, double *eps,
                       int32_t *iters, double *mode);
 
+/* Gradient of the lowest eigenvalue eps over the degrees of freedom, what
+ * the eigenvalue bias of eq. 13 and eq. 15 differentiates: for a simple
+ * eigenvalue with unit eigenvector q, d eps = q^T dH q, the third
+ * derivatives of V contracted twice with the atom displacement w = P q.
+ * One GPU evaluation of the pair pass with u = w that also accumulates
+ * T[u,u] (the kernels of the curvature bias), projected by P^T.
+ * mode: hd_min_mode's output layout, [dim][n] host doubles (read: mobile
+ * atoms and the first rigid atom; normalised here over the degrees of
+ * freedom).  grad: [dim][n] host doubles, written: each mobile atom's
+ * derivative, on every rigid atom the rigid body's (the sum over its atoms),
+ * fixed atoms 0.  The run state is restored afterwards.  HD_E_STATE before
+ * hd_finalize or when the system does not run on the grid kernels
+ * (HD_EXEC_GRID puts every system there); HD_E_ARG for a zero mode. */
+hd_status hd_min_mode_gradient(hd_ctx *ctx, int32_t sys, const double *mode, double *grad);
+
 /* Per-kernel timing of the last hd_step, measured with HIP events on the
  * context stream: total milliseconds and launches. */
 hd_status hd_last_step_timing(hd_ctx *ctx, double *ms, int64_t *launches);

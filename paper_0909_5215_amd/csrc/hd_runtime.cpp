@@ -1837,6 +1837,103 @@ hd_status hd_min_mode(hd_ctx *ctx, int32_t sys, int32_t max_iter, double tol, ui
   return sync_out(ctx);
 }
 
+hd_status hd_min_mode_gradient(hd_ctx *ctx, int32_t sys, const double *mode, double *grad) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_min_mode_gradient before hd_finalize");
+  if (check_sys(ctx, sys) != HD_OK || !mode || !grad)
+    return fail(ctx, HD_E_ARG, "hd_min_mode_gradient needs a valid system, a mode and an output");
+  Plan *plan = nullptr;
+  for (auto &P : ctx->plans)
+    if (std::find(P.ids.begin(), P.ids.end(), sys) != P.ids.end()) plan = &P;
+  if (!plan)
+    return fail(ctx, HD_E_STATE, "hd_min_mode_gradient needs the system on the grid kernels (HD_EXEC_GRID, "
+                                 "or a system with tip bonds, a general bias or the Nose-Hoover chain)");
+  const SysHost &h = ctx->sys[sys];
+  const int dim = h.dim, n = h.n;
+  const size_t nd = (size_t)dim * n;
+  // w = P q from the mode (mobile atoms' entries, the rigid body's taken from
+  // its first atom), normalised over the degrees of freedom
+  std::vector<double> w(nd, 0.0);
+  double nq = 0.0;
+  for (int i = 0; i < n; ++i)
+    if (h.role[i] == HD_ROLE_MOBILE)
+      for (int d = 0; d < dim; ++d) nq += mode[(size_t)d * n + i] * mode[(size_t)d * n + i];
+  if (h.n_rigid > 0)
+    for (int d = 0; d < dim; ++d) nq += mode[(size_t)d * n + h.first_rigid] * mode[(size_t)d * n + h.first_rigid];
+  if (!(nq > 0.0) || !std::isfinite(nq)) return fail(ctx, HD_E_ARG, "the mode is zero or not finite");
+  const double inv = 1.0 / std::sqrt(nq);
+  for (int i = 0; i < n; ++i) {
+    const int src = h.role[i] == HD_ROLE_RIGID ? h.first_rigid : i;
+    if (h.role[i] != HD_ROLE_FIXED)
+      for (int d = 0; d < dim; ++d) w[(size_t)d * n + i] = mode[(size_t)d * n + src] * inv;
+  }
+  hd_status st = sync_in(ctx);
+  if (st != HD_OK) return st;
+  if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
+  const int S = (int)ctx->sys.size();
+  std::vector<std::vector<char>> ck(S);
+  for (int s = 0; s < S; ++s) {
+    size_t b = 0;
+    if ((st = hd_get_state(ctx, s, nullptr, &b)) != HD_OK) return st;
+    ck[s].resize(b);
+    if ((st = hd_get_state(ctx, s, ck[s].data(), &b)) != HD_OK) return st;
+  }
+  const size_t N = (size_t)ctx->ntot;
+  const size_t ubytes = 3 * N * (ctx->prec == HD_FP64 ? sizeof(double) : sizeof(float));
+  struct Saved { void *dev; void *copy; size_t bytes; };
+  std::vector<Saved> saved = {{ctx->A.flj, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.hu, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.fb, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.tuu, nullptr, 3 * N * sizeof(double)},
+                              {ctx->A.eatom, nullptr, N * sizeof(double)},
+                              {ctx->A.u, nullptr, ubytes}};
+  auto release = [&]() {
+    for (auto &v : saved)
+      if (v.copy) (void)hipFree(v.copy);
+  };
+  hipError_t e = hipSuccess;
+  for (auto &v : saved) {
+    if ((e = hipMalloc(&v.copy, v.bytes)) != hipSuccess ||
+        (e = hipMemcpyAsync(v.copy, v.dev, v.bytes, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess) {
+      release();
+      return fail(ctx, HD_E_HIP, std::string("hd_min_mode_gradient: ") + hipGetErrorString(e));
+    }
+  }
+  // one evaluation with u = w (r_O moved) in the pair kernels that also
+  // accumulate T[u,u]
+  const double *x = (const double *)(ck[sys].data() + sizeof(CkptHeader));
+  std::vector<double> rO_tmp(nd), t(nd);
+  for (size_t k = 0; k < nd; ++k) rO_tmp[k] = x[k] - w[k];
+  for (int d = 0; d < dim && e == hipSuccess; ++d)
+    e = hipMemcpyAsync(ctx->A.rO + d * ctx->ntot + ctx->h_desc[sys].off, rO_tmp.data() + (size_t)d * n,
+                       sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream);
+  const int curv_was = plan->gp.any_curv;
+  plan->gp.any_curv = 1;
+  if (e == hipSuccess) st = evaluate_all(ctx);
+  plan->gp.any_curv = curv_was;
+  if (e == hipSuccess && st == HD_OK) st = copy_field(ctx, sys, ctx->A.tuu, t.data(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  // restore the run state
+  for (auto &v : saved)
+    if (e == hipSuccess) e = hipMemcpyAsync(v.dev, v.copy, v.bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  release();
+  if (e != hipSuccess) return fail(ctx, HD_E_HIP, std::string("hd_min_mode_gradient: ") + hipGetErrorString(e));
+  if (st != HD_OK) return st;
+  if ((st = restore_all(ctx, ck)) != HD_OK) return st;
+  // d eps / d y = P^T T[w, w]: mobile atoms' rows, the rigid body's the sum
+  // over its atoms (written on each rigid atom)
+  double tR[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < n; ++i)
+    if (h.role[i] == HD_ROLE_RIGID)
+      for (int d = 0; d < dim; ++d) tR[d] += t[(size_t)d * n + i];
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < dim; ++d)
+      grad[(size_t)d * n + i] = h.role[i] == HD_ROLE_MOBILE ? t[(size_t)d * n + i]
+                                : h.role[i] == HD_ROLE_RIGID ? tR[d] : 0.0;
+  return sync_out(ctx);
+}
+
 hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int64_t *n_pairs) {
   CHECK_CTX();
   if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");

@@ -118,6 +118,7 @@ _SIGS = {
                              _c.POINTER(_c.c_int64), _dp, _dp]),
     "hd_min_mode": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_uint64, _dp,
                                _c.POINTER(_c.c_int32), _dp]),
+    "hd_min_mode_gradient": (_c.c_int, [_P, _c.c_int32, _dp, _dp]),
     "hd_set_tip_bonds": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double, _c.c_double]),
     "hd_set_bias_variables": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double]),
     "hd_set_nose_hoover": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double]),
@@ -351,6 +352,15 @@ class Context:
         _check(self._h, load().hd_min_mode(self._h, int(s), int(max_iter), float(tol), int(seed), ctypes.byref(eps),
                                            ctypes.byref(it), _darr(m)), "hd_min_mode")
         return eps.value, it.value, m
+
+    def min_mode_gradient(self, s: int, mode: np.ndarray) -> np.ndarray:
+        """Gradient of the lowest eigenvalue over system s's degrees of
+        freedom (hd_min_mode_gradient), [dim][n]: mobile atoms' rows, the
+        rigid body's on each rigid atom."""
+        g = self._out(s) if 0 <= s < len(self.dims) else np.zeros(1)
+        q = np.ascontiguousarray(mode, dtype=np.float64)
+        _check(self._h, load().hd_min_mode_gradient(self._h, int(s), _darr(q), _darr(g)), "hd_min_mode_gradient")
+        return g
 
     # -- read-outs --------------------------------------------------------
     def _out(self, s):
