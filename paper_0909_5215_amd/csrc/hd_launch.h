@@ -43,8 +43,14 @@ struct FireSys {
 // atom counts) from the forces in A.ftot and the rigid-body force in the
 // state: convergence test on the largest force (< ftol), velocity mixing and
 // semi-implicit Euler step.  Forces must be re-evaluated before the next one.
+// partials: device scratch of fire_partials_doubles(count, nmax) doubles.
+constexpr int kFireChunk = 2048;   // atoms per first-level reduction block
+inline size_t fire_partials_doubles(int count, int nmax) {
+  return (size_t)count * (size_t)((nmax + kFireChunk - 1) / kFireChunk) * 4;
+}
 hipError_t fire_iteration(const SysDesc *descs, SysState *states, const Arrays &A, const int32_t *sys_list,
-                          int count, int nmax, FireSys *fire, double ftol, int64_t iter, hipStream_t stream);
+                          int count, int nmax, FireSys *fire, double ftol, int64_t iter, double *partials,
+                          hipStream_t stream);
 
 // Tiles of the grid scheduler: each tile is a contiguous atom range of one
 // system (tiles never straddle systems).

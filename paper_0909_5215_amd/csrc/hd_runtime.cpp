@@ -1505,11 +1505,13 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
                               {ctx->A.u, nullptr, ubytes}};
   int32_t *d_list = nullptr;
   hdk::FireSys *d_fire = nullptr;
+  double *d_fpart = nullptr;
   auto release = [&]() {
     for (auto &v : saved)
       if (v.copy) (void)hipFree(v.copy);
     if (d_list) (void)hipFree(d_list);
     if (d_fire) (void)hipFree(d_fire);
+    if (d_fpart) (void)hipFree(d_fpart);
   };
   auto hip_fail = [&](hipError_t e) {
     release();
@@ -1523,6 +1525,8 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
   }
   if ((e = hipMalloc(&d_list, sizeof(int32_t) * count)) != hipSuccess) return hip_fail(e);
   if ((e = hipMalloc(&d_fire, sizeof(hdk::FireSys) * count)) != hipSuccess) return hip_fail(e);
+  if ((e = hipMalloc(&d_fpart, sizeof(double) * hdk::fire_partials_doubles(count, nmax))) != hipSuccess)
+    return hip_fail(e);
   std::vector<hdk::FireSys> fs(count);
   for (int k = 0; k < count; ++k) {
     fs[k] = hdk::FireSys{};
@@ -1562,7 +1566,7 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
   int64_t it = 0;
   for (; st == HD_OK && it < max_iters; ++it) {
     if ((e = hdk::fire_iteration(ctx->d_desc, ctx->d_state, ctx->A, d_list, count, nmax, d_fire, ftol, it,
-                                 ctx->stream)) != hipSuccess)
+                                 d_fpart, ctx->stream)) != hipSuccess)
       break;
     if ((st = evaluate_all(ctx, false)) != HD_OK) break;
     if ((it & 31) == 31) {
