@@ -47,6 +47,14 @@ HBM_COUNTERS = {
         "src": ("hd_small.hip", "hd_device.h"), "sha": "1057f275dcdfdf11",
         "fetch_kib": 984.6, "fetch_scale": 2.0, "write_kib": 2896.3, "write_scale": 1.0,
     },
+    # the grid step as a whole: the float32 run's drift, pairs, kick and
+    # reduce launches of one step plus the list-rebuild launches averaged
+    # over steps (per_step: scaled by the steps one launch covers)
+    ("C3", "grid step (kg_* kernels, timed as a whole)"): {
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "edc10f4f6dea889c",
+        "fetch_kib": 277542.5, "fetch_scale": 2.0, "write_kib": 239648.0, "write_scale": 1.0,
+        "per_step": True,
+    },
 }
 
 # VALU wave-instructions of one launch of the stepping kernel (rocprofv3 --pmc
@@ -59,6 +67,10 @@ VALU_COUNTERS = {
     ("C2", "k_small<float, 2, 0, 512, false>"): {
         "src": ("hd_small.hip", "hd_device.h"), "sha": "1057f275dcdfdf11",
         "insts_valu": 1020319873.0, "steps": 2000,
+    },
+    ("C3", "grid step (kg_* kernels, timed as a whole)"): {
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "edc10f4f6dea889c",
+        "insts_valu": 123833232.0, "steps": 1,
     },
 }
 
@@ -356,6 +368,8 @@ def main():
     rec = HBM_COUNTERS.get((ckey, kname))
     if rec and src_hash(rec["src"]) == rec["sha"]:
         traffic_bytes = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+        if rec.get("per_step"):
+            traffic_bytes *= steps_per_launch
         traffic = round(traffic_bytes / avg_launch_s / 1e9, 4)
     # measured VALU issue of the stepping kernel (counters above), against the
     # chip and against the CUs the launch occupies (one workgroup per system
