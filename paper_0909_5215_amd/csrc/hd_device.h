@@ -248,6 +248,52 @@ __device__ __forceinline__ void bias_switch(const SysDesc &D, double v, double l
   dvp = -2.0 * D.m_b * D.dv_max * one * xm1 * inv;
 }
 
+// Nose-Hoover chain (Martyna, Klein, Tuckerman 1992) over half a step h =
+// dt/2 given twice the kinetic energy K2 of the thermostatted degrees of
+// freedom: the thermostat velocities xi from the chain's end inwards over
+// h/2, the particle velocities' scale factor exp(-xi_1 h) (returned) and the
+// thermostat positions eta advanced by h, then the thermostat velocities
+// outwards over h/2; each inner update sits between exp(-xi_{j+1} h/4)
+// factors (Trotter splitting of Martyna, Tuckerman, Tobias, Klein 1996).
+__device__ __forceinline__ double nhc_force(const SysDesc &D, const double *xi, int j, double k2) {
+  if (j == 0) return (k2 - D.nhc_NfkT) / D.nhc_Q1;
+  const double Qp = j == 1 ? D.nhc_Q1 : D.nhc_Q;
+  return (Qp * xi[j - 1] * xi[j - 1] - D.kT) / D.nhc_Q;
+}
+
+__device__ inline double nhc_half_step(const SysDesc &D, double *xi, double *eta, double K2) {
+  const int M = D.nhc_len;
+  const double h = D.hdt;
+  xi[M - 1] += 0.5 * h * nhc_force(D, xi, M - 1, K2);
+  for (int j = M - 2; j >= 0; --j) {
+    const double e = exp(-0.25 * h * xi[j + 1]);
+    xi[j] *= e;
+    xi[j] += 0.5 * h * nhc_force(D, xi, j, K2);
+    xi[j] *= e;
+  }
+  const double c = exp(-h * xi[0]);
+  K2 *= c * c;
+  for (int j = 0; j < M; ++j) eta[j] += h * xi[j];
+  for (int j = 0; j < M - 1; ++j) {
+    const double e = exp(-0.25 * h * xi[j + 1]);
+    xi[j] *= e;
+    xi[j] += 0.5 * h * nhc_force(D, xi, j, K2);
+    xi[j] *= e;
+  }
+  xi[M - 1] += 0.5 * h * nhc_force(D, xi, M - 1, K2);
+  return c;
+}
+
+// The chain's energy sum_j Q_j xi_j^2 / 2 + N_f kT eta_1 + kT sum_{j>1} eta_j.
+__device__ inline double nhc_energy(const SysDesc &D, const double *xi, const double *eta) {
+  double en = D.nhc_NfkT * eta[0];
+  for (int j = 0; j < D.nhc_len; ++j) {
+    en += 0.5 * (j == 0 ? D.nhc_Q1 : D.nhc_Q) * xi[j] * xi[j];
+    if (j > 0) en += D.kT * eta[j];
+  }
+  return en;
+}
+
 // Per-system scalars derived from the reduced sums (LJ part) and the rigid
 // body: drive energy and force, slope, bias.
 struct Scal {

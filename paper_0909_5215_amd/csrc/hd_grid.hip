@@ -739,19 +739,9 @@ __global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ desc
   }
 }
 
-// Nose-Hoover chain (Martyna, Klein, Tuckerman 1992) over half a step h, one
-// workgroup per system, before the drift and after the kick: 2K of the
-// mobile atoms and the rigid body, then the thermostat velocities from the
-// chain's end inwards over h/2, the particle velocities scaled by
-// exp(-xi_1 h) and the thermostat positions advanced by h, the thermostat
-// velocities outwards over h/2 (each inner update inside exp(-xi_{j+1} h/4)
-// factors; Trotter splitting of Martyna, Tuckerman, Tobias, Klein 1996).
-__device__ __forceinline__ double nhc_force(const SysDesc &D, const SysState &st, int j, double k2) {
-  if (j == 0) return (k2 - D.nhc_NfkT) / D.nhc_Q1;
-  const double Qp = j == 1 ? D.nhc_Q1 : D.nhc_Q;
-  return (Qp * st.xi[j - 1] * st.xi[j - 1] - D.kT) / D.nhc_Q;
-}
-
+// Nose-Hoover chain over half a step (nhc_half_step), one workgroup per
+// system, before the drift and after the kick: 2K of the mobile atoms and the
+// rigid body, the chain advanced by one thread, the velocities scaled.
 __global__ __launch_bounds__(256) void kg_nhc_half(const SysDesc *__restrict__ descs,
                                                    SysState *__restrict__ states, Arrays A,
                                                    const int32_t *__restrict__ sys_ids) {
@@ -773,32 +763,9 @@ __global__ __launch_bounds__(256) void kg_nhc_half(const SysDesc *__restrict__ d
     double K2 = k2[0];
     if (D.n_rigid > 0)
       for (int k = 0; k < D.dim; ++k) K2 += D.massR * st.VR[k] * st.VR[k];
-    const int M = D.nhc_len;
-    const double h = D.hdt;
-    st.xi[M - 1] += 0.5 * h * nhc_force(D, st, M - 1, K2);
-    for (int j = M - 2; j >= 0; --j) {
-      const double e = exp(-0.25 * h * st.xi[j + 1]);
-      st.xi[j] *= e;
-      st.xi[j] += 0.5 * h * nhc_force(D, st, j, K2);
-      st.xi[j] *= e;
-    }
-    const double c = exp(-h * st.xi[0]);
-    K2 *= c * c;
-    for (int j = 0; j < M; ++j) st.eta[j] += h * st.xi[j];
-    for (int j = 0; j < M - 1; ++j) {
-      const double e = exp(-0.25 * h * st.xi[j + 1]);
-      st.xi[j] *= e;
-      st.xi[j] += 0.5 * h * nhc_force(D, st, j, K2);
-      st.xi[j] *= e;
-    }
-    st.xi[M - 1] += 0.5 * h * nhc_force(D, st, M - 1, K2);
+    const double c = nhc_half_step(D, st.xi, st.eta, K2);
     for (int k = 0; k < D.dim; ++k) st.VR[k] *= c;
-    double en = D.nhc_NfkT * st.eta[0];
-    for (int j = 0; j < M; ++j) {
-      en += 0.5 * (j == 0 ? D.nhc_Q1 : D.nhc_Q) * st.xi[j] * st.xi[j];
-      if (j > 0) en += D.kT * st.eta[j];
-    }
-    st.e_nhc = en;
+    st.e_nhc = nhc_energy(D, st.xi, st.eta);
     scale_sh = c;
   }
   __syncthreads();

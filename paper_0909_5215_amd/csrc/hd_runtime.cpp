@@ -53,11 +53,13 @@ struct SysHost {
   std::vector<double> vel;  // explicit velocities set before finalize
 };
 
-// Systems the LDS-resident and one-workgroup kernels do not cover: models
-// with tip bonds, biases beyond the slope alone, the Nose-Hoover chain.
-static bool grid_only(const SysHost &h) {
-  return h.tip_bonds || h.bias_var1 != HD_BIAS_SLOPE || h.bias_var2 >= 0 || h.nhc_len > 0;
+// Systems the LDS-resident kernel does not cover: models with tip bonds and
+// biases beyond the slope alone.  The one-workgroup kernel does not cover
+// those nor the Nose-Hoover chain: they take the grid kernels.
+static bool lds_excluded(const SysHost &h) {
+  return h.tip_bonds || h.bias_var1 != HD_BIAS_SLOPE || h.bias_var2 >= 0;
 }
+static bool grid_only(const SysHost &h) { return lds_excluded(h) || h.nhc_len > 0; }
 
 struct Plan {
   std::vector<int> ids;  // systems of the plan
@@ -565,8 +567,8 @@ hd_status build_schedule(hd_ctx *ctx) {
       const SysHost &h = ctx->sys[s];
       const int maxnb = h.dim == 2 ? ctx->maxnb2 : ctx->maxnb3;
       // models with tip bonds or a bias beyond the slope alone run on the
-      // grid kernels only
-      const bool ok = h.n <= 1024 && maxnb <= 32767 && !grid_only(h) &&
+      // grid kernels only (the Nose-Hoover chain may stay LDS-resident)
+      const bool ok = h.n <= 1024 && maxnb <= 32767 && !lds_excluded(h) &&
                       hdk::small_lds_bytes(h.dim, prec, h.n, maxnb, ctx->h_desc[s].ncell) <= budget &&
                       !ctx->small_disabled;
       if (ok) cand.push_back(s);

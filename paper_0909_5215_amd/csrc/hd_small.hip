@@ -181,6 +181,8 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   __shared__ uint8_t tr_all[1024];
   __shared__ double sh_zR[2][3];      // rigid-body noise, drawn one step ahead
   __shared__ Scal sh_out;
+  __shared__ double sh_xi[4], sh_eta[4], sh_scale;   // Nose-Hoover chain
+  __shared__ double red_k[16];
 
   const int i = tid;
   const bool own = i < n;
@@ -212,7 +214,34 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   const bool compute_only = (mode & 1) != 0;
   const bool rigid_body = D.n_rigid > 0;
   const bool wave_rigid = __ballot(own && role == ROLE_RIGID) != 0;   // uniform per wavefront
-  if (!compute_only && rigid_body && tid == 0) {
+  // Nose-Hoover chain in place of the Langevin O step (D.thermostat == 1):
+  // the chain lives in LDS and is advanced by thread 0; every step ends with
+  // its closing half step and, within the launch, the next step's opening
+  // one (one reduction of 2K); the launch opens the first step itself
+  const bool nhc = !compute_only && D.thermostat == 1;
+  auto nhc_k2 = [&]() -> double {
+    double k2[1] = {0.0};
+    if (own && role == ROLE_MOBILE)
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) k2[0] += D.mass * v[k] * v[k];
+    block_sum<1>(k2, red_k);
+    double K2 = k2[0];
+    if (rigid_body)
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) K2 += D.massR * VR[k] * VR[k];
+    return K2;
+  };
+  if (nhc) {
+    if (tid == 0)
+      for (int j = 0; j < 4; ++j) { sh_xi[j] = stg->xi[j]; sh_eta[j] = stg->eta[j]; }
+    const double K2 = nhc_k2();
+    if (tid == 0) sh_scale = nhc_half_step(D, sh_xi, sh_eta, K2);
+    __syncthreads();
+    const double c = sh_scale;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { v[k] *= c; VR[k] *= c; }
+  }
+  if (!compute_only && !nhc && rigid_body && tid == 0) {
     double z[3];
     noise<DIM, T>(D.seed, step, (uint32_t)n, z);
 #pragma unroll
@@ -235,7 +264,19 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     int moved = 0;
     // ---- B A O A: mobile atoms, and the rigid body in every thread --------
     if (!compute_only) {
-      if (own && role == ROLE_MOBILE) {
+      if (own && role == ROLE_MOBILE && nhc) {
+        // velocity Verlet: half kick, full drift
+        double d2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          const double vv = v[k] + D.hdt * ft[k] * D.inv_mass;
+          x[k] = wrapx(x[k] + D.dt * vv, D.box[k], D.periodic[k]);
+          v[k] = vv;
+          const double dd = minimg(x[k] - xbs[k * stride + i], D.box[k], D.hbox[k], D.periodic[k]);
+          d2 += dd * dd;
+        }
+        if (d2 > D.skin_half2) moved = 1;
+      } else if (own && role == ROLE_MOBILE) {
         double z[3] = {zn[0], zn[1], zn[2]};
         if (!have_zn) noise<DIM, T>(D.seed, step, (uint32_t)i, z);
         have_zn = false;
@@ -254,7 +295,13 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         }
         if (d2 > D.skin_half2) moved = 1;
       }
-      if (rigid_body) {
+      if (rigid_body && nhc) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          VR[k] = VR[k] + D.hdt * FR[k] * D.inv_massR;
+          XR[k] = XR[k] + D.dt * VR[k];
+        }
+      } else if (rigid_body) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
           double vv = VR[k], xx = XR[k];
@@ -386,7 +433,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       if constexpr (sizeof(T) == 8) e_own = acc.e; else e_own = acc.e.get();
     }
     // the rigid body's noise for the next step, drawn while others finish
-    if (!compute_only && rigid_body && tid == 0) {
+    if (!compute_only && !nhc && rigid_body && tid == 0) {
       double z[3];
       noise<DIM, T>(D.seed, step + 1, (uint32_t)n, z);
 #pragma unroll
@@ -441,7 +488,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     __syncthreads();   // barrier C
     // while wave 0 evaluates the scalars, the other wavefronts draw their
     // atoms' normals for the next step (they depend on the counter only)
-    if (wave != 0 && !compute_only && own && role == ROLE_MOBILE && it + 1 < iters) {
+    if (wave != 0 && !compute_only && !nhc && own && role == ROLE_MOBILE && it + 1 < iters) {
       noise<DIM, T>(D.seed, step + 1, (uint32_t)i, zn);
       have_zn = true;
     }
@@ -518,6 +565,19 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       step = step + 1;
     }
     const bool bad = Bl.bad != 0;
+    if (nhc && !bad) {
+      // closing half step of this step, opening one of the next
+      const double K2 = nhc_k2();
+      if (tid == 0) {
+        double c = nhc_half_step(D, sh_xi, sh_eta, K2);
+        if (it + 1 < iters) c *= nhc_half_step(D, sh_xi, sh_eta, K2 * c * c);
+        sh_scale = c;
+      }
+      __syncthreads();
+      const double c = sh_scale;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { v[k] *= c; VR[k] *= c; }
+    }
     if (bad) flags |= FLAG_UNSTABLE;
     if ((it == iters - 1 || bad) && tid == 0) sh_out = S;
     if (bad) break;
@@ -565,6 +625,10 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     stg->flags = flags;
     stg->n_rebuilds = rebuilds;
     stg->rebuild = 0;
+    if (nhc) {
+      for (int j = 0; j < 4; ++j) { stg->xi[j] = sh_xi[j]; stg->eta[j] = sh_eta[j]; }
+      stg->e_nhc = nhc_energy(D, sh_xi, sh_eta);
+    }
   }
 }
 

@@ -45,11 +45,14 @@ def min_image_diff(spec, a, b):
     return d
 
 
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["lds", "grid"])
 @pytest.mark.parametrize("M", [1, 3])
 @pytest.mark.parametrize("model", ["2d", "3d", "cone", "paper2d"])
-def test_nhc_trajectory_fp64(hd, oracle_mod, model, M):
+def test_nhc_trajectory_fp64(hd, oracle_mod, model, M, exec_mode):
+    """Batched: the 2D and 3D models run LDS-resident (the cone model, with
+    tip bonds, on the grid); grid: every model on the grid kernels."""
     spec = nhc_spec(oracle_mod, model, 11, M)
-    ctx = hd.make_context([spec], precision=hd.HD_FP64, init_velocities=True)
+    ctx = hd.make_context([spec], precision=hd.HD_FP64, exec_mode=exec_mode, init_velocities=True)
     o = oracle_mod.OracleSystem(spec)
     o.init_velocities()
     ctx.step(40)
@@ -63,10 +66,11 @@ def test_nhc_trajectory_fp64(hd, oracle_mod, model, M):
     assert a["t_hyper"] == pytest.approx(b["t_hyper"], rel=1e-12)
 
 
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["lds", "grid"])
 @pytest.mark.parametrize("model", ["2d", "3d"])
-def test_nhc_trajectory_fp32c(hd, oracle_mod, model):
+def test_nhc_trajectory_fp32c(hd, oracle_mod, model, exec_mode):
     spec = nhc_spec(oracle_mod, model, 12)
-    ctx = hd.make_context([spec], precision=hd.HD_FP32C, init_velocities=True)
+    ctx = hd.make_context([spec], precision=hd.HD_FP32C, exec_mode=exec_mode, init_velocities=True)
     o = oracle_mod.OracleSystem(spec)
     o.init_velocities()
     ctx.step(20)
@@ -136,3 +140,38 @@ def test_nhc_arguments(hd):
     ctx.finalize()
     with pytest.raises(hd.HDError):
         ctx.set_nose_hoover(k, 0, 0.5)                   # after finalize
+
+
+@pytest.mark.parametrize("exec_mode", [0, 1], ids=["lds", "grid"])
+def test_nhc_across_launches(hd, oracle_mod, exec_mode):
+    """A run split into several launches (each opening the chain itself)
+    follows the oracle's uninterrupted run."""
+    spec = nhc_spec(oracle_mod, "paper2d", 14)
+    ctx = hd.make_context([spec], precision=hd.HD_FP64, exec_mode=exec_mode, init_velocities=True)
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    for n in (7, 13, 1, 19):
+        ctx.step(n)
+    o.step(40)
+    assert float(np.abs(min_image_diff(spec, ctx.positions(0), o.positions())).max()) < 1e-10
+    assert ctx.scalars(0)["e_nhc"] == pytest.approx(o.scalars()["e_nhc"], rel=1e-9)
+
+
+def test_nhc_lds_batch_p2(hd, oracle_mod):
+    """The P2 workload under the chain: 256 positions LDS-resident, sampled
+    systems against the oracle after 30 steps."""
+    from hd_inputs import CONFIGS
+    specs = CONFIGS["P2"]()
+    for k, s in enumerate(specs):
+        s.rO = s.pos.copy()
+        s.pos = perturbed(s, 0.05, 700 + k)
+        s.thermostat, s.nhc_len, s.nhc_tau = 1, 3, 0.5
+        s.bias_on = 0
+    ctx = hd.make_context(specs, precision=hd.HD_FP64, init_velocities=True)
+    assert ctx.schedule()["lds_resident"] == 1
+    ctx.step(30)
+    for k in (0, 131, 255):
+        o = oracle_mod.OracleSystem(specs[k])
+        o.init_velocities()
+        o.step(30)
+        assert float(np.abs(min_image_diff(specs[k], ctx.positions(k), o.positions())).max()) < 1e-10, k
