@@ -17,7 +17,9 @@ hipError_t launch_batched(int prec, int dim, const SysDesc *descs, SysState *sta
 // displacements, cell list and neighbour list fit in one workgroup's LDS.
 // All listed systems have dimension `dim`; nmax (<= 1024) is the LDS row
 // stride and bounds every listed n; maxnb is their neighbour capacity;
-// cellmax bounds every listed ncell.
+// cellmax bounds every listed ncell.  mode 0: nsteps steps; 1: one
+// evaluation; 2: steps with the Nose-Hoover chain compiled in (for groups
+// holding a system that uses it).
 hipError_t launch_small(int kind, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
                         const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax,
                         int block, int64_t nsteps, int mode, hipStream_t stream);

@@ -118,6 +118,7 @@ struct hd_ctx {
     int32_t *d_ids = nullptr;
     int nmax = 0, cellmax = 1, maxnb = 32;
     int block = 0;   // threads per workgroup
+    bool nhc = false;   // some system runs the Nose-Hoover chain
   };
   std::vector<Group> groups;
   std::vector<int32_t> small_ids, big_ids;
@@ -441,7 +442,8 @@ hd_status launch_groups(hd_ctx *ctx, int64_t nsteps, int mode, hipStream_t strea
     for (int s : G.ids) ctx->sorted_lists[s] = 0;
     if (G.small)
       HIPCHK(hdk::launch_small(small_kind(ctx), G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
-                               G.nmax, G.maxnb, G.cellmax, G.block, nsteps, mode, stream));
+                               G.nmax, G.maxnb, G.cellmax, G.block, nsteps, (mode == 0 && G.nhc) ? 2 : mode,
+                               stream));
     else
       HIPCHK(hdk::launch_batched(prec, G.dim, ctx->d_desc, ctx->d_state, ctx->A, G.d_ids, (int)G.ids.size(),
                                  ctx->block, nsteps, mode, stream));
@@ -595,6 +597,7 @@ hd_status build_schedule(hd_ctx *ctx) {
       hd_ctx::Group G;
       G.dim = d + 2; G.small = true; G.ids = sm[d]; G.nmax = gn[d]; G.cellmax = gc[d];
       G.maxnb = d == 0 ? ctx->maxnb2 : ctx->maxnb3;
+      for (int s : sm[d]) G.nhc = G.nhc || ctx->sys[s].nhc_len > 0;
       ctx->groups.push_back(G);
     }
     std::sort(ctx->big_ids.begin(), ctx->big_ids.end());

@@ -155,7 +155,7 @@ struct Bcast {
   int bias_live, bad;
 };
 
-template <int DIM, typename T, bool HALF, int BLOCK>
+template <int DIM, typename T, bool HALF, int BLOCK, bool NHC>
 __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Arrays &A,
                           int64_t nsteps, int mode, char *lds, const SmallLayout L) {
   constexpr int NW = BLOCK / 64;       // wavefronts per workgroup
@@ -218,7 +218,8 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   // the chain lives in LDS and is advanced by thread 0; every step ends with
   // its closing half step and, within the launch, the next step's opening
   // one (one reduction of 2K); the launch opens the first step itself
-  const bool nhc = !compute_only && D.thermostat == 1;
+  // (compiled in only with NHC: the Langevin instantiations stay as they were)
+  const bool nhc = NHC && !compute_only && D.thermostat == 1;
   auto nhc_k2 = [&]() -> double {
     double k2[1] = {0.0};
     if (own && role == ROLE_MOBILE)
@@ -632,7 +633,8 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   }
 }
 
-// MODE 0: nsteps BAOAB steps; MODE 1: one evaluation at the current
+// MODE 0: nsteps BAOAB steps (MODE 2: the same for groups holding a system
+// with the Nose-Hoover chain); MODE 1: one evaluation at the current
 // positions (separate instantiation so the two never share a profile row).
 // One instantiation per dimension and workgroup size, so that the register
 // budget follows the launch size.
@@ -643,7 +645,7 @@ __global__ __launch_bounds__(BLOCK) void k_small(const SysDesc *__restrict__ des
                                                  SmallLayout L) {
   extern __shared__ __align__(16) char lds[];
   const int s = sys_list[blockIdx.x];
-  run_small<DIM, T, HALF, BLOCK>(descs[s], states + s, A, nsteps, MODE, lds, L);
+  run_small<DIM, T, HALF, BLOCK, MODE == 2>(descs[s], states + s, A, nsteps, MODE & 1, lds, L);
 }
 
 template <typename T, int DIM, int MODE, int BLOCK, bool HALF>
@@ -657,8 +659,10 @@ static hipError_t launch_small_t(const SysDesc *descs, SysState *states, const A
 
 template <typename T, int DIM, bool HALF>
 static hipError_t allow_lds_d(int bytes) {
-  const void *fns[4] = {(const void *)k_small<T, DIM, 1, 1024, HALF>, (const void *)k_small<T, DIM, 0, 256, HALF>,
-                        (const void *)k_small<T, DIM, 0, 512, HALF>, (const void *)k_small<T, DIM, 0, 1024, HALF>};
+  const void *fns[7] = {(const void *)k_small<T, DIM, 1, 1024, HALF>, (const void *)k_small<T, DIM, 0, 256, HALF>,
+                        (const void *)k_small<T, DIM, 0, 512, HALF>, (const void *)k_small<T, DIM, 0, 1024, HALF>,
+                        (const void *)k_small<T, DIM, 2, 256, HALF>, (const void *)k_small<T, DIM, 2, 512, HALF>,
+                        (const void *)k_small<T, DIM, 2, 1024, HALF>};
   for (const void *f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -682,8 +686,15 @@ template <typename T, int DIM, bool HALF>
 static hipError_t launch_small_d(const SysDesc *descs, SysState *states, const Arrays &A,
                                  const int32_t *sys_list, int nsys, int block, size_t bytes, int64_t nsteps,
                                  int mode, SmallLayout L, hipStream_t stream) {
-  if (mode)
+  if (mode == 1)
     return launch_small_t<T, DIM, 1, 1024, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  if (mode == 2) {
+    if (block <= 256)
+      return launch_small_t<T, DIM, 2, 256, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+    if (block <= 512)
+      return launch_small_t<T, DIM, 2, 512, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+    return launch_small_t<T, DIM, 2, 1024, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
+  }
   if (block <= 256)
     return launch_small_t<T, DIM, 0, 256, HALF>(descs, states, A, sys_list, nsys, bytes, nsteps, L, stream);
   if (block <= 512)
