@@ -99,6 +99,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the lowest-eigenvalue search and its gradient on the paper's 3D model, "
+                         "and one cycle of the parallel slider-position algorithm on this workload")
     ap.add_argument("--half-lists", type=int, choices=[0, 1], default=None,
                     help="with --no-autotune: LDS-resident float32 pair pass on half (1) or full (0) lists")
     ap.add_argument("--quench-steps", type=int, default=20000, help="FIRE iteration cap of the r_O quench")
@@ -258,6 +261,52 @@ def make_run_ctx(hd, specs, states, precision, exec_mode, block):
     for k, st in enumerate(states):
         ctx.set_state(k, st)
     return ctx
+
+
+def extras(hd, torch, specs, states):
+    """Untimed-path operations of the method, timed on their own: the
+    lowest Hessian eigenvalue (Lanczos over GPU H u products) and its
+    gradient on the paper's 3D model at its FIRE minimum; one placement and
+    one cycle of the parallel slider-position algorithm on this workload."""
+    from hd_inputs import build_3d_cone
+    from paper_0909_5215_amd.sliding import ParallelSliding
+    out = {}
+    cone = build_3d_cone()
+    c = hd.make_context([cone], precision=hd.HD_FP64, exec_mode=hd.HD_EXEC_GRID, init_velocities=False)
+    c.quench([0], ftol=1e-8, max_iters=50000, set_reference=True)
+    _, _, (xm,) = c.quench([0], ftol=1e-8, max_iters=50000)
+    c.set_positions(0, xm)
+    t0 = time.perf_counter()
+    eps, iters, mode = c.min_mode(0, max_iter=400, tol=1e-9)
+    t1 = time.perf_counter()
+    c.min_mode_gradient(0, mode)
+    t2 = time.perf_counter()
+    out["min_mode"] = {"model": "the paper's 3D model (1983 atoms) at its FIRE minimum, float64, grid kernels",
+                       "eps": eps, "lanczos_iterations": iters, "seconds": round(t1 - t0, 4),
+                       "ms_per_hu_product": round((t1 - t0) * 1e3 / max(abs(iters), 1), 4),
+                       "gradient_seconds": round(t2 - t1, 4)}
+    c.close()
+    log(f"extras: min_mode {out['min_mode']}")
+    ctx = make_run_ctx(hd, specs, states, hd.HD_FP32C, hd.HD_EXEC_BATCHED, 0)
+    dx = specs[1].x_slider - specs[0].x_slider if len(specs) > 1 else 0.01
+    ps = ParallelSliding(ctx, x0=specs[0].x_slider, dx=dx, dtau=1000 * specs[0].dt, threshold=0.5,
+                         ftol=1e-6, max_quench=20000, chunk=100, check_every=5)
+    ctx.sync(); torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ps.start(0)
+    ctx.sync(); torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cyc = ps.run_cycle()
+    ctx.sync(); torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["sliding_cycle"] = {"positions": len(specs), "dtau": ps.dtau, "start_seconds": round(t1 - t0, 4),
+                            "cycle_seconds": round(t2 - t1, 4),
+                            "check_quench_seconds": round(ps.quench_seconds, 4),
+                            "check_ftol": ps.check_ftol, "steps_max": int(max(cyc.steps)),
+                            "transitions": int(sum(cyc.transitions)), "k_star": cyc.k_star}
+    ctx.close()
+    log(f"extras: sliding {out['sliding_cycle']}")
+    return out
 
 
 def time_steps(torch, ctx, steps):
@@ -473,6 +522,8 @@ def main():
         "mean_boost": float(np.mean(np.array(t_hyper) / np.maximum(np.array(t_md), 1e-300))),
         "r_O_quench": quench,
     }
+    if args.extras:
+        out["extras"] = extras(hd, torch, specs, states)
     print(json.dumps(out), flush=True)
 
 

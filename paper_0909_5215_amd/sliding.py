@@ -21,6 +21,7 @@ fixed slider positions are independent, so they may be tried at once).
 Every system needs its own thermostat seed, so that the copies of a seed
 state follow independent noise.
 """
+import time
 from dataclasses import dataclass
 from typing import List, Optional
 
@@ -43,13 +44,20 @@ class ParallelSliding:
 
     def __init__(self, ctx, x0: float, dx: float, dtau: float, threshold: float = 0.5,
                  ftol: float = 1e-6, max_quench: int = 20000, chunk: int = 100, check_every: int = 10,
-                 max_chunks: int = 10000):
-        if not (dtau > 0 and threshold > 0 and chunk > 0 and check_every > 0 and max_chunks > 0):
-            raise ValueError("dtau, threshold, chunk, check_every and max_chunks must be positive")
+                 max_chunks: int = 10000, check_ftol: float = 1e-4):
+        """ftol: force tolerance of the quench that sets r_O; check_ftol: of
+        the transition checks, which only compare a minimum's displacement
+        with `threshold` (a residual force f moves a minimum by about f/k, k
+        the stiffest curvature, ~57 here: far below any threshold)."""
+        if not (dtau > 0 and threshold > 0 and chunk > 0 and check_every > 0 and max_chunks > 0
+                and ftol > 0 and check_ftol > 0):
+            raise ValueError("dtau, threshold, tolerances, chunk, check_every and max_chunks must be positive")
         self.ctx = ctx
         self.S = ctx.num_systems()
         self.x0, self.dx, self.dtau = float(x0), float(dx), float(dtau)
         self.threshold, self.ftol, self.max_quench = float(threshold), float(ftol), int(max_quench)
+        self.check_ftol = float(check_ftol)
+        self.quench_seconds = 0.0      # wall time spent in transition checks
         self.chunk, self.check_every, self.max_chunks = int(chunk), int(check_every), int(max_chunks)
         self.base = 0
         self.seed_state: Optional[bytes] = None
@@ -90,7 +98,9 @@ class ParallelSliding:
             if not ((c + 1) % self.check_every == 0 or any(reached) or last):
                 continue
             live = [j for j in range(S) if not done[j]]
-            _, d, _ = ctx.quench(live, ftol=self.ftol, max_iters=self.max_quench)
+            t0 = time.perf_counter()
+            _, d, _ = ctx.quench(live, ftol=self.check_ftol, max_iters=self.max_quench)
+            self.quench_seconds += time.perf_counter() - t0
             for j, dj in zip(live, d):
                 disp[j] = float(dj)
                 if dj > self.threshold or reached[j] or last:
