@@ -348,8 +348,20 @@ def cpu_baseline(specs, states_x, budget_s):
         list(ex.map(lambda o: o.step(steps), systems))
     wall = time.perf_counter() - t0
     atoms = sum(specs[k].n for k in range(nsys))
+    # one core alone, a short bounded run of the first system
+    one_steps = max(5, int(2.0 / per_step))
+    t0 = time.perf_counter()
+    systems[0].step(one_steps)
+    one = specs[0].n * one_steps / (time.perf_counter() - t0)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": atoms * steps / wall, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nsys} of {len(specs)} systems x {steps} steps (FP64 oracle, one thread per system)"}
+            "sample": f"{nsys} of {len(specs)} systems x {steps} steps (FP64 oracle, one thread per system)",
+            "value_one_core": one, "cpu_model": model}
 
 
 def main():
