@@ -128,7 +128,7 @@ def workload(name):
         "P2": "the paper's 2D model: triangular 80 + tip 33 (113 atoms), k = 5, T = 0.01 "
               "x 256 slider positions dx_S = 0.01, slope bias on",
         "P3": "the paper's 3D model: fcc 1800 + conical tip 183 with harmonic tip bonds (1983 atoms) "
-              "x 64 slider positions dx_S = 0.01, slope bias on",
+              "x 256 slider positions dx_S = 0.01, slope bias on",
     }[name]
     return specs, desc
 

@@ -461,7 +461,7 @@ def config_p2(n_sys: int = 256) -> List[SystemSpec]:
     return out
 
 
-def config_p3(n_sys: int = 64) -> List[SystemSpec]:
+def config_p3(n_sys: int = 256) -> List[SystemSpec]:
     """The paper's 3D model (1800-atom substrate, 183-atom conical tip with
     harmonic tip bonds, spring k = 10) at n_sys consecutive slider positions
     k dx_S, dx_S = 0.01, T = 0.1, slope bias on."""
