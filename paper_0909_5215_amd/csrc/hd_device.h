@@ -711,33 +711,67 @@ __device__ __forceinline__ void pair_atom(const SysDesc &D, const Arrays &A, int
   }
 }
 
-// Pair pass of the atom at sorted position p over its full list (entries
-// hold sorted positions), neighbours read from the packed records; same
-// arithmetic as pair_atom.
-template <int DIM, typename T, int EXT = 0>
-__device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
-                                              const double xi[3], const T ui[3], int ti,
-                                              PairAcc<T> &acc, int q0 = 0, int qstep = 1) {
-  const int64_t off = D.off;
-  const int n = D.n;
-  const double *__restrict__ rec = A.rec + off * kRecDoubles;
-  const int32_t *__restrict__ nbr = A.nbr + D.nbr_off;
-  const int nn = A.nnb[off + p];
-  LJRow<T> R;
-  R.load(D, ti);
+// pair_disp with the last axis known periodic (LASTP) or open: on an open
+// axis the minimum image is an exact no-op (inv_box = box = 0), so skipping it
+// changes no bit and saves three float64 operations per neighbour.
+template <int DIM, bool LASTP>
+__device__ __forceinline__ double pair_disp_l(const SysDesc &D, const double xi[3], const double xj[3],
+                                              double dx[3]) {
+  double r2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const double raw = xi[k] - xj[k];
+    if (LASTP || k < DIM - 1) dx[k] = __builtin_fma(-D.box[k], __builtin_rint(raw * D.inv_box[k]), raw);
+    else dx[k] = raw;
+    r2 = add_sq_exact(r2, dx[k]);
+  }
+  return r2;
+}
+
+// The neighbour loop of pair_atom_rec: list entries walked by a 32-bit byte
+// offset advancing by a fixed stride, records addressed by 32-bit offsets
+// from the system's base (uniform), so that both loads take a scalar base.
+template <int DIM, typename T, int EXT, bool LASTP>
+__device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &R, const char *__restrict__ recb,
+                                              const char *__restrict__ nbrb, uint32_t lo, uint32_t lstep,
+                                              int cnt, const double xi[3], const T ui[3], PairAcc<T> &acc) {
 #pragma unroll 4
-  for (int q = q0; q < nn; q += qstep) {
+  for (int c = 0; c < cnt; ++c) {
     // the list is read once per step: a streaming load, so that it does not
     // evict the records the neighbouring atoms share
-    const int ent = __builtin_nontemporal_load(nbr + (int64_t)q * n + p);
-    const double *r = rec + (int64_t)(ent >> 1) * kRecDoubles;
+    const int ent = __builtin_nontemporal_load((const int32_t *)(nbrb + lo));
+    lo += lstep;
+    const double *r = (const double *)(recb + (((uint32_t)ent >> 1) << 6));
     double xj[3], dx[3];
     T uj[3];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; }
-    const double r2 = pair_disp<DIM>(D, xi, xj, dx);
+    const double r2 = pair_disp_l<DIM, LASTP>(D, xi, xj, dx);
     pair_term<DIM, T, EXT>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
   }
+}
+
+// Pair pass of the atom at sorted position p over its full list (entries
+// hold sorted positions), neighbours read from the packed records; same
+// arithmetic as pair_atom.  Lane q0 of qstep lanes takes entries q0,
+// q0 + qstep, ...
+template <int DIM, typename T, int EXT = 0>
+__device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
+                                              const double xi[3], const T ui[3], int ti,
+                                              PairAcc<T> &acc, int q0 = 0, int qstep = 1) {
+  static_assert(kRecDoubles == 8, "records are 64 bytes");
+  const int64_t off = D.off;
+  const int n = D.n;
+  const char *recb = (const char *)(A.rec + off * kRecDoubles);
+  const char *nbrb = (const char *)(A.nbr + D.nbr_off);
+  const int nn = A.nnb[off + p];
+  const int cnt = nn > q0 ? (nn - q0 + qstep - 1) / qstep : 0;
+  const uint32_t lo = ((uint32_t)q0 * (uint32_t)n + (uint32_t)p) * 4u;
+  const uint32_t lstep = (uint32_t)qstep * (uint32_t)n * 4u;
+  LJRow<T> R;
+  R.load(D, ti);
+  if (D.periodic[DIM - 1]) pair_loop_rec<DIM, T, EXT, true>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc);
+  else pair_loop_rec<DIM, T, EXT, false>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc);
 }
 
 // ---------------------------------------------------------------------------
