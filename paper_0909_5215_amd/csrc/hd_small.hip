@@ -10,6 +10,8 @@
 // The method is the one of the grid and one-workgroup kernels (BAOAB, LJ +
 // H u pair terms, slope bias of eq. 13-14, boosted clock of eq. 3); the
 // per-system sums are taken in a different fixed order.
+#include <type_traits>
+
 #include "hd_device.h"
 #include "hd_launch.h"
 
@@ -379,53 +381,60 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       T ui[3];
 #pragma unroll
       for (int k = 0; k < DIM; ++k) ui[k] = (T)u64[k];
-      if constexpr (HALF) {
-        // half list: the pair's vectors go to i (compensated, registers) and,
-        // negated, to j (float64 LDS atomics).  The next neighbour's data are
-        // loaded before this pair's atomics are issued, so that LDS latency
-        // overlaps the arithmetic.
-        int ent = nn > 0 ? nbr[i] : 0;
-        double xj[3];
-        float uj[3];
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + (ent >> 1)]; uj[k] = (float)us[k * stride + (ent >> 1)]; }
-        for (int q = 0; q < nn; ++q) {
-          const int j = ent >> 1, tj = ent & 1;
-          double dx[3];
-          const double r2 = pair_disp<DIM>(D, x, xj, dx);
-          const bool live = r2 < D.rc2;
-          float fv[3], hv[3], e;
-          pair_vals_f<DIM>(R, tj, live, dx, r2, (const float *)ui, uj, fv, hv, e);
-          if (q + 1 < nn) {
-            ent = nbr[(q + 1) * stride + i];
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + (ent >> 1)]; uj[k] = (float)us[k * stride + (ent >> 1)]; }
-          }
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) { acc.F[k].add(fv[k]); acc.H[k].add(hv[k]); }
-          acc.e.add(0.5f * e);
-          if (live) {
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-              atomicAdd(&jacc[k * stride + j], -(double)fv[k]);
-              atomicAdd(&jacc[(DIM + k) * stride + j], -(double)hv[k]);
+      // two versions of the loop, for a periodic and an open last axis (the
+      // open axis skips its minimum image, an exact no-op: no bit changes)
+      auto pair_pass = [&](auto last_periodic) {
+        constexpr bool LP = decltype(last_periodic)::value;
+        if constexpr (HALF) {
+          // half list: the pair's vectors go to i (compensated, registers) and,
+          // negated, to j (float64 LDS atomics).  The next neighbour's data are
+          // loaded before this pair's atomics are issued, so that LDS latency
+          // overlaps the arithmetic.
+          int ent = nn > 0 ? nbr[i] : 0;
+          double xj[3];
+          float uj[3];
+  #pragma unroll
+          for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + (ent >> 1)]; uj[k] = (float)us[k * stride + (ent >> 1)]; }
+          for (int q = 0; q < nn; ++q) {
+            const int j = ent >> 1, tj = ent & 1;
+            double dx[3];
+            const double r2 = pair_disp_l<DIM, LP>(D, x, xj, dx);
+            const bool live = r2 < D.rc2;
+            float fv[3], hv[3], e;
+            pair_vals_f<DIM>(R, tj, live, dx, r2, (const float *)ui, uj, fv, hv, e);
+            if (q + 1 < nn) {
+              ent = nbr[(q + 1) * stride + i];
+  #pragma unroll
+              for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + (ent >> 1)]; uj[k] = (float)us[k * stride + (ent >> 1)]; }
             }
-            atomicAdd(&jacc[2 * DIM * stride + j], 0.5 * (double)e);
+  #pragma unroll
+            for (int k = 0; k < DIM; ++k) { acc.F[k].add(fv[k]); acc.H[k].add(hv[k]); }
+            acc.e.add(0.5f * e);
+            if (live) {
+  #pragma unroll
+              for (int k = 0; k < DIM; ++k) {
+                atomicAdd(&jacc[k * stride + j], -(double)fv[k]);
+                atomicAdd(&jacc[(DIM + k) * stride + j], -(double)hv[k]);
+              }
+              atomicAdd(&jacc[2 * DIM * stride + j], 0.5 * (double)e);
+            }
+          }
+        } else {
+  #pragma unroll 4
+          for (int q = 0; q < nn; ++q) {
+            const int ent = nbr[q * stride + i];
+            const int j = ent >> 1;
+            double xj[3], dx[3];
+            T uj[3];
+  #pragma unroll
+            for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = us[k * stride + j]; }
+            const double r2 = pair_disp_l<DIM, LP>(D, x, xj, dx);
+            pair_term<DIM, T>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
           }
         }
-      } else {
-#pragma unroll 4
-        for (int q = 0; q < nn; ++q) {
-          const int ent = nbr[q * stride + i];
-          const int j = ent >> 1;
-          double xj[3], dx[3];
-          T uj[3];
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = us[k * stride + j]; }
-          const double r2 = pair_disp<DIM>(D, x, xj, dx);
-          pair_term<DIM, T>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
-        }
-      }
+      };
+      if (D.periodic[DIM - 1]) pair_pass(std::true_type{});
+      else pair_pass(std::false_type{});
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
         if constexpr (sizeof(T) == 8) { F[k] = acc.F[k]; H[k] = acc.H[k]; }
