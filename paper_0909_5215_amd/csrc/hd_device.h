@@ -728,6 +728,9 @@ __device__ __forceinline__ double pair_disp_l(const SysDesc &D, const double xi[
   return r2;
 }
 
+// List entries gathered together in the bonded pair loop.
+constexpr int kGatherBlock = 4;
+
 // The neighbour loop of pair_atom_rec: list entries walked by a 32-bit byte
 // offset advancing by a fixed stride, records addressed by 32-bit offsets
 // from the system's base (uniform), so that both loads take a scalar base.
@@ -735,19 +738,52 @@ template <int DIM, typename T, int EXT, bool LASTP>
 __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &R, const char *__restrict__ recb,
                                               const char *__restrict__ nbrb, uint32_t lo, uint32_t lstep,
                                               int cnt, const double xi[3], const T ui[3], PairAcc<T> &acc) {
-#pragma unroll 4
-  for (int c = 0; c < cnt; ++c) {
-    // the list is read once per step: a streaming load, so that it does not
-    // evict the records the neighbouring atoms share
-    const int ent = __builtin_nontemporal_load((const int32_t *)(nbrb + lo));
-    lo += lstep;
-    const double *r = (const double *)(recb + (((uint32_t)ent >> 1) << 6));
-    double xj[3], dx[3];
-    T uj[3];
+  if constexpr ((EXT & EXT_BONDS) != 0) {
+    // With tip bonds the pair term branches (bond or LJ), which keeps the
+    // compiler from hoisting the next neighbours' gathers over it: a block of
+    // kGatherBlock list entries and their records is loaded before the
+    // block's arithmetic (entries past the end repeat the block's first), and
+    // the terms are then added in list order as below.
+    for (int c0 = 0; c0 < cnt; c0 += kGatherBlock) {
+      int ent[kGatherBlock];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; }
-    const double r2 = pair_disp_l<DIM, LASTP>(D, xi, xj, dx);
-    pair_term<DIM, T, EXT>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
+      for (int u4 = 0; u4 < kGatherBlock; ++u4) {
+        const uint32_t o = lo + (c0 + u4 < cnt ? (uint32_t)u4 * lstep : 0u);
+        ent[u4] = __builtin_nontemporal_load((const int32_t *)(nbrb + o));
+      }
+      lo += (uint32_t)kGatherBlock * lstep;
+      double xj[kGatherBlock][3];
+      T uj[kGatherBlock][3];
+#pragma unroll
+      for (int u4 = 0; u4 < kGatherBlock; ++u4) {
+        const double *r = (const double *)(recb + (((uint32_t)ent[u4] >> 1) << 6));
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) { xj[u4][k] = r[k]; uj[u4][k] = (T)r[3 + k]; }
+      }
+#pragma unroll
+      for (int u4 = 0; u4 < kGatherBlock; ++u4) {
+        if (c0 + u4 < cnt) {
+          double dx[3];
+          const double r2 = pair_disp_l<DIM, LASTP>(D, xi, xj[u4], dx);
+          pair_term<DIM, T, EXT>(R, ent[u4] & 1, r2 < D.rc2, dx, r2, ui, uj[u4], acc);
+        }
+      }
+    }
+  } else {
+#pragma unroll 4
+    for (int c = 0; c < cnt; ++c) {
+      // the list is read once per step: a streaming load, so that it does not
+      // evict the records the neighbouring atoms share
+      const int ent = __builtin_nontemporal_load((const int32_t *)(nbrb + lo));
+      lo += lstep;
+      const double *r = (const double *)(recb + (((uint32_t)ent >> 1) << 6));
+      double xj[3], dx[3];
+      T uj[3];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; }
+      const double r2 = pair_disp_l<DIM, LASTP>(D, xi, xj, dx);
+      pair_term<DIM, T, EXT>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
+    }
   }
 }
 
