@@ -71,6 +71,27 @@ def test_tip_bonds_evaluation_fp32c(hd, oracle_mod, exec_mode):
     assert rel(ctx.forces(0, hd.HD_HU), ref["hu"]) <= 1e-5
 
 
+@pytest.mark.parametrize("large_block", [64, 320, 1024])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tip_bonds_every_lane_count(hd, oracle_mod, precision, large_block):
+    """The bonded pair loop gathers list entries and records four at a time,
+    so every lane's list ends in a ragged block: four, two and one lanes per
+    atom (64-, 320- and 1024-atom tiles, the 320-atom ones ragged against the
+    system) against the oracle."""
+    specs = [snapshot(MAKERS["paper"], 34), snapshot(MAKERS["small"], 35)]
+    ctx = hd.make_context(specs, precision=precision, init_velocities=False)
+    ctx.set_schedule({"lds_resident": 0, "small_block": 0, "persistent_large": 0,
+                      "large_block": large_block, "ms_per_step": 0.0})
+    ctx.compute()
+    assert ctx.schedule()["large_block"] == large_block
+    tol = 1e-11 if precision == hd.HD_FP64 else 1e-5
+    for k, s in enumerate(specs):
+        ref = oracle_mod.OracleSystem(s).compute()
+        assert rel(ctx.forces(k, hd.HD_FORCE_LJ), ref["f_lj"]) <= tol, k
+        assert rel(ctx.forces(k, hd.HD_HU), ref["hu"]) <= tol, k
+        assert ctx.scalars(k)["e_pot"] == pytest.approx(ref["e_pot"], rel=1e-11 if precision == hd.HD_FP64 else 1e-6)
+
+
 def test_tip_bonds_trajectory_fp64(hd, oracle_mod):
     spec = snapshot(build_3d_cone, 33)
     ctx = hd.make_context([spec], precision=hd.HD_FP64, init_velocities=True)
