@@ -539,7 +539,8 @@ __device__ __forceinline__ void bond_terms(const LJRow<T> &R, double r2, T &f, T
 // only: kernels that never see such a model keep the LJ-only registers).
 // With EXT_CURV also the pair's share of T[u,u], the gradient of u.H(r)u at
 // fixed u: (C |w|^2 + Dc (dx.w)^2) dx + 2 C (dx.w) w with Dc = (dC/dr)/r.
-template <int DIM, typename T, int EXT = 0>
+// WITH_E = false leaves the energy out (a step whose energy nobody reads).
+template <int DIM, typename T, int EXT = 0, bool WITH_E = true>
 __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, const double dx[3], double r2,
                                           const T ui[3], const T uj[3], PairAcc<T> &acc) {
   constexpr bool BONDS = (EXT & EXT_BONDS) != 0, CURV = (EXT & EXT_CURV) != 0;
@@ -570,7 +571,7 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       acc.F[k] += f * dx[k];
       acc.H[k] += CDw * dx[k] - f * w[k];
     }
-    acc.e += 0.5 * e;
+    if constexpr (WITH_E) acc.e += 0.5 * e;
     if constexpr (CURV) {
       double w2 = 0.0;
 #pragma unroll
@@ -608,7 +609,7 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       acc.F[k].add(f * d[k]);
       acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
     }
-    acc.e.add(0.5f * e);
+    if constexpr (WITH_E) acc.e.add(0.5f * e);
     if constexpr (CURV) {
       float w2 = 0.0f;
 #pragma unroll

@@ -381,10 +381,14 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       T ui[3];
 #pragma unroll
       for (int k = 0; k < DIM; ++k) ui[k] = (T)u64[k];
-      // two versions of the loop, for a periodic and an open last axis (the
-      // open axis skips its minimum image, an exact no-op: no bit changes)
-      auto pair_pass = [&](auto last_periodic) {
+      // versions of the loop for a periodic and an open last axis (the open
+      // axis skips its minimum image, an exact no-op: no bit changes), with
+      // and without the pair energy: within a launch only the last step's
+      // energy is read (the per-step instability test also counts forces
+      // beyond the limit, NaN included), so the other steps leave it out
+      auto pair_pass = [&](auto last_periodic, auto with_energy) {
         constexpr bool LP = decltype(last_periodic)::value;
+        constexpr bool WE = decltype(with_energy)::value;
         if constexpr (HALF) {
           // half list: the pair's vectors go to i (compensated, registers) and,
           // negated, to j (float64 LDS atomics).  The next neighbour's data are
@@ -409,14 +413,14 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
             }
   #pragma unroll
             for (int k = 0; k < DIM; ++k) { acc.F[k].add(fv[k]); acc.H[k].add(hv[k]); }
-            acc.e.add(0.5f * e);
+            if constexpr (WE) acc.e.add(0.5f * e);
             if (live) {
   #pragma unroll
               for (int k = 0; k < DIM; ++k) {
                 atomicAdd(&jacc[k * stride + j], -(double)fv[k]);
                 atomicAdd(&jacc[(DIM + k) * stride + j], -(double)hv[k]);
               }
-              atomicAdd(&jacc[2 * DIM * stride + j], 0.5 * (double)e);
+              if constexpr (WE) atomicAdd(&jacc[2 * DIM * stride + j], 0.5 * (double)e);
             }
           }
         } else {
@@ -429,12 +433,18 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   #pragma unroll
             for (int k = 0; k < DIM; ++k) { xj[k] = xs[k * stride + j]; uj[k] = us[k * stride + j]; }
             const double r2 = pair_disp_l<DIM, LP>(D, x, xj, dx);
-            pair_term<DIM, T>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
+            pair_term<DIM, T, 0, WE>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
           }
         }
       };
-      if (D.periodic[DIM - 1]) pair_pass(std::true_type{});
-      else pair_pass(std::false_type{});
+      const bool want_e = compute_only || it + 1 == iters;
+      if (D.periodic[DIM - 1]) {
+        if (want_e) pair_pass(std::true_type{}, std::true_type{});
+        else pair_pass(std::true_type{}, std::false_type{});
+      } else {
+        if (want_e) pair_pass(std::false_type{}, std::true_type{});
+        else pair_pass(std::false_type{}, std::false_type{});
+      }
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
         if constexpr (sizeof(T) == 8) { F[k] = acc.F[k]; H[k] = acc.H[k]; }
