@@ -241,9 +241,14 @@ hd_status hd_finalize(hd_ctx *ctx);
 
 /* Advance every system by n_steps BAOAB steps (asynchronous on the context
  * stream).  A system whose energy becomes non-finite, or one of whose atoms
- * feels a force above 1e6 eps/sigma, is frozen (HD_FLAG_UNSTABLE) while the
- * others continue; hd_set_positions or hd_set_state revive it.  Returns
- * HD_E_UNSTABLE when the last hd_sync found every system frozen. */
+ * feels a force above 1e6 eps/sigma (or a non-finite one), is frozen
+ * (HD_FLAG_UNSTABLE) while the others continue; hd_set_positions or
+ * hd_set_state revive it.  The energies read after the call are those of
+ * the last step; the LDS-resident kernel evaluates the pair energy on that
+ * step only, so a system frozen earlier within a launch reports e_lj and
+ * per-atom energies of zero for its last step (hd_compute re-evaluates
+ * them).  Returns HD_E_UNSTABLE when the last hd_sync found every system
+ * frozen. */
 hd_status hd_step(hd_ctx *ctx, int64_t n_steps);
 /* Evaluate forces, energy, H u and the bias at the current positions without
  * stepping or advancing the clock; rebuilds every neighbour list. */
