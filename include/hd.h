@@ -246,9 +246,8 @@ hd_status hd_finalize(hd_ctx *ctx);
  * hd_set_state revive it.  The energies read after the call are those of
  * the last step; the LDS-resident kernel evaluates the pair energy on that
  * step only, so a system frozen earlier within a launch reports e_lj and
- * per-atom energies of zero for its last step (hd_compute re-evaluates
- * them).  Returns HD_E_UNSTABLE when the last hd_sync found every system
- * frozen. */
+ * per-atom energies of zero for its last step.  Returns HD_E_UNSTABLE when
+ * the last hd_sync found every system frozen. */
 hd_status hd_step(hd_ctx *ctx, int64_t n_steps);
 /* Evaluate forces, energy, H u and the bias at the current positions without
  * stepping or advancing the clock; rebuilds every neighbour list. */
