@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from hd_inputs import (AFCC, A2D, ROLE_FIXED, ROLE_MOBILE, ROLE_RIGID, SystemSpec, build_3d_cone,
-                       build_2d, build_3d, perturbed)
+                       build_2d, build_3d, config_c5a, perturbed)
 from tests.conftest import golden
 
 
@@ -449,7 +449,7 @@ def test_equipartition(oracle_mod):
 
 
 def test_maxwell_boltzmann_init(oracle_mod):
-    spec = build_2d(kT=0.1) if False else build_2d()
+    spec = build_2d()
     spec.kT = 0.25
     o = oracle_mod.OracleSystem(spec)
     o.init_velocities()
@@ -460,6 +460,78 @@ def test_maxwell_boltzmann_init(oracle_mod):
     i = int(np.where(spec.role == ROLE_MOBILE)[0][3])
     z = oracle_mod.normals(spec.seed, 0, i, 1)
     np.testing.assert_array_equal(o.velocities()[:, i], math.sqrt(spec.kT) * z[:2])
+
+
+def _rigid_cluster(n_rigid, n_mobile=1, **kw):
+    """A 2D model of n_rigid rigid atoms in a row (one body of mass
+    n_rigid m) plus n_mobile mobile atoms far above it, out of reach."""
+    n = n_rigid + n_mobile
+    pos = np.zeros((2, n))
+    pos[0, :n_rigid] = 1.0 + 1.2 * np.arange(n_rigid)
+    pos[0, n_rigid:] = 1.0 + 1.2 * np.arange(n_mobile)
+    pos[1, n_rigid:] = 10.0
+    role = np.array([ROLE_RIGID] * n_rigid + [ROLE_MOBILE] * n_mobile, np.uint8)
+    typ = np.ones(n, np.uint8)
+    L = max(8.0, 1.2 * max(n_rigid, n_mobile) + 6.0)
+    spec = SystemSpec(dim=2, pos=pos, type=typ, role=role, box=np.array([L, 0.0, 0.0]),
+                      periodic=np.array([1, 0, 0], np.int32))
+    for k, v in kw.items():
+        setattr(spec, k, v)
+    return spec
+
+
+def test_rigid_body_maxwell_boltzmann_draw(oracle_mod):
+    """The rigid top layer is one body of mass n_R m (Sec. 3.1.1): its
+    Maxwell-Boltzmann velocity has variance kT/(n_R m) per axis, each of its
+    atoms moves with it, and the draw is the counter-based one of particle
+    index n (tag 1, step 0)."""
+    n_rigid, kT = 10, 0.25
+    vr = []
+    for seed in range(1, 1501):
+        spec = _rigid_cluster(n_rigid, kT=kT, seed=seed)
+        o = oracle_mod.OracleSystem(spec)
+        o.init_velocities()
+        _, VR, _ = o.rigid()
+        v = o.velocities()
+        np.testing.assert_array_equal(v[:, :n_rigid], np.repeat(VR[:2, None], n_rigid, axis=1))
+        vr.append(VR[:2])
+        if seed == 1:
+            z = oracle_mod.normals(seed, 0, spec.n, 1)
+            np.testing.assert_allclose(VR[:2], math.sqrt(kT / n_rigid) * z[:2], rtol=1e-15)
+    vr = np.array(vr)
+    # 3000 samples: the variance is known to about 2.6 % (one sigma)
+    assert vr.var() == pytest.approx(kT / n_rigid, rel=0.1)
+    assert abs(vr.mean()) < 4.0 * math.sqrt(kT / n_rigid / vr.size)
+
+
+@pytest.mark.parametrize("n_rigid", [1, 4])
+def test_continuous_sliding_drives_the_exact_oscillator(oracle_mod, n_rigid):
+    """Continuous sliding (Sec. 2.3, Fig. 1): the slider moves at constant
+    velocity, x_S(t) = x_S(0) + v_S t, and pulls the rigid layer (mass
+    M = n_R m) through the spring k.  Alone, started at rest at x_S(0) = 0,
+    the layer obeys M Y'' = k (v_S t - Y), whose solution is
+    Y(t) = v_S t - (v_S / w) sin(w t), w = sqrt(k/M).  Without friction the
+    step is velocity Verlet, second order: after 2000 steps the layer is
+    within 1e-6 of the solution (the error is ~1e-7); evaluating the slider
+    one step late or early shifts it by ~5e-5."""
+    v_s, dt, k, N = 0.01, 0.005, 1.0, 2000
+    spec = _rigid_cluster(n_rigid, gamma=0.0, kT=0.1, dt=dt, k_spring=k, f_normal=0.0,
+                          x_slider=0.0, v_slider=v_s)
+    o = oracle_mod.OracleSystem(spec)
+    o.step(N)
+    XR, VR, XR0 = o.rigid()
+    w = math.sqrt(k / n_rigid)
+    t = N * dt
+    sc = o.scalars()
+    assert sc["t_md"] == pytest.approx(t, rel=1e-12)
+    assert XR[0] - XR0[0] == pytest.approx(v_s * t - v_s / w * math.sin(w * t), abs=1e-6)
+    assert VR[0] == pytest.approx(v_s * (1.0 - math.cos(w * t)), abs=1e-6)
+    assert XR[1] == XR0[1] and VR[1] == 0.0
+    # read-outs: the slider at the last evaluation and the lateral force
+    # k (x_S - x_T) of eq. 10
+    assert sc["x_slider"] == pytest.approx(v_s * sc["t_md"], rel=1e-12)
+    assert sc["f_lat"] == pytest.approx(k * (sc["x_slider"] - sc["x_tip"]), rel=1e-12)
+    assert sc["x_tip"] == pytest.approx(XR[0] - XR0[0], rel=1e-12)
 
 
 def test_fixed_atoms_never_move_and_rigid_layer_stays_rigid(oracle_mod):
@@ -538,11 +610,12 @@ def test_model_sizes():
     t = build_3d()
     assert int((t.type == 0).sum()) == int(g["3d_substrate"])
     assert int((t.role == ROLE_FIXED).sum()) == int(g["3d_fixed"])
-    # every atom sits on a lattice site in registry: nearest distance 2^(1/6)
-    for spec in (s, t):
-        pairs = None
-    assert 20 * 20 * 6 * 4 == int(g["3d_substrate"])
-    assert 100 * 100 * 25 * 4 == int(g["3d_large_substrate"])
+    # the 1M-atom slab of the large single-instance workload, as built
+    (c5a,) = config_c5a()
+    assert int((c5a.type == 0).sum()) == int(g["3d_large_substrate"])
+    assert int((c5a.type == 1).sum()) == int(g["3d_large_tip"])
+    assert c5a.n == int(g["3d_large_total"])
+    assert int((c5a.role == ROLE_FIXED).sum()) == int(g["3d_large_fixed"])
 
 
 @pytest.mark.parametrize("maker", [lambda: build_2d(), lambda: build_3d()])
