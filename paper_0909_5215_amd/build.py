@@ -8,6 +8,7 @@ offsets) is rounded operation by operation.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -23,8 +24,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 def build(force: bool = True, verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+    def compile_one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
         extra = []
@@ -33,7 +33,14 @@ def build(force: bool = True, verbose: bool = False) -> str:
         cmd = [HIPCC] + COMMON + extra + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd))
-        r = subprocess.run(cmd, capture_output=True, text=True)
+        return obj, subprocess.run(cmd, capture_output=True, text=True)
+
+    # one hipcc per source, side by side (each is single-threaded)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    objs = []
+    for src, (obj, r) in zip(SOURCES, results):
         if r.returncode != 0:
             sys.stderr.write(r.stderr)
             raise RuntimeError(f"hipcc failed on {src}")

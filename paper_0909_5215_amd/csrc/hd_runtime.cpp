@@ -67,9 +67,14 @@ struct Plan {
   int32_t *d_sys = nullptr;
   int32_t *d_tile0 = nullptr;
   hdk::GridPlan gp{};
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec = nullptr;   // kGraphSteps steps
   int graph_steps = 0;
   int launches_per_graph = 0;
+  // the remainder of a call shorter than kGraphSteps, captured at the length
+  // last asked for (re-captured when a call needs another length)
+  hipGraphExec_t tail_exec = nullptr;
+  int tail_steps = 0;
+  int tail_launches = 0;
 };
 
 double minimg_h(double dx, double L, int periodic) {
@@ -139,6 +144,9 @@ struct hd_ctx {
   // (rows and entries are cell-sorted positions) rather than by a
   // one-workgroup kernel (atom indices)
   std::vector<uint8_t> sorted_lists;
+  // hd_bind_device: the context's own storage of each bindable batch field
+  // (x, v, ftot, flj, fb, hu), kept while the field lives in caller memory
+  double *own_field[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   int64_t last_launches = 0;
@@ -406,7 +414,7 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
   return HD_OK;
 }
 
-hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps) {
+hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps, hipGraphExec_t *exec, int *n_launches) {
   hipStream_t cs;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -420,11 +428,10 @@ hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps) {
     hipStreamDestroy(cs);
     return fail(ctx, HD_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
   }
-  HIPCHK(hipGraphInstantiate(&P.exec, g, nullptr, nullptr, 0));
+  HIPCHK(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
   HIPCHK(hipGraphDestroy(g));
   HIPCHK(hipStreamDestroy(cs));
-  P.graph_steps = steps;
-  P.launches_per_graph = launches;
+  *n_launches = launches;
   return HD_OK;
 }
 
@@ -470,25 +477,44 @@ hd_status evaluate_all(hd_ctx *ctx, bool force_rebuild = true) {
   return HD_OK;
 }
 
-// Grid plans: graph replays of kGraphSteps steps, the rest direct, then the
-// kinetic energy.
-hd_status run_plans(hd_ctx *ctx, int64_t n_steps, hipStream_t stream, int64_t *launches) {
-  const int prec = ctx->prec == HD_FP64 ? 0 : 1;
+// Graphs a call of n_steps replays on the grid plans: kGraphSteps steps, and
+// the remainder at its own length (re-captured when a call needs another
+// length).  Captured before the call's work is enqueued, so that the capture
+// stays outside the call's timed region.
+hd_status prepare_plans(hd_ctx *ctx, int64_t n_steps) {
   hd_status st;
   for (auto &P : ctx->plans) {
-    int64_t left = n_steps;
+    if (n_steps >= kGraphSteps && !P.exec) {
+      if ((st = capture_plan(ctx, P, kGraphSteps, &P.exec, &P.launches_per_graph)) != HD_OK) return st;
+      P.graph_steps = kGraphSteps;
+    }
+    const int left = (int)(n_steps % kGraphSteps);
+    if (left > 0 && (!P.tail_exec || P.tail_steps != left)) {
+      if (P.tail_exec) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream2));
+        HIPCHK(hipGraphExecDestroy(P.tail_exec));
+        P.tail_exec = nullptr;
+      }
+      if ((st = capture_plan(ctx, P, left, &P.tail_exec, &P.tail_launches)) != HD_OK) return st;
+      P.tail_steps = left;
+    }
+  }
+  return HD_OK;
+}
+
+// Grid plans: replays of the graphs prepare_plans captured, then the kinetic
+// energy.
+hd_status run_plans(hd_ctx *ctx, int64_t n_steps, hipStream_t stream, int64_t *launches) {
+  for (auto &P : ctx->plans) {
     for (int s : P.ids) ctx->sorted_lists[s] = 1;
-    if (left >= kGraphSteps && !P.exec && (st = capture_plan(ctx, P, kGraphSteps)) != HD_OK) return st;
-    while (left >= kGraphSteps && P.exec) {
+    for (int64_t g = 0; g < n_steps / kGraphSteps; ++g) {
       HIPCHK(hipGraphLaunch(P.exec, stream));
       *launches += P.launches_per_graph;
-      left -= P.graph_steps;
     }
-    while (left > 0) {
-      int l = 0;
-      HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, false, stream, &l));
-      *launches += l;
-      --left;
+    if (n_steps % kGraphSteps) {
+      HIPCHK(hipGraphLaunch(P.tail_exec, stream));
+      *launches += P.tail_launches;
     }
     HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, stream));
     ++*launches;
@@ -536,8 +562,10 @@ int small_block_for(const hd_ctx *ctx, int nmax) {
 void clear_schedule(hd_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipStreamSynchronize(ctx->stream2);
-  for (auto &P : ctx->plans)
+  for (auto &P : ctx->plans) {
     if (P.exec) (void)hipGraphExecDestroy(P.exec);
+    if (P.tail_exec) (void)hipGraphExecDestroy(P.tail_exec);
+  }
   ctx->plans.clear();
   if (ctx->batched_graph) (void)hipGraphExecDestroy(ctx->batched_graph);
   ctx->batched_graph = nullptr;
@@ -1049,6 +1077,7 @@ hd_status hd_step(hd_ctx *ctx, int64_t n_steps) {
   hd_status st = sync_in(ctx);
   if (st != HD_OK) return st;
   if (ctx->need_eval && (st = evaluate_all(ctx)) != HD_OK) return st;
+  if ((st = prepare_plans(ctx, n_steps)) != HD_OK) return st;
   int64_t launches = 0;
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
   // persistent groups on the context stream, grid plans concurrently on the
@@ -1284,6 +1313,77 @@ hd_status hd_copy_forces_device(hd_ctx *ctx, int32_t sys, int32_t which, double 
   return copy_field(ctx, sys, src, dev_out, hipMemcpyDeviceToDevice);
 }
 
+// The Arrays member of each bindable field, in HD_FIELD_* order.
+static double *&bound_field(hd_ctx *ctx, int field) {
+  hdk::Arrays &A = ctx->A;
+  switch (field) {
+    case HD_FIELD_POSITIONS: return A.x;
+    case HD_FIELD_VELOCITIES: return A.v;
+    case HD_FIELD_FORCES: return A.ftot;
+    case HD_FIELD_FORCES_LJ: return A.flj;
+    case HD_FIELD_FORCES_BIAS: return A.fb;
+    default: return A.hu;
+  }
+}
+
+// Captured graphs hold the batch arrays' addresses as kernel arguments: drop
+// them so that the next call captures the current ones.
+static hd_status drop_graphs(hd_ctx *ctx) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream2));
+  for (auto &P : ctx->plans) {
+    if (P.exec) HIPCHK(hipGraphExecDestroy(P.exec));
+    if (P.tail_exec) HIPCHK(hipGraphExecDestroy(P.tail_exec));
+    P.exec = nullptr;
+    P.tail_exec = nullptr;
+    P.tail_steps = 0;
+  }
+  if (ctx->batched_graph) HIPCHK(hipGraphExecDestroy(ctx->batched_graph));
+  ctx->batched_graph = nullptr;
+  return HD_OK;
+}
+
+hd_status hd_batch_layout(hd_ctx *ctx, int32_t sys, int64_t *offset, int64_t *ntot) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !offset || !ntot) return fail(ctx, HD_E_ARG, "bad system or null output");
+  *offset = ctx->h_desc[sys].off;
+  *ntot = ctx->ntot;
+  return HD_OK;
+}
+
+hd_status hd_bind_device(hd_ctx *ctx, int32_t sys, int32_t field, void *dev_ptr) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_bind_device before hd_finalize");
+  if (sys != HD_ALL_SYSTEMS)
+    return fail(ctx, HD_E_ARG, "fields are bound for the whole batch (sys = HD_ALL_SYSTEMS)");
+  if (field < HD_FIELD_POSITIONS || field > HD_FIELD_HU) return fail(ctx, HD_E_ARG, "unknown field");
+  if (dev_ptr) {
+    if (((uintptr_t)dev_ptr & 7u) != 0) return fail(ctx, HD_E_ARG, "device pointer not 8-byte aligned");
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, dev_ptr) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, HD_E_ARG, "not a HIP device allocation");
+    }
+    if (at.type != hipMemoryTypeDevice || at.device != ctx->device)
+      return fail(ctx, HD_E_ARG, "not device memory of the context's device");
+  }
+  hd_status st = sync_in(ctx);
+  if (st != HD_OK) return st;
+  double *&cur = bound_field(ctx, field);
+  double *&own = ctx->own_field[field];
+  double *target = dev_ptr ? (double *)dev_ptr : (own ? own : cur);
+  if (target == cur) return HD_OK;
+  if ((st = drop_graphs(ctx)) != HD_OK) return st;
+  // the field's current contents move to its new storage
+  HIPCHK(hipMemcpyAsync(target, cur, sizeof(double) * 3 * ctx->ntot, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!own) own = cur;
+  cur = target;
+  if (cur == own) own = nullptr;
+  return HD_OK;
+}
+
 hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
   CHECK_CTX();
   if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
@@ -1401,12 +1501,35 @@ hd_status hd_set_velocities(hd_ctx *ctx, int32_t sys, const double *vel) {
 }
 
 // Checkpoint layout: header, then x, v, rO, xb, ftot as [dim][n] doubles.
+// params_fp fingerprints the parameters the stored forces were evaluated
+// with (the potential, the drive and the bias), so that a state restored into
+// a system with other parameters gets its forces re-evaluated.
 struct CkptHeader {
   uint32_t magic, version;
   int32_t dim, n;
+  uint64_t params_fp;
   SysState state;
 };
 static const uint32_t kMagic = 0x68644350u;  // "hdCP"
+static const uint32_t kCkptVersion = 2;
+
+// FNV-1a over the parameters that shape a system's forces (not the seed,
+// the time step or the thermostat, which only shape the dynamics).
+static uint64_t params_fingerprint(const SysHost &h) {
+  uint64_t f = 1469598103934665603ull;
+  auto mix = [&f](const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) { f ^= b[i]; f *= 1099511628211ull; }
+  };
+  mix(&h.dim, sizeof h.dim); mix(&h.n, sizeof h.n);
+  mix(h.box, sizeof h.box); mix(h.periodic, sizeof h.periodic); mix(&h.mass, sizeof h.mass);
+  mix(&h.lj, sizeof h.lj); mix(&h.dr, sizeof h.dr); mix(&h.bias, sizeof h.bias);
+  mix(&h.tip_bonds, sizeof h.tip_bonds); mix(&h.k_bond, sizeof h.k_bond); mix(&h.r_bond, sizeof h.r_bond);
+  mix(&h.r_bond_cut, sizeof h.r_bond_cut); mix(&h.bias_var1, sizeof h.bias_var1);
+  mix(&h.bias_var2, sizeof h.bias_var2); mix(&h.b2_lo, sizeof h.b2_lo); mix(&h.b2_hi, sizeof h.b2_hi);
+  mix(h.XR0, sizeof h.XR0);
+  return f;
+}
 
 hd_status hd_get_state(hd_ctx *ctx, int32_t sys, void *buf, size_t *bytes) {
   CHECK_CTX();
@@ -1419,9 +1542,10 @@ hd_status hd_get_state(hd_ctx *ctx, int32_t sys, void *buf, size_t *bytes) {
   if (*bytes < need) return fail(ctx, HD_E_ARG, "checkpoint buffer too small");
   CkptHeader h{};
   h.magic = kMagic;
-  h.version = 1;
+  h.version = kCkptVersion;
   h.dim = s.dim;
   h.n = s.n;
+  h.params_fp = params_fingerprint(s);
   HIPCHK(hipMemcpyAsync(&h.state, ctx->d_state + sys, sizeof(SysState), hipMemcpyDeviceToHost, ctx->stream));
   double *p = (double *)((char *)buf + sizeof(CkptHeader));
   const double *fields[5] = {ctx->A.x, ctx->A.v, ctx->A.rO, ctx->A.xb, ctx->A.ftot};
@@ -1444,7 +1568,7 @@ hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) 
   if (bytes < sizeof(CkptHeader) + 5 * nd * sizeof(double)) return fail(ctx, HD_E_ARG, "checkpoint too short");
   CkptHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (h.magic != kMagic || h.version != 1 || h.dim != s.dim || h.n != s.n)
+  if (h.magic != kMagic || h.version != kCkptVersion || h.dim != s.dim || h.n != s.n)
     return fail(ctx, HD_E_ARG, "checkpoint does not match this system");
   const double *p = (const double *)((const char *)buf + sizeof(CkptHeader));
   double *fields[5] = {ctx->A.x, ctx->A.v, ctx->A.rO, ctx->A.xb, ctx->A.ftot};
@@ -1463,6 +1587,9 @@ hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) 
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->all_frozen = false;
+  // forces evaluated under other parameters (another slider position, bias,
+  // ...) are re-evaluated before the next step, as after a parameter change
+  if (h.params_fp != params_fingerprint(s)) ctx->need_eval = true;
   return HD_OK;
 }
 
@@ -1991,6 +2118,8 @@ void hd_destroy(hd_ctx *ctx) {
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   for (auto &P : ctx->plans)
     if (P.exec) hipGraphExecDestroy(P.exec);
+  for (auto &P : ctx->plans)
+    if (P.tail_exec) hipGraphExecDestroy(P.tail_exec);
   if (ctx->batched_graph) hipGraphExecDestroy(ctx->batched_graph);
   for (void *p : ctx->sched_allocs) hipFree(p);
   for (void *p : ctx->allocs) hipFree(p);

@@ -13,6 +13,9 @@ from hd_inputs import config_c2, config_c3, config_c4, config_c5a, config_c5b, p
 
 pytestmark = pytest.mark.gpu
 
+FORCE_TOL = 1e-5     # relative L2 force error of the float32 path, per system
+DV_TOL = 1e-6        # |dV - dV_ref| / dV_max
+
 
 @pytest.fixture(scope="module")
 def hd():
@@ -46,9 +49,9 @@ def check_batch(hd, oracle_mod, specs, sample):
         assert np.isfinite(sc["e_pot"]) and sc["flags"] == 0, k
     for k in sample:
         ref = oracle_mod.OracleSystem(specs[k]).compute()
-        assert rel(ctx.forces(k), ref["f_tot"]) <= 1e-5, k
+        assert rel(ctx.forces(k), ref["f_tot"]) <= FORCE_TOL, k
         sc = ctx.scalars(k)
-        assert abs(sc["dv"] - ref["dv"]) <= 1e-6 * specs[k].dv_max, k
+        assert abs(sc["dv"] - ref["dv"]) <= DV_TOL * specs[k].dv_max, k
         assert sc["e_pot"] == pytest.approx(ref["e_pot"], rel=1e-6), k
     return ctx
 
@@ -98,10 +101,17 @@ def test_c3_short_trajectory_sampled(hd, oracle_mod):
     ctx.step(nsteps)
     for k in sample:
         o = oracle_mod.OracleSystem(specs[k])
-        # the per-atom force error at the start bounds the drift of the
-        # positions: |dx| <~ (n dt)^2/2 * max|dF| (with a factor 4 for growth)
-        dF = np.abs(f0[k] - o.compute()["f_tot"]).max()
-        bound = 4.0 * 0.5 * (nsteps * specs[k].dt) ** 2 * max(dF, 1e-7)
+        f_ref = o.compute()["f_tot"]
+        # the stated float32 tolerance first: relative L2 force error <= 1e-5
+        rel = np.linalg.norm(f0[k] - f_ref) / np.linalg.norm(f_ref)
+        assert rel <= FORCE_TOL, (k, rel)
+        # a force error within that tolerance is at most FORCE_TOL |F_ref|_2
+        # on any one atom; held over n steps it moves an atom by at most
+        # (n dt)^2 / 2 times that (unit mass), and the dynamics can amplify a
+        # displacement error over t = n dt by at most about
+        # (cosh(w t) - 1) / ((w t)^2 / 2) ~ 1.4 for the stiffest mode of the
+        # fcc lattice (w ~ 20 / tau at t = 0.1 tau): a factor 4 covers it
+        bound = 4.0 * 0.5 * (nsteps * specs[k].dt) ** 2 * FORCE_TOL * np.linalg.norm(f_ref)
         o.init_velocities()
         o.step(nsteps)
         dx = ctx.positions(k) - o.positions()
@@ -109,5 +119,5 @@ def test_c3_short_trajectory_sampled(hd, oracle_mod):
             if specs[k].periodic[d]:
                 dx[d] -= specs[k].box[d] * np.round(dx[d] / specs[k].box[d])
         err = float(np.abs(dx).max())
-        assert err < bound, (k, err, bound, dF)
+        assert err < bound, (k, err, bound)
         assert ctx.scalars(k)["t_hyper"] == pytest.approx(o.scalars()["t_hyper"], rel=1e-6)
