@@ -10,16 +10,21 @@
  * every system runs in HIP kernels on the GPU:
  *   - Lennard-Jones energy and forces with a type table (eq. 9; parameters of
  *     Sec. 3.1.1 / Sec. 3.2.1), energy-shifted at rc, over cell-binned Verlet
- *     neighbour lists with a skin;
+ *     neighbour lists with a skin; optionally harmonic tip bonds (eq. 12) for
+ *     the conical-tip model of Sec. 3.2.1;
  *   - the slider drive on the rigid top tip layer: spring k to the slider
  *     along x, anchor of stiffness k along y in 3D, normal load F_N pushing
  *     down (Sec. 3.1.1, Sec. 3.2.1); lateral force F_R = k (x_S - x_T) (eq. 10);
- *   - the slope bias: d (eq. 7), g = grad V . s (eq. 5), dV1(g) (eq. 14)
- *     combined by eq. 13 with the eigenvalue term dV2 set to zero, and the
- *     bias force -dV1'(g) grad g with grad g = (H u - F - g u/d)/d;
+ *   - the bias of Sec. 2.2: the distance d (eq. 7), the slope
+ *     g = grad V . s (eq. 5), the curvature kappa (eq. 6) and the lowest
+ *     Hessian eigenvalue (the variable of eq. 15), one or two of them through
+ *     the switch of eq. 14 and combined by eq. 13 (the slope alone by
+ *     default), with the bias force -grad dV by the chain rule;
  *   - the boosted clock t_hyper = sum dt exp(dV/kT) (eq. 3, eq. 8);
- *   - a Langevin BAOAB step (the paper's Nose-Hoover chain is replaced by a
- *     Langevin thermostat), with Philox4x32-10 normals.
+ *   - a Langevin BAOAB step with Philox4x32-10 normals, or the paper's
+ *     Nose-Hoover chain with velocity Verlet (Sec. 3.1.1), per system;
+ *   - the FIRE quench that gives the basin minimum r_O and the
+ *     quench-and-compare transition check of Sec. 2.3.
  *
  * Conventions
  *   - Every call returns hd_status; nothing throws across the ABI.  On
@@ -30,8 +35,10 @@
  *     k*n_atoms + i).  Device pointers (the *_device calls) must hold the same
  *     layout and stay valid until the call returns.
  *   - Device memory is owned by the context (hd_finalize allocates it,
- *     hd_destroy frees it).  Work is ordered on the context's HIP stream; the
- *     hd_read_* calls synchronise that stream before returning.
+ *     hd_destroy frees it), except for fields the caller binds to its own
+ *     device storage with hd_bind_device.  Work is ordered on the context's
+ *     HIP stream; the hd_read_* calls synchronise that stream before
+ *     returning.
  *   - Systems are added before hd_finalize; per-system parameters (slider,
  *     bias, thermostat) may change afterwards.
  *   - One context per host thread.
@@ -266,11 +273,47 @@ hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out);
 hd_status hd_copy_positions_device(hd_ctx *ctx, int32_t sys, double *dev_out);
 hd_status hd_copy_forces_device(hd_ctx *ctx, int32_t sys, int32_t which, double *dev_out);
 
-/* Checkpoint of one system: positions, velocities, reference, rigid body,
- * step, clock and seed.  With buf == NULL, *bytes receives the size needed.
- * Philox is counter based, so a restored run continues bit-identically. */
+/* Checkpoint of one system's run state: positions, velocities, the
+ * reference r_O, the list build positions, the last total forces, the rigid
+ * body, the step count, both clocks, the last scalars and the Nose-Hoover
+ * chain's state.  The seed, the slider position and every parameter are not
+ * part of it: they stay with the system the state is restored into, so a
+ * state copied into several systems (the redistribution of Sec. 2.3)
+ * continues there with each system's own noise stream and slider; when the
+ * target's potential, drive or bias parameters differ from the source's,
+ * its forces are re-evaluated before the next step, as after a parameter
+ * change.  With buf == NULL, *bytes receives the size needed.  Philox is
+ * counter based, so a state restored into the system it came from (or one
+ * with the same seed and parameters) continues bit-identically. */
 hd_status hd_get_state(hd_ctx *ctx, int32_t sys, void *buf, size_t *bytes);
 hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes);
+
+/* Zero-copy binding of a batch field to caller-owned device memory, for
+ * example a torch tensor's storage (the boundary of Sec. 2.3's parallel
+ * algorithm, where positions and forces feed other device code).  The batch
+ * stores each field as float64 [3][ntot]: component k of atom i of system s
+ * at k*ntot + offset(s) + i (hd_batch_layout gives offset and ntot; the
+ * third row of a 2D system is unused).  sys must be HD_ALL_SYSTEMS.
+ * field: HD_FIELD_POSITIONS, HD_FIELD_VELOCITIES, HD_FIELD_FORCES (total),
+ * HD_FIELD_FORCES_LJ (LJ + drive), HD_FIELD_FORCES_BIAS or HD_FIELD_HU.
+ * dev_ptr: 3*ntot doubles of device memory on the context's device, 8-byte
+ * aligned, kept alive by the caller until it is unbound or the context is
+ * destroyed.  The field's current contents are copied into it and from then
+ * on every kernel reads and writes the field there; the caller may read it
+ * between calls (stream-ordered on the context stream), and changes
+ * positions or velocities only through hd_set_positions, hd_set_velocities
+ * or hd_set_state.  dev_ptr == NULL unbinds: the contents are copied back
+ * into the context's own storage.  After HD_OK the previous storage is no
+ * longer used.  HD_E_STATE before hd_finalize; HD_E_ARG for another sys, an
+ * unknown field, or a pointer that is not aligned device memory of the
+ * context's device. */
+#define HD_ALL_SYSTEMS (-1)
+enum { HD_FIELD_POSITIONS = 0, HD_FIELD_VELOCITIES = 1, HD_FIELD_FORCES = 2, HD_FIELD_FORCES_LJ = 3,
+       HD_FIELD_FORCES_BIAS = 4, HD_FIELD_HU = 5 };
+hd_status hd_bind_device(hd_ctx *ctx, int32_t sys, int32_t field, void *dev_ptr);
+/* Where system sys lives in the batch arrays: *offset = its first atom,
+ * *ntot = atoms in the batch (after hd_finalize). */
+hd_status hd_batch_layout(hd_ctx *ctx, int32_t sys, int64_t *offset, int64_t *ntot);
 
 /* Neighbour pairs (i < j, system-local indices) of the current list, i.e.
  * pairs with r^2 < (rc + skin)^2 at the last build, without fixed-fixed and

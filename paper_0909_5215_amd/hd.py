@@ -25,6 +25,9 @@ HD_BIAS_SLOPE, HD_BIAS_CURVATURE, HD_BIAS_DISTANCE = 0, 1, 2
 HD_FLAG_UNSTABLE, HD_FLAG_NBR_OVERFLOW = 1, 2
 HD_LAUNCH_LDS, HD_LAUNCH_PERSISTENT_LARGE = 1, 2
 HD_QUENCH_CHECK, HD_QUENCH_SET_REFERENCE = 0, 1
+HD_ALL_SYSTEMS = -1
+HD_FIELD_POSITIONS, HD_FIELD_VELOCITIES, HD_FIELD_FORCES, HD_FIELD_FORCES_LJ, HD_FIELD_FORCES_BIAS, HD_FIELD_HU = \
+    0, 1, 2, 3, 4, 5
 
 _c = ctypes
 _dp = _c.POINTER(_c.c_double)
@@ -122,6 +125,8 @@ _SIGS = {
     "hd_set_tip_bonds": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double, _c.c_double]),
     "hd_set_bias_variables": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double]),
     "hd_set_nose_hoover": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double]),
+    "hd_bind_device": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_void_p]),
+    "hd_batch_layout": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64)]),
     "hd_last_error": (_c.c_char_p, [_P]),
     "hd_destroy": (None, [_P]),
 }
@@ -189,6 +194,7 @@ class Context:
         if getattr(self, "_h", None):
             load().hd_destroy(self._h)
             self._h = None
+        self._bound = {}
 
     def __del__(self):
         try:
@@ -393,6 +399,35 @@ class Context:
     def copy_forces_device(self, s: int, which: int, dev_ptr: int):
         _check(self._h, load().hd_copy_forces_device(self._h, s, int(which), ctypes.c_void_p(dev_ptr)),
                "hd_copy_forces_device")
+
+    def batch_layout(self, s: int):
+        """(offset, ntot): system s occupies atoms offset .. offset + n - 1 of
+        the batch arrays, which hold ntot atoms."""
+        off, nt = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._h, load().hd_batch_layout(self._h, int(s), ctypes.byref(off), ctypes.byref(nt)),
+               "hd_batch_layout")
+        return off.value, nt.value
+
+    def bind_device(self, field: int, tensor=None):
+        """Bind a batch field (HD_FIELD_*) to a caller-owned device tensor of
+        shape (3, ntot), float64, contiguous, on the context's device
+        (hd_bind_device); None unbinds.  The tensor is kept referenced here
+        while bound."""
+        if not hasattr(self, "_bound"):
+            self._bound = {}
+        ptr = None
+        if tensor is not None:
+            _, nt = self.batch_layout(0)
+            shape = tuple(tensor.shape)
+            if shape != (3, nt) or str(tensor.dtype) != "torch.float64" or not tensor.is_contiguous():
+                raise ValueError(f"bind_device needs a contiguous float64 tensor of shape (3, {nt}), got "
+                                 f"{shape} {tensor.dtype}")
+            ptr = ctypes.c_void_p(tensor.data_ptr())
+        _check(self._h, load().hd_bind_device(self._h, HD_ALL_SYSTEMS, int(field), ptr), "hd_bind_device")
+        if tensor is None:
+            self._bound.pop(int(field), None)
+        else:
+            self._bound[int(field)] = tensor
 
     def get_state(self, s: int) -> bytes:
         n = ctypes.c_size_t()
