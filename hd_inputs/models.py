@@ -87,6 +87,11 @@ class SystemSpec:
     k_bond: float = 72.0 * 2.0 ** (-1.0 / 3.0)
     r_bond: float = 2.0 ** (1.0 / 6.0)
     r_bond_cut: float = 1.36
+    # eigenvalue bias variable (bias_var 3): the mode estimate, atom layout
+    # (dim, n) (rigid atoms the rigid body's component, fixed atoms 0), and
+    # the step of its per-step rotation towards the lowest mode
+    mode: Optional[np.ndarray] = None
+    mode_alpha: float = 0.0
     # basin reference r_O (defaults to the lattice positions)
     rO: Optional[np.ndarray] = None
     label: str = ""
@@ -104,6 +109,8 @@ class SystemSpec:
             setattr(c, f, getattr(self, f).copy())
         if self.rO is not None:
             c.rO = self.rO.copy()
+        if self.mode is not None:
+            c.mode = self.mode.copy()
         return c
 
 

@@ -24,6 +24,10 @@ struct orc_sys {
     double XR[3], VR[3], XR0[3];
     double *ftot;            /* total force at the current positions */
     double *tuu;             /* T[u,u] of the last evaluation */
+    /* eigenvalue variable: the mode estimate q (atom layout, rigid atoms
+     * the body's component), its normalised spread w = P q/|q|, H w and
+     * T[w,w] of the last evaluation */
+    double *qm, *wn, *hw, *tww;
     double xi[4], eta[4];    /* Nose-Hoover chain velocities and positions */
     double FR[3];            /* total force on the rigid body */
     int64_t step;
@@ -299,6 +303,10 @@ orc_sys *orc_create(const orc_params *p, const double *x, const uint8_t *type,
     s->cofs = (double *)calloc(nd, sizeof(double));
     s->ftot = (double *)calloc(nd, sizeof(double));
     s->tuu = (double *)calloc(nd, sizeof(double));
+    s->qm = (double *)calloc(nd, sizeof(double));
+    s->wn = (double *)calloc(nd, sizeof(double));
+    s->hw = (double *)calloc(nd, sizeof(double));
+    s->tww = (double *)calloc(nd, sizeof(double));
     s->type = (uint8_t *)malloc(p->n);
     s->role = (uint8_t *)malloc(p->n);
     memcpy(s->x, x, sizeof(double) * nd);
@@ -313,6 +321,7 @@ void orc_destroy(orc_sys *s)
 {
     if (!s) return;
     free(s->x); free(s->v); free(s->rO); free(s->cofs); free(s->ftot); free(s->tuu);
+    free(s->qm); free(s->wn); free(s->hw); free(s->tww);
     free(s->type); free(s->role);
     free(s);
 }
@@ -585,11 +594,74 @@ static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot
     double g = has_d ? -G / d : 0.0;
     double kappa = has_d ? uHu / d2 : 0.0;
 
+    /* The eigenvalue variable (eq. 15): lambda = w.Hw, the Rayleigh quotient
+     * of the reduced Hessian along the mode estimate, with w = P q/|q| the
+     * mode spread over the atoms (each rigid atom moves with the rigid body,
+     * fixed atoms do not move) and |q| taken over the degrees of freedom.
+     * A second pass of the pair terms with u replaced by w gives H w and
+     * T[w,w], the gradient of lambda at fixed q; the drive's Hessian adds
+     * its share on the rigid atoms as for H u. */
+    const int eig = (p->bias_var1 == 3 || p->bias_var2 == 3);
+    double lam = 0.0;
+    int have_q = 0;
+    memset(s->wn, 0, sizeof(double) * nd);
+    memset(s->hw, 0, sizeof(double) * nd);
+    memset(s->tww, 0, sizeof(double) * nd);
+    if (eig) {
+        double q2 = 0.0;
+        for (int i = 0; i < n; ++i)
+            if (s->role[i] == MOBILE)
+                for (int k = 0; k < dim; ++k) q2 += s->qm[k * n + i] * s->qm[k * n + i];
+        if (s->n_rigid > 0)
+            for (int k = 0; k < dim; ++k)
+                q2 += s->qm[k * n + s->first_rigid] * s->qm[k * n + s->first_rigid];
+        have_q = q2 > 0.0;
+        if (have_q) {
+            const double inv = 1.0 / sqrt(q2);
+            for (int i = 0; i < n; ++i) {
+                if (s->role[i] == FIXED) continue;
+                const int src = s->role[i] == RIGID ? s->first_rigid : i;
+                for (int k = 0; k < dim; ++k) s->wn[k * n + i] = s->qm[k * n + src] * inv;
+            }
+            double *f2 = (double *)calloc(nd, sizeof(double));
+            double *e2 = (double *)calloc((size_t)n, sizeof(double));
+            pair_ctx c2 = c;
+            c2.u = s->wn; c2.f = f2; c2.hu = s->hw; c2.e_atom = e2; c2.tuu = s->tww; c2.e_lj = 0.0;
+            if (s->brute) {
+                for (int i = 0; i < n; ++i)
+                    for (int j = i + 1; j < n; ++j) {
+                        if (excluded(s->role, i, j)) continue;
+                        lj_pair(&c2, i, j);
+                    }
+            } else {
+                for_pairs_cells(p, s->x, s->role, p->rc, 1, lj_pair, &c2);
+            }
+            free(f2);
+            free(e2);
+            if (s->n_rigid > 0) {
+                const int nR = s->n_rigid, nspring = (dim == 3) ? 2 : 1;
+                double WR[3] = {0, 0, 0};
+                for (int i = 0; i < n; ++i)
+                    if (s->role[i] == RIGID)
+                        for (int k = 0; k < dim; ++k) WR[k] += s->wn[k * n + i];
+                for (int i = 0; i < n; ++i) {
+                    if (s->role[i] != RIGID) continue;
+                    for (int k = 0; k < nspring; ++k)
+                        s->hw[k * n + i] += p->k_spring / ((double)nR * nR) * WR[k];
+                }
+            }
+            for (int i = 0; i < n; ++i) {
+                if (s->role[i] == FIXED) continue;
+                for (int k = 0; k < dim; ++k) lam += s->wn[k * n + i] * s->hw[k * n + i];
+            }
+        }
+    }
+
     /* Bias (eq. 13): dV = dV1(v1) + dV2(v2) - dV1 dV2 / dV_max, each dVi the
      * switch of eq. 14 in its variable (no second variable: dV2 = 0, and
      * eq. 13 reduces to dV1).  Its force is -grad dV, by the chain rule
      * -(1 - dV2/dV_max) dV1' grad v1 - (1 - dV1/dV_max) dV2' grad v2. */
-    const double val[3] = {g, kappa, d};
+    const double val[4] = {g, kappa, d, lam};
     double dv1 = 0.0, dvp1 = 0.0, dv2 = 0.0, dvp2 = 0.0;
     const int v1 = p->bias_var1, v2 = p->bias_var2;
     if (p->bias_on) {
@@ -609,10 +681,11 @@ static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot
             if (s->role[i] == FIXED) continue;
             for (int k = 0; k < dim; ++k) {
                 const size_t q = (size_t)k * n + i;
-                double grad[3];
+                double grad[4];
                 grad[0] = (hu[q] - f[q] - g * u[q] / d) / d;
                 grad[1] = (2.0 * hu[q] + s->tuu[q]) / d2 - 2.0 * kappa * u[q] / d2;
                 grad[2] = u[q] / d;
+                grad[3] = s->tww[q];
                 double gr = w1 * grad[v1];
                 if (v2 >= 0) gr += w2 * grad[v2];
                 fb[q] = -gr;
@@ -642,6 +715,7 @@ static void evaluate(orc_sys *s, double *f, double *hu, double *fb, double *ftot
     sc->dv = dv;
     sc->dvp = dvp;
     sc->kappa = kappa;
+    sc->lambda = lam;
     sc->dv1 = dv1;
     sc->dv2 = dv2;
     sc->e_nhc = nhc_energy(s);
@@ -673,6 +747,79 @@ void orc_compute(orc_sys *s, double *f_lj, double *hu, double *f_b, double *f_to
     if (f_tot) memcpy(f_tot, s->ftot, sizeof(double) * nd);
     if (e_atom) memcpy(e_atom, E, sizeof(double) * s->n);
     if (out) *out = sc;
+    free(F); free(H); free(B); free(E);
+}
+
+/* One rotation step of the eigenvalue variable's mode estimate after an
+ * evaluation: q <- w - alpha (P^T H w - lambda w) over the degrees of
+ * freedom (w the unit mode of that evaluation, P^T H w's rigid-body row the
+ * sum over its atoms), a gradient step on the Rayleigh quotient that turns
+ * w towards the lowest mode; normalised at the next evaluation. */
+static void rotate_mode(orc_sys *s)
+{
+    const orc_params *p = &s->p;
+    const int n = s->n, dim = s->dim;
+    if (!(p->bias_var1 == 3 || p->bias_var2 == 3)) return;
+    const double lam = s->last.lambda, a = p->mode_alpha;
+    int any = 0;
+    for (int i = 0; i < n && !any; ++i)
+        for (int k = 0; k < dim; ++k) any = any || s->wn[k * n + i] != 0.0;
+    if (!any) return;
+    for (int i = 0; i < n; ++i) {
+        if (s->role[i] != MOBILE) continue;
+        for (int k = 0; k < dim; ++k) {
+            const size_t q = (size_t)k * n + i;
+            s->qm[q] = s->wn[q] - a * (s->hw[q] - lam * s->wn[q]);
+        }
+    }
+    if (s->n_rigid > 0) {
+        const int f = s->first_rigid;
+        for (int k = 0; k < dim; ++k) {
+            double HR = 0.0;
+            for (int i = 0; i < n; ++i)
+                if (s->role[i] == RIGID) HR += s->hw[k * n + i];
+            const double qR = s->wn[k * n + f] - a * (HR - lam * s->wn[k * n + f]);
+            for (int i = 0; i < n; ++i)
+                if (s->role[i] == RIGID) s->qm[k * n + i] = qR;
+        }
+    }
+}
+
+void orc_set_mode(orc_sys *s, const double *q)
+{
+    const int n = s->n;
+    for (int i = 0; i < n; ++i) {
+        const int src = s->role[i] == RIGID ? s->first_rigid : i;
+        for (int k = 0; k < s->dim; ++k)
+            s->qm[k * n + i] = s->role[i] == FIXED ? 0.0 : q[k * n + src];
+    }
+    s->have_force = 0;
+}
+
+void orc_get_mode(const orc_sys *s, double *q)
+{
+    const int n = s->n, dim = s->dim;
+    double q2 = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (s->role[i] == MOBILE)
+            for (int k = 0; k < dim; ++k) q2 += s->qm[k * n + i] * s->qm[k * n + i];
+    if (s->n_rigid > 0)
+        for (int k = 0; k < dim; ++k) q2 += s->qm[k * n + s->first_rigid] * s->qm[k * n + s->first_rigid];
+    const double inv = q2 > 0.0 ? 1.0 / sqrt(q2) : 0.0;
+    for (size_t k = 0; k < (size_t)dim * n; ++k) q[k] = s->qm[k] * inv;
+}
+
+void orc_rotate_mode(orc_sys *s)
+{
+    const size_t nd = (size_t)s->dim * s->n;
+    double *F = (double *)malloc(sizeof(double) * nd);
+    double *H = (double *)malloc(sizeof(double) * nd);
+    double *B = (double *)malloc(sizeof(double) * nd);
+    double *E = (double *)malloc(sizeof(double) * s->n);
+    evaluate(s, F, H, B, s->ftot, E, &s->last);
+    s->have_force = 1;
+    rotate_mode(s);
+    s->have_force = 0;
     free(F); free(H); free(B); free(E);
 }
 
@@ -805,6 +952,7 @@ static void nhc_vv_step(orc_sys *s, double *F, double *H, double *B, double *E)
     }
     s->step = s->step + 1;
     evaluate(s, F, H, B, s->ftot, E, &s->last);
+    rotate_mode(s);
     for (int i = 0; i < n; ++i) {
         if (s->role[i] != MOBILE) continue;
         for (int k = 0; k < dim; ++k) s->v[k * n + i] = s->v[k * n + i] + hdt * s->ftot[k * n + i] / p->mass;
@@ -872,6 +1020,7 @@ void orc_step(orc_sys *s, int64_t nsteps)
         }
         s->step = step + 1;
         evaluate(s, F, H, B, s->ftot, E, &s->last);
+        rotate_mode(s);
         for (int i = 0; i < n; ++i) {
             if (s->role[i] != MOBILE) continue;
             for (int k = 0; k < dim; ++k)
@@ -1018,5 +1167,6 @@ int64_t orc_fire(orc_sys *s, double ftol, int64_t maxit)
 
 void orc_get_tuu(const orc_sys *s, double *t)
 {
-    memcpy(t, s->tuu, sizeof(double) * (size_t)s->dim * s->n);
+    const int eig = (s->p.bias_var1 == 3 || s->p.bias_var2 == 3);
+    memcpy(t, eig ? s->tww : s->tuu, sizeof(double) * (size_t)s->dim * s->n);
 }

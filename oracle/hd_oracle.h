@@ -15,13 +15,17 @@
  *     F_R = k (x_S - x_T) (eq. 10);
  *   - everything about the basin minimum r_O, over the generalised position
  *     vector;
- *   - the local variables d (eq. 7), slope g = grad V . s (eq. 5) and
- *     curvature kappa = d2V/ds2 = u.Hu/d^2 (eq. 6), any one or two of them
- *     as bias variables: each through the switch of eq. 14 (eq. 15's form),
- *     two combined by eq. 13; the bias force from the chain rule, with
- *     grad g = (Hu - F - g u/d)/d, grad kappa = (2 Hu + T[u,u])/d^2
- *     - 2 kappa u/d^2 (T[u,u]: third derivatives of V contracted twice with
- *     u) and grad d = u/d;
+ *   - the local variables d (eq. 7), slope g = grad V . s (eq. 5),
+ *     curvature kappa = d2V/ds2 = u.Hu/d^2 (eq. 6) and the eigenvalue
+ *     variable of eq. 15 (the lowest Hessian eigenvalue, tracked as the
+ *     Rayleigh quotient lambda = q^T H q along a mode estimate q that turns
+ *     towards the lowest mode by one gradient step per time step), any one
+ *     or two of them as bias variables: each through the switch of eq. 14
+ *     (eq. 15's form), two combined by eq. 13; the bias force from the
+ *     chain rule, with grad g = (Hu - F - g u/d)/d,
+ *     grad kappa = (2 Hu + T[u,u])/d^2 - 2 kappa u/d^2 (T[u,u]: third
+ *     derivatives of V contracted twice with u), grad d = u/d and
+ *     grad lambda = T[q,q] at fixed q;
  *   - the boosted clock t_hyper = sum dt exp(dV/kT) (eq. 3 as a time average;
  *     eq. 8 fixes what it means for stepped sliding);
  *   - a Langevin BAOAB step, or the paper's Nose-Hoover chain thermostat
@@ -74,6 +78,11 @@ typedef struct {
      * model has a rigid layer) */
     int32_t thermostat, nhc_len;
     double nhc_tau;
+    /* eigenvalue bias variable (3): the Rayleigh quotient of the reduced
+     * Hessian along the system's mode estimate q; after every step q takes
+     * one rotation step q <- q - mode_alpha (H q - lambda q) (normalised
+     * over the degrees of freedom at the next evaluation) */
+    double mode_alpha;
 } orc_params;
 
 typedef struct {
@@ -88,6 +97,9 @@ typedef struct {
     /* Nose-Hoover chain energy sum_j Q_j xi_j^2 / 2 + N_f kT eta_1
      * + kT sum_{j>1} eta_j: with e_kin + e_pot + dv it is conserved */
     double e_nhc;
+    /* the eigenvalue variable lambda = q^T H q along the unit mode estimate
+     * (systems biased on it; 0 otherwise) */
+    double lambda;
 } orc_scalars;
 
 /* Opaque simulation state for one system. */
@@ -130,8 +142,18 @@ void orc_compute(orc_sys *s, double *f_lj, double *hu, double *f_b, double *f_to
  * each; entries beyond nhc_len unused). */
 void orc_get_nhc(const orc_sys *s, double xi[4], double eta[4]);
 void orc_set_nhc(orc_sys *s, const double xi[4], const double eta[4]);
-/* T[u,u] of the last evaluation: the gradient of u.H(r)u at fixed u. */
+/* T[u,u] of the last evaluation: the gradient of u.H(r)u at fixed u (for
+ * a system biased on the eigenvalue variable, T[q,q] along its unit mode). */
 void orc_get_tuu(const orc_sys *s, double *t);
+/* Mode estimate of the eigenvalue variable, atom layout [dim][n]: mobile
+ * atoms' components, the rigid body's (read from its first atom) and zero
+ * for fixed atoms; orc_get_mode returns it normalised over the degrees of
+ * freedom. */
+void orc_set_mode(orc_sys *s, const double *q);
+void orc_get_mode(const orc_sys *s, double *q);
+/* Evaluate at the current positions and take one rotation step of the mode
+ * (what a time step does after its force evaluation), without moving. */
+void orc_rotate_mode(orc_sys *s);
 /* Advance nsteps BAOAB steps (bias included when enabled). */
 void orc_step(orc_sys *s, int64_t nsteps);
 void orc_get_positions(const orc_sys *s, double *x);

@@ -44,6 +44,7 @@ class OrcParams(ctypes.Structure):
         ("bias_var1", ctypes.c_int32), ("bias_var2", ctypes.c_int32),
         ("b2_lo", ctypes.c_double), ("b2_hi", ctypes.c_double),
         ("thermostat", ctypes.c_int32), ("nhc_len", ctypes.c_int32), ("nhc_tau", ctypes.c_double),
+        ("mode_alpha", ctypes.c_double),
     ]
 
 
@@ -57,11 +58,13 @@ class OrcScalars(ctypes.Structure):
         ("t_md", ctypes.c_double), ("t_hyper", ctypes.c_double),
         ("step", ctypes.c_int64), ("flags", ctypes.c_int32), ("pad_f", ctypes.c_int32),
         ("kappa", ctypes.c_double), ("dv1", ctypes.c_double), ("dv2", ctypes.c_double),
-        ("e_nhc", ctypes.c_double),
+        ("e_nhc", ctypes.c_double), ("lambda_", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["lambda"] = d.pop("lambda_")
+        return d
 
 
 _lib = None
@@ -101,6 +104,9 @@ def lib():
         L.orc_get_tuu.argtypes = [vp, dp]
         L.orc_get_nhc.argtypes = [vp, dp, dp]
         L.orc_set_nhc.argtypes = [vp, dp, dp]
+        L.orc_set_mode.argtypes = [vp, dp]
+        L.orc_get_mode.argtypes = [vp, dp]
+        L.orc_rotate_mode.argtypes = [vp]
         L.orc_fire.argtypes = [vp, ctypes.c_double, ctypes.c_int64]
         L.orc_fire.restype = ctypes.c_int64
         _lib = L
@@ -144,6 +150,7 @@ def params_from_spec(spec, **over) -> OrcParams:
     p.thermostat = int(getattr(spec, "thermostat", 0))
     p.nhc_len = int(getattr(spec, "nhc_len", 3))
     p.nhc_tau = float(getattr(spec, "nhc_tau", 0.5))
+    p.mode_alpha = float(getattr(spec, "mode_alpha", 0.0))
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -201,6 +208,8 @@ class OracleSystem:
         self._h = lib().orc_create(ctypes.byref(self._p), _dp(x), _u8(self._type),
                                    _u8(self._role), _dp(rO))
         lib().orc_set_pair_method(self._h, 1 if brute else 0)
+        if getattr(spec, "mode", None) is not None:
+            self.set_mode(spec.mode)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -270,6 +279,22 @@ class OracleSystem:
         xi = np.ascontiguousarray(xi, dtype=np.float64)
         eta = np.ascontiguousarray(eta, dtype=np.float64)
         lib().orc_set_nhc(self._h, _dp(xi), _dp(eta))
+
+    def set_mode(self, q):
+        """Mode estimate of the eigenvalue variable, atom layout [dim][n]
+        (rigid body read from its first atom)."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        lib().orc_set_mode(self._h, _dp(q))
+
+    def mode(self) -> np.ndarray:
+        """The mode estimate normalised over the degrees of freedom."""
+        q = np.zeros((self.dim, self.n))
+        lib().orc_get_mode(self._h, _dp(q))
+        return q
+
+    def rotate_mode(self):
+        """Evaluate at the current positions and rotate the mode once."""
+        lib().orc_rotate_mode(self._h)
 
     def fire(self, ftol=1e-10, maxit=200000) -> int:
         return int(lib().orc_fire(self._h, float(ftol), int(maxit)))

@@ -826,8 +826,12 @@ def _var_spec(oracle_mod, maker, x, rO, v1, v2, frac1=0.4, frac2=0.6):
     """Bias on variables v1 (and v2), thresholds placed so that each variable
     sits inside its switch; the distance switch runs the other way (lo > hi)."""
     spec = maker(x_slider=0.1)
+    if 3 in (v1, v2):
+        # the eigenvalue variable along a seeded mode estimate
+        spec.mode = np.random.default_rng(7).standard_normal((spec.dim, spec.n))
+        spec.bias_var1 = 3
     res = oracle_mod.OracleSystem(spec, x=x, rO=rO).compute()
-    val = {0: res["g"], 1: res["kappa"], 2: res["d"]}
+    val = {0: res["g"], 1: res["kappa"], 2: res["d"], 3: res["lambda"]}
 
     def thresholds(v, frac):
         span = 2.0 * abs(val[v]) + 1.0
@@ -842,7 +846,7 @@ def _var_spec(oracle_mod, maker, x, rO, v1, v2, frac1=0.4, frac2=0.6):
     return spec
 
 
-VAR_PAIRS = [(1, -1), (2, -1), (0, 1), (0, 2), (1, 2), (2, 0)]
+VAR_PAIRS = [(1, -1), (2, -1), (0, 1), (0, 2), (1, 2), (2, 0), (3, -1), (0, 3)]
 
 
 @pytest.mark.parametrize("maker", [small2d, small3d, small_cone], ids=["2d", "3d", "cone"])
@@ -1043,3 +1047,63 @@ def test_eigenvalue_gradient_matches_eigenvalue_differences(oracle_mod, maker):
         ep = oracle_mod.lowest_hessian_eigenvalue(spec, spec.pos + dx)[0]
         em = oracle_mod.lowest_hessian_eigenvalue(spec, spec.pos - dx)[0]
         assert abs((ep - em) / (2 * h) - grad[c]) <= 1e-5 * scale, c
+
+
+# --------------------------------------------------------------------------
+# The eigenvalue variable along the trajectory (eq. 13, eq. 15)
+# --------------------------------------------------------------------------
+def _dof_vector(oracle_mod, spec, q_atoms):
+    """Atom-layout mode -> vector over the degrees of freedom (mobile atoms,
+    then the rigid body's component read from one rigid atom)."""
+    mob, rig, m = oracle_mod.dof_layout(spec)
+    out = list(np.asarray(q_atoms)[:, mob].T.reshape(-1))
+    if len(rig):
+        out += list(np.asarray(q_atoms)[:, rig[0]])
+    return np.array(out)
+
+
+def test_mode_rotation_converges_to_the_lowest_eigenvalue(oracle_mod):
+    """One rotation step per time step, q <- q - alpha (H q - lambda q), is a
+    gradient step on the Rayleigh quotient: at a fixed configuration the
+    steps reach the library eigensolver's lowest eigenvalue of the reduced
+    Hessian and its eigenvector (a model with a rigid layer, whose body's
+    row and drive term take part)."""
+    spec = small2d()
+    o = oracle_mod.OracleSystem(spec)
+    assert o.fire(1e-8) >= 0
+    x = o.positions()
+    H = oracle_mod.reduced_hessian(spec, x)
+    w, V = np.linalg.eigh(0.5 * (H + H.T))
+    assert w[1] - w[0] > 1.0            # a simple lowest eigenvalue
+    s = spec.copy()
+    s.pos, s.bias_var1, s.bias_on = x, 3, 0
+    s.mode_alpha = 0.9 / w[-1]
+    s.mode = np.random.default_rng(1).standard_normal((s.dim, s.n))
+    r = oracle_mod.OracleSystem(s)
+    lam = []
+    for it in range(3000):
+        r.rotate_mode()
+        lam.append(r.scalars()["lambda"])
+    assert lam[-1] == pytest.approx(w[0], rel=1e-10)
+    assert lam[10] > lam[100] > lam[1000] > w[0] - 1e-9     # from above
+    q = _dof_vector(oracle_mod, spec, r.mode())
+    assert abs(np.linalg.norm(q) - 1.0) < 1e-12
+    assert abs(float(q @ V[:, 0])) > 1.0 - 1e-9
+
+
+@pytest.mark.parametrize("maker", [small2d, small_cone], ids=["2d", "cone"])
+def test_eigen_variable_is_the_rayleigh_quotient(oracle_mod, maker):
+    """Along the library eigenvector the variable is the lowest eigenvalue,
+    and its gradient at fixed mode is the eigenvalue's gradient (pinned
+    against differences of the library eigenvalue above); a scaled mode
+    gives the same values (normalisation over the degrees of freedom)."""
+    spec = maker()
+    x = perturbed(spec, 0.03, 5)
+    eps, q, grad = oracle_mod.eigenvalue_gradient(spec, x)
+    s = spec.copy()
+    s.pos, s.bias_var1, s.bias_on = x, 3, 0
+    s.mode = 3.7 * oracle_mod.dof_to_atoms(spec, q)
+    r = oracle_mod.OracleSystem(s).compute()
+    assert r["lambda"] == pytest.approx(eps, rel=1e-10)
+    g = oracle_mod.dof_project(spec, r["tuu"])
+    np.testing.assert_allclose(g, grad, rtol=0, atol=1e-10 * np.abs(grad).max())
