@@ -145,17 +145,22 @@ typedef struct {
                          one variable) */
     double e_nhc;     /* Nose-Hoover chain energy (0 under Langevin): with
                          e_pot + e_kin + dv it is conserved */
+    double lambda;    /* the eigenvalue variable (eq. 15): the Rayleigh
+                         quotient along the mode estimate (systems biased on
+                         it; 0 otherwise) */
 } hd_scalars;
 
 enum { HD_FLAG_UNSTABLE = 1, HD_FLAG_NBR_OVERFLOW = 2 };
 
 /* Which per-atom force hd_read_forces returns. */
 /* HD_TUU: T[u,u], the gradient of u.H(r)u at fixed u (third derivatives of
- * V contracted twice with u), kept for systems biased on the curvature. */
+ * V contracted twice with u), kept for systems biased on the curvature; for
+ * systems biased on the eigenvalue T[w,w] along the unit mode estimate of
+ * the last evaluation (the eigenvalue variable's gradient). */
 enum { HD_FORCE_TOTAL = 0, HD_FORCE_LJ = 1, HD_FORCE_BIAS = 2, HD_HU = 3, HD_TUU = 4 };
 
-/* Bias variables (eq. 5-7). */
-enum { HD_BIAS_SLOPE = 0, HD_BIAS_CURVATURE = 1, HD_BIAS_DISTANCE = 2 };
+/* Bias variables (eq. 5-7, eq. 15). */
+enum { HD_BIAS_SLOPE = 0, HD_BIAS_CURVATURE = 1, HD_BIAS_DISTANCE = 2, HD_BIAS_EIGENVALUE = 3 };
 
 /* Create a context on HIP device `device`.  hip_stream is a hipStream_t to
  * order work on (for example torch.cuda.current_stream().cuda_stream) or NULL
@@ -199,19 +204,47 @@ hd_status hd_set_tip_bonds(hd_ctx *ctx, int32_t sys, int32_t enabled, double k_b
  * critical values lo2, hi2 (same dV_max and m_b), the two combined by
  * eq. 13: dV = dV1 + dV2 - dV1 dV2 / dV_max.  Variables: HD_BIAS_SLOPE
  * g = grad V . s (eq. 5), HD_BIAS_CURVATURE kappa = d2V/ds2 = u.Hu/d^2
- * (eq. 6), HD_BIAS_DISTANCE d = |r - r_O| (eq. 7).  A switch is dV_max at or
- * beyond its upper value and zero at or beyond its lower one; for the slope
- * and the curvature lower < upper, for the distance lower > upper (the bias
- * is full near r_O and vanishes as d grows).  The bias force is -grad dV by
- * the chain rule, with grad g = (Hu - F - g u/d)/d,
- * grad kappa = (2 Hu + T[u,u])/d^2 - 2 kappa u/d^2 and grad d = u/d.
+ * (eq. 6), HD_BIAS_DISTANCE d = |r - r_O| (eq. 7), HD_BIAS_EIGENVALUE the
+ * lowest Hessian eigenvalue of eq. 15 (see hd_set_min_mode).  A switch is
+ * dV_max at or beyond its upper value and zero at or beyond its lower one;
+ * for the slope, the curvature and the eigenvalue lower < upper, for the
+ * distance lower > upper (the bias is full near r_O and vanishes as d
+ * grows).  The bias force is -grad dV by the chain rule, with
+ * grad g = (Hu - F - g u/d)/d, grad kappa = (2 Hu + T[u,u])/d^2
+ * - 2 kappa u/d^2, grad d = u/d and grad lambda = T[w,w].
  * Default: the slope alone.  Before hd_finalize only (HD_E_STATE after);
- * HD_E_ARG for an unknown variable or var2 == var1, and, while the bias is
- * enabled, for critical values in the wrong order (also those set by
- * hd_set_bias, which checks the same against the current variables) or,
- * with two variables, dv_max = 0.  Systems with any other choice than the
- * slope alone run on the grid kernels (never LDS-resident). */
+ * HD_E_ARG for an unknown variable, var2 == var1, the curvature with the
+ * eigenvalue, and, while the bias is enabled, for critical values in the
+ * wrong order (also those set by hd_set_bias, which checks the same against
+ * the current variables) or, with two variables, dv_max = 0.  Systems with
+ * any other choice than the slope alone run on the grid kernels (never
+ * LDS-resident). */
 hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t var2, double lo2, double hi2);
+
+/* The eigenvalue variable of eq. 15 along the trajectory.  The paper biases
+ * on the lowest eigenvalue of the Hessian but does not say how it follows
+ * it; here each system carries a mode estimate q over its degrees of
+ * freedom (mobile atoms' coordinates and the rigid body's), the variable is
+ * the Rayleigh quotient lambda = w.Hw of the unbiased potential's Hessian
+ * along w = P q/|q| (the mode spread over the atoms: each rigid atom moves
+ * with the rigid body, fixed atoms stay; the drive's Hessian included), its
+ * gradient at fixed q is T[w,w] (third derivatives of V contracted twice
+ * with w, from the same pair pass), and after every step's force
+ * evaluation q takes one gradient step on the Rayleigh quotient,
+ * q <- w - alpha (P^T H w - lambda w), which turns it towards the lowest mode
+ * (at a fixed configuration the steps converge to it when alpha is below
+ * 1 / the largest eigenvalue).  mode: host [dim][n], hd_min_mode's layout
+ * (mobile atoms' components, the rigid body's read from its first rigid
+ * atom, fixed atoms ignored); any nonzero length (it is stored normalised
+ * over the degrees of freedom).  Before or after
+ * hd_finalize; HD_E_STATE unless the system is biased on the eigenvalue
+ * (hd_set_bias_variables first); HD_E_ARG for alpha < 0.  Without a mode
+ * (all zero) lambda is 0 and exerts no force. */
+hd_status hd_set_min_mode(hd_ctx *ctx, int32_t sys, const double *mode, double alpha);
+/* The current mode estimate, normalised over the degrees of freedom, into
+ * out [dim][n] (rigid atoms: the rigid body's component; fixed atoms 0).
+ * HD_E_STATE unless the system is biased on the eigenvalue. */
+hd_status hd_read_min_mode(hd_ctx *ctx, int32_t sys, double *out);
 
 /* Thermostat of system `sys`: chain_len = 0 keeps Langevin BAOAB (the
  * default, friction gamma of hd_thermo_params); 1..4 selects the paper's

@@ -11,11 +11,15 @@ enum : int { FLAG_UNSTABLE = 1, FLAG_NBR_OVERFLOW = 2 };
 // Per-system sums: E, d2, G, sumF_R[3], sumHu_R[3], sumU_R[3], and the count
 // of atoms whose LJ force is non-finite or above kForceLimit.  The grid
 // kernels' tile partials add u.Hu and sumT_R[3] (the third-derivative vector
-// T[u,u] over the rigid layer) for systems biased on the curvature.
-enum : int { NRED = 13, NPART = 17 };
-// Bias variables (eq. 5-7) and the extra pair-pass terms a plan compiles in.
-enum : int { BVAR_SLOPE = 0, BVAR_CURV = 1, BVAR_DIST = 2 };
-enum : int { EXT_BONDS = 1, EXT_CURV = 2 };
+// T[u,u] over the rigid layer) for systems biased on the curvature, and for
+// systems biased on the eigenvalue w.Hw, sumT_R[3] (T[w,w]), the mobile
+// atoms' |w|^2 and sumHw_R[3], w the mode estimate spread over the atoms.
+enum : int { NRED = 13, NPART = 21 };
+enum : int { P_XHX = 13, P_TR = 14, P_W2 = 17, P_HWR = 18 };
+// Bias variables (eq. 5-7, eq. 15) and the extra pair-pass terms a plan
+// compiles in.
+enum : int { BVAR_SLOPE = 0, BVAR_CURV = 1, BVAR_DIST = 2, BVAR_EIG = 3 };
+enum : int { EXT_BONDS = 1, EXT_CURV = 2, EXT_EIG = 4 };
 constexpr double kForceLimit2 = 1e12;  // (1e6 eps/sigma)^2
 
 // Read-only description of one system (uploaded at finalize / parameter
@@ -65,6 +69,11 @@ struct SysDesc {
   // nhc_NfkT = N_f kT (grid kernels only)
   int32_t thermostat, nhc_len;
   double nhc_Q1, nhc_Q, nhc_NfkT;
+  // eigenvalue variable (eq. 15; grid kernels only): eig != 0 when one of
+  // the bias variables is it; the mode estimate's rotation step after each
+  // step is q <- (q - mode_alpha (P^T H q - lambda q)) / |q|
+  int32_t eig, pad3;
+  double mode_alpha;
 };
 
 // Mutable per-system state.
@@ -78,6 +87,9 @@ struct SysState {
   double kappa, dv1, dv2;
   double xi[4], eta[4];        // Nose-Hoover chain velocities and positions
   double e_nhc;                // the chain's energy (conserved with K + V + dV)
+  double qR[3];                // eigenvalue variable: the rigid body's mode component
+  double lambda;               // the eigenvalue variable of the last evaluation
+  double eig_inv_q2;           // 1/|q|^2 of the mode that evaluation used
 };
 
 struct Arrays {
@@ -106,7 +118,16 @@ struct Arrays {
   // (double 3) of each sorted position, written by the cell sort, so a
   // stencil row's candidates are consecutive 32-byte records
   double *brec;                           // [ntot][4]
-  double *tuu;                            // [3][ntot] T[u,u] (curvature bias)
+  double *tuu;                            // [3][ntot] T[u,u] (curvature bias) or T[w,w] (eigenvalue)
+  // eigenvalue bias: the mode estimate q of the mobile atoms (rigid atoms'
+  // in SysState.qR), H w of the last pair pass, and per sorted position the
+  // mode spread over the atoms (w: doubles 0-2 of a 32-byte record)
+  double *qm, *hw;                        // [3][ntot]
+  double *recw;                           // [ntot][4]
+  // grid kernels: the tiles (indices into the plan's tiles) and systems
+  // whose lists expire this step, and their counts (written by kg_compact
+  // after the drift, cleared by kg_reduce)
+  int32_t *rb_tiles, *rb_sys, *rb_count;
 };
 
 constexpr int kRecDoubles = 8;
@@ -306,12 +327,16 @@ struct Scal {
   // general bias (eq. 13 over any of slope, curvature, distance): the bias
   // force is cH Hu + cF F + cU u + cT T[u,u] where live
   double kappa, dv1, dv2, cH, cF, cU, cT;
+  // eigenvalue variable: lambda = w.Hw/|q|^2 and eig_s = 1/|q| (0 without a
+  // mode), |q| over the degrees of freedom
+  double lambda, eig_s;
   int live;
 };
 
 template <int DIM, bool GEN = false>
 __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double *sums,
-                                             const double XR[3], int64_t step, Scal &S) {
+                                             const double XR[3], int64_t step, Scal &S,
+                                             const double *qR = nullptr) {
   constexpr int dim = DIM;
   S.xs = D.x_slider + D.v_slider * ((double)step * D.dt);
   S.e_lj = sums[0];
@@ -357,11 +382,32 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double *sum
   S.g = has_d ? -G * inv_d : 0.0;
   S.kappa = 0.0; S.dv2 = 0.0;
   S.cH = S.cF = S.cU = S.cT = 0.0;
+  S.lambda = 0.0; S.eig_s = 0.0;
   S.live = 0;
   if constexpr (GEN) {
     if (D.gen_bias) {
+      // the eigenvalue variable (eq. 15): lambda = w.Hw / |q|^2 along the
+      // mode estimate q (w = P q spread over the atoms), |q|^2 over the
+      // degrees of freedom (mobile atoms and the rigid body once), the
+      // drive's Hessian adding k |q_R|^2 on its spring axes
+      double inv_q2 = 0.0;
+      if (D.eig) {
+        double q2 = sums[P_W2], xhx = sums[P_XHX];
+        if (D.n_rigid > 0 && qR) {
+          constexpr int nspring = dim == 3 ? 2 : 1;
+#pragma unroll
+          for (int k = 0; k < dim; ++k) q2 += qR[k] * qR[k];
+#pragma unroll
+          for (int k = 0; k < nspring; ++k) xhx += D.k_spring * qR[k] * qR[k];
+        }
+        if (q2 > 0.0) {
+          inv_q2 = 1.0 / q2;
+          S.lambda = xhx * inv_q2;
+          S.eig_s = sqrt(inv_q2);
+        }
+      }
       // curvature kappa = u.Hu/d^2 (eq. 6), the drive's Hessian included
-      double uHu = sums[13];
+      double uHu = D.eig ? 0.0 : sums[P_XHX];
       if (D.n_rigid > 0) {
         constexpr int nspring = dim == 3 ? 2 : 1;
 #pragma unroll
@@ -371,7 +417,9 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double *sum
       S.kappa = has_d ? uHu * inv_d2 : 0.0;
       double dv1 = 0.0, p1 = 0.0, dv2 = 0.0, p2 = 0.0;
       const int v1 = D.bias_var1, v2 = D.bias_var2;
-      auto value = [&](int v) { return v == BVAR_SLOPE ? S.g : (v == BVAR_CURV ? S.kappa : S.d); };
+      auto value = [&](int v) {
+        return v == BVAR_SLOPE ? S.g : (v == BVAR_CURV ? S.kappa : (v == BVAR_DIST ? S.d : S.lambda));
+      };
       if (D.bias_on) {
         bias_switch(D, value(v1), D.g_lo, D.g_hi, D.inv_glh, dv1, p1);
         if (v2 >= 0) bias_switch(D, value(v2), D.b2_lo, D.b2_hi, D.inv_glh2, dv2, p2);
@@ -396,6 +444,7 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double *sum
         if (v == BVAR_SLOPE) { cH -= w * inv_d; cF += w * inv_d; cU += w * S.g * inv_d2; }
         else if (v == BVAR_CURV) { cH -= 2.0 * w * inv_d2; cT -= w * inv_d2; cU += 2.0 * w * S.kappa * inv_d2; }
         else if (v == BVAR_DIST) { cU -= w * inv_d; }
+        else if (v == BVAR_EIG) { cT -= w * inv_q2; }   // grad lambda = T[w,w]/|q|^2
       }
       if (S.live) { S.cH = cH; S.cF = cF; S.cU = cU; S.cT = cT; }
       S.bias_a = 0.0; S.bias_b = 0.0;
@@ -405,7 +454,7 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double *sum
         for (int k = 0; k < dim; ++k) {
           const double sumHu = sums[6 + k] + nR * S.hud[k];
           const double sumF = sums[3 + k] + S.Fd[k];
-          S.sumFb[k] = S.cH * sumHu + S.cF * sumF + S.cU * sums[9 + k] + S.cT * sums[14 + k];
+          S.sumFb[k] = S.cH * sumHu + S.cF * sumF + S.cU * sums[9 + k] + S.cT * sums[P_TR + k];
         }
       }
       return;
@@ -449,19 +498,20 @@ struct Comp {  // Kahan compensated float sum: s - c is the running total
 
 template <typename T> struct PairAcc;
 
-// F, H u, the half pair energy and (curvature bias only) T[u,u]
+// F, H u, the half pair energy, T[u,u] (curvature bias) or T[w,w]
+// (eigenvalue bias) and H w (eigenvalue bias)
 template <> struct PairAcc<double> {
-  double F[3], H[3], X[3], e;
+  double F[3], H[3], X[3], W[3], e;
   __device__ __forceinline__ void init() {
-    for (int k = 0; k < 3; ++k) { F[k] = 0.0; H[k] = 0.0; X[k] = 0.0; }
+    for (int k = 0; k < 3; ++k) { F[k] = 0.0; H[k] = 0.0; X[k] = 0.0; W[k] = 0.0; }
     e = 0.0;
   }
 };
 
 template <> struct PairAcc<float> {
-  Comp F[3], H[3], X[3], e;
+  Comp F[3], H[3], X[3], W[3], e;
   __device__ __forceinline__ void init() {
-    for (int k = 0; k < 3; ++k) { F[k].init(); H[k].init(); X[k].init(); }
+    for (int k = 0; k < 3; ++k) { F[k].init(); H[k].init(); X[k].init(); W[k].init(); }
     e.init();
   }
 };
@@ -540,10 +590,14 @@ __device__ __forceinline__ void bond_terms(const LJRow<T> &R, double r2, T &f, T
 // With EXT_CURV also the pair's share of T[u,u], the gradient of u.H(r)u at
 // fixed u: (C |w|^2 + Dc (dx.w)^2) dx + 2 C (dx.w) w with Dc = (dC/dr)/r.
 // WITH_E = false leaves the energy out (a step whose energy nobody reads).
+// With EXT_EIG also, for the eigenvalue bias, the pair's shares of H w and
+// T[w,w] with w = wi - wj the mode estimate's difference (T[w,w] in the X
+// accumulator: the curvature and the eigenvalue bias are not combined).
 template <int DIM, typename T, int EXT = 0, bool WITH_E = true>
 __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, const double dx[3], double r2,
-                                          const T ui[3], const T uj[3], PairAcc<T> &acc) {
-  constexpr bool BONDS = (EXT & EXT_BONDS) != 0, CURV = (EXT & EXT_CURV) != 0;
+                                          const T ui[3], const T uj[3], PairAcc<T> &acc,
+                                          const T *wi = nullptr, const T *wj = nullptr) {
+  constexpr bool BONDS = (EXT & EXT_BONDS) != 0, CURV = (EXT & EXT_CURV) != 0, EIG = (EXT & EXT_EIG) != 0;
   if constexpr (sizeof(T) == 8) {
     double f, C, e, Dc = 0.0;
     if (BONDS && R.bond && tj) {
@@ -557,7 +611,22 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
       C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
       e = 4.0 * eps * (sr6 * sr6 - sr6) - (tj ? R.shift[1] : R.shift[0]) * m;
-      if constexpr (CURV) Dc = eps * r2i * r2i * r2i * sr6 * (-10752.0 * sr6 + 1920.0);
+      if constexpr (CURV || EIG) Dc = eps * r2i * r2i * r2i * sr6 * (-10752.0 * sr6 + 1920.0);
+    }
+    if constexpr (EIG) {
+      double om[3], Do = 0.0, o2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        om[k] = wi[k] - wj[k];
+        Do += dx[k] * om[k];
+        o2 += om[k] * om[k];
+      }
+      const double CDo = C * Do, a = C * o2 + Dc * Do * Do, b = 2.0 * CDo;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        acc.W[k] += CDo * dx[k] - f * om[k];
+        acc.X[k] += a * dx[k] + b * om[k];
+      }
     }
     double w[3], Dw = 0.0;
 #pragma unroll
@@ -594,7 +663,7 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       f = epsr * (48.0f * sr6 - 24.0f);
       C = epsr * r2i * (672.0f * sr6 - 192.0f);
       e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
-      if constexpr (CURV) Dc = epsr * r2i * r2i * (-10752.0f * sr6 + 1920.0f);
+      if constexpr (CURV || EIG) Dc = epsr * r2i * r2i * (-10752.0f * sr6 + 1920.0f);
     }
     float d[3], w[3], Dw = 0.0f;
 #pragma unroll
@@ -602,6 +671,21 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       d[k] = (float)dx[k];
       w[k] = ui[k] - uj[k];
       Dw = __builtin_fmaf(d[k], w[k], Dw);
+    }
+    if constexpr (EIG) {
+      float om[3], Do = 0.0f, o2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        om[k] = wi[k] - wj[k];
+        Do = __builtin_fmaf(d[k], om[k], Do);
+        o2 = __builtin_fmaf(om[k], om[k], o2);
+      }
+      const float CDo = C * Do, a = __builtin_fmaf(Dc * Do, Do, C * o2), b = 2.0f * CDo;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        acc.W[k].add(__builtin_fmaf(CDo, d[k], -f * om[k]));
+        acc.X[k].add(__builtin_fmaf(a, d[k], b * om[k]));
+      }
     }
     const float CDw = C * Dw;
 #pragma unroll
@@ -738,8 +822,25 @@ constexpr int kGatherBlock = 4;
 template <int DIM, typename T, int EXT, bool LASTP>
 __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &R, const char *__restrict__ recb,
                                               const char *__restrict__ nbrb, uint32_t lo, uint32_t lstep,
-                                              int cnt, const double xi[3], const T ui[3], PairAcc<T> &acc) {
-  if constexpr ((EXT & EXT_BONDS) != 0) {
+                                              int cnt, const double xi[3], const T ui[3], PairAcc<T> &acc,
+                                              const char *__restrict__ recwb = nullptr, const T *wi = nullptr) {
+  if constexpr ((EXT & EXT_EIG) != 0) {
+    // eigenvalue bias: the neighbour's mode estimate comes from its 32-byte
+    // mode record beside the pair record
+    for (int c = 0; c < cnt; ++c) {
+      const int ent = __builtin_nontemporal_load((const int32_t *)(nbrb + lo));
+      lo += lstep;
+      const uint32_t pj = (uint32_t)ent >> 1;
+      const double *r = (const double *)(recb + (pj << 6));
+      const double *rw = (const double *)(recwb + (pj << 5));
+      double xj[3], dx[3];
+      T uj[3], wj[3];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; wj[k] = (T)rw[k]; }
+      const double r2 = pair_disp_l<DIM, LASTP>(D, xi, xj, dx);
+      pair_term<DIM, T, EXT>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc, wi, wj);
+    }
+  } else if constexpr ((EXT & EXT_BONDS) != 0) {
     // With tip bonds the pair term branches (bond or LJ), which keeps the
     // compiler from hoisting the next neighbours' gathers over it: a block of
     // kGatherBlock list entries and their records is loaded before the
@@ -795,7 +896,8 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
 template <int DIM, typename T, int EXT = 0>
 __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
                                               const double xi[3], const T ui[3], int ti,
-                                              PairAcc<T> &acc, int q0 = 0, int qstep = 1) {
+                                              PairAcc<T> &acc, int q0 = 0, int qstep = 1,
+                                              const T *wi = nullptr) {
   static_assert(kRecDoubles == 8, "records are 64 bytes");
   const int64_t off = D.off;
   const int n = D.n;
@@ -805,10 +907,11 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
   const int cnt = nn > q0 ? (nn - q0 + qstep - 1) / qstep : 0;
   const uint32_t lo = ((uint32_t)q0 * (uint32_t)n + (uint32_t)p) * 4u;
   const uint32_t lstep = (uint32_t)qstep * (uint32_t)n * 4u;
+  const char *recwb = (EXT & EXT_EIG) != 0 ? (const char *)(A.recw + off * 4) : nullptr;
   LJRow<T> R;
   R.load(D, ti);
-  if (D.periodic[DIM - 1]) pair_loop_rec<DIM, T, EXT, true>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc);
-  else pair_loop_rec<DIM, T, EXT, false>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc);
+  if (D.periodic[DIM - 1]) pair_loop_rec<DIM, T, EXT, true>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
+  else pair_loop_rec<DIM, T, EXT, false>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
 }
 
 // ---------------------------------------------------------------------------

@@ -50,23 +50,38 @@ __device__ void rigid_advance(const SysDesc &D, const SysState &st, int64_t step
   }
 }
 
-// B A O A for every atom of the tile (B and a full A under the Nose-Hoover
-// chain, whose velocity scalings are separate launches); rigid atoms follow
-// the rigid body, which each of their threads advances identically.  Also refreshes u and raises
-// the system's rebuild flag when an atom has left its skin.
-template <int DIM, typename T>
-__device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A, const Tile &t,
-                           bool compute_only) {
-  const int i = t.first + threadIdx.x;
-  if (threadIdx.x >= t.count) return;
+// Half kick v + (dt/2) F/m, with one explicit rounding pattern wherever it is
+// taken (a step's closing kick and the next step's opening one, in separate
+// kernels or in the fused one), so that a run split across calls is the
+// same bit for bit as one call.
+__device__ __forceinline__ double half_kick(const SysDesc &D, double v, double f) {
+  return __builtin_fma(D.hdt * f, D.inv_mass, v);
+}
+
+// B A O A for one atom (B and a full A under the Nose-Hoover chain, whose
+// velocity scalings are separate launches); rigid atoms follow the rigid
+// body, which each of their threads advances identically.  A mobile atom's
+// velocity, total force and mode estimate come from memory, or (FUSED) from
+// the fused kick's registers vr, fr, qr.  Writes the atom's pair record and
+// mode record, and raises the system's rebuild flag when the atom has left
+// its skin.
+template <int DIM, typename T, bool FUSED = false>
+__device__ __forceinline__ void drift_atom(const SysDesc &D, const SysState &st, const Arrays &A, int i,
+                                           bool compute_only, const double (&vr)[3], const double (&fr)[3],
+                                           const double (&qr)[3]) {
   const int64_t N = A.ntot, a = D.off + i;
   const int tr = A.tr[a], role = tr >> 1;
   double *rec = A.rec + (D.off + A.pos[a]) * kRecDoubles;
   if (role == ROLE_FIXED) {
-    // fixed atoms: position as is, u = 0
+    // fixed atoms: position as is, u = 0 (and no mode component)
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { rec[k] = A.x[k * N + a]; rec[3 + k] = 0.0; }
     rec[7] = (double)tr;
+    if (D.eig) {
+      double *rw = A.recw + (D.off + A.pos[a]) * 4;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) rw[k] = 0.0;
+    }
     return;
   }
   const int64_t step = st.step;
@@ -75,7 +90,7 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
     if (!compute_only && D.thermostat == 1) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
-        const double v = A.v[k * N + a] + D.hdt * A.ftot[k * N + a] * D.inv_mass;
+        const double v = half_kick(D, FUSED ? vr[k] : A.v[k * N + a], FUSED ? fr[k] : A.ftot[k * N + a]);
         const double x = wrapx(A.x[k * N + a] + D.dt * v, D.box[k], D.periodic[k]);
         A.x[k * N + a] = x;
         A.v[k * N + a] = v;
@@ -86,8 +101,8 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
       noise<DIM, T>(D.seed, step, (uint32_t)i, z);
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
-        double v = A.v[k * N + a], x = A.x[k * N + a];
-        v = v + D.hdt * A.ftot[k * N + a] * D.inv_mass;
+        double v = FUSED ? vr[k] : A.v[k * N + a], x = A.x[k * N + a];
+        v = half_kick(D, v, FUSED ? fr[k] : A.ftot[k * N + a]);
         x = x + D.hdt * v;
         v = D.c1 * v + D.c2 * z[k];
         x = x + D.hdt * v;
@@ -119,18 +134,24 @@ __device__ void drift_tile(const SysDesc &D, const SysState &st, const Arrays &A
       A.x[k * N + a] = xn[k];
     }
   }
+  // the pair record (the grid kernels read u there only)
   double d2 = 0.0;
-  T *u = (T *)A.u;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const double uk = minimg(xn[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
-    u[k * N + a] = (T)uk;
     rec[k] = xn[k];
     rec[3 + k] = uk;
     const double dd = minimg(xn[k] - A.xb[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
     d2 += dd * dd;
   }
   rec[7] = (double)tr;
+  if (D.eig) {
+    // the mode estimate spread over the atoms, beside the pair record
+    double *rw = A.recw + (D.off + A.pos[a]) * 4;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+      rw[k] = role == ROLE_MOBILE ? (FUSED ? qr[k] : A.qm[k * N + a]) : st.qR[k];
+  }
   // an atom outside its skin forces a rebuild from the current positions
   // (value 1), superseding a pending rebuild from build positions (value 2)
   if (d2 > D.skin_half2) atomicExch(&A.rebuild_flag[A.sys_of[a]], 1);
@@ -142,15 +163,30 @@ __global__ __launch_bounds__(1024) void kg_drift(const SysDesc *__restrict__ des
                                                  const Tile *__restrict__ tiles, int ntiles,
                                                  int compute_only) {
   const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  if (threadIdx.x >= t.count) return;
   const SysDesc &D = descs[t.sys];
-  if (D.dim == 2) drift_tile<2, T>(D, states[t.sys], A, t, compute_only != 0);
-  else drift_tile<3, T>(D, states[t.sys], A, t, compute_only != 0);
+  const int i = t.first + threadIdx.x;
+  const double none[3] = {0, 0, 0};
+  if (D.dim == 2) drift_atom<2, T>(D, states[t.sys], A, i, compute_only != 0, none, none, none);
+  else drift_atom<3, T>(D, states[t.sys], A, i, compute_only != 0, none, none, none);
 }
 
 // ---- neighbour-list rebuild, only for systems whose flag is raised --------
+// After the drift has raised the flags, kg_compact lists the raised tiles and
+// systems (in any order: the rebuild's results do not depend on it); the
+// rebuild kernels then run fixed grids that walk only those lists, so a step
+// in which no list expired costs a few empty launches.  The lists' counts are
+// cleared by kg_reduce, after the rebuild of the step has read them.
 __global__ void kg_set_flags(int32_t *flags, const int32_t *sys_ids, int nsys, int value) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < nsys) flags[sys_ids[k]] = value;
+}
+
+__global__ __launch_bounds__(256) void kg_compact(Arrays A, const Tile *__restrict__ tiles, int ntiles,
+                                                  const int32_t *__restrict__ sys_ids, int nsys) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ntiles && A.rebuild_flag[tiles[k].sys]) A.rb_tiles[atomicAdd(&A.rb_count[0], 1)] = k;
+  if (k < nsys && A.rebuild_flag[sys_ids[k]]) A.rb_sys[atomicAdd(&A.rb_count[1], 1)] = sys_ids[k];
 }
 
 template <int DIM>
@@ -166,52 +202,59 @@ __device__ int cell_of_g(const SysDesc &D, const double *x, int64_t N, int64_t a
 }
 
 __global__ __launch_bounds__(1024) void kg_cell_count(const SysDesc *__restrict__ descs, Arrays A,
-                                                      const Tile *__restrict__ tiles, int ntiles) {
-  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
-  const int flag = A.rebuild_flag[t.sys];
-  if (!flag || threadIdx.x >= t.count) return;
-  const SysDesc &D = descs[t.sys];
-  const int64_t a = D.off + t.first + threadIdx.x;
-  const double *xs = flag == 2 ? A.xb : A.x;  // 2: from the recorded build positions
-  const int c = D.dim == 2 ? cell_of_g<2>(D, xs, A.ntot, a) : cell_of_g<3>(D, xs, A.ntot, a);
-  A.cidx[a] = c;
-  atomicAdd(&A.cell_count[D.cell_off + c], 1);
+                                                      const Tile *__restrict__ tiles) {
+  const int nw = __hip_atomic_load(&A.rb_count[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+    const Tile t = tiles[A.rb_tiles[w]];
+    if (threadIdx.x >= t.count) continue;
+    const int flag = A.rebuild_flag[t.sys];
+    const SysDesc &D = descs[t.sys];
+    const int64_t a = D.off + t.first + threadIdx.x;
+    const double *xs = flag == 2 ? A.xb : A.x;  // 2: from the recorded build positions
+    const int c = D.dim == 2 ? cell_of_g<2>(D, xs, A.ntot, a) : cell_of_g<3>(D, xs, A.ntot, a);
+    A.cidx[a] = c;
+    atomicAdd(&A.cell_count[D.cell_off + c], 1);
+  }
 }
 
-__global__ __launch_bounds__(1024) void kg_cell_scan(const SysDesc *__restrict__ descs, Arrays A,
-                                                     const int32_t *__restrict__ sys_ids) {
-  const int s = sys_ids[blockIdx.x];
-  if (!A.rebuild_flag[s]) return;
+__global__ __launch_bounds__(1024) void kg_cell_scan(const SysDesc *__restrict__ descs, Arrays A) {
   __shared__ int lds_int[32];
-  const SysDesc &D = descs[s];
-  const int tid = threadIdx.x, B = blockDim.x, ncell = D.ncell;
-  int32_t *cnt = A.cell_count + D.cell_off;
-  int32_t *cst = A.cell_start + D.cstart_off;
-  const int chunk = (ncell + B - 1) / B;
-  const int c0 = tid * chunk, c1 = min(ncell, c0 + chunk);
-  int local = 0;
-  for (int c = c0; c < c1; ++c) local += __hip_atomic_load(&cnt[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  int total = 0;
-  int run = block_exscan(local, lds_int, total);
-  for (int c = c0; c < c1; ++c) {
-    const int k = __hip_atomic_load(&cnt[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    cst[c] = run;
-    run += k;
-    __hip_atomic_store(&cnt[c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int nw = __hip_atomic_load(&A.rb_count[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+    const int s = A.rb_sys[w];
+    const SysDesc &D = descs[s];
+    const int tid = threadIdx.x, B = blockDim.x, ncell = D.ncell;
+    int32_t *cnt = A.cell_count + D.cell_off;
+    int32_t *cst = A.cell_start + D.cstart_off;
+    const int chunk = (ncell + B - 1) / B;
+    const int c0 = tid * chunk, c1 = min(ncell, c0 + chunk);
+    int local = 0;
+    for (int c = c0; c < c1; ++c) local += __hip_atomic_load(&cnt[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int total = 0;
+    int run = block_exscan(local, lds_int, total);
+    for (int c = c0; c < c1; ++c) {
+      const int k = __hip_atomic_load(&cnt[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      cst[c] = run;
+      run += k;
+      __hip_atomic_store(&cnt[c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid == 0) cst[ncell] = total;
   }
-  if (tid == 0) cst[ncell] = total;
 }
 
 __global__ __launch_bounds__(1024) void kg_cell_scatter(const SysDesc *__restrict__ descs, Arrays A,
-                                                        const Tile *__restrict__ tiles, int ntiles) {
-  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
-  if (!A.rebuild_flag[t.sys] || threadIdx.x >= t.count) return;
-  const SysDesc &D = descs[t.sys];
-  const int i = t.first + threadIdx.x;
-  const int64_t a = D.off + i;
-  const int c = A.cidx[a];
-  const int slot = atomicAdd(&A.cell_count[D.cell_off + c], 1);
-  A.cell_atoms[D.off + A.cell_start[D.cstart_off + c] + slot] = i;
+                                                        const Tile *__restrict__ tiles) {
+  const int nw = __hip_atomic_load(&A.rb_count[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+    const Tile t = tiles[A.rb_tiles[w]];
+    if (threadIdx.x >= t.count) continue;
+    const SysDesc &D = descs[t.sys];
+    const int i = t.first + threadIdx.x;
+    const int64_t a = D.off + i;
+    const int c = A.cidx[a];
+    const int slot = atomicAdd(&A.cell_count[D.cell_off + c], 1);
+    A.cell_atoms[D.off + A.cell_start[D.cstart_off + c] + slot] = i;
+  }
 }
 
 // Build record of sorted position p (atom i): build position and type/role.
@@ -232,11 +275,11 @@ __device__ __forceinline__ void put_brec(const SysDesc &D, const Arrays &A, cons
 // than kSortMax atoms, which only clamping at an open boundary can produce,
 // are sorted by insertion.
 constexpr int kSortMax = 256;
-__global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ descs, Arrays A,
-                                                    const int32_t *__restrict__ sys_ids, int nsys) {
+__global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ descs, Arrays A) {
   __shared__ int keys[4][kSortMax];
-  const int s = sys_ids[blockIdx.y];
-  if (!A.rebuild_flag[s]) return;
+  const int nw = __hip_atomic_load(&A.rb_count[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int ws = blockIdx.y; ws < nw; ws += gridDim.y) {
+  const int s = A.rb_sys[ws];
   const SysDesc &D = descs[s];
   const double *xs = A.rebuild_flag[s] == 2 ? A.xb : A.x;  // 2: from the recorded build positions
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -271,6 +314,7 @@ __global__ __launch_bounds__(256) void kg_cell_sort(const SysDesc *__restrict__ 
     }
     if (have && lane == 0) __hip_atomic_store(&A.cell_count[D.cell_off + c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
+  }
   }
 }
 
@@ -470,29 +514,36 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
     rec[3 + k] = (tr >> 1) == ROLE_FIXED ? 0.0 : minimg(xk - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
   }
   rec[7] = (double)tr;
+  if (D.eig) {
+    double *rw = A.recw + (off + p) * 4;
+    for (int k = 0; k < DIM; ++k)
+      rw[k] = (tr >> 1) == ROLE_MOBILE ? A.qm[k * N + a] : ((tr >> 1) == ROLE_RIGID ? st.qR[k] : 0.0);
+  }
   if (flag != 2)
     for (int k = 0; k < DIM; ++k) A.xb[k * N + a] = A.x[k * N + a];
   if (p == 0 && flag != 2) atomicAdd(&st.n_rebuilds, 1);
 }
 
-// blockIdx.x = part * ntiles + tile: consecutive blocks go to different XCDs,
-// so the few systems that rebuild in a step spread over the whole chip.
+// Work item w = part * (flagged tiles) + k: consecutive items are parts of
+// different tiles, and consecutive workgroups go to different XCDs, so the
+// few systems that rebuild in a step spread over the whole chip.
 __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__restrict__ descs,
                                                                SysState *__restrict__ states, Arrays A,
-                                                               const Tile *__restrict__ tiles, int ntiles) {
+                                                               const Tile *__restrict__ tiles, int parts) {
   __shared__ int32_t sub[kRowCap * kBuildThreads];
   __shared__ int counts[kBuildThreads];
-  const int tile = blockIdx.x % ntiles, part = blockIdx.x / ntiles;
-  const Tile t = tiles[tile];
-  const int flag = A.rebuild_flag[t.sys];
-  if (!flag) return;
-  const SysDesc &D = descs[t.sys];
-  if (D.dim == 2) {
-    if (part * (kBuildThreads / 3) >= t.count) return;
-    build_rows<2>(D, states[t.sys], A, t, part, flag, sub, counts);
-  } else {
-    if (part * (kBuildThreads / 9) >= t.count) return;
-    build_rows<3>(D, states[t.sys], A, t, part, flag, sub, counts);
+  const int nt = __hip_atomic_load(&A.rb_count[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int w = blockIdx.x; w < nt * parts; w += gridDim.x) {
+    const int part = w / nt;
+    const Tile t = tiles[A.rb_tiles[w - part * nt]];
+    const int flag = A.rebuild_flag[t.sys];
+    const SysDesc &D = descs[t.sys];
+    if (D.dim == 2) {
+      if (part * (kBuildThreads / 3) < t.count) build_rows<2>(D, states[t.sys], A, t, part, flag, sub, counts);
+    } else {
+      if (part * (kBuildThreads / 9) < t.count) build_rows<3>(D, states[t.sys], A, t, part, flag, sub, counts);
+    }
+    __syncthreads();   // sub and counts are reused by the next item
   }
 }
 
@@ -503,7 +554,10 @@ __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__
 // latency.
 template <int DIM, typename T, int LPA, int EXT>
 __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int tile_index) {
-  constexpr bool CURV = (EXT & EXT_CURV) != 0;
+  constexpr bool CURV = (EXT & EXT_CURV) != 0, EIG = (EXT & EXT_EIG) != 0;
+  static_assert(!(CURV && EIG), "the curvature and the eigenvalue bias share the X accumulator");
+  // partial slots this instantiation fills
+  constexpr int NVALID = EIG ? NPART : (CURV ? NRED + 4 : NRED);
   __shared__ double red[NPART * 16];
   const int64_t N = A.ntot;
   double sums[NRED];
@@ -523,16 +577,26 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
     u64[k] = r[3 + k];
     ui[k] = (T)u64[k];
   }
+  double w64[3] = {0, 0, 0};
+  T wi[3] = {0, 0, 0};
+  if constexpr (EIG) {
+    const double *rw = A.recw + (D.off + p) * 4;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { w64[k] = rw[k]; wi[k] = (T)w64[k]; }
+  }
   PairAcc<T> acc;
   acc.init();
-  if (valid) pair_atom_rec<DIM, T, EXT>(D, A, p, xi, ui, tr & 1, acc, sub, LPA);
-  double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, X[3] = {0, 0, 0}, e;
+  if (valid) pair_atom_rec<DIM, T, EXT>(D, A, p, xi, ui, tr & 1, acc, sub, LPA, wi);
+  double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, X[3] = {0, 0, 0}, W[3] = {0, 0, 0}, e;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     if constexpr (sizeof(T) == 8) { F[k] = acc.F[k]; H[k] = acc.H[k]; }
     else { F[k] = acc.F[k].get(); H[k] = acc.H[k].get(); }
-    if constexpr (CURV) {
+    if constexpr (CURV || EIG) {
       if constexpr (sizeof(T) == 8) X[k] = acc.X[k]; else X[k] = acc.X[k].get();
+    }
+    if constexpr (EIG) {
+      if constexpr (sizeof(T) == 8) W[k] = acc.W[k]; else W[k] = acc.W[k].get();
     }
   }
   if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
@@ -541,21 +605,32 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { F[k] += dpp_mov_f64<0xb1>(F[k]); H[k] += dpp_mov_f64<0xb1>(H[k]); }
     e += dpp_mov_f64<0xb1>(e);   // lanes 0<->1, 2<->3
-    if constexpr (CURV) {
+    if constexpr (CURV || EIG) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) X[k] += dpp_mov_f64<0xb1>(X[k]);
+    }
+    if constexpr (EIG) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) W[k] += dpp_mov_f64<0xb1>(W[k]);
     }
   }
   if constexpr (LPA >= 4) {
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { F[k] += dpp_mov_f64<0x4e>(F[k]); H[k] += dpp_mov_f64<0x4e>(H[k]); }
     e += dpp_mov_f64<0x4e>(e);   // lanes 0<->2, 1<->3
-    if constexpr (CURV) {
+    if constexpr (CURV || EIG) {
 #pragma unroll
       for (int k = 0; k < DIM; ++k) X[k] += dpp_mov_f64<0x4e>(X[k]);
     }
+    if constexpr (EIG) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) W[k] += dpp_mov_f64<0x4e>(W[k]);
+    }
   }
   double ext[4] = {0.0, 0.0, 0.0, 0.0};   // u.Hu, sum over the rigid layer of T
+  // eigenvalue bias: w.Hw, the rigid layer's T[w,w], the mobile atoms' |w|^2
+  // and the rigid layer's H w (slots P_XHX ... P_HWR + 2)
+  double ext8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   static_assert(LPA == 1 || LPA == 2 || LPA == 4, "one, two or four lanes per atom");
   if (valid && sub == 0) {
     const int64_t a = D.off + A.cell_atoms[D.off + p];
@@ -590,6 +665,22 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
         for (int k = 0; k < DIM; ++k) ext[1 + k] = X[k];
       }
     }
+    if constexpr (EIG) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { A.tuu[k * N + a] = X[k]; A.hw[k * N + a] = W[k]; }
+      if (role != ROLE_FIXED) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ext8[0] += w64[k] * W[k];
+      }
+      if (role == ROLE_MOBILE) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ext8[4] += w64[k] * w64[k];
+      }
+      if (role == ROLE_RIGID) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) { ext8[1 + k] = X[k]; ext8[5 + k] = W[k]; }
+      }
+    }
   }
   // the tile's sums: a reduce-scatter butterfly within each wavefront (the
   // rigid-layer sums only in wavefronts holding rigid atoms; elsewhere they
@@ -618,10 +709,14 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
     const double tot = wave_sums_scatter<4>(ext, lane);
     if (lane < 4) red[(NRED + wave_scatter_index<4>(lane)) * 16 + wave] = tot;
   }
+  if constexpr (EIG) {
+    const double tot = wave_sums_scatter<8>(ext8, lane);
+    if (lane < 8) red[(NRED + wave_scatter_index<8>(lane)) * 16 + wave] = tot;
+  }
   __syncthreads();
   if (threadIdx.x < NPART) {
     double s = 0.0;
-    if (CURV || threadIdx.x < NRED)
+    if (threadIdx.x < NVALID)
       for (int w = 0; w < nw; ++w) s += red[threadIdx.x * 16 + w];
     A.partials[(int64_t)tile_index * NPART + threadIdx.x] = s;
   }
@@ -653,7 +748,20 @@ __device__ void reduce_system(const SysDesc &D, SysState &st, const Arrays &A, i
     }
     const int64_t estep = compute_only ? st.step : st.step + 1;
     Scal S;
-    eval_scalars<DIM, true>(D, tot, XRn, estep, S);
+    eval_scalars<DIM, true>(D, tot, XRn, estep, S, st.qR);
+    st.lambda = S.lambda;
+    st.eig_inv_q2 = S.eig_s * S.eig_s;
+    if (!compute_only && D.eig && S.eig_s > 0.0 && D.n_rigid > 0) {
+      // the rigid body's row of the mode's rotation step: its atoms' H w and
+      // the drive's Hessian k q_R on the spring axes
+      constexpr int nspring = DIM == 3 ? 2 : 1;
+      double qn[3] = {0, 0, 0};
+      for (int k = 0; k < DIM; ++k) {
+        const double HR = tot[P_HWR + k] + (k < nspring ? D.k_spring * st.qR[k] : 0.0);
+        qn[k] = S.eig_s * (st.qR[k] - D.mode_alpha * (HR - S.lambda * st.qR[k]));
+      }
+      for (int k = 0; k < DIM; ++k) st.qR[k] = qn[k];
+    }
     double FR[3] = {0, 0, 0};
     for (int k = 0; k < DIM; ++k) FR[k] = tot[3 + k] + S.Fd[k] + S.sumFb[k];
     if (!compute_only) {
@@ -686,6 +794,8 @@ __global__ __launch_bounds__(256) void kg_reduce(const SysDesc *__restrict__ des
   const SysDesc &D = descs[s];
   if (D.dim == 2) reduce_system<2>(D, states[s], A, s, first, nts, gs, compute_only != 0);
   else reduce_system<3>(D, states[s], A, s, first, nts, gs, compute_only != 0);
+  // this step's rebuild lists have been used: empty them for the next one
+  if (blockIdx.x == 0 && threadIdx.x == 0) { A.rb_count[0] = 0; A.rb_count[1] = 0; }
 }
 
 // EXT: the extra pair terms the plan's systems need -- EXT_BONDS for models
@@ -703,16 +813,19 @@ __global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ des
 }
 
 // ---- bias force, total force and final B -----------------------------------
-__global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ descs, Arrays A,
-                                                const Tile *__restrict__ tiles, int ntiles,
-                                                const GridScal *__restrict__ gs, int compute_only) {
-  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
-  if (threadIdx.x >= t.count) return;
-  const SysDesc &D = descs[t.sys];
-  const Scal &S = gs[t.sys].S;
-  const int64_t N = A.ntot, a = D.off + t.first + threadIdx.x;
-  const int role = A.tr[a] >> 1;
-  for (int k = 0; k < D.dim; ++k) {
+// One atom's closing kick of a step: the drive's share on rigid atoms, the
+// bias force, the total force ft and the final B (mobile atoms; rigid atoms
+// take the rigid body's velocity), and the eigenvalue variable's mode
+// rotation.  store: write the forces and the velocity (a step that closes a
+// call, or an evaluation); the fused kick-drift keeps them in registers.
+template <int DIM>
+__device__ __forceinline__ void kick_atom(const SysDesc &D, const GridScal &G, const Arrays &A, int64_t a,
+                                          int role, bool compute_only, bool store, double (&ft)[3],
+                                          double (&vn)[3], double (&qn)[3]) {
+  const Scal &S = G.S;
+  const int64_t N = A.ntot;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
     double f = A.flj[k * N + a], h = A.hu[k * N + a], fb = 0.0;
     if (role != ROLE_FIXED) {
       if (role == ROLE_RIGID) { f += S.Fd[k] * D.inv_nR; h += S.hud[k]; }
@@ -720,22 +833,69 @@ __global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ desc
         if (S.live) {
           const double uk = minimg(A.x[k * N + a] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
           fb = S.cH * h + S.cF * f + S.cU * uk;
-          if (D.curv) fb += S.cT * A.tuu[k * N + a];
+          if (D.curv || D.eig) fb += S.cT * A.tuu[k * N + a];
         }
       } else if (D.bias_on && S.d >= 1e-12 && S.dvp != 0.0) {
         const double uk = minimg(A.x[k * N + a] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
         fb = S.bias_a * (h - f - S.bias_b * uk);
       }
     }
-    const double ft = f + fb;
-    A.flj[k * N + a] = f;
-    A.hu[k * N + a] = h;
-    A.fb[k * N + a] = fb;
-    A.ftot[k * N + a] = ft;
-    if (!compute_only) {
-      if (role == ROLE_MOBILE) A.v[k * N + a] = A.v[k * N + a] + D.hdt * ft * D.inv_mass;
-      else if (role == ROLE_RIGID) A.v[k * N + a] = gs[t.sys].VRn[k];
+    ft[k] = f + fb;
+    if (store) {
+      A.flj[k * N + a] = f;
+      A.hu[k * N + a] = h;
+      A.fb[k * N + a] = fb;
+      A.ftot[k * N + a] = ft[k];
     }
+    if (!compute_only) {
+      if (role == ROLE_MOBILE) vn[k] = half_kick(D, A.v[k * N + a], ft[k]);
+      else vn[k] = G.VRn[k];
+      if (store && role != ROLE_FIXED) A.v[k * N + a] = vn[k];
+      // the mode estimate's rotation step towards the lowest mode
+      if (D.eig && role == ROLE_MOBILE) {
+        const double q = A.qm[k * N + a];
+        qn[k] = S.eig_s > 0.0 ? S.eig_s * (q - D.mode_alpha * (A.hw[k * N + a] - S.lambda * q)) : q;
+        A.qm[k * N + a] = qn[k];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ descs, Arrays A,
+                                                const Tile *__restrict__ tiles, int ntiles,
+                                                const GridScal *__restrict__ gs, int compute_only) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  if (threadIdx.x >= t.count) return;
+  const SysDesc &D = descs[t.sys];
+  const int64_t a = D.off + t.first + threadIdx.x;
+  const int role = A.tr[a] >> 1;
+  double ft[3], vn[3], qn[3];
+  if (D.dim == 2) kick_atom<2>(D, gs[t.sys], A, a, role, compute_only != 0, true, ft, vn, qn);
+  else kick_atom<3>(D, gs[t.sys], A, a, role, compute_only != 0, true, ft, vn, qn);
+}
+
+// A step's closing kick fused with the next step's B A O A (Langevin plans
+// only: the Nose-Hoover chain scales the velocities in between): the total
+// force, velocity and mode stay in registers between the two, so the forces
+// are not written and read back, and x, v and r_O are read once.
+template <typename T>
+__global__ __launch_bounds__(1024) void kg_kick_drift(const SysDesc *__restrict__ descs,
+                                                      const SysState *__restrict__ states, Arrays A,
+                                                      const Tile *__restrict__ tiles, int ntiles,
+                                                      const GridScal *__restrict__ gs) {
+  const Tile t = tiles[xcd_tile(blockIdx.x, ntiles)];
+  if (threadIdx.x >= t.count) return;
+  const SysDesc &D = descs[t.sys];
+  const int i = t.first + threadIdx.x;
+  const int64_t a = D.off + i;
+  const int role = A.tr[a] >> 1;
+  double ft[3] = {0, 0, 0}, vn[3] = {0, 0, 0}, qn[3] = {0, 0, 0};
+  if (D.dim == 2) {
+    kick_atom<2>(D, gs[t.sys], A, a, role, false, false, ft, vn, qn);
+    drift_atom<2, T, true>(D, states[t.sys], A, i, false, vn, ft, qn);
+  } else {
+    kick_atom<3>(D, gs[t.sys], A, a, role, false, false, ft, vn, qn);
+    drift_atom<3, T, true>(D, states[t.sys], A, i, false, vn, ft, qn);
   }
 }
 
@@ -802,42 +962,43 @@ __global__ __launch_bounds__(256) void kg_ekin(const SysDesc *__restrict__ descs
 // ---------------------------------------------------------------------------
 size_t grid_scal_bytes() { return sizeof(GridScal); }
 
-hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
-                     const GridPlan &P, bool compute_only, hipStream_t stream, int *launches,
-                     bool force_rebuild) {
+namespace {
+
+// The rebuild of the lists that expired: compaction of the raised flags,
+// then the cell count, scan, scatter and sort and the list build over the
+// listed tiles and systems only (fixed grids).
+int launch_rebuild(const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
+                   hipStream_t stream) {
+  const int nt = P.ntiles, B = P.block;
+  const int nc = nt > P.nsys ? nt : P.nsys;
+  hipLaunchKernelGGL(kg_compact, dim3((nc + 255) / 256), dim3(256), 0, stream, A, P.tiles, nt, P.sys_ids, P.nsys);
+  const int gt = nt < 2048 ? nt : 2048;
+  hipLaunchKernelGGL(kg_cell_count, dim3(gt), dim3(B), 0, stream, descs, A, P.tiles);
+  hipLaunchKernelGGL(kg_cell_scan, dim3(P.nsys < 256 ? P.nsys : 256), dim3(256), 0, stream, descs, A);
+  hipLaunchKernelGGL(kg_cell_scatter, dim3(gt), dim3(B), 0, stream, descs, A, P.tiles);
+  const int sort_blocks = (P.max_ncell + 3) / 4 < 1024 ? (P.max_ncell + 3) / 4 : 1024;
+  hipLaunchKernelGGL(kg_cell_sort, dim3(sort_blocks > 0 ? sort_blocks : 1, P.nsys < 64 ? P.nsys : 64), dim3(256), 0,
+                     stream, descs, A);
+  // enough workgroups per tile for 3D systems (kBuildThreads / 9 atoms each)
+  const int parts = (B + kBuildThreads / 9 - 1) / (kBuildThreads / 9);
+  const int gb = nt * parts < 4096 ? nt * parts : 4096;
+  hipLaunchKernelGGL(kg_build_list, dim3(gb), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles, parts);
+  return 6;
+}
+
+// The pair pass (four or two lanes per atom where the workgroup allows it)
+// and the per-system reduction.
+int launch_pairs_reduce(int prec, const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
+                        bool compute_only, hipStream_t stream) {
   const int nt = P.ntiles, B = P.block, co = compute_only ? 1 : 0;
   GridScal *gs = (GridScal *)P.gscal;
-  int nl = 0;
-  if (!compute_only && P.any_nhc) {
-    hipLaunchKernelGGL(kg_nhc_half, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids);
-    ++nl;
-  }
-  if (compute_only && force_rebuild) {
-    hipLaunchKernelGGL(kg_set_flags, dim3((P.nsys + 255) / 256), dim3(256), 0, stream,
-                       A.rebuild_flag, P.sys_ids, P.nsys, 1);
-    ++nl;
-  }
-  if (prec == 0)
-    hipLaunchKernelGGL(kg_drift<double>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, co);
-  else
-    hipLaunchKernelGGL(kg_drift<float>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, co);
-  hipLaunchKernelGGL(kg_cell_count, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
-  hipLaunchKernelGGL(kg_cell_scan, dim3(P.nsys), dim3(256), 0, stream, descs, A, P.sys_ids);
-  hipLaunchKernelGGL(kg_cell_scatter, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt);
-  const int sort_blocks = (P.max_ncell + 3) / 4 < 1024 ? (P.max_ncell + 3) / 4 : 1024;
-  hipLaunchKernelGGL(kg_cell_sort, dim3(sort_blocks > 0 ? sort_blocks : 1, P.nsys), dim3(256), 0, stream,
-                     descs, A, P.sys_ids, P.nsys);
-  // enough blocks per tile for 3D systems (kBuildThreads / 9 atoms each)
-  const int parts = (B + kBuildThreads / 9 - 1) / (kBuildThreads / 9);
-  hipLaunchKernelGGL(kg_build_list, dim3(nt * parts), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles,
-                     nt);
-  // four or two lanes per atom where the workgroup allows it
   const int lpa = B <= 256 ? 4 : (B <= 512 ? 2 : 1);
 #define HD_PAIRS(TT, L, BB) \
   hipLaunchKernelGGL((kg_pairs<TT, L, BB>), dim3(nt), dim3(L * B), 0, stream, descs, A, P.tiles, nt)
 #define HD_PAIRS_B(TT, L)                                                                        \
   do {                                                                                           \
-    if (P.any_curv) { if (P.any_bonds) HD_PAIRS(TT, L, 3); else HD_PAIRS(TT, L, 2); }            \
+    if (P.any_eig) { if (P.any_bonds) HD_PAIRS(TT, L, 5); else HD_PAIRS(TT, L, 4); }             \
+    else if (P.any_curv) { if (P.any_bonds) HD_PAIRS(TT, L, 3); else HD_PAIRS(TT, L, 2); }       \
     else { if (P.any_bonds) HD_PAIRS(TT, L, 1); else HD_PAIRS(TT, L, 0); }                       \
   } while (0)
   if (prec == 0) {
@@ -849,11 +1010,71 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
 #undef HD_PAIRS
   hipLaunchKernelGGL(kg_reduce, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids, P.sys_tile0,
                      P.tiles, gs, co);
-  hipLaunchKernelGGL(kg_kick, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, co);
-  nl += 9;
-  if (!compute_only && P.any_nhc) {
-    hipLaunchKernelGGL(kg_nhc_half, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids);
+  return 2;
+}
+
+int launch_drift(int prec, const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
+                 bool compute_only, hipStream_t stream) {
+  const int nt = P.ntiles, co = compute_only ? 1 : 0;
+  if (prec == 0)
+    hipLaunchKernelGGL(kg_drift<double>, dim3(nt), dim3(P.block), 0, stream, descs, states, A, P.tiles, nt, co);
+  else
+    hipLaunchKernelGGL(kg_drift<float>, dim3(nt), dim3(P.block), 0, stream, descs, states, A, P.tiles, nt, co);
+  return 1;
+}
+
+int launch_nhc(const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P, hipStream_t stream) {
+  hipLaunchKernelGGL(kg_nhc_half, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids);
+  return 1;
+}
+
+}  // namespace
+
+hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
+                     const GridPlan &P, bool compute_only, hipStream_t stream, int *launches,
+                     bool force_rebuild) {
+  if (!compute_only) return grid_steps(prec, descs, states, A, P, 1, stream, launches);
+  int nl = 0;
+  if (force_rebuild) {
+    hipLaunchKernelGGL(kg_set_flags, dim3((P.nsys + 255) / 256), dim3(256), 0, stream,
+                       A.rebuild_flag, P.sys_ids, P.nsys, 1);
     ++nl;
+  }
+  nl += launch_drift(prec, descs, states, A, P, true, stream);
+  nl += launch_rebuild(descs, states, A, P, stream);
+  nl += launch_pairs_reduce(prec, descs, states, A, P, true, stream);
+  hipLaunchKernelGGL(kg_kick, dim3(P.ntiles), dim3(P.block), 0, stream, descs, A, P.tiles, P.ntiles,
+                     (const GridScal *)P.gscal, 1);
+  ++nl;
+  if (launches) *launches += nl;
+  return hipGetLastError();
+}
+
+hipError_t grid_steps(int prec, const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
+                      int nsteps, hipStream_t stream, int *launches) {
+  const int nt = P.ntiles, B = P.block;
+  const GridScal *gs = (const GridScal *)P.gscal;
+  // Langevin plans fuse each step's closing kick with the next step's drift
+  const bool fuse = !P.any_nhc;
+  int nl = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    if (!fuse || s == 0) {
+      if (P.any_nhc) nl += launch_nhc(descs, states, A, P, stream);
+      nl += launch_drift(prec, descs, states, A, P, false, stream);
+    }
+    nl += launch_rebuild(descs, states, A, P, stream);
+    nl += launch_pairs_reduce(prec, descs, states, A, P, false, stream);
+    if (fuse && s + 1 < nsteps) {
+      if (prec == 0)
+        hipLaunchKernelGGL(kg_kick_drift<double>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, gs);
+      else
+        hipLaunchKernelGGL(kg_kick_drift<float>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, gs);
+      ++nl;
+    } else {
+      hipLaunchKernelGGL(kg_kick, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, 0);
+      ++nl;
+      if (P.any_nhc) nl += launch_nhc(descs, states, A, P, stream);
+    }
   }
   if (launches) *launches += nl;
   return hipGetLastError();

@@ -72,6 +72,7 @@ struct GridPlan {
   int any_bonds;           // some covered system has harmonic tip bonds
   int any_curv;            // some covered system is biased on the curvature
   int any_nhc;             // some covered system has the Nose-Hoover chain
+  int any_eig;             // some covered system is biased on the eigenvalue
 };
 
 size_t grid_scal_bytes();
@@ -84,6 +85,11 @@ size_t grid_scal_bytes();
 hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arrays &A,
                      const GridPlan &P, bool compute_only, hipStream_t stream, int *launches,
                      bool force_rebuild = true);
+// nsteps full steps in one sequence of launches (graph-capturable): plans
+// without the Nose-Hoover chain fuse each step's closing kick with the next
+// step's drift, so only the last step writes the force arrays.
+hipError_t grid_steps(int prec, const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
+                      int nsteps, hipStream_t stream, int *launches);
 // Kinetic energy of the covered systems.
 hipError_t grid_ekin(const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
                      hipStream_t stream);

@@ -47,6 +47,11 @@ struct SysHost {
   // of nhc_len thermostats with relaxation time nhc_tau
   int nhc_len = 0;
   double nhc_tau = 0.5;
+  // eigenvalue variable (hd_set_min_mode): the mode estimate, [dim][n]
+  // (mobile atoms and the rigid body's component on its atoms), and the step
+  // of its rotation
+  std::vector<double> mode;
+  double mode_alpha = 0.0;
   int n_rigid = 0, first_rigid = -1;
   double XR[3] = {0, 0, 0}, XR0[3] = {0, 0, 0};
   bool init_vel = false;
@@ -144,6 +149,7 @@ struct hd_ctx {
   // (rows and entries are cell-sorted positions) rather than by a
   // one-workgroup kernel (atom indices)
   std::vector<uint8_t> sorted_lists;
+  bool any_eig = false;   // some system is biased on the eigenvalue variable
   // hd_bind_device: the context's own storage of each bindable batch field
   // (x, v, ftot, flj, fb, hu), kept while the field lives in caller memory
   double *own_field[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -295,6 +301,8 @@ void fill_desc(const hd_ctx *ctx, const SysHost &s, SysDesc &D) {
     D.nhc_Q1 = D.nhc_NfkT * t2;
     D.nhc_Q = s.th.kT * t2;
   }
+  D.eig = (s.bias_var1 == HD_BIAS_EIGENVALUE || s.bias_var2 == HD_BIAS_EIGENVALUE) ? 1 : 0;
+  D.mode_alpha = s.mode_alpha;
   D.inv_nR = s.n_rigid > 0 ? 1.0 / s.n_rigid : 0.0;
   D.k_nR2 = s.n_rigid > 0 ? s.dr.k_spring / ((double)s.n_rigid * s.n_rigid) : 0.0;
   (void)ctx;
@@ -389,6 +397,7 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
     if (ctx->sys[s].tip_bonds) P.gp.any_bonds = 1;
     if (ctx->h_desc[s].curv) P.gp.any_curv = 1;
     if (ctx->h_desc[s].thermostat == 1) P.gp.any_nhc = 1;
+    if (ctx->h_desc[s].eig) P.gp.any_eig = 1;
   }
   hd_status st = dalloc(ctx, &P.d_tiles, tiles.size(), true);
   if (st != HD_OK) return st;
@@ -420,8 +429,7 @@ hd_status capture_plan(hd_ctx *ctx, Plan &P, int steps, hipGraphExec_t *exec, in
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   int launches = 0;
   hipError_t e = hipSuccess;
-  for (int i = 0; i < steps && e == hipSuccess; ++i)
-    e = hdk::grid_step(ctx->prec == HD_FP64 ? 0 : 1, ctx->d_desc, ctx->d_state, ctx->A, P.gp, false, cs, &launches);
+  e = hdk::grid_steps(ctx->prec == HD_FP64 ? 0 : 1, ctx->d_desc, ctx->d_state, ctx->A, P.gp, steps, cs, &launches);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(cs, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -575,6 +583,7 @@ void clear_schedule(hd_ctx *ctx) {
   ctx->small_ids.clear();
   ctx->big_ids.clear();
   ctx->A.partials = nullptr;
+  ctx->A.rb_tiles = nullptr;
 }
 
 // Assign systems to the LDS-resident groups, the one-workgroup kernel or the
@@ -678,6 +687,7 @@ hd_status build_schedule(hd_ctx *ctx) {
     int max_tiles = 1;
     for (auto &P : ctx->plans) max_tiles = std::max(max_tiles, P.gp.ntiles);
     ALLOC(A.partials, (size_t)max_tiles * hdk::NPART);
+    ALLOC(A.rb_tiles, (size_t)max_tiles);
   }
   if (!ctx->plans.empty()) {
     // grid path: the first step rebuilds every list from the recorded build
@@ -864,8 +874,12 @@ hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t 
   CHECK_CTX();
   if (check_sys(ctx, sys) != HD_OK) return fail(ctx, HD_E_ARG, "bad system");
   SysHost &s = ctx->sys[sys];
-  if (var1 < HD_BIAS_SLOPE || var1 > HD_BIAS_DISTANCE || var2 < -1 || var2 > HD_BIAS_DISTANCE || var2 == var1)
-    return fail(ctx, HD_E_ARG, "bias variables: var1 in {slope, curvature, distance}, var2 another one or -1");
+  if (var1 < HD_BIAS_SLOPE || var1 > HD_BIAS_EIGENVALUE || var2 < -1 || var2 > HD_BIAS_EIGENVALUE || var2 == var1)
+    return fail(ctx, HD_E_ARG,
+                "bias variables: var1 in {slope, curvature, distance, eigenvalue}, var2 another one or -1");
+  if ((var1 == HD_BIAS_CURVATURE && var2 == HD_BIAS_EIGENVALUE) ||
+      (var1 == HD_BIAS_EIGENVALUE && var2 == HD_BIAS_CURVATURE))
+    return fail(ctx, HD_E_ARG, "the curvature and the eigenvalue cannot be combined");
   if (const char *why = bias_problem(s.bias, var1, var2, lo2, hi2)) return fail(ctx, HD_E_ARG, why);
   if (ctx->finalized) return fail(ctx, HD_E_STATE, "hd_set_bias_variables after hd_finalize");
   s.bias_var1 = var1;
@@ -873,6 +887,52 @@ hd_status hd_set_bias_variables(hd_ctx *ctx, int32_t sys, int32_t var1, int32_t 
   s.b2_lo = var2 >= 0 ? lo2 : 0.0;
   s.b2_hi = var2 >= 0 ? hi2 : 1.0;
   return HD_OK;
+}
+
+hd_status hd_set_min_mode(hd_ctx *ctx, int32_t sys, const double *mode, double alpha) {
+  CHECK_CTX();
+  if (check_sys(ctx, sys) != HD_OK || !mode) return fail(ctx, HD_E_ARG, "bad system or null mode");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(ctx, HD_E_ARG, "mode step alpha must be >= 0");
+  SysHost &h = ctx->sys[sys];
+  if (h.bias_var1 != HD_BIAS_EIGENVALUE && h.bias_var2 != HD_BIAS_EIGENVALUE)
+    return fail(ctx, HD_E_STATE, "hd_set_min_mode: the system is not biased on the eigenvalue");
+  const size_t nd = (size_t)h.dim * h.n;
+  h.mode.assign(nd, 0.0);
+  double q2 = 0.0;
+  for (int i = 0; i < h.n; ++i) {
+    const int src = h.role[i] == HD_ROLE_RIGID ? h.first_rigid : i;
+    if (h.role[i] == HD_ROLE_FIXED) continue;
+    for (int k = 0; k < h.dim; ++k) {
+      const double q = mode[(size_t)k * h.n + src];
+      if (!std::isfinite(q)) return fail(ctx, HD_E_ARG, "mode must be finite");
+      h.mode[(size_t)k * h.n + i] = q;
+      if (h.role[i] == HD_ROLE_MOBILE || i == h.first_rigid) q2 += q * q;
+    }
+  }
+  // stored unit over the degrees of freedom
+  if (q2 > 0.0)
+    for (double &q : h.mode) q /= std::sqrt(q2);
+  h.mode_alpha = alpha;
+  if (!ctx->finalized) return HD_OK;
+  // into the running batch: the mobile atoms' components and the rigid body's
+  hd_status st = sync_in(ctx);
+  if (st != HD_OK) return st;
+  const SysDesc &D = ctx->h_desc[sys];
+  std::vector<double> q(h.mode);
+  for (int i = 0; i < h.n; ++i)
+    if (h.role[i] != HD_ROLE_MOBILE)
+      for (int k = 0; k < h.dim; ++k) q[(size_t)k * h.n + i] = 0.0;
+  for (int k = 0; k < h.dim; ++k)
+    HIPCHK(hipMemcpyAsync(ctx->A.qm + k * ctx->ntot + D.off, q.data() + (size_t)k * h.n, sizeof(double) * h.n,
+                          hipMemcpyHostToDevice, ctx->stream));
+  SysState T;
+  HIPCHK(hipMemcpyAsync(&T, ctx->d_state + sys, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < 3; ++k) T.qR[k] = (h.n_rigid > 0 && k < h.dim) ? h.mode[(size_t)k * h.n + h.first_rigid] : 0.0;
+  HIPCHK(hipMemcpyAsync(ctx->d_state + sys, &T, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->need_eval = true;
+  return upload_desc(ctx, sys);
 }
 
 hd_status hd_set_nose_hoover(hd_ctx *ctx, int32_t sys, int32_t chain_len, double tau) {
@@ -985,6 +1045,15 @@ hd_status hd_finalize(hd_ctx *ctx) {
   ALLOC(A.rec, (size_t)N * hdk::kRecDoubles);
   ALLOC(A.brec, (size_t)N * 4);
   ALLOC(A.tuu, 3 * N);
+  {
+    // eigenvalue bias arrays, only when some system uses it
+    bool any_eig = false;
+    for (const auto &h : ctx->sys)
+      any_eig = any_eig || h.bias_var1 == HD_BIAS_EIGENVALUE || h.bias_var2 == HD_BIAS_EIGENVALUE;
+    const size_t ne = any_eig ? (size_t)N : 1;
+    ALLOC(A.qm, 3 * ne); ALLOC(A.hw, 3 * ne); ALLOC(A.recw, 4 * ne);
+    ctx->any_eig = any_eig;
+  }
   ALLOC(A.pos, N);
   if (ctx->prec == HD_FP64) { double *u; ALLOC(u, 3 * N); A.u = u; }
   else { float *u; ALLOC(u, 3 * N); A.u = u; }
@@ -992,6 +1061,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
   ALLOC(A.cell_count, cell_off); ALLOC(A.cell_start, cstart_off); ALLOC(A.cell_atoms, N); ALLOC(A.cidx, N);
   ALLOC(A.sys_of, N);
   ALLOC(A.XR_next, 6 * S); ALLOC(A.rebuild_flag, S);
+  ALLOC(A.rb_sys, S); ALLOC(A.rb_count, 2);
   ALLOC(ctx->d_desc, S); ALLOC(ctx->d_state, S); ALLOC(ctx->d_all, S);
   {
     char *g;
@@ -1033,6 +1103,20 @@ hd_status hd_finalize(hd_ctx *ctx) {
       }
     }
     T.rebuild = 1;
+    if (!h.mode.empty() && h.n_rigid > 0)
+      for (int k = 0; k < h.dim; ++k) T.qR[k] = h.mode[(size_t)k * h.n + h.first_rigid];
+  }
+  if (ctx->any_eig) {
+    std::vector<double> qm(3 * N, 0.0);
+    for (int s = 0; s < S; ++s) {
+      const SysHost &h = ctx->sys[s];
+      if (h.mode.empty()) continue;
+      for (int k = 0; k < h.dim; ++k)
+        for (int i = 0; i < h.n; ++i)
+          if (h.role[i] == HD_ROLE_MOBILE) qm[k * N + ctx->h_desc[s].off + i] = h.mode[(size_t)k * h.n + i];
+    }
+    HIPCHK(hipMemcpyAsync(A.qm, qm.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
   }
   HIPCHK(hipMemcpyAsync(A.x, x.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(A.xb, x.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
@@ -1271,7 +1355,14 @@ hd_status hd_read_forces(hd_ctx *ctx, int32_t sys, int32_t which, double *out) {
   if (!src) return fail(ctx, HD_E_ARG, "unknown force selector");
   hd_status st = copy_field(ctx, sys, src, out, hipMemcpyDeviceToHost);
   if (st != HD_OK) return st;
+  SysState T;
+  HIPCHK(hipMemcpyAsync(&T, ctx->d_state + sys, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (which == HD_TUU && ctx->h_desc[sys].eig) {
+    // the kernels keep T[q,q] of the mode as stored; along the unit mode:
+    const size_t nd = (size_t)ctx->sys[sys].dim * ctx->sys[sys].n;
+    for (size_t q = 0; q < nd; ++q) out[q] *= T.eig_inv_q2;
+  }
   return HD_OK;
 }
 
@@ -1282,6 +1373,33 @@ hd_status hd_read_positions(hd_ctx *ctx, int32_t sys, double *out) {
   hd_status st = copy_field(ctx, sys, ctx->A.x, out, hipMemcpyDeviceToHost);
   if (st != HD_OK) return st;
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HD_OK;
+}
+
+hd_status hd_read_min_mode(hd_ctx *ctx, int32_t sys, double *out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !out) return fail(ctx, HD_E_ARG, "bad system or null output");
+  const SysHost &h = ctx->sys[sys];
+  if (!ctx->h_desc[sys].eig) return fail(ctx, HD_E_STATE, "the system is not biased on the eigenvalue");
+  hd_status st = copy_field(ctx, sys, ctx->A.qm, out, hipMemcpyDeviceToHost);
+  if (st != HD_OK) return st;
+  SysState T;
+  HIPCHK(hipMemcpyAsync(&T, ctx->d_state + sys, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  // normalised over the degrees of freedom: mobile atoms and the rigid body
+  double q2 = 0.0;
+  for (int i = 0; i < h.n; ++i)
+    for (int k = 0; k < h.dim; ++k) {
+      double &q = out[(size_t)k * h.n + i];
+      if (h.role[i] == HD_ROLE_RIGID) q = T.qR[k];
+      else if (h.role[i] == HD_ROLE_FIXED) q = 0.0;
+      else q2 += q * q;
+    }
+  if (h.n_rigid > 0)
+    for (int k = 0; k < h.dim; ++k) q2 += T.qR[k] * T.qR[k];
+  const double inv = q2 > 0.0 ? 1.0 / std::sqrt(q2) : 0.0;
+  for (size_t q = 0; q < (size_t)h.dim * h.n; ++q) out[q] *= inv;
   return HD_OK;
 }
 
@@ -1409,6 +1527,7 @@ hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
   out->dv1 = T.dv1;
   out->dv2 = T.dv2;
   out->e_nhc = T.e_nhc;
+  out->lambda = T.lambda;
   return HD_OK;
 }
 
@@ -1500,7 +1619,8 @@ hd_status hd_set_velocities(hd_ctx *ctx, int32_t sys, const double *vel) {
   return HD_OK;
 }
 
-// Checkpoint layout: header, then x, v, rO, xb, ftot as [dim][n] doubles.
+// Checkpoint layout: header, then x, v, rO, xb, ftot and the mode estimate
+// as [dim][n] doubles.
 // params_fp fingerprints the parameters the stored forces were evaluated
 // with (the potential, the drive and the bias), so that a state restored into
 // a system with other parameters gets its forces re-evaluated.
@@ -1511,7 +1631,7 @@ struct CkptHeader {
   SysState state;
 };
 static const uint32_t kMagic = 0x68644350u;  // "hdCP"
-static const uint32_t kCkptVersion = 2;
+static const uint32_t kCkptVersion = 3;
 
 // FNV-1a over the parameters that shape a system's forces (not the seed,
 // the time step or the thermostat, which only shape the dynamics).
@@ -1537,7 +1657,7 @@ hd_status hd_get_state(hd_ctx *ctx, int32_t sys, void *buf, size_t *bytes) {
   if (check_sys(ctx, sys) != HD_OK || !bytes) return fail(ctx, HD_E_ARG, "bad system or null size");
   const SysHost &s = ctx->sys[sys];
   const size_t nd = (size_t)s.dim * s.n;
-  const size_t need = sizeof(CkptHeader) + 5 * nd * sizeof(double);
+  const size_t need = sizeof(CkptHeader) + 6 * nd * sizeof(double);
   if (!buf) { *bytes = need; return HD_OK; }
   if (*bytes < need) return fail(ctx, HD_E_ARG, "checkpoint buffer too small");
   CkptHeader h{};
@@ -1548,11 +1668,15 @@ hd_status hd_get_state(hd_ctx *ctx, int32_t sys, void *buf, size_t *bytes) {
   h.params_fp = params_fingerprint(s);
   HIPCHK(hipMemcpyAsync(&h.state, ctx->d_state + sys, sizeof(SysState), hipMemcpyDeviceToHost, ctx->stream));
   double *p = (double *)((char *)buf + sizeof(CkptHeader));
-  const double *fields[5] = {ctx->A.x, ctx->A.v, ctx->A.rO, ctx->A.xb, ctx->A.ftot};
-  for (int f = 0; f < 5; ++f) {
+  // the eigenvalue variable's mode estimate (mobile atoms) rides along as a
+  // sixth field, zero for systems without it
+  const double *fields[6] = {ctx->A.x, ctx->A.v, ctx->A.rO, ctx->A.xb, ctx->A.ftot, ctx->A.qm};
+  const int nf = ctx->any_eig ? 6 : 5;
+  for (int f = 0; f < nf; ++f) {
     hd_status st = copy_field(ctx, sys, fields[f], p + f * nd, hipMemcpyDeviceToHost);
     if (st != HD_OK) return st;
   }
+  if (nf == 5) std::memset(p + 5 * nd, 0, nd * sizeof(double));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   std::memcpy(buf, &h, sizeof(h));
   *bytes = need;
@@ -1565,15 +1689,15 @@ hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) 
   if (check_sys(ctx, sys) != HD_OK || !buf) return fail(ctx, HD_E_ARG, "bad system or null buffer");
   const SysHost &s = ctx->sys[sys];
   const size_t nd = (size_t)s.dim * s.n;
-  if (bytes < sizeof(CkptHeader) + 5 * nd * sizeof(double)) return fail(ctx, HD_E_ARG, "checkpoint too short");
+  if (bytes < sizeof(CkptHeader) + 6 * nd * sizeof(double)) return fail(ctx, HD_E_ARG, "checkpoint too short");
   CkptHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (h.magic != kMagic || h.version != kCkptVersion || h.dim != s.dim || h.n != s.n)
     return fail(ctx, HD_E_ARG, "checkpoint does not match this system");
   const double *p = (const double *)((const char *)buf + sizeof(CkptHeader));
-  double *fields[5] = {ctx->A.x, ctx->A.v, ctx->A.rO, ctx->A.xb, ctx->A.ftot};
+  double *fields[6] = {ctx->A.x, ctx->A.v, ctx->A.rO, ctx->A.xb, ctx->A.ftot, ctx->A.qm};
   const SysDesc &D = ctx->h_desc[sys];
-  for (int f = 0; f < 5; ++f)
+  for (int f = 0; f < (ctx->any_eig ? 6 : 5); ++f)
     for (int k = 0; k < s.dim; ++k)
       HIPCHK(hipMemcpyAsync(fields[f] + k * ctx->ntot + D.off, p + f * nd + (size_t)k * s.n, sizeof(double) * s.n,
                             hipMemcpyHostToDevice, ctx->stream));
@@ -2043,10 +2167,12 @@ hd_status hd_min_mode_gradient(hd_ctx *ctx, int32_t sys, const double *mode, dou
   for (int d = 0; d < dim && e == hipSuccess; ++d)
     e = hipMemcpyAsync(ctx->A.rO + d * ctx->ntot + ctx->h_desc[sys].off, rO_tmp.data() + (size_t)d * n,
                        sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream);
-  const int curv_was = plan->gp.any_curv;
+  const int curv_was = plan->gp.any_curv, eig_was = plan->gp.any_eig;
   plan->gp.any_curv = 1;
+  plan->gp.any_eig = 0;
   if (e == hipSuccess) st = evaluate_all(ctx);
   plan->gp.any_curv = curv_was;
+  plan->gp.any_eig = eig_was;
   if (e == hipSuccess && st == HD_OK) st = copy_field(ctx, sys, ctx->A.tuu, t.data(), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   // restore the run state

@@ -17,6 +17,18 @@
 
 namespace hdk {
 
+// Fixed point of the half-list partner sums: units of 2^-32.  A float32
+// term rounds once (to nearest) onto the grid; the sum of a pair list's
+// terms (each below 2^31 in magnitude, far beyond the instability limit
+// on forces) is then exact in 64 bits.
+constexpr double kFixScale = 4294967296.0;   // 2^32
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+  return (unsigned long long)(long long)__builtin_rint((double)v * kFixScale);
+}
+__device__ __forceinline__ double from_fixed(unsigned long long a) {
+  return (double)(long long)a * (1.0 / kFixScale);
+}
+
 struct SmallLayout {
   int nmax, maxnb, cellmax;
   size_t off_x, off_acc, off_ref, off_u, off_nbr, off_cnt, off_cst, off_cat, bytes;
@@ -24,7 +36,9 @@ struct SmallLayout {
 
 // Pair-pass variants ("kind"): 0 float64 with full lists; 1 float32 with half
 // lists (each pair once; the partner's share of F, H u and the energy is
-// accumulated in float64 in LDS, the acc region); 2 float32 with full lists.
+// accumulated in LDS, the acc region, as 64-bit fixed point: integer
+// addition does not depend on the order the atomics land in); 2 float32
+// with full lists.
 __host__ __device__ inline SmallLayout small_layout(int dim, int kind, int nmax, int maxnb, int cellmax) {
   const int tsize = kind == 0 ? 8 : 4;
   SmallLayout L;
@@ -166,7 +180,8 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
   const int n = D.n, stride = L.nmax;
   const int64_t N = A.ntot, off = D.off;
   double *xs = (double *)(lds + L.off_x);
-  double *jacc = (double *)(lds + L.off_acc);   // [2*DIM+1][stride]: F, H u, e of the j side
+  // [2*DIM+1][stride]: F, H u, e of the j side, fixed point (kFixScale units)
+  unsigned long long *jacc = (unsigned long long *)(lds + L.off_acc);
   double *rOs = (double *)(lds + L.off_ref);    // [DIM][stride] r_O
   double *xbs = rOs + DIM * stride;             // [DIM][stride] positions at the last build
   T *us = (T *)(lds + L.off_u);
@@ -254,8 +269,10 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 
   const int64_t iters = compute_only ? 1 : nsteps;
   // the list lives in LDS only for this launch: rebuild at the start, from
-  // the recorded build positions unless an evaluation was requested
-  int rebuild_req = (compute_only || rebuild_state == 1) ? 1 : 2;
+  // the recorded build positions unless an evaluation was requested (an
+  // evaluation right after a restored checkpoint also rebuilds from them, so
+  // that it leaves the restored run's build positions as they are)
+  int rebuild_req = compute_only ? (rebuild_state == 2 ? 2 : 1) : (rebuild_state == 1 ? 1 : 2);
   int vote_parity = 0;
   int nn = 0;
   double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, e_own = 0.0, fbv[3] = {0, 0, 0};
@@ -338,7 +355,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       }
       if constexpr (HALF) {
 #pragma unroll
-        for (int k = 0; k < 2 * DIM + 1; ++k) jacc[k * stride + i] = 0.0;
+        for (int k = 0; k < 2 * DIM + 1; ++k) jacc[k * stride + i] = 0ull;
       }
     }
     const int need = block_any(moved, vote, vote_parity);   // barrier A
@@ -391,9 +408,11 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         constexpr bool WE = decltype(with_energy)::value;
         if constexpr (HALF) {
           // half list: the pair's vectors go to i (compensated, registers) and,
-          // negated, to j (float64 LDS atomics).  The next neighbour's data are
-          // loaded before this pair's atomics are issued, so that LDS latency
-          // overlaps the arithmetic.
+          // negated, to j (fixed-point LDS atomics: each float32 term rounded
+          // once to a multiple of 2^-32, then summed exactly, so the j side's
+          // total does not depend on the order of the atomics).  The next
+          // neighbour's data are loaded before this pair's atomics are issued,
+          // so that LDS latency overlaps the arithmetic.
           int ent = nn > 0 ? nbr[i] : 0;
           double xj[3];
           float uj[3];
@@ -417,10 +436,10 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
             if (live) {
   #pragma unroll
               for (int k = 0; k < DIM; ++k) {
-                atomicAdd(&jacc[k * stride + j], -(double)fv[k]);
-                atomicAdd(&jacc[(DIM + k) * stride + j], -(double)hv[k]);
+                atomicAdd(&jacc[k * stride + j], to_fixed(-fv[k]));
+                atomicAdd(&jacc[(DIM + k) * stride + j], to_fixed(-hv[k]));
               }
-              if constexpr (WE) atomicAdd(&jacc[2 * DIM * stride + j], 0.5 * (double)e);
+              if constexpr (WE) atomicAdd(&jacc[2 * DIM * stride + j], to_fixed(0.5f * e));
             }
           }
         } else {
@@ -463,8 +482,11 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       __syncthreads();   // barrier B: every pair's j-side share has landed
       if (own) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) { F[k] += jacc[k * stride + i]; H[k] += jacc[(DIM + k) * stride + i]; }
-        e_own += jacc[2 * DIM * stride + i];
+        for (int k = 0; k < DIM; ++k) {
+          F[k] += from_fixed(jacc[k * stride + i]);
+          H[k] += from_fixed(jacc[(DIM + k) * stride + i]);
+        }
+        e_own += from_fixed(jacc[2 * DIM * stride + i]);
       }
     }
     // ---- per-system sums (eq. 5, 7 and the rigid layer): DPP within each

@@ -21,7 +21,7 @@ HD_OK, HD_E_ARG, HD_E_OOM, HD_E_HIP, HD_E_STATE, HD_E_UNSTABLE, HD_E_NOGPU = 0, 
 HD_FP64, HD_FP32C = 0, 1
 HD_EXEC_BATCHED, HD_EXEC_GRID, HD_EXEC_SEQUENTIAL = 0, 1, 2
 HD_FORCE_TOTAL, HD_FORCE_LJ, HD_FORCE_BIAS, HD_HU, HD_TUU = 0, 1, 2, 3, 4
-HD_BIAS_SLOPE, HD_BIAS_CURVATURE, HD_BIAS_DISTANCE = 0, 1, 2
+HD_BIAS_SLOPE, HD_BIAS_CURVATURE, HD_BIAS_DISTANCE, HD_BIAS_EIGENVALUE = 0, 1, 2, 3
 HD_FLAG_UNSTABLE, HD_FLAG_NBR_OVERFLOW = 1, 2
 HD_LAUNCH_LDS, HD_LAUNCH_PERSISTENT_LARGE = 1, 2
 HD_QUENCH_CHECK, HD_QUENCH_SET_REFERENCE = 0, 1
@@ -65,10 +65,12 @@ class hd_scalars(_c.Structure):
                 ("x_tip", _c.c_double), ("f_lat", _c.c_double), ("step", _c.c_int64),
                 ("flags", _c.c_int32), ("n_rebuilds", _c.c_int32),
                 ("kappa", _c.c_double), ("dv1", _c.c_double), ("dv2", _c.c_double),
-                ("e_nhc", _c.c_double)]
+                ("e_nhc", _c.c_double), ("lambda_", _c.c_double)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["lambda"] = d.pop("lambda_")
+        return d
 
 
 class hd_schedule(_c.Structure):
@@ -125,6 +127,8 @@ _SIGS = {
     "hd_set_tip_bonds": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double, _c.c_double]),
     "hd_set_bias_variables": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_double, _c.c_double]),
     "hd_set_nose_hoover": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double]),
+    "hd_set_min_mode": (_c.c_int, [_P, _c.c_int32, _dp, _c.c_double]),
+    "hd_read_min_mode": (_c.c_int, [_P, _c.c_int32, _dp]),
     "hd_bind_device": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_void_p]),
     "hd_batch_layout": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64)]),
     "hd_last_error": (_c.c_char_p, [_P]),
@@ -140,6 +144,14 @@ def load() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        # one HIP runtime per process: PyTorch ships its own, and when it is
+        # installed it is loaded first so that libhd.so binds to the same one
+        # (device pointers and streams are then shared; two runtimes in one
+        # process cannot both open the device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -239,6 +251,8 @@ class Context:
             self.set_bias_variables(s, v1, v2, getattr(spec, "b2_lo", 0.0), getattr(spec, "b2_hi", 1.0))
         if spec.bias_on:
             self.set_bias(s, True, spec.m_b, spec.dv_max, spec.g_lo, spec.g_hi)
+        if HD_BIAS_EIGENVALUE in (v1, v2) and getattr(spec, "mode", None) is not None:
+            self.set_min_mode(s, spec.mode, float(getattr(spec, "mode_alpha", 0.0)))
         if int(getattr(spec, "thermostat", 0)) == 1:
             self.set_nose_hoover(s, int(getattr(spec, "nhc_len", 3)), float(getattr(spec, "nhc_tau", 0.5)))
         if getattr(spec, "tip_bonds", 0):
@@ -248,6 +262,19 @@ class Context:
     def set_tip_bonds(self, s: int, enabled: bool, k_bond: float, r_bond: float, r_cut: float):
         _check(self._h, load().hd_set_tip_bonds(self._h, s, int(bool(enabled)), float(k_bond), float(r_bond),
                                                 float(r_cut)), "hd_set_tip_bonds")
+
+    def set_min_mode(self, s: int, mode: np.ndarray, alpha: float):
+        """Mode estimate of the eigenvalue variable ([dim][n], hd_min_mode's
+        layout) and the step of its per-step rotation (hd_set_min_mode)."""
+        a = np.ascontiguousarray(mode, dtype=np.float64)
+        _check(self._h, load().hd_set_min_mode(self._h, int(s), _darr(a), float(alpha)), "hd_set_min_mode")
+
+    def min_mode_estimate(self, s: int) -> np.ndarray:
+        """The current mode estimate, unit over the degrees of freedom
+        (hd_read_min_mode)."""
+        o = self._out(s)
+        _check(self._h, load().hd_read_min_mode(self._h, int(s), _darr(o)), "hd_read_min_mode")
+        return o
 
     def set_nose_hoover(self, s: int, chain_len: int, tau: float = 0.5):
         _check(self._h, load().hd_set_nose_hoover(self._h, s, int(chain_len), float(tau)), "hd_set_nose_hoover")

@@ -42,5 +42,5 @@ def test_struct_sizes_match_header_layout():
     # hd_system_desc: 2 ints, 3 doubles, 3 ints (+pad), 3 pointers, 1 double
     assert ctypes.sizeof(hd.hd_system_desc) == 8 + 24 + 16 + 24 + 8
     assert ctypes.sizeof(hd.hd_lj_params) == 8 * 10
-    # hd_scalars: 11 doubles, step, flags + n_rebuilds, kappa, dv1, dv2, e_nhc
-    assert ctypes.sizeof(hd.hd_scalars) == 8 * 11 + 8 + 8 + 8 * 4
+    # hd_scalars: 11 doubles, step, flags + n_rebuilds, kappa, dv1, dv2, e_nhc, lambda
+    assert ctypes.sizeof(hd.hd_scalars) == 8 * 11 + 8 + 8 + 8 * 5

@@ -134,7 +134,8 @@ def test_at_the_reference(hd, oracle_mod):
 def test_bias_variable_arguments(hd):
     ctx = hd.Context(hd.HD_FP64)
     k = ctx.add_system(build_2d())
-    for bad in ((3, -1), (-1, -1), (0, 0), (1, 3)):
+    # 4 is no variable; the curvature and the eigenvalue (3) are not combined
+    for bad in ((4, -1), (-1, -1), (0, 0), (1, 3), (3, 1), (0, 4)):
         with pytest.raises(hd.HDError):
             ctx.set_bias_variables(k, *bad)
     ctx.set_bias_variables(k, 0, 2, 1.0, 2.0)            # bias off: not checked ...

@@ -32,7 +32,7 @@ def _spec2d(seed, x_slider=0.25):
 
 
 def _spec3d(seed, x_slider=0.4):
-    s = build_3d(8, 8, 4, 4.0)
+    s = build_3d(10, 10, 4, 4.0)
     s.x_slider = x_slider
     s.rO = s.pos.copy()
     s.pos = perturbed(s, 0.05, seed)

@@ -73,9 +73,9 @@ def test_neighbour_pairs_bit_exact(hd, oracle_mod, maker, exec_mode):
 
 def _build_positions(blob, dim, n):
     """Recorded build positions from a checkpoint: header, then x, v, r_O,
-    x_build, F (each dim x n float64)."""
+    x_build, F and the eigenvalue variable's mode (each dim x n float64)."""
     nd = dim * n
-    body = np.frombuffer(blob[len(blob) - 5 * nd * 8:], dtype=np.float64)
+    body = np.frombuffer(blob[len(blob) - 6 * nd * 8:], dtype=np.float64)
     return body[3 * nd:4 * nd].reshape(dim, n).copy()
 
 
