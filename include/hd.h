@@ -430,6 +430,23 @@ hd_status hd_autotune(hd_ctx *ctx, double min_ms, int64_t max_steps, hd_schedule
 hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
                     int32_t mode, int64_t *iters, double *max_disp, double *x_min);
 
+/* hd_quench without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the same minimisation, arguments, results and error
+ * codes as hd_quench, but the FIRE state, the system list and the reduction
+ * partials live in a static device array of 1 MiB that each device holds
+ * for the life of the process, and the read-out arrays (LJ and bias forces,
+ * H u, per-atom energies) are evaluated again at the restored positions
+ * instead of being saved.  It needs 4 count and 64 count bytes, each
+ * rounded up to a multiple of 256, plus 32 count ceil(n_max / 2048) bytes,
+ * n_max the largest listed system; HD_E_ARG (with the sizes in the message)
+ * beyond 1 MiB.  Calls on one device share
+ * the array: calls that overlap on one device (several contexts on several
+ * host threads) race.  Host memory is still used for the checkpoints of
+ * every system. */
+hd_status hd_quench_noalloc(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
+                            int32_t mode, int64_t *iters, double *max_disp, double *x_min);
+
 /* Lowest eigenvalue of the Hessian of the unbiased potential over system
  * sys's degrees of freedom (its mobile atoms' coordinates and the rigid
  * body's), the variable of the eigenvalue bias (§2.2, eq. 15), at the

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,6 +21,18 @@
 
 using hdk::SysDesc;
 using hdk::SysState;
+
+// Static device scratch of hd_quench_noalloc (FIRE state, system list and
+// reduction partials), for callers that cannot allocate device memory.  Each
+// device holds its own copy for the life of the process; in host code the
+// array's name is not a device address, so its per-device address is taken
+// once (hd_create) and only that address is used.  Calls that overlap on one
+// device share it and race.
+constexpr size_t kScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch[kMaxDevices] = {};
+static std::mutex g_scratch_mutex;
 
 namespace {
 
@@ -722,6 +735,19 @@ hd_status hd_create(hd_precision prec, int device, void *hip_stream, hd_ctx **ou
   if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return HD_E_HIP; }
   ctx->user_stream = (hipStream_t)hip_stream;
   if (hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking) != hipSuccess) { delete ctx; return HD_E_HIP; }
+  std::unique_lock<std::mutex> scratch_lock(g_scratch_mutex);
+  if (device < kMaxDevices && !g_scratch[device]) {
+    // the static scratch array's address on this device (current above)
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      hipStreamDestroy(ctx->stream);
+      hipStreamDestroy(ctx->stream2);
+      delete ctx;
+      return HD_E_HIP;
+    }
+    g_scratch[device] = ptr;
+  }
+  scratch_lock.unlock();
   hipEventCreate(&ctx->ev0);
   hipEventCreate(&ctx->ev1);
   hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
@@ -1717,8 +1743,14 @@ hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) 
   return HD_OK;
 }
 
-hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
-                    int32_t mode, int64_t *iters, double *max_disp, double *x_min) {
+// FIRE quench of the listed systems (hd_quench).  With no_alloc, the FIRE
+// state, the system list and the reduction partials are carved out of the
+// device's static scratch array and nothing is allocated on the device; the
+// read-out arrays (LJ and bias forces, H u, per-atom energies, u) are then
+// re-evaluated at the restored positions instead of being saved and copied
+// back.
+static hd_status quench_run(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
+                            int32_t mode, int64_t *iters, double *max_disp, double *x_min, bool no_alloc) {
   CHECK_CTX();
   if (!ctx->finalized) return fail(ctx, HD_E_STATE, "hd_quench before hd_finalize");
   if (!systems || count <= 0 || !iters || !max_disp || !(ftol > 0) || max_iters < 1 ||
@@ -1732,6 +1764,20 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
     if (s < 0 || s >= S || seen[s]) return fail(ctx, HD_E_ARG, "quench systems must be distinct valid indices");
     seen[s] = 1;
     nmax = std::max(nmax, ctx->sys[s].n);
+  }
+  const size_t list_bytes = (sizeof(int32_t) * count + 255) & ~(size_t)255;
+  const size_t fire_bytes = (sizeof(hdk::FireSys) * count + 255) & ~(size_t)255;
+  const size_t part_bytes = sizeof(double) * hdk::fire_partials_doubles(count, nmax);
+  char *scratch = nullptr;
+  if (no_alloc) {
+    if (list_bytes + fire_bytes + part_bytes > kScratchBytes)
+      return fail(ctx, HD_E_ARG, "hd_quench_noalloc: " + std::to_string(count) + " systems of up to " +
+                                     std::to_string(nmax) + " atoms need " +
+                                     std::to_string(list_bytes + fire_bytes + part_bytes) +
+                                     " bytes of scratch, above the " + std::to_string(kScratchBytes) +
+                                     "-byte limit");
+    scratch = (char *)g_scratch[ctx->device];
+    if (!scratch) return fail(ctx, HD_E_STATE, "hd_quench_noalloc: the device's scratch address is not known");
   }
   hd_status st = sync_in(ctx);
   if (st != HD_OK) return st;
@@ -1754,17 +1800,20 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
   const size_t N = (size_t)ctx->ntot;
   const size_t ubytes = 3 * N * (ctx->prec == HD_FP64 ? sizeof(double) : sizeof(float));
   struct Saved { void *dev; void *copy; size_t bytes; };
-  std::vector<Saved> saved = {{ctx->A.flj, nullptr, 3 * N * sizeof(double)},
-                              {ctx->A.hu, nullptr, 3 * N * sizeof(double)},
-                              {ctx->A.fb, nullptr, 3 * N * sizeof(double)},
-                              {ctx->A.eatom, nullptr, N * sizeof(double)},
-                              {ctx->A.u, nullptr, ubytes}};
+  std::vector<Saved> saved;
+  if (!no_alloc)
+    saved = {{ctx->A.flj, nullptr, 3 * N * sizeof(double)},
+             {ctx->A.hu, nullptr, 3 * N * sizeof(double)},
+             {ctx->A.fb, nullptr, 3 * N * sizeof(double)},
+             {ctx->A.eatom, nullptr, N * sizeof(double)},
+             {ctx->A.u, nullptr, ubytes}};
   int32_t *d_list = nullptr;
   hdk::FireSys *d_fire = nullptr;
   double *d_fpart = nullptr;
   auto release = [&]() {
     for (auto &v : saved)
       if (v.copy) (void)hipFree(v.copy);
+    if (no_alloc) return;
     if (d_list) (void)hipFree(d_list);
     if (d_fire) (void)hipFree(d_fire);
     if (d_fpart) (void)hipFree(d_fpart);
@@ -1779,10 +1828,15 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
     if ((e = hipMemcpyAsync(v.copy, v.dev, v.bytes, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess)
       return hip_fail(e);
   }
-  if ((e = hipMalloc(&d_list, sizeof(int32_t) * count)) != hipSuccess) return hip_fail(e);
-  if ((e = hipMalloc(&d_fire, sizeof(hdk::FireSys) * count)) != hipSuccess) return hip_fail(e);
-  if ((e = hipMalloc(&d_fpart, sizeof(double) * hdk::fire_partials_doubles(count, nmax))) != hipSuccess)
-    return hip_fail(e);
+  if (no_alloc) {
+    d_list = (int32_t *)scratch;
+    d_fire = (hdk::FireSys *)(scratch + list_bytes);
+    d_fpart = (double *)(scratch + list_bytes + fire_bytes);
+  } else {
+    if ((e = hipMalloc(&d_list, list_bytes)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMalloc(&d_fire, fire_bytes)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMalloc(&d_fpart, part_bytes)) != hipSuccess) return hip_fail(e);
+  }
   std::vector<hdk::FireSys> fs(count);
   for (int k = 0; k < count; ++k) {
     fs[k] = hdk::FireSys{};
@@ -1862,6 +1916,14 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
   if (e != hipSuccess) return fail(ctx, HD_E_HIP, std::string("hd_quench: ") + hipGetErrorString(e));
   if (st != HD_OK) return st;
   if ((st = restore_all(ctx, ck)) != HD_OK) return st;
+  // without saved copies the read-out arrays are evaluated again at the
+  // restored positions (lists rebuilt from the restored build positions,
+  // which reproduces them bit for bit), and the states restored once more so
+  // that the pending rebuild from the build positions is as hd_quench leaves it
+  if (no_alloc) {
+    if ((st = evaluate_all(ctx, false)) != HD_OK) return st;
+    if ((st = restore_all(ctx, ck)) != HD_OK) return st;
+  }
   // results: iterations, the largest displacement from r_O (check) or from
   // the starting positions (set reference), the minima
   size_t o = 0;
@@ -1887,6 +1949,16 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
     o += nd;
   }
   return sync_out(ctx);
+}
+
+hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
+                    int32_t mode, int64_t *iters, double *max_disp, double *x_min) {
+  return quench_run(ctx, systems, count, ftol, max_iters, mode, iters, max_disp, x_min, false);
+}
+
+hd_status hd_quench_noalloc(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
+                            int32_t mode, int64_t *iters, double *max_disp, double *x_min) {
+  return quench_run(ctx, systems, count, ftol, max_iters, mode, iters, max_disp, x_min, true);
 }
 
 namespace {

@@ -121,6 +121,8 @@ _SIGS = {
                                _c.POINTER(_c.c_int32)]),
     "hd_quench": (_c.c_int, [_P, _c.POINTER(_c.c_int32), _c.c_int32, _c.c_double, _c.c_int64, _c.c_int32,
                              _c.POINTER(_c.c_int64), _dp, _dp]),
+    "hd_quench_noalloc": (_c.c_int, [_P, _c.POINTER(_c.c_int32), _c.c_int32, _c.c_double, _c.c_int64, _c.c_int32,
+                                     _c.POINTER(_c.c_int64), _dp, _dp]),
     "hd_min_mode": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_double, _c.c_uint64, _dp,
                                _c.POINTER(_c.c_int32), _dp]),
     "hd_min_mode_gradient": (_c.c_int, [_P, _c.c_int32, _dp, _dp]),
@@ -351,13 +353,15 @@ class Context:
     def num_systems(self) -> int:
         return int(load().hd_num_systems(self._h))
 
-    def quench(self, systems, ftol: float = 1e-10, max_iters: int = 100000, set_reference: bool = False):
+    def quench(self, systems, ftol: float = 1e-10, max_iters: int = 100000, set_reference: bool = False,
+               no_alloc: bool = False):
         """FIRE minimisation of the listed systems from their current
         positions (hd_quench); the run state is left as it was.  Returns
         (iters, max_disp, minima): per system the iterations used (negative:
         not converged), the largest displacement from r_O (or, with
         set_reference, from the start; the minimum then becomes r_O), and the
-        minimum positions [dim][n]."""
+        minimum positions [dim][n].  no_alloc: hd_quench_noalloc (no device
+        allocation; scratch in the library's static device array)."""
         systems = [int(k) for k in systems]
         n = len(systems)
         ids = (ctypes.c_int32 * n)(*systems)
@@ -367,8 +371,9 @@ class Context:
         tot = sum(self.dims[k] * self.sizes[k] for k in valid)
         xm = np.zeros(tot, dtype=np.float64)
         mode = HD_QUENCH_SET_REFERENCE if set_reference else HD_QUENCH_CHECK
-        _check(self._h, load().hd_quench(self._h, ids, n, float(ftol), int(max_iters), mode, iters, _darr(disp),
-                                         _darr(xm)), "hd_quench")
+        fn = load().hd_quench_noalloc if no_alloc else load().hd_quench
+        _check(self._h, fn(self._h, ids, n, float(ftol), int(max_iters), mode, iters, _darr(disp), _darr(xm)),
+               "hd_quench_noalloc" if no_alloc else "hd_quench")
         minima, o = [], 0
         for k in systems:
             m = self.dims[k] * self.sizes[k]
