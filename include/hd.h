@@ -285,9 +285,12 @@ hd_status hd_finalize(hd_ctx *ctx);
  * (HD_FLAG_UNSTABLE) while the others continue; hd_set_positions or
  * hd_set_state revive it.  The energies read after the call are those of
  * the last step; the LDS-resident kernel evaluates the pair energy on that
- * step only, so a system frozen earlier within a launch reports e_lj and
- * per-atom energies of zero for its last step.  Returns HD_E_UNSTABLE when
- * the last hd_sync found every system frozen. */
+ * step only, so a system frozen earlier within a launch reports a pair
+ * energy and per-atom energies of zero for its last step: its e_pot is the
+ * drive energy alone and stays finite (test the flags, not isfinite(e_pot)).
+ * A system frozen by an evaluation (hd_finalize, hd_compute) keeps that
+ * evaluation's energies and its step count.  Returns HD_E_UNSTABLE when the
+ * last hd_sync found every system frozen. */
 hd_status hd_step(hd_ctx *ctx, int64_t n_steps);
 /* Evaluate forces, energy, H u and the bias at the current positions without
  * stepping or advancing the clock; rebuilds every neighbour list. */

@@ -72,7 +72,10 @@ struct SysDesc {
   // eigenvalue variable (eq. 15; grid kernels only): eig != 0 when one of
   // the bias variables is it; the mode estimate's rotation step after each
   // step is q <- (q - mode_alpha (P^T H q - lambda q)) / |q|
-  int32_t eig, pad3;
+  int32_t eig;
+  // grid plans of LJ-only systems below 32768 atoms keep 16-bit list
+  // entries ((sorted position << 1) | type in an unsigned short)
+  int32_t list16;
   double mode_alpha;
 };
 
@@ -819,7 +822,7 @@ constexpr int kGatherBlock = 4;
 // The neighbour loop of pair_atom_rec: list entries walked by a 32-bit byte
 // offset advancing by a fixed stride, records addressed by 32-bit offsets
 // from the system's base (uniform), so that both loads take a scalar base.
-template <int DIM, typename T, int EXT, bool LASTP>
+template <int DIM, typename T, int EXT, bool LASTP, bool E16 = false>
 __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &R, const char *__restrict__ recb,
                                               const char *__restrict__ nbrb, uint32_t lo, uint32_t lstep,
                                               int cnt, const double xi[3], const T ui[3], PairAcc<T> &acc,
@@ -876,7 +879,8 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
     for (int c = 0; c < cnt; ++c) {
       // the list is read once per step: a streaming load, so that it does not
       // evict the records the neighbouring atoms share
-      const int ent = __builtin_nontemporal_load((const int32_t *)(nbrb + lo));
+      const int ent = E16 ? (int)__builtin_nontemporal_load((const uint16_t *)(nbrb + lo))
+                          : __builtin_nontemporal_load((const int32_t *)(nbrb + lo));
       lo += lstep;
       const double *r = (const double *)(recb + (((uint32_t)ent >> 1) << 6));
       double xj[3], dx[3];
@@ -893,11 +897,12 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
 // hold sorted positions), neighbours read from the packed records; same
 // arithmetic as pair_atom.  Lane q0 of qstep lanes takes entries q0,
 // q0 + qstep, ...
-template <int DIM, typename T, int EXT = 0>
+template <int DIM, typename T, int EXT = 0, bool E16 = false>
 __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
                                               const double xi[3], const T ui[3], int ti,
                                               PairAcc<T> &acc, int q0 = 0, int qstep = 1,
                                               const T *wi = nullptr) {
+  static_assert(!E16 || EXT == 0, "16-bit lists serve the LJ-only pass");
   static_assert(kRecDoubles == 8, "records are 64 bytes");
   const int64_t off = D.off;
   const int n = D.n;
@@ -905,13 +910,16 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
   const char *nbrb = (const char *)(A.nbr + D.nbr_off);
   const int nn = A.nnb[off + p];
   const int cnt = nn > q0 ? (nn - q0 + qstep - 1) / qstep : 0;
-  const uint32_t lo = ((uint32_t)q0 * (uint32_t)n + (uint32_t)p) * 4u;
-  const uint32_t lstep = (uint32_t)qstep * (uint32_t)n * 4u;
+  constexpr uint32_t esz = E16 ? 2u : 4u;   // bytes per list entry
+  const uint32_t lo = ((uint32_t)q0 * (uint32_t)n + (uint32_t)p) * esz;
+  const uint32_t lstep = (uint32_t)qstep * (uint32_t)n * esz;
   const char *recwb = (EXT & EXT_EIG) != 0 ? (const char *)(A.recw + off * 4) : nullptr;
   LJRow<T> R;
   R.load(D, ti);
-  if (D.periodic[DIM - 1]) pair_loop_rec<DIM, T, EXT, true>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
-  else pair_loop_rec<DIM, T, EXT, false>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
+  if (D.periodic[DIM - 1])
+    pair_loop_rec<DIM, T, EXT, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
+  else
+    pair_loop_rec<DIM, T, EXT, false, E16>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
 }
 
 // ---------------------------------------------------------------------------

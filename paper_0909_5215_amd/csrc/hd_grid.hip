@@ -383,7 +383,11 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
             double dx[3];
             const double r2 = pair_disp<DIM>(D, xi, xj[u], dx);
             if (r2 < D.rl2) {
-              if (cnt < D.maxnb) list[(int64_t)cnt * n + p] = (pp << 1) | (trj[u] & 1);
+              if (cnt < D.maxnb) {
+                const int e = (pp << 1) | (trj[u] & 1);
+                if (D.list16) ((uint16_t *)list)[(int64_t)cnt * n + p] = (uint16_t)e;
+                else list[(int64_t)cnt * n + p] = e;
+              }
               ++cnt;
             }
           }
@@ -399,13 +403,14 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
 // parallelism, which a system whose skin expired needs to hide memory
 // latency.  A row with more than kRowCap entries sends its atom to
 // list_atom_g.  Blocks of kBuildThreads threads, enough of them per tile for
-// kBuildThreads / 9 atoms each.
+// kBuildThreads / 9 atoms each.  The sub-lists take 16-bit entries for
+// systems with 16-bit lists: half the LDS, twice the workgroups per CU.
 constexpr int kBuildThreads = 256;
 constexpr int kRowCap = 48;
 
-template <int DIM>
+template <int DIM, typename SubT>
 __device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
-                        const double xi[3], int ri, const int cc[3], int oy, int oz, int32_t *sub) {
+                        const double xi[3], int ri, const int cc[3], int oy, int oz, SubT *sub) {
   const int32_t *cstart = A.cell_start + D.cstart_off;
   const double *__restrict__ brec = A.brec + D.off * 4;
   int lo0 = 0, hi0 = 0;
@@ -444,7 +449,7 @@ __device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
         double dx[3];
         const double r2 = pair_disp<DIM>(D, xi, xj[u], dx);
         if (r2 < D.rl2) {
-          if (cnt < kRowCap) sub[cnt * kBuildThreads] = (pp << 1) | (trj[u] & 1);
+          if (cnt < kRowCap) sub[cnt * kBuildThreads] = (SubT)((pp << 1) | (trj[u] & 1));
           ++cnt;
         }
       }
@@ -453,9 +458,9 @@ __device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
   return cnt;
 }
 
-template <int DIM>
+template <int DIM, typename SubT>
 __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, const Tile &t, int part, int flag,
-                           int32_t *sub_all, int *counts) {
+                           SubT *sub_all, int *counts) {
   constexpr int S = DIM == 3 ? 9 : 3;        // stencil rows per atom
   constexpr int APB = kBuildThreads / S;     // atoms per block
   const int tid = threadIdx.x, la = tid / S, r = tid % S;
@@ -480,7 +485,7 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
     }
     const int oy = DIM == 3 ? r % 3 - 1 : r - 1, oz = DIM == 3 ? r / 3 - 1 : 0;
     const bool in_y = D.nc[1] > 1 || oy == 0, in_z = DIM < 3 || D.nc[2] > 1 || oz == 0;
-    if (in_y && in_z) cnt = scan_row<DIM>(D, A, p, xi, ri, cc, oy, oz, sub_all + tid);
+    if (in_y && in_z) cnt = scan_row<DIM, SubT>(D, A, p, xi, ri, cc, oy, oz, sub_all + tid);
   }
   counts[tid] = cnt;
   __syncthreads();
@@ -496,8 +501,14 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
   int32_t *list = A.nbr + D.nbr_off;
   const int n = D.n;
   if (!over) {
-    for (int k = 0; k < cnt && before + k < D.maxnb; ++k)
-      list[(int64_t)(before + k) * n + p] = sub_all[k * kBuildThreads + tid];
+    if (D.list16) {
+      uint16_t *list16 = (uint16_t *)list;
+      for (int k = 0; k < cnt && before + k < D.maxnb; ++k)
+        list16[(int64_t)(before + k) * n + p] = (uint16_t)sub_all[k * kBuildThreads + tid];
+    } else {
+      for (int k = 0; k < cnt && before + k < D.maxnb; ++k)
+        list[(int64_t)(before + k) * n + p] = (int32_t)sub_all[k * kBuildThreads + tid];
+    }
   }
   if (r != 0) return;
   if (over) total = list_atom_g<DIM>(D, A, p);   // a crowded row: the one-lane build
@@ -527,10 +538,12 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
 // Work item w = part * (flagged tiles) + k: consecutive items are parts of
 // different tiles, and consecutive workgroups go to different XCDs, so the
 // few systems that rebuild in a step spread over the whole chip.
-__global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__restrict__ descs,
+template <bool E16>
+__global__ __launch_bounds__(kBuildThreads) __attribute__((amdgpu_waves_per_eu(5))) void kg_build_list(const SysDesc *__restrict__ descs,
                                                                SysState *__restrict__ states, Arrays A,
                                                                const Tile *__restrict__ tiles, int parts) {
-  __shared__ int32_t sub[kRowCap * kBuildThreads];
+  using SubT = typename std::conditional<E16, uint16_t, int32_t>::type;
+  __shared__ SubT sub[kRowCap * kBuildThreads];
   __shared__ int counts[kBuildThreads];
   const int nt = __hip_atomic_load(&A.rb_count[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int w = blockIdx.x; w < nt * parts; w += gridDim.x) {
@@ -539,9 +552,9 @@ __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__
     const int flag = A.rebuild_flag[t.sys];
     const SysDesc &D = descs[t.sys];
     if (D.dim == 2) {
-      if (part * (kBuildThreads / 3) < t.count) build_rows<2>(D, states[t.sys], A, t, part, flag, sub, counts);
+      if (part * (kBuildThreads / 3) < t.count) build_rows<2, SubT>(D, states[t.sys], A, t, part, flag, sub, counts);
     } else {
-      if (part * (kBuildThreads / 9) < t.count) build_rows<3>(D, states[t.sys], A, t, part, flag, sub, counts);
+      if (part * (kBuildThreads / 9) < t.count) build_rows<3, SubT>(D, states[t.sys], A, t, part, flag, sub, counts);
     }
     __syncthreads();   // sub and counts are reused by the next item
   }
@@ -552,7 +565,7 @@ __global__ __launch_bounds__(kBuildThreads) void kg_build_list(const SysDesc *__
 // s + LPA, ...; the lanes' sums are then combined by quad permutes (a + b on
 // both lanes, the same bits).  More wavefronts per tile hide more gather
 // latency.
-template <int DIM, typename T, int LPA, int EXT>
+template <int DIM, typename T, int LPA, int EXT, bool E16 = false>
 __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int tile_index) {
   constexpr bool CURV = (EXT & EXT_CURV) != 0, EIG = (EXT & EXT_EIG) != 0;
   static_assert(!(CURV && EIG), "the curvature and the eigenvalue bias share the X accumulator");
@@ -586,7 +599,7 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
   }
   PairAcc<T> acc;
   acc.init();
-  if (valid) pair_atom_rec<DIM, T, EXT>(D, A, p, xi, ui, tr & 1, acc, sub, LPA, wi);
+  if (valid) pair_atom_rec<DIM, T, EXT, E16>(D, A, p, xi, ui, tr & 1, acc, sub, LPA, wi);
   double F[3] = {0, 0, 0}, H[3] = {0, 0, 0}, X[3] = {0, 0, 0}, W[3] = {0, 0, 0}, e;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -802,14 +815,14 @@ __global__ __launch_bounds__(256) void kg_reduce(const SysDesc *__restrict__ des
 // with harmonic tip bonds, EXT_CURV for a curvature bias (T[u,u]) -- each
 // combination a separate instantiation, so that LJ-only plans keep their
 // register budget.
-template <typename T, int LPA, int EXT>
+template <typename T, int LPA, int EXT, bool E16 = false>
 __global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ descs, Arrays A,
                                                  const Tile *__restrict__ tiles, int ntiles) {
   const int ti = xcd_tile(blockIdx.x, ntiles);
   const Tile t = tiles[ti];
   const SysDesc &D = descs[t.sys];
-  if (D.dim == 2) pairs_tile<2, T, LPA, EXT>(D, A, t, ti);
-  else pairs_tile<3, T, LPA, EXT>(D, A, t, ti);
+  if (D.dim == 2) pairs_tile<2, T, LPA, EXT, E16>(D, A, t, ti);
+  else pairs_tile<3, T, LPA, EXT, E16>(D, A, t, ti);
 }
 
 // ---- bias force, total force and final B -----------------------------------
@@ -982,7 +995,10 @@ int launch_rebuild(const SysDesc *descs, SysState *states, const Arrays &A, cons
   // enough workgroups per tile for 3D systems (kBuildThreads / 9 atoms each)
   const int parts = (B + kBuildThreads / 9 - 1) / (kBuildThreads / 9);
   const int gb = nt * parts < 4096 ? nt * parts : 4096;
-  hipLaunchKernelGGL(kg_build_list, dim3(gb), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles, parts);
+  if (P.list16)
+    hipLaunchKernelGGL(kg_build_list<true>, dim3(gb), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles, parts);
+  else
+    hipLaunchKernelGGL(kg_build_list<false>, dim3(gb), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles, parts);
   return 6;
 }
 
@@ -995,11 +1011,15 @@ int launch_pairs_reduce(int prec, const SysDesc *descs, SysState *states, const 
   const int lpa = B <= 256 ? 4 : (B <= 512 ? 2 : 1);
 #define HD_PAIRS(TT, L, BB) \
   hipLaunchKernelGGL((kg_pairs<TT, L, BB>), dim3(nt), dim3(L * B), 0, stream, descs, A, P.tiles, nt)
+#define HD_PAIRS16(TT, L) \
+  hipLaunchKernelGGL((kg_pairs<TT, L, 0, true>), dim3(nt), dim3(L * B), 0, stream, descs, A, P.tiles, nt)
 #define HD_PAIRS_B(TT, L)                                                                        \
   do {                                                                                           \
     if (P.any_eig) { if (P.any_bonds) HD_PAIRS(TT, L, 5); else HD_PAIRS(TT, L, 4); }             \
     else if (P.any_curv) { if (P.any_bonds) HD_PAIRS(TT, L, 3); else HD_PAIRS(TT, L, 2); }       \
-    else { if (P.any_bonds) HD_PAIRS(TT, L, 1); else HD_PAIRS(TT, L, 0); }                       \
+    else if (P.any_bonds) HD_PAIRS(TT, L, 1);                                                    \
+    else if (P.list16) HD_PAIRS16(TT, L);                                                        \
+    else HD_PAIRS(TT, L, 0);                                                                     \
   } while (0)
   if (prec == 0) {
     if (lpa == 4) HD_PAIRS_B(double, 4); else if (lpa == 2) HD_PAIRS_B(double, 2); else HD_PAIRS_B(double, 1);
@@ -1007,6 +1027,7 @@ int launch_pairs_reduce(int prec, const SysDesc *descs, SysState *states, const 
     if (lpa == 4) HD_PAIRS_B(float, 4); else if (lpa == 2) HD_PAIRS_B(float, 2); else HD_PAIRS_B(float, 1);
   }
 #undef HD_PAIRS_B
+#undef HD_PAIRS16
 #undef HD_PAIRS
   hipLaunchKernelGGL(kg_reduce, dim3(P.nsys), dim3(256), 0, stream, descs, states, A, P.sys_ids, P.sys_tile0,
                      P.tiles, gs, co);

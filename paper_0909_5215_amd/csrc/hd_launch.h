@@ -73,6 +73,7 @@ struct GridPlan {
   int any_curv;            // some covered system is biased on the curvature
   int any_nhc;             // some covered system has the Nose-Hoover chain
   int any_eig;             // some covered system is biased on the eigenvalue
+  int list16;              // LJ-only systems below 32768 atoms: 16-bit list entries
 };
 
 size_t grid_scal_bytes();

@@ -65,6 +65,10 @@ struct SysHost {
   // of its rotation
   std::vector<double> mode;
   double mode_alpha = 0.0;
+  // schedule: the system is in a grid plan that keeps 16-bit list entries;
+  // lists_wide: its list still holds the 32-bit entries of a curvature
+  // evaluation (hd_min_mode_gradient) until the next step or evaluation
+  int list16 = 0, lists_wide = 0;
   int n_rigid = 0, first_rigid = -1;
   double XR[3] = {0, 0, 0}, XR0[3] = {0, 0, 0};
   bool init_vel = false;
@@ -316,6 +320,7 @@ void fill_desc(const hd_ctx *ctx, const SysHost &s, SysDesc &D) {
   }
   D.eig = (s.bias_var1 == HD_BIAS_EIGENVALUE || s.bias_var2 == HD_BIAS_EIGENVALUE) ? 1 : 0;
   D.mode_alpha = s.mode_alpha;
+  D.list16 = s.list16;
   D.inv_nR = s.n_rigid > 0 ? 1.0 / s.n_rigid : 0.0;
   D.k_nR2 = s.n_rigid > 0 ? s.dr.k_spring / ((double)s.n_rigid * s.n_rigid) : 0.0;
   (void)ctx;
@@ -412,6 +417,11 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
     if (ctx->h_desc[s].thermostat == 1) P.gp.any_nhc = 1;
     if (ctx->h_desc[s].eig) P.gp.any_eig = 1;
   }
+  // LJ-only plans whose systems' sorted positions fit 15 bits keep 16-bit
+  // list entries (half the list traffic of the pair pass)
+  P.gp.list16 = (!P.gp.any_bonds && !P.gp.any_curv && !P.gp.any_eig) ? 1 : 0;
+  for (int s : systems)
+    if (ctx->sys[s].n > 32767) P.gp.list16 = 0;
   hd_status st = dalloc(ctx, &P.d_tiles, tiles.size(), true);
   if (st != HD_OK) return st;
   st = dalloc(ctx, &P.d_sys, systems.size(), true);
@@ -490,7 +500,7 @@ hd_status evaluate_all(hd_ctx *ctx, bool force_rebuild = true) {
   if (st != HD_OK) return st;
   for (auto &P : ctx->plans) {
     int l = 0;
-    for (int s : P.ids) ctx->sorted_lists[s] = 1;
+    for (int s : P.ids) { ctx->sorted_lists[s] = 1; ctx->sys[s].lists_wide = 0; }
     HIPCHK(hdk::grid_step(prec, ctx->d_desc, ctx->d_state, ctx->A, P.gp, true, ctx->stream, &l, force_rebuild));
     HIPCHK(hdk::grid_ekin(ctx->d_desc, ctx->d_state, ctx->A, P.gp, ctx->stream));
   }
@@ -528,7 +538,10 @@ hd_status prepare_plans(hd_ctx *ctx, int64_t n_steps) {
 // energy.
 hd_status run_plans(hd_ctx *ctx, int64_t n_steps, hipStream_t stream, int64_t *launches) {
   for (auto &P : ctx->plans) {
-    for (int s : P.ids) ctx->sorted_lists[s] = 1;
+    for (int s : P.ids) {
+      ctx->sorted_lists[s] = 1;
+      if (n_steps > 0) ctx->sys[s].lists_wide = 0;   // the first step rebuilds a restored list
+    }
     for (int64_t g = 0; g < n_steps / kGraphSteps; ++g) {
       HIPCHK(hipGraphLaunch(P.exec, stream));
       *launches += P.launches_per_graph;
@@ -696,6 +709,13 @@ hd_status build_schedule(hd_ctx *ctx) {
     for (int s = 0; s < S; ++s)
       if ((st = build_plan(ctx, std::vector<int>{s}, ctx->plans[s])) != HD_OK) return st;
   }
+  // list format of each system: 16-bit entries in list16 plans
+  for (int s = 0; s < S; ++s) ctx->sys[s].list16 = 0;
+  for (auto &P : ctx->plans)
+    if (P.gp.list16)
+      for (int s : P.ids) ctx->sys[s].list16 = 1;
+  for (int s = 0; s < S; ++s)
+    if ((st = upload_desc(ctx, s)) != HD_OK) return st;
   {
     int max_tiles = 1;
     for (auto &P : ctx->plans) max_tiles = std::max(max_tiles, P.gp.ntiles);
@@ -1528,13 +1548,7 @@ hd_status hd_bind_device(hd_ctx *ctx, int32_t sys, int32_t field, void *dev_ptr)
   return HD_OK;
 }
 
-hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
-  CHECK_CTX();
-  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
-  if (check_sys(ctx, sys) != HD_OK || !out) return fail(ctx, HD_E_ARG, "bad system or null output");
-  SysState T;
-  HIPCHK(hipMemcpyAsync(&T, ctx->d_state + sys, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+static void scalars_of(const SysState &T, hd_scalars *out) {
   out->e_pot = T.e_pot;
   out->e_kin = T.e_kin;
   out->dv = T.dv;
@@ -1554,6 +1568,16 @@ hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
   out->dv2 = T.dv2;
   out->e_nhc = T.e_nhc;
   out->lambda = T.lambda;
+}
+
+hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  if (check_sys(ctx, sys) != HD_OK || !out) return fail(ctx, HD_E_ARG, "bad system or null output");
+  SysState T;
+  HIPCHK(hipMemcpyAsync(&T, ctx->d_state + sys, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  scalars_of(T, out);
   return HD_OK;
 }
 
@@ -2239,12 +2263,26 @@ hd_status hd_min_mode_gradient(hd_ctx *ctx, int32_t sys, const double *mode, dou
   for (int d = 0; d < dim && e == hipSuccess; ++d)
     e = hipMemcpyAsync(ctx->A.rO + d * ctx->ntot + ctx->h_desc[sys].off, rO_tmp.data() + (size_t)d * n,
                        sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream);
-  const int curv_was = plan->gp.any_curv, eig_was = plan->gp.any_eig;
+  // the curvature kernels read 32-bit lists: the plan's systems build those
+  // for this evaluation (every list is rebuilt by it), and 16-bit ones again
+  // from the restored build positions at the next step
+  const int curv_was = plan->gp.any_curv, eig_was = plan->gp.any_eig, l16_was = plan->gp.list16;
   plan->gp.any_curv = 1;
   plan->gp.any_eig = 0;
-  if (e == hipSuccess) st = evaluate_all(ctx);
+  plan->gp.list16 = 0;
+  for (int q : plan->ids)
+    if (l16_was && st == HD_OK) { ctx->sys[q].list16 = 0; st = upload_desc(ctx, q); }
+  if (e == hipSuccess && st == HD_OK) st = evaluate_all(ctx);
   plan->gp.any_curv = curv_was;
   plan->gp.any_eig = eig_was;
+  plan->gp.list16 = l16_was;
+  for (int q : plan->ids)
+    if (l16_was) {
+      ctx->sys[q].list16 = 1;
+      ctx->sys[q].lists_wide = 1;
+      const hd_status su = upload_desc(ctx, q);
+      if (st == HD_OK) st = su;
+    }
   if (e == hipSuccess && st == HD_OK) st = copy_field(ctx, sys, ctx->A.tuu, t.data(), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   // restore the run state
@@ -2276,7 +2314,17 @@ hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int
   const SysDesc &D = ctx->h_desc[sys];
   std::vector<int32_t> nnb(s.n), list((size_t)D.maxnb * s.n), cat(s.n);
   HIPCHK(hipMemcpyAsync(nnb.data(), ctx->A.nnb + D.off, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(list.data(), ctx->A.nbr + D.nbr_off, sizeof(int32_t) * list.size(), hipMemcpyDeviceToHost, ctx->stream));
+  if (D.list16 && ctx->sorted_lists[sys] && !s.lists_wide) {
+    // 16-bit entries (grid plans of small LJ-only systems)
+    std::vector<uint16_t> l16(list.size());
+    HIPCHK(hipMemcpyAsync(l16.data(), ctx->A.nbr + D.nbr_off, sizeof(uint16_t) * l16.size(), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (size_t q = 0; q < list.size(); ++q) list[q] = l16[q];
+  } else {
+    HIPCHK(hipMemcpyAsync(list.data(), ctx->A.nbr + D.nbr_off, sizeof(int32_t) * list.size(), hipMemcpyDeviceToHost,
+                          ctx->stream));
+  }
   HIPCHK(hipMemcpyAsync(cat.data(), ctx->A.cell_atoms + D.off, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   // grid lists are indexed by cell-sorted position (cat maps it to the atom)

@@ -123,18 +123,35 @@ def test_argument_errors(hd):
         c2.add_system(bad)
 
 
-def test_unstable_system_is_frozen_others_continue(hd):
+def test_unstable_system_is_frozen_others_continue(hd, oracle_mod):
+    """Two atoms 0.05 apart are frozen by the set-up evaluation; two atoms
+    0.6 apart blow up within the first launch (the oracle's force passes
+    1e6 at its third step).  The healthy system runs on."""
     good = build_2d()
-    bad = build_2d()
+    early, late = build_2d(), build_2d()
     i, j = 150, 151                                  # two mobile substrate atoms
-    bad.pos[0, j] = bad.pos[0, i] + 0.05              # nearly on top of each other
-    bad.pos[1, j] = bad.pos[1, i]
-    ctx = hd.make_context([good, bad], precision=hd.HD_FP64)
+    for s, gap in ((early, 0.05), (late, 0.6)):
+        s.pos[0, j] = s.pos[0, i] + gap
+        s.pos[1, j] = s.pos[1, i]
+    ctx = hd.make_context([good, early, late], precision=hd.HD_FP64)
+    e0 = ctx.scalars(1)["e_pot"]
+    assert e0 == pytest.approx(oracle_mod.OracleSystem(early).compute()["e_pot"], rel=1e-12)
     ctx.step(50)
     assert ctx.scalars(0)["flags"] == 0
     assert ctx.scalars(0)["step"] == 50
-    assert ctx.scalars(1)["flags"] & hd.HD_FLAG_UNSTABLE
-    assert ctx.scalars(1)["step"] < 50
+    for k in (1, 2):
+        assert ctx.scalars(k)["flags"] & hd.HD_FLAG_UNSTABLE
+    # frozen before its first step: the readout keeps the evaluation's
+    # (finite, huge) energy
+    assert ctx.scalars(1)["step"] == 0
+    assert ctx.scalars(1)["e_pot"] == e0
+    # frozen within a launch of the LDS-resident kernel, which evaluates the
+    # pair energy on a launch's last step only: the frozen system reports a
+    # pair energy of zero, so e_pot is the (finite, small) drive energy alone
+    # rather than the blown-up pair energy
+    sc = ctx.scalars(2)
+    assert 0 < sc["step"] < 50
+    assert np.isfinite(sc["e_pot"]) and abs(sc["e_pot"]) < 10.0
 
 
 def test_crowded_stencil_rows_fall_back_to_one_lane_build(hd, oracle_mod):

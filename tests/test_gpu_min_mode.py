@@ -104,7 +104,7 @@ def test_eigenvalue_gradient(hd, oracle_mod, maker):
     assert np.all(ctx.min_mode_gradient(0, mode)[:, spec.role == 1] == 0.0)   # fixed atoms
 
 
-def test_eigenvalue_gradient_leaves_the_run_untouched(hd):
+def test_eigenvalue_gradient_leaves_the_run_untouched(hd, oracle_mod):
     specs = [small2d(), small3d()]
     for s in specs:
         s.pos = perturbed(s, 0.05, 27)
@@ -115,6 +115,13 @@ def test_eigenvalue_gradient_leaves_the_run_untouched(hd):
         if probe:
             _, _, mode = ctx.min_mode(1, max_iter=40, tol=1e-8)
             ctx.min_mode_gradient(1, mode)
+            # the gradient's evaluation rebuilds the lists at the current
+            # positions (32-bit entries, on the curvature kernels): read
+            # back before the next step, they hold the brute-force pair set
+            got = set(map(tuple, ctx.debug_pairs(1).tolist()))
+            s1 = specs[1]
+            want = oracle_mod.pairs_brute(s1, ctx.positions(1), s1.rc + s1.skin, exclude=True)
+            assert got == set(map(tuple, want.tolist()))
         ctx.step(30)
         runs.append([(ctx.positions(k), ctx.velocities(k), ctx.scalars(k)["t_hyper"]) for k in range(2)])
     for a, b in zip(*runs):

@@ -228,6 +228,32 @@ def test_mixed_uneven_batch(hd, oracle_mod):
         assert abs(ctx.scalars(k)["dv"] - ref["dv"]) <= 1e-6 * s.dv_max
 
 
+@pytest.mark.parametrize("precision,half", [(0, 0), (1, 0), (1, 1)])
+def test_lds_energy_after_a_multistep_launch(hd, oracle_mod, precision, half):
+    """The LDS-resident kernel evaluates the pair energy on a launch's last
+    step only: after a 30-step launch the energy, dV and slope match the
+    oracle's same trajectory (float64 1e-10; float32 1e-6 relative, full and
+    half lists)."""
+    spec = biased(oracle_mod, snapshot_2d(seed=61))
+    o = oracle_mod.OracleSystem(spec)
+    o.init_velocities()
+    o.step(30)
+    ctx = hd.make_context([spec], precision=precision)
+    shape = ctx.schedule()
+    assert shape["lds_resident"] == 1
+    if precision == 1:
+        shape["small_half_lists"] = half
+        ctx.set_schedule(shape)
+    ctx.step(30)
+    sc, so = ctx.scalars(0), o.scalars()
+    tol = 1e-10 if precision == 0 else 1e-6
+    assert sc["step"] == 30
+    assert sc["e_pot"] == pytest.approx(so["e_pot"], rel=tol)
+    assert abs(sc["dv"] - so["dv"]) <= tol * spec.dv_max
+    assert sc["g"] == pytest.approx(so["g"], rel=10 * tol, abs=tol)
+    ctx.close()
+
+
 @pytest.mark.parametrize("lds", [True, False])
 def test_fp64_determinism_and_checkpoint(hd, oracle_mod, lds):
     """Chunked runs equal one long run bit for bit, and a checkpoint restored
