@@ -304,6 +304,10 @@ hd_status hd_read_forces(hd_ctx *ctx, int32_t sys, int32_t which, double *out);
 hd_status hd_read_positions(hd_ctx *ctx, int32_t sys, double *out);
 hd_status hd_read_velocities(hd_ctx *ctx, int32_t sys, double *out);
 hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out);
+/* The scalars of systems first .. first + count - 1 in one device-to-host
+ * copy (out holds count entries; count 0 reads nothing).  HD_E_ARG for a
+ * range outside the context's systems. */
+hd_status hd_read_scalars_batch(hd_ctx *ctx, int32_t first, int32_t count, hd_scalars *out);
 /* Device-to-device copy of a system's positions / forces into a caller
  * buffer of dim*n_atoms doubles (stream-ordered, not synchronising). */
 hd_status hd_copy_positions_device(hd_ctx *ctx, int32_t sys, double *dev_out);
@@ -414,8 +418,11 @@ hd_status hd_autotune(hd_ctx *ctx, double min_ms, int64_t max_steps, hd_schedule
  * potential (LJ plus the drive at each system's slider position), from each
  * listed system's current positions, starting at rest.  Mobile atoms and the
  * rigid body move (semi-implicit Euler, first step dt); fixed atoms stay.
- * Converged when the largest force on a degree of freedom is below ftol.
- * Every system's run state (positions, velocities, forces, clock, lists) is
+ * Converged when the largest force on a degree of freedom is below ftol
+ * (iters 0: already at the start).  LDS-resident systems run the whole
+ * quench in one launch of the LDS kernel (iterations and evaluations in
+ * LDS); the others iterate grid kernels, evaluations and the FIRE step, the
+ * convergence read back every 32 iterations.  Every system's run state (positions, velocities, forces, clock, lists) is
  * restored afterwards, so stepping continues exactly as without the call.
  *   systems[0..count): distinct system indices (after hd_finalize);
  *   mode HD_QUENCH_CHECK: max_disp[k] = the largest atom displacement

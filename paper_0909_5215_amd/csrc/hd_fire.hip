@@ -19,9 +19,6 @@ namespace hdk {
 
 namespace {
 
-// FIRE constants (the values of Bitzek et al.)
-constexpr double kAlpha0 = 0.1, kFinc = 1.1, kFdec = 0.5, kFalpha = 0.99;
-constexpr int kNmin = 5;
 constexpr int kFireThreads = 256;
 
 // First level of the reductions, spread over the chip: blockIdx.y is the
@@ -123,14 +120,14 @@ __global__ __launch_bounds__(kFireThreads) void k_fire_control(const SysDesc *__
     f.mixf = fn > 0.0 ? f.alpha * vn / fn : 0.0;
     f.reset = 0;
     for (int k = 0; k < D.dim; ++k) VR[k] = f.mixv * VR[k] + f.mixf * st.FR[k];
-    if (f.since_neg > kNmin) {
-      f.dt = fmin(f.dt * kFinc, 10.0 * D.dt);
-      f.alpha *= kFalpha;
+    if (f.since_neg > kFireNmin) {
+      f.dt = fmin(f.dt * kFireFinc, 10.0 * D.dt);
+      f.alpha *= kFireFalpha;
     }
     f.since_neg += 1;
   } else {
-    f.dt *= kFdec;
-    f.alpha = kAlpha0;
+    f.dt *= kFireFdec;
+    f.alpha = kFireAlpha0;
     f.since_neg = 0;
     f.reset = 1;
     for (int k = 0; k < 3; ++k) VR[k] = 0.0;

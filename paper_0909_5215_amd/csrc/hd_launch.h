@@ -6,6 +6,8 @@
 
 namespace hdk {
 
+struct FireSys;   // a listed system's FIRE state (below)
+
 // One workgroup of `block` threads (256, 512 or 1024) per listed system, all
 // of dimension `dim`; nsteps BAOAB steps (mode 1: evaluate only, 1024
 // threads).  prec 0 = float64, 1 = float32 compensated.
@@ -23,6 +25,15 @@ hipError_t launch_batched(int prec, int dim, const SysDesc *descs, SysState *sta
 hipError_t launch_small(int kind, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
                         const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax,
                         int block, int64_t nsteps, int mode, hipStream_t stream);
+// The FIRE quench of the listed LDS-resident systems in one launch (fire[b]
+// is sys_list[b]'s minimiser state, set up as for fire_iteration): up to
+// max_iters iterations, each testing convergence (no degree of freedom with
+// |F| >= ftol) at the current forces, then mixing and stepping, then an
+// evaluation in LDS.  Starts from the forces and rigid-body force of an
+// unbiased evaluation at the current positions.
+hipError_t launch_small_fire(int kind, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
+                             const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax, int64_t max_iters,
+                             FireSys *fire, double ftol, hipStream_t stream);
 size_t small_lds_bytes(int dim, int kind, int nmax, int maxnb, int cellmax);
 // Dynamic LDS bytes of one LDS-resident group, and the one-time permission to
 // use that much (call outside graph capture, before the first launch).
@@ -47,6 +58,9 @@ struct FireSys {
 // semi-implicit Euler step.  Forces must be re-evaluated before the next one.
 // partials: device scratch of fire_partials_doubles(count, nmax) doubles.
 constexpr int kFireChunk = 2048;   // atoms per first-level reduction block
+// FIRE constants (the values of Bitzek et al.)
+constexpr double kFireAlpha0 = 0.1, kFireFinc = 1.1, kFireFdec = 0.5, kFireFalpha = 0.99;
+constexpr int kFireNmin = 5;
 inline size_t fire_partials_doubles(int count, int nmax) {
   return (size_t)count * (size_t)((nmax + kFireChunk - 1) / kFireChunk) * 4;
 }

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -1581,6 +1582,22 @@ hd_status hd_read_scalars(hd_ctx *ctx, int32_t sys, hd_scalars *out) {
   return HD_OK;
 }
 
+// The states of consecutive systems lie side by side: one copy for all.
+hd_status hd_read_scalars_batch(hd_ctx *ctx, int32_t first, int32_t count, hd_scalars *out) {
+  CHECK_CTX();
+  if (!ctx->finalized) return fail(ctx, HD_E_STATE, "not finalized");
+  const int32_t S = (int32_t)ctx->sys.size();
+  if (first < 0 || count < 0 || first > S - count || (count > 0 && !out))
+    return fail(ctx, HD_E_ARG, "hd_read_scalars_batch needs 0 <= first, first + count <= systems and an output");
+  if (count == 0) return HD_OK;
+  std::vector<SysState> T(count);
+  HIPCHK(hipMemcpyAsync(T.data(), ctx->d_state + first, sizeof(SysState) * count, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int32_t k = 0; k < count; ++k) scalars_of(T[k], out + k);
+  return HD_OK;
+}
+
 // Replace positions of one system: the rigid body follows its first atom.
 hd_status hd_set_positions(hd_ctx *ctx, int32_t sys, const double *pos) {
   CHECK_CTX();
@@ -1861,13 +1878,39 @@ static hd_status quench_run(hd_ctx *ctx, const int32_t *systems, int32_t count, 
     if ((e = hipMalloc(&d_fire, fire_bytes)) != hipSuccess) return hip_fail(e);
     if ((e = hipMalloc(&d_fpart, part_bytes)) != hipSuccess) return hip_fail(e);
   }
+  // LDS-resident systems first, group by group: each group's listed systems
+  // take the whole quench in one launch of the LDS kernel's FIRE mode; the
+  // others (grid plans, the one-workgroup global kernel) follow, iterated
+  // from here.  ord is the order of d_list and of the FIRE states.
+  using Group = std::remove_reference<decltype(ctx->groups[0])>::type;
+  struct LdsRun { const Group *G; int first, n; };
+  std::vector<int> at(S, -1);
+  for (int k = 0; k < count; ++k) at[systems[k]] = k;
+  std::vector<char> in_lds(S, 0);
+  std::vector<int32_t> ord;
+  std::vector<LdsRun> lds_runs;
+  for (const auto &G : ctx->groups) {
+    if (!G.small) continue;
+    const int f = (int)ord.size();
+    for (int s : G.ids)
+      if (at[s] >= 0) { ord.push_back(s); in_lds[s] = 1; }
+    if ((int)ord.size() > f) lds_runs.push_back({&G, f, (int)ord.size() - f});
+  }
+  const int n_lds = (int)ord.size();
+  int nmax_rest = 0;
+  for (int k = 0; k < count; ++k)
+    if (!in_lds[systems[k]]) {
+      ord.push_back(systems[k]);
+      nmax_rest = std::max(nmax_rest, ctx->sys[systems[k]].n);
+    }
+  const int n_rest = count - n_lds;
   std::vector<hdk::FireSys> fs(count);
   for (int k = 0; k < count; ++k) {
     fs[k] = hdk::FireSys{};
-    fs[k].dt = ctx->sys[systems[k]].th.dt;
-    fs[k].alpha = 0.1;
+    fs[k].dt = ctx->sys[ord[k]].th.dt;
+    fs[k].alpha = hdk::kFireAlpha0;
   }
-  if ((e = hipMemcpyAsync(d_list, systems, sizeof(int32_t) * count, hipMemcpyHostToDevice, ctx->stream)) !=
+  if ((e = hipMemcpyAsync(d_list, ord.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, ctx->stream)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(d_fire, fs.data(), sizeof(hdk::FireSys) * count, hipMemcpyHostToDevice, ctx->stream)) !=
           hipSuccess)
@@ -1897,19 +1940,25 @@ static hd_status quench_run(hd_ctx *ctx, const int32_t *systems, int32_t count, 
   // iterations: forces, then the FIRE step; convergence read back every 32.
   // Grid lists are rebuilt only when atoms leave half the skin.
   st = evaluate_all(ctx, false);
+  for (const auto &R : lds_runs) {
+    if (st != HD_OK || e != hipSuccess) break;
+    for (int q = 0; q < R.n; ++q) ctx->sorted_lists[ord[R.first + q]] = 0;
+    e = hdk::launch_small_fire(small_kind(ctx), R.G->dim, ctx->d_desc, ctx->d_state, ctx->A, d_list + R.first, R.n,
+                               R.G->nmax, R.G->maxnb, R.G->cellmax, max_iters, d_fire + R.first, ftol, ctx->stream);
+  }
   int64_t it = 0;
-  for (; st == HD_OK && it < max_iters; ++it) {
-    if ((e = hdk::fire_iteration(ctx->d_desc, ctx->d_state, ctx->A, d_list, count, nmax, d_fire, ftol, it,
-                                 d_fpart, ctx->stream)) != hipSuccess)
+  for (; n_rest > 0 && st == HD_OK && e == hipSuccess && it < max_iters; ++it) {
+    if ((e = hdk::fire_iteration(ctx->d_desc, ctx->d_state, ctx->A, d_list + n_lds, n_rest, nmax_rest,
+                                 d_fire + n_lds, ftol, it, d_fpart, ctx->stream)) != hipSuccess)
       break;
     if ((st = evaluate_all(ctx, false)) != HD_OK) break;
     if ((it & 31) == 31) {
-      if ((e = hipMemcpyAsync(fs.data(), d_fire, sizeof(hdk::FireSys) * count, hipMemcpyDeviceToHost,
-                              ctx->stream)) != hipSuccess ||
+      if ((e = hipMemcpyAsync(fs.data() + n_lds, d_fire + n_lds, sizeof(hdk::FireSys) * n_rest,
+                              hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
           (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
         break;
       bool all = true;
-      for (const auto &f : fs) all = all && f.done;
+      for (int k = n_lds; k < count; ++k) all = all && fs[k].done;
       if (all) break;
     }
   }
@@ -1950,6 +1999,8 @@ static hd_status quench_run(hd_ctx *ctx, const int32_t *systems, int32_t count, 
   }
   // results: iterations, the largest displacement from r_O (check) or from
   // the starting positions (set reference), the minima
+  std::vector<int> pos(count);   // listed system k's FIRE state is fs[pos[k]]
+  for (int q = 0; q < count; ++q) pos[at[ord[q]]] = q;
   size_t o = 0;
   for (int k = 0; k < count; ++k) {
     const int s = systems[k];
@@ -1966,7 +2017,8 @@ static hd_status quench_run(hd_ctx *ctx, const int32_t *systems, int32_t count, 
       }
       worst = std::max(worst, std::sqrt(d2));
     }
-    iters[k] = fs[k].done ? fs[k].iters : -max_iters;
+    const hdk::FireSys &f = fs[pos[k]];
+    iters[k] = f.done ? f.iters : -max_iters;
     max_disp[k] = worst;
     if (x_min) std::memcpy(x_min + o, xm.data() + o, sizeof(double) * nd);
     if (mode == HD_QUENCH_SET_REFERENCE && (st = hd_set_reference(ctx, s, xm.data() + o)) != HD_OK) return st;

@@ -171,9 +171,10 @@ struct Bcast {
   int bias_live, bad;
 };
 
-template <int DIM, typename T, bool HALF, int BLOCK, bool NHC>
+template <int DIM, typename T, bool HALF, int BLOCK, bool NHC, bool FIRE = false>
 __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Arrays &A,
-                          int64_t nsteps, int mode, char *lds, const SmallLayout L) {
+                          int64_t nsteps, int mode, char *lds, const SmallLayout L,
+                          FireSys *__restrict__ fire = nullptr, double ftol2 = 0.0) {
   constexpr int NW = BLOCK / 64;       // wavefronts per workgroup
   static_assert(!HALF || sizeof(T) == 4, "half lists are a float32 variant");
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -259,13 +260,30 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 #pragma unroll
     for (int k = 0; k < DIM; ++k) { v[k] *= c; VR[k] *= c; }
   }
-  if (!compute_only && !nhc && rigid_body && tid == 0) {
+  if (!FIRE && !compute_only && !nhc && rigid_body && tid == 0) {
     double z[3];
     noise<DIM, T>(D.seed, step, (uint32_t)n, z);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) sh_zR[step & 1][k] = z[k];
   }
   __syncthreads();   // the first step's rigid-body noise and the atom table are in LDS
+  // FIRE (quench mode): the minimiser's state, kept by every thread
+  // (identical arithmetic everywhere, like the rigid body)
+  double f_dt = 0.0, f_alpha = 0.0;
+  int f_since = 0, f_done = 0;
+  int64_t f_iters = 0;
+  if constexpr (FIRE) {
+    f_dt = fire->dt;
+    f_alpha = fire->alpha;
+    f_since = fire->since_neg;
+    // the read-out scalars of the evaluation before the launch, kept when
+    // the starting point has already converged
+    if (tid == 0) {
+      sh_out.e_lj = stg->e_lj; sh_out.v_drive = stg->v_drive; sh_out.e_pot = stg->e_pot;
+      sh_out.d = stg->d; sh_out.g = stg->g; sh_out.dv = stg->dv; sh_out.dvp = stg->dvp;
+      sh_out.xs = stg->x_slider; sh_out.x_tip = stg->x_tip; sh_out.f_lat = stg->f_lat;
+    }
+  }
 
   const int64_t iters = compute_only ? 1 : nsteps;
   // the list lives in LDS only for this launch: rebuild at the start, from
@@ -282,8 +300,86 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
 
   for (int64_t it = 0; it < iters; ++it) {
     int moved = 0;
+    if constexpr (FIRE) {
+      // ---- FIRE iteration at the current forces: power P = F.v, |v|, |F|
+      // over the mobile atoms and the rigid body; converged when no degree
+      // of freedom feels |F| >= ftol; else velocity mixing, step-size
+      // control and a semi-implicit Euler step (the values of Bitzek et al.)
+      double q4[4] = {0.0, 0.0, 0.0, 0.0};
+      if (own && role == ROLE_MOBILE) {
+        double a2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          q4[0] += ft[k] * v[k];
+          q4[1] += v[k] * v[k];
+          q4[2] += ft[k] * ft[k];
+          a2 += ft[k] * ft[k];
+        }
+        q4[3] = a2 < ftol2 ? 0.0 : 1.0;
+      }
+      block_sum<4>(q4, red[(step + 1) & 1]);
+      double P = q4[0], vv = q4[1], ff = q4[2];
+      bool big = q4[3] > 0.0;
+      if (rigid_body) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          P += FR[k] * VR[k];
+          vv += VR[k] * VR[k];
+          ff += FR[k] * FR[k];
+          r2 += FR[k] * FR[k];
+        }
+        big = big || !(r2 < ftol2);
+      }
+      if (!big) {
+        f_done = 1;
+        f_iters = it;
+        break;
+      }
+      const double vn = sqrt(vv), fn = sqrt(ff);
+      double mixv = 0.0, mixf = 0.0;
+      const bool reset = !(P > 0.0);
+      if (!reset) {
+        mixv = 1.0 - f_alpha;
+        mixf = fn > 0.0 ? f_alpha * vn / fn : 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) VR[k] = mixv * VR[k] + mixf * FR[k];
+        if (f_since > kFireNmin) {
+          f_dt = fmin(f_dt * kFireFinc, 10.0 * D.dt);
+          f_alpha *= kFireFalpha;
+        }
+        f_since += 1;
+      } else {
+        f_dt *= kFireFdec;
+        f_alpha = kFireAlpha0;
+        f_since = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) VR[k] = 0.0;
+      }
+      if (rigid_body) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          VR[k] += f_dt * FR[k] * D.inv_massR;
+          XR[k] += f_dt * VR[k];
+        }
+      }
+      f_iters = it + 1;
+      if (own && role == ROLE_MOBILE) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          double vk = reset ? 0.0 : mixv * v[k] + mixf * ft[k];
+          vk += f_dt * ft[k] * D.inv_mass;
+          v[k] = vk;
+          x[k] = wrapx(x[k] + f_dt * vk, D.box[k], D.periodic[k]);
+          const double dd = minimg(x[k] - xbs[k * stride + i], D.box[k], D.hbox[k], D.periodic[k]);
+          d2 += dd * dd;
+        }
+        if (d2 > D.skin_half2) moved = 1;
+      }
+    }
     // ---- B A O A: mobile atoms, and the rigid body in every thread --------
-    if (!compute_only) {
+    if (!FIRE && !compute_only) {
       if (own && role == ROLE_MOBILE && nhc) {
         // velocity Verlet: half kick, full drift
         double d2 = 0.0;
@@ -345,7 +441,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
           const double dd = minimg(x[k] - xbs[k * stride + i], D.box[k], D.hbox[k], D.periodic[k]);
           d2 += dd * dd;
         }
-        if (!compute_only && d2 > D.skin_half2) moved = 1;
+        if ((FIRE || !compute_only) && d2 > D.skin_half2) moved = 1;
       }
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
@@ -472,7 +568,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       if constexpr (sizeof(T) == 8) e_own = acc.e; else e_own = acc.e.get();
     }
     // the rigid body's noise for the next step, drawn while others finish
-    if (!compute_only && !nhc && rigid_body && tid == 0) {
+    if (!FIRE && !compute_only && !nhc && rigid_body && tid == 0) {
       double z[3];
       noise<DIM, T>(D.seed, step + 1, (uint32_t)n, z);
 #pragma unroll
@@ -530,7 +626,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     __syncthreads();   // barrier C
     // while wave 0 evaluates the scalars, the other wavefronts draw their
     // atoms' normals for the next step (they depend on the counter only)
-    if (wave != 0 && !compute_only && !nhc && own && role == ROLE_MOBILE && it + 1 < iters) {
+    if (!FIRE && wave != 0 && !compute_only && !nhc && own && role == ROLE_MOBILE && it + 1 < iters) {
       noise<DIM, T>(D.seed, step + 1, (uint32_t)i, zn);
       have_zn = true;
     }
@@ -577,14 +673,14 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     }
     __syncthreads();   // barrier D
     // the boosted clock (eq. 3) is wave 0's alone, off the others' path
-    if (wave == 0 && !compute_only) t_hyper += D.dt * exp(S.dv * D.inv_kT);
+    if (!FIRE && wave == 0 && !compute_only) t_hyper += D.dt * exp(S.dv * D.inv_kT);
     // ---- bias force, total force, final B ------------------------------------
     // one batch of LDS reads, then branch-free arithmetic
     const Bcast Bl = B;
     {
       const bool rigid = own && role == ROLE_RIGID;
       const bool biased = own && role != ROLE_FIXED && Bl.bias_live;
-      const bool kick = !compute_only && own && role == ROLE_MOBILE;
+      const bool kick = !FIRE && !compute_only && own && role == ROLE_MOBILE;
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
         const double f = F[k] + (rigid ? Bl.Fd_n[k] : 0.0);
@@ -599,7 +695,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
     }
 #pragma unroll
     for (int k = 0; k < DIM; ++k) FR[k] = Bl.FR[k];
-    if (!compute_only) {
+    if (!FIRE && !compute_only) {
       if (rigid_body)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) VR[k] = VR[k] + D.hdt * FR[k] * D.inv_massR;
@@ -621,7 +717,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       for (int k = 0; k < DIM; ++k) { v[k] *= c; VR[k] *= c; }
     }
     if (bad) flags |= FLAG_UNSTABLE;
-    if ((it == iters - 1 || bad) && tid == 0) sh_out = S;
+    if ((FIRE || it == iters - 1 || bad) && tid == 0) sh_out = S;
     if (bad) break;
   }
   // ---- write back ----------------------------------------------------------
@@ -671,6 +767,13 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       for (int j = 0; j < 4; ++j) { stg->xi[j] = sh_xi[j]; stg->eta[j] = sh_eta[j]; }
       stg->e_nhc = nhc_energy(D, sh_xi, sh_eta);
     }
+    if constexpr (FIRE) {
+      fire->dt = f_dt;
+      fire->alpha = f_alpha;
+      fire->since_neg = f_since;
+      fire->done = f_done;
+      fire->iters = f_iters;
+    }
   }
 }
 
@@ -689,6 +792,22 @@ __global__ __launch_bounds__(BLOCK) void k_small(const SysDesc *__restrict__ des
   run_small<DIM, T, HALF, BLOCK, MODE == 2>(descs[s], states + s, A, nsteps, MODE & 1, lds, L);
 }
 
+// FIRE quench of the listed systems (fire[b] belongs to sys_list[b]): up to
+// max_iters iterations in one launch, each one an LDS pair pass at the
+// stepping kernel's evaluation (one workgroup of 512 or 1024 threads per
+// system: 512 keeps the register budget of the stepping kernel's 512-thread
+// variant, without spills).
+template <typename T, int DIM, int BLOCK, bool HALF>
+__global__ __launch_bounds__(BLOCK) void k_small_fire(const SysDesc *__restrict__ descs,
+                                                     SysState *__restrict__ states, Arrays A,
+                                                     const int32_t *__restrict__ sys_list, int64_t max_iters,
+                                                     SmallLayout L, FireSys *__restrict__ fire, double ftol2) {
+  extern __shared__ __align__(16) char lds[];
+  const int s = sys_list[blockIdx.x];
+  run_small<DIM, T, HALF, BLOCK, false, true>(descs[s], states + s, A, max_iters, 0, lds, L, fire + blockIdx.x,
+                                              ftol2);
+}
+
 template <typename T, int DIM, int MODE, int BLOCK, bool HALF>
 static hipError_t launch_small_t(const SysDesc *descs, SysState *states, const Arrays &A,
                                  const int32_t *sys_list, int nsys, size_t bytes, int64_t nsteps,
@@ -700,10 +819,11 @@ static hipError_t launch_small_t(const SysDesc *descs, SysState *states, const A
 
 template <typename T, int DIM, bool HALF>
 static hipError_t allow_lds_d(int bytes) {
-  const void *fns[7] = {(const void *)k_small<T, DIM, 1, 1024, HALF>, (const void *)k_small<T, DIM, 0, 256, HALF>,
+  const void *fns[9] = {(const void *)k_small<T, DIM, 1, 1024, HALF>, (const void *)k_small<T, DIM, 0, 256, HALF>,
                         (const void *)k_small<T, DIM, 0, 512, HALF>, (const void *)k_small<T, DIM, 0, 1024, HALF>,
                         (const void *)k_small<T, DIM, 2, 256, HALF>, (const void *)k_small<T, DIM, 2, 512, HALF>,
-                        (const void *)k_small<T, DIM, 2, 1024, HALF>};
+                        (const void *)k_small<T, DIM, 2, 1024, HALF>, (const void *)k_small_fire<T, DIM, 512, HALF>,
+                        (const void *)k_small_fire<T, DIM, 1024, HALF>};
   for (const void *f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -760,6 +880,37 @@ hipError_t launch_small(int kind, int dim, const SysDesc *descs, SysState *state
                     : launch_small_d<float, 3, true>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream);
   return dim == 2 ? launch_small_d<float, 2, false>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream)
                   : launch_small_d<float, 3, false>(descs, states, A, sys_list, nsys, block, b, nsteps, mode, L, stream);
+}
+
+template <typename T, int DIM, bool HALF>
+static hipError_t launch_fire_d(const SysDesc *descs, SysState *states, const Arrays &A, const int32_t *sys_list,
+                                int nsys, size_t bytes, int64_t max_iters, SmallLayout L, FireSys *fire,
+                                double ftol2, hipStream_t stream) {
+  if (L.nmax <= 512)
+    hipLaunchKernelGGL((k_small_fire<T, DIM, 512, HALF>), dim3(nsys), dim3(512), bytes, stream, descs, states, A,
+                       sys_list, max_iters, L, fire, ftol2);
+  else
+    hipLaunchKernelGGL((k_small_fire<T, DIM, 1024, HALF>), dim3(nsys), dim3(1024), bytes, stream, descs, states, A,
+                       sys_list, max_iters, L, fire, ftol2);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_fire(int kind, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
+                             const int32_t *sys_list, int nsys, int nmax, int maxnb, int cellmax, int64_t max_iters,
+                             FireSys *fire, double ftol, hipStream_t stream) {
+  if (nsys <= 0) return hipSuccess;
+  if (nmax > 1024 || kind < 0 || kind > 2 || (dim != 2 && dim != 3) || max_iters < 1) return hipErrorInvalidValue;
+  const SmallLayout L = small_layout(dim, kind, nmax, maxnb, cellmax);
+  const size_t b = L.bytes;
+  const double f2 = ftol * ftol;
+  if (kind == 0)
+    return dim == 2 ? launch_fire_d<double, 2, false>(descs, states, A, sys_list, nsys, b, max_iters, L, fire, f2, stream)
+                    : launch_fire_d<double, 3, false>(descs, states, A, sys_list, nsys, b, max_iters, L, fire, f2, stream);
+  if (kind == 1)
+    return dim == 2 ? launch_fire_d<float, 2, true>(descs, states, A, sys_list, nsys, b, max_iters, L, fire, f2, stream)
+                    : launch_fire_d<float, 3, true>(descs, states, A, sys_list, nsys, b, max_iters, L, fire, f2, stream);
+  return dim == 2 ? launch_fire_d<float, 2, false>(descs, states, A, sys_list, nsys, b, max_iters, L, fire, f2, stream)
+                  : launch_fire_d<float, 3, false>(descs, states, A, sys_list, nsys, b, max_iters, L, fire, f2, stream);
 }
 
 }  // namespace hdk

@@ -106,6 +106,7 @@ _SIGS = {
     "hd_read_positions": (_c.c_int, [_P, _c.c_int32, _dp]),
     "hd_read_velocities": (_c.c_int, [_P, _c.c_int32, _dp]),
     "hd_read_scalars": (_c.c_int, [_P, _c.c_int32, _c.POINTER(hd_scalars)]),
+    "hd_read_scalars_batch": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.POINTER(hd_scalars)]),
     "hd_copy_positions_device": (_c.c_int, [_P, _c.c_int32, _c.c_void_p]),
     "hd_copy_forces_device": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_void_p]),
     "hd_get_state": (_c.c_int, [_P, _c.c_int32, _c.c_void_p, _c.POINTER(_c.c_size_t)]),
@@ -423,6 +424,15 @@ class Context:
         sc = hd_scalars()
         _check(self._h, load().hd_read_scalars(self._h, s, ctypes.byref(sc)), "hd_read_scalars")
         return sc.as_dict()
+
+    def scalars_batch(self, first: int = 0, count: Optional[int] = None) -> List[dict]:
+        """Scalars of systems first .. first + count - 1 (default: all from
+        first) in one device-to-host copy."""
+        if count is None:
+            count = self.num_systems() - first
+        arr = (hd_scalars * max(count, 1))()
+        _check(self._h, load().hd_read_scalars_batch(self._h, first, count, arr), "hd_read_scalars_batch")
+        return [arr[k].as_dict() for k in range(count)]
 
     def copy_positions_device(self, s: int, dev_ptr: int):
         _check(self._h, load().hd_copy_positions_device(self._h, s, ctypes.c_void_p(dev_ptr)),

@@ -78,7 +78,7 @@ class ParallelSliding:
             ctx.set_slider(j, self.slider(base + j))
         ctx.quench(range(self.S), ftol=self.ftol, max_iters=self.max_quench, set_reference=True)
         self.base = base
-        sc = [ctx.scalars(j) for j in range(self.S)]
+        sc = ctx.scalars_batch(0, self.S)
         self._t0 = [s["t_hyper"] for s in sc]
         self._step0 = [s["step"] for s in sc]
 
@@ -92,7 +92,7 @@ class ParallelSliding:
         states: List[Optional[bytes]] = [None] * S
         for c in range(self.max_chunks):
             ctx.step(self.chunk)
-            sc = [ctx.scalars(j) for j in range(S)]
+            sc = ctx.scalars_batch(0, S)
             reached = [not done[j] and sc[j]["t_hyper"] - self._t0[j] >= self.dtau for j in range(S)]
             last = c == self.max_chunks - 1
             if not ((c + 1) % self.check_every == 0 or any(reached) or last):

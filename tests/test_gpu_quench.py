@@ -141,3 +141,69 @@ def test_quench_argument_errors(hd):
         ctx.quench([0], ftol=0.0)
     with pytest.raises(hd.HDError):
         ctx.quench([0], max_iters=0)
+
+
+def test_lds_and_grid_fire_reach_the_same_minima_in_one_call(hd, oracle_mod):
+    """LDS-resident systems take the whole quench in one launch of the LDS
+    kernel's FIRE mode, grid systems iterate FIRE kernels and evaluations:
+    in one call over a mixed batch (listed out of order) every system's
+    results sit at its own listed index, and every minimum is the oracle
+    FIRE's.  Quenched again from its minimum, a system converges at once."""
+    big = jittered(build_3d(10, 10, 4, 4.0), 41)     # 1743 atoms: grid kernels
+    small = jittered(build_2d(), 42)                 # 480 atoms: LDS-resident
+    small3 = jittered(small_3d(), 43)                # 614 atoms: LDS-resident
+    specs = [small, big, small3]
+    for s in specs:
+        s.x_slider = 0.2
+    ctx = hd.make_context(specs, precision=hd.HD_FP64, init_velocities=False)
+    order = [2, 1, 0]
+    iters, disp, xms = ctx.quench(order, ftol=1e-8, max_iters=200000)
+    for k, sidx in enumerate(order):
+        spec = specs[sidx]
+        assert iters[k] > 0
+        ref = oracle_mod.OracleSystem(spec)
+        assert ref.fire(ftol=1e-8, maxit=200000) >= 0
+        assert float(np.abs(min_image(spec, xms[k] - ref.positions())).max()) < 1e-5
+        want = float(np.sqrt((min_image(spec, xms[k] - spec.rO) ** 2).sum(0)).max())
+        assert disp[k] == pytest.approx(want, rel=1e-12)
+    # from the minimum: converged at the first test, on both paths
+    for sidx in (0, 1):
+        ctx.set_positions(sidx, xms[order.index(sidx)])
+    it2, _, _ = ctx.quench([1, 0], ftol=1e-8, max_iters=1000)
+    assert list(it2) == [0, 0]
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lds_fire_matches_the_grid_fire(hd, precision):
+    """The same systems quenched on the LDS kernel and on the grid kernels
+    land on the same minimum: float64 to 1e-8 within 1e-6; float32 pair
+    forces converge only to a coarser tolerance (1e-3), which leaves soft
+    modes undetermined to about ftol / (their curvature): the same basin,
+    within a tenth of a lattice spacing."""
+    specs = [jittered(build_2d(), 50), jittered(small_3d(), 51)]
+    ftol = 1e-8 if precision == 0 else 1e-3
+    out = []
+    for mode in (hd.HD_EXEC_BATCHED, hd.HD_EXEC_GRID):
+        ctx = hd.make_context(specs, precision=precision, exec_mode=mode, init_velocities=False)
+        iters, disp, xms = ctx.quench([0, 1], ftol=ftol, max_iters=200000)
+        assert all(v > 0 for v in iters)
+        out.append(xms)
+        ctx.close()
+    tol = 1e-6 if precision == 0 else 0.1
+    for s, a, b in zip(specs, *out):
+        assert float(np.abs(min_image(s, a - b)).max()) < tol
+
+
+def test_scalars_batch_matches_single_reads(hd):
+    specs = [jittered(build_2d(), 60 + k) for k in range(3)]
+    ctx = hd.make_context(specs, precision=hd.HD_FP32C)
+    ctx.step(25)
+    got = ctx.scalars_batch()
+    assert got == [ctx.scalars(k) for k in range(3)]
+    assert ctx.scalars_batch(1, 2) == got[1:]
+    assert ctx.scalars_batch(3, 0) == []
+    for first, count in ((-1, 1), (2, 2), (0, 4)):
+        with pytest.raises(hd.HDError):
+            ctx.scalars_batch(first, count)
+    ctx.close()

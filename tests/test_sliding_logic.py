@@ -39,6 +39,10 @@ class FakeContext:
     def scalars(self, j):
         return {"t_hyper": self.th[j], "step": self.step_n[j], "f_lat": 0.1 * j, "x_slider": self.slider[j]}
 
+    def scalars_batch(self, first=0, count=None):
+        count = self.S - first if count is None else count
+        return [self.scalars(j) for j in range(first, first + count)]
+
     def quench(self, systems, ftol=1e-6, max_iters=1000, set_reference=False):
         systems = list(systems)
         self.quenched.append((systems, set_reference))
