@@ -97,6 +97,7 @@ struct SysState {
 
 struct Arrays {
   int64_t ntot;
+  int32_t rec_f32, pad_rec;               // pair records in the float32 layout (below)
   double *x, *v, *rO, *xb, *cofs, *ftot;  // [3][ntot]
   double *flj, *hu, *fb;                  // [3][ntot]
   double *eatom;                          // [ntot]
@@ -111,15 +112,20 @@ struct Arrays {
   // grid kernels: atoms are visited in cell-sorted order.  pos[a] is the
   // sorted position of atom a within its system (cell_atoms is the inverse);
   // rec holds one 64-byte pair record per sorted position, refreshed by
-  // every drift: x (float64, doubles 0-2), u (float64, doubles 3-5) and
-  // type | role << 1 (double 7).  Neighbour lists hold sorted positions, so a
-  // neighbour's data is one aligned record, and the atoms of a wavefront
-  // share cells and read nearby records.
+  // every drift.  float64 runs: x (doubles 0-2), u (doubles 3-5) and
+  // type | role << 1 (double 7).  float32 runs (rec_f32): x (doubles 0-2), u
+  // as float32 (bytes 24-35), type | role << 1 (int32, bytes 36-39) and u as
+  // float64 (doubles 5-7, for the atom's own per-system sums), so that a
+  // neighbour is the record's first 40 bytes and needs no conversion.
+  // Neighbour lists hold sorted positions, so a neighbour's data is one
+  // aligned record, and the atoms of a wavefront share cells and read nearby
+  // records.
   int32_t *pos;                           // [ntot]
   double *rec;                            // [ntot][8]
   // list build: the build positions (doubles 0-2) and type | role << 1
-  // (double 3) of each sorted position, written by the cell sort, so a
-  // stencil row's candidates are consecutive 32-byte records
+  // (integer bits of the fourth slot) of each sorted position, written by
+  // the cell sort, so a stencil row's candidates are consecutive 32-byte
+  // records
   double *brec;                           // [ntot][4]
   double *tuu;                            // [3][ntot] T[u,u] (curvature bias) or T[w,w] (eigenvalue)
   // eigenvalue bias: the mode estimate q of the mobile atoms (rigid atoms'
@@ -134,6 +140,28 @@ struct Arrays {
 };
 
 constexpr int kRecDoubles = 8;
+
+// Write the pair record of one atom (layout above).
+__device__ __forceinline__ void rec_store(const Arrays &A, double *rec, int dim, const double x[3],
+                                          const double u[3], int tr) {
+  for (int k = 0; k < dim; ++k) rec[k] = x[k];
+  if (A.rec_f32) {
+    float *uf = (float *)(rec + 3);
+    for (int k = 0; k < dim; ++k) { uf[k] = (float)u[k]; rec[5 + k] = u[k]; }
+    ((int32_t *)rec)[9] = tr;
+  } else {
+    for (int k = 0; k < dim; ++k) rec[3 + k] = u[k];
+    rec[7] = (double)tr;
+  }
+}
+
+// A neighbour's u component from its pair record (float32 kernels read the
+// float32 layout, float64 kernels the float64 one).
+template <typename T>
+__device__ __forceinline__ T rec_u(const double *r, int k) {
+  if constexpr (sizeof(T) == 4) return ((const float *)(r + 3))[k];
+  else return r[3 + k];
+}
 
 // ---------------------------------------------------------------------------
 // Small helpers
@@ -839,7 +867,7 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
       double xj[3], dx[3];
       T uj[3], wj[3];
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; wj[k] = (T)rw[k]; }
+      for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = rec_u<T>(r, k); wj[k] = (T)rw[k]; }
       const double r2 = pair_disp_l<DIM, LASTP>(D, xi, xj, dx);
       pair_term<DIM, T, EXT>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc, wi, wj);
     }
@@ -863,7 +891,7 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
       for (int u4 = 0; u4 < kGatherBlock; ++u4) {
         const double *r = (const double *)(recb + (((uint32_t)ent[u4] >> 1) << 6));
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) { xj[u4][k] = r[k]; uj[u4][k] = (T)r[3 + k]; }
+        for (int k = 0; k < DIM; ++k) { xj[u4][k] = r[k]; uj[u4][k] = rec_u<T>(r, k); }
       }
 #pragma unroll
       for (int u4 = 0; u4 < kGatherBlock; ++u4) {
@@ -886,7 +914,7 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
       double xj[3], dx[3];
       T uj[3];
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = (T)r[3 + k]; }
+      for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = rec_u<T>(r, k); }
       const double r2 = pair_disp_l<DIM, LASTP>(D, xi, xj, dx);
       pair_term<DIM, T, EXT>(R, ent & 1, r2 < D.rc2, dx, r2, ui, uj, acc);
     }

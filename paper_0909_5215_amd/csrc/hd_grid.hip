@@ -74,9 +74,11 @@ __device__ __forceinline__ void drift_atom(const SysDesc &D, const SysState &st,
   double *rec = A.rec + (D.off + A.pos[a]) * kRecDoubles;
   if (role == ROLE_FIXED) {
     // fixed atoms: position as is, u = 0 (and no mode component)
+    double xf[3] = {0, 0, 0};
+    const double zero[3] = {0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) { rec[k] = A.x[k * N + a]; rec[3 + k] = 0.0; }
-    rec[7] = (double)tr;
+    for (int k = 0; k < DIM; ++k) xf[k] = A.x[k * N + a];
+    rec_store(A, rec, DIM, xf, zero, tr);
     if (D.eig) {
       double *rw = A.recw + (D.off + A.pos[a]) * 4;
 #pragma unroll
@@ -135,16 +137,14 @@ __device__ __forceinline__ void drift_atom(const SysDesc &D, const SysState &st,
     }
   }
   // the pair record (the grid kernels read u there only)
-  double d2 = 0.0;
+  double d2 = 0.0, un[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    const double uk = minimg(xn[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
-    rec[k] = xn[k];
-    rec[3 + k] = uk;
+    un[k] = minimg(xn[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
     const double dd = minimg(xn[k] - A.xb[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
     d2 += dd * dd;
   }
-  rec[7] = (double)tr;
+  rec_store(A, rec, DIM, xn, un, tr);
   if (D.eig) {
     // the mode estimate spread over the atoms, beside the pair record
     double *rw = A.recw + (D.off + A.pos[a]) * 4;
@@ -265,7 +265,7 @@ __device__ __forceinline__ void put_brec(const SysDesc &D, const Arrays &A, cons
   b[0] = xs[a];
   b[1] = xs[N + a];
   b[2] = D.dim == 3 ? xs[2 * N + a] : 0.0;
-  b[3] = (double)A.tr[a];
+  ((int64_t *)b)[3] = (int64_t)A.tr[a];   // type/role as integer bits
 }
 
 // Sort each cell's atoms by index (so that lists are built in a fixed order),
@@ -330,7 +330,7 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
   double xi[3];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) xi[k] = brec[(int64_t)p * 4 + k];
-  const int ri = (int)brec[(int64_t)p * 4 + 3] >> 1;
+  const int ri = (int)((const int64_t *)brec)[(int64_t)p * 4 + 3] >> 1;
   int cc[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -368,7 +368,7 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
           for (int u = 0; u < 4; ++u) {
             const int pp = p0 + u < pe ? p0 + u : p0;
             const double *cr = brec + (int64_t)pp * 4;
-            trj[u] = (int)cr[3];
+            trj[u] = (int)((const int64_t *)cr)[3];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) xj[u][k] = cr[k];
           }
@@ -408,7 +408,7 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
 constexpr int kBuildThreads = 256;
 constexpr int kRowCap = 48;
 
-template <int DIM, typename SubT>
+template <int DIM, typename SubT, bool SHIFT>
 __device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
                         const double xi[3], int ri, const int cc[3], int oy, int oz, SubT *sub) {
   const int32_t *cstart = A.cell_start + D.cstart_off;
@@ -419,11 +419,20 @@ __device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
   for (int ox = lo0; ox <= hi0; ++ox) {
     int q3[3] = {cc[0] + ox, cc[1] + oy, cc[2] + oz};
     bool skip = false;
+    // SHIFT: the image of a wrapped stencil cell is the box length away
+    // (every periodic axis has at least three cells, so for each pair within
+    // the list radius this is the minimum image, rounded as the general rule
+    // rounds it)
+    double sh[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if (q3[k] < 0 || q3[k] >= D.nc[k]) {
-        if (k < DIM && D.periodic[k]) q3[k] = (q3[k] + D.nc[k]) % D.nc[k];
-        else skip = true;
+        if (k < DIM && D.periodic[k]) {
+          sh[k] = q3[k] < 0 ? D.box[k] : -D.box[k];
+          q3[k] = (q3[k] + D.nc[k]) % D.nc[k];
+        } else {
+          skip = true;
+        }
       }
     }
     if (skip) continue;
@@ -436,19 +445,26 @@ __device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
       for (int u = 0; u < 4; ++u) {
         const int pp = p0 + u < pe ? p0 + u : p0;
         const double *cr = brec + (int64_t)pp * 4;
-        trj[u] = (int)cr[3];
+        trj[u] = (int)((const int64_t *)cr)[3];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) xj[u][k] = cr[k];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int pp = p0 + u;
-        if (pp >= pe || pp == p) continue;
         const int rj = trj[u] >> 1;
-        if ((ri == ROLE_FIXED && rj == ROLE_FIXED) || (ri == ROLE_RIGID && rj == ROLE_RIGID)) continue;
-        double dx[3];
-        const double r2 = pair_disp<DIM>(D, xi, xj[u], dx);
-        if (r2 < D.rl2) {
+        const bool excl = pp >= pe || pp == p || (ri == ROLE_FIXED && rj == ROLE_FIXED) ||
+                          (ri == ROLE_RIGID && rj == ROLE_RIGID);
+        double r2;
+        if constexpr (SHIFT) {
+          r2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) r2 = add_sq_exact(r2, (xi[k] - xj[u][k]) + sh[k]);
+        } else {
+          double dx[3];
+          r2 = pair_disp<DIM>(D, xi, xj[u], dx);
+        }
+        if (!excl && r2 < D.rl2) {
           if (cnt < kRowCap) sub[cnt * kBuildThreads] = (SubT)((pp << 1) | (trj[u] & 1));
           ++cnt;
         }
@@ -477,7 +493,7 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
     const double *b = A.brec + (off + p) * 4;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) xi[k] = b[k];
-    ri = (int)b[3] >> 1;
+    ri = (int)((const int64_t *)b)[3] >> 1;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const int ck = (int)floor((xi[k] - D.lo[k]) * D.inv_h[k]);
@@ -485,7 +501,12 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
     }
     const int oy = DIM == 3 ? r % 3 - 1 : r - 1, oz = DIM == 3 ? r / 3 - 1 : 0;
     const bool in_y = D.nc[1] > 1 || oy == 0, in_z = DIM < 3 || D.nc[2] > 1 || oz == 0;
-    if (in_y && in_z) cnt = scan_row<DIM, SubT>(D, A, p, xi, ri, cc, oy, oz, sub_all + tid);
+    bool shift = true;   // every periodic axis has at least three cells
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) shift = shift && (!D.periodic[k] || D.nc[k] >= 3);
+    if (in_y && in_z)
+      cnt = shift ? scan_row<DIM, SubT, true>(D, A, p, xi, ri, cc, oy, oz, sub_all + tid)
+                  : scan_row<DIM, SubT, false>(D, A, p, xi, ri, cc, oy, oz, sub_all + tid);
   }
   counts[tid] = cnt;
   __syncthreads();
@@ -519,12 +540,14 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
   A.pos[a] = p;
   double *rec = A.rec + (off + p) * kRecDoubles;
   const int tr = A.tr[a];
-  for (int k = 0; k < DIM; ++k) {
-    const double xk = A.x[k * N + a];
-    rec[k] = xk;
-    rec[3 + k] = (tr >> 1) == ROLE_FIXED ? 0.0 : minimg(xk - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+  {
+    double xr[3] = {0, 0, 0}, ur[3] = {0, 0, 0};
+    for (int k = 0; k < DIM; ++k) {
+      xr[k] = A.x[k * N + a];
+      ur[k] = (tr >> 1) == ROLE_FIXED ? 0.0 : minimg(xr[k] - A.rO[k * N + a], D.box[k], D.hbox[k], D.periodic[k]);
+    }
+    rec_store(A, rec, DIM, xr, ur, tr);
   }
-  rec[7] = (double)tr;
   if (D.eig) {
     double *rw = A.recw + (off + p) * 4;
     for (int k = 0; k < DIM; ++k)
@@ -581,13 +604,14 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
   // one atom per sorted position; results go to the atom's own index
   const int p = t.first + (valid ? la : 0);
   const double *r = A.rec + (D.off + p) * kRecDoubles;
-  const int tr = (int)r[7], role = tr >> 1;
+  constexpr bool F32 = sizeof(T) == 4;   // float32 record layout
+  const int tr = F32 ? ((const int32_t *)r)[9] : (int)r[7], role = tr >> 1;
   double xi[3] = {0, 0, 0}, u64[3] = {0, 0, 0};
   T ui[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     xi[k] = r[k];
-    u64[k] = r[3 + k];
+    u64[k] = F32 ? r[5 + k] : r[3 + k];
     ui[k] = (T)u64[k];
   }
   double w64[3] = {0, 0, 0};

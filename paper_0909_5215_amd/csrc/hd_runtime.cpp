@@ -1084,6 +1084,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
   ctx->ntot = N;
   hdk::Arrays &A = ctx->A;
   A.ntot = N;
+  A.rec_f32 = ctx->prec == HD_FP64 ? 0 : 1;
   hd_status st;
 #define ALLOC(p, cnt) do { st = dalloc(ctx, &(p), (cnt)); if (st != HD_OK) return st; } while (0)
   ALLOC(A.x, 3 * N); ALLOC(A.v, 3 * N); ALLOC(A.rO, 3 * N); ALLOC(A.xb, 3 * N); ALLOC(A.cofs, 3 * N);
