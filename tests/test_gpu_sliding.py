@@ -79,6 +79,40 @@ def test_latest_transition_seeds_the_next_cycle(hd):
     assert float(np.max(d)) < 1e-4
 
 
+
+def test_cycle_detects_a_spontaneous_slip(hd):
+    """No reference is moved: the spring pulls the tip, and at the two
+    strongest slider positions (lateral force near 10 eps/sigma) the tip
+    slips by a lattice spacing during plain MD at kT = 0.1 (at x_S = 10
+    no slip comes within the cycle).  The check quench reads the slip as a
+    transition (a displacement of one spacing, two if it slipped twice
+    between checks), and the latest slipping position seeds the next
+    cycle."""
+    from paper_0909_5215_amd.sliding import ParallelSliding
+    S = 4
+    specs = []
+    for k in range(S):
+        s = build_2d()
+        s.seed = 700 + k
+        specs.append(s)
+    ctx = hd.make_context(specs, precision=hd.HD_FP64)
+    dt = specs[0].dt
+    ps = ParallelSliding(ctx, x0=10.0, dx=0.5, dtau=8000 * dt, threshold=0.5, chunk=500, check_every=2)
+    ps.start(0)
+    r = ps.run_cycle()
+    a = float(2.0 ** (1.0 / 6.0))
+    assert not r.transitions[0]
+    assert r.transitions[2] or r.transitions[3]
+    assert r.k_star >= 2 and r.next_base == r.k_star
+    for j in range(S):
+        if r.transitions[j]:
+            assert 0.8 * a < r.max_disp[j] < 2.5 * a
+            assert r.steps[j] < 8000
+    ps.advance(r)
+    for j in range(S):
+        assert ctx.scalars(j)["x_slider"] == pytest.approx(10.0 + 0.5 * (r.k_star + j))
+
+
 def test_argument_errors(hd):
     from paper_0909_5215_amd.sliding import ParallelSliding
     ctx = hd.make_context(batch(2), precision=hd.HD_FP64)
