@@ -1323,7 +1323,7 @@ hd_status hd_autotune(hd_ctx *ctx, double min_ms, int64_t max_steps, hd_schedule
     else any_large = true;
   }
   std::vector<hd_schedule> cand;
-  const int large_grid[3] = {128, 256, 512}, large_pers[3] = {256, 512, 1024};
+  const int large_grid[4] = {64, 128, 256, 512}, large_pers[3] = {256, 512, 1024};
   auto add_large = [&](hd_schedule c, bool need) {
     if (!need) { c.persistent_large = 0; c.large_block = 256; cand.push_back(c); return; }
     for (int b : large_grid) { c.persistent_large = 0; c.large_block = b; cand.push_back(c); }

@@ -344,7 +344,7 @@ class Context:
     def autotune(self, min_ms: float = 20.0, max_steps: int = 8192):
         """Time every launch shape on this batch, keep the fastest (the
         trajectory is left where it was).  Returns (chosen, trials)."""
-        cap = 32
+        cap = 128   # more than the candidate shapes of any batch
         buf = (hd_schedule * cap)()
         n = ctypes.c_int32()
         _check(self._h, load().hd_autotune(self._h, float(min_ms), int(max_steps), buf, cap, ctypes.byref(n)),

@@ -42,8 +42,9 @@ def test_autotune_keeps_state_and_picks_fastest(hd, oracle_mod, precision):
     before = [state(ctx, k) for k in range(len(specs))]
     chosen, trials = ctx.autotune(min_ms=2.0, max_steps=256)
     # LDS on (block 512 or 1024; float32 also with or without half lists)
-    # x 6 shapes for the large system, then LDS off x 6
-    assert len(trials) == (18 if precision == 0 else 30)
+    # x 7 shapes for the large system (grid tiles of 64 to 512 atoms, the
+    # one-workgroup kernel at 256 to 1024 threads), then LDS off x 7
+    assert len(trials) == (21 if precision == 0 else 35)
     assert all(t["ms_per_step"] > 0 for t in trials)
     best = min(trials, key=lambda t: t["ms_per_step"])
     assert chosen["ms_per_step"] == best["ms_per_step"]

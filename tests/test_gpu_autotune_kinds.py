@@ -14,6 +14,7 @@ SHAPES = [
     {"lds_resident": 1, "small_block": 1024, "persistent_large": 0, "large_block": 128, "small_half_lists": 0},
     {"lds_resident": 1, "small_block": 512, "persistent_large": 1, "large_block": 1024, "small_half_lists": 0},
     {"lds_resident": 0, "small_block": 0, "persistent_large": 0, "large_block": 512},
+    {"lds_resident": 0, "small_block": 0, "persistent_large": 0, "large_block": 64},
     {"lds_resident": 0, "small_block": 0, "persistent_large": 1, "large_block": 256},
 ]
 

@@ -42,8 +42,8 @@ def snapshot(oracle_mod, spec, seed, need_bias=True):
     return s
 
 
-def check_batch(hd, oracle_mod, specs, sample):
-    ctx = hd.make_context(specs, precision=hd.HD_FP32C, init_velocities=False)
+def check_batch(hd, oracle_mod, specs, sample, block=0):
+    ctx = hd.make_context(specs, precision=hd.HD_FP32C, init_velocities=False, block_threads=block)
     for k in range(len(specs)):
         sc = ctx.scalars(k)
         assert np.isfinite(sc["e_pot"]) and sc["flags"] == 0, k
@@ -61,18 +61,22 @@ def test_c2_full_batch(hd, oracle_mod):
     check_batch(hd, oracle_mod, specs, range(len(specs)))
 
 
-def test_c3_sampled(hd, oracle_mod):
+# the grid tile sizes the autotuner picks for the 3D batches (64 or 128
+# atoms), and the default
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_c3_sampled(hd, oracle_mod, block):
     base = config_c3()
     sample = [0, 21, 42, 63]
     specs = [snapshot(oracle_mod, s, 200 + k, need_bias=(k in sample)) for k, s in enumerate(base)]
-    check_batch(hd, oracle_mod, specs, sample)
+    check_batch(hd, oracle_mod, specs, sample, block)
 
 
-def test_c5b_sampled(hd, oracle_mod):
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_c5b_sampled(hd, oracle_mod, block):
     base = config_c5b()
     sample = [0, 101, 255]
     specs = [snapshot(oracle_mod, s, 300 + k, need_bias=(k in sample)) for k, s in enumerate(base)]
-    check_batch(hd, oracle_mod, specs, sample)
+    check_batch(hd, oracle_mod, specs, sample, block)
 
 
 def test_c4_sampled(hd, oracle_mod):
