@@ -59,8 +59,8 @@ HBM_COUNTERS = {
     # fused kick-drift, the rebuild launches, pairs, reduce) summed and
     # divided by its steps (per_step: scaled by the steps one launch covers)
     ("C5b", "grid step (kg_* kernels, timed as a whole)"): {
-        "src": ("hd_grid.hip", "hd_device.h"), "sha": "b91dbacbc38f4fe5",
-        "fetch_kib": 533729.7, "fetch_scale": 2.0, "write_kib": 404879.4, "write_scale": 1.0,
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "3b29ad1df82a36c8",
+        "fetch_kib": 526933.5, "fetch_scale": 2.0, "write_kib": 403343.0, "write_scale": 1.0,
         "per_step": True,
     },
 }
@@ -81,8 +81,8 @@ VALU_COUNTERS = {
         "insts_valu": 882279891.9, "steps": 2000,
     },
     ("C5b", "grid step (kg_* kernels, timed as a whole)"): {
-        "src": ("hd_grid.hip", "hd_device.h"), "sha": "b91dbacbc38f4fe5",
-        "insts_valu": 353542493.1, "steps": 1,
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "3b29ad1df82a36c8",
+        "insts_valu": 348157639.1, "steps": 1,
     },
 }
 

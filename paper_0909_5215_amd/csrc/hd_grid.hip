@@ -402,8 +402,8 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
 // list_atom_g builds (same entries, same order) with 3 or 9 times the
 // parallelism, which a system whose skin expired needs to hide memory
 // latency.  A row with more than kRowCap entries sends its atom to
-// list_atom_g.  Blocks of kBuildThreads threads, enough of them per tile for
-// kBuildThreads / 9 atoms each.  The sub-lists take 16-bit entries for
+// list_atom_g.  Blocks of kBuildThreads threads, kBuildThreads / 9 atoms
+// each (3D).  The sub-lists take 16-bit entries for
 // systems with 16-bit lists: half the LDS, twice the workgroups per CU.
 constexpr int kBuildThreads = 256;
 constexpr int kRowCap = 48;
@@ -475,15 +475,14 @@ __device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
 }
 
 template <int DIM, typename SubT>
-__device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, const Tile &t, int part, int flag,
+__device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, int first, int count, int flag,
                            SubT *sub_all, int *counts) {
   constexpr int S = DIM == 3 ? 9 : 3;        // stencil rows per atom
   constexpr int APB = kBuildThreads / S;     // atoms per block
   const int tid = threadIdx.x, la = tid / S, r = tid % S;
-  const int lp = part * APB + la;            // atom within the tile
-  const bool active = la < APB && lp < t.count;
+  const bool active = la < APB && la < count;
   const int64_t off = D.off, N = A.ntot;
-  const int p = t.first + lp;
+  const int p = first + la;
   int i = 0, ri = 0;
   double xi[3] = {0, 0, 0};
   int cc[3] = {0, 0, 0};
@@ -558,27 +557,31 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, cons
   if (p == 0 && flag != 2) atomicAdd(&st.n_rebuilds, 1);
 }
 
-// Work item w = part * (flagged tiles) + k: consecutive items are parts of
-// different tiles, and consecutive workgroups go to different XCDs, so the
-// few systems that rebuild in a step spread over the whole chip.
+// Work item w = chunk * (flagged systems) + k: a chunk of kBuildThreads / 9
+// (3D) or / 3 (2D) consecutive sorted positions of the k-th system whose
+// list expired, independent of the tile size (every lane of a chunk but a
+// system's last has an atom); consecutive items are chunks of different
+// systems, and consecutive workgroups go to different XCDs, so the few
+// systems that rebuild in a step spread over the whole chip.
 template <bool E16>
 __global__ __launch_bounds__(kBuildThreads) __attribute__((amdgpu_waves_per_eu(5))) void kg_build_list(const SysDesc *__restrict__ descs,
                                                                SysState *__restrict__ states, Arrays A,
-                                                               const Tile *__restrict__ tiles, int parts) {
+                                                               int chunks) {
   using SubT = typename std::conditional<E16, uint16_t, int32_t>::type;
   __shared__ SubT sub[kRowCap * kBuildThreads];
   __shared__ int counts[kBuildThreads];
-  const int nt = __hip_atomic_load(&A.rb_count[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int w = blockIdx.x; w < nt * parts; w += gridDim.x) {
-    const int part = w / nt;
-    const Tile t = tiles[A.rb_tiles[w - part * nt]];
-    const int flag = A.rebuild_flag[t.sys];
-    const SysDesc &D = descs[t.sys];
-    if (D.dim == 2) {
-      if (part * (kBuildThreads / 3) < t.count) build_rows<2, SubT>(D, states[t.sys], A, t, part, flag, sub, counts);
-    } else {
-      if (part * (kBuildThreads / 9) < t.count) build_rows<3, SubT>(D, states[t.sys], A, t, part, flag, sub, counts);
-    }
+  const int nrb = __hip_atomic_load(&A.rb_count[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int w = blockIdx.x; w < nrb * chunks; w += gridDim.x) {
+    const int c = w / nrb;
+    const int s = A.rb_sys[w - c * nrb];
+    const SysDesc &D = descs[s];
+    const int apb = D.dim == 2 ? kBuildThreads / 3 : kBuildThreads / 9;
+    const int first = c * apb;
+    if (first >= D.n) continue;   // the same for every thread of the workgroup
+    const int count = D.n - first < apb ? D.n - first : apb;
+    const int flag = A.rebuild_flag[s];
+    if (D.dim == 2) build_rows<2, SubT>(D, states[s], A, first, count, flag, sub, counts);
+    else build_rows<3, SubT>(D, states[s], A, first, count, flag, sub, counts);
     __syncthreads();   // sub and counts are reused by the next item
   }
 }
@@ -1016,13 +1019,15 @@ int launch_rebuild(const SysDesc *descs, SysState *states, const Arrays &A, cons
   const int sort_blocks = (P.max_ncell + 3) / 4 < 1024 ? (P.max_ncell + 3) / 4 : 1024;
   hipLaunchKernelGGL(kg_cell_sort, dim3(sort_blocks > 0 ? sort_blocks : 1, P.nsys < 64 ? P.nsys : 64), dim3(256), 0,
                      stream, descs, A);
-  // enough workgroups per tile for 3D systems (kBuildThreads / 9 atoms each)
-  const int parts = (B + kBuildThreads / 9 - 1) / (kBuildThreads / 9);
-  const int gb = nt * parts < 4096 ? nt * parts : 4096;
+  // work items: chunks of a system's sorted positions (kBuildThreads / 9
+  // atoms each in 3D, / 3 in 2D), for every system whose list expired
+  const int chunks = (P.max_n + kBuildThreads / 9 - 1) / (kBuildThreads / 9);
+  const int64_t items = (int64_t)P.nsys * chunks;
+  const int gb = items < 4096 ? (int)items : 4096;
   if (P.list16)
-    hipLaunchKernelGGL(kg_build_list<true>, dim3(gb), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles, parts);
+    hipLaunchKernelGGL(kg_build_list<true>, dim3(gb), dim3(kBuildThreads), 0, stream, descs, states, A, chunks);
   else
-    hipLaunchKernelGGL(kg_build_list<false>, dim3(gb), dim3(kBuildThreads), 0, stream, descs, states, A, P.tiles, parts);
+    hipLaunchKernelGGL(kg_build_list<false>, dim3(gb), dim3(kBuildThreads), 0, stream, descs, states, A, chunks);
   return 6;
 }
 

@@ -82,6 +82,7 @@ struct GridPlan {
   const int32_t *sys_tile0;  // device, first tile of each covered system
   int nsys;
   int max_ncell;           // largest cell count among the covered systems
+  int max_n;               // largest atom count among the covered systems
   void *gscal;             // device, per-system scalars of the last evaluation
   int any_bonds;           // some covered system has harmonic tip bonds
   int any_curv;            // some covered system is biased on the curvature

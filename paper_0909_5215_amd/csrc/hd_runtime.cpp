@@ -413,6 +413,7 @@ hd_status build_plan(hd_ctx *ctx, const std::vector<int> &systems, Plan &P) {
       tiles.push_back(T);
     }
     max_ncell = std::max(max_ncell, ctx->h_desc[s].ncell);
+    P.gp.max_n = std::max(P.gp.max_n, n);
     if (ctx->sys[s].tip_bonds) P.gp.any_bonds = 1;
     if (ctx->h_desc[s].curv) P.gp.any_curv = 1;
     if (ctx->h_desc[s].thermostat == 1) P.gp.any_nhc = 1;
