@@ -140,15 +140,20 @@ def workload(name):
     return specs, desc
 
 
-# bias variables: 0 slope (eq. 5), 1 curvature (eq. 6), 2 distance (eq. 7)
-BIAS_CHOICES = {"slope": (0, -1), "curvature": (1, -1), "distance": (2, -1),
-                "slope+curvature": (0, 1), "slope+distance": (0, 2), "curvature+distance": (1, 2)}
+# bias variables: 0 slope (eq. 5), 1 curvature (eq. 6), 2 distance (eq. 7),
+# 3 the lowest eigenvalue along a rotated mode (eq. 15)
+BIAS_CHOICES = {"slope": (0, -1), "curvature": (1, -1), "distance": (2, -1), "eigenvalue": (3, -1),
+                "slope+curvature": (0, 1), "slope+distance": (0, 2), "curvature+distance": (1, 2),
+                "slope+eigenvalue": (0, 3)}
+# the eigenvalue variable's mode estimate: a seeded random start, rotated
+# once per step with this step (stable for these models' Hessian spectra)
+MODE_ALPHA = 2e-4
 
 
 def thresholds(var, samples):
     """Critical values (lower, upper) of a switch from unbiased samples."""
     a = np.asarray(samples)
-    if var == 2:
+    if var == 2:   # the distance: biased below a small value
         lo, hi = np.quantile(a, 0.95), np.quantile(a, 0.5)
         if not lo > hi:
             lo = hi + 1e-3 * (abs(hi) + 1.0)
@@ -190,9 +195,8 @@ def prepare(hd, specs, quench_steps, prerun_steps, block):
     every = max(1, prerun_steps // (2 * nsamp))
     for _ in range(nsamp):
         ctx.step(every)
-        for k in range(len(specs)):
-            sc = ctx.scalars(k)
-            samples[k].append((sc["g"], sc["kappa"], sc["d"]))
+        for k, sc in enumerate(ctx.scalars_batch()):
+            samples[k].append((sc["g"], sc["kappa"], sc["d"], sc["lambda"]))
     states = []
     for k, s in enumerate(specs):
         v = np.array(samples[k])
@@ -408,10 +412,13 @@ def main():
 
     specs, desc = workload(args.config)
     v1, v2 = BIAS_CHOICES[args.bias]
-    for s in specs:
+    for k, s in enumerate(specs):
         if args.skin is not None:
             s.skin = args.skin
         s.bias_var1, s.bias_var2 = v1, v2
+        if 3 in (v1, v2):
+            s.mode = np.random.default_rng(9000 + k).standard_normal(s.pos.shape)
+            s.mode_alpha = MODE_ALPHA
         if args.thermostat == "nhc":
             s.thermostat, s.nhc_len, s.nhc_tau = 1, 3, 0.5
     ckey = args.config if args.bias == "slope" else f"{args.config}/{args.bias}"
