@@ -921,15 +921,134 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
   }
 }
 
+// Quad gather for four lanes per atom.  The plain loop has every lane load its
+// neighbour's record itself, in three loads whose lanes touch up to 64
+// different cache lines each.  Here the quad of an atom fetches the records
+// of its four lanes' neighbours one after the other, lane s bringing bytes
+// 16s..16s+15 of the record straight into LDS, so that each load touches one
+// line per quad (about 8 times fewer vector-L1 lookups per pair); every lane
+// then reads its own neighbour (x and u, the record's first 36 or 48 bytes)
+// from LDS.  The next round's list entries are requested behind the records,
+// so that their memory latency overlaps the round's arithmetic.  The LDS slot
+// of a load is 1024 + 16 bytes per wavefront: with that stride the 16 lanes
+// served together by an LDS read take 16 different bank groups.  Two
+// neighbours per lane per round: larger rounds take more LDS than they gain
+// (the LDS then bounds the workgroups per CU).
+constexpr int kQuadUnroll = 2;               // neighbours per lane per round
+constexpr int kQuadSlot = 1040;              // bytes per load in a wavefront's LDS area
+constexpr int kQuadWaveBytes = kQuadUnroll * 4 * kQuadSlot;
+
+template <int Q>
+__device__ __forceinline__ int quad_bcast(int v) {   // lane Q's value to its whole quad
+  return __builtin_amdgcn_update_dpp(0, v, Q * 0x55, 0xf, 0xf, true);
+}
+
+// One 16-byte chunk of a record into a lane's place in an LDS slot.
+__device__ __forceinline__ void lds_chunk(const char *__restrict__ src, char *slot) {
+  __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)slot, 16, 0, 0);
+}
+
+// The neighbour loop of one lane of a quad: cnt is the lane's entry count,
+// rounds the quad's (every lane of the quad runs them, so that the quad's
+// loads are complete; entries past a lane's count are its own position,
+// masked).  lds is this wavefront's kQuadWaveBytes area (wave-uniform).
+template <int DIM, typename T, bool LASTP, bool E16>
+__device__ __forceinline__ void pair_loop_quad(const SysDesc &D, const LJRow<T> &R, const char *__restrict__ recb,
+                                               const char *__restrict__ nbrb, uint32_t lo, uint32_t lstep, int cnt,
+                                               int rounds, int self, const double xi[3], const T ui[3],
+                                               PairAcc<T> &acc, char *lds) {
+  const uint32_t chunk = (threadIdx.x & 3) * 16;
+  const int rd = (threadIdx.x & 3) * kQuadSlot + ((threadIdx.x & 63) >> 2) * 64;   // own record in a round's slot
+  // the system's constants in registers: the waits below are compiler
+  // barriers, across which loads through D would be repeated
+  const double rc2 = D.rc2;
+  double box[3], ibox[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { box[k] = D.box[k]; ibox[k] = D.inv_box[k]; }
+  const uint32_t lo0 = lo;
+  // list entries c .. c + kQuadUnroll - 1 of this lane, as loaded (past its
+  // count: from an address inside its list, replaced by use() with its own
+  // position)
+  auto entries = [&](int c, int (&ent)[kQuadUnroll]) {
+#pragma unroll
+    for (int j = 0; j < kQuadUnroll; ++j) {
+      const uint32_t o = c + j < cnt ? lo + (uint32_t)j * lstep : lo0;
+      ent[j] = E16 ? (int)__builtin_nontemporal_load((const uint16_t *)(nbrb + o))
+                   : __builtin_nontemporal_load((const int32_t *)(nbrb + o));
+    }
+    lo += (uint32_t)kQuadUnroll * lstep;
+  };
+  auto use = [&](int c, int (&ent)[kQuadUnroll]) {
+#pragma unroll
+    for (int j = 0; j < kQuadUnroll; ++j) ent[j] = c + j < cnt ? ent[j] : self << 1;
+  };
+  int ent[kQuadUnroll];
+  entries(0, ent);
+  use(0, ent);
+  for (int c = 0; c < rounds * kQuadUnroll; c += kQuadUnroll) {
+    // the last round's LDS reads are complete before its slots are refilled
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    // each lane's record offset to its whole quad, plus the lane's chunk
+    // (DPP adds, with every lane of the quad active)
+    uint32_t o[kQuadUnroll][4];
+#pragma unroll
+    for (int j = 0; j < kQuadUnroll; ++j) {
+      const uint32_t roff = ((uint32_t)ent[j] >> 1) << 6;
+      o[j][0] = (uint32_t)quad_bcast<0>((int)roff) + chunk;
+      o[j][1] = (uint32_t)quad_bcast<1>((int)roff) + chunk;
+      o[j][2] = (uint32_t)quad_bcast<2>((int)roff) + chunk;
+      o[j][3] = (uint32_t)quad_bcast<3>((int)roff) + chunk;
+    }
+    // a neighbour needs the record's first 48 bytes: the quad's fourth lane
+    // loads nothing
+    if (chunk < 48) {
+#pragma unroll
+      for (int j = 0; j < kQuadUnroll; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) lds_chunk(recb + o[j][t], lds + (j * 4 + t) * kQuadSlot);
+    }
+    // the next round's entries are requested after this round's records (a
+    // compiler barrier keeps that order), so that the wait below, which
+    // leaves the last kQuadUnroll loads in flight, covers the records only;
+    // the loads write LDS behind the compiler's back, hence the explicit wait
+    int nxt[kQuadUnroll];
+    asm volatile("" ::: "memory");
+    entries(c + kQuadUnroll, nxt);
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kQuadUnroll) : "memory");
+#pragma unroll
+    for (int j = 0; j < kQuadUnroll; ++j) {
+      const double *r = (const double *)(lds + j * 4 * kQuadSlot + rd);
+      double xj[3], dx[3];
+      T uj[3];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) { xj[k] = r[k]; uj[k] = rec_u<T>(r, k); }
+      double r2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const double raw = xi[k] - xj[k];
+        if (LASTP || k < DIM - 1) dx[k] = __builtin_fma(-box[k], __builtin_rint(raw * ibox[k]), raw);
+        else dx[k] = raw;
+        r2 = add_sq_exact(r2, dx[k]);
+      }
+      pair_term<DIM, T, 0>(R, ent[j] & 1, c + j < cnt && r2 < rc2, dx, r2, ui, uj, acc);
+    }
+#pragma unroll
+    for (int j = 0; j < kQuadUnroll; ++j) ent[j] = nxt[j];
+    use(c + kQuadUnroll, ent);
+  }
+}
+
 // Pair pass of the atom at sorted position p over its full list (entries
 // hold sorted positions), neighbours read from the packed records; same
 // arithmetic as pair_atom.  Lane q0 of qstep lanes takes entries q0,
-// q0 + qstep, ...
-template <int DIM, typename T, int EXT = 0, bool E16 = false>
+// q0 + qstep, ...  With quad_lds (four lanes per atom, LJ-only terms) the
+// quad gather above, in that wavefront's LDS area.
+template <int DIM, typename T, int EXT = 0, bool E16 = false, bool QUAD = false>
 __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
                                               const double xi[3], const T ui[3], int ti,
                                               PairAcc<T> &acc, int q0 = 0, int qstep = 1,
-                                              const T *wi = nullptr) {
+                                              const T *wi = nullptr, char *quad_lds = nullptr) {
+  static_assert(!QUAD || EXT == 0, "the quad gather serves the LJ-only pass");
   static_assert(!E16 || EXT == 0, "16-bit lists serve the LJ-only pass");
   static_assert(kRecDoubles == 8, "records are 64 bytes");
   const int64_t off = D.off;
@@ -944,6 +1063,15 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
   const char *recwb = (EXT & EXT_EIG) != 0 ? (const char *)(A.recw + off * 4) : nullptr;
   LJRow<T> R;
   R.load(D, ti);
+  if constexpr (QUAD) {
+    // (qstep == 4) every lane of the quad runs the rounds of its first lane
+    const int rounds = ((nn + 3) / 4 + kQuadUnroll - 1) / kQuadUnroll;
+    if (D.periodic[DIM - 1])
+      pair_loop_quad<DIM, T, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds);
+    else
+      pair_loop_quad<DIM, T, false, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds);
+    return;
+  }
   if (D.periodic[DIM - 1])
     pair_loop_rec<DIM, T, EXT, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
   else

@@ -92,6 +92,9 @@ struct GridPlan {
 };
 
 size_t grid_scal_bytes();
+// Allow the pair kernels with the quad gather their dynamic LDS (up to
+// 1024-thread workgroups; once per schedule, outside any graph capture).
+hipError_t grid_allow_lds();
 
 // One full step (or an evaluation when compute_only) of the grid scheduler.
 // Enqueues several kernels on `stream`; safe to capture in a HIP graph (no

@@ -693,6 +693,7 @@ hd_status build_schedule(hd_ctx *ctx) {
                                   hdk::small_group_bytes(prec, G.dim, G.nmax, G.maxnb, G.cellmax)));
     }
   }
+  HIPCHK(hdk::grid_allow_lds());
   // grid plans (with the one-workgroup kernel for the large systems, the
   // models with tip bonds or a general bias still take the grid)
   std::vector<int> grid_big;
