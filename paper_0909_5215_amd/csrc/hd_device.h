@@ -926,14 +926,15 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
 // different cache lines each.  Here the quad of an atom fetches the records
 // of its four lanes' neighbours one after the other, lane s bringing bytes
 // 16s..16s+15 of the record straight into LDS, so that each load touches one
-// line per quad (about 8 times fewer vector-L1 lookups per pair); every lane
-// then reads its own neighbour (x and u, the record's first 36 or 48 bytes)
-// from LDS.  The next round's list entries are requested behind the records,
-// so that their memory latency overlaps the round's arithmetic.  The LDS slot
-// of a load is 1024 + 16 bytes per wavefront: with that stride the 16 lanes
-// served together by an LDS read take 16 different bank groups.  Two
-// neighbours per lane per round: larger rounds take more LDS than they gain
-// (the LDS then bounds the workgroups per CU).
+// line per quad (about half the vector-L1 lookups per pair); every lane then
+// reads its own neighbour (x and u, the record's first 36 or 48 bytes) from
+// LDS.  The next round's list entries are requested behind the records, so
+// that their memory latency overlaps the round's arithmetic.  The LDS slot of
+// a load is 1024 + 16 bytes per wavefront: with that stride the 16 lanes
+// served together by an LDS read take 16 different bank groups.  The pair
+// terms are any but the eigenvalue bias's (which also reads the neighbour's
+// mode record).  Two neighbours per lane per round: larger rounds take more
+// LDS than they gain (the LDS then bounds the workgroups per CU).
 constexpr int kQuadUnroll = 2;               // neighbours per lane per round
 constexpr int kQuadSlot = 1040;              // bytes per load in a wavefront's LDS area
 constexpr int kQuadWaveBytes = kQuadUnroll * 4 * kQuadSlot;
@@ -952,7 +953,7 @@ __device__ __forceinline__ void lds_chunk(const char *__restrict__ src, char *sl
 // rounds the quad's (every lane of the quad runs them, so that the quad's
 // loads are complete; entries past a lane's count are its own position,
 // masked).  lds is this wavefront's kQuadWaveBytes area (wave-uniform).
-template <int DIM, typename T, bool LASTP, bool E16>
+template <int DIM, typename T, int EXT, bool LASTP, bool E16>
 __device__ __forceinline__ void pair_loop_quad(const SysDesc &D, const LJRow<T> &R, const char *__restrict__ recb,
                                                const char *__restrict__ nbrb, uint32_t lo, uint32_t lstep, int cnt,
                                                int rounds, int self, const double xi[3], const T ui[3],
@@ -1030,7 +1031,7 @@ __device__ __forceinline__ void pair_loop_quad(const SysDesc &D, const LJRow<T> 
         else dx[k] = raw;
         r2 = add_sq_exact(r2, dx[k]);
       }
-      pair_term<DIM, T, 0>(R, ent[j] & 1, c + j < cnt && r2 < rc2, dx, r2, ui, uj, acc);
+      pair_term<DIM, T, EXT>(R, ent[j] & 1, c + j < cnt && r2 < rc2, dx, r2, ui, uj, acc);
     }
 #pragma unroll
     for (int j = 0; j < kQuadUnroll; ++j) ent[j] = nxt[j];
@@ -1041,14 +1042,14 @@ __device__ __forceinline__ void pair_loop_quad(const SysDesc &D, const LJRow<T> 
 // Pair pass of the atom at sorted position p over its full list (entries
 // hold sorted positions), neighbours read from the packed records; same
 // arithmetic as pair_atom.  Lane q0 of qstep lanes takes entries q0,
-// q0 + qstep, ...  With quad_lds (four lanes per atom, LJ-only terms) the
-// quad gather above, in that wavefront's LDS area.
+// q0 + qstep, ...  With QUAD (four lanes per atom, no eigenvalue terms) the
+// quad gather above, in the wavefront's LDS area quad_lds.
 template <int DIM, typename T, int EXT = 0, bool E16 = false, bool QUAD = false>
 __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
                                               const double xi[3], const T ui[3], int ti,
                                               PairAcc<T> &acc, int q0 = 0, int qstep = 1,
                                               const T *wi = nullptr, char *quad_lds = nullptr) {
-  static_assert(!QUAD || EXT == 0, "the quad gather serves the LJ-only pass");
+  static_assert(!QUAD || (EXT & EXT_EIG) == 0, "the quad gather reads no mode records");
   static_assert(!E16 || EXT == 0, "16-bit lists serve the LJ-only pass");
   static_assert(kRecDoubles == 8, "records are 64 bytes");
   const int64_t off = D.off;
@@ -1067,9 +1068,9 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
     // (qstep == 4) every lane of the quad runs the rounds of its first lane
     const int rounds = ((nn + 3) / 4 + kQuadUnroll - 1) / kQuadUnroll;
     if (D.periodic[DIM - 1])
-      pair_loop_quad<DIM, T, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds);
+      pair_loop_quad<DIM, T, EXT, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds);
     else
-      pair_loop_quad<DIM, T, false, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds);
+      pair_loop_quad<DIM, T, EXT, false, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds);
     return;
   }
   if (D.periodic[DIM - 1])
