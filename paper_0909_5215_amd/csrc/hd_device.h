@@ -931,9 +931,9 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
 // LDS.  The next round's list entries are requested behind the records, so
 // that their memory latency overlaps the round's arithmetic.  The LDS slot of
 // a load is 1024 + 16 bytes per wavefront: with that stride the 16 lanes
-// served together by an LDS read take 16 different bank groups.  The pair
-// terms are any but the eigenvalue bias's (which also reads the neighbour's
-// mode record).  Two neighbours per lane per round: larger rounds take more
+// served together by an LDS read take 16 different bank groups.  With the
+// eigenvalue bias each lane also loads its neighbour's mode record itself.
+// Two neighbours per lane per round: larger rounds take more
 // LDS than they gain (the LDS then bounds the workgroups per CU).
 constexpr int kQuadUnroll = 2;               // neighbours per lane per round
 constexpr int kQuadSlot = 1040;              // bytes per load in a wavefront's LDS area
@@ -957,7 +957,9 @@ template <int DIM, typename T, int EXT, bool LASTP, bool E16>
 __device__ __forceinline__ void pair_loop_quad(const SysDesc &D, const LJRow<T> &R, const char *__restrict__ recb,
                                                const char *__restrict__ nbrb, uint32_t lo, uint32_t lstep, int cnt,
                                                int rounds, int self, const double xi[3], const T ui[3],
-                                               PairAcc<T> &acc, char *lds) {
+                                               PairAcc<T> &acc, char *lds, const char *__restrict__ recwb = nullptr,
+                                               const T *wi = nullptr) {
+  constexpr bool EIG = (EXT & EXT_EIG) != 0;
   const uint32_t chunk = (threadIdx.x & 3) * 16;
   const int rd = (threadIdx.x & 3) * kQuadSlot + ((threadIdx.x & 63) >> 2) * 64;   // own record in a round's slot
   // the system's constants in registers: the waits below are compiler
@@ -1008,6 +1010,17 @@ __device__ __forceinline__ void pair_loop_quad(const SysDesc &D, const LJRow<T> 
 #pragma unroll
         for (int t = 0; t < 4; ++t) lds_chunk(recb + o[j][t], lds + (j * 4 + t) * kQuadSlot);
     }
+    // eigenvalue bias: each lane loads its neighbour's mode component itself
+    // (32-byte mode records beside the pair records)
+    T wj[kQuadUnroll][3];
+    if constexpr (EIG) {
+#pragma unroll
+      for (int j = 0; j < kQuadUnroll; ++j) {
+        const double *rw = (const double *)(recwb + (((uint32_t)ent[j] >> 1) << 5));
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) wj[j][k] = (T)rw[k];
+      }
+    }
     // the next round's entries are requested after this round's records (a
     // compiler barrier keeps that order), so that the wait below, which
     // leaves the last kQuadUnroll loads in flight, covers the records only;
@@ -1031,7 +1044,7 @@ __device__ __forceinline__ void pair_loop_quad(const SysDesc &D, const LJRow<T> 
         else dx[k] = raw;
         r2 = add_sq_exact(r2, dx[k]);
       }
-      pair_term<DIM, T, EXT>(R, ent[j] & 1, c + j < cnt && r2 < rc2, dx, r2, ui, uj, acc);
+      pair_term<DIM, T, EXT>(R, ent[j] & 1, c + j < cnt && r2 < rc2, dx, r2, ui, uj, acc, wi, EIG ? wj[j] : nullptr);
     }
 #pragma unroll
     for (int j = 0; j < kQuadUnroll; ++j) ent[j] = nxt[j];
@@ -1042,14 +1055,13 @@ __device__ __forceinline__ void pair_loop_quad(const SysDesc &D, const LJRow<T> 
 // Pair pass of the atom at sorted position p over its full list (entries
 // hold sorted positions), neighbours read from the packed records; same
 // arithmetic as pair_atom.  Lane q0 of qstep lanes takes entries q0,
-// q0 + qstep, ...  With QUAD (four lanes per atom, no eigenvalue terms) the
-// quad gather above, in the wavefront's LDS area quad_lds.
+// q0 + qstep, ...  With QUAD (four lanes per atom) the quad gather above, in
+// the wavefront's LDS area quad_lds.
 template <int DIM, typename T, int EXT = 0, bool E16 = false, bool QUAD = false>
 __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A, int p,
                                               const double xi[3], const T ui[3], int ti,
                                               PairAcc<T> &acc, int q0 = 0, int qstep = 1,
                                               const T *wi = nullptr, char *quad_lds = nullptr) {
-  static_assert(!QUAD || (EXT & EXT_EIG) == 0, "the quad gather reads no mode records");
   static_assert(!E16 || EXT == 0, "16-bit lists serve the LJ-only pass");
   static_assert(kRecDoubles == 8, "records are 64 bytes");
   const int64_t off = D.off;
@@ -1068,9 +1080,11 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
     // (qstep == 4) every lane of the quad runs the rounds of its first lane
     const int rounds = ((nn + 3) / 4 + kQuadUnroll - 1) / kQuadUnroll;
     if (D.periodic[DIM - 1])
-      pair_loop_quad<DIM, T, EXT, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds);
+      pair_loop_quad<DIM, T, EXT, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds,
+                                             recwb, wi);
     else
-      pair_loop_quad<DIM, T, EXT, false, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds);
+      pair_loop_quad<DIM, T, EXT, false, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds,
+                                              recwb, wi);
     return;
   }
   if (D.periodic[DIM - 1])

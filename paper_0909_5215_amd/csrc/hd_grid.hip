@@ -626,11 +626,11 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
   }
   PairAcc<T> acc;
   acc.init();
-  if constexpr (LPA == 4 && !EIG) {
+  if constexpr (LPA == 4) {
     // the quad gather, in this wavefront's share of the dynamic LDS
     extern __shared__ __attribute__((aligned(16))) char quad_area[];
     char *ql = quad_area + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kQuadWaveBytes;
-    if (valid) pair_atom_rec<DIM, T, EXT, E16, true>(D, A, p, xi, ui, tr & 1, acc, sub, LPA, nullptr, ql);
+    if (valid) pair_atom_rec<DIM, T, EXT, E16, true>(D, A, p, xi, ui, tr & 1, acc, sub, LPA, wi, ql);
   } else {
     if (valid) pair_atom_rec<DIM, T, EXT, E16>(D, A, p, xi, ui, tr & 1, acc, sub, LPA, wi);
   }
@@ -1012,11 +1012,14 @@ size_t grid_scal_bytes() { return sizeof(GridScal); }
 hipError_t grid_allow_lds() {
   // the largest quad-gather workgroup: 256 atoms, 1024 threads
   const int bytes = 16 * kQuadWaveBytes;
-  const void *fns[10] = {(const void *)kg_pairs<float, 4, 0, true>,  (const void *)kg_pairs<float, 4, 0, false>,
-                         (const void *)kg_pairs<float, 4, 1, false>, (const void *)kg_pairs<float, 4, 2, false>,
-                         (const void *)kg_pairs<float, 4, 3, false>, (const void *)kg_pairs<double, 4, 0, true>,
-                         (const void *)kg_pairs<double, 4, 0, false>, (const void *)kg_pairs<double, 4, 1, false>,
-                         (const void *)kg_pairs<double, 4, 2, false>, (const void *)kg_pairs<double, 4, 3, false>};
+  const void *fns[14] = {
+      (const void *)kg_pairs<float, 4, 0, true>,   (const void *)kg_pairs<float, 4, 0, false>,
+      (const void *)kg_pairs<float, 4, 1, false>,  (const void *)kg_pairs<float, 4, 2, false>,
+      (const void *)kg_pairs<float, 4, 3, false>,  (const void *)kg_pairs<float, 4, 4, false>,
+      (const void *)kg_pairs<float, 4, 5, false>,  (const void *)kg_pairs<double, 4, 0, true>,
+      (const void *)kg_pairs<double, 4, 0, false>, (const void *)kg_pairs<double, 4, 1, false>,
+      (const void *)kg_pairs<double, 4, 2, false>, (const void *)kg_pairs<double, 4, 3, false>,
+      (const void *)kg_pairs<double, 4, 4, false>, (const void *)kg_pairs<double, 4, 5, false>};
   for (const void *f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -1060,11 +1063,10 @@ int launch_pairs_reduce(int prec, const SysDesc *descs, SysState *states, const 
   const int nt = P.ntiles, B = P.block, co = compute_only ? 1 : 0;
   GridScal *gs = (GridScal *)P.gscal;
   const int lpa = B <= 256 ? 4 : (B <= 512 ? 2 : 1);
-  // dynamic LDS of the quad gather (four lanes per atom, no eigenvalue terms)
+  // dynamic LDS of the quad gather (four lanes per atom)
   const size_t qb = (size_t)(4 * B / 64) * kQuadWaveBytes;
 #define HD_PAIRS(TT, L, BB)                                                                      \
-  hipLaunchKernelGGL((kg_pairs<TT, L, BB>), dim3(nt), dim3(L * B), (L == 4 && (BB & EXT_EIG) == 0) ? qb : 0, \
-                     stream, descs, A, P.tiles, nt)
+  hipLaunchKernelGGL((kg_pairs<TT, L, BB>), dim3(nt), dim3(L * B), L == 4 ? qb : 0, stream, descs, A, P.tiles, nt)
 #define HD_PAIRS16(TT, L)                                                                        \
   hipLaunchKernelGGL((kg_pairs<TT, L, 0, true>), dim3(nt), dim3(L * B), L == 4 ? qb : 0, stream, descs, A, \
                      P.tiles, nt)
