@@ -48,19 +48,19 @@ CSRC = os.path.join(ROOT, "paper_0909_5215_amd", "csrc")
 # longer describes the kernel and the traffic is reported as null.
 HBM_COUNTERS = {
     ("C2", "k_small<float, 2, 0, 512, false>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "08768e8f2cde25f3",
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "927a0ac8e7e9f253",
         "fetch_kib": 1010.2, "fetch_scale": 2.0, "write_kib": 2896.8, "write_scale": 1.0,
     },
     ("C2", "k_small<float, 2, 0, 512, true>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "08768e8f2cde25f3",
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "927a0ac8e7e9f253",
         "fetch_kib": 1005.8, "fetch_scale": 2.0, "write_kib": 2449.7, "write_scale": 1.0,
     },
     # the grid step as a whole: every kg_* launch of the float32 run (the
     # fused kick-drift, the rebuild launches, pairs, reduce) summed and
     # divided by its steps (per_step: scaled by the steps one launch covers)
     ("C5b", "grid step (kg_* kernels, timed as a whole)"): {
-        "src": ("hd_grid.hip", "hd_device.h"), "sha": "e7425b334b7e8661",
-        "fetch_kib": 522342.8, "fetch_scale": 2.0, "write_kib": 403318.2, "write_scale": 1.0,
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "a4191cb5a0cb9be6",
+        "fetch_kib": 522391.6, "fetch_scale": 2.0, "write_kib": 403311.2, "write_scale": 1.0,
         "per_step": True,
     },
 }
@@ -73,15 +73,15 @@ HBM_COUNTERS = {
 VALU_ISSUE_PEAK_G = 256 * 2.4
 VALU_COUNTERS = {
     ("C2", "k_small<float, 2, 0, 512, false>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "08768e8f2cde25f3",
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "927a0ac8e7e9f253",
         "insts_valu": 912003885.6, "steps": 2000,
     },
     ("C2", "k_small<float, 2, 0, 512, true>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "08768e8f2cde25f3",
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "927a0ac8e7e9f253",
         "insts_valu": 882282002.6, "steps": 2000,
     },
     ("C5b", "grid step (kg_* kernels, timed as a whole)"): {
-        "src": ("hd_grid.hip", "hd_device.h"), "sha": "e7425b334b7e8661",
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "a4191cb5a0cb9be6",
         "insts_valu": 379104052.2, "steps": 1,
     },
 }
