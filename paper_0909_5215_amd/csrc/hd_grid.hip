@@ -476,7 +476,7 @@ __device__ int scan_row(const SysDesc &D, const Arrays &A, int p,
 
 template <int DIM, typename SubT>
 __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, int first, int count, int flag,
-                           SubT *sub_all, int *counts) {
+                           SubT *sub_all, int *counts, int *pre) {
   constexpr int S = DIM == 3 ? 9 : 3;        // stencil rows per atom
   constexpr int APB = kBuildThreads / S;     // atoms per block
   const int tid = threadIdx.x, la = tid / S, r = tid % S;
@@ -509,28 +509,46 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, int 
   }
   counts[tid] = cnt;
   __syncthreads();
-  if (!active) return;
-  int before = 0, total = 0;
+  // per atom (its first lane): where each row's entries start in its list,
+  // and how many entries the block writes for it (none when a row is crowded:
+  // the one-lane build below writes that atom's whole list)
+  constexpr int PS = S + 1;
+  int total = 0;
   bool over = false;
-  for (int q = 0; q < S; ++q) {
-    const int c = counts[la * S + q];
-    if (q < r) before += c;
-    total += c;
-    over = over || c > kRowCap;
+  if (active && r == 0) {
+    for (int q = 0; q < S; ++q) {
+      const int c = counts[la * S + q];
+      pre[la * PS + q] = total;
+      total += c;
+      over = over || c > kRowCap;
+    }
+    pre[la * PS + S] = over ? 0 : (total < D.maxnb ? total : D.maxnb);
   }
+  __syncthreads();
+  // The block writes its atoms' lists together: entry q of consecutive sorted
+  // positions is consecutive in memory, so thread (g, a) takes entries g,
+  // g + G, ... of atom a, and a wavefront writes runs of consecutive
+  // positions (one cache line per entry index) instead of one entry per line.
+  // Same entries in the same places as row-by-row writes.
   int32_t *list = A.nbr + D.nbr_off;
   const int n = D.n;
-  if (!over) {
-    if (D.list16) {
-      uint16_t *list16 = (uint16_t *)list;
-      for (int k = 0; k < cnt && before + k < D.maxnb; ++k)
-        list16[(int64_t)(before + k) * n + p] = (uint16_t)sub_all[k * kBuildThreads + tid];
-    } else {
-      for (int k = 0; k < cnt && before + k < D.maxnb; ++k)
-        list[(int64_t)(before + k) * n + p] = (int32_t)sub_all[k * kBuildThreads + tid];
+  {
+    const int nb = count < APB ? count : APB;
+    const int G = kBuildThreads / nb;
+    if (tid < G * nb) {
+      const int a = tid % nb, g = tid / nb;
+      const int *pa = pre + a * PS;
+      const int lim = pa[S];
+      int rr = 0;
+      for (int q = g; q < lim; q += G) {
+        while (rr + 1 < S && pa[rr + 1] <= q) ++rr;   // the row that holds entry q
+        const SubT e = sub_all[(q - pa[rr]) * kBuildThreads + a * S + rr];
+        if (D.list16) ((uint16_t *)list)[(int64_t)q * n + first + a] = (uint16_t)e;
+        else list[(int64_t)q * n + first + a] = (int32_t)e;
+      }
     }
   }
-  if (r != 0) return;
+  if (!active || r != 0) return;
   if (over) total = list_atom_g<DIM>(D, A, p);   // a crowded row: the one-lane build
   const int64_t a = off + i;
   A.nnb[off + p] = total < D.maxnb ? total : D.maxnb;
@@ -570,6 +588,7 @@ __global__ __launch_bounds__(kBuildThreads) __attribute__((amdgpu_waves_per_eu(5
   using SubT = typename std::conditional<E16, uint16_t, int32_t>::type;
   __shared__ SubT sub[kRowCap * kBuildThreads];
   __shared__ int counts[kBuildThreads];
+  __shared__ int pre[(kBuildThreads / 3) * 4];   // per atom: row starts and entries to write
   const int nrb = __hip_atomic_load(&A.rb_count[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int w = blockIdx.x; w < nrb * chunks; w += gridDim.x) {
     const int c = w / nrb;
@@ -580,8 +599,8 @@ __global__ __launch_bounds__(kBuildThreads) __attribute__((amdgpu_waves_per_eu(5
     if (first >= D.n) continue;   // the same for every thread of the workgroup
     const int count = D.n - first < apb ? D.n - first : apb;
     const int flag = A.rebuild_flag[s];
-    if (D.dim == 2) build_rows<2, SubT>(D, states[s], A, first, count, flag, sub, counts);
-    else build_rows<3, SubT>(D, states[s], A, first, count, flag, sub, counts);
+    if (D.dim == 2) build_rows<2, SubT>(D, states[s], A, first, count, flag, sub, counts, pre);
+    else build_rows<3, SubT>(D, states[s], A, first, count, flag, sub, counts, pre);
     __syncthreads();   // sub and counts are reused by the next item
   }
 }
