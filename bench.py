@@ -59,8 +59,8 @@ HBM_COUNTERS = {
     # fused kick-drift, the rebuild launches, pairs, reduce) summed and
     # divided by its steps (per_step: scaled by the steps one launch covers)
     ("C5b", "grid step (kg_* kernels, timed as a whole)"): {
-        "src": ("hd_grid.hip", "hd_device.h"), "sha": "a4191cb5a0cb9be6",
-        "fetch_kib": 522391.6, "fetch_scale": 2.0, "write_kib": 403311.2, "write_scale": 1.0,
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "828141ed6016af9d",
+        "fetch_kib": 520984.6, "fetch_scale": 2.0, "write_kib": 403215.1, "write_scale": 1.0,
         "per_step": True,
     },
 }
@@ -81,8 +81,8 @@ VALU_COUNTERS = {
         "insts_valu": 882282002.6, "steps": 2000,
     },
     ("C5b", "grid step (kg_* kernels, timed as a whole)"): {
-        "src": ("hd_grid.hip", "hd_device.h"), "sha": "a4191cb5a0cb9be6",
-        "insts_valu": 379104052.2, "steps": 1,
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "828141ed6016af9d",
+        "insts_valu": 379926193.7, "steps": 1,
     },
 }
 
