@@ -403,8 +403,9 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
 // parallelism, which a system whose skin expired needs to hide memory
 // latency.  A row with more than kRowCap entries sends its atom to
 // list_atom_g.  Blocks of kBuildThreads threads, kBuildThreads / 9 atoms
-// each (3D).  The sub-lists take 16-bit entries for
-// systems with 16-bit lists: half the LDS, twice the workgroups per CU.
+// each (3D), lanes ordered atoms-fastest within a row.  The sub-lists take
+// 16-bit entries for systems with 16-bit lists: half the LDS, twice the
+// workgroups per CU.
 constexpr int kBuildThreads = 256;
 constexpr int kRowCap = 48;
 
@@ -479,8 +480,11 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, int 
                            SubT *sub_all, int *counts, int *pre) {
   constexpr int S = DIM == 3 ? 9 : 3;        // stencil rows per atom
   constexpr int APB = kBuildThreads / S;     // atoms per block
-  const int tid = threadIdx.x, la = tid / S, r = tid % S;
-  const bool active = la < APB && la < count;
+  // lane (row r, atom la), atoms fastest: a quad of lanes scans one stencil
+  // row for four consecutive positions, which share a cell, so its candidate
+  // loads hit the same cache lines (the vector L1 looks lines up per quad)
+  const int tid = threadIdx.x, r = tid / APB, la = tid % APB;
+  const bool active = r < S && la < count;
   const int64_t off = D.off, N = A.ntot;
   const int p = first + la;
   int i = 0, ri = 0;
@@ -517,7 +521,7 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, int 
   bool over = false;
   if (active && r == 0) {
     for (int q = 0; q < S; ++q) {
-      const int c = counts[la * S + q];
+      const int c = counts[q * APB + la];
       pre[la * PS + q] = total;
       total += c;
       over = over || c > kRowCap;
@@ -542,7 +546,7 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, int 
       int rr = 0;
       for (int q = g; q < lim; q += G) {
         while (rr + 1 < S && pa[rr + 1] <= q) ++rr;   // the row that holds entry q
-        const SubT e = sub_all[(q - pa[rr]) * kBuildThreads + a * S + rr];
+        const SubT e = sub_all[(q - pa[rr]) * kBuildThreads + rr * APB + a];
         if (D.list16) ((uint16_t *)list)[(int64_t)q * n + first + a] = (uint16_t)e;
         else list[(int64_t)q * n + first + a] = (int32_t)e;
       }
