@@ -48,7 +48,8 @@ struct SysDesc {
   double lo[3], inv_h[3];
   int64_t cell_off, cstart_off;
   // neighbour list: entry (j << 1 | type_j) of slot k of atom i at
-  // nbr[nbr_off + k*n + i]
+  // nbr[nbr_off + k*n + i]; grid plans (i the sorted position) at
+  // nbr[nbr_off + grid_list_index(k, n, i)], below
   int64_t nbr_off;
   int32_t maxnb, pad0;
   double XR0[3];
@@ -844,23 +845,41 @@ __device__ __forceinline__ double pair_disp_l(const SysDesc &D, const double xi[
   return r2;
 }
 
+// Grid-plan neighbour lists: the entries of a sorted position come in
+// blocks of four consecutive slots, block b of position i in the four entries
+// from (b n + i) 4, so that the four lanes of an atom's quad (slots s, s + 4,
+// ... for lane s) read one contiguous piece per load, and a wavefront's
+// lanes (16 consecutive positions) one contiguous run.  Capacity: the
+// per-system region holds roundup4(maxnb) n entries.
+__host__ __device__ inline int64_t grid_list_index(int64_t k, int64_t n, int64_t i) {
+  return ((k >> 2) * n + i) * 4 + (k & 3);
+}
+// Byte offsets of a sorted position's grid-list entries.
+struct ListAddr {
+  uint32_t base, row;   // the position's first entry; one block row (4 n entries)
+  uint32_t esz;         // bytes per entry
+  __device__ __forceinline__ uint32_t at(int k) const {
+    return ((uint32_t)k >> 2) * row + base + ((uint32_t)k & 3u) * esz;
+  }
+};
+
 // List entries gathered together in the bonded pair loop.
 constexpr int kGatherBlock = 4;
 
-// The neighbour loop of pair_atom_rec: list entries walked by a 32-bit byte
-// offset advancing by a fixed stride, records addressed by 32-bit offsets
-// from the system's base (uniform), so that both loads take a scalar base.
+// The neighbour loop of pair_atom_rec (one or two lanes per atom): lane q0 of
+// qstep takes entries q0, q0 + qstep, ... of the grid list, addressed by
+// 32-bit byte offsets like the records (offsets from the system's uniform
+// bases, so that both loads take a scalar base).
 template <int DIM, typename T, int EXT, bool LASTP, bool E16 = false>
 __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &R, const char *__restrict__ recb,
-                                              const char *__restrict__ nbrb, uint32_t lo, uint32_t lstep,
+                                              const char *__restrict__ nbrb, const ListAddr la, int q0, int qstep,
                                               int cnt, const double xi[3], const T ui[3], PairAcc<T> &acc,
                                               const char *__restrict__ recwb = nullptr, const T *wi = nullptr) {
   if constexpr ((EXT & EXT_EIG) != 0) {
     // eigenvalue bias: the neighbour's mode estimate comes from its 32-byte
     // mode record beside the pair record
     for (int c = 0; c < cnt; ++c) {
-      const int ent = __builtin_nontemporal_load((const int32_t *)(nbrb + lo));
-      lo += lstep;
+      const int ent = __builtin_nontemporal_load((const int32_t *)(nbrb + la.at(q0 + c * qstep)));
       const uint32_t pj = (uint32_t)ent >> 1;
       const double *r = (const double *)(recb + (pj << 6));
       const double *rw = (const double *)(recwb + (pj << 5));
@@ -881,10 +900,9 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
       int ent[kGatherBlock];
 #pragma unroll
       for (int u4 = 0; u4 < kGatherBlock; ++u4) {
-        const uint32_t o = lo + (c0 + u4 < cnt ? (uint32_t)u4 * lstep : 0u);
+        const uint32_t o = la.at(q0 + (c0 + u4 < cnt ? c0 + u4 : c0) * qstep);
         ent[u4] = __builtin_nontemporal_load((const int32_t *)(nbrb + o));
       }
-      lo += (uint32_t)kGatherBlock * lstep;
       double xj[kGatherBlock][3];
       T uj[kGatherBlock][3];
 #pragma unroll
@@ -907,9 +925,9 @@ __device__ __forceinline__ void pair_loop_rec(const SysDesc &D, const LJRow<T> &
     for (int c = 0; c < cnt; ++c) {
       // the list is read once per step: a streaming load, so that it does not
       // evict the records the neighbouring atoms share
-      const int ent = E16 ? (int)__builtin_nontemporal_load((const uint16_t *)(nbrb + lo))
-                          : __builtin_nontemporal_load((const int32_t *)(nbrb + lo));
-      lo += lstep;
+      const uint32_t o = la.at(q0 + c * qstep);
+      const int ent = E16 ? (int)__builtin_nontemporal_load((const uint16_t *)(nbrb + o))
+                          : __builtin_nontemporal_load((const int32_t *)(nbrb + o));
       const double *r = (const double *)(recb + (((uint32_t)ent >> 1) << 6));
       double xj[3], dx[3];
       T uj[3];
@@ -1071,13 +1089,14 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
   const int nn = A.nnb[off + p];
   const int cnt = nn > q0 ? (nn - q0 + qstep - 1) / qstep : 0;
   constexpr uint32_t esz = E16 ? 2u : 4u;   // bytes per list entry
-  const uint32_t lo = ((uint32_t)q0 * (uint32_t)n + (uint32_t)p) * esz;
-  const uint32_t lstep = (uint32_t)qstep * (uint32_t)n * esz;
+  const ListAddr la{(uint32_t)p * 4u * esz, (uint32_t)n * 4u * esz, esz};
   const char *recwb = (EXT & EXT_EIG) != 0 ? (const char *)(A.recw + off * 4) : nullptr;
   LJRow<T> R;
   R.load(D, ti);
   if constexpr (QUAD) {
-    // (qstep == 4) every lane of the quad runs the rounds of its first lane
+    // (qstep == 4) every lane of the quad runs the rounds of its first lane;
+    // lane q0's entries q0 + 4c are one block row apart
+    const uint32_t lo = la.at(q0), lstep = la.row;
     const int rounds = ((nn + 3) / 4 + kQuadUnroll - 1) / kQuadUnroll;
     if (D.periodic[DIM - 1])
       pair_loop_quad<DIM, T, EXT, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, rounds, p, xi, ui, acc, quad_lds,
@@ -1088,9 +1107,9 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
     return;
   }
   if (D.periodic[DIM - 1])
-    pair_loop_rec<DIM, T, EXT, true, E16>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
+    pair_loop_rec<DIM, T, EXT, true, E16>(D, R, recb, nbrb, la, q0, qstep, cnt, xi, ui, acc, recwb, wi);
   else
-    pair_loop_rec<DIM, T, EXT, false, E16>(D, R, recb, nbrb, lo, lstep, cnt, xi, ui, acc, recwb, wi);
+    pair_loop_rec<DIM, T, EXT, false, E16>(D, R, recb, nbrb, la, q0, qstep, cnt, xi, ui, acc, recwb, wi);
 }
 
 // ---------------------------------------------------------------------------

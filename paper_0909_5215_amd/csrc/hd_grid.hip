@@ -385,8 +385,8 @@ __device__ int list_atom_g(const SysDesc &D, const Arrays &A, int p) {
             if (r2 < D.rl2) {
               if (cnt < D.maxnb) {
                 const int e = (pp << 1) | (trj[u] & 1);
-                if (D.list16) ((uint16_t *)list)[(int64_t)cnt * n + p] = (uint16_t)e;
-                else list[(int64_t)cnt * n + p] = e;
+                if (D.list16) ((uint16_t *)list)[grid_list_index(cnt, n, p)] = (uint16_t)e;
+                else list[grid_list_index(cnt, n, p)] = e;
               }
               ++cnt;
             }
@@ -530,10 +530,10 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, int 
   }
   __syncthreads();
   // The block writes its atoms' lists together: entry q of consecutive sorted
-  // positions is consecutive in memory, so thread (g, a) takes entries g,
-  // g + G, ... of atom a, and a wavefront writes runs of consecutive
-  // positions (one cache line per entry index) instead of one entry per line.
-  // Same entries in the same places as row-by-row writes.
+  // positions is four entries apart in memory, so thread (g, a) takes
+  // entries g, g + G, ... of atom a, and a wavefront writes short-strided
+  // runs over consecutive positions instead of one entry per line.  Same
+  // entries in the same places as row-by-row writes.
   int32_t *list = A.nbr + D.nbr_off;
   const int n = D.n;
   {
@@ -547,8 +547,8 @@ __device__ void build_rows(const SysDesc &D, SysState &st, const Arrays &A, int 
       for (int q = g; q < lim; q += G) {
         while (rr + 1 < S && pa[rr + 1] <= q) ++rr;   // the row that holds entry q
         const SubT e = sub_all[(q - pa[rr]) * kBuildThreads + rr * APB + a];
-        if (D.list16) ((uint16_t *)list)[(int64_t)q * n + first + a] = (uint16_t)e;
-        else list[(int64_t)q * n + first + a] = (int32_t)e;
+        if (D.list16) ((uint16_t *)list)[grid_list_index(q, n, first + a)] = (uint16_t)e;
+        else list[grid_list_index(q, n, first + a)] = (int32_t)e;
       }
     }
   }

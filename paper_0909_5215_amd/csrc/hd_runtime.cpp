@@ -1079,7 +1079,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
     off += h.n;
     cell_off += D.ncell;
     cstart_off += D.ncell + 1;
-    nbr_off += (int64_t)D.maxnb * h.n;
+    nbr_off += (int64_t)((D.maxnb + 3) / 4 * 4) * h.n;   // grid lists come in blocks of four slots
     max_dim = std::max(max_dim, h.dim);
   }
   const int64_t N = off;
@@ -2367,7 +2367,7 @@ hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int
   if (check_sys(ctx, sys) != HD_OK || !n_pairs || (cap > 0 && !ij)) return fail(ctx, HD_E_ARG, "bad arguments");
   const SysHost &s = ctx->sys[sys];
   const SysDesc &D = ctx->h_desc[sys];
-  std::vector<int32_t> nnb(s.n), list((size_t)D.maxnb * s.n), cat(s.n);
+  std::vector<int32_t> nnb(s.n), list((size_t)(D.maxnb + 3) / 4 * 4 * s.n), cat(s.n);
   HIPCHK(hipMemcpyAsync(nnb.data(), ctx->A.nnb + D.off, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, ctx->stream));
   if (D.list16 && ctx->sorted_lists[sys] && !s.lists_wide) {
     // 16-bit entries (grid plans of small LJ-only systems)
@@ -2389,7 +2389,7 @@ hd_status hd_debug_pairs(hd_ctx *ctx, int32_t sys, int32_t *ij, int64_t cap, int
   std::vector<std::pair<int32_t, int32_t>> pr;
   for (int r = 0; r < s.n; ++r)
     for (int q = 0; q < nnb[r]; ++q) {
-      const int e = list[(size_t)q * s.n + r] >> 1;
+      const int e = list[sorted ? (size_t)hdk::grid_list_index(q, s.n, r) : (size_t)q * s.n + r] >> 1;
       const int i = sorted ? cat[r] : r, j = sorted ? cat[e] : e;
       if (j == i) continue;
       pr.emplace_back(std::min(i, j), std::max(i, j));
