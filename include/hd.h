@@ -67,7 +67,7 @@ typedef enum {
  * scalars and the clock are float64 in both. */
 typedef enum {
     HD_FP64 = 0,   /* float64 pair arithmetic */
-    HD_FP32C = 1   /* float32 pair arithmetic with compensated per-atom sums;
+    HD_FP32C = 1   /* float32 pair arithmetic, per-atom sums in float64;
                       displacements and the cutoff decision in float64; the
                       Langevin normals formed in float32 from the same Philox
                       words (relative error ~1e-7) */

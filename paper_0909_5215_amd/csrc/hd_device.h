@@ -513,19 +513,16 @@ __device__ __forceinline__ void eval_scalars(const SysDesc &D, const double *sum
 //
 // FP64: everything in double.  FP32C: the displacement and the cutoff test
 // are float64 (so the interacting set is decided exactly as in float64); the
-// pair arithmetic is float32 and the per-atom sums are compensated (Kahan
-// two-term sums), converted to float64 at the end.
+// pair arithmetic is float32, and each atom's sums of the float32 terms are
+// float64.  On gfx950 a float64 add issues at the rate of a float32 one, so
+// the float64 sum costs two operations per term (convert, add) where a
+// compensated float32 sum costs four, and is the more accurate of the two.
 
-struct Comp {  // Kahan compensated float sum: s - c is the running total
-  float s, c;
-  __device__ __forceinline__ void init() { s = 0.f; c = 0.f; }
-  __device__ __forceinline__ void add(float x) {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-  }
-  __device__ __forceinline__ double get() const { return (double)s - (double)c; }
+struct Sum64 {  // float32 terms summed in float64
+  double s;
+  __device__ __forceinline__ void init() { s = 0.0; }
+  __device__ __forceinline__ void add(float x) { s += (double)x; }
+  __device__ __forceinline__ double get() const { return s; }
 };
 
 template <typename T> struct PairAcc;
@@ -541,7 +538,7 @@ template <> struct PairAcc<double> {
 };
 
 template <> struct PairAcc<float> {
-  Comp F[3], H[3], X[3], W[3], e;
+  Sum64 F[3], H[3], X[3], W[3], e;
   __device__ __forceinline__ void init() {
     for (int k = 0; k < 3; ++k) { F[k].init(); H[k].init(); X[k].init(); W[k].init(); }
     e.init();

@@ -10,7 +10,7 @@ struct FireSys;   // a listed system's FIRE state (below)
 
 // One workgroup of `block` threads (256, 512 or 1024) per listed system, all
 // of dimension `dim`; nsteps BAOAB steps (mode 1: evaluate only, 1024
-// threads).  prec 0 = float64, 1 = float32 compensated.
+// threads).  prec 0 = float64, 1 = float32 pair terms summed in float64.
 hipError_t launch_batched(int prec, int dim, const SysDesc *descs, SysState *states, const Arrays &A,
                           const int32_t *sys_list, int nsys, int block, int64_t nsteps, int mode,
                           hipStream_t stream);

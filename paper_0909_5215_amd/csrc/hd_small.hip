@@ -503,7 +503,7 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
         constexpr bool LP = decltype(last_periodic)::value;
         constexpr bool WE = decltype(with_energy)::value;
         if constexpr (HALF) {
-          // half list: the pair's vectors go to i (compensated, registers) and,
+          // half list: the pair's vectors go to i (float64 sums, registers) and,
           // negated, to j (fixed-point LDS atomics: each float32 term rounded
           // once to a multiple of 2^-32, then summed exactly, so the j side's
           // total does not depend on the order of the atomics).  The next

@@ -1,6 +1,6 @@
 """Parity at the workloads' full sizes, in the launch configuration the
-benchmark times (batched scheduler, float32 pair arithmetic with compensated
-sums).  The oracle evaluates sampled systems of each batch in full; every
+benchmark times (batched scheduler, float32 pair arithmetic with float64
+per-atom sums).  The oracle evaluates sampled systems of each batch in full; every
 system's scalars must be finite.
 
 Tolerances as in test_gpu_parity: relative L2 force error <= 1e-5 per system,
