@@ -286,7 +286,7 @@ hd_status hd_finalize(hd_ctx *ctx);
  * hd_set_state revive it.  The energies read after the call are those of
  * the last step; the LDS-resident kernel evaluates the pair energy on that
  * step only, so a system frozen earlier within a launch reports a pair
- * energy and per-atom energies of zero for its last step: its e_pot is the
+ * energy of zero for its last step: its e_pot is the
  * drive energy alone and stays finite (test the flags, not isfinite(e_pot)).
  * A system frozen by an evaluation (hd_finalize, hd_compute) keeps that
  * evaluation's energies and its step count.  Returns HD_E_UNSTABLE when the
@@ -446,7 +446,7 @@ hd_status hd_quench(hd_ctx *ctx, const int32_t *systems, int32_t count, double f
  * codes as hd_quench, but the FIRE state, the system list and the reduction
  * partials live in a static device array of 1 MiB that each device holds
  * for the life of the process, and the read-out arrays (LJ and bias forces,
- * H u, per-atom energies) are evaluated again at the restored positions
+ * H u) are evaluated again at the restored positions
  * instead of being saved.  It needs 4 count and 64 count bytes, each
  * rounded up to a multiple of 256, plus 32 count ceil(n_max / 2048) bytes,
  * n_max the largest listed system; HD_E_ARG (with the sizes in the message)

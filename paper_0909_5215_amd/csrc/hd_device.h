@@ -101,7 +101,7 @@ struct Arrays {
   int32_t rec_f32, pad_rec;               // pair records in the float32 layout (below)
   double *x, *v, *rO, *xb, *cofs, *ftot;  // [3][ntot]
   double *flj, *hu, *fb;                  // [3][ntot]
-  double *eatom;                          // [ntot]
+  float *flj_f, *hu_f;                    // [3][ntot] float32 runs' grid pair sums, read by the grid kick
   void *u;                                // [3][ntot] float or double
   uint8_t *tr;                            // type | role << 1
   int32_t *nbr, *nnb;

@@ -704,12 +704,17 @@ __device__ void pairs_tile(const SysDesc &D, const Arrays &A, const Tile &t, int
   static_assert(LPA == 1 || LPA == 2 || LPA == 4, "one, two or four lanes per atom");
   if (valid && sub == 0) {
     const int64_t a = D.off + A.cell_atoms[D.off + p];
+    // float32 runs hand the kick float32 sums (rounded once, from float64)
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      A.flj[k * N + a] = F[k];
-      A.hu[k * N + a] = H[k];
+      if constexpr (sizeof(T) == 8) {
+        A.flj[k * N + a] = F[k];
+        A.hu[k * N + a] = H[k];
+      } else {
+        A.flj_f[k * N + a] = (float)F[k];
+        A.hu_f[k * N + a] = (float)H[k];
+      }
     }
-    A.eatom[a] = e;
     sums[0] = e;
     double f2 = 0.0;
 #pragma unroll
@@ -888,7 +893,7 @@ __global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ des
 // take the rigid body's velocity), and the eigenvalue variable's mode
 // rotation.  store: write the forces and the velocity (a step that closes a
 // call, or an evaluation); the fused kick-drift keeps them in registers.
-template <int DIM>
+template <int DIM, typename T>
 __device__ __forceinline__ void kick_atom(const SysDesc &D, const GridScal &G, const Arrays &A, int64_t a,
                                           int role, bool compute_only, bool store, double (&ft)[3],
                                           double (&vn)[3], double (&qn)[3]) {
@@ -896,7 +901,9 @@ __device__ __forceinline__ void kick_atom(const SysDesc &D, const GridScal &G, c
   const int64_t N = A.ntot;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    double f = A.flj[k * N + a], h = A.hu[k * N + a], fb = 0.0;
+    double f, h, fb = 0.0;
+    if constexpr (sizeof(T) == 8) { f = A.flj[k * N + a]; h = A.hu[k * N + a]; }
+    else { f = A.flj_f[k * N + a]; h = A.hu_f[k * N + a]; }
     if (role != ROLE_FIXED) {
       if (role == ROLE_RIGID) { f += S.Fd[k] * D.inv_nR; h += S.hud[k]; }
       if (D.gen_bias) {
@@ -931,6 +938,7 @@ __device__ __forceinline__ void kick_atom(const SysDesc &D, const GridScal &G, c
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ descs, Arrays A,
                                                 const Tile *__restrict__ tiles, int ntiles,
                                                 const GridScal *__restrict__ gs, int compute_only) {
@@ -940,8 +948,8 @@ __global__ __launch_bounds__(1024) void kg_kick(const SysDesc *__restrict__ desc
   const int64_t a = D.off + t.first + threadIdx.x;
   const int role = A.tr[a] >> 1;
   double ft[3], vn[3], qn[3];
-  if (D.dim == 2) kick_atom<2>(D, gs[t.sys], A, a, role, compute_only != 0, true, ft, vn, qn);
-  else kick_atom<3>(D, gs[t.sys], A, a, role, compute_only != 0, true, ft, vn, qn);
+  if (D.dim == 2) kick_atom<2, T>(D, gs[t.sys], A, a, role, compute_only != 0, true, ft, vn, qn);
+  else kick_atom<3, T>(D, gs[t.sys], A, a, role, compute_only != 0, true, ft, vn, qn);
 }
 
 // A step's closing kick fused with the next step's B A O A (Langevin plans
@@ -961,10 +969,10 @@ __global__ __launch_bounds__(1024) void kg_kick_drift(const SysDesc *__restrict_
   const int role = A.tr[a] >> 1;
   double ft[3] = {0, 0, 0}, vn[3] = {0, 0, 0}, qn[3] = {0, 0, 0};
   if (D.dim == 2) {
-    kick_atom<2>(D, gs[t.sys], A, a, role, false, false, ft, vn, qn);
+    kick_atom<2, T>(D, gs[t.sys], A, a, role, false, false, ft, vn, qn);
     drift_atom<2, T, true>(D, states[t.sys], A, i, false, vn, ft, qn);
   } else {
-    kick_atom<3>(D, gs[t.sys], A, a, role, false, false, ft, vn, qn);
+    kick_atom<3, T>(D, gs[t.sys], A, a, role, false, false, ft, vn, qn);
     drift_atom<3, T, true>(D, states[t.sys], A, i, false, vn, ft, qn);
   }
 }
@@ -1144,8 +1152,12 @@ hipError_t grid_step(int prec, const SysDesc *descs, SysState *states, const Arr
   nl += launch_drift(prec, descs, states, A, P, true, stream);
   nl += launch_rebuild(descs, states, A, P, stream);
   nl += launch_pairs_reduce(prec, descs, states, A, P, true, stream);
-  hipLaunchKernelGGL(kg_kick, dim3(P.ntiles), dim3(P.block), 0, stream, descs, A, P.tiles, P.ntiles,
-                     (const GridScal *)P.gscal, 1);
+  if (prec == 0)
+    hipLaunchKernelGGL(kg_kick<double>, dim3(P.ntiles), dim3(P.block), 0, stream, descs, A, P.tiles, P.ntiles,
+                       (const GridScal *)P.gscal, 1);
+  else
+    hipLaunchKernelGGL(kg_kick<float>, dim3(P.ntiles), dim3(P.block), 0, stream, descs, A, P.tiles, P.ntiles,
+                       (const GridScal *)P.gscal, 1);
   ++nl;
   if (launches) *launches += nl;
   return hipGetLastError();
@@ -1172,7 +1184,8 @@ hipError_t grid_steps(int prec, const SysDesc *descs, SysState *states, const Ar
         hipLaunchKernelGGL(kg_kick_drift<float>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, gs);
       ++nl;
     } else {
-      hipLaunchKernelGGL(kg_kick, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, 0);
+      if (prec == 0) hipLaunchKernelGGL(kg_kick<double>, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, 0);
+      else hipLaunchKernelGGL(kg_kick<float>, dim3(nt), dim3(B), 0, stream, descs, A, P.tiles, nt, gs, 0);
       ++nl;
       if (P.any_nhc) nl += launch_nhc(descs, states, A, P, stream);
     }

@@ -301,7 +301,6 @@ __device__ void run_system(const SysDesc &D, SysState *__restrict__ stg, const A
       }
       double e;
       if constexpr (sizeof(T) == 8) e = acc.e; else e = acc.e.get();
-      A.eatom[a] = e;
       sums[0] += e;
       {
         double f2 = 0.0;

@@ -1091,7 +1091,7 @@ hd_status hd_finalize(hd_ctx *ctx) {
 #define ALLOC(p, cnt) do { st = dalloc(ctx, &(p), (cnt)); if (st != HD_OK) return st; } while (0)
   ALLOC(A.x, 3 * N); ALLOC(A.v, 3 * N); ALLOC(A.rO, 3 * N); ALLOC(A.xb, 3 * N); ALLOC(A.cofs, 3 * N);
   ALLOC(A.ftot, 3 * N); ALLOC(A.flj, 3 * N); ALLOC(A.hu, 3 * N); ALLOC(A.fb, 3 * N);
-  ALLOC(A.eatom, N);
+  if (ctx->prec != HD_FP64) { ALLOC(A.flj_f, 3 * N); ALLOC(A.hu_f, 3 * N); }
   ALLOC(A.rec, (size_t)N * hdk::kRecDoubles);
   ALLOC(A.brec, (size_t)N * 4);
   ALLOC(A.tuu, 3 * N);
@@ -1790,7 +1790,7 @@ hd_status hd_set_state(hd_ctx *ctx, int32_t sys, const void *buf, size_t bytes) 
 // FIRE quench of the listed systems (hd_quench).  With no_alloc, the FIRE
 // state, the system list and the reduction partials are carved out of the
 // device's static scratch array and nothing is allocated on the device; the
-// read-out arrays (LJ and bias forces, H u, per-atom energies, u) are then
+// read-out arrays (LJ and bias forces, H u, u) are then
 // re-evaluated at the restored positions instead of being saved and copied
 // back.
 static hd_status quench_run(hd_ctx *ctx, const int32_t *systems, int32_t count, double ftol, int64_t max_iters,
@@ -1849,7 +1849,6 @@ static hd_status quench_run(hd_ctx *ctx, const int32_t *systems, int32_t count, 
     saved = {{ctx->A.flj, nullptr, 3 * N * sizeof(double)},
              {ctx->A.hu, nullptr, 3 * N * sizeof(double)},
              {ctx->A.fb, nullptr, 3 * N * sizeof(double)},
-             {ctx->A.eatom, nullptr, N * sizeof(double)},
              {ctx->A.u, nullptr, ubytes}};
   int32_t *d_list = nullptr;
   hdk::FireSys *d_fire = nullptr;
@@ -2129,7 +2128,6 @@ hd_status hd_min_mode(hd_ctx *ctx, int32_t sys, int32_t max_iter, double tol, ui
   std::vector<Saved> saved = {{ctx->A.flj, nullptr, 3 * N * sizeof(double)},
                               {ctx->A.hu, nullptr, 3 * N * sizeof(double)},
                               {ctx->A.fb, nullptr, 3 * N * sizeof(double)},
-                              {ctx->A.eatom, nullptr, N * sizeof(double)},
                               {ctx->A.u, nullptr, ubytes}};
   auto release = [&]() {
     for (auto &v : saved)
@@ -2296,7 +2294,6 @@ hd_status hd_min_mode_gradient(hd_ctx *ctx, int32_t sys, const double *mode, dou
                               {ctx->A.hu, nullptr, 3 * N * sizeof(double)},
                               {ctx->A.fb, nullptr, 3 * N * sizeof(double)},
                               {ctx->A.tuu, nullptr, 3 * N * sizeof(double)},
-                              {ctx->A.eatom, nullptr, N * sizeof(double)},
                               {ctx->A.u, nullptr, ubytes}};
   auto release = [&]() {
     for (auto &v : saved)

@@ -735,7 +735,6 @@ __device__ void run_small(const SysDesc &D, SysState *__restrict__ stg, const Ar
       A.flj[k * N + a] = F[k]; A.hu[k * N + a] = H[k]; A.fb[k * N + a] = fbv[k];
       u[k * N + a] = us[k * stride + i];
     }
-    A.eatom[a] = e_own;
     A.nnb[a] = nn;
     // the list itself lives in LDS; leave a copy in the global list so that
     // read-outs (hd_debug_pairs) see the list the last step used
