@@ -48,19 +48,19 @@ CSRC = os.path.join(ROOT, "paper_0909_5215_amd", "csrc")
 # longer describes the kernel and the traffic is reported as null.
 HBM_COUNTERS = {
     ("C2", "k_small<float, 2, 0, 512, false>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "8a26a24be46da5d6",
-        "fetch_kib": 1001.8, "fetch_scale": 2.0, "write_kib": 2896.8, "write_scale": 1.0,
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "995233e0a384dbaa",
+        "fetch_kib": 1000.5, "fetch_scale": 2.0, "write_kib": 2776.8, "write_scale": 1.0,
     },
     ("C2", "k_small<float, 2, 0, 512, true>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "8a26a24be46da5d6",
-        "fetch_kib": 996.6, "fetch_scale": 2.0, "write_kib": 2449.6, "write_scale": 1.0,
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "995233e0a384dbaa",
+        "fetch_kib": 995.0, "fetch_scale": 2.0, "write_kib": 2329.6, "write_scale": 1.0,
     },
     # the grid step as a whole: every kg_* launch of the float32 run (the
     # fused kick-drift, the rebuild launches, pairs, reduce) summed and
     # divided by its steps (per_step: scaled by the steps one launch covers)
     ("C5b", "grid step (kg_* kernels, timed as a whole)"): {
-        "src": ("hd_grid.hip", "hd_device.h"), "sha": "863bc99ecc588203",
-        "fetch_kib": 464099.9, "fetch_scale": 2.0, "write_kib": 397237.7, "write_scale": 1.0,
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "51daadba0ccb129a",
+        "fetch_kib": 437171.4, "fetch_scale": 2.0, "write_kib": 332279.8, "write_scale": 1.0,
         "per_step": True,
     },
 }
@@ -73,16 +73,16 @@ HBM_COUNTERS = {
 VALU_ISSUE_PEAK_G = 256 * 2.4
 VALU_COUNTERS = {
     ("C2", "k_small<float, 2, 0, 512, false>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "8a26a24be46da5d6",
-        "insts_valu": 839596137.1, "steps": 2000,
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "995233e0a384dbaa",
+        "insts_valu": 840605926.1, "steps": 2000,
     },
     ("C2", "k_small<float, 2, 0, 512, true>"): {
-        "src": ("hd_small.hip", "hd_device.h"), "sha": "8a26a24be46da5d6",
-        "insts_valu": 797252902.1, "steps": 2000,
+        "src": ("hd_small.hip", "hd_device.h"), "sha": "995233e0a384dbaa",
+        "insts_valu": 798289717.9, "steps": 2000,
     },
     ("C5b", "grid step (kg_* kernels, timed as a whole)"): {
-        "src": ("hd_grid.hip", "hd_device.h"), "sha": "863bc99ecc588203",
-        "insts_valu": 342200790.4, "steps": 1,
+        "src": ("hd_grid.hip", "hd_device.h"), "sha": "51daadba0ccb129a",
+        "insts_valu": 343066653.5, "steps": 1,
     },
 }
 
