@@ -284,8 +284,11 @@ hd_status hd_finalize(hd_ctx *ctx);
  * feels a force above 1e6 eps/sigma (or a non-finite one), is frozen
  * (HD_FLAG_UNSTABLE) while the others continue; hd_set_positions or
  * hd_set_state revive it.  The energies read after the call are those of
- * the last step; the LDS-resident kernel evaluates the pair energy on that
- * step only, so a system frozen earlier within a launch reports a pair
+ * the last step (the grid kernels evaluate the pair energy only on the last
+ * step of each replayed sequence of steps, the call's last among them, and
+ * test stability by the forces elsewhere); the LDS-resident kernel
+ * evaluates the pair energy on that step only, so a system frozen earlier
+ * within a launch reports a pair
  * energy of zero for its last step: its e_pot is the
  * drive energy alone and stays finite (test the flags, not isfinite(e_pot)).
  * A system frozen by an evaluation (hd_finalize, hd_compute) keeps that

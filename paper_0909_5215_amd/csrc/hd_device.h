@@ -19,7 +19,9 @@ enum : int { P_XHX = 13, P_TR = 14, P_W2 = 17, P_HWR = 18 };
 // Bias variables (eq. 5-7, eq. 15) and the extra pair-pass terms a plan
 // compiles in.
 enum : int { BVAR_SLOPE = 0, BVAR_CURV = 1, BVAR_DIST = 2, BVAR_EIG = 3 };
-enum : int { EXT_BONDS = 1, EXT_CURV = 2, EXT_EIG = 4 };
+// EXT_NOE: a pair pass whose energy nobody reads (the steps before a
+// captured sequence's last) leaves the pair energy out.
+enum : int { EXT_BONDS = 1, EXT_CURV = 2, EXT_EIG = 4, EXT_NOE = 8 };
 constexpr double kForceLimit2 = 1e12;  // (1e6 eps/sigma)^2
 
 // Read-only description of one system (uploaded at finalize / parameter
@@ -618,7 +620,8 @@ __device__ __forceinline__ void bond_terms(const LJRow<T> &R, double r2, T &f, T
 // only: kernels that never see such a model keep the LJ-only registers).
 // With EXT_CURV also the pair's share of T[u,u], the gradient of u.H(r)u at
 // fixed u: (C |w|^2 + Dc (dx.w)^2) dx + 2 C (dx.w) w with Dc = (dC/dr)/r.
-// WITH_E = false leaves the energy out (a step whose energy nobody reads).
+// WITH_E = false, or EXT_NOE, leaves the energy out (a step whose energy
+// nobody reads).
 // With EXT_EIG also, for the eigenvalue bias, the pair's shares of H w and
 // T[w,w] with w = wi - wj the mode estimate's difference (T[w,w] in the X
 // accumulator: the curvature and the eigenvalue bias are not combined).
@@ -627,6 +630,7 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
                                           const T ui[3], const T uj[3], PairAcc<T> &acc,
                                           const T *wi = nullptr, const T *wj = nullptr) {
   constexpr bool BONDS = (EXT & EXT_BONDS) != 0, CURV = (EXT & EXT_CURV) != 0, EIG = (EXT & EXT_EIG) != 0;
+  constexpr bool WE = WITH_E && (EXT & EXT_NOE) == 0;
   if constexpr (sizeof(T) == 8) {
     double f, C, e, Dc = 0.0;
     if (BONDS && R.bond && tj) {
@@ -669,7 +673,7 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       acc.F[k] += f * dx[k];
       acc.H[k] += CDw * dx[k] - f * w[k];
     }
-    if constexpr (WITH_E) acc.e += 0.5 * e;
+    if constexpr (WE) acc.e += 0.5 * e;
     if constexpr (CURV) {
       double w2 = 0.0;
 #pragma unroll
@@ -722,7 +726,7 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
       acc.F[k].add(f * d[k]);
       acc.H[k].add(__builtin_fmaf(CDw, d[k], -f * w[k]));
     }
-    if constexpr (WITH_E) acc.e.add(0.5f * e);
+    if constexpr (WE) acc.e.add(0.5f * e);
     if constexpr (CURV) {
       float w2 = 0.0f;
 #pragma unroll
@@ -1077,7 +1081,7 @@ __device__ __forceinline__ void pair_atom_rec(const SysDesc &D, const Arrays &A,
                                               const double xi[3], const T ui[3], int ti,
                                               PairAcc<T> &acc, int q0 = 0, int qstep = 1,
                                               const T *wi = nullptr, char *quad_lds = nullptr) {
-  static_assert(!E16 || EXT == 0, "16-bit lists serve the LJ-only pass");
+  static_assert(!E16 || (EXT & ~EXT_NOE) == 0, "16-bit lists serve the LJ-only pass");
   static_assert(kRecDoubles == 8, "records are 64 bytes");
   const int64_t off = D.off;
   const int n = D.n;

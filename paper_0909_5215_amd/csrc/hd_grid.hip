@@ -876,7 +876,7 @@ __global__ __launch_bounds__(256) void kg_reduce(const SysDesc *__restrict__ des
 // EXT: the extra pair terms the plan's systems need -- EXT_BONDS for models
 // with harmonic tip bonds, EXT_CURV for a curvature bias (T[u,u]) -- each
 // combination a separate instantiation, so that LJ-only plans keep their
-// register budget.
+// register budget; EXT_NOE for the steps whose pair energy is not read.
 template <typename T, int LPA, int EXT, bool E16 = false>
 __global__ __launch_bounds__(1024) void kg_pairs(const SysDesc *__restrict__ descs, Arrays A,
                                                  const Tile *__restrict__ tiles, int ntiles) {
@@ -1043,14 +1043,21 @@ size_t grid_scal_bytes() { return sizeof(GridScal); }
 hipError_t grid_allow_lds() {
   // the largest quad-gather workgroup: 256 atoms, 1024 threads
   const int bytes = 16 * kQuadWaveBytes;
-  const void *fns[14] = {
+  const void *fns[28] = {
       (const void *)kg_pairs<float, 4, 0, true>,   (const void *)kg_pairs<float, 4, 0, false>,
       (const void *)kg_pairs<float, 4, 1, false>,  (const void *)kg_pairs<float, 4, 2, false>,
       (const void *)kg_pairs<float, 4, 3, false>,  (const void *)kg_pairs<float, 4, 4, false>,
       (const void *)kg_pairs<float, 4, 5, false>,  (const void *)kg_pairs<double, 4, 0, true>,
       (const void *)kg_pairs<double, 4, 0, false>, (const void *)kg_pairs<double, 4, 1, false>,
       (const void *)kg_pairs<double, 4, 2, false>, (const void *)kg_pairs<double, 4, 3, false>,
-      (const void *)kg_pairs<double, 4, 4, false>, (const void *)kg_pairs<double, 4, 5, false>};
+      (const void *)kg_pairs<double, 4, 4, false>, (const void *)kg_pairs<double, 4, 5, false>,
+      (const void *)kg_pairs<float, 4, 8, true>,   (const void *)kg_pairs<float, 4, 8, false>,
+      (const void *)kg_pairs<float, 4, 9, false>,  (const void *)kg_pairs<float, 4, 10, false>,
+      (const void *)kg_pairs<float, 4, 11, false>, (const void *)kg_pairs<float, 4, 12, false>,
+      (const void *)kg_pairs<float, 4, 13, false>, (const void *)kg_pairs<double, 4, 8, true>,
+      (const void *)kg_pairs<double, 4, 8, false>, (const void *)kg_pairs<double, 4, 9, false>,
+      (const void *)kg_pairs<double, 4, 10, false>, (const void *)kg_pairs<double, 4, 11, false>,
+      (const void *)kg_pairs<double, 4, 12, false>, (const void *)kg_pairs<double, 4, 13, false>};
   for (const void *f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -1088,9 +1095,9 @@ int launch_rebuild(const SysDesc *descs, SysState *states, const Arrays &A, cons
 }
 
 // The pair pass (four or two lanes per atom where the workgroup allows it)
-// and the per-system reduction.
+// and the per-system reduction.  with_e = false leaves the pair energy out.
 int launch_pairs_reduce(int prec, const SysDesc *descs, SysState *states, const Arrays &A, const GridPlan &P,
-                        bool compute_only, hipStream_t stream) {
+                        bool compute_only, hipStream_t stream, bool with_e = true) {
   const int nt = P.ntiles, B = P.block, co = compute_only ? 1 : 0;
   GridScal *gs = (GridScal *)P.gscal;
   const int lpa = B <= 256 ? 4 : (B <= 512 ? 2 : 1);
@@ -1098,22 +1105,27 @@ int launch_pairs_reduce(int prec, const SysDesc *descs, SysState *states, const 
   const size_t qb = (size_t)(4 * B / 64) * kQuadWaveBytes;
 #define HD_PAIRS(TT, L, BB)                                                                      \
   hipLaunchKernelGGL((kg_pairs<TT, L, BB>), dim3(nt), dim3(L * B), L == 4 ? qb : 0, stream, descs, A, P.tiles, nt)
-#define HD_PAIRS16(TT, L)                                                                        \
-  hipLaunchKernelGGL((kg_pairs<TT, L, 0, true>), dim3(nt), dim3(L * B), L == 4 ? qb : 0, stream, descs, A, \
+#define HD_PAIRS16(TT, L, NE)                                                                    \
+  hipLaunchKernelGGL((kg_pairs<TT, L, NE, true>), dim3(nt), dim3(L * B), L == 4 ? qb : 0, stream, descs, A, \
                      P.tiles, nt)
-#define HD_PAIRS_B(TT, L)                                                                        \
+#define HD_PAIRS_B(TT, L, NE)                                                                    \
   do {                                                                                           \
-    if (P.any_eig) { if (P.any_bonds) HD_PAIRS(TT, L, 5); else HD_PAIRS(TT, L, 4); }             \
-    else if (P.any_curv) { if (P.any_bonds) HD_PAIRS(TT, L, 3); else HD_PAIRS(TT, L, 2); }       \
-    else if (P.any_bonds) HD_PAIRS(TT, L, 1);                                                    \
-    else if (P.list16) HD_PAIRS16(TT, L);                                                        \
-    else HD_PAIRS(TT, L, 0);                                                                     \
+    if (P.any_eig) { if (P.any_bonds) HD_PAIRS(TT, L, 5 | NE); else HD_PAIRS(TT, L, 4 | NE); }   \
+    else if (P.any_curv) { if (P.any_bonds) HD_PAIRS(TT, L, 3 | NE); else HD_PAIRS(TT, L, 2 | NE); } \
+    else if (P.any_bonds) HD_PAIRS(TT, L, 1 | NE);                                               \
+    else if (P.list16) HD_PAIRS16(TT, L, NE);                                                    \
+    else HD_PAIRS(TT, L, NE);                                                                    \
+  } while (0)
+#define HD_PAIRS_E(TT, NE)                                                                       \
+  do {                                                                                           \
+    if (lpa == 4) HD_PAIRS_B(TT, 4, NE); else if (lpa == 2) HD_PAIRS_B(TT, 2, NE); else HD_PAIRS_B(TT, 1, NE); \
   } while (0)
   if (prec == 0) {
-    if (lpa == 4) HD_PAIRS_B(double, 4); else if (lpa == 2) HD_PAIRS_B(double, 2); else HD_PAIRS_B(double, 1);
+    if (with_e) HD_PAIRS_E(double, 0); else HD_PAIRS_E(double, EXT_NOE);
   } else {
-    if (lpa == 4) HD_PAIRS_B(float, 4); else if (lpa == 2) HD_PAIRS_B(float, 2); else HD_PAIRS_B(float, 1);
+    if (with_e) HD_PAIRS_E(float, 0); else HD_PAIRS_E(float, EXT_NOE);
   }
+#undef HD_PAIRS_E
 #undef HD_PAIRS_B
 #undef HD_PAIRS16
 #undef HD_PAIRS
@@ -1176,7 +1188,8 @@ hipError_t grid_steps(int prec, const SysDesc *descs, SysState *states, const Ar
       nl += launch_drift(prec, descs, states, A, P, false, stream);
     }
     nl += launch_rebuild(descs, states, A, P, stream);
-    nl += launch_pairs_reduce(prec, descs, states, A, P, false, stream);
+    // the pair energy only where a caller can read it: the sequence's last step
+    nl += launch_pairs_reduce(prec, descs, states, A, P, false, stream, s + 1 == nsteps);
     if (fuse && s + 1 < nsteps) {
       if (prec == 0)
         hipLaunchKernelGGL(kg_kick_drift<double>, dim3(nt), dim3(B), 0, stream, descs, states, A, P.tiles, nt, gs);
