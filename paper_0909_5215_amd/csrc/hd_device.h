@@ -636,14 +636,14 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
     if (BONDS && R.bond && tj) {
       bond_terms<double>(R, r2, f, C, e, Dc);
     } else {
-      const double m = live ? 1.0 : 0.0;
+      // outside the cut: epsilon and the shift are zero, r2 stands in as 1
       const double r2i = 1.0 / (live ? r2 : 1.0);
-      const double eps = (tj ? R.eps[1] : R.eps[0]) * m;
+      const double eps = live ? (tj ? R.eps[1] : R.eps[0]) : 0.0;
       const double sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
       const double sr6 = sr2 * sr2 * sr2;
       f = eps * r2i * sr6 * (48.0 * sr6 - 24.0);
       C = eps * r2i * r2i * sr6 * (672.0 * sr6 - 192.0);
-      e = 4.0 * eps * (sr6 * sr6 - sr6) - (tj ? R.shift[1] : R.shift[0]) * m;
+      e = 4.0 * eps * (sr6 * sr6 - sr6) - (live ? (tj ? R.shift[1] : R.shift[0]) : 0.0);
       if constexpr (CURV || EIG) Dc = eps * r2i * r2i * r2i * sr6 * (-10752.0 * sr6 + 1920.0);
     }
     if constexpr (EIG) {
@@ -687,15 +687,15 @@ __device__ __forceinline__ void pair_term(const LJRow<T> &R, int tj, bool live, 
     if (BONDS && R.bond && tj) {
       bond_terms<float>(R, r2, f, C, e, Dc);
     } else {
-      const float m = live ? 1.0f : 0.0f;
+      // outside the cut: epsilon and the shift are zero, r2 stands in as 1
       const float r2i = rcp_nr(live ? (float)r2 : 1.0f);
-      const float eps = (tj ? R.eps[1] : R.eps[0]) * m;
+      const float eps = live ? (tj ? R.eps[1] : R.eps[0]) : 0.0f;
       const float sr2 = (tj ? R.sig2[1] : R.sig2[0]) * r2i;
       const float sr6 = sr2 * sr2 * sr2;
       const float epsr = eps * r2i * sr6;
       f = epsr * (48.0f * sr6 - 24.0f);
       C = epsr * r2i * (672.0f * sr6 - 192.0f);
-      e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (tj ? R.shift[1] : R.shift[0]) * m;
+      e = 4.0f * eps * sr6 * (sr6 - 1.0f) - (live ? (tj ? R.shift[1] : R.shift[0]) : 0.0f);
       if constexpr (CURV || EIG) Dc = epsr * r2i * r2i * (-10752.0f * sr6 + 1920.0f);
     }
     float d[3], w[3], Dw = 0.0f;
